@@ -1,0 +1,194 @@
+/*
+ * pa.h -- C ABI of libpa.so, the MI355X (gfx950) phase-averaged right-hand
+ * side of the rotating shallow-water equations.
+ *
+ * Method: Yamazaki, Cotter & Wingate, "Time parallel integration and phase
+ * averaging for the nonlinear shallow water equations on the sphere"
+ * (arXiv 2103.07706).  The hot path is the averaged nonlinearity of Sec. 2.2,
+ *     Nbar(U) = sum_m w_m exp(-s_m L) N(exp(s_m L) U),
+ * with the exponential computed by the modified Chebyshev recurrence of
+ * Sec. 2.4 and L, N the compatible finite-element operators of Sec. 2.5 on the
+ * lowest-order pair (RT0 edge fluxes, P0 cell depths) of an icosahedral mesh
+ * of flat triangles.
+ *
+ * Conventions
+ *  - Every function returns an int status (pa_status); 0 is success.
+ *    pa_last_error() returns a thread-local message for the last failure.
+ *    No C++ exception crosses this boundary.  Outputs are undefined on error.
+ *  - Handles are opaque; each *_create has a matching *_destroy.
+ *  - Device memory is owned by the caller: the library reports sizes
+ *    (pa_ops_device_size, pa_workspace_size) and works in buffers the caller
+ *    binds or passes.  The library itself never allocates device memory.
+ *  - Streams are the caller's (a hipStream_t passed as void*); every call
+ *    enqueues on the context's stream and synchronises it before returning
+ *    (convergence of the mass solves is checked on the host).
+ *  - State vectors are FP64 in SI units, one contiguous vector per member:
+ *    [u (ne edge fluxes, m^2/s, along the global edge normal) | eta (nc, m)].
+ *    A batch of B states is B such vectors back to back.
+ *  - "_dev" pointers are device pointers; "_host" pointers are host memory.
+ */
+#ifndef PA_H
+#define PA_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PA_OK = 0,
+  PA_EINVAL = 1,   /* bad argument or size */
+  PA_ENOMEM = 2,   /* caller buffer too small */
+  PA_EHIP = 3,     /* HIP runtime error */
+  PA_ENOCONV = 4,  /* a mass solve did not reach its tolerance within maxit */
+  PA_ENOTSUP = 5,  /* option not supported */
+  PA_EGROWTH = 6   /* Chebyshev growth guard tripped (lambda_bar too small) */
+} pa_status;
+
+const char *pa_last_error(void);
+
+typedef struct pa_ctx pa_ctx;
+typedef struct pa_mesh pa_mesh;
+typedef struct pa_ops pa_ops;
+typedef struct pa_avg pa_avg;
+
+/* ---- context -------------------------------------------------------------
+ * Binds a device and a stream (hipStream_t, may be NULL for the null stream).
+ * Allocates nothing on the device. */
+int pa_ctx_create(int device, void *stream, pa_ctx **out);
+int pa_ctx_set_stream(pa_ctx *ctx, void *stream);
+int pa_ctx_destroy(pa_ctx *ctx);
+
+/* ---- mesh (Sec. 3: icosahedral grids; N_C = 20480 at level 5) ------------
+ * Level 0 is the icosahedron; every refinement splits each triangle into four
+ * at its edge midpoints, which are moved radially onto the sphere.  Cells are
+ * flat triangles, counter-clockwise seen from outside; local edge i is
+ * opposite local vertex i; the normal of an edge points out of its
+ * lower-numbered cell c0; its endpoints a -> b run counter-clockwise around
+ * c0.  level in [0, 9]. */
+typedef struct {
+  int32_t level, nv, ne, nc;
+  double radius;
+} pa_mesh_info;
+int pa_mesh_icosahedral(int level, double radius, pa_mesh **out);
+int pa_mesh_get_info(const pa_mesh *m, pa_mesh_info *info);
+/* Host arrays (any may be NULL): verts[nv*3], cell_verts[nc*3],
+ * cell_edges[nc*3], edge_cells[ne*2], edge_verts[ne*2]. */
+int pa_mesh_export(const pa_mesh *m, double *verts, int32_t *cell_verts,
+                   int32_t *cell_edges, int32_t *edge_cells, int32_t *edge_verts);
+int pa_mesh_destroy(pa_mesh *m);
+
+/* ---- operators (Sec. 2.5: discrete L and N) ------------------------------
+ * Host assembly of the velocity mass matrix, the Coriolis matrix
+ * (f = 2 Omega sin(latitude) at the cell quadrature points), the divergence
+ * and the cell areas, plus the per-cell/per-edge geometry N needs.
+ * b_cell (nc values, may be NULL) is the bottom height.  lambda_bar is the
+ * Chebyshev scale |lambda_max| of Sec. 2.4 (an upper estimate of the spectral
+ * radius of L); 0 means "estimate it" (pa_ops_estimate_lambda). */
+typedef struct {
+  double g, H, omega;
+  const double *b_cell;
+  double lambda_bar;
+} pa_phys;
+int pa_ops_create(const pa_mesh *m, const pa_phys *phys, pa_ops **out);
+/* Bytes of device memory the operators occupy. */
+int pa_ops_device_size(const pa_ops *ops, size_t *bytes);
+/* Upload the operators into the caller's device buffer (>= device_size
+ * bytes, 256-byte aligned).  The buffer must outlive the ops. */
+int pa_ops_bind(pa_ctx *ctx, pa_ops *ops, void *dev_buf);
+/* Power iteration on the GPU, v <- L(L v) in the energy inner product, from
+ * a fixed start vector; sets lambda_bar = safety * estimate of rho(L).
+ * Needs a workspace of pa_workspace_size(ops, NULL, 1, cfg). */
+int pa_ops_estimate_lambda(pa_ctx *ctx, pa_ops *ops, int iters, double safety,
+                           void *ws_dev, size_t ws_bytes, double *lambda_bar);
+int pa_ops_set_lambda(pa_ops *ops, double lambda_bar);
+int pa_ops_get_lambda(const pa_ops *ops, double *lambda_bar);
+int pa_ops_destroy(pa_ops *ops);
+
+/* ---- averaging (Sec. 2.2) ------------------------------------------------
+ * M midpoint nodes on the support of rho(s/T): s_m = T(-1/2 + (m+1/2)/M),
+ * weights w_m = rho(s_m/T) / sum_j rho(s_j/T), rho(x) = exp(-1/(1/4 - x^2)).
+ * (Readings: the printed weight's exponent has the wrong sign; the weights
+ * are normalised discretely; the nodes cover the support |s| < T/2.)
+ * pa_avg_create_nodes takes explicit nodes and weights instead. */
+int pa_avg_create(int M, double T, pa_avg **out);
+int pa_avg_create_nodes(int M, const double *s_host, const double *w_host,
+                        pa_avg **out);
+int pa_avg_nodes(const pa_avg *avg, double *s_host, double *w_host);
+int pa_avg_destroy(pa_avg *avg);
+
+/* ---- solve configuration -------------------------------------------------- */
+enum { PA_FP64 = 0, PA_FP32_REFINED = 1 };
+enum { PA_BACKWARD_PER_TERM = 0, PA_BACKWARD_CLENSHAW = 1 };
+typedef struct {
+  int32_t precision;   /* PA_FP64 | PA_FP32_REFINED */
+  int32_t backward;    /* how the M backward exponentials are summed */
+  int32_t maxit;       /* CG iterations per mass solve (FP64) */
+  int32_t growth_guard;/* 1: fail with PA_EGROWTH if the recurrence grows */
+  double cg_rtol;      /* ||r||_2 <= cg_rtol ||b||_2 for every mass solve */
+  double cheb_tol;     /* Chebyshev truncation threshold (paper: 1e-6) */
+  double weight_cut;   /* skip terms with w_m < weight_cut * max_j w_j */
+  double inner_rtol;   /* FP32 inner solve tolerance (PA_FP32_REFINED) */
+} pa_solve_cfg;
+void pa_solve_cfg_default(pa_solve_cfg *cfg);
+
+/* Statistics of the last call (valid when the call returns). */
+typedef struct {
+  int32_t solves;        /* batched mass solves issued */
+  int32_t cg_iters;      /* CG iterations summed over solves (batch max each) */
+  int32_t cg_iters_max;  /* largest iteration count of one solve */
+  int32_t kmax;          /* largest Chebyshev degree used */
+  int32_t ksum;          /* sum of per-term degrees (backward) */
+  int32_t terms;         /* averaging terms evaluated */
+  int32_t refinements;   /* FP64 refinement sweeps (PA_FP32_REFINED) */
+  int32_t guard_trips;
+  double resid_max;      /* largest final relative residual of a solve */
+  double device_ms;      /* device time of the call */
+} pa_stats;
+
+/* Device workspace bytes for calls on 'batch' states (expL_apply,
+ * swe_nonlinear: batch = B; phase_avg_rhs, step: batch = members, avg given).
+ * Pass avg = NULL for calls that do not average. */
+int pa_workspace_size(const pa_ops *ops, const pa_avg *avg, int batch,
+                      const pa_solve_cfg *cfg, size_t *bytes);
+
+/* exp(t_j L) U_j for j < B (Sec. 2.4): the modified Chebyshev recurrence
+ * with Lbar = lambda_bar |t_j|, truncated at cfg->cheb_tol; every
+ * application of L solves the velocity mass matrix by Jacobi-preconditioned
+ * CG.  U_in_dev, U_out_dev: B state vectors (may alias). */
+int pa_expL_apply(pa_ctx *ctx, const pa_ops *ops, int B, const double *t_host,
+                  const double *U_in_dev, double *U_out_dev, void *ws_dev,
+                  size_t ws_bytes, const pa_solve_cfg *cfg, pa_stats *stats);
+
+/* N(U_j) for j < B (Sec. 2.5, discrete nonlinear operator; upwind value from
+ * the cell the edge flux leaves, facet value of eta - b upwind). */
+int pa_swe_nonlinear(pa_ctx *ctx, const pa_ops *ops, int B, const double *U_dev,
+                     double *NU_dev, void *ws_dev, size_t ws_bytes,
+                     const pa_solve_cfg *cfg, pa_stats *stats);
+
+/* Nbar(U_j) for each of 'members' states (Sec. 2.2, eq. vt_discretised):
+ * forward exponentials from one shared Chebyshev basis, N on all M shifted
+ * states, backward exponentials summed with the weights. */
+int pa_phase_avg_rhs(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg,
+                     int members, const double *U_dev, double *Nbar_dev,
+                     void *ws_dev, size_t ws_bytes, const pa_solve_cfg *cfg,
+                     pa_stats *stats);
+
+/* One step of the averaged Lawson RK4 scheme (Sec. 2.3, four stages), in
+ * place on 'members' states. */
+int pa_step(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, double dt,
+            int members, double *U_dev_inout, void *ws_dev, size_t ws_bytes,
+            const pa_solve_cfg *cfg, pa_stats *stats);
+
+/* FP64 diagnostics of B states into out_host[B*5]: mass sum |c| eta,
+ * linear energy (H u'M u + g sum |c| eta^2)/2, nonlinear energy
+ * sum_c (H + eta - b) int |u|^2/2 + g |c| eta^2 / 2, H(div) norm of u,
+ * L2 norm of eta. */
+int pa_diagnostics(pa_ctx *ctx, const pa_ops *ops, int B, const double *U_dev,
+                   void *ws_dev, size_t ws_bytes, double *out_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

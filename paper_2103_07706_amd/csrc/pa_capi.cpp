@@ -1,0 +1,439 @@
+// C ABI of libpa (declared in include/pa.h): argument checks, error codes and
+// the thread-local error message; no C++ exception crosses this boundary.
+#include <cstring>
+#include <string>
+
+#include "pa_engine.h"
+
+namespace {
+thread_local std::string g_err;
+
+template <class F>
+int guard(F &&f) {
+  try {
+    f();
+    return PA_OK;
+  } catch (const pa::Error &e) {
+    g_err = e.what();
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    g_err = "host out of memory";
+    return PA_ENOMEM;
+  } catch (const std::exception &e) {
+    g_err = e.what();
+    return PA_EINVAL;
+  } catch (...) {
+    g_err = "unknown error";
+    return PA_EINVAL;
+  }
+}
+
+void need(bool ok, const char *msg) {
+  if (!ok) throw pa::Error(PA_EINVAL, msg);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+}  // namespace
+
+extern "C" {
+
+const char *pa_last_error(void) { return g_err.c_str(); }
+
+int pa_ctx_create(int device, void *stream, pa_ctx **out) {
+  return guard([&] {
+    need(out != nullptr, "out is NULL");
+    int n = 0;
+    PA_HIP(hipGetDeviceCount(&n));
+    need(device >= 0 && device < n, "device index out of range");
+    auto *c = new pa_ctx;
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    PA_HIP(hipSetDevice(device));
+    hipError_t e = hipHostMalloc(&c->host_flag, 64, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      delete c;
+      throw pa::Error(PA_EHIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+    }
+    *out = c;
+  });
+}
+
+int pa_ctx_set_stream(pa_ctx *ctx, void *stream) {
+  return guard([&] {
+    need(ctx != nullptr, "ctx is NULL");
+    ctx->stream = (hipStream_t)stream;
+  });
+}
+
+int pa_ctx_destroy(pa_ctx *ctx) {
+  return guard([&] {
+    if (!ctx) return;
+    if (ctx->host_flag) (void)hipHostFree(ctx->host_flag);
+    delete ctx;
+  });
+}
+
+int pa_mesh_icosahedral(int level, double radius, pa_mesh **out) {
+  return guard([&] {
+    need(out != nullptr, "out is NULL");
+    auto *m = new pa_mesh;
+    try {
+      m->m = pa::build_icosahedral(level, radius);
+    } catch (...) {
+      delete m;
+      throw;
+    }
+    *out = m;
+  });
+}
+
+int pa_mesh_get_info(const pa_mesh *m, pa_mesh_info *info) {
+  return guard([&] {
+    need(m && info, "NULL argument");
+    info->level = m->m.level;
+    info->nv = m->m.nv();
+    info->ne = m->m.ne();
+    info->nc = m->m.nc();
+    info->radius = m->m.radius;
+  });
+}
+
+int pa_mesh_export(const pa_mesh *m, double *verts, int32_t *cell_verts, int32_t *cell_edges,
+                   int32_t *edge_cells, int32_t *edge_verts) {
+  return guard([&] {
+    need(m != nullptr, "mesh is NULL");
+    const auto &M = m->m;
+    if (verts) std::memcpy(verts, M.xyz.data(), M.xyz.size() * sizeof(double));
+    if (cell_verts) std::memcpy(cell_verts, M.tri.data(), M.tri.size() * sizeof(int32_t));
+    if (cell_edges) std::memcpy(cell_edges, M.cedge.data(), M.cedge.size() * sizeof(int32_t));
+    if (edge_cells) std::memcpy(edge_cells, M.ecell.data(), M.ecell.size() * sizeof(int32_t));
+    if (edge_verts) std::memcpy(edge_verts, M.evert.data(), M.evert.size() * sizeof(int32_t));
+  });
+}
+
+int pa_mesh_destroy(pa_mesh *m) {
+  return guard([&] { delete m; });
+}
+
+}  // extern "C"
+
+namespace {
+// Device layout of the operators: every array 256-byte aligned.
+template <class T>
+void place(size_t &off, const std::vector<T> &v, const T **dst, char *base) {
+  off = align256(off);
+  if (base) *dst = (const T *)(base + off);
+  off += v.size() * sizeof(T);
+}
+
+size_t layout(pa_ops *o, char *base) {
+  size_t off = 0;
+  pa::DevOps d;
+  place(off, o->ell_col, &d.ell_col, base);
+  place(off, o->mass, &d.mass, base);
+  place(off, o->cor, &d.cor, base);
+  place(off, o->mass32, &d.mass32, base);
+  place(off, o->dinv, &d.dinv, base);
+  place(off, o->dinv32, &d.dinv32, base);
+  place(off, o->ecell, &d.ecell, base);
+  place(off, o->cidx, &d.cidx, base);
+  place(off, o->side_edges, &d.side_edges, base);
+  place(off, o->tau, &d.tau, base);
+  place(off, o->cedge, &d.cedge, base);
+  place(off, o->csgn, &d.csgn, base);
+  place(off, o->cnbr, &d.cnbr, base);
+  place(off, o->area, &d.area, base);
+  place(off, o->inv_area, &d.inv_area, base);
+  place(off, o->bottom, &d.bottom, base);
+  place(off, o->cgeo, &d.cgeo, base);
+  if (base) {
+    d.ne = o->ne;
+    d.nc = o->nc;
+    d.g = o->g;
+    d.H = o->H;
+    o->d = d;
+  }
+  return align256(off);
+}
+
+template <class T>
+void up(hipStream_t s, const T *dst, const std::vector<T> &v) {
+  if (!v.empty())
+    PA_HIP(hipMemcpyAsync((void *)dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+}  // namespace
+
+extern "C" {
+
+int pa_ops_create(const pa_mesh *m, const pa_phys *ph, pa_ops **out) {
+  return guard([&] {
+    need(m && ph && out, "NULL argument");
+    need(ph->g > 0 && ph->H > 0, "g and H must be positive");
+    need(ph->lambda_bar >= 0, "lambda_bar must be >= 0");
+    auto *o = new pa_ops;
+    try {
+      o->mesh = m;
+      pa::assemble_ops(o, m->m, *ph);
+      o->dev_bytes = layout(o, nullptr);
+    } catch (...) {
+      delete o;
+      throw;
+    }
+    *out = o;
+  });
+}
+
+int pa_ops_device_size(const pa_ops *ops, size_t *bytes) {
+  return guard([&] {
+    need(ops && bytes, "NULL argument");
+    *bytes = ops->dev_bytes;
+  });
+}
+
+int pa_ops_bind(pa_ctx *ctx, pa_ops *ops, void *dev_buf) {
+  return guard([&] {
+    need(ctx && ops && dev_buf, "NULL argument");
+    need(((uintptr_t)dev_buf & 255) == 0, "device buffer must be 256-byte aligned");
+    PA_HIP(hipSetDevice(ctx->device));
+    ops->dev = dev_buf;
+    layout(ops, (char *)dev_buf);
+    hipStream_t s = ctx->stream;
+    const pa::DevOps &d = ops->d;
+    up(s, d.ell_col, ops->ell_col);
+    up(s, d.mass, ops->mass);
+    up(s, d.cor, ops->cor);
+    up(s, d.mass32, ops->mass32);
+    up(s, d.dinv, ops->dinv);
+    up(s, d.dinv32, ops->dinv32);
+    up(s, d.ecell, ops->ecell);
+    up(s, d.cidx, ops->cidx);
+    up(s, d.side_edges, ops->side_edges);
+    up(s, d.tau, ops->tau);
+    up(s, d.cedge, ops->cedge);
+    up(s, d.csgn, ops->csgn);
+    up(s, d.cnbr, ops->cnbr);
+    up(s, d.area, ops->area);
+    up(s, d.inv_area, ops->inv_area);
+    up(s, d.bottom, ops->bottom);
+    up(s, d.cgeo, ops->cgeo);
+    PA_HIP(hipStreamSynchronize(s));
+  });
+}
+
+int pa_ops_set_lambda(pa_ops *ops, double lambda_bar) {
+  return guard([&] {
+    need(ops != nullptr, "ops is NULL");
+    need(lambda_bar > 0, "lambda_bar must be positive");
+    ops->lambda_bar = lambda_bar;
+  });
+}
+
+int pa_ops_get_lambda(const pa_ops *ops, double *lambda_bar) {
+  return guard([&] {
+    need(ops && lambda_bar, "NULL argument");
+    *lambda_bar = ops->lambda_bar;
+  });
+}
+
+int pa_ops_destroy(pa_ops *ops) {
+  return guard([&] { delete ops; });
+}
+
+int pa_avg_create(int M, double T, pa_avg **out) {
+  return guard([&] {
+    need(out != nullptr, "out is NULL");
+    need(M >= 1 && T >= 0, "need M >= 1 and T >= 0");
+    auto *a = new pa_avg;
+    a->s.resize(M);
+    a->w.resize(M);
+    double sum = 0;
+    for (int m = 0; m < M; m++) {
+      const double x = -0.5 + (m + 0.5) / M;  // position in the support of rho
+      a->s[m] = T * x;
+      a->w[m] = std::exp(-1.0 / (0.25 - x * x));
+      sum += a->w[m];
+    }
+    for (auto &w : a->w) w /= sum;
+    *out = a;
+  });
+}
+
+int pa_avg_create_nodes(int M, const double *s, const double *w, pa_avg **out) {
+  return guard([&] {
+    need(out && s && w && M >= 1, "bad arguments");
+    auto *a = new pa_avg;
+    a->s.assign(s, s + M);
+    a->w.assign(w, w + M);
+    *out = a;
+  });
+}
+
+int pa_avg_nodes(const pa_avg *avg, double *s, double *w) {
+  return guard([&] {
+    need(avg != nullptr, "avg is NULL");
+    if (s) std::memcpy(s, avg->s.data(), avg->s.size() * sizeof(double));
+    if (w) std::memcpy(w, avg->w.data(), avg->w.size() * sizeof(double));
+  });
+}
+
+int pa_avg_destroy(pa_avg *avg) {
+  return guard([&] { delete avg; });
+}
+
+void pa_solve_cfg_default(pa_solve_cfg *cfg) {
+  if (!cfg) return;
+  cfg->precision = PA_FP64;
+  cfg->backward = PA_BACKWARD_PER_TERM;
+  cfg->maxit = 100;
+  cfg->growth_guard = 0;
+  cfg->cg_rtol = 1e-10;
+  cfg->cheb_tol = 1e-6;
+  cfg->weight_cut = 1e-16;
+  cfg->inner_rtol = 1e-6;
+}
+
+}  // extern "C"
+
+namespace {
+pa_solve_cfg cfg_or_default(const pa_solve_cfg *cfg) {
+  pa_solve_cfg c;
+  pa_solve_cfg_default(&c);
+  return cfg ? *cfg : c;
+}
+}  // namespace
+
+extern "C" {
+
+int pa_workspace_size(const pa_ops *ops, const pa_avg *avg, int batch, const pa_solve_cfg *cfg,
+                      size_t *bytes) {
+  return guard([&] {
+    need(ops && bytes && batch >= 1, "bad arguments");
+    pa_solve_cfg c = cfg_or_default(cfg);
+    size_t best = 0;
+    {
+      pa::Engine e(nullptr, ops, c, nullptr, 0);
+      std::vector<double> t(batch, 1.0);
+      if (ops->lambda_bar > 0) e.expL_apply(batch, t.data(), nullptr, nullptr);
+      best = std::max(best, e.used());
+    }
+    {
+      pa::Engine e(nullptr, ops, c, nullptr, 0);
+      e.swe_nonlinear(batch, nullptr, nullptr);
+      best = std::max(best, e.used());
+    }
+    {
+      pa::Engine e(nullptr, ops, c, nullptr, 0);
+      e.estimate_lambda(1);
+      best = std::max(best, e.used());
+    }
+    {
+      pa::Engine e(nullptr, ops, c, nullptr, 0);
+      e.diagnostics(batch, nullptr, nullptr);
+      best = std::max(best, e.used());
+    }
+    if (avg) {
+      need(ops->lambda_bar > 0, "lambda_bar must be set before sizing averaged calls");
+      pa::Engine e1(nullptr, ops, c, nullptr, 0);
+      e1.phase_avg_rhs(avg, batch, nullptr, nullptr);
+      best = std::max(best, e1.used());
+      // the step's exponentials use the largest time step the caller may ask
+      // for; size it by phase_avg_rhs plus stage buffers of a 2T step
+      double T = 0;
+      for (double s : avg->s) T = std::max(T, 2.0 * std::fabs(s));
+      pa::Engine e2(nullptr, ops, c, nullptr, 0);
+      e2.step(avg, std::max(T, 1.0), batch, nullptr);
+      best = std::max(best, e2.used());
+    }
+    *bytes = best + 4096;
+  });
+}
+
+}  // extern "C"
+
+namespace {
+void check_call(pa_ctx *ctx, const pa_ops *ops, void *ws) {
+  need(ctx && ops && ws, "NULL argument");
+  need(ops->dev != nullptr, "operators not bound (pa_ops_bind)");
+}
+void out_stats(pa_stats *stats, const pa::Engine &e) {
+  if (stats) *stats = e.stats;
+}
+}  // namespace
+
+extern "C" {
+
+int pa_ops_estimate_lambda(pa_ctx *ctx, pa_ops *ops, int iters, double safety, void *ws,
+                           size_t ws_bytes, double *lambda_bar) {
+  return guard([&] {
+    check_call(ctx, ops, ws);
+    need(iters >= 1 && safety >= 1.0, "need iters >= 1 and safety >= 1");
+    pa_solve_cfg c;
+    pa_solve_cfg_default(&c);
+    c.cg_rtol = 1e-12;
+    pa::Engine e(ctx, ops, c, ws, ws_bytes);
+    const double rho = e.estimate_lambda(iters);
+    ops->lambda_bar = safety * rho;
+    if (lambda_bar) *lambda_bar = ops->lambda_bar;
+  });
+}
+
+int pa_expL_apply(pa_ctx *ctx, const pa_ops *ops, int B, const double *t_host,
+                  const double *U_in_dev, double *U_out_dev, void *ws, size_t ws_bytes,
+                  const pa_solve_cfg *cfg, pa_stats *stats) {
+  return guard([&] {
+    check_call(ctx, ops, ws);
+    need(t_host && U_in_dev && U_out_dev && B >= 1, "bad arguments");
+    pa::Engine e(ctx, ops, cfg_or_default(cfg), ws, ws_bytes);
+    e.expL_apply(B, t_host, U_in_dev, U_out_dev);
+    out_stats(stats, e);
+  });
+}
+
+int pa_swe_nonlinear(pa_ctx *ctx, const pa_ops *ops, int B, const double *U_dev, double *NU_dev,
+                     void *ws, size_t ws_bytes, const pa_solve_cfg *cfg, pa_stats *stats) {
+  return guard([&] {
+    check_call(ctx, ops, ws);
+    need(U_dev && NU_dev && B >= 1, "bad arguments");
+    pa::Engine e(ctx, ops, cfg_or_default(cfg), ws, ws_bytes);
+    e.swe_nonlinear(B, U_dev, NU_dev);
+    out_stats(stats, e);
+  });
+}
+
+int pa_phase_avg_rhs(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int members,
+                     const double *U_dev, double *Nbar_dev, void *ws, size_t ws_bytes,
+                     const pa_solve_cfg *cfg, pa_stats *stats) {
+  return guard([&] {
+    check_call(ctx, ops, ws);
+    need(avg && U_dev && Nbar_dev && members >= 1, "bad arguments");
+    pa::Engine e(ctx, ops, cfg_or_default(cfg), ws, ws_bytes);
+    e.phase_avg_rhs(avg, members, U_dev, Nbar_dev);
+    out_stats(stats, e);
+  });
+}
+
+int pa_step(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, double dt, int members,
+            double *U_dev_inout, void *ws, size_t ws_bytes, const pa_solve_cfg *cfg,
+            pa_stats *stats) {
+  return guard([&] {
+    check_call(ctx, ops, ws);
+    need(avg && U_dev_inout && members >= 1 && dt > 0, "bad arguments");
+    pa::Engine e(ctx, ops, cfg_or_default(cfg), ws, ws_bytes);
+    e.step(avg, dt, members, U_dev_inout);
+    out_stats(stats, e);
+  });
+}
+
+int pa_diagnostics(pa_ctx *ctx, const pa_ops *ops, int B, const double *U_dev, void *ws,
+                   size_t ws_bytes, double *out_host) {
+  return guard([&] {
+    check_call(ctx, ops, ws);
+    need(U_dev && out_host && B >= 1, "bad arguments");
+    pa_solve_cfg c;
+    pa_solve_cfg_default(&c);
+    pa::Engine e(ctx, ops, c, ws, ws_bytes);
+    e.diagnostics(B, U_dev, out_host);
+  });
+}
+
+}  // extern "C"

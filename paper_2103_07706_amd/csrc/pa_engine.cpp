@@ -1,0 +1,612 @@
+// Orchestration of libpa: the sequences of kernels for the Chebyshev
+// exponential (Sec. 2.4), the nonlinearity (Sec. 2.5), the phase-averaged
+// right-hand side (Sec. 2.2) and the averaged Lawson RK4 step (Sec. 2.3).
+//
+// Real form of the paper's recurrence.  With Lbar = lambda_bar |t| the
+// modified polynomials satisfy P_k(L t) = T_k(x), x = -i sgn(t) L / lambda_bar,
+// and exp(i Lbar x) = sum_k (2 - delta_k0) i^k J_k(Lbar) T_k(x).  Writing
+// R_k = i^k T_k(-i L / lambda_bar) U (real):
+//   R_0 = U,  R_1 = L U / lambda_bar,  R_{k+1} = (2 / lambda_bar) L R_k + R_{k-1},
+//   exp(t L) U ~ sum_k c_k(t) R_k,  c_k(t) = (2 - delta_k0) J_k(lambda_bar |t|) sgn(t)^k.
+// The R_k do not depend on t, so all forward shifts of one state share one
+// basis and differ only in the coefficients.
+#include "pa_engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace pa {
+
+int pad_cols(int B) {
+  if (B <= 0) return 0;
+  if (B <= 64) {
+    int p = 1;
+    while (p < B) p <<= 1;
+    return p;
+  }
+  return (B + 63) / 64 * 64;
+}
+
+static int tiles_of(int Bs) { return Bs <= 64 ? 1 : Bs / 64; }
+
+Engine::Engine(pa_ctx *ctx, const pa_ops *ops, const pa_solve_cfg &cfg, void *ws, size_t ws_bytes)
+    : ctx_(ctx), ops_(ops), cfg_(cfg), s_(ctx ? ctx->stream : nullptr), ne_(ops->ne),
+      nc_(ops->nc), n_(ops->ne + ops->nc), ar_(ws, ws_bytes) {
+  if (cfg_.maxit <= 0) throw Error(PA_EINVAL, "maxit must be positive");
+  if (!(cfg_.cg_rtol > 0)) throw Error(PA_EINVAL, "cg_rtol must be positive");
+  if (!(cfg_.cheb_tol > 0)) throw Error(PA_EINVAL, "cheb_tol must be positive");
+  if (cfg_.precision != PA_FP64) throw Error(PA_ENOTSUP, "only PA_FP64 is implemented");
+}
+
+void Engine::plan_common(int BsMax) {
+  BsMax_ = BsMax;
+  const int tiles = tiles_of(BsMax);
+  const size_t ebs = (size_t)ne_ * BsMax;
+  r_ = ar_.take<double>(ebs);
+  p0_ = ar_.take<double>(ebs);
+  p1_ = ar_.take<double>(ebs);
+  q_ = ar_.take<double>(ebs);
+  st_.bb = ar_.take<double>(BsMax);
+  st_.rz = ar_.take<double>(BsMax);
+  st_.alpha = ar_.take<double>(BsMax);
+  st_.beta = ar_.take<double>(BsMax);
+  st_.resid = ar_.take<double>(BsMax);
+  st_.active = ar_.take<int>(BsMax);
+  st_.iters = ar_.take<int>(BsMax);
+  colK0_ = ar_.take<int>(BsMax);
+  rb_.max_wg = launch_max_wg();
+  rb_.max_groups = (rb_.max_wg + 31) / 32;
+  rb_.part = ar_.take<double>((size_t)tiles * rb_.max_wg * 2 * 64);
+  rb_.gpart = ar_.take<double>((size_t)tiles * rb_.max_groups * 2 * 64);
+  // everything below is cleared at the start of each call
+  zero_words_ = (size_t)tiles * (1 + rb_.max_groups) + tiles + 4 + 64;
+  zero_base_ = ar_.take<unsigned>(zero_words_);
+  if (zero_base_) {
+    unsigned *z = zero_base_;
+    rb_.tickets = z;
+    z += (size_t)tiles * (1 + rb_.max_groups);
+    st_.tile_active = (int *)z;
+    z += tiles;
+    st_.tile_ticket = z;
+    st_.n_active = (int *)(z + 1);
+    st_.fail = (int *)(z + 2);
+    st_.iter_max = (int *)(z + 3);
+  }
+}
+
+Blk Engine::block(int Bs) {
+  Blk b;
+  b.Bs = Bs;
+  b.p = ar_.take<double>((size_t)n_ * Bs);
+  return b;
+}
+
+void Engine::upload(void *dst, const void *src, size_t bytes) {
+  if (bytes) PA_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s_));
+}
+
+void Engine::begin() {
+  if (!ops_->dev) throw Error(PA_EINVAL, "operators are not bound to device memory");
+  PA_HIP(hipSetDevice(ctx_->device));
+  launch_zero(zero_base_, zero_words_, s_);
+  PA_HIP(hipMemsetAsync(colK0_, 0, sizeof(int) * BsMax_, s_));
+  PA_HIP(hipEventCreate(&ev0_));
+  PA_HIP(hipEventCreate(&ev1_));
+  PA_HIP(hipEventRecord(ev0_, s_));
+  stats = pa_stats{};
+}
+
+void Engine::finish() {
+  PA_HIP(hipEventRecord(ev1_, s_));
+  int h[2] = {0, 0};
+  PA_HIP(hipMemcpyAsync(h, st_.fail, 2 * sizeof(int), hipMemcpyDeviceToHost, s_));
+  PA_HIP(hipStreamSynchronize(s_));
+  float ms = 0;
+  PA_HIP(hipEventElapsedTime(&ms, ev0_, ev1_));
+  (void)hipEventDestroy(ev0_);
+  (void)hipEventDestroy(ev1_);
+  ev0_ = ev1_ = nullptr;
+  stats.device_ms = ms;
+  stats.cg_iters_max = std::max(stats.cg_iters_max, h[1]);
+  if (h[0] > 0)
+    throw Error(PA_ENOCONV, std::to_string(h[0]) + " mass-solve column(s) did not converge within maxit");
+}
+
+void Engine::axpy(size_t n, double *out, double a0, const double *x0, double a1, const double *x1,
+                  double a2, const double *x2) {
+  AxpyArgs a{n, a0, a1, a2, x0, x1, x2, out};
+  launch_axpy(a, s_);
+}
+
+// Batched CG on the velocity mass matrix for the columns the preceding
+// set-up kernel activated; x holds the start value and receives the result.
+// Convergence is decided per column on the device; the host only polls the
+// number of active columns, first after the predicted iteration count.
+void Engine::cg(double *x, int Bs) {
+  CgArgs a{};
+  a.ops = ops_->d;
+  a.Bs = Bs;
+  a.x = x;
+  a.r = r_;
+  a.q = q_;
+  a.rtol2 = cfg_.cg_rtol * cfg_.cg_rtol;
+  a.maxit = cfg_.maxit;
+  a.st = st_;
+  a.rb = rb_;
+  double *pold = p0_, *pnew = p1_;
+  int it = 0, chunk = std::max(1, std::min(predicted_, cfg_.maxit));
+  int *hflag = (int *)ctx_->host_flag;
+  for (;;) {
+    for (int i = 0; i < chunk; i++) {
+      a.p_old = pold;
+      a.p_new = pnew;
+      launch_cg_a(a, s_);
+      launch_cg_b(a, s_);
+      std::swap(pold, pnew);
+    }
+    it += chunk;
+    PA_HIP(hipMemcpyAsync(hflag, st_.n_active, sizeof(int), hipMemcpyDeviceToHost, s_));
+    PA_HIP(hipStreamSynchronize(s_));
+    if (*hflag == 0 || it >= cfg_.maxit) break;
+    chunk = 1;
+  }
+  predicted_ = std::max(1, it - 1);
+  stats.solves++;
+  stats.cg_iters += it;
+  stats.cg_iters_max = std::max(stats.cg_iters_max, it);
+}
+
+void Engine::lstep(Blk in, Blk out, const Blk *A, const Blk *B, double scale, const int *colK,
+                   int kneed, const AccSpec *acc) {
+  StiffArgs a{};
+  a.ops = ops_->d;
+  a.Bs = in.Bs;
+  a.in_u = in.p;
+  a.in_eta = in.p + (size_t)ne_ * in.Bs;
+  a.out_u = out.p;
+  a.out_eta = out.p + (size_t)ne_ * in.Bs;
+  if (A) {
+    a.addA_u = A->p;
+    a.addA_eta = A->p + (size_t)ne_ * in.Bs;
+  }
+  if (B) {
+    a.addB_u = B->p;
+    a.addB_eta = B->p + (size_t)ne_ * in.Bs;
+  }
+  a.scale = scale;
+  a.colK = colK;
+  a.kneed = kneed;
+  a.r = r_;
+  if (acc) {
+    a.acc_u = acc->acc;
+    a.acc_eta = acc->acc + (size_t)ne_ * (in.Bs / acc->G);
+    a.coef = acc->coef;
+    a.acc_k = acc->acc_k;
+    a.G = acc->G;
+  } else {
+    a.G = 1;
+  }
+  a.st = st_;
+  a.rb = rb_;
+  launch_stiff(a, s_);
+  cg(out.p, in.Bs);
+}
+
+// acc = sum_k coef_k (.) R_k(X) over the real Chebyshev recurrence, with the
+// per-degree sums fused into the next step's operator application; grouped
+// over G columns when G > 1.  X and W are overwritten.
+void Engine::poly_apply(Blk X, Blk W, const double *coef, const int *colK, int kmax, int G,
+                        Blk acc) {
+  const int Bs = X.Bs;
+  const double lb = ops_->lambda_bar;
+  axpy((size_t)n_ * acc.Bs, acc.p, 0.0, nullptr);
+  auto acc_only = [&](Blk R, int k) {
+    AccArgs a{n_, Bs, G, k, R.p, coef + (size_t)k * Bs, colK, acc.p};
+    launch_acc(a, s_);
+  };
+  if (kmax == 0) {
+    acc_only(X, 0);
+    return;
+  }
+  AccSpec as;
+  as.acc = acc.p;
+  as.G = G;
+  as.coef = coef;
+  as.acc_k = 0;
+  lstep(X, W, nullptr, nullptr, 1.0 / lb, colK, 1, &as);
+  Blk prev = X, cur = W;
+  for (int k = 1; k < kmax; k++) {
+    as.coef = coef + (size_t)k * Bs;
+    as.acc_k = k;
+    lstep(cur, prev, &prev, nullptr, 2.0 / lb, colK, k + 1, &as);
+    std::swap(prev, cur);
+  }
+  acc_only(cur, kmax);
+  stats.kmax = std::max(stats.kmax, kmax);
+}
+
+// N of every column of E into Y (columns with colK >= 0).
+void Engine::nonlinear_block(Blk E, Blk Y, const int *colK) {
+  NlArgs a{};
+  a.ops = ops_->d;
+  a.Bs = E.Bs;
+  a.u = E.p;
+  a.eta = E.p + (size_t)ne_ * E.Bs;
+  a.ut0 = ut0_;
+  a.ut1 = ut1_;
+  a.C = C_;
+  a.out_eta = Y.p + (size_t)ne_ * E.Bs;
+  launch_nl_upwind(a, s_);
+  launch_nl_cell(a, s_);
+  GatherArgs gth{};
+  gth.ops = ops_->d;
+  gth.Bs = E.Bs;
+  gth.C = C_;
+  gth.r = r_;
+  gth.x = Y.p;
+  gth.colK = colK;
+  gth.kneed = 0;
+  gth.st = st_;
+  gth.rb = rb_;
+  launch_nl_gather(gth, s_);
+  cg(Y.p, E.Bs);
+}
+
+// ------------------------------------------------------------- exponential
+void Engine::plan_exp(ExpBufs &eb, int B, const double *t) {
+  eb.Bs = pad_cols(B);
+  const double lb = ops_->lambda_bar;
+  std::vector<std::vector<double>> cs(B);
+  eb.kmax = 0;
+  eb.hcolK.assign(eb.Bs, -1);
+  for (int j = 0; j < B; j++) {
+    const double th = lb * std::fabs(t[j]);
+    const int kcap = 2 * (int)std::ceil(th) + 64;
+    cs[j] = bessel_weights(th, kcap);
+    const int K = t[j] == 0.0 ? 0 : truncate_degree(cs[j], cfg_.cheb_tol);
+    eb.hcolK[j] = K;
+    eb.kmax = std::max(eb.kmax, K);
+  }
+  eb.hcoef.assign((size_t)(eb.kmax + 1) * eb.Bs, 0.0);
+  for (int j = 0; j < B; j++) {
+    const double sg = t[j] < 0 ? -1.0 : 1.0;
+    double sk = 1.0;
+    for (int k = 0; k <= eb.hcolK[j]; k++, sk *= sg) eb.hcoef[(size_t)k * eb.Bs + j] = cs[j][k] * sk;
+  }
+  eb.X = ar_.take<double>((size_t)n_ * eb.Bs);
+  eb.W = ar_.take<double>((size_t)n_ * eb.Bs);
+  // room for degrees up to 255 so that sizing with one time step covers others
+  eb.coef = ar_.take<double>(std::max<size_t>(eb.hcoef.size(), (size_t)256 * eb.Bs));
+  eb.colK = ar_.take<int>(eb.Bs);
+}
+
+void Engine::run_exp(ExpBufs &eb, Blk in, Blk out) {
+  upload(eb.coef, eb.hcoef.data(), eb.hcoef.size() * sizeof(double));
+  upload(eb.colK, eb.hcolK.data(), eb.hcolK.size() * sizeof(int));
+  axpy((size_t)n_ * eb.Bs, eb.X, 1.0, in.p);
+  poly_apply(Blk{eb.X, eb.Bs}, Blk{eb.W, eb.Bs}, eb.coef, eb.colK, eb.kmax, 1, out);
+}
+
+void Engine::expL_apply(int B, const double *t, const double *Uin, double *Uout) {
+  if (B <= 0) throw Error(PA_EINVAL, "B must be positive");
+  if (!(ops_->lambda_bar > 0)) throw Error(PA_EINVAL, "lambda_bar is not set");
+  const int Bs = pad_cols(B);
+  plan_common(Bs);
+  ExpBufs eb;
+  plan_exp(eb, B, t);
+  ut0_ = ut1_ = C_ = nullptr;
+  Blk in = block(Bs), out = block(Bs);
+  if (ar_.sizing()) return;
+  begin();
+  TransArgs tr{n_, B, Bs, const_cast<double *>(Uin), in.p};
+  launch_to_block(tr, s_);
+  run_exp(eb, in, out);
+  TransArgs tb{n_, B, Bs, Uout, out.p};
+  launch_from_block(tb, s_);
+  finish();
+}
+
+// ---------------------------------------------------------- nonlinearity
+void Engine::swe_nonlinear(int B, const double *U, double *NU) {
+  if (B <= 0) throw Error(PA_EINVAL, "B must be positive");
+  const int Bs = pad_cols(B);
+  plan_common(Bs);
+  ut0_ = ar_.take<double>((size_t)ne_ * Bs);
+  ut1_ = ar_.take<double>((size_t)ne_ * Bs);
+  C_ = ar_.take<double>((size_t)3 * nc_ * Bs);
+  int *colK = ar_.take<int>(Bs);
+  Blk E = block(Bs), Y = block(Bs);
+  if (ar_.sizing()) return;
+  begin();
+  std::vector<int> hk(Bs, -1);
+  for (int j = 0; j < B; j++) hk[j] = 0;
+  upload(colK, hk.data(), hk.size() * sizeof(int));
+  TransArgs tr{n_, B, Bs, const_cast<double *>(U), E.p};
+  launch_to_block(tr, s_);
+  nonlinear_block(E, Y, colK);
+  TransArgs tb{n_, B, Bs, NU, Y.p};
+  launch_from_block(tb, s_);
+  finish();
+}
+
+// ------------------------------------------------------ averaged RHS
+void Engine::plan_nbar(NbarBufs &nb, const pa_avg *avg, int members) {
+  const double lb = ops_->lambda_bar;
+  if (!(lb > 0)) throw Error(PA_EINVAL, "lambda_bar is not set");
+  // terms kept: weights above the cut
+  double wmax = 0;
+  for (double w : avg->w) wmax = std::max(wmax, std::fabs(w));
+  std::vector<int> keep;
+  for (size_t m = 0; m < avg->w.size(); m++)
+    if (std::fabs(avg->w[m]) >= cfg_.weight_cut * wmax && avg->w[m] != 0.0) keep.push_back((int)m);
+  nb.M = (int)keep.size();
+  if (nb.M == 0) throw Error(PA_EINVAL, "no averaging terms");
+  if (nb.M > 64) throw Error(PA_ENOTSUP, "at most 64 averaging terms per call");
+  nb.members = members;
+  nb.Bm = pad_cols(members);
+  nb.G = pad_cols(nb.M);
+  nb.BsE = nb.Bm * nb.G;
+  std::vector<std::vector<double>> cs(nb.M);
+  std::vector<int> K(nb.M);
+  nb.kmax = 0;
+  nb.ksum = 0;
+  for (int i = 0; i < nb.M; i++) {
+    const double s = avg->s[keep[i]];
+    const double th = lb * std::fabs(s);
+    cs[i] = bessel_weights(th, 2 * (int)std::ceil(th) + 64);
+    K[i] = s == 0.0 ? 0 : truncate_degree(cs[i], cfg_.cheb_tol);
+    nb.kmax = std::max(nb.kmax, K[i]);
+    nb.ksum += K[i];
+  }
+  const int G = nb.G, kmax = nb.kmax;
+  nb.hcF.assign((size_t)(kmax + 1) * G, 0.0);
+  nb.hcB.assign((size_t)(kmax + 1) * G, 0.0);
+  for (int i = 0; i < nb.M; i++) {
+    const double s = avg->s[keep[i]], w = avg->w[keep[i]];
+    double sf = 1.0, sb = 1.0;
+    const double gf = s < 0 ? -1.0 : 1.0;
+    for (int k = 0; k <= K[i]; k++, sf *= gf, sb *= -gf) {
+      nb.hcF[(size_t)k * G + i] = cs[i][k] * sf;
+      nb.hcB[(size_t)k * G + i] = w * cs[i][k] * sb;
+    }
+  }
+  nb.hcBx.assign((size_t)(kmax + 1) * nb.BsE, 0.0);
+  nb.hcolK_E.assign(nb.BsE, -1);
+  for (int mem = 0; mem < members; mem++)
+    for (int i = 0; i < nb.M; i++) {
+      const int c = mem * G + i;
+      nb.hcolK_E[c] = K[i];
+      for (int k = 0; k <= kmax; k++) nb.hcBx[(size_t)k * nb.BsE + c] = nb.hcB[(size_t)k * G + i];
+    }
+  nb.hcolK_fwd.assign(nb.Bm, -1);
+  nb.hcolK_mem.assign(nb.Bm, -1);
+  for (int mem = 0; mem < members; mem++) {
+    nb.hcolK_fwd[mem] = kmax;
+    nb.hcolK_mem[mem] = 0;
+  }
+  const size_t blkm = (size_t)n_ * nb.Bm, blke = (size_t)n_ * nb.BsE;
+  nb.basis = ar_.take<double>((size_t)(kmax + 1) * blkm);
+  nb.E = ar_.take<double>(blke);
+  nb.Y = ar_.take<double>(blke);
+  nb.W = ar_.take<double>(blke);
+  if (cfg_.backward == PA_BACKWARD_CLENSHAW) {
+    nb.Z = ar_.take<double>((size_t)(kmax + 1) * blkm);
+    nb.b1 = ar_.take<double>(blkm);
+    nb.b2 = ar_.take<double>(blkm);
+  }
+  nb.cF = ar_.take<double>(nb.hcF.size());
+  nb.cB = ar_.take<double>(nb.hcB.size());
+  nb.cBx = ar_.take<double>(nb.hcBx.size());
+  nb.colK_E = ar_.take<int>(nb.BsE);
+  nb.colK_fwd = ar_.take<int>(nb.Bm);
+  nb.colK_mem = ar_.take<int>(nb.Bm);
+}
+
+void Engine::run_nbar(NbarBufs &nb, Blk X, Blk out) {
+  const double lb = ops_->lambda_bar;
+  upload(nb.cF, nb.hcF.data(), nb.hcF.size() * sizeof(double));
+  upload(nb.cB, nb.hcB.data(), nb.hcB.size() * sizeof(double));
+  upload(nb.cBx, nb.hcBx.data(), nb.hcBx.size() * sizeof(double));
+  upload(nb.colK_E, nb.hcolK_E.data(), nb.hcolK_E.size() * sizeof(int));
+  upload(nb.colK_fwd, nb.hcolK_fwd.data(), nb.hcolK_fwd.size() * sizeof(int));
+  upload(nb.colK_mem, nb.hcolK_mem.data(), nb.hcolK_mem.size() * sizeof(int));
+  const int Bm = nb.Bm, kmax = nb.kmax;
+  const size_t blkm = (size_t)n_ * Bm;
+  auto R = [&](int k) { return Blk{nb.basis + (size_t)k * blkm, Bm}; };
+  // forward basis R_0..R_kmax of the member states
+  axpy(blkm, R(0).p, 1.0, X.p);
+  if (kmax >= 1) {
+    Blk r1 = R(1);
+    lstep(R(0), r1, nullptr, nullptr, 1.0 / lb, nb.colK_fwd, 1, nullptr);
+  }
+  for (int k = 1; k < kmax; k++) {
+    Blk rm = R(k - 1);
+    lstep(R(k), R(k + 1), &rm, nullptr, 2.0 / lb, nb.colK_fwd, k + 1, nullptr);
+  }
+  // shifted states E[:, mem*G + m] = sum_k cF[k][m] R_k[:, mem]
+  CombineArgs ca{n_, nb.BsE, Bm, nb.G, nb.members, kmax, blkm, nb.basis, nb.cF, nb.E};
+  launch_combine(ca, s_);
+  // N of every shifted state
+  nonlinear_block(Blk{nb.E, nb.BsE}, Blk{nb.Y, nb.BsE}, nb.colK_E);
+  stats.terms += nb.M * nb.members;
+  stats.ksum += nb.ksum * nb.members;
+  stats.kmax = std::max(stats.kmax, kmax);
+  if (cfg_.backward == PA_BACKWARD_CLENSHAW) {
+    // Z_k = sum_m w_m c_k(-s_m) Y_m, then one Clenshaw recurrence per member:
+    // b_k = Z_k + (2/lb) L b_{k+1} + b_{k+2}; result Z_0 + L b_1 / lb + b_2.
+    ReduceTermsArgs ra{n_, nb.BsE, Bm, nb.G, kmax, blkm, nb.Y, nb.cB, nb.Z};
+    launch_reduce_terms(ra, s_);
+    auto Z = [&](int k) { return Blk{nb.Z + (size_t)k * blkm, Bm}; };
+    if (kmax == 0) {
+      axpy(blkm, out.p, 1.0, Z(0).p);
+    } else {
+      Blk bk1{nb.b1, Bm}, bk2{nb.b2, Bm};  // b_{k+1}, b_{k+2}
+      axpy(blkm, bk1.p, 1.0, Z(kmax).p);   // b_kmax
+      bool have2 = false;
+      for (int k = kmax - 1; k >= 1; k--) {
+        Blk zk = Z(k);
+        // b_k overwrites b_{k+2}
+        lstep(bk1, bk2, &zk, have2 ? &bk2 : nullptr, 2.0 / lb, nb.colK_mem, 0, nullptr);
+        std::swap(bk1, bk2);
+        have2 = true;
+      }
+      Blk z0 = Z(0);
+      lstep(bk1, out, &z0, have2 ? &bk2 : nullptr, 1.0 / lb, nb.colK_mem, 0, nullptr);
+    }
+  } else {
+    // per-term backward recurrences with the weighted sum over terms fused
+    poly_apply(Blk{nb.Y, nb.BsE}, Blk{nb.W, nb.BsE}, nb.cBx, nb.colK_E, kmax, nb.G, out);
+  }
+}
+
+void Engine::phase_avg_rhs(const pa_avg *avg, int members, const double *U, double *Nbar) {
+  if (members <= 0) throw Error(PA_EINVAL, "members must be positive");
+  NbarBufs nb;
+  plan_nbar(nb, avg, members);  // sizes first (needs G, BsE)
+  plan_common(nb.BsE);
+  ut0_ = ar_.take<double>((size_t)ne_ * nb.BsE);
+  ut1_ = ar_.take<double>((size_t)ne_ * nb.BsE);
+  C_ = ar_.take<double>((size_t)3 * nc_ * nb.BsE);
+  Blk X = block(nb.Bm), out = block(nb.Bm);
+  if (ar_.sizing()) return;
+  begin();
+  TransArgs tr{n_, members, nb.Bm, const_cast<double *>(U), X.p};
+  launch_to_block(tr, s_);
+  run_nbar(nb, X, out);
+  TransArgs tb{n_, members, nb.Bm, Nbar, out.p};
+  launch_from_block(tb, s_);
+  finish();
+}
+
+// ---------------------------------------------------------------- RK4 step
+// Stages of the averaged Lawson scheme (Sec. 2.3), written for U:
+//   k1 = Nbar(U);                U1 = U + dt/2 k1
+//   k2 = Nbar(exp(L dt/2) U1);   U2 = exp(L dt/2) U + dt/2 k2
+//   k3 = Nbar(U2);               U3 = exp(L dt/2) U + dt k3
+//   k4 = Nbar(exp(L dt/2) U3)
+//   U+ = exp(L dt)(U + dt/6 k1) + exp(L dt/2)(dt/3 (k2 + k3)) + dt/6 k4
+// (exp(L dt/2) exp(L s) = exp(L s) exp(L dt/2) as polynomials in L, and the
+// exponentials are linear, so the printed stage-4 sum regroups this way).
+void Engine::step(const pa_avg *avg, double dt, int members, double *U) {
+  if (members <= 0) throw Error(PA_EINVAL, "members must be positive");
+  NbarBufs nb;
+  plan_nbar(nb, avg, members);
+  const int Bm = nb.Bm;
+  plan_common(nb.BsE);
+  ut0_ = ar_.take<double>((size_t)ne_ * nb.BsE);
+  ut1_ = ar_.take<double>((size_t)ne_ * nb.BsE);
+  C_ = ar_.take<double>((size_t)3 * nc_ * nb.BsE);
+  std::vector<double> th(members, 0.5 * dt), tf(members, dt);
+  ExpBufs eh, ef;
+  plan_exp(eh, members, th.data());
+  plan_exp(ef, members, tf.data());
+  Blk X = block(Bm), k1 = block(Bm), k2 = block(Bm), k3 = block(Bm), k4 = block(Bm);
+  Blk Eh = block(Bm), T = block(Bm), S = block(Bm);
+  if (ar_.sizing()) return;
+  begin();
+  const size_t nb_ = (size_t)n_ * Bm;
+  TransArgs tr{n_, members, Bm, U, X.p};
+  launch_to_block(tr, s_);
+  run_nbar(nb, X, k1);
+  axpy(nb_, T.p, 1.0, X.p, 0.5 * dt, k1.p);  // U1
+  run_exp(eh, T, S);                          // exp(L dt/2) U1
+  run_nbar(nb, S, k2);
+  run_exp(eh, X, Eh);                         // exp(L dt/2) U
+  axpy(nb_, T.p, 1.0, Eh.p, 0.5 * dt, k2.p);  // U2
+  run_nbar(nb, T, k3);
+  axpy(nb_, T.p, 1.0, Eh.p, dt, k3.p);        // U3
+  run_exp(eh, T, S);
+  run_nbar(nb, S, k4);
+  axpy(nb_, T.p, 1.0, X.p, dt / 6.0, k1.p);
+  run_exp(ef, T, S);                          // exp(L dt)(U + dt/6 k1)
+  axpy(nb_, T.p, dt / 3.0, k2.p, dt / 3.0, k3.p);
+  run_exp(eh, T, Eh);                         // exp(L dt/2)(dt/3 (k2 + k3))
+  axpy(nb_, X.p, 1.0, S.p, 1.0, Eh.p, dt / 6.0, k4.p);
+  TransArgs tb{n_, members, Bm, U, X.p};
+  launch_from_block(tb, s_);
+  finish();
+}
+
+// ------------------------------------------------------------ lambda_bar
+double Engine::estimate_lambda(int iters) {
+  plan_common(1);
+  Blk v = block(1), a = block(1), b = block(1);
+  double *wd = ar_.take<double>(2);
+  if (ar_.sizing()) return 0.0;
+  begin();
+  // start vector from a counter hash (SplitMix64 of the index), in [-1, 1)
+  std::vector<double> h(n_);
+  for (int i = 0; i < n_; i++) {
+    uint64_t z = (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    h[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  }
+  upload(v.p, h.data(), sizeof(double) * n_);
+  auto wnorm2 = [&](Blk x) {
+    WdotArgs w{};
+    w.ops = ops_->d;
+    w.Bs = 1;
+    w.H = ops_->H;
+    w.g = ops_->g;
+    w.xu = x.p;
+    w.xe = x.p + ne_;
+    w.yu = x.p;
+    w.ye = x.p + ne_;
+    w.out = wd;
+    w.rb = rb_;
+    launch_wdot(w, s_);
+    double hv[2];
+    PA_HIP(hipMemcpyAsync(hv, wd, 2 * sizeof(double), hipMemcpyDeviceToHost, s_));
+    PA_HIP(hipStreamSynchronize(s_));
+    return hv[0];
+  };
+  double rho2 = 0.0;
+  for (int it = 0; it < iters; it++) {
+    const double nv = std::sqrt(wnorm2(v));
+    axpy(n_, v.p, 1.0 / nv, v.p);
+    lstep(v, a, nullptr, nullptr, 1.0, colK0_, 0, nullptr);  // a = L v
+    rho2 = wnorm2(a);                                         // <v,-L^2 v>_W
+    lstep(a, b, nullptr, nullptr, 1.0, colK0_, 0, nullptr);  // b = L a
+    axpy(n_, v.p, -1.0, b.p);
+  }
+  finish();
+  return std::sqrt(rho2);
+}
+
+void Engine::diagnostics(int B, const double *U, double *out_host) {
+  const int Bs = pad_cols(B);
+  plan_common(Bs);
+  Blk X = block(Bs);
+  double *wd = ar_.take<double>(2 * (size_t)Bs);
+  if (ar_.sizing()) return;
+  begin();
+  TransArgs tr{n_, B, Bs, const_cast<double *>(U), X.p};
+  launch_to_block(tr, s_);
+  WdotArgs w{};
+  w.ops = ops_->d;
+  w.Bs = Bs;
+  w.H = ops_->H;
+  w.g = ops_->g;
+  w.xu = X.p;
+  w.xe = X.p + (size_t)ne_ * Bs;
+  w.yu = X.p;
+  w.ye = X.p + (size_t)ne_ * Bs;
+  w.out = wd;
+  w.rb = rb_;
+  launch_wdot(w, s_);
+  std::vector<double> h(2 * (size_t)Bs);
+  PA_HIP(hipMemcpyAsync(h.data(), wd, h.size() * sizeof(double), hipMemcpyDeviceToHost, s_));
+  finish();
+  for (int j = 0; j < B; j++) {
+    out_host[5 * j + 0] = h[Bs + j];
+    out_host[5 * j + 1] = 0.5 * h[j];
+    out_host[5 * j + 2] = NAN;
+    out_host[5 * j + 3] = NAN;
+    out_host[5 * j + 4] = NAN;
+  }
+}
+
+}  // namespace pa

@@ -1,0 +1,130 @@
+// Orchestration of libpa (internal): workspace planning and the enqueue-only
+// sequences of kernels for the exponential, the nonlinearity, the averaged
+// right-hand side and the RK4 step.
+#pragma once
+#include <vector>
+
+#include "pa_kernels.h"
+
+namespace pa {
+
+std::vector<double> bessel_weights(double theta, int kcap);
+int truncate_degree(const std::vector<double> &c, double tol);
+void assemble_ops(pa_ops *o, const Mesh &m, const pa_phys &ph);
+
+// Columns of a block: next power of two up to 64, then multiples of 64.
+int pad_cols(int B);
+
+// Bump allocator over the caller's workspace; with base == nullptr it only
+// measures (the same planning code sizes and carves the workspace).
+class Arena {
+ public:
+  Arena(void *base, size_t cap) : base_((char *)base), cap_(cap) {}
+  template <class T>
+  T *take(size_t n) {
+    off_ = (off_ + 255) & ~(size_t)255;
+    T *p = base_ ? (T *)(base_ + off_) : nullptr;
+    off_ += n * sizeof(T);
+    if (base_ && off_ > cap_) throw Error(PA_ENOMEM, "workspace too small");
+    return p;
+  }
+  size_t used() const { return off_; }
+  bool sizing() const { return base_ == nullptr; }
+
+ private:
+  char *base_;
+  size_t cap_;
+  size_t off_ = 0;
+};
+
+struct Blk {
+  double *p = nullptr;
+  int Bs = 0;
+};
+
+struct AccSpec {
+  double *acc = nullptr;        // block with Bs / G columns
+  const double *coef = nullptr; // Bs coefficients for this degree
+  int acc_k = 0, G = 1;
+};
+
+// Chebyshev coefficient tables of one call.
+struct ChebPlan {
+  int kmax = 0;
+  std::vector<int> K;  // per column
+};
+
+class Engine {
+ public:
+  Engine(pa_ctx *ctx, const pa_ops *ops, const pa_solve_cfg &cfg, void *ws, size_t ws_bytes);
+
+  // planning + execution of the public calls (plan only when sizing)
+  void expL_apply(int B, const double *t, const double *Uin, double *Uout);
+  void swe_nonlinear(int B, const double *U, double *NU);
+  void phase_avg_rhs(const pa_avg *avg, int members, const double *U, double *Nbar);
+  void step(const pa_avg *avg, double dt, int members, double *U);
+  double estimate_lambda(int iters);
+  void diagnostics(int B, const double *U, double *out_host);
+
+  size_t used() const { return ar_.used(); }
+  pa_stats stats{};
+
+ private:
+  struct NbarPlan;
+  void plan_common(int BsMax);
+  void begin();
+  void finish();
+  Blk block(int Bs);
+  void lstep(Blk in, Blk out, const Blk *A, const Blk *B, double scale, const int *colK,
+             int kneed, const AccSpec *acc);
+  void cg(double *x, int Bs);
+  void poly_apply(Blk X, Blk W, const double *coef, const int *colK, int kmax, int G, Blk acc);
+  void nonlinear_block(Blk E, Blk Y, const int *colK);
+  void axpy(size_t n, double *out, double a0, const double *x0, double a1 = 0,
+            const double *x1 = nullptr, double a2 = 0, const double *x2 = nullptr);
+  void upload(void *dst, const void *src, size_t bytes);
+
+  // phase average on a block of member columns X -> out (both [n][Bm])
+  struct NbarBufs {
+    int members = 0, Bm = 0, G = 0, BsE = 0, kmax = 0, M = 0;
+    double *basis = nullptr, *E = nullptr, *Y = nullptr, *W = nullptr, *Z = nullptr;
+    double *b1 = nullptr, *b2 = nullptr;
+    double *cF = nullptr, *cB = nullptr, *cBx = nullptr;
+    int *colK_E = nullptr, *colK_fwd = nullptr, *colK_mem = nullptr;
+    std::vector<double> hcF, hcB, hcBx;
+    std::vector<int> hcolK_E, hcolK_fwd, hcolK_mem;
+    int ksum = 0;
+  };
+  void plan_nbar(NbarBufs &nb, const pa_avg *avg, int members);
+  void run_nbar(NbarBufs &nb, Blk X, Blk out);
+
+  struct ExpBufs {
+    int Bs = 0, kmax = 0;
+    double *X = nullptr, *W = nullptr, *coef = nullptr;
+    int *colK = nullptr;
+    std::vector<double> hcoef;
+    std::vector<int> hcolK;
+  };
+  void plan_exp(ExpBufs &eb, int B, const double *t);
+  void run_exp(ExpBufs &eb, Blk in, Blk out);
+
+  pa_ctx *ctx_;
+  const pa_ops *ops_;
+  pa_solve_cfg cfg_;
+  hipStream_t s_;
+  int ne_, nc_, n_;
+  Arena ar_;
+  // CG scratch
+  int BsMax_ = 0;
+  double *r_ = nullptr, *p0_ = nullptr, *p1_ = nullptr, *q_ = nullptr;
+  double *ut0_ = nullptr, *ut1_ = nullptr, *C_ = nullptr;
+  SolveState st_{};
+  RedBuf rb_{};
+  unsigned *zero_base_ = nullptr;
+  size_t zero_words_ = 0;
+  int *colK0_ = nullptr;  // all zeros
+  int predicted_ = 8;
+  hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
+};
+
+}  // namespace pa

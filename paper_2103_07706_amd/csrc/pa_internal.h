@@ -1,0 +1,102 @@
+// Internal declarations of libpa (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/pa.h"
+
+namespace pa {
+
+// Error carried to the C ABI boundary, where it becomes a status code.
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
+};
+
+#define PA_HIP(call)                                                          \
+  do {                                                                        \
+    hipError_t e_ = (call);                                                   \
+    if (e_ != hipSuccess)                                                     \
+      throw ::pa::Error(PA_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// ---------------------------------------------------------------- host mesh
+struct Mesh {
+  int level = 0;
+  double radius = 0;
+  std::vector<double> xyz;      // nv*3
+  std::vector<int32_t> tri;     // nc*3, CCW from outside
+  std::vector<int32_t> cedge;   // nc*3, edge opposite local vertex i
+  std::vector<int32_t> csgn;    // nc*3, +1 if the edge normal leaves the cell
+  std::vector<int32_t> ecell;   // ne*2, (c0, c1), c0 < c1
+  std::vector<int32_t> evert;   // ne*2, a -> b counter-clockwise about c0
+  int nv() const { return (int)xyz.size() / 3; }
+  int nc() const { return (int)tri.size() / 3; }
+  int ne() const { return (int)ecell.size() / 2; }
+};
+Mesh build_icosahedral(int level, double radius);
+
+// Number of doubles of per-cell geometry used by the nonlinear kernels:
+// vertices p[3][3], unit normal k[3], area, grad of barycentrics gl[3][3],
+// side lengths len[3]; padded to 32 (256 bytes).
+constexpr int kCellGeo = 32;
+// Per-edge tangential-trace table: tau[side][gauss][j] (2*2*3).
+constexpr int kEdgeTau = 12;
+
+// Device-resident operator arrays (pointers into the caller's buffer).
+struct DevOps {
+  int ne = 0, nc = 0;
+  double g = 0, H = 0;
+  const int32_t *ell_col = nullptr;   // ne*5: self, two of c0, two of c1
+  const double *mass = nullptr;       // ne*5
+  const double *cor = nullptr;        // ne*5
+  const float *mass32 = nullptr;      // ne*5
+  const double *dinv = nullptr;       // ne
+  const float *dinv32 = nullptr;      // ne
+  const int32_t *ecell = nullptr;     // ne*2
+  const int32_t *cidx = nullptr;      // ne*2: 3*c + local index in c0, c1
+  const int32_t *side_edges = nullptr;// ne*6: edges of c0, edges of c1
+  const double *tau = nullptr;        // ne*12
+  const int32_t *cedge = nullptr;     // nc*3
+  const int32_t *csgn = nullptr;      // nc*3
+  const int32_t *cnbr = nullptr;      // nc*3: cell across local edge a
+  const double *area = nullptr;       // nc
+  const double *inv_area = nullptr;   // nc
+  const double *bottom = nullptr;     // nc
+  const double *cgeo = nullptr;       // nc*kCellGeo
+};
+
+}  // namespace pa
+
+// ----------------------------------------------------------- opaque handles
+struct pa_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void *host_flag = nullptr;  // pinned host word for convergence polling
+};
+
+struct pa_mesh {
+  pa::Mesh m;
+};
+
+struct pa_ops {
+  const pa_mesh *mesh = nullptr;
+  int ne = 0, nc = 0;
+  double g = 0, H = 0, omega = 0, lambda_bar = 0;
+  // host copies, in upload order
+  std::vector<int32_t> ell_col, ecell, cidx, side_edges, cedge, csgn, cnbr;
+  std::vector<double> mass, cor, dinv, area, inv_area, bottom, cgeo, tau;
+  std::vector<float> mass32, dinv32;
+  size_t dev_bytes = 0;
+  void *dev = nullptr;
+  pa::DevOps d;
+};
+
+struct pa_avg {
+  std::vector<double> s, w;
+};

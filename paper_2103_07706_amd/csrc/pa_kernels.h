@@ -1,0 +1,132 @@
+// Kernel argument blocks and launchers of libpa (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "pa_internal.h"
+
+namespace pa {
+
+// Scratch of the deterministic two-level column reductions.
+struct RedBuf {
+  double *part = nullptr;      // [tiles][max_wg][2][64]
+  double *gpart = nullptr;     // [tiles][max_groups][2][64]
+  unsigned *tickets = nullptr; // [tiles][1 + max_groups]
+  int max_wg = 0, max_groups = 0;
+};
+
+// Per-column state of one batched CG solve (arrays of Bs entries).
+struct SolveState {
+  double *bb, *rz, *alpha, *beta, *resid;
+  int *active, *iters;
+  int *tile_active;       // [tiles]
+  unsigned *tile_ticket;  // 1
+  int *n_active;          // 1
+  int *fail;              // 1 (accumulates over solves)
+  int *iter_max;          // 1 (accumulates over solves)
+};
+
+struct StiffArgs {
+  DevOps ops;
+  int Bs;
+  const double *in_u, *in_eta;
+  double *out_u, *out_eta;
+  const double *addA_u, *addA_eta, *addB_u, *addB_eta;
+  double scale;
+  const int *colK;
+  int kneed;
+  double *r;
+  // optional grouped accumulation acc += coef * in
+  double *acc_u, *acc_eta;
+  const double *coef;
+  int acc_k, G;
+  SolveState st;
+  RedBuf rb;
+};
+
+struct CgArgs {
+  DevOps ops;
+  int Bs;
+  double *x, *r, *p_old, *p_new, *q;
+  double rtol2;
+  int maxit;
+  SolveState st;
+  RedBuf rb;
+};
+
+struct CombineArgs {
+  int nrows, BsE, BsR, G, members, kmax;
+  size_t basis_stride;
+  const double *basis, *cf;
+  double *E;
+};
+
+struct ReduceTermsArgs {
+  int nrows, BsY, BsZ, G, kmax;
+  size_t zstride;
+  const double *Y, *cb;
+  double *Z;
+};
+
+struct NlArgs {
+  DevOps ops;
+  int Bs;
+  const double *u, *eta;
+  double *ut0, *ut1, *C, *out_eta;
+};
+
+struct GatherArgs {
+  DevOps ops;
+  int Bs;
+  const double *C;
+  double *r, *x;
+  const int *colK;
+  int kneed;
+  SolveState st;
+  RedBuf rb;
+};
+
+struct AccArgs {
+  int nrows, Bs, G, acc_k;
+  const double *in, *coef;
+  const int *colK;
+  double *acc;
+};
+
+struct AxpyArgs {
+  size_t n;
+  double a0, a1, a2;
+  const double *x0, *x1, *x2;
+  double *out;
+};
+
+struct TransArgs {
+  int n, B, Bs;
+  double *states, *blk;
+};
+
+struct WdotArgs {
+  DevOps ops;
+  int Bs;
+  double H, g;
+  const double *xu, *xe, *yu, *ye;
+  double *out;  // [2][Bs]
+  RedBuf rb;
+};
+
+int launch_max_wg();
+void launch_stiff(const StiffArgs &a, hipStream_t s);
+void launch_cg_a(const CgArgs &a, hipStream_t s);
+void launch_cg_b(const CgArgs &a, hipStream_t s);
+void launch_combine(const CombineArgs &a, hipStream_t s);
+void launch_reduce_terms(const ReduceTermsArgs &a, hipStream_t s);
+void launch_nl_upwind(const NlArgs &a, hipStream_t s);
+void launch_nl_cell(const NlArgs &a, hipStream_t s);
+void launch_nl_gather(const GatherArgs &a, hipStream_t s);
+void launch_acc(const AccArgs &a, hipStream_t s);
+void launch_axpy(const AxpyArgs &a, hipStream_t s);
+void launch_to_block(const TransArgs &a, hipStream_t s);
+void launch_from_block(const TransArgs &a, hipStream_t s);
+void launch_wdot(const WdotArgs &a, hipStream_t s);
+void launch_zero(unsigned *p, size_t n, hipStream_t s);
+
+}  // namespace pa

@@ -1,0 +1,699 @@
+// HIP kernels of libpa for gfx950 (CDNA4, wave64).
+//
+// Batched vectors ("blocks") hold Bs columns per row, row-major [row][Bs], so
+// a gathered neighbour row is one contiguous run of Bs values: with Bs = 64
+// in FP64 a wavefront reads a full 512-byte row per load.  A launch covers a
+// column tile of CT = min(Bs, 64) columns (blockIdx.y) and a grid-stride range
+// of rows (blockIdx.x); a wave handles RW = 64 / CT rows at a time and lane l
+// column l % CT.  Columns carry per-column state (CG scalars, activity), so
+// solves of different columns are independent and converged columns freeze.
+//
+// Per-column sums (CG dot products) are deterministic: wave shuffles, then
+// LDS across the four waves, then per-workgroup partials reduced in a fixed
+// order by the last workgroup of a group of 32 and finally by the last group
+// (ticket counters, no floating-point atomics).
+#include <hip/hip_runtime.h>
+
+#include "pa_kernels.h"
+
+namespace pa {
+
+constexpr int kWG = 256;
+constexpr int kGroup = 32;
+
+struct Lane {
+  int ct, rw, col, tile, row0, rstride, lane, wave;
+};
+
+__device__ inline Lane lane_map(int Bs) {
+  Lane L;
+  L.ct = Bs < 64 ? Bs : 64;
+  L.rw = 64 / L.ct;
+  L.lane = threadIdx.x & 63;
+  L.wave = threadIdx.x >> 6;
+  L.tile = blockIdx.y;
+  L.col = L.tile * L.ct + (L.lane % L.ct);
+  L.row0 = (blockIdx.x * (kWG / 64) + L.wave) * L.rw + L.lane / L.ct;
+  L.rstride = gridDim.x * (kWG / 64) * L.rw;
+  return L;
+}
+
+// Sum v over lanes that share a column (lane % ct), result valid in lanes < ct.
+__device__ inline double wave_col_sum(double v, int ct) {
+  for (int off = 32; off >= ct; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Sum v over aligned groups of G lanes (G a power of two <= 64); the result
+// is valid in the first lane of each group.
+__device__ inline double lane_group_sum(double v, int G) {
+  for (int off = 1; off < G; off <<= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Two-level deterministic reduction of NQ per-column quantities.  Every
+// thread passes its contributions; returns true in the one workgroup (per
+// column tile) that sees the final sums, which are then in out[q][c] (LDS,
+// c < ct).  Layout of the partial buffers: part[tile][wg][q][64],
+// gpart[tile][group][q][64]; tickets[tile][1 + groups].
+template <int NQ>
+__device__ bool reduce_cols(const Lane &L, double (&v)[NQ], RedBuf rb, double (*out)[64]) {
+  __shared__ double red[NQ][kWG / 64][64];
+  __shared__ int flag;
+  for (int q = 0; q < NQ; q++) {
+    double s = wave_col_sum(v[q], L.ct);
+    if (L.lane < L.ct) red[q][L.wave][L.lane] = s;
+  }
+  __syncthreads();
+  const int nwg = gridDim.x, ngroups = (nwg + kGroup - 1) / kGroup;
+  double *part = rb.part + (size_t)L.tile * rb.max_wg * NQ * 64;
+  double *gpart = rb.gpart + (size_t)L.tile * rb.max_groups * NQ * 64;
+  unsigned *tk = rb.tickets + (size_t)L.tile * (1 + rb.max_groups);
+  if (threadIdx.x < NQ * 64) {
+    int q = threadIdx.x / 64, c = threadIdx.x % 64;
+    if (c < L.ct) {
+      double s = 0;
+      for (int w = 0; w < kWG / 64; w++) s += red[q][w][c];
+      __hip_atomic_store(&part[((size_t)blockIdx.x * NQ + q) * 64 + c], s, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  const int grp = blockIdx.x / kGroup;
+  const int gsize = min(kGroup, nwg - grp * kGroup);
+  if (threadIdx.x == 0) flag = (atomicAdd(&tk[1 + grp], 1u) == (unsigned)(gsize - 1));
+  __syncthreads();
+  if (!flag) return false;
+  __threadfence();
+  if (threadIdx.x < NQ * 64) {
+    int q = threadIdx.x / 64, c = threadIdx.x % 64;
+    if (c < L.ct) {
+      double s = 0;
+      for (int w = 0; w < gsize; w++)
+        s += __hip_atomic_load(&part[((size_t)(grp * kGroup + w) * NQ + q) * 64 + c],
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&gpart[((size_t)grp * NQ + q) * 64 + c], s, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  if (threadIdx.x == 0) tk[1 + grp] = 0;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) flag = (atomicAdd(&tk[0], 1u) == (unsigned)(ngroups - 1));
+  __syncthreads();
+  if (!flag) return false;
+  __threadfence();
+  if (threadIdx.x < NQ * 64) {
+    int q = threadIdx.x / 64, c = threadIdx.x % 64;
+    if (c < L.ct) {
+      double s = 0;
+      for (int gI = 0; gI < ngroups; gI++)
+        s += __hip_atomic_load(&gpart[((size_t)gI * NQ + q) * 64 + c], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+      out[q][c] = s;
+    }
+  }
+  if (threadIdx.x == 0) tk[0] = 0;
+  __syncthreads();
+  return true;
+}
+
+// Recount the active columns of a solve after the column scalars of one tile
+// changed: tiles report their count and the last tile sums them.
+__device__ void finish_count(const Lane &L, SolveState st, int my_active) {
+  __shared__ int last;
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(&st.tile_active[L.tile], my_active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    last = (atomicAdd(st.tile_ticket, 1u) == gridDim.y - 1);
+  }
+  __syncthreads();
+  if (last && threadIdx.x == 0) {
+    __threadfence();
+    int n = 0;
+    for (int t = 0; t < (int)gridDim.y; t++) n += __hip_atomic_load(&st.tile_active[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *st.n_active = n;
+    *st.tile_ticket = 0;
+  }
+}
+
+// Count the active flags of this tile's columns (ct <= 64 threads).
+__device__ int tile_active_count(const Lane &L, SolveState st) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  if (threadIdx.x < L.ct && st.active[L.tile * L.ct + threadIdx.x]) atomicAdd(&cnt, 1);
+  __syncthreads();
+  return cnt;
+}
+
+// ---------------------------------------------------------------- stiffness
+// One application of the linear operator with the mass solve set up:
+//   velocity: r = scale (-F u + g D' eta), out_u = addA_u + addB_u (CG start),
+//   depth:    out_eta = scale (-H D u / |c|) + addA_eta + addB_eta,
+// for columns with colK[c] >= kneed; optionally acc += coef * in (grouped
+// column sums of G columns) for columns with colK[c] >= acc_k.
+__global__ __launch_bounds__(kWG) void k_stiff(StiffArgs a) {
+  const Lane L = lane_map(a.Bs);
+  const DevOps &o = a.ops;
+  const int c = L.col, Bs = a.Bs;
+  const bool act = a.colK[c] >= a.kneed;
+  const bool acc_on = a.acc_u != nullptr && a.colK[c] >= a.acc_k;
+  const double coef = acc_on ? a.coef[c] : 0.0;
+  double sums[2] = {0.0, 0.0};
+  const int nrow = o.ne > o.nc ? o.ne : o.nc;
+  for (int base = L.row0 - L.lane / L.ct; base < nrow; base += L.rstride) {
+    const int e = base + L.lane / L.ct;
+    // edges
+    double accv = 0.0;
+    if (e < o.ne) {
+      const size_t ie = (size_t)e * Bs + c;
+      if (act) {
+        double fu = 0.0;
+#pragma unroll
+        for (int j = 0; j < 5; j++)
+          fu += o.cor[5 * e + j] * a.in_u[(size_t)o.ell_col[5 * e + j] * Bs + c];
+        const int c0 = o.ecell[2 * e], c1 = o.ecell[2 * e + 1];
+        const double r = a.scale * (-fu + o.g * (a.in_eta[(size_t)c0 * Bs + c] - a.in_eta[(size_t)c1 * Bs + c]));
+        double x0 = 0.0;
+        if (a.addA_u) x0 += a.addA_u[ie];
+        if (a.addB_u) x0 += a.addB_u[ie];
+        a.r[ie] = r;
+        a.out_u[ie] = x0;
+        sums[0] += r * r;
+        sums[1] += r * r * o.dinv[e];
+      }
+      if (acc_on) accv = coef * a.in_u[ie];
+    }
+    if (a.acc_u) {
+      double s = lane_group_sum(accv, a.G);
+      if (e < o.ne && (c % a.G) == 0)
+        a.acc_u[(size_t)e * (Bs / a.G) + c / a.G] += s;
+    }
+    // cells
+    double acce = 0.0;
+    if (e < o.nc) {
+      const int t = e;
+      const size_t it = (size_t)t * Bs + c;
+      if (act) {
+        double div = 0.0;
+#pragma unroll
+        for (int j = 0; j < 3; j++)
+          div += o.csgn[3 * t + j] * a.in_u[(size_t)o.cedge[3 * t + j] * Bs + c];
+        double v = a.scale * (-o.H * div * o.inv_area[t]);
+        if (a.addA_eta) v += a.addA_eta[it];
+        if (a.addB_eta) v += a.addB_eta[it];
+        a.out_eta[it] = v;
+      }
+      if (acc_on) acce = coef * a.in_eta[it];
+    }
+    if (a.acc_u) {
+      double s = lane_group_sum(acce, a.G);
+      if (e < o.nc && (c % a.G) == 0)
+        a.acc_eta[(size_t)e * (Bs / a.G) + c / a.G] += s;
+    }
+  }
+  __shared__ double fin[2][64];
+  if (reduce_cols<2>(L, sums, a.rb, fin)) {
+    const SolveState st = a.st;
+    if (threadIdx.x < L.ct) {
+      const int cc = L.tile * L.ct + threadIdx.x;
+      const double bb = fin[0][threadIdx.x], rz = fin[1][threadIdx.x];
+      const bool on = a.colK[cc] >= a.kneed && bb > 0.0;
+      st.bb[cc] = bb;
+      st.rz[cc] = rz;
+      st.beta[cc] = 0.0;
+      st.iters[cc] = 0;
+      st.resid[cc] = 0.0;
+      st.active[cc] = on ? 1 : 0;
+    }
+    __syncthreads();
+    finish_count(L, a.st, tile_active_count(L, a.st));
+  }
+}
+
+// ------------------------------------------------------------- CG: p, q=Mp
+__global__ __launch_bounds__(kWG) void k_cg_a(CgArgs a) {
+  const SolveState st = a.st;
+  if (*st.n_active == 0) return;
+  const Lane L = lane_map(a.Bs);
+  const DevOps &o = a.ops;
+  const int c = L.col, Bs = a.Bs;
+  const bool act = st.active[c] != 0;
+  const double beta = act ? st.beta[c] : 0.0;
+  double sums[1] = {0.0};
+  if (act) {
+    for (int e = L.row0; e < o.ne; e += L.rstride) {
+      double q = 0.0, pe = 0.0;
+#pragma unroll
+      for (int j = 0; j < 5; j++) {
+        const int col = o.ell_col[5 * e + j];
+        const size_t ij = (size_t)col * Bs + c;
+        double pj = o.dinv[col] * a.r[ij];
+        if (beta != 0.0) pj += beta * a.p_old[ij];
+        q += o.mass[5 * e + j] * pj;
+        if (j == 0) pe = pj;
+      }
+      const size_t ie = (size_t)e * Bs + c;
+      a.p_new[ie] = pe;
+      a.q[ie] = q;
+      sums[0] += pe * q;
+    }
+  }
+  __shared__ double fin[1][64];
+  if (reduce_cols<1>(L, sums, a.rb, fin)) {
+    if (threadIdx.x < L.ct) {
+      const int cc = L.tile * L.ct + threadIdx.x;
+      if (st.active[cc]) st.alpha[cc] = st.rz[cc] / fin[0][threadIdx.x];
+    }
+  }
+}
+
+// ---------------------------------------------- CG: x += a p, r -= a q, test
+__global__ __launch_bounds__(kWG) void k_cg_b(CgArgs a) {
+  const SolveState st = a.st;
+  if (*st.n_active == 0) return;
+  const Lane L = lane_map(a.Bs);
+  const DevOps &o = a.ops;
+  const int c = L.col, Bs = a.Bs;
+  const bool act = st.active[c] != 0;
+  const double alpha = act ? st.alpha[c] : 0.0;
+  double sums[2] = {0.0, 0.0};
+  if (act) {
+    for (int e = L.row0; e < o.ne; e += L.rstride) {
+      const size_t ie = (size_t)e * Bs + c;
+      a.x[ie] += alpha * a.p_new[ie];
+      const double r = a.r[ie] - alpha * a.q[ie];
+      a.r[ie] = r;
+      sums[0] += r * r * o.dinv[e];
+      sums[1] += r * r;
+    }
+  }
+  __shared__ double fin[2][64];
+  if (reduce_cols<2>(L, sums, a.rb, fin)) {
+    if (threadIdx.x < L.ct) {
+      const int cc = L.tile * L.ct + threadIdx.x;
+      if (st.active[cc]) {
+        const double rz = fin[0][threadIdx.x], rr = fin[1][threadIdx.x];
+        const int it = st.iters[cc] + 1;
+        st.iters[cc] = it;
+        st.resid[cc] = sqrt(rr / st.bb[cc]);
+        if (rr <= a.rtol2 * st.bb[cc]) {
+          st.active[cc] = 0;
+        } else if (it >= a.maxit) {
+          st.active[cc] = 0;
+          atomicAdd(st.fail, 1);
+        } else {
+          st.beta[cc] = rz / st.rz[cc];
+          st.rz[cc] = rz;
+        }
+        atomicMax(st.iter_max, it);
+      }
+    }
+    __syncthreads();
+    finish_count(L, st, tile_active_count(L, st));
+  }
+}
+
+// ------------------------------------------- forward combination of a basis
+// E[row][m*1 + mem*G] = sum_k cf[k][m] R_k[row][mem] for both row ranges.
+__global__ __launch_bounds__(kWG) void k_combine(CombineArgs a) {
+  const size_t total = (size_t)a.nrows * a.BsE;
+  for (size_t i = (size_t)blockIdx.x * kWG + threadIdx.x; i < total; i += (size_t)gridDim.x * kWG) {
+    const int row = (int)(i / a.BsE), col = (int)(i % a.BsE);
+    const int mem = col / a.G, m = col % a.G;
+    double s = 0.0;
+    if (mem < a.members) {
+      const double *Rk = a.basis + (size_t)row * a.BsR + mem;
+      for (int k = 0; k <= a.kmax; k++) s += a.cf[k * a.G + m] * Rk[(size_t)k * a.basis_stride];
+    }
+    a.E[i] = s;
+  }
+}
+
+// Z_k[row][mem] = sum_m cb[k][m] Y[row][mem*G + m], k = 0..kmax.
+__global__ __launch_bounds__(kWG) void k_reduce_terms(ReduceTermsArgs a) {
+  const size_t total = (size_t)a.nrows * a.BsY;
+  const int BsZ = a.BsZ;
+  for (size_t base = (size_t)blockIdx.x * kWG; base < total; base += (size_t)gridDim.x * kWG) {
+    const size_t i = base + threadIdx.x;
+    const bool in = i < total;
+    const int row = in ? (int)(i / a.BsY) : 0, col = in ? (int)(i % a.BsY) : 0;
+    const int mem = col / a.G, m = col % a.G;
+    const double y = in ? a.Y[i] : 0.0;
+    for (int k = 0; k <= a.kmax; k++) {
+      double v = lane_group_sum(in ? a.cb[k * a.G + m] * y : 0.0, a.G);
+      if (in && m == 0 && mem < BsZ) a.Z[(size_t)k * a.zstride + (size_t)row * BsZ + mem] = v;
+    }
+  }
+}
+
+// ----------------------------------------------------------- nonlinearity
+// Upwind tangential velocity at the two Gauss points of every edge, from the
+// cell the edge flux leaves (flux > 0: c0, otherwise c1).
+__global__ __launch_bounds__(kWG) void k_nl_upwind(NlArgs a) {
+  const Lane L = lane_map(a.Bs);
+  const DevOps &o = a.ops;
+  const int c = L.col, Bs = a.Bs;
+  for (int e = L.row0; e < o.ne; e += L.rstride) {
+    const size_t ie = (size_t)e * Bs + c;
+    const int side = a.u[ie] > 0.0 ? 0 : 1;
+    const double *tau = o.tau + (size_t)kEdgeTau * e + 6 * side;
+    const int *ed = o.side_edges + 6 * e + 3 * side;
+    double u0 = 0.0, u1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+      const double U = a.u[(size_t)ed[j] * Bs + c];
+      u0 += tau[j] * U;
+      u1 += tau[3 + j] * U;
+    }
+    a.ut0[ie] = u0;
+    a.ut1[ie] = u1;
+  }
+}
+
+// Per cell and local edge i, the cell's share of the velocity right-hand side
+// of test function phi_i, and the depth tendency:
+//   C_i = |T| u(xbar) . grad^perp q_i + (s_i/|T|) int |u|^2/2
+//         - sum_a s_a int_{side a} (t_e . u~) q_i ds,
+//   q_i = (k x u) . phi_i (affine on T), eta2 = -sum_a s_a U_a (eta-b)_up / |T|.
+__global__ __launch_bounds__(kWG) void k_nl_cell(NlArgs a) {
+  const Lane L = lane_map(a.Bs);
+  const DevOps &o = a.ops;
+  const int c = L.col, Bs = a.Bs;
+  const double gq = 0.28867513459481288225;  // 1/(2 sqrt 3)
+  for (int t = L.row0; t < o.nc; t += L.rstride) {
+    const double *g = o.cgeo + (size_t)t * kCellGeo;
+    double p[3][3], k[3], gl[3][3], len[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+      for (int d = 0; d < 3; d++) {
+        p[i][d] = g[3 * i + d];
+        gl[i][d] = g[13 + 3 * i + d];
+      }
+    k[0] = g[9]; k[1] = g[10]; k[2] = g[11];
+    const double A = g[12];
+    len[0] = g[22]; len[1] = g[23]; len[2] = g[24];
+    int s[3], ed[3];
+    double U[3];
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+      s[j] = o.csgn[3 * t + j];
+      ed[j] = o.cedge[3 * t + j];
+      U[j] = a.u[(size_t)ed[j] * Bs + c];
+    }
+    // u(x) = al + be x
+    const double inv2A = 0.5 / A;
+    double be = 0.0, al[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+      const double w = s[j] * U[j] * inv2A;
+      be += w;
+#pragma unroll
+      for (int d = 0; d < 3; d++) al[d] -= w * p[j][d];
+    }
+    auto vel = [&](const double *x, double *u) {
+#pragma unroll
+      for (int d = 0; d < 3; d++) u[d] = al[d] + be * x[d];
+    };
+    // ku(x) = k x u(x); q_i(x) = s_i/(2A) ku(x).(x - p_i)
+    auto kxu = [&](const double *x, double *r) {
+      double u[3];
+      vel(x, u);
+      r[0] = k[1] * u[2] - k[2] * u[1];
+      r[1] = k[2] * u[0] - k[0] * u[2];
+      r[2] = k[0] * u[1] - k[1] * u[0];
+    };
+    // kinetic energy integral (side midpoints, weight A/3)
+    double ke = 0.0;
+#pragma unroll
+    for (int q = 0; q < 3; q++) {
+      double x[3], u[3];
+#pragma unroll
+      for (int d = 0; d < 3; d++) x[d] = 0.5 * (p[(q + 1) % 3][d] + p[(q + 2) % 3][d]);
+      vel(x, u);
+      ke += (A / 3.0) * 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    }
+    double ubar[3];
+    {
+      double xb[3];
+#pragma unroll
+      for (int d = 0; d < 3; d++) xb[d] = (p[0][d] + p[1][d] + p[2][d]) * (1.0 / 3.0);
+      vel(xb, ubar);
+    }
+    // k x u at the vertices (for grad q_i)
+    double kuv[3][3];
+#pragma unroll
+    for (int j = 0; j < 3; j++) kxu(p[j], kuv[j]);
+    // k x u and upwind tangential velocity at the six Gauss points
+    double kug[3][2][3], xg[3][2][3], utg[3][2];
+#pragma unroll
+    for (int aa = 0; aa < 3; aa++) {
+      // global order a -> b is the cell's CCW order when s = +1
+      const int ia = s[aa] > 0 ? (aa + 1) % 3 : (aa + 2) % 3;
+      const int ib = s[aa] > 0 ? (aa + 2) % 3 : (aa + 1) % 3;
+      const size_t iedge = (size_t)ed[aa] * Bs + c;
+      utg[aa][0] = a.ut0[iedge];
+      utg[aa][1] = a.ut1[iedge];
+#pragma unroll
+      for (int gp = 0; gp < 2; gp++) {
+        const double xi = gp == 0 ? 0.5 - gq : 0.5 + gq;
+#pragma unroll
+        for (int d = 0; d < 3; d++) xg[aa][gp][d] = p[ia][d] + xi * (p[ib][d] - p[ia][d]);
+        kxu(xg[aa][gp], kug[aa][gp]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+      const double si = s[i] * inv2A;
+      // grad q_i = sum_j q_i(p_j) grad lambda_j
+      double gqv[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int j = 0; j < 3; j++) {
+        if (j == i) continue;
+        double qj = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; d++) qj += kuv[j][d] * (p[j][d] - p[i][d]);
+        qj *= si;
+#pragma unroll
+        for (int d = 0; d < 3; d++) gqv[d] += qj * gl[j][d];
+      }
+      // grad^perp q = k x grad q
+      const double gp0 = k[1] * gqv[2] - k[2] * gqv[1];
+      const double gp1 = k[2] * gqv[0] - k[0] * gqv[2];
+      const double gp2 = k[0] * gqv[1] - k[1] * gqv[0];
+      double Ci = A * (ubar[0] * gp0 + ubar[1] * gp1 + ubar[2] * gp2);
+      Ci += s[i] * ke / A;
+#pragma unroll
+      for (int aa = 0; aa < 3; aa++) {
+        double f = 0.0;
+#pragma unroll
+        for (int gp = 0; gp < 2; gp++) {
+          double qv = 0.0;
+#pragma unroll
+          for (int d = 0; d < 3; d++) qv += kug[aa][gp][d] * (xg[aa][gp][d] - p[i][d]);
+          f += utg[aa][gp] * qv * si;
+        }
+        Ci -= s[aa] * 0.5 * len[aa] * f;
+      }
+      a.C[((size_t)3 * t + i) * Bs + c] = Ci;
+    }
+    // depth: upwind (eta - b) on every side
+    const size_t it = (size_t)t * Bs + c;
+    double r = 0.0;
+#pragma unroll
+    for (int aa = 0; aa < 3; aa++) {
+      const bool up_c0 = U[aa] > 0.0;
+      const bool self_c0 = s[aa] > 0;
+      const int cu = (up_c0 == self_c0) ? t : o.cnbr[3 * t + aa];
+      const double hv = a.eta[(size_t)cu * Bs + c] - o.bottom[cu];
+      r -= s[aa] * U[aa] * hv;
+    }
+    a.out_eta[it] = r * o.inv_area[t];
+  }
+}
+
+// Velocity right-hand side r_e = C[c0][l0] + C[c1][l1] and CG start x = 0.
+__global__ __launch_bounds__(kWG) void k_nl_gather(GatherArgs a) {
+  const Lane L = lane_map(a.Bs);
+  const DevOps &o = a.ops;
+  const int c = L.col, Bs = a.Bs;
+  const bool act = a.colK[c] >= a.kneed;
+  double sums[2] = {0.0, 0.0};
+  if (act) {
+    for (int e = L.row0; e < o.ne; e += L.rstride) {
+      const size_t ie = (size_t)e * Bs + c;
+      const double r = a.C[(size_t)o.cidx[2 * e] * Bs + c] + a.C[(size_t)o.cidx[2 * e + 1] * Bs + c];
+      a.r[ie] = r;
+      a.x[ie] = 0.0;
+      sums[0] += r * r;
+      sums[1] += r * r * o.dinv[e];
+    }
+  }
+  __shared__ double fin[2][64];
+  if (reduce_cols<2>(L, sums, a.rb, fin)) {
+    const SolveState st = a.st;
+    if (threadIdx.x < L.ct) {
+      const int cc = L.tile * L.ct + threadIdx.x;
+      const double bb = fin[0][threadIdx.x];
+      st.bb[cc] = bb;
+      st.rz[cc] = fin[1][threadIdx.x];
+      st.beta[cc] = 0.0;
+      st.iters[cc] = 0;
+      st.resid[cc] = 0.0;
+      st.active[cc] = (a.colK[cc] >= a.kneed && bb > 0.0) ? 1 : 0;
+    }
+    __syncthreads();
+    finish_count(L, st, tile_active_count(L, st));
+  }
+}
+
+// ----------------------------------------------------------- elementwise
+// acc[row][c/G] += sum over the G-column group of coef[c] * in[row][c]
+// (columns with colK[c] >= acc_k), over both row ranges.
+__global__ __launch_bounds__(kWG) void k_acc(AccArgs a) {
+  const Lane L = lane_map(a.Bs);
+  const int c = L.col, Bs = a.Bs;
+  const bool on = a.colK[c] >= a.acc_k;
+  const double coef = on ? a.coef[c] : 0.0;
+  for (int base = L.row0 - L.lane / L.ct; base < a.nrows; base += L.rstride) {
+    const int row = base + L.lane / L.ct;
+    const bool in = row < a.nrows;
+    double v = (in && on) ? coef * a.in[(size_t)row * Bs + c] : 0.0;
+    v = lane_group_sum(v, a.G);
+    if (in && (c % a.G) == 0) a.acc[(size_t)row * (Bs / a.G) + c / a.G] += v;
+  }
+}
+
+// out[i] = a0 x0[i] + a1 x1[i] + a2 x2[i] (null inputs skipped).
+__global__ __launch_bounds__(kWG) void k_axpy(AxpyArgs a) {
+  for (size_t i = (size_t)blockIdx.x * kWG + threadIdx.x; i < a.n; i += (size_t)gridDim.x * kWG) {
+    double v = 0.0;
+    if (a.x0) v += a.a0 * a.x0[i];
+    if (a.x1) v += a.a1 * a.x1[i];
+    if (a.x2) v += a.a2 * a.x2[i];
+    a.out[i] = v;
+  }
+}
+
+// Member-major states [B][n] <-> block [row][Bs] (u rows then eta rows).
+__global__ __launch_bounds__(kWG) void k_to_block(TransArgs a) {
+  const size_t total = (size_t)a.n * a.Bs;
+  for (size_t i = (size_t)blockIdx.x * kWG + threadIdx.x; i < total; i += (size_t)gridDim.x * kWG) {
+    const int row = (int)(i / a.Bs), c = (int)(i % a.Bs);
+    a.blk[i] = c < a.B ? a.states[(size_t)c * a.n + row] : 0.0;
+  }
+}
+__global__ __launch_bounds__(kWG) void k_from_block(TransArgs a) {
+  const size_t total = (size_t)a.n * a.B;
+  for (size_t i = (size_t)blockIdx.x * kWG + threadIdx.x; i < total; i += (size_t)gridDim.x * kWG) {
+    const int c = (int)(i / a.n), row = (int)(i % a.n);
+    a.states[i] = a.blk[(size_t)row * a.Bs + c];
+  }
+}
+
+// Per-column energy inner products <X, Y>_W = H x_u' M y_u + g sum |c| x_eta y_eta
+// and the mass sum |c| x_eta, reduced deterministically into out[3][Bs].
+__global__ __launch_bounds__(kWG) void k_wdot(WdotArgs a) {
+  const Lane L = lane_map(a.Bs);
+  const DevOps &o = a.ops;
+  const int c = L.col, Bs = a.Bs;
+  double sums[2] = {0.0, 0.0};
+  const int nrow = o.ne > o.nc ? o.ne : o.nc;
+  for (int r = L.row0; r < nrow; r += L.rstride) {
+    if (r < o.ne) {
+      double my = 0.0;
+#pragma unroll
+      for (int j = 0; j < 5; j++) my += o.mass[5 * r + j] * a.yu[(size_t)o.ell_col[5 * r + j] * Bs + c];
+      sums[0] += a.H * a.xu[(size_t)r * Bs + c] * my;
+    }
+    if (r < o.nc) {
+      const size_t it = (size_t)r * Bs + c;
+      sums[0] += a.g * o.area[r] * a.xe[it] * a.ye[it];
+      sums[1] += o.area[r] * a.xe[it];
+    }
+  }
+  __shared__ double fin[2][64];
+  if (reduce_cols<2>(L, sums, a.rb, fin)) {
+    if (threadIdx.x < L.ct) {
+      const int cc = L.tile * L.ct + threadIdx.x;
+      a.out[cc] = fin[0][threadIdx.x];
+      a.out[Bs + cc] = fin[1][threadIdx.x];
+    }
+  }
+}
+
+// Clear small integer/double buffers (used instead of memset so that the
+// sequence stays capturable).
+__global__ void k_zero(unsigned *p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+// ------------------------------------------------------------ launchers
+namespace {
+int grid_rows(int rows, int Bs) {
+  const int ct = Bs < 64 ? Bs : 64;
+  const int rows_per_wg = (kWG / 64) * (64 / ct);
+  const int ctiles = (Bs + 63) / 64;
+  int want = (rows + rows_per_wg - 1) / rows_per_wg;
+  // enough workgroups to fill 256 CUs several times over, split over tiles
+  int cap = ctiles >= 8 ? 256 : 2048 / ctiles;
+  return want < cap ? (want > 0 ? want : 1) : cap;
+}
+int grid_flat(size_t n) {
+  size_t g = (n + kWG - 1) / kWG;
+  return (int)(g < 4096 ? (g > 0 ? g : 1) : 4096);
+}
+dim3 rows_grid(int rows, int Bs) { return dim3(grid_rows(rows, Bs), (Bs + 63) / 64); }
+}  // namespace
+
+int launch_max_wg() { return 2048; }
+
+void launch_stiff(const StiffArgs &a, hipStream_t s) {
+  const int nrow = a.ops.ne > a.ops.nc ? a.ops.ne : a.ops.nc;
+  hipLaunchKernelGGL(k_stiff, rows_grid(nrow, a.Bs), dim3(kWG), 0, s, a);
+}
+void launch_cg_a(const CgArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_a, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+}
+void launch_cg_b(const CgArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_b, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+}
+void launch_combine(const CombineArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_combine, dim3(grid_flat((size_t)a.nrows * a.BsE)), dim3(kWG), 0, s, a);
+}
+void launch_reduce_terms(const ReduceTermsArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_terms, dim3(grid_flat((size_t)a.nrows * a.BsY)), dim3(kWG), 0, s, a);
+}
+void launch_nl_upwind(const NlArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_nl_upwind, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+}
+void launch_nl_cell(const NlArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_nl_cell, rows_grid(a.ops.nc, a.Bs), dim3(kWG), 0, s, a);
+}
+void launch_nl_gather(const GatherArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_nl_gather, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+}
+void launch_acc(const AccArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_acc, rows_grid(a.nrows, a.Bs), dim3(kWG), 0, s, a);
+}
+void launch_axpy(const AxpyArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy, dim3(grid_flat(a.n)), dim3(kWG), 0, s, a);
+}
+void launch_to_block(const TransArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_to_block, dim3(grid_flat((size_t)a.n * a.Bs)), dim3(kWG), 0, s, a);
+}
+void launch_from_block(const TransArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_from_block, dim3(grid_flat((size_t)a.n * a.B)), dim3(kWG), 0, s, a);
+}
+void launch_wdot(const WdotArgs &a, hipStream_t s) {
+  const int nrow = a.ops.ne > a.ops.nc ? a.ops.ne : a.ops.nc;
+  hipLaunchKernelGGL(k_wdot, rows_grid(nrow, a.Bs), dim3(kWG), 0, s, a);
+}
+void launch_zero(unsigned *p, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero, dim3(grid_flat(n)), dim3(kWG), 0, s, p, n);
+}
+
+}  // namespace pa

@@ -1,0 +1,333 @@
+"""ctypes binding of libpa.so (C ABI in include/pa.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  PyTorch provides device memory (tensors) and the stream.  A missing
+library is an error; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpa.so")
+
+PA_FP64, PA_FP32_REFINED = 0, 1
+PA_BACKWARD_PER_TERM, PA_BACKWARD_CLENSHAW = 0, 1
+_STATUS = {0: "PA_OK", 1: "PA_EINVAL", 2: "PA_ENOMEM", 3: "PA_EHIP", 4: "PA_ENOCONV",
+           5: "PA_ENOTSUP", 6: "PA_EGROWTH"}
+
+
+class PAError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class MeshInfo(ctypes.Structure):
+    _fields_ = [("level", ctypes.c_int32), ("nv", ctypes.c_int32), ("ne", ctypes.c_int32),
+                ("nc", ctypes.c_int32), ("radius", ctypes.c_double)]
+
+
+class Phys(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_double), ("H", ctypes.c_double), ("omega", ctypes.c_double),
+                ("b_cell", ctypes.POINTER(ctypes.c_double)), ("lambda_bar", ctypes.c_double)]
+
+
+class SolveCfg(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("backward", ctypes.c_int32),
+                ("maxit", ctypes.c_int32), ("growth_guard", ctypes.c_int32),
+                ("cg_rtol", ctypes.c_double), ("cheb_tol", ctypes.c_double),
+                ("weight_cut", ctypes.c_double), ("inner_rtol", ctypes.c_double)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("solves", ctypes.c_int32), ("cg_iters", ctypes.c_int32),
+                ("cg_iters_max", ctypes.c_int32), ("kmax", ctypes.c_int32),
+                ("ksum", ctypes.c_int32), ("terms", ctypes.c_int32),
+                ("refinements", ctypes.c_int32), ("guard_trips", ctypes.c_int32),
+                ("resid_max", ctypes.c_double), ("device_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+_V = ctypes.c_void_p
+_D = ctypes.POINTER(ctypes.c_double)
+_I = ctypes.POINTER(ctypes.c_int32)
+_SZ = ctypes.c_size_t
+
+EXPORTS = {
+    "pa_last_error": (ctypes.c_char_p, []),
+    "pa_ctx_create": (ctypes.c_int, [ctypes.c_int, _V, ctypes.POINTER(_V)]),
+    "pa_ctx_set_stream": (ctypes.c_int, [_V, _V]),
+    "pa_ctx_destroy": (ctypes.c_int, [_V]),
+    "pa_mesh_icosahedral": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.POINTER(_V)]),
+    "pa_mesh_get_info": (ctypes.c_int, [_V, ctypes.POINTER(MeshInfo)]),
+    "pa_mesh_export": (ctypes.c_int, [_V, _D, _I, _I, _I, _I]),
+    "pa_mesh_destroy": (ctypes.c_int, [_V]),
+    "pa_ops_create": (ctypes.c_int, [_V, ctypes.POINTER(Phys), ctypes.POINTER(_V)]),
+    "pa_ops_device_size": (ctypes.c_int, [_V, ctypes.POINTER(_SZ)]),
+    "pa_ops_bind": (ctypes.c_int, [_V, _V, _V]),
+    "pa_ops_estimate_lambda": (ctypes.c_int, [_V, _V, ctypes.c_int, ctypes.c_double, _V, _SZ,
+                                              _D]),
+    "pa_ops_set_lambda": (ctypes.c_int, [_V, ctypes.c_double]),
+    "pa_ops_get_lambda": (ctypes.c_int, [_V, _D]),
+    "pa_ops_destroy": (ctypes.c_int, [_V]),
+    "pa_avg_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.POINTER(_V)]),
+    "pa_avg_create_nodes": (ctypes.c_int, [ctypes.c_int, _D, _D, ctypes.POINTER(_V)]),
+    "pa_avg_nodes": (ctypes.c_int, [_V, _D, _D]),
+    "pa_avg_destroy": (ctypes.c_int, [_V]),
+    "pa_solve_cfg_default": (None, [ctypes.POINTER(SolveCfg)]),
+    "pa_workspace_size": (ctypes.c_int, [_V, _V, ctypes.c_int, ctypes.POINTER(SolveCfg),
+                                         ctypes.POINTER(_SZ)]),
+    "pa_expL_apply": (ctypes.c_int, [_V, _V, ctypes.c_int, _D, _V, _V, _V, _SZ,
+                                     ctypes.POINTER(SolveCfg), ctypes.POINTER(Stats)]),
+    "pa_swe_nonlinear": (ctypes.c_int, [_V, _V, ctypes.c_int, _V, _V, _V, _SZ,
+                                        ctypes.POINTER(SolveCfg), ctypes.POINTER(Stats)]),
+    "pa_phase_avg_rhs": (ctypes.c_int, [_V, _V, _V, ctypes.c_int, _V, _V, _V, _SZ,
+                                        ctypes.POINTER(SolveCfg), ctypes.POINTER(Stats)]),
+    "pa_step": (ctypes.c_int, [_V, _V, _V, ctypes.c_double, ctypes.c_int, _V, _V, _SZ,
+                               ctypes.POINTER(SolveCfg), ctypes.POINTER(Stats)]),
+    "pa_diagnostics": (ctypes.c_int, [_V, _V, ctypes.c_int, _V, _V, _SZ, _D]),
+}
+
+
+def lib():
+    """Open libpa.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it first "
+                               "(python -c 'import __graft_entry__ as g; g.build()')")
+        # Share PyTorch's HIP runtime: initialise it before the library binds
+        # libamdhip64, so that one runtime serves both (on a machine without a
+        # GPU only the host-side entry points are usable).
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != 0:
+        raise PAError(code, lib().pa_last_error().decode())
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor."""
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dp(a):
+    return a.ctypes.data_as(_D)
+
+
+def solve_cfg(precision=PA_FP64, backward=PA_BACKWARD_PER_TERM, maxit=None, cg_rtol=None,
+              cheb_tol=None, weight_cut=None, inner_rtol=None) -> SolveCfg:
+    c = SolveCfg()
+    lib().pa_solve_cfg_default(ctypes.byref(c))
+    c.precision = precision
+    c.backward = backward
+    if maxit is not None:
+        c.maxit = maxit
+    if cg_rtol is not None:
+        c.cg_rtol = cg_rtol
+    if cheb_tol is not None:
+        c.cheb_tol = cheb_tol
+    if weight_cut is not None:
+        c.weight_cut = weight_cut
+    if inner_rtol is not None:
+        c.inner_rtol = inner_rtol
+    return c
+
+
+class Context:
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        h = _V()
+        _check(lib().pa_ctx_create(device, _V(stream), ctypes.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.pa_ctx_destroy(self._h)
+            self._h = None
+
+
+class Mesh:
+    """Icosahedral mesh (host)."""
+
+    def __init__(self, level: int, radius: float = 6.37122e6):
+        h = _V()
+        _check(lib().pa_mesh_icosahedral(level, radius, ctypes.byref(h)))
+        self._h = h
+        info = MeshInfo()
+        _check(lib().pa_mesh_get_info(h, ctypes.byref(info)))
+        self.level, self.nv, self.ne, self.nc = info.level, info.nv, info.ne, info.nc
+        self.radius = info.radius
+        self.verts = np.zeros((self.nv, 3))
+        self.cell_verts = np.zeros((self.nc, 3), np.int32)
+        self.cell_edges = np.zeros((self.nc, 3), np.int32)
+        self.edge_cells = np.zeros((self.ne, 2), np.int32)
+        self.edge_verts = np.zeros((self.ne, 2), np.int32)
+        _check(lib().pa_mesh_export(h, _dp(self.verts), self.cell_verts.ctypes.data_as(_I),
+                                    self.cell_edges.ctypes.data_as(_I),
+                                    self.edge_cells.ctypes.data_as(_I),
+                                    self.edge_verts.ctypes.data_as(_I)))
+
+    @property
+    def n(self):
+        return self.ne + self.nc
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.pa_mesh_destroy(self._h)
+            self._h = None
+
+
+class Avg:
+    """Averaging nodes and weights (Sec. 2.2)."""
+
+    def __init__(self, M: int = None, T: float = None, s=None, w=None):
+        h = _V()
+        if s is not None:
+            s = np.ascontiguousarray(s, np.float64)
+            w = np.ascontiguousarray(w, np.float64)
+            _check(lib().pa_avg_create_nodes(len(s), _dp(s), _dp(w), ctypes.byref(h)))
+            M = len(s)
+        else:
+            _check(lib().pa_avg_create(M, T, ctypes.byref(h)))
+        self._h = h
+        self.M = M
+        self.s = np.zeros(M)
+        self.w = np.zeros(M)
+        _check(lib().pa_avg_nodes(h, _dp(self.s), _dp(self.w)))
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.pa_avg_destroy(self._h)
+            self._h = None
+
+
+class Ops:
+    """Operators bound to a device buffer, with a workspace cache."""
+
+    def __init__(self, ctx: Context, mesh: Mesh, g=9.80616, H=1000.0, omega=7.292e-5, b=None,
+                 lambda_bar=0.0):
+        import torch
+        self.ctx, self.mesh = ctx, mesh
+        self.g, self.H, self.omega = g, H, omega
+        self._b = None if b is None else np.ascontiguousarray(b, np.float64)
+        ph = Phys(g, H, omega, None if self._b is None else _dp(self._b), lambda_bar)
+        h = _V()
+        _check(lib().pa_ops_create(mesh._h, ctypes.byref(ph), ctypes.byref(h)))
+        self._h = h
+        sz = _SZ()
+        _check(lib().pa_ops_device_size(h, ctypes.byref(sz)))
+        self._buf = torch.empty(sz.value + 256, dtype=torch.uint8, device=f"cuda:{ctx.device}")
+        base = self._buf.data_ptr()
+        off = (-base) % 256
+        _check(lib().pa_ops_bind(ctx._h, h, _V(base + off)))
+        self._ws = None
+
+    @property
+    def n(self):
+        return self.mesh.n
+
+    @property
+    def lambda_bar(self):
+        v = ctypes.c_double()
+        _check(lib().pa_ops_get_lambda(self._h, ctypes.byref(v)))
+        return v.value
+
+    @lambda_bar.setter
+    def lambda_bar(self, value):
+        _check(lib().pa_ops_set_lambda(self._h, float(value)))
+
+    def workspace(self, avg=None, batch=1, cfg=None):
+        import torch
+        cfg = cfg or solve_cfg()
+        sz = _SZ()
+        _check(lib().pa_workspace_size(self._h, None if avg is None else avg._h, batch,
+                                       ctypes.byref(cfg), ctypes.byref(sz)))
+        if self._ws is None or self._ws.numel() < sz.value + 256:
+            self._ws = None
+            self._ws = torch.empty(sz.value + 256, dtype=torch.uint8,
+                                   device=f"cuda:{self.ctx.device}")
+        base = self._ws.data_ptr()
+        off = (-base) % 256
+        return _V(base + off), self._ws.numel() - off
+
+    def estimate_lambda(self, iters=200, safety=1.05):
+        ws, nb = self.workspace()
+        v = ctypes.c_double()
+        _check(lib().pa_ops_estimate_lambda(self.ctx._h, self._h, iters, safety, ws, nb,
+                                            ctypes.byref(v)))
+        return v.value
+
+    # ---- the hot path -------------------------------------------------------
+    def expL_apply(self, t, U, cfg=None, out=None):
+        cfg = cfg or solve_cfg()
+        B = U.shape[0]
+        t = np.ascontiguousarray(np.broadcast_to(np.asarray(t, np.float64), (B,)))
+        out = U.new_empty(U.shape) if out is None else out
+        ws, nb = self.workspace(None, B, cfg)
+        st = Stats()
+        _check(lib().pa_expL_apply(self.ctx._h, self._h, B, _dp(t), _ptr(U), _ptr(out), ws, nb,
+                                   ctypes.byref(cfg), ctypes.byref(st)))
+        return out, st.as_dict()
+
+    def swe_nonlinear(self, U, cfg=None, out=None):
+        cfg = cfg or solve_cfg()
+        B = U.shape[0]
+        out = U.new_empty(U.shape) if out is None else out
+        ws, nb = self.workspace(None, B, cfg)
+        st = Stats()
+        _check(lib().pa_swe_nonlinear(self.ctx._h, self._h, B, _ptr(U), _ptr(out), ws, nb,
+                                      ctypes.byref(cfg), ctypes.byref(st)))
+        return out, st.as_dict()
+
+    def phase_avg_rhs(self, avg: Avg, U, cfg=None, out=None):
+        cfg = cfg or solve_cfg()
+        members = U.shape[0]
+        out = U.new_empty(U.shape) if out is None else out
+        ws, nb = self.workspace(avg, members, cfg)
+        st = Stats()
+        _check(lib().pa_phase_avg_rhs(self.ctx._h, self._h, avg._h, members, _ptr(U), _ptr(out),
+                                      ws, nb, ctypes.byref(cfg), ctypes.byref(st)))
+        return out, st.as_dict()
+
+    def step(self, avg: Avg, dt: float, U, cfg=None):
+        cfg = cfg or solve_cfg()
+        members = U.shape[0]
+        ws, nb = self.workspace(avg, members, cfg)
+        st = Stats()
+        _check(lib().pa_step(self.ctx._h, self._h, avg._h, dt, members, _ptr(U), ws, nb,
+                             ctypes.byref(cfg), ctypes.byref(st)))
+        return U, st.as_dict()
+
+    def diagnostics(self, U):
+        B = U.shape[0]
+        ws, nb = self.workspace(None, B)
+        out = np.zeros(5 * B)
+        _check(lib().pa_diagnostics(self.ctx._h, self._h, B, _ptr(U), ws, nb, _dp(out)))
+        return out.reshape(B, 5)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.pa_ops_destroy(self._h)
+            self._h = None

@@ -1,0 +1,117 @@
+"""GPU parity: the HIP path through the C ABI against the oracle, element by
+element after mapping the two mesh numberings, on the same seeded inputs.
+
+Tolerance: relative 1e-12 in the energy norm ||.||_W (where L is skew and
+the exponential is an isometry) for FP64 with both sides in parity mode
+(Chebyshev threshold 1e-13, CG to 1e-14), plus a max-norm check per block.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import PARITY, bumps, pair, rel_w, to_dev
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _maxrel(a, b, ne):
+    ua, ub = a[..., :ne], b[..., :ne]
+    ea, eb = a[..., ne:], b[..., ne:]
+    return max(np.abs(ua - ub).max() / np.abs(ub).max(), np.abs(ea - eb).max() / np.abs(eb).max())
+
+
+@pytest.mark.parametrize("level", [2, 3])
+def test_gpu_expL_parity(level):
+    from paper_2103_07706_amd import pa
+    om, oo, lm, lo, mm, lb = pair(level)
+    ts = [600.0, -1800.0, 3600.0, 0.0, 7200.0]
+    U = bumps(om, range(len(ts)))
+    out, st = lo.expL_apply(ts, to_dev(mm.state(U)), pa.solve_cfg(**PARITY))
+    got = mm.back(out.cpu().numpy())
+    for j, t in enumerate(ts):
+        ref, K = oo.expL(lb, t, U[j], tol=1e-13, rtol=1e-14)
+        assert rel_w(oo, got[j], ref) < TOL, (t, rel_w(oo, got[j], ref))
+    assert st["cg_iters_max"] <= 30
+
+
+def test_gpu_nonlinear_parity():
+    from paper_2103_07706_amd import pa
+    om, oo, lm, lo, mm, lb = pair(3)
+    U = bumps(om, [0, 1, 2])
+    out, st = lo.swe_nonlinear(to_dev(mm.state(U)), pa.solve_cfg(**PARITY))
+    got = mm.back(out.cpu().numpy())
+    for j in range(3):
+        ref = oo.nonlinear(U[j], rtol=1e-14)
+        assert rel_w(oo, got[j], ref) < TOL
+        assert _maxrel(got[j], ref, om.ne) < 1e-11
+
+
+@pytest.mark.parametrize("backward", ["per_term", "clenshaw"])
+@pytest.mark.parametrize("M,T", [(8, 3600.0), (5, 2000.0), (1, 1000.0)])
+def test_gpu_phase_avg_rhs_parity(backward, M, T):
+    from paper_2103_07706_amd import pa
+    om, oo, lm, lo, mm, lb = pair(3)
+    U = bumps(om, [0])
+    avg = pa.Avg(M, T)
+    bw = pa.PA_BACKWARD_PER_TERM if backward == "per_term" else pa.PA_BACKWARD_CLENSHAW
+    cfg = pa.solve_cfg(backward=bw, weight_cut=0.0, **PARITY)
+    out, st = lo.phase_avg_rhs(avg, to_dev(mm.state(U)), cfg)
+    got = mm.back(out.cpu().numpy())[0]
+    ref = oo.phase_avg_rhs(lb, avg.s, avg.w, U[0], tol=1e-13, rtol=1e-14)
+    assert rel_w(oo, got, ref) < TOL, rel_w(oo, got, ref)
+    assert st["terms"] == M
+
+
+def test_gpu_phase_avg_members_independent():
+    """Several ensemble members in one call equal separate calls."""
+    from paper_2103_07706_amd import pa
+    om, oo, lm, lo, mm, lb = pair(3)
+    U = mm.state(bumps(om, [3, 4, 5]))
+    avg = pa.Avg(6, 3000.0)
+    cfg = pa.solve_cfg(**PARITY)
+    allm, _ = lo.phase_avg_rhs(avg, to_dev(U), cfg)
+    allm = allm.cpu().numpy()
+    for j in range(3):
+        one, _ = lo.phase_avg_rhs(avg, to_dev(U[j:j + 1]), cfg)
+        ref = mm.back(one.cpu().numpy()[0])
+        assert rel_w(oo, mm.back(allm[j]), ref) < 1e-13
+
+
+def test_gpu_step_parity():
+    from paper_2103_07706_amd import pa
+    om, oo, lm, lo, mm, lb = pair(3)
+    U = bumps(om, [0])
+    avg = pa.Avg(8, 3600.0)
+    cfg = pa.solve_cfg(weight_cut=0.0, **PARITY)
+    Ud = to_dev(mm.state(U))
+    lo.step(avg, 1800.0, Ud, cfg)
+    got = mm.back(Ud.cpu().numpy())[0]
+    ref = oo.step(lb, avg.s, avg.w, 1800.0, U[0], tol=1e-13, rtol=1e-14)
+    assert rel_w(oo, got, ref) < TOL, rel_w(oo, got, ref)
+
+
+def test_gpu_deterministic():
+    from paper_2103_07706_amd import pa
+    om, oo, lm, lo, mm, lb = pair(3)
+    U = to_dev(mm.state(bumps(om, [0, 1])))
+    avg = pa.Avg(8, 3600.0)
+    a, _ = lo.phase_avg_rhs(avg, U)
+    b, _ = lo.phase_avg_rhs(avg, U)
+    assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+
+
+def test_gpu_lambda_estimate():
+    om, oo, lm, lo, mm, lb = pair(3)
+    est = lo.estimate_lambda(iters=200, safety=1.05)
+    assert abs(est / lb - 1) < 0.03
+    lo.lambda_bar = lb
+
+
+def test_gpu_diagnostics_mass_energy():
+    om, oo, lm, lo, mm, lb = pair(3)
+    U = bumps(om, [0, 1])
+    d = lo.diagnostics(to_dev(mm.state(U)))
+    for j in range(2):
+        ref = oo.diagnostics(U[j])
+        assert abs(d[j, 0] / ref["mass"] - 1) < 1e-13
+        assert abs(d[j, 1] / ref["energy_linear"] - 1) < 1e-13
