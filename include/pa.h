@@ -188,6 +188,23 @@ int pa_step(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, double dt,
 int pa_diagnostics(pa_ctx *ctx, const pa_ops *ops, int B, const double *U_dev,
                    void *ws_dev, size_t ws_bytes, double *out_host);
 
+/* ---- measurement hook -----------------------------------------------------
+ * Brackets every launch of one kernel on the context's stream with HIP
+ * events and counts the algorithmic bytes it moves (operands it must stream
+ * at least once per launch, for the columns still active in the launch).
+ * pa_ctx_profile starts a new tally (PA_KERNEL_NONE switches it off);
+ * pa_ctx_profile_read returns the tally so far.  The calls made while the
+ * hook is on fill it; reading needs no further synchronisation. */
+enum { PA_KERNEL_NONE = 0, PA_KERNEL_CG_SPMV = 1, PA_KERNEL_CG_UPDATE = 2 };
+typedef struct {
+  int64_t launches;   /* launches of the kernel */
+  int64_t work_launches; /* launches that found active columns */
+  double total_ms;    /* summed event time of all launches */
+  double bytes;       /* algorithmic bytes of all launches */
+} pa_kernel_profile;
+int pa_ctx_profile(pa_ctx *ctx, int kernel);
+int pa_ctx_profile_read(pa_ctx *ctx, pa_kernel_profile *out);
+
 #ifdef __cplusplus
 }
 #endif

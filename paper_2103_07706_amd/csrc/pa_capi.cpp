@@ -65,9 +65,30 @@ int pa_ctx_set_stream(pa_ctx *ctx, void *stream) {
   });
 }
 
+int pa_ctx_profile(pa_ctx *ctx, int kernel) {
+  return guard([&] {
+    need(ctx != nullptr, "ctx is NULL");
+    need(kernel >= PA_KERNEL_NONE && kernel <= PA_KERNEL_CG_UPDATE, "unknown kernel id");
+    ctx->prof_kernel = kernel;
+    ctx->prof_launches = ctx->prof_work = 0;
+    ctx->prof_ms = ctx->prof_bytes = 0.0;
+  });
+}
+
+int pa_ctx_profile_read(pa_ctx *ctx, pa_kernel_profile *out) {
+  return guard([&] {
+    need(ctx && out, "NULL argument");
+    out->launches = ctx->prof_launches;
+    out->work_launches = ctx->prof_work;
+    out->total_ms = ctx->prof_ms;
+    out->bytes = ctx->prof_bytes;
+  });
+}
+
 int pa_ctx_destroy(pa_ctx *ctx) {
   return guard([&] {
     if (!ctx) return;
+    for (auto e : ctx->prof_pool) (void)hipEventDestroy(e);
     if (ctx->host_flag) (void)hipHostFree(ctx->host_flag);
     delete ctx;
   });

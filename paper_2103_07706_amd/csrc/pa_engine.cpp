@@ -56,22 +56,16 @@ void Engine::plan_common(int BsMax) {
   st_.iters = ar_.take<int>(BsMax);
   colK0_ = ar_.take<int>(BsMax);
   rb_.max_wg = launch_max_wg();
-  rb_.max_groups = (rb_.max_wg + 31) / 32;
   rb_.part = ar_.take<double>((size_t)tiles * rb_.max_wg * 2 * 64);
-  rb_.gpart = ar_.take<double>((size_t)tiles * rb_.max_groups * 2 * 64);
-  // everything below is cleared at the start of each call
-  zero_words_ = (size_t)tiles * (1 + rb_.max_groups) + tiles + 4 + 64;
+  // counters, cleared at the start of each call
+  zero_words_ = 64;
   zero_base_ = ar_.take<unsigned>(zero_words_);
   if (zero_base_) {
     unsigned *z = zero_base_;
-    rb_.tickets = z;
-    z += (size_t)tiles * (1 + rb_.max_groups);
-    st_.tile_active = (int *)z;
-    z += tiles;
-    st_.tile_ticket = z;
-    st_.n_active = (int *)(z + 1);
+    st_.cnt = (int *)z;
     st_.fail = (int *)(z + 2);
     st_.iter_max = (int *)(z + 3);
+    st_.prof = z + 4;
   }
 }
 
@@ -99,9 +93,27 @@ void Engine::begin() {
 
 void Engine::finish() {
   PA_HIP(hipEventRecord(ev1_, s_));
-  int h[2] = {0, 0};
-  PA_HIP(hipMemcpyAsync(h, st_.fail, 2 * sizeof(int), hipMemcpyDeviceToHost, s_));
+  int h[4] = {0, 0, 0, 0};
+  PA_HIP(hipMemcpyAsync(h, st_.fail, 4 * sizeof(int), hipMemcpyDeviceToHost, s_));
   PA_HIP(hipStreamSynchronize(s_));
+  if (ctx_->prof_kernel != PA_KERNEL_NONE) {
+    for (size_t i = 0; i + 1 < prof_ev_.size(); i += 2) {
+      float t = 0;
+      PA_HIP(hipEventElapsedTime(&t, prof_ev_[i], prof_ev_[i + 1]));
+      ctx_->prof_ms += t;
+    }
+    ctx_->prof_launches += (int64_t)prof_ev_.size() / 2;
+    for (auto ev : prof_ev_) ctx_->prof_pool.push_back(ev);
+    prof_ev_.clear();
+    // algorithmic bytes: per active column and row, the vectors the kernel
+    // must stream once; per row and launch, the matrix row it reads
+    const double cols = (unsigned)h[2], work = (unsigned)h[3];
+    if (ctx_->prof_kernel == PA_KERNEL_CG_SPMV)   // r, p_old in; p_new, q out; ELL row + dinv
+      ctx_->prof_bytes += (double)ne_ * (32.0 * cols + 68.0 * work);
+    else if (ctx_->prof_kernel == PA_KERNEL_CG_UPDATE)  // x, p, r, q in; x, r out; dinv
+      ctx_->prof_bytes += (double)ne_ * (48.0 * cols + 8.0 * work);
+    ctx_->prof_work += (int64_t)work;
+  }
   float ms = 0;
   PA_HIP(hipEventElapsedTime(&ms, ev0_, ev1_));
   (void)hipEventDestroy(ev0_);
@@ -111,6 +123,47 @@ void Engine::finish() {
   stats.cg_iters_max = std::max(stats.cg_iters_max, h[1]);
   if (h[0] > 0)
     throw Error(PA_ENOCONV, std::to_string(h[0]) + " mass-solve column(s) did not converge within maxit");
+}
+
+// Column sums of the set-up kernel's partials: bb = r.r, rz = r.z and the
+// initial active set (count into slot 1, the slot iteration 0 reads).
+void Engine::finalize_init(int nwg, int Bs, const int *colK, int kneed) {
+  FinArgs f{};
+  f.mode = FIN_INIT;
+  f.Bs = Bs;
+  f.nwg = nwg;
+  f.max_wg = rb_.max_wg;
+  f.nq = 2;
+  f.part = rb_.part;
+  f.st = st_;
+  f.colK = colK;
+  f.kneed = kneed;
+  f.slot_out = 1;
+  launch_finalize(f, s_);
+}
+
+void Engine::wdot_out(int Bs, double *out) {
+  FinArgs f{};
+  f.mode = FIN_OUT;
+  f.Bs = Bs;
+  f.nwg = launch_rows_grid(std::max(ne_, nc_), Bs);
+  f.max_wg = rb_.max_wg;
+  f.nq = 2;
+  f.part = rb_.part;
+  f.st = st_;
+  f.out = out;
+  launch_finalize(f, s_);
+}
+
+hipEvent_t Engine::take_event() {
+  if (!ctx_->prof_pool.empty()) {
+    hipEvent_t e = ctx_->prof_pool.back();
+    ctx_->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  PA_HIP(hipEventCreate(&e));
+  return e;
 }
 
 void Engine::axpy(size_t n, double *out, double a0, const double *x0, double a1, const double *x1,
@@ -134,19 +187,51 @@ void Engine::cg(double *x, int Bs) {
   a.maxit = cfg_.maxit;
   a.st = st_;
   a.rb = rb_;
+  a.count_cols = ctx_->prof_kernel;
   double *pold = p0_, *pnew = p1_;
+  auto timed = [&](int which, auto launch) {
+    if (ctx_->prof_kernel != which) {
+      launch();
+      return;
+    }
+    hipEvent_t e0 = take_event(), e1 = take_event();
+    PA_HIP(hipEventRecord(e0, s_));
+    launch();
+    PA_HIP(hipEventRecord(e1, s_));
+    prof_ev_.push_back(e0);
+    prof_ev_.push_back(e1);
+  };
   int it = 0, chunk = std::max(1, std::min(predicted_, cfg_.maxit));
   int *hflag = (int *)ctx_->host_flag;
+  FinArgs fa{};
+  fa.Bs = Bs;
+  fa.nwg = launch_rows_grid(ne_, Bs);
+  fa.max_wg = rb_.max_wg;
+  fa.part = rb_.part;
+  fa.st = st_;
+  fa.rtol2 = a.rtol2;
+  fa.maxit = a.maxit;
   for (;;) {
     for (int i = 0; i < chunk; i++) {
+      const int k = it + i;
       a.p_old = pold;
       a.p_new = pnew;
-      launch_cg_a(a, s_);
-      launch_cg_b(a, s_);
+      a.slot_in = (k + 1) & 1;  // count written by the previous finalize
+      timed(PA_KERNEL_CG_SPMV, [&] { launch_cg_a(a, s_); });
+      fa.mode = FIN_ALPHA;
+      fa.nq = 1;
+      fa.slot_in = (k + 1) & 1;
+      fa.slot_zero = k & 1;
+      launch_finalize(fa, s_);
+      timed(PA_KERNEL_CG_UPDATE, [&] { launch_cg_b(a, s_); });
+      fa.mode = FIN_BETA;
+      fa.nq = 2;
+      fa.slot_out = k & 1;
+      launch_finalize(fa, s_);
       std::swap(pold, pnew);
     }
     it += chunk;
-    PA_HIP(hipMemcpyAsync(hflag, st_.n_active, sizeof(int), hipMemcpyDeviceToHost, s_));
+    PA_HIP(hipMemcpyAsync(hflag, st_.cnt + ((it - 1) & 1), sizeof(int), hipMemcpyDeviceToHost, s_));
     PA_HIP(hipStreamSynchronize(s_));
     if (*hflag == 0 || it >= cfg_.maxit) break;
     chunk = 1;
@@ -190,6 +275,7 @@ void Engine::lstep(Blk in, Blk out, const Blk *A, const Blk *B, double scale, co
   a.st = st_;
   a.rb = rb_;
   launch_stiff(a, s_);
+  finalize_init(launch_rows_grid(std::max(ne_, nc_), in.Bs), in.Bs, colK, kneed);
   cg(out.p, in.Bs);
 }
 
@@ -250,6 +336,7 @@ void Engine::nonlinear_block(Blk E, Blk Y, const int *colK) {
   gth.st = st_;
   gth.rb = rb_;
   launch_nl_gather(gth, s_);
+  finalize_init(launch_rows_grid(ne_, E.Bs), E.Bs, colK, 0);
   cg(Y.p, E.Bs);
 }
 
@@ -558,6 +645,7 @@ double Engine::estimate_lambda(int iters) {
     w.out = wd;
     w.rb = rb_;
     launch_wdot(w, s_);
+    wdot_out(1, wd);
     double hv[2];
     PA_HIP(hipMemcpyAsync(hv, wd, 2 * sizeof(double), hipMemcpyDeviceToHost, s_));
     PA_HIP(hipStreamSynchronize(s_));
@@ -597,6 +685,7 @@ void Engine::diagnostics(int B, const double *U, double *out_host) {
   w.out = wd;
   w.rb = rb_;
   launch_wdot(w, s_);
+  wdot_out(Bs, wd);
   std::vector<double> h(2 * (size_t)Bs);
   PA_HIP(hipMemcpyAsync(h.data(), wd, h.size() * sizeof(double), hipMemcpyDeviceToHost, s_));
   finish();

@@ -83,6 +83,10 @@ class Engine {
   void axpy(size_t n, double *out, double a0, const double *x0, double a1 = 0,
             const double *x1 = nullptr, double a2 = 0, const double *x2 = nullptr);
   void upload(void *dst, const void *src, size_t bytes);
+  hipEvent_t take_event();
+  void finalize_init(int nwg, int Bs, const int *colK, int kneed);
+  void wdot_out(int Bs, double *out);
+  std::vector<hipEvent_t> prof_ev_;
 
   // phase average on a block of member columns X -> out (both [n][Bm])
   struct NbarBufs {

@@ -78,6 +78,11 @@ struct pa_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   void *host_flag = nullptr;  // pinned host word for convergence polling
+  // measurement hook (pa_ctx_profile)
+  int prof_kernel = 0;
+  std::vector<hipEvent_t> prof_pool;
+  int64_t prof_launches = 0, prof_work = 0;
+  double prof_ms = 0.0, prof_bytes = 0.0;
 };
 
 struct pa_mesh {

@@ -6,23 +6,20 @@
 
 namespace pa {
 
-// Scratch of the deterministic two-level column reductions.
+// Per-workgroup partial column sums: [tiles][max_wg][nq][64].
 struct RedBuf {
-  double *part = nullptr;      // [tiles][max_wg][2][64]
-  double *gpart = nullptr;     // [tiles][max_groups][2][64]
-  unsigned *tickets = nullptr; // [tiles][1 + max_groups]
-  int max_wg = 0, max_groups = 0;
+  double *part = nullptr;
+  int max_wg = 0;
 };
 
 // Per-column state of one batched CG solve (arrays of Bs entries).
 struct SolveState {
   double *bb, *rz, *alpha, *beta, *resid;
   int *active, *iters;
-  int *tile_active;       // [tiles]
-  unsigned *tile_ticket;  // 1
-  int *n_active;          // 1
+  int *cnt;               // [2]: active columns after the last finalize, by parity
   int *fail;              // 1 (accumulates over solves)
   int *iter_max;          // 1 (accumulates over solves)
+  unsigned *prof;         // [2]: active columns summed over launches, work launches
 };
 
 struct StiffArgs {
@@ -46,11 +43,26 @@ struct StiffArgs {
 struct CgArgs {
   DevOps ops;
   int Bs;
+  int count_cols;  // measurement hook: tally active columns of each launch
+  int slot_in;     // cnt slot holding the active count (early exit when 0)
   double *x, *r, *p_old, *p_new, *q;
   double rtol2;
   int maxit;
   SolveState st;
   RedBuf rb;
+};
+
+enum { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_OUT = 3 };
+struct FinArgs {
+  int mode, Bs, nwg, max_wg, nq;
+  const double *part;
+  SolveState st;
+  const int *colK;
+  int kneed;
+  double rtol2;
+  int maxit;
+  int slot_in, slot_out, slot_zero;
+  double *out;
 };
 
 struct CombineArgs {
@@ -114,6 +126,8 @@ struct WdotArgs {
 };
 
 int launch_max_wg();
+int launch_rows_grid(int rows, int Bs);
+void launch_finalize(const FinArgs &a, hipStream_t s);
 void launch_stiff(const StiffArgs &a, hipStream_t s);
 void launch_cg_a(const CgArgs &a, hipStream_t s);
 void launch_cg_b(const CgArgs &a, hipStream_t s);

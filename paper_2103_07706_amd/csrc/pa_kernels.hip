@@ -51,101 +51,38 @@ __device__ inline double lane_group_sum(double v, int G) {
   return v;
 }
 
-// Two-level deterministic reduction of NQ per-column quantities.  Every
-// thread passes its contributions; returns true in the one workgroup (per
-// column tile) that sees the final sums, which are then in out[q][c] (LDS,
-// c < ct).  Layout of the partial buffers: part[tile][wg][q][64],
-// gpart[tile][group][q][64]; tickets[tile][1 + groups].
+// Per-workgroup column sums of NQ quantities: wave shuffles, then LDS over the
+// four waves, stored to part[tile][wg][q][64] with plain stores.  The
+// cross-workgroup sum is done by k_finalize after the kernel boundary, which
+// gives the coherence that per-workgroup device-scope fences would otherwise
+// buy with an L2 write-back and invalidate per workgroup.
 template <int NQ>
-__device__ bool reduce_cols(const Lane &L, double (&v)[NQ], RedBuf rb, double (*out)[64]) {
+__device__ void wg_partials(const Lane &L, double (&v)[NQ], double *part, int max_wg) {
   __shared__ double red[NQ][kWG / 64][64];
-  __shared__ int flag;
   for (int q = 0; q < NQ; q++) {
     double s = wave_col_sum(v[q], L.ct);
     if (L.lane < L.ct) red[q][L.wave][L.lane] = s;
   }
   __syncthreads();
-  const int nwg = gridDim.x, ngroups = (nwg + kGroup - 1) / kGroup;
-  double *part = rb.part + (size_t)L.tile * rb.max_wg * NQ * 64;
-  double *gpart = rb.gpart + (size_t)L.tile * rb.max_groups * NQ * 64;
-  unsigned *tk = rb.tickets + (size_t)L.tile * (1 + rb.max_groups);
   if (threadIdx.x < NQ * 64) {
-    int q = threadIdx.x / 64, c = threadIdx.x % 64;
+    const int q = threadIdx.x / 64, c = threadIdx.x % 64;
     if (c < L.ct) {
       double s = 0;
       for (int w = 0; w < kWG / 64; w++) s += red[q][w][c];
-      __hip_atomic_store(&part[((size_t)blockIdx.x * NQ + q) * 64 + c], s, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
+      part[(((size_t)L.tile * max_wg + blockIdx.x) * NQ + q) * 64 + c] = s;
     }
-  }
-  __threadfence();
-  __syncthreads();
-  const int grp = blockIdx.x / kGroup;
-  const int gsize = min(kGroup, nwg - grp * kGroup);
-  if (threadIdx.x == 0) flag = (atomicAdd(&tk[1 + grp], 1u) == (unsigned)(gsize - 1));
-  __syncthreads();
-  if (!flag) return false;
-  __threadfence();
-  if (threadIdx.x < NQ * 64) {
-    int q = threadIdx.x / 64, c = threadIdx.x % 64;
-    if (c < L.ct) {
-      double s = 0;
-      for (int w = 0; w < gsize; w++)
-        s += __hip_atomic_load(&part[((size_t)(grp * kGroup + w) * NQ + q) * 64 + c],
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&gpart[((size_t)grp * NQ + q) * 64 + c], s, __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    }
-  }
-  if (threadIdx.x == 0) tk[1 + grp] = 0;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) flag = (atomicAdd(&tk[0], 1u) == (unsigned)(ngroups - 1));
-  __syncthreads();
-  if (!flag) return false;
-  __threadfence();
-  if (threadIdx.x < NQ * 64) {
-    int q = threadIdx.x / 64, c = threadIdx.x % 64;
-    if (c < L.ct) {
-      double s = 0;
-      for (int gI = 0; gI < ngroups; gI++)
-        s += __hip_atomic_load(&gpart[((size_t)gI * NQ + q) * 64 + c], __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-      out[q][c] = s;
-    }
-  }
-  if (threadIdx.x == 0) tk[0] = 0;
-  __syncthreads();
-  return true;
-}
-
-// Recount the active columns of a solve after the column scalars of one tile
-// changed: tiles report their count and the last tile sums them.
-__device__ void finish_count(const Lane &L, SolveState st, int my_active) {
-  __shared__ int last;
-  if (threadIdx.x == 0) {
-    __hip_atomic_store(&st.tile_active[L.tile], my_active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    last = (atomicAdd(st.tile_ticket, 1u) == gridDim.y - 1);
-  }
-  __syncthreads();
-  if (last && threadIdx.x == 0) {
-    __threadfence();
-    int n = 0;
-    for (int t = 0; t < (int)gridDim.y; t++) n += __hip_atomic_load(&st.tile_active[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    *st.n_active = n;
-    *st.tile_ticket = 0;
   }
 }
 
-// Count the active flags of this tile's columns (ct <= 64 threads).
-__device__ int tile_active_count(const Lane &L, SolveState st) {
-  __shared__ int cnt;
-  if (threadIdx.x == 0) cnt = 0;
-  __syncthreads();
-  if (threadIdx.x < L.ct && st.active[L.tile * L.ct + threadIdx.x]) atomicAdd(&cnt, 1);
-  __syncthreads();
-  return cnt;
+// Measurement hook: the first workgroup of each tile adds the tile's active
+// columns to prof[0]; tile 0 counts the launch in prof[1].
+__device__ void count_active(const Lane &L, SolveState st) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    unsigned n = 0;
+    for (int j = 0; j < L.ct; j++) n += st.active[L.tile * L.ct + j] ? 1u : 0u;
+    atomicAdd(&st.prof[0], n);
+    if (L.tile == 0) atomicAdd(&st.prof[1], 1u);
+  }
 }
 
 // ---------------------------------------------------------------- stiffness
@@ -214,30 +151,16 @@ __global__ __launch_bounds__(kWG) void k_stiff(StiffArgs a) {
         a.acc_eta[(size_t)e * (Bs / a.G) + c / a.G] += s;
     }
   }
-  __shared__ double fin[2][64];
-  if (reduce_cols<2>(L, sums, a.rb, fin)) {
-    const SolveState st = a.st;
-    if (threadIdx.x < L.ct) {
-      const int cc = L.tile * L.ct + threadIdx.x;
-      const double bb = fin[0][threadIdx.x], rz = fin[1][threadIdx.x];
-      const bool on = a.colK[cc] >= a.kneed && bb > 0.0;
-      st.bb[cc] = bb;
-      st.rz[cc] = rz;
-      st.beta[cc] = 0.0;
-      st.iters[cc] = 0;
-      st.resid[cc] = 0.0;
-      st.active[cc] = on ? 1 : 0;
-    }
-    __syncthreads();
-    finish_count(L, a.st, tile_active_count(L, a.st));
-  }
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) a.st.cnt[1] = 0;
+  wg_partials<2>(L, sums, a.rb.part, a.rb.max_wg);
 }
 
 // ------------------------------------------------------------- CG: p, q=Mp
 __global__ __launch_bounds__(kWG) void k_cg_a(CgArgs a) {
   const SolveState st = a.st;
-  if (*st.n_active == 0) return;
+  if (st.cnt[a.slot_in] == 0) return;
   const Lane L = lane_map(a.Bs);
+  if (a.count_cols == 1) count_active(L, st);
   const DevOps &o = a.ops;
   const int c = L.col, Bs = a.Bs;
   const bool act = st.active[c] != 0;
@@ -261,20 +184,15 @@ __global__ __launch_bounds__(kWG) void k_cg_a(CgArgs a) {
       sums[0] += pe * q;
     }
   }
-  __shared__ double fin[1][64];
-  if (reduce_cols<1>(L, sums, a.rb, fin)) {
-    if (threadIdx.x < L.ct) {
-      const int cc = L.tile * L.ct + threadIdx.x;
-      if (st.active[cc]) st.alpha[cc] = st.rz[cc] / fin[0][threadIdx.x];
-    }
-  }
+  wg_partials<1>(L, sums, a.rb.part, a.rb.max_wg);
 }
 
 // ---------------------------------------------- CG: x += a p, r -= a q, test
 __global__ __launch_bounds__(kWG) void k_cg_b(CgArgs a) {
   const SolveState st = a.st;
-  if (*st.n_active == 0) return;
+  if (st.cnt[a.slot_in] == 0) return;
   const Lane L = lane_map(a.Bs);
+  if (a.count_cols == 2) count_active(L, st);
   const DevOps &o = a.ops;
   const int c = L.col, Bs = a.Bs;
   const bool act = st.active[c] != 0;
@@ -290,30 +208,7 @@ __global__ __launch_bounds__(kWG) void k_cg_b(CgArgs a) {
       sums[1] += r * r;
     }
   }
-  __shared__ double fin[2][64];
-  if (reduce_cols<2>(L, sums, a.rb, fin)) {
-    if (threadIdx.x < L.ct) {
-      const int cc = L.tile * L.ct + threadIdx.x;
-      if (st.active[cc]) {
-        const double rz = fin[0][threadIdx.x], rr = fin[1][threadIdx.x];
-        const int it = st.iters[cc] + 1;
-        st.iters[cc] = it;
-        st.resid[cc] = sqrt(rr / st.bb[cc]);
-        if (rr <= a.rtol2 * st.bb[cc]) {
-          st.active[cc] = 0;
-        } else if (it >= a.maxit) {
-          st.active[cc] = 0;
-          atomicAdd(st.fail, 1);
-        } else {
-          st.beta[cc] = rz / st.rz[cc];
-          st.rz[cc] = rz;
-        }
-        atomicMax(st.iter_max, it);
-      }
-    }
-    __syncthreads();
-    finish_count(L, st, tile_active_count(L, st));
-  }
+  wg_partials<2>(L, sums, a.rb.part, a.rb.max_wg);
 }
 
 // ------------------------------------------- forward combination of a basis
@@ -532,22 +427,8 @@ __global__ __launch_bounds__(kWG) void k_nl_gather(GatherArgs a) {
       sums[1] += r * r * o.dinv[e];
     }
   }
-  __shared__ double fin[2][64];
-  if (reduce_cols<2>(L, sums, a.rb, fin)) {
-    const SolveState st = a.st;
-    if (threadIdx.x < L.ct) {
-      const int cc = L.tile * L.ct + threadIdx.x;
-      const double bb = fin[0][threadIdx.x];
-      st.bb[cc] = bb;
-      st.rz[cc] = fin[1][threadIdx.x];
-      st.beta[cc] = 0.0;
-      st.iters[cc] = 0;
-      st.resid[cc] = 0.0;
-      st.active[cc] = (a.colK[cc] >= a.kneed && bb > 0.0) ? 1 : 0;
-    }
-    __syncthreads();
-    finish_count(L, st, tile_active_count(L, st));
-  }
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) a.st.cnt[1] = 0;
+  wg_partials<2>(L, sums, a.rb.part, a.rb.max_wg);
 }
 
 // ----------------------------------------------------------- elementwise
@@ -615,20 +496,75 @@ __global__ __launch_bounds__(kWG) void k_wdot(WdotArgs a) {
       sums[1] += o.area[r] * a.xe[it];
     }
   }
-  __shared__ double fin[2][64];
-  if (reduce_cols<2>(L, sums, a.rb, fin)) {
-    if (threadIdx.x < L.ct) {
-      const int cc = L.tile * L.ct + threadIdx.x;
-      a.out[cc] = fin[0][threadIdx.x];
-      a.out[Bs + cc] = fin[1][threadIdx.x];
-    }
-  }
+  wg_partials<2>(L, sums, a.rb.part, a.rb.max_wg);
 }
 
 // Clear small integer/double buffers (used instead of memset so that the
 // sequence stays capturable).
 __global__ void k_zero(unsigned *p, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+// ------------------------------------------------------------- finalize
+// Column sums of the per-workgroup partials of the preceding kernel, one
+// wave per column (lane j adds partials j, j+64, ...; then a fixed shuffle
+// tree), followed by the per-column update of the CG scalars:
+//   FIN_INIT  bb = r.r, rz = r.z, active = colK >= kneed && bb > 0
+//   FIN_ALPHA alpha = rz / p.q
+//   FIN_BETA  convergence test ||r||^2 <= rtol^2 bb, else beta = rz'/rz
+//   FIN_OUT   plain sums to out[q * Bs + c]
+// Active columns are counted into cnt[slot_out] (integer atomics).
+__global__ __launch_bounds__(kWG) void k_finalize(FinArgs a) {
+  const SolveState st = a.st;
+  if (a.mode == FIN_ALPHA && blockIdx.x == 0 && threadIdx.x == 0) st.cnt[a.slot_zero] = 0;
+  if ((a.mode == FIN_ALPHA || a.mode == FIN_BETA) && st.cnt[a.slot_in] == 0) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ct = a.Bs < 64 ? a.Bs : 64;
+  const int cpb = ct < 4 ? ct : 4;            // columns per workgroup
+  const int blocks_per_tile = ct / cpb;
+  const int tile = blockIdx.x / blocks_per_tile;
+  const int cl = (blockIdx.x % blocks_per_tile) * cpb + wave;  // column in tile
+  if (wave >= cpb) return;
+  const int c = tile * ct + cl;
+  double v[2] = {0.0, 0.0};
+  for (int w = lane; w < a.nwg; w += 64)
+    for (int q = 0; q < a.nq; q++)
+      v[q] += a.part[(((size_t)tile * a.max_wg + w) * a.nq + q) * 64 + cl];
+  for (int q = 0; q < a.nq; q++) v[q] = wave_col_sum(v[q], 1);
+  if (lane != 0) return;
+  bool on = false;
+  if (a.mode == FIN_INIT) {
+    on = a.colK[c] >= a.kneed && v[0] > 0.0;
+    st.bb[c] = v[0];
+    st.rz[c] = v[1];
+    st.beta[c] = 0.0;
+    st.iters[c] = 0;
+    st.resid[c] = 0.0;
+    st.active[c] = on ? 1 : 0;
+  } else if (a.mode == FIN_ALPHA) {
+    if (st.active[c]) st.alpha[c] = st.rz[c] / v[0];
+  } else if (a.mode == FIN_BETA) {
+    if (st.active[c]) {
+      const int it = st.iters[c] + 1;
+      st.iters[c] = it;
+      st.resid[c] = sqrt(v[1] / st.bb[c]);
+      if (v[1] <= a.rtol2 * st.bb[c]) {
+        st.active[c] = 0;
+      } else if (it >= a.maxit) {
+        st.active[c] = 0;
+        atomicAdd(st.fail, 1);
+      } else {
+        st.beta[c] = v[0] / st.rz[c];
+        st.rz[c] = v[0];
+        on = true;
+      }
+      atomicMax(st.iter_max, it);
+    }
+  } else {
+    a.out[c] = v[0];
+    a.out[a.Bs + c] = v[1];
+  }
+  if (on) atomicAdd(&st.cnt[a.slot_out], 1);
 }
 
 // ------------------------------------------------------------ launchers
@@ -650,6 +586,7 @@ dim3 rows_grid(int rows, int Bs) { return dim3(grid_rows(rows, Bs), (Bs + 63) / 
 }  // namespace
 
 int launch_max_wg() { return 2048; }
+int launch_rows_grid(int rows, int Bs) { return grid_rows(rows, Bs); }
 
 void launch_stiff(const StiffArgs &a, hipStream_t s) {
   const int nrow = a.ops.ne > a.ops.nc ? a.ops.ne : a.ops.nc;
@@ -691,6 +628,12 @@ void launch_from_block(const TransArgs &a, hipStream_t s) {
 void launch_wdot(const WdotArgs &a, hipStream_t s) {
   const int nrow = a.ops.ne > a.ops.nc ? a.ops.ne : a.ops.nc;
   hipLaunchKernelGGL(k_wdot, rows_grid(nrow, a.Bs), dim3(kWG), 0, s, a);
+}
+void launch_finalize(const FinArgs &a, hipStream_t s) {
+  const int ct = a.Bs < 64 ? a.Bs : 64;
+  const int cpb = ct < 4 ? ct : 4;
+  const int tiles = (a.Bs + 63) / 64;
+  hipLaunchKernelGGL(k_finalize, dim3(tiles * (ct / cpb)), dim3(kWG), 0, s, a);
 }
 void launch_zero(unsigned *p, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_zero, dim3(grid_flat(n)), dim3(kWG), 0, s, p, n);

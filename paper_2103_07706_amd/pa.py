@@ -44,6 +44,14 @@ class SolveCfg(ctypes.Structure):
                 ("weight_cut", ctypes.c_double), ("inner_rtol", ctypes.c_double)]
 
 
+PA_KERNEL_NONE, PA_KERNEL_CG_SPMV, PA_KERNEL_CG_UPDATE = 0, 1, 2
+
+
+class KernelProfile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64), ("work_launches", ctypes.c_int64),
+                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("solves", ctypes.c_int32), ("cg_iters", ctypes.c_int32),
                 ("cg_iters_max", ctypes.c_int32), ("kmax", ctypes.c_int32),
@@ -66,6 +74,8 @@ EXPORTS = {
     "pa_ctx_create": (ctypes.c_int, [ctypes.c_int, _V, ctypes.POINTER(_V)]),
     "pa_ctx_set_stream": (ctypes.c_int, [_V, _V]),
     "pa_ctx_destroy": (ctypes.c_int, [_V]),
+    "pa_ctx_profile": (ctypes.c_int, [_V, ctypes.c_int]),
+    "pa_ctx_profile_read": (ctypes.c_int, [_V, ctypes.POINTER(KernelProfile)]),
     "pa_mesh_icosahedral": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.POINTER(_V)]),
     "pa_mesh_get_info": (ctypes.c_int, [_V, ctypes.POINTER(MeshInfo)]),
     "pa_mesh_export": (ctypes.c_int, [_V, _D, _I, _I, _I, _I]),
@@ -161,6 +171,15 @@ class Context:
         h = _V()
         _check(lib().pa_ctx_create(device, _V(stream), ctypes.byref(h)))
         self._h = h
+
+    def profile(self, kernel: int):
+        """Start timing every launch of one kernel (PA_KERNEL_NONE: off)."""
+        _check(lib().pa_ctx_profile(self._h, kernel))
+
+    def profile_read(self):
+        p = KernelProfile()
+        _check(lib().pa_ctx_profile_read(self._h, ctypes.byref(p)))
+        return {f: getattr(p, f) for f, _ in p._fields_}
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
