@@ -203,6 +203,14 @@ typedef struct {
   double bytes;       /* algorithmic bytes of all launches */
 } pa_kernel_profile;
 int pa_ctx_profile(pa_ctx *ctx, int kernel);
+/* Iteration budget of the mass solves.  After a call whose outputs do not
+ * alias its inputs, the context remembers (per cg_rtol) the largest CG
+ * iteration count plus two; later such calls launch exactly that many
+ * iterations with no host polling and check convergence once at the end,
+ * repeating the call with polling if a column outlived the budget.  This
+ * sets (iters > 0) or clears (iters = 0) the remembered value, e.g. to test
+ * the repeat path. */
+int pa_ctx_set_cg_budget(pa_ctx *ctx, double cg_rtol, int iters);
 int pa_ctx_profile_read(pa_ctx *ctx, pa_kernel_profile *out);
 
 #ifdef __cplusplus

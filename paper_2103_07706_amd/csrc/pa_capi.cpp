@@ -75,6 +75,16 @@ int pa_ctx_profile(pa_ctx *ctx, int kernel) {
   });
 }
 
+int pa_ctx_set_cg_budget(pa_ctx *ctx, double cg_rtol, int iters) {
+  return guard([&] {
+    need(ctx != nullptr && iters >= 0, "bad arguments");
+    if (iters == 0)
+      ctx->cg_budget.erase(cg_rtol);
+    else
+      ctx->cg_budget[cg_rtol] = iters;
+  });
+}
+
 int pa_ctx_profile_read(pa_ctx *ctx, pa_kernel_profile *out) {
   return guard([&] {
     need(ctx && out, "NULL argument");
@@ -379,6 +389,22 @@ void check_call(pa_ctx *ctx, const pa_ops *ops, void *ws) {
 void out_stats(pa_stats *stats, const pa::Engine &e) {
   if (stats) *stats = e.stats;
 }
+
+// Run a call with the context's learned CG iteration budget when allowed
+// (outputs not aliasing inputs); if a solve outlives the budget, run it
+// again with host polling, which also relearns the budget.
+template <class F>
+void run_with_budget(pa_ctx *ctx, double rtol, bool allowed, F &&f) {
+  if (allowed && ctx->cg_budget.count(rtol)) {
+    try {
+      f(true);
+      return;
+    } catch (const pa::BudgetExceeded &) {
+      ctx->cg_budget.erase(rtol);
+    }
+  }
+  f(false);
+}
 }  // namespace
 
 extern "C" {
@@ -404,9 +430,14 @@ int pa_expL_apply(pa_ctx *ctx, const pa_ops *ops, int B, const double *t_host,
   return guard([&] {
     check_call(ctx, ops, ws);
     need(t_host && U_in_dev && U_out_dev && B >= 1, "bad arguments");
-    pa::Engine e(ctx, ops, cfg_or_default(cfg), ws, ws_bytes);
-    e.expL_apply(B, t_host, U_in_dev, U_out_dev);
-    out_stats(stats, e);
+    const pa_solve_cfg c = cfg_or_default(cfg);
+    const bool may = U_in_dev != U_out_dev;
+    run_with_budget(ctx, c.cg_rtol, may, [&](bool budget) {
+      pa::Engine e(ctx, ops, cfg_or_default(cfg), ws, ws_bytes);
+      e.allow_budget(budget, may);
+      e.expL_apply(B, t_host, U_in_dev, U_out_dev);
+      out_stats(stats, e);
+    });
   });
 }
 
@@ -415,9 +446,14 @@ int pa_swe_nonlinear(pa_ctx *ctx, const pa_ops *ops, int B, const double *U_dev,
   return guard([&] {
     check_call(ctx, ops, ws);
     need(U_dev && NU_dev && B >= 1, "bad arguments");
-    pa::Engine e(ctx, ops, cfg_or_default(cfg), ws, ws_bytes);
-    e.swe_nonlinear(B, U_dev, NU_dev);
-    out_stats(stats, e);
+    const pa_solve_cfg c = cfg_or_default(cfg);
+    const bool may = U_dev != NU_dev;
+    run_with_budget(ctx, c.cg_rtol, may, [&](bool budget) {
+      pa::Engine e(ctx, ops, cfg_or_default(cfg), ws, ws_bytes);
+      e.allow_budget(budget, may);
+      e.swe_nonlinear(B, U_dev, NU_dev);
+      out_stats(stats, e);
+    });
   });
 }
 
@@ -427,9 +463,14 @@ int pa_phase_avg_rhs(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int memb
   return guard([&] {
     check_call(ctx, ops, ws);
     need(avg && U_dev && Nbar_dev && members >= 1, "bad arguments");
-    pa::Engine e(ctx, ops, cfg_or_default(cfg), ws, ws_bytes);
-    e.phase_avg_rhs(avg, members, U_dev, Nbar_dev);
-    out_stats(stats, e);
+    const pa_solve_cfg c = cfg_or_default(cfg);
+    const bool may = U_dev != Nbar_dev;
+    run_with_budget(ctx, c.cg_rtol, may, [&](bool budget) {
+      pa::Engine e(ctx, ops, cfg_or_default(cfg), ws, ws_bytes);
+      e.allow_budget(budget, may);
+      e.phase_avg_rhs(avg, members, U_dev, Nbar_dev);
+      out_stats(stats, e);
+    });
   });
 }
 

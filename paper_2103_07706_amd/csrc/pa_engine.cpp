@@ -55,8 +55,12 @@ void Engine::plan_common(int BsMax) {
   st_.active = ar_.take<int>(BsMax);
   st_.iters = ar_.take<int>(BsMax);
   colK0_ = ar_.take<int>(BsMax);
+  st_.rz2 = ar_.take<double>(8);
+  st_.act2 = ar_.take<int>(8);
+  st_.it2 = ar_.take<int>(8);
   rb_.max_wg = launch_max_wg();
-  rb_.part = ar_.take<double>((size_t)tiles * rb_.max_wg * 2 * 64);
+  rb_.partA = ar_.take<double>((size_t)tiles * rb_.max_wg * 64);
+  rb_.partB = ar_.take<double>((size_t)tiles * rb_.max_wg * 2 * 64);
   // counters, cleared at the start of each call
   zero_words_ = 64;
   zero_base_ = ar_.take<unsigned>(zero_words_);
@@ -66,6 +70,7 @@ void Engine::plan_common(int BsMax) {
     st_.fail = (int *)(z + 2);
     st_.iter_max = (int *)(z + 3);
     st_.prof = z + 4;
+    st_.budget_fail = (int *)(z + 6);
   }
 }
 
@@ -93,8 +98,8 @@ void Engine::begin() {
 
 void Engine::finish() {
   PA_HIP(hipEventRecord(ev1_, s_));
-  int h[4] = {0, 0, 0, 0};
-  PA_HIP(hipMemcpyAsync(h, st_.fail, 4 * sizeof(int), hipMemcpyDeviceToHost, s_));
+  int h[5] = {0, 0, 0, 0, 0};
+  PA_HIP(hipMemcpyAsync(h, st_.fail, 5 * sizeof(int), hipMemcpyDeviceToHost, s_));
   PA_HIP(hipStreamSynchronize(s_));
   if (ctx_->prof_kernel != PA_KERNEL_NONE) {
     for (size_t i = 0; i + 1 < prof_ev_.size(); i += 2) {
@@ -123,6 +128,9 @@ void Engine::finish() {
   stats.cg_iters_max = std::max(stats.cg_iters_max, h[1]);
   if (h[0] > 0)
     throw Error(PA_ENOCONV, std::to_string(h[0]) + " mass-solve column(s) did not converge within maxit");
+  if (h[4] > 0) throw BudgetExceeded();
+  // next calls on this context run without polling, with this budget
+  if (learn_budget_) ctx_->cg_budget[cfg_.cg_rtol] = std::min(cfg_.maxit, h[1] + 2);
 }
 
 // Column sums of the set-up kernel's partials: bb = r.r, rz = r.z and the
@@ -134,7 +142,7 @@ void Engine::finalize_init(int nwg, int Bs, const int *colK, int kneed) {
   f.nwg = nwg;
   f.max_wg = rb_.max_wg;
   f.nq = 2;
-  f.part = rb_.part;
+  f.part = rb_.partB;
   f.st = st_;
   f.colK = colK;
   f.kneed = kneed;
@@ -149,7 +157,7 @@ void Engine::wdot_out(int Bs, double *out) {
   f.nwg = launch_rows_grid(std::max(ne_, nc_), Bs);
   f.max_wg = rb_.max_wg;
   f.nq = 2;
-  f.part = rb_.part;
+  f.part = rb_.partB;
   f.st = st_;
   f.out = out;
   launch_finalize(f, s_);
@@ -173,10 +181,14 @@ void Engine::axpy(size_t n, double *out, double a0, const double *x0, double a1,
 }
 
 // Batched CG on the velocity mass matrix for the columns the preceding
-// set-up kernel activated; x holds the start value and receives the result.
-// Convergence is decided per column on the device; the host only polls the
-// number of active columns, first after the predicted iteration count.
-void Engine::cg(double *x, int Bs) {
+// set-up kernel prepared (r = right-hand side, x = start value, partials of
+// r.z and r.r).  Convergence is decided per column on the device.  Small
+// batches (Bs <= 4) use the fused kernels (two launches per iteration);
+// larger ones add a finalize kernel after each.  Without an iteration budget
+// the host polls the active count (first after the predicted count); with
+// one (learned from earlier calls on the context) it launches exactly that
+// many iterations and only checks at the end of the call.
+void Engine::cg(double *x, int Bs, const int *colK, int kneed, int nwg_init) {
   CgArgs a{};
   a.ops = ops_->d;
   a.Bs = Bs;
@@ -188,7 +200,16 @@ void Engine::cg(double *x, int Bs) {
   a.st = st_;
   a.rb = rb_;
   a.count_cols = ctx_->prof_kernel;
+  a.colK = colK;
+  a.kneed = kneed;
+  const int nwg = launch_rows_grid(ne_, Bs);
+  int budget = 0;
+  if (budget_ok_) {
+    auto itb = ctx_->cg_budget.find(cfg_.cg_rtol);
+    if (itb != ctx_->cg_budget.end()) budget = itb->second;
+  }
   double *pold = p0_, *pnew = p1_;
+  int *hflag = (int *)ctx_->host_flag;
   auto timed = [&](int which, auto launch) {
     if (ctx_->prof_kernel != which) {
       launch();
@@ -201,45 +222,91 @@ void Engine::cg(double *x, int Bs) {
     prof_ev_.push_back(e0);
     prof_ev_.push_back(e1);
   };
-  int it = 0, chunk = std::max(1, std::min(predicted_, cfg_.maxit));
-  int *hflag = (int *)ctx_->host_flag;
-  FinArgs fa{};
-  fa.Bs = Bs;
-  fa.nwg = launch_rows_grid(ne_, Bs);
-  fa.max_wg = rb_.max_wg;
-  fa.part = rb_.part;
-  fa.st = st_;
-  fa.rtol2 = a.rtol2;
-  fa.maxit = a.maxit;
-  for (;;) {
-    for (int i = 0; i < chunk; i++) {
-      const int k = it + i;
+  auto poll = [&](int slot) {
+    PA_HIP(hipMemcpyAsync(hflag, st_.cnt + slot, sizeof(int), hipMemcpyDeviceToHost, s_));
+    PA_HIP(hipStreamSynchronize(s_));
+    return *hflag;
+  };
+  int it = 0;
+  if (Bs <= 4) {
+    a.fused = 1;
+    auto A = [&](int k, bool last) {
+      a.k = k;
+      a.nwg_prev = k == 0 ? nwg_init : nwg;
       a.p_old = pold;
       a.p_new = pnew;
-      a.slot_in = (k + 1) & 1;  // count written by the previous finalize
+      a.last_check = last ? 1 : 0;
+      a.check_only = last ? 1 : 0;
       timed(PA_KERNEL_CG_SPMV, [&] { launch_cg_a(a, s_); });
-      fa.mode = FIN_ALPHA;
-      fa.nq = 1;
-      fa.slot_in = (k + 1) & 1;
-      fa.slot_zero = k & 1;
-      launch_finalize(fa, s_);
+    };
+    auto B = [&](int k) {
+      a.k = k;
+      a.nwg_prev = nwg;
+      a.p_new = pnew;
       timed(PA_KERNEL_CG_UPDATE, [&] { launch_cg_b(a, s_); });
-      fa.mode = FIN_BETA;
-      fa.nq = 2;
-      fa.slot_out = k & 1;
-      launch_finalize(fa, s_);
       std::swap(pold, pnew);
+    };
+    A(0, false);
+    if (budget > 0) {
+      for (int k = 0; k < budget; k++) {
+        B(k);
+        A(k + 1, k + 1 == budget);
+      }
+      it = budget;
+    } else {
+      int chunk = std::max(1, std::min(predicted_, cfg_.maxit));
+      for (;;) {
+        for (int i = 0; i < chunk && it < cfg_.maxit; i++) {
+          B(it);
+          it++;
+          A(it, false);
+        }
+        if (poll(it & 1) == 0 || it >= cfg_.maxit) break;
+        chunk = 1;
+      }
     }
-    it += chunk;
-    PA_HIP(hipMemcpyAsync(hflag, st_.cnt + ((it - 1) & 1), sizeof(int), hipMemcpyDeviceToHost, s_));
-    PA_HIP(hipStreamSynchronize(s_));
-    if (*hflag == 0 || it >= cfg_.maxit) break;
-    chunk = 1;
+  } else {
+    a.fused = 0;
+    finalize_init(nwg_init, Bs, colK, kneed);
+    FinArgs fa{};
+    fa.Bs = Bs;
+    fa.nwg = nwg;
+    fa.max_wg = rb_.max_wg;
+    fa.st = st_;
+    fa.rtol2 = a.rtol2;
+    fa.maxit = a.maxit;
+    const int total = budget > 0 ? budget : cfg_.maxit;
+    int chunk = budget > 0 ? budget : std::max(1, std::min(predicted_, cfg_.maxit));
+    for (;;) {
+      for (int i = 0; i < chunk && it < total; i++) {
+        const int k = it++;
+        a.p_old = pold;
+        a.p_new = pnew;
+        a.slot_in = (k + 1) & 1;  // count written by the previous finalize
+        timed(PA_KERNEL_CG_SPMV, [&] { launch_cg_a(a, s_); });
+        fa.mode = FIN_ALPHA;
+        fa.nq = 1;
+        fa.part = rb_.partA;
+        fa.slot_in = (k + 1) & 1;
+        fa.slot_zero = k & 1;
+        launch_finalize(fa, s_);
+        timed(PA_KERNEL_CG_UPDATE, [&] { launch_cg_b(a, s_); });
+        fa.mode = FIN_BETA;
+        fa.nq = 2;
+        fa.part = rb_.partB;
+        fa.slot_out = k & 1;
+        fa.last_check = (budget > 0 && it == budget) ? 1 : 0;
+        launch_finalize(fa, s_);
+        std::swap(pold, pnew);
+      }
+      if (budget > 0 || it >= total) break;
+      if (poll((it - 1) & 1) == 0) break;
+      chunk = 1;
+    }
   }
   predicted_ = std::max(1, it - 1);
   stats.solves++;
   stats.cg_iters += it;
-  stats.cg_iters_max = std::max(stats.cg_iters_max, it);
 }
 
 void Engine::lstep(Blk in, Blk out, const Blk *A, const Blk *B, double scale, const int *colK,
@@ -275,8 +342,7 @@ void Engine::lstep(Blk in, Blk out, const Blk *A, const Blk *B, double scale, co
   a.st = st_;
   a.rb = rb_;
   launch_stiff(a, s_);
-  finalize_init(launch_rows_grid(std::max(ne_, nc_), in.Bs), in.Bs, colK, kneed);
-  cg(out.p, in.Bs);
+  cg(out.p, in.Bs, colK, kneed, launch_rows_grid(std::max(ne_, nc_), in.Bs));
 }
 
 // acc = sum_k coef_k (.) R_k(X) over the real Chebyshev recurrence, with the
@@ -336,8 +402,7 @@ void Engine::nonlinear_block(Blk E, Blk Y, const int *colK) {
   gth.st = st_;
   gth.rb = rb_;
   launch_nl_gather(gth, s_);
-  finalize_init(launch_rows_grid(ne_, E.Bs), E.Bs, colK, 0);
-  cg(Y.p, E.Bs);
+  cg(Y.p, E.Bs, colK, 0, launch_rows_grid(ne_, E.Bs));
 }
 
 // ------------------------------------------------------------- exponential

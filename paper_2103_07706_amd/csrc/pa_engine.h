@@ -17,6 +17,12 @@ int pad_cols(int B);
 
 // Bump allocator over the caller's workspace; with base == nullptr it only
 // measures (the same planning code sizes and carves the workspace).
+// Raised when a solve still had active columns after the learned iteration
+// budget; the call is then repeated with polling.
+struct BudgetExceeded : Error {
+  BudgetExceeded() : Error(PA_ENOCONV, "iteration budget exceeded") {}
+};
+
 class Arena {
  public:
   Arena(void *base, size_t cap) : base_((char *)base), cap_(cap) {}
@@ -67,6 +73,13 @@ class Engine {
   void diagnostics(int B, const double *U, double *out_host);
 
   size_t used() const { return ar_.used(); }
+  // allow the learned CG iteration budget (no host polling) for this call
+  // use: launch the learned budget without polling; learn: record the
+  // largest iteration count of this call as the next budget
+  void allow_budget(bool use, bool learn) {
+    budget_ok_ = use;
+    learn_budget_ = learn;
+  }
   pa_stats stats{};
 
  private:
@@ -77,7 +90,7 @@ class Engine {
   Blk block(int Bs);
   void lstep(Blk in, Blk out, const Blk *A, const Blk *B, double scale, const int *colK,
              int kneed, const AccSpec *acc);
-  void cg(double *x, int Bs);
+  void cg(double *x, int Bs, const int *colK, int kneed, int nwg_init);
   void poly_apply(Blk X, Blk W, const double *coef, const int *colK, int kmax, int G, Blk acc);
   void nonlinear_block(Blk E, Blk Y, const int *colK);
   void axpy(size_t n, double *out, double a0, const double *x0, double a1 = 0,
@@ -128,6 +141,7 @@ class Engine {
   size_t zero_words_ = 0;
   int *colK0_ = nullptr;  // all zeros
   int predicted_ = 8;
+  bool budget_ok_ = false, learn_budget_ = false;
   hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
 };
 

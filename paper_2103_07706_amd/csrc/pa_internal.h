@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <map>
 #include <cstdint>
 #include <stdexcept>
 #include <string>
@@ -78,6 +79,8 @@ struct pa_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   void *host_flag = nullptr;  // pinned host word for convergence polling
+  // learned CG iterations per solve, per tolerance (absent: poll)
+  std::map<double, int> cg_budget;
   // measurement hook (pa_ctx_profile)
   int prof_kernel = 0;
   std::vector<hipEvent_t> prof_pool;

@@ -6,9 +6,11 @@
 
 namespace pa {
 
-// Per-workgroup partial column sums: [tiles][max_wg][nq][64].
+// Per-workgroup partial column sums: [tiles][max_wg][nq][64].  partA holds
+// p.q of the SpMV kernel, partB the (r.z, r.r) pairs of the set-up and update
+// kernels (and the energy products).
 struct RedBuf {
-  double *part = nullptr;
+  double *partA = nullptr, *partB = nullptr;
   int max_wg = 0;
 };
 
@@ -16,7 +18,12 @@ struct RedBuf {
 struct SolveState {
   double *bb, *rz, *alpha, *beta, *resid;
   int *active, *iters;
+  // fused small-batch CG: per-column scalars double-buffered by iteration
+  // parity so that workgroup 0 can publish them while others still read
+  double *rz2;            // [2][Bs]
+  int *act2, *it2;        // [2][Bs]
   int *cnt;               // [2]: active columns after the last finalize, by parity
+  int *budget_fail;       // 1: columns still active when an iteration budget ran out
   int *fail;              // 1 (accumulates over solves)
   int *iter_max;          // 1 (accumulates over solves)
   unsigned *prof;         // [2]: active columns summed over launches, work launches
@@ -45,6 +52,11 @@ struct CgArgs {
   int Bs;
   int count_cols;  // measurement hook: tally active columns of each launch
   int slot_in;     // cnt slot holding the active count (early exit when 0)
+  // fused small-batch mode (Bs <= 4): every workgroup reduces the partials
+  // of the previous kernel itself
+  int fused, k, nwg_prev, check_only, last_check;
+  const int *colK;
+  int kneed;
   double *x, *r, *p_old, *p_new, *q;
   double rtol2;
   int maxit;
@@ -62,6 +74,7 @@ struct FinArgs {
   double rtol2;
   int maxit;
   int slot_in, slot_out, slot_zero;
+  int last_check;
   double *out;
 };
 

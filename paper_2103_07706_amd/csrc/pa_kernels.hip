@@ -118,8 +118,8 @@ __global__ __launch_bounds__(kWG) void k_stiff(StiffArgs a) {
         if (a.addB_u) x0 += a.addB_u[ie];
         a.r[ie] = r;
         a.out_u[ie] = x0;
-        sums[0] += r * r;
-        sums[1] += r * r * o.dinv[e];
+        sums[0] += r * r * o.dinv[e];
+        sums[1] += r * r;
       }
       if (acc_on) accv = coef * a.in_u[ie];
     }
@@ -152,19 +152,104 @@ __global__ __launch_bounds__(kWG) void k_stiff(StiffArgs a) {
     }
   }
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) a.st.cnt[1] = 0;
-  wg_partials<2>(L, sums, a.rb.part, a.rb.max_wg);
+  wg_partials<2>(L, sums, a.rb.partB, a.rb.max_wg);
 }
 
 // ------------------------------------------------------------- CG: p, q=Mp
+// Fused small-batch prologue (Bs <= 4, one wave per column): reduce the
+// (r.z, r.r) partials of the previous kernel, decide convergence and beta;
+// workgroup 0 publishes the scalars for the iteration's parity.
+struct FusedCols {
+  double beta[4];
+  int act[4];
+  int any;
+};
+
+__device__ void fused_convergence(const CgArgs &a, const Lane &L, FusedCols &fc) {
+  const SolveState st = a.st;
+  if (threadIdx.x == 0) fc.any = 0;
+  __syncthreads();
+  const int cc = L.wave;
+  if (cc < L.ct) {
+    double v0 = 0.0, v1 = 0.0;
+    for (int g = L.lane; g < a.nwg_prev; g += 64) {
+      v0 += a.rb.partB[((size_t)g * 2 + 0) * 64 + cc];
+      v1 += a.rb.partB[((size_t)g * 2 + 1) * 64 + cc];
+    }
+    v0 = wave_col_sum(v0, 1);
+    v1 = wave_col_sum(v1, 1);
+    if (L.lane == 0) {
+      const int cur = a.k & 1, prev = cur ^ 1;
+      const bool w0 = blockIdx.x == 0;
+      double beta = 0.0;
+      int act = 0;
+      if (a.k == 0) {
+        act = (a.colK[cc] >= a.kneed && v1 > 0.0) ? 1 : 0;
+        if (w0) {
+          st.bb[cc] = v1;
+          st.resid[cc] = 0.0;
+          st.it2[cur * 4 + cc] = 0;
+          st.rz2[cur * 4 + cc] = v0;
+          st.act2[cur * 4 + cc] = act;
+        }
+      } else if (st.act2[prev * 4 + cc]) {
+        const int it = st.it2[prev * 4 + cc] + 1;
+        const double bb = st.bb[cc];
+        bool fail = false;
+        if (v1 <= a.rtol2 * bb) {
+          act = 0;
+        } else if (it >= a.maxit) {
+          fail = true;
+        } else {
+          act = 1;
+          beta = v0 / st.rz2[prev * 4 + cc];
+        }
+        if (w0) {
+          st.it2[cur * 4 + cc] = it;
+          st.resid[cc] = sqrt(v1 / bb);
+          st.rz2[cur * 4 + cc] = v0;
+          if (fail) atomicAdd(st.fail, 1);
+          if (act && a.last_check) atomicAdd(st.budget_fail, 1);
+          atomicMax(st.iter_max, it);
+        }
+      }
+      if (w0) st.act2[cur * 4 + cc] = act;
+      fc.beta[cc] = beta;
+      fc.act[cc] = act;
+      if (act) atomicOr(&fc.any, 1);
+    }
+  }
+  __syncthreads();
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    int n = 0;
+    for (int j = 0; j < L.ct; j++) n += fc.act[j];
+    st.cnt[a.k & 1] = n;
+    if (a.count_cols == 1 && n > 0 && !a.check_only) {
+      atomicAdd(&st.prof[0], (unsigned)n);
+      atomicAdd(&st.prof[1], 1u);
+    }
+  }
+}
+
 __global__ __launch_bounds__(kWG) void k_cg_a(CgArgs a) {
   const SolveState st = a.st;
-  if (st.cnt[a.slot_in] == 0) return;
   const Lane L = lane_map(a.Bs);
-  if (a.count_cols == 1) count_active(L, st);
+  __shared__ FusedCols fc;
+  bool act;
+  double beta;
+  if (a.fused) {
+    fused_convergence(a, L, fc);
+    if (!fc.any || a.check_only) return;
+    act = fc.act[L.col] != 0;
+    beta = act ? fc.beta[L.col] : 0.0;
+  } else {
+    if (st.cnt[a.slot_in] == 0) return;
+    if (a.count_cols == 1) count_active(L, st);
+    act = st.active[L.col] != 0;
+    beta = act ? st.beta[L.col] : 0.0;
+  }
   const DevOps &o = a.ops;
   const int c = L.col, Bs = a.Bs;
-  const bool act = st.active[c] != 0;
-  const double beta = act ? st.beta[c] : 0.0;
   double sums[1] = {0.0};
   if (act) {
     for (int e = L.row0; e < o.ne; e += L.rstride) {
@@ -184,19 +269,51 @@ __global__ __launch_bounds__(kWG) void k_cg_a(CgArgs a) {
       sums[0] += pe * q;
     }
   }
-  wg_partials<1>(L, sums, a.rb.part, a.rb.max_wg);
+  wg_partials<1>(L, sums, a.rb.partA, a.rb.max_wg);
 }
 
 // ---------------------------------------------- CG: x += a p, r -= a q, test
 __global__ __launch_bounds__(kWG) void k_cg_b(CgArgs a) {
   const SolveState st = a.st;
-  if (st.cnt[a.slot_in] == 0) return;
   const Lane L = lane_map(a.Bs);
-  if (a.count_cols == 2) count_active(L, st);
+  bool act;
+  double alpha;
+  if (a.fused) {
+    // alpha = rz / p.q from the SpMV kernel's partials (one wave per column)
+    __shared__ double s_alpha[4];
+    __shared__ int s_act[4], s_any;
+    if (threadIdx.x == 0) s_any = 0;
+    __syncthreads();
+    const int cc = L.wave, cur = a.k & 1;
+    if (cc < L.ct) {
+      double pq = 0.0;
+      for (int g = L.lane; g < a.nwg_prev; g += 64) pq += a.rb.partA[(size_t)g * 64 + cc];
+      pq = wave_col_sum(pq, 1);
+      if (L.lane == 0) {
+        const int on = st.act2[cur * 4 + cc];
+        s_act[cc] = on;
+        s_alpha[cc] = on ? st.rz2[cur * 4 + cc] / pq : 0.0;
+        if (on) atomicOr(&s_any, 1);
+      }
+    }
+    __syncthreads();
+    if (!s_any) return;
+    if (a.count_cols == 2 && blockIdx.x == 0 && threadIdx.x == 0) {
+      unsigned n = 0;
+      for (int j = 0; j < L.ct; j++) n += s_act[j];
+      atomicAdd(&st.prof[0], n);
+      atomicAdd(&st.prof[1], 1u);
+    }
+    act = s_act[L.col] != 0;
+    alpha = s_alpha[L.col];
+  } else {
+    if (st.cnt[a.slot_in] == 0) return;
+    if (a.count_cols == 2) count_active(L, st);
+    act = st.active[L.col] != 0;
+    alpha = act ? st.alpha[L.col] : 0.0;
+  }
   const DevOps &o = a.ops;
   const int c = L.col, Bs = a.Bs;
-  const bool act = st.active[c] != 0;
-  const double alpha = act ? st.alpha[c] : 0.0;
   double sums[2] = {0.0, 0.0};
   if (act) {
     for (int e = L.row0; e < o.ne; e += L.rstride) {
@@ -208,7 +325,7 @@ __global__ __launch_bounds__(kWG) void k_cg_b(CgArgs a) {
       sums[1] += r * r;
     }
   }
-  wg_partials<2>(L, sums, a.rb.part, a.rb.max_wg);
+  wg_partials<2>(L, sums, a.rb.partB, a.rb.max_wg);
 }
 
 // ------------------------------------------- forward combination of a basis
@@ -423,12 +540,12 @@ __global__ __launch_bounds__(kWG) void k_nl_gather(GatherArgs a) {
       const double r = a.C[(size_t)o.cidx[2 * e] * Bs + c] + a.C[(size_t)o.cidx[2 * e + 1] * Bs + c];
       a.r[ie] = r;
       a.x[ie] = 0.0;
-      sums[0] += r * r;
-      sums[1] += r * r * o.dinv[e];
+      sums[0] += r * r * o.dinv[e];
+      sums[1] += r * r;
     }
   }
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) a.st.cnt[1] = 0;
-  wg_partials<2>(L, sums, a.rb.part, a.rb.max_wg);
+  wg_partials<2>(L, sums, a.rb.partB, a.rb.max_wg);
 }
 
 // ----------------------------------------------------------- elementwise
@@ -496,7 +613,7 @@ __global__ __launch_bounds__(kWG) void k_wdot(WdotArgs a) {
       sums[1] += o.area[r] * a.xe[it];
     }
   }
-  wg_partials<2>(L, sums, a.rb.part, a.rb.max_wg);
+  wg_partials<2>(L, sums, a.rb.partB, a.rb.max_wg);
 }
 
 // Clear small integer/double buffers (used instead of memset so that the
@@ -534,9 +651,9 @@ __global__ __launch_bounds__(kWG) void k_finalize(FinArgs a) {
   if (lane != 0) return;
   bool on = false;
   if (a.mode == FIN_INIT) {
-    on = a.colK[c] >= a.kneed && v[0] > 0.0;
-    st.bb[c] = v[0];
-    st.rz[c] = v[1];
+    on = a.colK[c] >= a.kneed && v[1] > 0.0;
+    st.bb[c] = v[1];
+    st.rz[c] = v[0];
     st.beta[c] = 0.0;
     st.iters[c] = 0;
     st.resid[c] = 0.0;
@@ -557,6 +674,7 @@ __global__ __launch_bounds__(kWG) void k_finalize(FinArgs a) {
         st.beta[c] = v[0] / st.rz[c];
         st.rz[c] = v[0];
         on = true;
+        if (a.last_check) atomicAdd(st.budget_fail, 1);
       }
       atomicMax(st.iter_max, it);
     }

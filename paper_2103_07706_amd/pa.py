@@ -76,6 +76,7 @@ EXPORTS = {
     "pa_ctx_destroy": (ctypes.c_int, [_V]),
     "pa_ctx_profile": (ctypes.c_int, [_V, ctypes.c_int]),
     "pa_ctx_profile_read": (ctypes.c_int, [_V, ctypes.POINTER(KernelProfile)]),
+    "pa_ctx_set_cg_budget": (ctypes.c_int, [_V, ctypes.c_double, ctypes.c_int]),
     "pa_mesh_icosahedral": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.POINTER(_V)]),
     "pa_mesh_get_info": (ctypes.c_int, [_V, ctypes.POINTER(MeshInfo)]),
     "pa_mesh_export": (ctypes.c_int, [_V, _D, _I, _I, _I, _I]),
@@ -175,6 +176,9 @@ class Context:
     def profile(self, kernel: int):
         """Start timing every launch of one kernel (PA_KERNEL_NONE: off)."""
         _check(lib().pa_ctx_profile(self._h, kernel))
+
+    def set_cg_budget(self, cg_rtol: float, iters: int):
+        _check(lib().pa_ctx_set_cg_budget(self._h, cg_rtol, iters))
 
     def profile_read(self):
         p = KernelProfile()

@@ -115,3 +115,37 @@ def test_gpu_diagnostics_mass_energy():
         ref = oo.diagnostics(U[j])
         assert abs(d[j, 0] / ref["mass"] - 1) < 1e-13
         assert abs(d[j, 1] / ref["energy_linear"] - 1) < 1e-13
+
+
+@pytest.mark.parametrize("B", [1, 2, 3, 4, 5, 64, 65])
+def test_gpu_expL_batch_shapes(B):
+    """Fused (B <= 4) and finalize (B > 4) CG paths, padded column counts,
+    more than one column tile (B = 65)."""
+    from paper_2103_07706_amd import pa
+    om, oo, lm, lo, mm, lb = pair(2)
+    rng = np.random.default_rng(B)
+    ts = rng.uniform(-5000.0, 5000.0, B)
+    U = bumps(om, [j % 7 for j in range(B)])
+    out, st = lo.expL_apply(ts, to_dev(mm.state(U)), pa.solve_cfg(**PARITY))
+    got = mm.back(out.cpu().numpy())
+    for j in range(0, B, max(1, B // 6)):
+        ref, _ = oo.expL(lb, ts[j], U[j], tol=1e-13, rtol=1e-14)
+        assert rel_w(oo, got[j], ref) < TOL
+
+
+def test_gpu_budget_mode_and_repeat():
+    """Second call runs on the learned iteration budget without polling and
+    gives the same result; a budget that is too small is detected and the
+    call repeated with polling."""
+    from paper_2103_07706_amd import pa
+    om, oo, lm, lo, mm, lb = pair(3)
+    U = to_dev(mm.state(bumps(om, [2])))
+    avg = pa.Avg(8, 3600.0)
+    cfg = pa.solve_cfg(cg_rtol=1e-11)
+    lo.ctx.set_cg_budget(1e-11, 0)
+    a, _ = lo.phase_avg_rhs(avg, U, cfg)   # polling, learns the budget
+    b, _ = lo.phase_avg_rhs(avg, U, cfg)   # budget
+    assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+    lo.ctx.set_cg_budget(1e-11, 3)         # far too small: repeat with polling
+    c, _ = lo.phase_avg_rhs(avg, U, cfg)
+    assert np.array_equal(a.cpu().numpy(), c.cpu().numpy())
