@@ -43,10 +43,13 @@ void Engine::plan_common(int BsMax) {
   BsMax_ = BsMax;
   const int tiles = tiles_of(BsMax);
   const size_t ebs = (size_t)ne_ * BsMax;
-  r_ = ar_.take<double>(ebs);
-  p0_ = ar_.take<double>(ebs);
-  p1_ = ar_.take<double>(ebs);
-  q_ = ar_.take<double>(ebs);
+  r_ = ar_.take<double>(ebs);   // r[0]; the set-up kernels write r_0 here
+  r1_ = ar_.take<double>(ebs);
+  w0_ = ar_.take<double>(ebs);
+  w1_ = ar_.take<double>(ebs);
+  s0_ = ar_.take<double>(ebs);
+  s1_ = ar_.take<double>(ebs);
+  p_ = ar_.take<double>(ebs);
   st_.bb = ar_.take<double>(BsMax);
   st_.rz = ar_.take<double>(BsMax);
   st_.alpha = ar_.take<double>(BsMax);
@@ -56,11 +59,12 @@ void Engine::plan_common(int BsMax) {
   st_.iters = ar_.take<int>(BsMax);
   colK0_ = ar_.take<int>(BsMax);
   st_.rz2 = ar_.take<double>(8);
+  st_.al2 = ar_.take<double>(8);
   st_.act2 = ar_.take<int>(8);
   st_.it2 = ar_.take<int>(8);
   rb_.max_wg = launch_max_wg();
-  rb_.partA = ar_.take<double>((size_t)tiles * rb_.max_wg * 64);
-  rb_.partB = ar_.take<double>((size_t)tiles * rb_.max_wg * 2 * 64);
+  rb_.partA = ar_.take<double>((size_t)tiles * rb_.max_wg * 3 * 64);
+  rb_.partB = ar_.take<double>((size_t)tiles * rb_.max_wg * 3 * 64);
   // counters, cleared at the start of each call
   zero_words_ = 64;
   zero_base_ = ar_.take<unsigned>(zero_words_);
@@ -113,10 +117,10 @@ void Engine::finish() {
     // algorithmic bytes: per active column and row, the vectors the kernel
     // must stream once; per row and launch, the matrix row it reads
     const double cols = (unsigned)h[2], work = (unsigned)h[3];
-    if (ctx_->prof_kernel == PA_KERNEL_CG_SPMV)   // r, p_old in; p_new, q out; ELL row + dinv
-      ctx_->prof_bytes += (double)ne_ * (32.0 * cols + 68.0 * work);
-    else if (ctx_->prof_kernel == PA_KERNEL_CG_UPDATE)  // x, p, r, q in; x, r out; dinv
-      ctx_->prof_bytes += (double)ne_ * (48.0 * cols + 8.0 * work);
+    // x, p, r, w, s in; x, p, r', w', s' out; ELL row (5 cols, 5 values)
+    // and the Jacobi diagonal once per launch
+    if (ctx_->prof_kernel == PA_KERNEL_CG_ITER)
+      ctx_->prof_bytes += (double)ne_ * (80.0 * cols + 68.0 * work);
     ctx_->prof_work += (int64_t)work;
   }
   float ms = 0;
@@ -131,23 +135,6 @@ void Engine::finish() {
   if (h[4] > 0) throw BudgetExceeded();
   // next calls on this context run without polling, with this budget
   if (learn_budget_) ctx_->cg_budget[cfg_.cg_rtol] = std::min(cfg_.maxit, h[1] + 2);
-}
-
-// Column sums of the set-up kernel's partials: bb = r.r, rz = r.z and the
-// initial active set (count into slot 1, the slot iteration 0 reads).
-void Engine::finalize_init(int nwg, int Bs, const int *colK, int kneed) {
-  FinArgs f{};
-  f.mode = FIN_INIT;
-  f.Bs = Bs;
-  f.nwg = nwg;
-  f.max_wg = rb_.max_wg;
-  f.nq = 2;
-  f.part = rb_.partB;
-  f.st = st_;
-  f.colK = colK;
-  f.kneed = kneed;
-  f.slot_out = 1;
-  launch_finalize(f, s_);
 }
 
 void Engine::wdot_out(int Bs, double *out) {
@@ -181,25 +168,26 @@ void Engine::axpy(size_t n, double *out, double a0, const double *x0, double a1,
 }
 
 // Batched CG on the velocity mass matrix for the columns the preceding
-// set-up kernel prepared (r = right-hand side, x = start value, partials of
-// r.z and r.r).  Convergence is decided per column on the device.  Small
-// batches (Bs <= 4) use the fused kernels (two launches per iteration);
-// larger ones add a finalize kernel after each.  Without an iteration budget
-// the host polls the active count (first after the predicted count); with
-// one (learned from earlier calls on the context) it launches exactly that
-// many iterations and only checks at the end of the call.
+// set-up kernel prepared (r_0 in r[0], start value in x).  Convergence is
+// decided per column on the device.  Small batches (Bs <= 4) run the fused
+// kernels (one launch per iteration, each workgroup reducing the previous
+// partials); larger ones follow each iteration with a finalize kernel.
+// Without an iteration budget the host polls the active count (first after
+// the predicted count); with one (learned from earlier calls on the context)
+// exactly that many iterations are launched and convergence is checked once
+// at the end of the call.
 void Engine::cg(double *x, int Bs, const int *colK, int kneed, int nwg_init) {
+  (void)nwg_init;
   CgArgs a{};
   a.ops = ops_->d;
   a.Bs = Bs;
   a.x = x;
-  a.r = r_;
-  a.q = q_;
+  a.p = p_;
   a.rtol2 = cfg_.cg_rtol * cfg_.cg_rtol;
   a.maxit = cfg_.maxit;
   a.st = st_;
   a.rb = rb_;
-  a.count_cols = ctx_->prof_kernel;
+  a.count_cols = ctx_->prof_kernel == PA_KERNEL_CG_ITER ? 1 : 0;
   a.colK = colK;
   a.kneed = kneed;
   const int nwg = launch_rows_grid(ne_, Bs);
@@ -208,10 +196,11 @@ void Engine::cg(double *x, int Bs, const int *colK, int kneed, int nwg_init) {
     auto itb = ctx_->cg_budget.find(cfg_.cg_rtol);
     if (itb != ctx_->cg_budget.end()) budget = itb->second;
   }
-  double *pold = p0_, *pnew = p1_;
+  double *r[2] = {r_, r1_}, *w[2] = {w0_, w1_}, *sv[2] = {s0_, s1_};
+  double *part[2] = {rb_.partA, rb_.partB};
   int *hflag = (int *)ctx_->host_flag;
-  auto timed = [&](int which, auto launch) {
-    if (ctx_->prof_kernel != which) {
+  auto timed = [&](auto launch) {
+    if (ctx_->prof_kernel != PA_KERNEL_CG_ITER) {
       launch();
       return;
     }
@@ -227,77 +216,72 @@ void Engine::cg(double *x, int Bs, const int *colK, int kneed, int nwg_init) {
     PA_HIP(hipStreamSynchronize(s_));
     return *hflag;
   };
+  // w_0 = M D^-1 r_0 and the first partials
+  a.r_in = r[0];
+  a.w_out = w[0];
+  a.part_out = part[0];
+  launch_cg_init(a, s_);
+  // iteration k reads r[k&1], w[k&1], s[(k+1)&1]; writes the other halves
+  auto iter = [&](int k, bool last) {
+    a.k = k;
+    a.r_in = r[k & 1];
+    a.r_out = r[(k + 1) & 1];
+    a.w_in = w[k & 1];
+    a.w_out = w[(k + 1) & 1];
+    a.s_in = sv[(k + 1) & 1];
+    a.s_out = sv[k & 1];
+    a.part_in = part[k & 1];
+    a.part_out = part[(k + 1) & 1];
+    a.nwg_prev = nwg;
+    a.last_check = last ? 1 : 0;
+    a.check_only = last ? 1 : 0;
+    timed([&] { launch_cg_iter(a, s_); });
+  };
   int it = 0;
   if (Bs <= 4) {
+    // kernel k tests r_k and, if needed, performs iteration k
     a.fused = 1;
-    auto A = [&](int k, bool last) {
-      a.k = k;
-      a.nwg_prev = k == 0 ? nwg_init : nwg;
-      a.p_old = pold;
-      a.p_new = pnew;
-      a.last_check = last ? 1 : 0;
-      a.check_only = last ? 1 : 0;
-      timed(PA_KERNEL_CG_SPMV, [&] { launch_cg_a(a, s_); });
-    };
-    auto B = [&](int k) {
-      a.k = k;
-      a.nwg_prev = nwg;
-      a.p_new = pnew;
-      timed(PA_KERNEL_CG_UPDATE, [&] { launch_cg_b(a, s_); });
-      std::swap(pold, pnew);
-    };
-    A(0, false);
     if (budget > 0) {
-      for (int k = 0; k < budget; k++) {
-        B(k);
-        A(k + 1, k + 1 == budget);
-      }
+      for (int k = 0; k <= budget; k++) iter(k, k == budget);
       it = budget;
     } else {
-      int chunk = std::max(1, std::min(predicted_, cfg_.maxit));
+      int chunk = std::max(1, std::min(predicted_, cfg_.maxit)) + 1;
       for (;;) {
-        for (int i = 0; i < chunk && it < cfg_.maxit; i++) {
-          B(it);
-          it++;
-          A(it, false);
-        }
-        if (poll(it & 1) == 0 || it >= cfg_.maxit) break;
+        for (int i = 0; i < chunk && it <= cfg_.maxit; i++) iter(it++, false);
+        if (poll((it - 1) & 1) == 0 || it > cfg_.maxit) break;
         chunk = 1;
       }
+      it -= 1;
     }
   } else {
+    // kernel k performs iteration k; the finalize after it tests r_{k+1}
     a.fused = 0;
-    finalize_init(nwg_init, Bs, colK, kneed);
     FinArgs fa{};
     fa.Bs = Bs;
-    fa.nwg = nwg;
     fa.max_wg = rb_.max_wg;
+    fa.nq = 3;
     fa.st = st_;
     fa.rtol2 = a.rtol2;
     fa.maxit = a.maxit;
+    fa.mode = FIN_INIT;
+    fa.nwg = nwg;
+    fa.part = part[0];
+    fa.colK = colK;
+    fa.kneed = kneed;
+    fa.slot_out = 1;
+    launch_finalize(fa, s_);
+    fa.mode = FIN_STEP;
     const int total = budget > 0 ? budget : cfg_.maxit;
     int chunk = budget > 0 ? budget : std::max(1, std::min(predicted_, cfg_.maxit));
     for (;;) {
       for (int i = 0; i < chunk && it < total; i++) {
         const int k = it++;
-        a.p_old = pold;
-        a.p_new = pnew;
-        a.slot_in = (k + 1) & 1;  // count written by the previous finalize
-        timed(PA_KERNEL_CG_SPMV, [&] { launch_cg_a(a, s_); });
-        fa.mode = FIN_ALPHA;
-        fa.nq = 1;
-        fa.part = rb_.partA;
+        iter(k, false);
+        fa.part = part[(k + 1) & 1];
         fa.slot_in = (k + 1) & 1;
-        fa.slot_zero = k & 1;
-        launch_finalize(fa, s_);
-        timed(PA_KERNEL_CG_UPDATE, [&] { launch_cg_b(a, s_); });
-        fa.mode = FIN_BETA;
-        fa.nq = 2;
-        fa.part = rb_.partB;
         fa.slot_out = k & 1;
         fa.last_check = (budget > 0 && it == budget) ? 1 : 0;
         launch_finalize(fa, s_);
-        std::swap(pold, pnew);
       }
       if (budget > 0 || it >= total) break;
       if (poll((it - 1) & 1) == 0) break;

@@ -97,7 +97,6 @@ class Engine {
             const double *x1 = nullptr, double a2 = 0, const double *x2 = nullptr);
   void upload(void *dst, const void *src, size_t bytes);
   hipEvent_t take_event();
-  void finalize_init(int nwg, int Bs, const int *colK, int kneed);
   void wdot_out(int Bs, double *out);
   std::vector<hipEvent_t> prof_ev_;
 
@@ -133,7 +132,8 @@ class Engine {
   Arena ar_;
   // CG scratch
   int BsMax_ = 0;
-  double *r_ = nullptr, *p0_ = nullptr, *p1_ = nullptr, *q_ = nullptr;
+  double *r_ = nullptr, *r1_ = nullptr, *w0_ = nullptr, *w1_ = nullptr;
+  double *s0_ = nullptr, *s1_ = nullptr, *p_ = nullptr;
   double *ut0_ = nullptr, *ut1_ = nullptr, *C_ = nullptr;
   SolveState st_{};
   RedBuf rb_{};

@@ -20,8 +20,8 @@ struct SolveState {
   int *active, *iters;
   // fused small-batch CG: per-column scalars double-buffered by iteration
   // parity so that workgroup 0 can publish them while others still read
-  double *rz2;            // [2][Bs]
-  int *act2, *it2;        // [2][Bs]
+  double *rz2, *al2;      // [2][4]: gamma and alpha
+  int *act2, *it2;        // [2][4]
   int *cnt;               // [2]: active columns after the last finalize, by parity
   int *budget_fail;       // 1: columns still active when an iteration budget ran out
   int *fail;              // 1 (accumulates over solves)
@@ -50,21 +50,24 @@ struct StiffArgs {
 struct CgArgs {
   DevOps ops;
   int Bs;
-  int count_cols;  // measurement hook: tally active columns of each launch
-  int slot_in;     // cnt slot holding the active count (early exit when 0)
-  // fused small-batch mode (Bs <= 4): every workgroup reduces the partials
-  // of the previous kernel itself
-  int fused, k, nwg_prev, check_only, last_check;
-  const int *colK;
-  int kneed;
-  double *x, *r, *p_old, *p_new, *q;
+  double *x, *p;
+  const double *r_in, *w_in, *s_in;
+  double *r_out, *w_out, *s_out;
+  const double *part_in;  // partials of the previous kernel (fused mode)
+  double *part_out;
   double rtol2;
   int maxit;
+  int k;          // iteration index
+  int fused;      // Bs <= 4: every workgroup reduces part_in itself
+  int nwg_prev, check_only, last_check;
+  int count_cols; // measurement hook: tally active columns of each launch
+  const int *colK;
+  int kneed;
   SolveState st;
   RedBuf rb;
 };
 
-enum { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_OUT = 3 };
+enum { FIN_INIT = 0, FIN_STEP = 1, FIN_OUT = 2 };
 struct FinArgs {
   int mode, Bs, nwg, max_wg, nq;
   const double *part;
@@ -142,8 +145,8 @@ int launch_max_wg();
 int launch_rows_grid(int rows, int Bs);
 void launch_finalize(const FinArgs &a, hipStream_t s);
 void launch_stiff(const StiffArgs &a, hipStream_t s);
-void launch_cg_a(const CgArgs &a, hipStream_t s);
-void launch_cg_b(const CgArgs &a, hipStream_t s);
+void launch_cg_init(const CgArgs &a, hipStream_t s);
+void launch_cg_iter(const CgArgs &a, hipStream_t s);
 void launch_combine(const CombineArgs &a, hipStream_t s);
 void launch_reduce_terms(const ReduceTermsArgs &a, hipStream_t s);
 void launch_nl_upwind(const NlArgs &a, hipStream_t s);

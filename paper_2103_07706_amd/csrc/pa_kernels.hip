@@ -22,10 +22,15 @@ constexpr int kWG = 256;
 constexpr int kGroup = 32;
 
 struct Lane {
-  int ct, rw, col, tile, row0, rstride, lane, wave;
+  int ct, rw, col, tile, row0, rstride, rend, lane, wave;
 };
 
-__device__ inline Lane lane_map(int Bs) {
+// Rows of a launch are split XCD-aware: workgroups are dispatched round-robin
+// over the eight XCDs (blockIdx.x % 8), so each XCD gets one contiguous slice
+// of rows and each of its workgroups a contiguous block of that slice.  Rows
+// that are ELL neighbours (numbered close together) then meet in one XCD's
+// L2 instead of being fetched by several.  gridDim.x is a multiple of 8.
+__device__ inline Lane lane_map(int Bs, int nrows) {
   Lane L;
   L.ct = Bs < 64 ? Bs : 64;
   L.rw = 64 / L.ct;
@@ -33,8 +38,13 @@ __device__ inline Lane lane_map(int Bs) {
   L.wave = threadIdx.x >> 6;
   L.tile = blockIdx.y;
   L.col = L.tile * L.ct + (L.lane % L.ct);
-  L.row0 = (blockIdx.x * (kWG / 64) + L.wave) * L.rw + L.lane / L.ct;
-  L.rstride = gridDim.x * (kWG / 64) * L.rw;
+  const int G = gridDim.x;
+  const int v = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+  const int rpw = (nrows + G - 1) / G;
+  const int rbeg = v * rpw;
+  L.rend = min(nrows, rbeg + rpw);
+  L.row0 = rbeg + L.wave * L.rw + L.lane / L.ct;
+  L.rstride = (kWG / 64) * L.rw;
   return L;
 }
 
@@ -92,19 +102,17 @@ __device__ void count_active(const Lane &L, SolveState st) {
 // for columns with colK[c] >= kneed; optionally acc += coef * in (grouped
 // column sums of G columns) for columns with colK[c] >= acc_k.
 __global__ __launch_bounds__(kWG) void k_stiff(StiffArgs a) {
-  const Lane L = lane_map(a.Bs);
+  const Lane L = lane_map(a.Bs, a.ops.ne > a.ops.nc ? a.ops.ne : a.ops.nc);
   const DevOps &o = a.ops;
   const int c = L.col, Bs = a.Bs;
   const bool act = a.colK[c] >= a.kneed;
   const bool acc_on = a.acc_u != nullptr && a.colK[c] >= a.acc_k;
   const double coef = acc_on ? a.coef[c] : 0.0;
-  double sums[2] = {0.0, 0.0};
-  const int nrow = o.ne > o.nc ? o.ne : o.nc;
-  for (int base = L.row0 - L.lane / L.ct; base < nrow; base += L.rstride) {
+  for (int base = L.row0 - L.lane / L.ct; base < L.rend; base += L.rstride) {
     const int e = base + L.lane / L.ct;
     // edges
     double accv = 0.0;
-    if (e < o.ne) {
+    if (e < o.ne && e < L.rend) {
       const size_t ie = (size_t)e * Bs + c;
       if (act) {
         double fu = 0.0;
@@ -118,19 +126,17 @@ __global__ __launch_bounds__(kWG) void k_stiff(StiffArgs a) {
         if (a.addB_u) x0 += a.addB_u[ie];
         a.r[ie] = r;
         a.out_u[ie] = x0;
-        sums[0] += r * r * o.dinv[e];
-        sums[1] += r * r;
       }
       if (acc_on) accv = coef * a.in_u[ie];
     }
     if (a.acc_u) {
       double s = lane_group_sum(accv, a.G);
-      if (e < o.ne && (c % a.G) == 0)
+      if (e < o.ne && e < L.rend && (c % a.G) == 0)
         a.acc_u[(size_t)e * (Bs / a.G) + c / a.G] += s;
     }
     // cells
     double acce = 0.0;
-    if (e < o.nc) {
+    if (e < o.nc && e < L.rend) {
       const int t = e;
       const size_t it = (size_t)t * Bs + c;
       if (act) {
@@ -147,73 +153,114 @@ __global__ __launch_bounds__(kWG) void k_stiff(StiffArgs a) {
     }
     if (a.acc_u) {
       double s = lane_group_sum(acce, a.G);
-      if (e < o.nc && (c % a.G) == 0)
+      if (e < o.nc && e < L.rend && (c % a.G) == 0)
         a.acc_eta[(size_t)e * (Bs / a.G) + c / a.G] += s;
     }
   }
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) a.st.cnt[1] = 0;
-  wg_partials<2>(L, sums, a.rb.partB, a.rb.max_wg);
 }
 
-// ------------------------------------------------------------- CG: p, q=Mp
-// Fused small-batch prologue (Bs <= 4, one wave per column): reduce the
-// (r.z, r.r) partials of the previous kernel, decide convergence and beta;
-// workgroup 0 publishes the scalars for the iteration's parity.
+// -------------------------------------------------- CG (Chronopoulos-Gear)
+// Jacobi-preconditioned CG in the single-reduction form of Chronopoulos and
+// Gear: with u = D^-1 r and w = M u,
+//   p = u + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s,
+//   u' = D^-1 r,  w' = M u',  gamma' = r'.u',  delta' = w'.u',
+//   beta' = gamma'/gamma,  alpha' = gamma' / (delta' - beta' gamma'/alpha).
+// One kernel per iteration.  u' at the five ELL neighbours is recomputed from
+// the previous iteration's r, w and s (those arrays are double-buffered), so
+// no second grid-wide step is needed between the update and the SpMV.
+//
+// Set-up: k_cg_init forms w_0 = M D^-1 r_0 and the partials of
+// (gamma_0, delta_0, |r_0|^2).  Columns converge when |r|^2 <= rtol^2 |b|^2.
+
+// w_0 = M D^-1 r_0 and partials (r.u, w.u, r.r).
+__global__ __launch_bounds__(kWG) void k_cg_init(CgArgs a) {
+  const Lane L = lane_map(a.Bs, a.ops.ne);
+  const DevOps &o = a.ops;
+  const int c = L.col, Bs = a.Bs;
+  const bool on = a.colK[c] >= a.kneed;
+  double sums[3] = {0.0, 0.0, 0.0};
+  if (on) {
+    for (int e = L.row0; e < L.rend; e += L.rstride) {
+      double w = 0.0;
+#pragma unroll
+      for (int j = 0; j < 5; j++) {
+        const int col = o.ell_col[5 * e + j];
+        w += o.mass[5 * e + j] * (o.dinv[col] * a.r_in[(size_t)col * Bs + c]);
+      }
+      const size_t ie = (size_t)e * Bs + c;
+      const double r = a.r_in[ie], u = o.dinv[e] * r;
+      a.w_out[ie] = w;
+      sums[0] += r * u;
+      sums[1] += w * u;
+      sums[2] += r * r;
+    }
+  }
+  wg_partials<3>(L, sums, a.part_out, a.rb.max_wg);
+}
+
+// Fused small-batch prologue (Bs <= 4, tile 0, one wave per column): reduce
+// the previous kernel's partials, test convergence, form alpha and beta.
+// Workgroup 0 publishes the scalars into the iteration's parity slot; all
+// workgroups take the same decisions from the same sums.
 struct FusedCols {
-  double beta[4];
+  double alpha[4], beta[4];
   int act[4];
   int any;
 };
 
-__device__ void fused_convergence(const CgArgs &a, const Lane &L, FusedCols &fc) {
+__device__ void fused_step(const CgArgs &a, const Lane &L, FusedCols &fc) {
   const SolveState st = a.st;
   if (threadIdx.x == 0) fc.any = 0;
   __syncthreads();
   const int cc = L.wave;
   if (cc < L.ct) {
-    double v0 = 0.0, v1 = 0.0;
-    for (int g = L.lane; g < a.nwg_prev; g += 64) {
-      v0 += a.rb.partB[((size_t)g * 2 + 0) * 64 + cc];
-      v1 += a.rb.partB[((size_t)g * 2 + 1) * 64 + cc];
-    }
-    v0 = wave_col_sum(v0, 1);
-    v1 = wave_col_sum(v1, 1);
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int g = L.lane; g < a.nwg_prev; g += 64)
+#pragma unroll
+      for (int q = 0; q < 3; q++) v[q] += a.part_in[((size_t)g * 3 + q) * 64 + cc];
+#pragma unroll
+    for (int q = 0; q < 3; q++) v[q] = wave_col_sum(v[q], 1);
     if (L.lane == 0) {
       const int cur = a.k & 1, prev = cur ^ 1;
       const bool w0 = blockIdx.x == 0;
-      double beta = 0.0;
+      double alpha = 0.0, beta = 0.0;
       int act = 0;
       if (a.k == 0) {
-        act = (a.colK[cc] >= a.kneed && v1 > 0.0) ? 1 : 0;
+        act = (a.colK[cc] >= a.kneed && v[2] > 0.0) ? 1 : 0;
+        alpha = act ? v[0] / v[1] : 0.0;
         if (w0) {
-          st.bb[cc] = v1;
-          st.resid[cc] = 0.0;
+          st.bb[cc] = v[2];
+          st.resid[cc] = act ? 1.0 : 0.0;
           st.it2[cur * 4 + cc] = 0;
-          st.rz2[cur * 4 + cc] = v0;
-          st.act2[cur * 4 + cc] = act;
+          st.rz2[cur * 4 + cc] = v[0];
+          st.al2[cur * 4 + cc] = alpha;
         }
       } else if (st.act2[prev * 4 + cc]) {
         const int it = st.it2[prev * 4 + cc] + 1;
         const double bb = st.bb[cc];
         bool fail = false;
-        if (v1 <= a.rtol2 * bb) {
+        if (v[2] <= a.rtol2 * bb) {
           act = 0;
         } else if (it >= a.maxit) {
           fail = true;
         } else {
           act = 1;
-          beta = v0 / st.rz2[prev * 4 + cc];
+          beta = v[0] / st.rz2[prev * 4 + cc];
+          alpha = v[0] / (v[1] - beta * v[0] / st.al2[prev * 4 + cc]);
         }
         if (w0) {
           st.it2[cur * 4 + cc] = it;
-          st.resid[cc] = sqrt(v1 / bb);
-          st.rz2[cur * 4 + cc] = v0;
+          st.rz2[cur * 4 + cc] = v[0];
+          st.al2[cur * 4 + cc] = alpha;
+          st.resid[cc] = sqrt(v[2] / bb);
           if (fail) atomicAdd(st.fail, 1);
           if (act && a.last_check) atomicAdd(st.budget_fail, 1);
           atomicMax(st.iter_max, it);
         }
       }
       if (w0) st.act2[cur * 4 + cc] = act;
+      fc.alpha[cc] = alpha;
       fc.beta[cc] = beta;
       fc.act[cc] = act;
       if (act) atomicOr(&fc.any, 1);
@@ -224,108 +271,69 @@ __device__ void fused_convergence(const CgArgs &a, const Lane &L, FusedCols &fc)
     int n = 0;
     for (int j = 0; j < L.ct; j++) n += fc.act[j];
     st.cnt[a.k & 1] = n;
-    if (a.count_cols == 1 && n > 0 && !a.check_only) {
+    if (a.count_cols && n > 0 && !a.check_only) {
       atomicAdd(&st.prof[0], (unsigned)n);
       atomicAdd(&st.prof[1], 1u);
     }
   }
 }
 
-__global__ __launch_bounds__(kWG) void k_cg_a(CgArgs a) {
+// One CG iteration for every active column.
+__global__ __launch_bounds__(kWG) void k_cg_iter(CgArgs a) {
   const SolveState st = a.st;
-  const Lane L = lane_map(a.Bs);
+  const Lane L = lane_map(a.Bs, a.ops.ne);
   __shared__ FusedCols fc;
   bool act;
-  double beta;
+  double alpha, beta;
   if (a.fused) {
-    fused_convergence(a, L, fc);
+    fused_step(a, L, fc);
     if (!fc.any || a.check_only) return;
     act = fc.act[L.col] != 0;
-    beta = act ? fc.beta[L.col] : 0.0;
+    alpha = fc.alpha[L.col];
+    beta = fc.beta[L.col];
   } else {
-    if (st.cnt[a.slot_in] == 0) return;
-    if (a.count_cols == 1) count_active(L, st);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) st.cnt[a.k & 1] = 0;
+    if (st.cnt[(a.k + 1) & 1] == 0) return;
+    if (a.count_cols) count_active(L, st);
     act = st.active[L.col] != 0;
+    alpha = act ? st.alpha[L.col] : 0.0;
     beta = act ? st.beta[L.col] : 0.0;
   }
   const DevOps &o = a.ops;
   const int c = L.col, Bs = a.Bs;
-  double sums[1] = {0.0};
+  double sums[3] = {0.0, 0.0, 0.0};
   if (act) {
-    for (int e = L.row0; e < o.ne; e += L.rstride) {
-      double q = 0.0, pe = 0.0;
+    for (int e = L.row0; e < L.rend; e += L.rstride) {
+      double wn = 0.0, se = 0.0, rn = 0.0, un = 0.0;
 #pragma unroll
       for (int j = 0; j < 5; j++) {
         const int col = o.ell_col[5 * e + j];
         const size_t ij = (size_t)col * Bs + c;
-        double pj = o.dinv[col] * a.r[ij];
-        if (beta != 0.0) pj += beta * a.p_old[ij];
-        q += o.mass[5 * e + j] * pj;
-        if (j == 0) pe = pj;
+        double s = a.w_in[ij];
+        if (beta != 0.0) s += beta * a.s_in[ij];
+        const double r = a.r_in[ij] - alpha * s;
+        const double u = o.dinv[col] * r;
+        wn += o.mass[5 * e + j] * u;
+        if (j == 0) {
+          se = s;
+          rn = r;
+          un = u;
+        }
       }
       const size_t ie = (size_t)e * Bs + c;
-      a.p_new[ie] = pe;
-      a.q[ie] = q;
-      sums[0] += pe * q;
+      double p = o.dinv[e] * a.r_in[ie];
+      if (beta != 0.0) p += beta * a.p[ie];
+      a.p[ie] = p;
+      a.x[ie] += alpha * p;
+      a.s_out[ie] = se;
+      a.r_out[ie] = rn;
+      a.w_out[ie] = wn;
+      sums[0] += rn * un;
+      sums[1] += wn * un;
+      sums[2] += rn * rn;
     }
   }
-  wg_partials<1>(L, sums, a.rb.partA, a.rb.max_wg);
-}
-
-// ---------------------------------------------- CG: x += a p, r -= a q, test
-__global__ __launch_bounds__(kWG) void k_cg_b(CgArgs a) {
-  const SolveState st = a.st;
-  const Lane L = lane_map(a.Bs);
-  bool act;
-  double alpha;
-  if (a.fused) {
-    // alpha = rz / p.q from the SpMV kernel's partials (one wave per column)
-    __shared__ double s_alpha[4];
-    __shared__ int s_act[4], s_any;
-    if (threadIdx.x == 0) s_any = 0;
-    __syncthreads();
-    const int cc = L.wave, cur = a.k & 1;
-    if (cc < L.ct) {
-      double pq = 0.0;
-      for (int g = L.lane; g < a.nwg_prev; g += 64) pq += a.rb.partA[(size_t)g * 64 + cc];
-      pq = wave_col_sum(pq, 1);
-      if (L.lane == 0) {
-        const int on = st.act2[cur * 4 + cc];
-        s_act[cc] = on;
-        s_alpha[cc] = on ? st.rz2[cur * 4 + cc] / pq : 0.0;
-        if (on) atomicOr(&s_any, 1);
-      }
-    }
-    __syncthreads();
-    if (!s_any) return;
-    if (a.count_cols == 2 && blockIdx.x == 0 && threadIdx.x == 0) {
-      unsigned n = 0;
-      for (int j = 0; j < L.ct; j++) n += s_act[j];
-      atomicAdd(&st.prof[0], n);
-      atomicAdd(&st.prof[1], 1u);
-    }
-    act = s_act[L.col] != 0;
-    alpha = s_alpha[L.col];
-  } else {
-    if (st.cnt[a.slot_in] == 0) return;
-    if (a.count_cols == 2) count_active(L, st);
-    act = st.active[L.col] != 0;
-    alpha = act ? st.alpha[L.col] : 0.0;
-  }
-  const DevOps &o = a.ops;
-  const int c = L.col, Bs = a.Bs;
-  double sums[2] = {0.0, 0.0};
-  if (act) {
-    for (int e = L.row0; e < o.ne; e += L.rstride) {
-      const size_t ie = (size_t)e * Bs + c;
-      a.x[ie] += alpha * a.p_new[ie];
-      const double r = a.r[ie] - alpha * a.q[ie];
-      a.r[ie] = r;
-      sums[0] += r * r * o.dinv[e];
-      sums[1] += r * r;
-    }
-  }
-  wg_partials<2>(L, sums, a.rb.partB, a.rb.max_wg);
+  wg_partials<3>(L, sums, a.part_out, a.rb.max_wg);
 }
 
 // ------------------------------------------- forward combination of a basis
@@ -365,10 +373,10 @@ __global__ __launch_bounds__(kWG) void k_reduce_terms(ReduceTermsArgs a) {
 // Upwind tangential velocity at the two Gauss points of every edge, from the
 // cell the edge flux leaves (flux > 0: c0, otherwise c1).
 __global__ __launch_bounds__(kWG) void k_nl_upwind(NlArgs a) {
-  const Lane L = lane_map(a.Bs);
+  const Lane L = lane_map(a.Bs, a.ops.ne);
   const DevOps &o = a.ops;
   const int c = L.col, Bs = a.Bs;
-  for (int e = L.row0; e < o.ne; e += L.rstride) {
+  for (int e = L.row0; e < L.rend; e += L.rstride) {
     const size_t ie = (size_t)e * Bs + c;
     const int side = a.u[ie] > 0.0 ? 0 : 1;
     const double *tau = o.tau + (size_t)kEdgeTau * e + 6 * side;
@@ -391,11 +399,11 @@ __global__ __launch_bounds__(kWG) void k_nl_upwind(NlArgs a) {
 //         - sum_a s_a int_{side a} (t_e . u~) q_i ds,
 //   q_i = (k x u) . phi_i (affine on T), eta2 = -sum_a s_a U_a (eta-b)_up / |T|.
 __global__ __launch_bounds__(kWG) void k_nl_cell(NlArgs a) {
-  const Lane L = lane_map(a.Bs);
+  const Lane L = lane_map(a.Bs, a.ops.nc);
   const DevOps &o = a.ops;
   const int c = L.col, Bs = a.Bs;
   const double gq = 0.28867513459481288225;  // 1/(2 sqrt 3)
-  for (int t = L.row0; t < o.nc; t += L.rstride) {
+  for (int t = L.row0; t < L.rend; t += L.rstride) {
     const double *g = o.cgeo + (size_t)t * kCellGeo;
     double p[3][3], k[3], gl[3][3], len[3];
 #pragma unroll
@@ -529,36 +537,30 @@ __global__ __launch_bounds__(kWG) void k_nl_cell(NlArgs a) {
 
 // Velocity right-hand side r_e = C[c0][l0] + C[c1][l1] and CG start x = 0.
 __global__ __launch_bounds__(kWG) void k_nl_gather(GatherArgs a) {
-  const Lane L = lane_map(a.Bs);
+  const Lane L = lane_map(a.Bs, a.ops.ne);
   const DevOps &o = a.ops;
   const int c = L.col, Bs = a.Bs;
-  const bool act = a.colK[c] >= a.kneed;
-  double sums[2] = {0.0, 0.0};
-  if (act) {
-    for (int e = L.row0; e < o.ne; e += L.rstride) {
+  if (a.colK[c] >= a.kneed) {
+    for (int e = L.row0; e < L.rend; e += L.rstride) {
       const size_t ie = (size_t)e * Bs + c;
-      const double r = a.C[(size_t)o.cidx[2 * e] * Bs + c] + a.C[(size_t)o.cidx[2 * e + 1] * Bs + c];
-      a.r[ie] = r;
+      a.r[ie] = a.C[(size_t)o.cidx[2 * e] * Bs + c] + a.C[(size_t)o.cidx[2 * e + 1] * Bs + c];
       a.x[ie] = 0.0;
-      sums[0] += r * r * o.dinv[e];
-      sums[1] += r * r;
     }
   }
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) a.st.cnt[1] = 0;
-  wg_partials<2>(L, sums, a.rb.partB, a.rb.max_wg);
 }
 
 // ----------------------------------------------------------- elementwise
 // acc[row][c/G] += sum over the G-column group of coef[c] * in[row][c]
 // (columns with colK[c] >= acc_k), over both row ranges.
 __global__ __launch_bounds__(kWG) void k_acc(AccArgs a) {
-  const Lane L = lane_map(a.Bs);
+  const Lane L = lane_map(a.Bs, a.nrows);
   const int c = L.col, Bs = a.Bs;
   const bool on = a.colK[c] >= a.acc_k;
   const double coef = on ? a.coef[c] : 0.0;
-  for (int base = L.row0 - L.lane / L.ct; base < a.nrows; base += L.rstride) {
+  for (int base = L.row0 - L.lane / L.ct; base < L.rend; base += L.rstride) {
     const int row = base + L.lane / L.ct;
-    const bool in = row < a.nrows;
+    const bool in = row < L.rend;
     double v = (in && on) ? coef * a.in[(size_t)row * Bs + c] : 0.0;
     v = lane_group_sum(v, a.G);
     if (in && (c % a.G) == 0) a.acc[(size_t)row * (Bs / a.G) + c / a.G] += v;
@@ -595,12 +597,11 @@ __global__ __launch_bounds__(kWG) void k_from_block(TransArgs a) {
 // Per-column energy inner products <X, Y>_W = H x_u' M y_u + g sum |c| x_eta y_eta
 // and the mass sum |c| x_eta, reduced deterministically into out[3][Bs].
 __global__ __launch_bounds__(kWG) void k_wdot(WdotArgs a) {
-  const Lane L = lane_map(a.Bs);
+  const Lane L = lane_map(a.Bs, a.ops.ne > a.ops.nc ? a.ops.ne : a.ops.nc);
   const DevOps &o = a.ops;
   const int c = L.col, Bs = a.Bs;
   double sums[2] = {0.0, 0.0};
-  const int nrow = o.ne > o.nc ? o.ne : o.nc;
-  for (int r = L.row0; r < nrow; r += L.rstride) {
+  for (int r = L.row0; r < L.rend; r += L.rstride) {
     if (r < o.ne) {
       double my = 0.0;
 #pragma unroll
@@ -633,8 +634,7 @@ __global__ void k_zero(unsigned *p, size_t n) {
 // Active columns are counted into cnt[slot_out] (integer atomics).
 __global__ __launch_bounds__(kWG) void k_finalize(FinArgs a) {
   const SolveState st = a.st;
-  if (a.mode == FIN_ALPHA && blockIdx.x == 0 && threadIdx.x == 0) st.cnt[a.slot_zero] = 0;
-  if ((a.mode == FIN_ALPHA || a.mode == FIN_BETA) && st.cnt[a.slot_in] == 0) return;
+  if (a.mode == FIN_STEP && st.cnt[a.slot_in] == 0) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ct = a.Bs < 64 ? a.Bs : 64;
   const int cpb = ct < 4 ? ct : 4;            // columns per workgroup
@@ -643,7 +643,7 @@ __global__ __launch_bounds__(kWG) void k_finalize(FinArgs a) {
   const int cl = (blockIdx.x % blocks_per_tile) * cpb + wave;  // column in tile
   if (wave >= cpb) return;
   const int c = tile * ct + cl;
-  double v[2] = {0.0, 0.0};
+  double v[3] = {0.0, 0.0, 0.0};
   for (int w = lane; w < a.nwg; w += 64)
     for (int q = 0; q < a.nq; q++)
       v[q] += a.part[(((size_t)tile * a.max_wg + w) * a.nq + q) * 64 + cl];
@@ -651,27 +651,30 @@ __global__ __launch_bounds__(kWG) void k_finalize(FinArgs a) {
   if (lane != 0) return;
   bool on = false;
   if (a.mode == FIN_INIT) {
-    on = a.colK[c] >= a.kneed && v[1] > 0.0;
-    st.bb[c] = v[1];
+    // (gamma_0, delta_0, |b|^2)
+    on = a.colK[c] >= a.kneed && v[2] > 0.0;
+    st.bb[c] = v[2];
     st.rz[c] = v[0];
+    st.alpha[c] = on ? v[0] / v[1] : 0.0;
     st.beta[c] = 0.0;
     st.iters[c] = 0;
-    st.resid[c] = 0.0;
+    st.resid[c] = on ? 1.0 : 0.0;
     st.active[c] = on ? 1 : 0;
-  } else if (a.mode == FIN_ALPHA) {
-    if (st.active[c]) st.alpha[c] = st.rz[c] / v[0];
-  } else if (a.mode == FIN_BETA) {
+  } else if (a.mode == FIN_STEP) {
+    // (gamma', delta', |r'|^2) after one iteration
     if (st.active[c]) {
       const int it = st.iters[c] + 1;
       st.iters[c] = it;
-      st.resid[c] = sqrt(v[1] / st.bb[c]);
-      if (v[1] <= a.rtol2 * st.bb[c]) {
+      st.resid[c] = sqrt(v[2] / st.bb[c]);
+      if (v[2] <= a.rtol2 * st.bb[c]) {
         st.active[c] = 0;
       } else if (it >= a.maxit) {
         st.active[c] = 0;
         atomicAdd(st.fail, 1);
       } else {
-        st.beta[c] = v[0] / st.rz[c];
+        const double beta = v[0] / st.rz[c];
+        st.alpha[c] = v[0] / (v[1] - beta * v[0] / st.alpha[c]);
+        st.beta[c] = beta;
         st.rz[c] = v[0];
         on = true;
         if (a.last_check) atomicAdd(st.budget_fail, 1);
@@ -687,14 +690,25 @@ __global__ __launch_bounds__(kWG) void k_finalize(FinArgs a) {
 
 // ------------------------------------------------------------ launchers
 namespace {
+// Workgroups along the rows of one column tile (a multiple of 8, see
+// lane_map).  Narrow batches (Bs <= 4) are latency-bound: about four rows per
+// thread keeps the launch short and the partial sums few.  Wider ones fill
+// the 256 CUs several times over, split over the column tiles.
 int grid_rows(int rows, int Bs) {
   const int ct = Bs < 64 ? Bs : 64;
-  const int rows_per_wg = (kWG / 64) * (64 / ct);
+  const int rows_per_pass = (kWG / 64) * (64 / ct);
   const int ctiles = (Bs + 63) / 64;
-  int want = (rows + rows_per_wg - 1) / rows_per_wg;
-  // enough workgroups to fill 256 CUs several times over, split over tiles
-  int cap = ctiles >= 8 ? 256 : 2048 / ctiles;
-  return want < cap ? (want > 0 ? want : 1) : cap;
+  int want, cap;
+  if (Bs <= 4) {
+    want = (rows + 4 * rows_per_pass - 1) / (4 * rows_per_pass);
+    cap = 256;
+  } else {
+    want = (rows + rows_per_pass - 1) / rows_per_pass;
+    cap = ctiles >= 8 ? 256 : 2048 / ctiles;
+  }
+  int g = want < cap ? want : cap;
+  g = (g + 7) / 8 * 8;
+  return g > 0 ? g : 8;
 }
 int grid_flat(size_t n) {
   size_t g = (n + kWG - 1) / kWG;
@@ -710,11 +724,11 @@ void launch_stiff(const StiffArgs &a, hipStream_t s) {
   const int nrow = a.ops.ne > a.ops.nc ? a.ops.ne : a.ops.nc;
   hipLaunchKernelGGL(k_stiff, rows_grid(nrow, a.Bs), dim3(kWG), 0, s, a);
 }
-void launch_cg_a(const CgArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_a, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+void launch_cg_init(const CgArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_init, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
 }
-void launch_cg_b(const CgArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_b, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+void launch_cg_iter(const CgArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_iter, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
 }
 void launch_combine(const CombineArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_combine, dim3(grid_flat((size_t)a.nrows * a.BsE)), dim3(kWG), 0, s, a);

@@ -44,7 +44,7 @@ class SolveCfg(ctypes.Structure):
                 ("weight_cut", ctypes.c_double), ("inner_rtol", ctypes.c_double)]
 
 
-PA_KERNEL_NONE, PA_KERNEL_CG_SPMV, PA_KERNEL_CG_UPDATE = 0, 1, 2
+PA_KERNEL_NONE, PA_KERNEL_CG_ITER = 0, 1
 
 
 class KernelProfile(ctypes.Structure):
