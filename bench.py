@@ -30,7 +30,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="l6_m64")
-    ap.add_argument("--backward", default="per_term", choices=["per_term", "clenshaw"])
+    ap.add_argument("--backward", default="clenshaw", choices=["per_term", "clenshaw"])
+    ap.add_argument("--graph", type=int, default=1)
+    ap.add_argument("--autotune", type=int, default=1)
     ap.add_argument("--cpu-baseline", dest="cpu", type=int, default=1)
     ap.add_argument("--cpu-terms", type=int, default=4)
     return ap.parse_args()
@@ -97,8 +99,12 @@ def main():
         dtype=torch.float64, device="cuda:0")
     avg = pa.Avg(wl.M, wl.T)
     bw = pa.PA_BACKWARD_PER_TERM if args.backward == "per_term" else pa.PA_BACKWARD_CLENSHAW
-    cfg = pa.solve_cfg(backward=bw, cheb_tol=1e-6, cg_rtol=1e-10)
+    cfg = pa.solve_cfg(backward=bw, cheb_tol=1e-6, cg_rtol=1e-10, use_graph=bool(args.graph))
     out = torch.empty_like(U)
+    tune = None
+    if args.autotune:
+        tune = ops.autotune(avg, U, cfg)
+        print(f"autotune {tune}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         ops.phase_avg_rhs(avg, U, cfg, out=out)
         print("warmup step done", file=sys.stderr, flush=True)
@@ -141,7 +147,9 @@ def main():
                    "cheb_tol": 1e-6, "cg_rtol": 1e-10, "backward": args.backward,
                    "precision": "fp64", "preconditioner": "jacobi", "lambda_bar": lam,
                    "kmax": stats["kmax"], "ksum": stats["ksum"], "terms": stats["terms"],
-                   "cg_iters_max": stats["cg_iters_max"], "solves": stats["solves"]},
+                   "cg_iters_max": stats["cg_iters_max"], "solves": stats["solves"],
+                   "graph": bool(stats["graph"]), "cg_budget": stats["budget"],
+                   "launch_tune": tune},
         "roofline": {"bound": "hbm", "kernel": "k_cg_iter", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "avg_launch_us": 1e3 * avg_ms,

@@ -130,6 +130,10 @@ typedef struct {
   double cheb_tol;     /* Chebyshev truncation threshold (paper: 1e-6) */
   double weight_cut;   /* skip terms with w_m < weight_cut * max_j w_j */
   double inner_rtol;   /* FP32 inner solve tolerance (PA_FP32_REFINED) */
+  int32_t use_graph;   /* 1: capture pa_phase_avg_rhs into a HIP graph once an
+                          iteration budget is known and replay it while its
+                          inputs (pointers, sizes, settings) stay the same */
+  int32_t reserved;
 } pa_solve_cfg;
 void pa_solve_cfg_default(pa_solve_cfg *cfg);
 
@@ -145,6 +149,8 @@ typedef struct {
   int32_t guard_trips;
   double resid_max;      /* largest final relative residual of a solve */
   double device_ms;      /* device time of the call */
+  int32_t graph;         /* 1 if the call ran as a graph replay or capture */
+  int32_t budget;        /* CG iterations per solve launched (0: polled) */
 } pa_stats;
 
 /* Device workspace bytes for calls on 'batch' states (expL_apply,
@@ -211,6 +217,24 @@ int pa_ctx_profile(pa_ctx *ctx, int kernel);
  * sets (iters > 0) or clears (iters = 0) the remembered value, e.g. to test
  * the repeat path. */
 int pa_ctx_set_cg_budget(pa_ctx *ctx, double cg_rtol, int iters);
+
+/* ---- launch shape and autotuner -------------------------------------------
+ * Row-parallel kernels take their grid from a process-wide launch shape:
+ * rows per thread for batches of at most 4 columns (latency-bound), and the
+ * workgroup cap per column tile for wider batches.  pa_autotune times
+ * pa_phase_avg_rhs over a small set of shapes on the given problem (the
+ * workspace must fit it) and keeps the fastest; it returns the choice and
+ * the best time. */
+typedef struct {
+  int32_t narrow_rows_per_thread;
+  int32_t wide_max_wg;
+  double best_ms;
+} pa_launch_tune;
+int pa_get_launch_tune(pa_launch_tune *out);
+int pa_set_launch_tune(const pa_launch_tune *t);
+int pa_autotune(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int members,
+                const double *U_dev, double *out_dev, void *ws_dev,
+                size_t ws_bytes, const pa_solve_cfg *cfg, pa_launch_tune *out);
 int pa_ctx_profile_read(pa_ctx *ctx, pa_kernel_profile *out);
 
 #ifdef __cplusplus

@@ -98,6 +98,10 @@ int pa_ctx_profile_read(pa_ctx *ctx, pa_kernel_profile *out) {
 int pa_ctx_destroy(pa_ctx *ctx) {
   return guard([&] {
     if (!ctx) return;
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->ev_a) (void)hipEventDestroy(ctx->ev_a);
+    if (ctx->ev_b) (void)hipEventDestroy(ctx->ev_b);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (auto e : ctx->prof_pool) (void)hipEventDestroy(e);
     if (ctx->host_flag) (void)hipHostFree(ctx->host_flag);
     delete ctx;
@@ -321,6 +325,8 @@ void pa_solve_cfg_default(pa_solve_cfg *cfg) {
   cfg->cheb_tol = 1e-6;
   cfg->weight_cut = 1e-16;
   cfg->inner_rtol = 1e-6;
+  cfg->use_graph = 0;
+  cfg->reserved = 0;
 }
 
 }  // extern "C"
@@ -483,6 +489,75 @@ int pa_step(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, double dt, int me
     pa::Engine e(ctx, ops, cfg_or_default(cfg), ws, ws_bytes);
     e.step(avg, dt, members, U_dev_inout);
     out_stats(stats, e);
+  });
+}
+
+int pa_get_launch_tune(pa_launch_tune *out) {
+  return guard([&] {
+    need(out != nullptr, "out is NULL");
+    pa::LaunchTune t = pa::launch_tuning();
+    out->narrow_rows_per_thread = t.narrow_rows_per_thread;
+    out->wide_max_wg = t.wide_max_wg;
+    out->best_ms = 0.0;
+  });
+}
+
+int pa_set_launch_tune(const pa_launch_tune *t) {
+  return guard([&] {
+    need(t != nullptr, "t is NULL");
+    need(t->narrow_rows_per_thread >= 1 && t->narrow_rows_per_thread <= 64, "rows per thread in [1, 64]");
+    need(t->wide_max_wg >= 8 && t->wide_max_wg <= 2048, "wide_max_wg in [8, 2048]");
+    pa::LaunchTune lt;
+    lt.narrow_rows_per_thread = t->narrow_rows_per_thread;
+    lt.wide_max_wg = t->wide_max_wg;
+    pa::set_launch_tuning(lt);
+  });
+}
+
+int pa_autotune(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int members, const double *U_dev,
+                double *out_dev, void *ws, size_t ws_bytes, const pa_solve_cfg *cfg,
+                pa_launch_tune *out) {
+  return guard([&] {
+    check_call(ctx, ops, ws);
+    need(avg && U_dev && out_dev && out && members >= 1 && U_dev != out_dev, "bad arguments");
+    const pa_solve_cfg c = cfg_or_default(cfg);
+    const pa::LaunchTune keep = pa::launch_tuning();
+    const int rpts[] = {1, 2, 4, 8};
+    const int caps[] = {512, 1024, 2048};
+    double best = 1e300;
+    pa::LaunchTune best_t = keep;
+    auto time_once = [&]() {
+      pa_stats st{};
+      run_with_budget(ctx, c.cg_rtol, true, [&](bool budget) {
+        pa::Engine e(ctx, ops, c, ws, ws_bytes);
+        e.allow_budget(budget, true);
+        e.phase_avg_rhs(avg, members, U_dev, out_dev);
+        st = e.stats;
+      });
+      return st.device_ms;
+    };
+    try {
+      for (int rpt : rpts)
+        for (int cap : caps) {
+          pa::LaunchTune t;
+          t.narrow_rows_per_thread = rpt;
+          t.wide_max_wg = cap;
+          pa::set_launch_tuning(t);
+          time_once();  // warm-up (and graph capture when enabled)
+          double ms = std::min(time_once(), time_once());
+          if (ms < best) {
+            best = ms;
+            best_t = t;
+          }
+        }
+    } catch (...) {
+      pa::set_launch_tuning(keep);
+      throw;
+    }
+    pa::set_launch_tuning(best_t);
+    out->narrow_rows_per_thread = best_t.narrow_rows_per_thread;
+    out->wide_max_wg = best_t.wide_max_wg;
+    out->best_ms = best;
   });
 }
 

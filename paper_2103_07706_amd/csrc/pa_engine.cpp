@@ -32,7 +32,7 @@ static int tiles_of(int Bs) { return Bs <= 64 ? 1 : Bs / 64; }
 
 Engine::Engine(pa_ctx *ctx, const pa_ops *ops, const pa_solve_cfg &cfg, void *ws, size_t ws_bytes)
     : ctx_(ctx), ops_(ops), cfg_(cfg), s_(ctx ? ctx->stream : nullptr), ne_(ops->ne),
-      nc_(ops->nc), n_(ops->ne + ops->nc), ar_(ws, ws_bytes) {
+      nc_(ops->nc), n_(ops->ne + ops->nc), ar_(ws, ws_bytes), ws_base_(ws) {
   if (cfg_.maxit <= 0) throw Error(PA_EINVAL, "maxit must be positive");
   if (!(cfg_.cg_rtol > 0)) throw Error(PA_EINVAL, "cg_rtol must be positive");
   if (!(cfg_.cheb_tol > 0)) throw Error(PA_EINVAL, "cheb_tol must be positive");
@@ -93,7 +93,7 @@ void Engine::begin() {
   if (!ops_->dev) throw Error(PA_EINVAL, "operators are not bound to device memory");
   PA_HIP(hipSetDevice(ctx_->device));
   launch_zero(zero_base_, zero_words_, s_);
-  PA_HIP(hipMemsetAsync(colK0_, 0, sizeof(int) * BsMax_, s_));
+  launch_zero((unsigned *)colK0_, BsMax_, s_);
   PA_HIP(hipEventCreate(&ev0_));
   PA_HIP(hipEventCreate(&ev1_));
   PA_HIP(hipEventRecord(ev0_, s_));
@@ -291,6 +291,7 @@ void Engine::cg(double *x, int Bs, const int *colK, int kneed, int nwg_init) {
   predicted_ = std::max(1, it - 1);
   stats.solves++;
   stats.cg_iters += it;
+  stats.budget = budget;
 }
 
 void Engine::lstep(Blk in, Blk out, const Blk *A, const Blk *B, double scale, const int *colK,
@@ -539,14 +540,18 @@ void Engine::plan_nbar(NbarBufs &nb, const pa_avg *avg, int members) {
   nb.colK_mem = ar_.take<int>(nb.Bm);
 }
 
-void Engine::run_nbar(NbarBufs &nb, Blk X, Blk out) {
-  const double lb = ops_->lambda_bar;
+void Engine::upload_nbar(NbarBufs &nb) {
   upload(nb.cF, nb.hcF.data(), nb.hcF.size() * sizeof(double));
   upload(nb.cB, nb.hcB.data(), nb.hcB.size() * sizeof(double));
   upload(nb.cBx, nb.hcBx.data(), nb.hcBx.size() * sizeof(double));
   upload(nb.colK_E, nb.hcolK_E.data(), nb.hcolK_E.size() * sizeof(int));
   upload(nb.colK_fwd, nb.hcolK_fwd.data(), nb.hcolK_fwd.size() * sizeof(int));
   upload(nb.colK_mem, nb.hcolK_mem.data(), nb.hcolK_mem.size() * sizeof(int));
+}
+
+void Engine::run_nbar(NbarBufs &nb, Blk X, Blk out, bool uploaded) {
+  const double lb = ops_->lambda_bar;
+  if (!uploaded) upload_nbar(nb);
   const int Bm = nb.Bm, kmax = nb.kmax;
   const size_t blkm = (size_t)n_ * Bm;
   auto R = [&](int k) { return Blk{nb.basis + (size_t)k * blkm, Bm}; };
@@ -607,12 +612,81 @@ void Engine::phase_avg_rhs(const pa_avg *avg, int members, const double *U, doub
   Blk X = block(nb.Bm), out = block(nb.Bm);
   if (ar_.sizing()) return;
   begin();
-  TransArgs tr{n_, members, nb.Bm, const_cast<double *>(U), X.p};
-  launch_to_block(tr, s_);
-  run_nbar(nb, X, out);
-  TransArgs tb{n_, members, nb.Bm, Nbar, out.p};
-  launch_from_block(tb, s_);
+  upload_nbar(nb);
+  auto body = [&] {
+    TransArgs tr{n_, members, nb.Bm, const_cast<double *>(U), X.p};
+    launch_to_block(tr, s_);
+    run_nbar(nb, X, out, true);
+    TransArgs tb{n_, members, nb.Bm, Nbar, out.p};
+    launch_from_block(tb, s_);
+  };
+  // Graph replay: with an iteration budget the whole call is a fixed kernel
+  // sequence with no host synchronisation, so it is captured once (on the
+  // context's own capture stream) and replayed while nothing it depends on
+  // changes.
+  int budget = 0;
+  if (budget_ok_) {
+    auto itb = ctx_->cg_budget.find(cfg_.cg_rtol);
+    if (itb != ctx_->cg_budget.end()) budget = itb->second;
+  }
+  if (cfg_.use_graph && budget > 0 && ctx_->prof_kernel == PA_KERNEL_NONE) {
+    GraphKey key;
+    key.ops = ops_;
+    key.avg = avg;
+    key.members = members;
+    key.in = U;
+    key.out = Nbar;
+    key.ws = ws_base_;
+    key.budget = budget;
+    key.lambda_bar = ops_->lambda_bar;
+    key.cfg = cfg_;
+    key.tune = launch_tuning();
+    run_graph(key, body);
+  } else {
+    body();
+  }
   finish();
+}
+
+// Capture 'body' into a graph (or reuse the context's graph for the same
+// key) and launch it, ordered after the work already on the caller's stream.
+void Engine::run_graph(const GraphKey &key, const std::function<void()> &body) {
+  if (!ctx_->cap_stream) PA_HIP(hipStreamCreateWithFlags(&ctx_->cap_stream, hipStreamNonBlocking));
+  if (!ctx_->ev_a) PA_HIP(hipEventCreateWithFlags(&ctx_->ev_a, hipEventDisableTiming));
+  if (!ctx_->ev_b) PA_HIP(hipEventCreateWithFlags(&ctx_->ev_b, hipEventDisableTiming));
+  hipStream_t caller = s_, cs = ctx_->cap_stream;
+  PA_HIP(hipEventRecord(ctx_->ev_a, caller));
+  PA_HIP(hipStreamWaitEvent(cs, ctx_->ev_a, 0));
+  if (!(ctx_->graph_exec && ctx_->graph_key == key)) {
+    if (ctx_->graph_exec) (void)hipGraphExecDestroy(ctx_->graph_exec);
+    ctx_->graph_exec = nullptr;
+    hipGraph_t g = nullptr;
+    s_ = cs;
+    PA_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    try {
+      body();
+    } catch (...) {
+      (void)hipStreamEndCapture(cs, &g);
+      if (g) (void)hipGraphDestroy(g);
+      s_ = caller;
+      throw;
+    }
+    PA_HIP(hipStreamEndCapture(cs, &g));
+    s_ = caller;
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) throw Error(PA_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    ctx_->graph_exec = ex;
+    ctx_->graph_key = key;
+    ctx_->graph_stats = stats;
+  } else {
+    stats = ctx_->graph_stats;
+  }
+  PA_HIP(hipGraphLaunch(ctx_->graph_exec, cs));
+  PA_HIP(hipEventRecord(ctx_->ev_b, cs));
+  PA_HIP(hipStreamWaitEvent(caller, ctx_->ev_b, 0));
+  stats.graph = 1;
 }
 
 // ---------------------------------------------------------------- RK4 step
@@ -644,16 +718,17 @@ void Engine::step(const pa_avg *avg, double dt, int members, double *U) {
   const size_t nb_ = (size_t)n_ * Bm;
   TransArgs tr{n_, members, Bm, U, X.p};
   launch_to_block(tr, s_);
-  run_nbar(nb, X, k1);
+  upload_nbar(nb);
+  run_nbar(nb, X, k1, true);
   axpy(nb_, T.p, 1.0, X.p, 0.5 * dt, k1.p);  // U1
   run_exp(eh, T, S);                          // exp(L dt/2) U1
-  run_nbar(nb, S, k2);
+  run_nbar(nb, S, k2, true);
   run_exp(eh, X, Eh);                         // exp(L dt/2) U
   axpy(nb_, T.p, 1.0, Eh.p, 0.5 * dt, k2.p);  // U2
-  run_nbar(nb, T, k3);
+  run_nbar(nb, T, k3, true);
   axpy(nb_, T.p, 1.0, Eh.p, dt, k3.p);        // U3
   run_exp(eh, T, S);
-  run_nbar(nb, S, k4);
+  run_nbar(nb, S, k4, true);
   axpy(nb_, T.p, 1.0, X.p, dt / 6.0, k1.p);
   run_exp(ef, T, S);                          // exp(L dt)(U + dt/6 k1)
   axpy(nb_, T.p, dt / 3.0, k2.p, dt / 3.0, k3.p);

@@ -2,6 +2,7 @@
 // sequences of kernels for the exponential, the nonlinearity, the averaged
 // right-hand side and the RK4 step.
 #pragma once
+#include <functional>
 #include <vector>
 
 #include "pa_kernels.h"
@@ -112,7 +113,9 @@ class Engine {
     int ksum = 0;
   };
   void plan_nbar(NbarBufs &nb, const pa_avg *avg, int members);
-  void run_nbar(NbarBufs &nb, Blk X, Blk out);
+  void upload_nbar(NbarBufs &nb);
+  void run_nbar(NbarBufs &nb, Blk X, Blk out, bool uploaded);
+  void run_graph(const GraphKey &key, const std::function<void()> &body);
 
   struct ExpBufs {
     int Bs = 0, kmax = 0;
@@ -141,6 +144,7 @@ class Engine {
   size_t zero_words_ = 0;
   int *colK0_ = nullptr;  // all zeros
   int predicted_ = 8;
+  void *ws_base_ = nullptr;
   bool budget_ok_ = false, learn_budget_ = false;
   hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
 };

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <cstring>
 #include <map>
 #include <cstdint>
 #include <stdexcept>
@@ -72,6 +73,29 @@ struct DevOps {
   const double *cgeo = nullptr;       // nc*kCellGeo
 };
 
+// Launch shape of the row-parallel kernels (set by the autotuner).
+struct LaunchTune {
+  int narrow_rows_per_thread = 4;  // batches of <= 4 columns
+  int wide_max_wg = 2048;          // workgroups per column tile, wider batches
+  bool operator==(const LaunchTune &o) const {
+    return narrow_rows_per_thread == o.narrow_rows_per_thread && wide_max_wg == o.wide_max_wg;
+  }
+};
+
+// What a captured averaged-RHS graph depends on.
+struct GraphKey {
+  const void *ops = nullptr, *avg = nullptr, *in = nullptr, *out = nullptr, *ws = nullptr;
+  int members = 0, budget = 0;
+  double lambda_bar = 0;
+  pa_solve_cfg cfg{};
+  LaunchTune tune{};
+  bool operator==(const GraphKey &o) const {
+    return ops == o.ops && avg == o.avg && in == o.in && out == o.out && ws == o.ws &&
+           members == o.members && budget == o.budget && lambda_bar == o.lambda_bar &&
+           tune == o.tune && std::memcmp(&cfg, &o.cfg, sizeof(cfg)) == 0;
+  }
+};
+
 }  // namespace pa
 
 // ----------------------------------------------------------- opaque handles
@@ -81,6 +105,12 @@ struct pa_ctx {
   void *host_flag = nullptr;  // pinned host word for convergence polling
   // learned CG iterations per solve, per tolerance (absent: poll)
   std::map<double, int> cg_budget;
+  // graph replay of the averaged right-hand side
+  hipStream_t cap_stream = nullptr;
+  hipEvent_t ev_a = nullptr, ev_b = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  pa::GraphKey graph_key{};
+  pa_stats graph_stats{};
   // measurement hook (pa_ctx_profile)
   int prof_kernel = 0;
   std::vector<hipEvent_t> prof_pool;

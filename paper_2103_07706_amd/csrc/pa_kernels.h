@@ -142,6 +142,8 @@ struct WdotArgs {
 };
 
 int launch_max_wg();
+LaunchTune launch_tuning();
+void set_launch_tuning(const LaunchTune &t);
 int launch_rows_grid(int rows, int Bs);
 void launch_finalize(const FinArgs &a, hipStream_t s);
 void launch_stiff(const StiffArgs &a, hipStream_t s);

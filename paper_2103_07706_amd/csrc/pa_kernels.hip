@@ -694,17 +694,20 @@ namespace {
 // lane_map).  Narrow batches (Bs <= 4) are latency-bound: about four rows per
 // thread keeps the launch short and the partial sums few.  Wider ones fill
 // the 256 CUs several times over, split over the column tiles.
+LaunchTune g_tune;  // process-wide launch shape (see set_launch_tuning)
+
 int grid_rows(int rows, int Bs) {
   const int ct = Bs < 64 ? Bs : 64;
   const int rows_per_pass = (kWG / 64) * (64 / ct);
   const int ctiles = (Bs + 63) / 64;
   int want, cap;
   if (Bs <= 4) {
-    want = (rows + 4 * rows_per_pass - 1) / (4 * rows_per_pass);
-    cap = 256;
+    const int rpt = g_tune.narrow_rows_per_thread;
+    want = (rows + rpt * rows_per_pass - 1) / (rpt * rows_per_pass);
+    cap = 2048;
   } else {
     want = (rows + rows_per_pass - 1) / rows_per_pass;
-    cap = ctiles >= 8 ? 256 : 2048 / ctiles;
+    cap = ctiles >= 8 ? 256 : g_tune.wide_max_wg / ctiles;
   }
   int g = want < cap ? want : cap;
   g = (g + 7) / 8 * 8;
@@ -718,6 +721,13 @@ dim3 rows_grid(int rows, int Bs) { return dim3(grid_rows(rows, Bs), (Bs + 63) / 
 }  // namespace
 
 int launch_max_wg() { return 2048; }
+LaunchTune launch_tuning() { return g_tune; }
+void set_launch_tuning(const LaunchTune &t) {
+  g_tune = t;
+  if (g_tune.narrow_rows_per_thread < 1) g_tune.narrow_rows_per_thread = 1;
+  if (g_tune.wide_max_wg < 8) g_tune.wide_max_wg = 8;
+  if (g_tune.wide_max_wg > 2048) g_tune.wide_max_wg = 2048;
+}
 int launch_rows_grid(int rows, int Bs) { return grid_rows(rows, Bs); }
 
 void launch_stiff(const StiffArgs &a, hipStream_t s) {

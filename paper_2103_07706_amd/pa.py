@@ -41,7 +41,8 @@ class SolveCfg(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("backward", ctypes.c_int32),
                 ("maxit", ctypes.c_int32), ("growth_guard", ctypes.c_int32),
                 ("cg_rtol", ctypes.c_double), ("cheb_tol", ctypes.c_double),
-                ("weight_cut", ctypes.c_double), ("inner_rtol", ctypes.c_double)]
+                ("weight_cut", ctypes.c_double), ("inner_rtol", ctypes.c_double),
+                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 PA_KERNEL_NONE, PA_KERNEL_CG_ITER = 0, 1
@@ -52,12 +53,18 @@ class KernelProfile(ctypes.Structure):
                 ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
+class LaunchTune(ctypes.Structure):
+    _fields_ = [("narrow_rows_per_thread", ctypes.c_int32), ("wide_max_wg", ctypes.c_int32),
+                ("best_ms", ctypes.c_double)]
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("solves", ctypes.c_int32), ("cg_iters", ctypes.c_int32),
                 ("cg_iters_max", ctypes.c_int32), ("kmax", ctypes.c_int32),
                 ("ksum", ctypes.c_int32), ("terms", ctypes.c_int32),
                 ("refinements", ctypes.c_int32), ("guard_trips", ctypes.c_int32),
-                ("resid_max", ctypes.c_double), ("device_ms", ctypes.c_double)]
+                ("resid_max", ctypes.c_double), ("device_ms", ctypes.c_double),
+                ("graph", ctypes.c_int32), ("budget", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -105,6 +112,10 @@ EXPORTS = {
     "pa_step": (ctypes.c_int, [_V, _V, _V, ctypes.c_double, ctypes.c_int, _V, _V, _SZ,
                                ctypes.POINTER(SolveCfg), ctypes.POINTER(Stats)]),
     "pa_diagnostics": (ctypes.c_int, [_V, _V, ctypes.c_int, _V, _V, _SZ, _D]),
+    "pa_get_launch_tune": (ctypes.c_int, [ctypes.POINTER(LaunchTune)]),
+    "pa_set_launch_tune": (ctypes.c_int, [ctypes.POINTER(LaunchTune)]),
+    "pa_autotune": (ctypes.c_int, [_V, _V, _V, ctypes.c_int, _V, _V, _V, _SZ,
+                                   ctypes.POINTER(SolveCfg), ctypes.POINTER(LaunchTune)]),
 }
 
 
@@ -145,11 +156,12 @@ def _dp(a):
 
 
 def solve_cfg(precision=PA_FP64, backward=PA_BACKWARD_PER_TERM, maxit=None, cg_rtol=None,
-              cheb_tol=None, weight_cut=None, inner_rtol=None) -> SolveCfg:
+              cheb_tol=None, weight_cut=None, inner_rtol=None, use_graph=False) -> SolveCfg:
     c = SolveCfg()
     lib().pa_solve_cfg_default(ctypes.byref(c))
     c.precision = precision
     c.backward = backward
+    c.use_graph = 1 if use_graph else 0
     if maxit is not None:
         c.maxit = maxit
     if cg_rtol is not None:
@@ -342,6 +354,35 @@ class Ops:
         _check(lib().pa_step(self.ctx._h, self._h, avg._h, dt, members, _ptr(U), ws, nb,
                              ctypes.byref(cfg), ctypes.byref(st)))
         return U, st.as_dict()
+
+    def autotune(self, avg: Avg, U, cfg=None, cache=None):
+        """Pick the launch shape for this problem (pa_autotune).  With a
+        cache file (JSON), a shape stored for the same problem key is applied
+        instead of searching, and a new search result is stored."""
+        import json
+        cfg = cfg or solve_cfg()
+        members = U.shape[0]
+        key = (f"level{self.mesh.level}_members{members}_M{avg.M}_rtol{cfg.cg_rtol:g}_"
+               f"tol{cfg.cheb_tol:g}_bw{cfg.backward}_prec{cfg.precision}_graph{cfg.use_graph}")
+        table = {}
+        if cache and os.path.exists(cache):
+            table = json.load(open(cache))
+            if key in table:
+                t = LaunchTune(table[key]["narrow_rows_per_thread"], table[key]["wide_max_wg"], 0.0)
+                _check(lib().pa_set_launch_tune(ctypes.byref(t)))
+                return dict(table[key], cached=True)
+        out = U.new_empty(U.shape)
+        ws, nb = self.workspace(avg, members, cfg)
+        t = LaunchTune()
+        _check(lib().pa_autotune(self.ctx._h, self._h, avg._h, members, _ptr(U), _ptr(out), ws,
+                                 nb, ctypes.byref(cfg), ctypes.byref(t)))
+        res = {"narrow_rows_per_thread": t.narrow_rows_per_thread, "wide_max_wg": t.wide_max_wg,
+               "best_ms": t.best_ms}
+        if cache:
+            table[key] = res
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1)
+        return dict(res, cached=False)
 
     def diagnostics(self, U):
         B = U.shape[0]

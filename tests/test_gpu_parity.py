@@ -149,3 +149,47 @@ def test_gpu_budget_mode_and_repeat():
     lo.ctx.set_cg_budget(1e-11, 3)         # far too small: repeat with polling
     c, _ = lo.phase_avg_rhs(avg, U, cfg)
     assert np.array_equal(a.cpu().numpy(), c.cpu().numpy())
+
+
+def test_gpu_graph_replay_matches_eager():
+    """The averaged RHS captured as a HIP graph: every replay, with eager
+    library work and synchronisations in between, equals the eager result;
+    a different output buffer forces a new capture."""
+    import torch
+    from paper_2103_07706_amd import pa
+    om, oo, lm, lo, mm, lb = pair(3)
+    U = to_dev(mm.state(bumps(om, [1])))
+    avg = pa.Avg(8, 3600.0)
+    ref, _ = lo.phase_avg_rhs(avg, U, pa.solve_cfg(cg_rtol=1e-12))
+    ref = ref.cpu().numpy()
+    gcfg = pa.solve_cfg(cg_rtol=1e-12, use_graph=True)
+    out = torch.empty_like(U)
+    graphs = 0
+    for i in range(4):
+        out.fill_(float("nan"))
+        _, st = lo.phase_avg_rhs(avg, U, gcfg, out=out)
+        graphs += st["graph"]
+        assert np.array_equal(out.cpu().numpy(), ref), i
+        lo.swe_nonlinear(U)
+        torch.cuda.synchronize()
+    assert graphs == 4
+    out2 = torch.empty_like(U)
+    _, st = lo.phase_avg_rhs(avg, U, gcfg, out=out2)
+    assert st["graph"] == 1 and np.array_equal(out2.cpu().numpy(), ref)
+
+
+def test_gpu_autotune_keeps_parity(tmp_path):
+    from paper_2103_07706_amd import pa
+    om, oo, lm, lo, mm, lb = pair(3)
+    U = bumps(om, [0])
+    avg = pa.Avg(8, 3600.0)
+    cfg = pa.solve_cfg(weight_cut=0.0, use_graph=True, **PARITY)
+    Ud = to_dev(mm.state(U))
+    cache = str(tmp_path / "tune.json")
+    res = lo.autotune(avg, Ud, cfg, cache=cache)
+    assert res["narrow_rows_per_thread"] in (1, 2, 4, 8) and not res["cached"]
+    assert lo.autotune(avg, Ud, cfg, cache=cache)["cached"]
+    out, _ = lo.phase_avg_rhs(avg, Ud, cfg)
+    got = mm.back(out.cpu().numpy())[0]
+    ref = oo.phase_avg_rhs(lb, avg.s, avg.w, U[0], tol=1e-13, rtol=1e-14)
+    assert rel_w(oo, got, ref) < TOL
