@@ -32,6 +32,7 @@ def parse():
     ap.add_argument("--workload", default="l6_m64")
     ap.add_argument("--backward", default="clenshaw", choices=["per_term", "clenshaw"])
     ap.add_argument("--graph", type=int, default=1)
+    ap.add_argument("--solver", default="chebyshev", choices=["cg", "chebyshev"])
     ap.add_argument("--autotune", type=int, default=1)
     ap.add_argument("--cpu-baseline", dest="cpu", type=int, default=1)
     ap.add_argument("--cpu-terms", type=int, default=4)
@@ -99,7 +100,9 @@ def main():
         dtype=torch.float64, device="cuda:0")
     avg = pa.Avg(wl.M, wl.T)
     bw = pa.PA_BACKWARD_PER_TERM if args.backward == "per_term" else pa.PA_BACKWARD_CLENSHAW
-    cfg = pa.solve_cfg(backward=bw, cheb_tol=1e-6, cg_rtol=1e-10, use_graph=bool(args.graph))
+    solver = pa.PA_SOLVER_CG if args.solver == "cg" else pa.PA_SOLVER_CHEBYSHEV
+    cfg = pa.solve_cfg(backward=bw, cheb_tol=1e-6, cg_rtol=1e-10, use_graph=bool(args.graph),
+                       solver=solver)
     out = torch.empty_like(U)
     tune = None
     if args.autotune:
@@ -146,6 +149,7 @@ def main():
                    "edges": mesh.ne, "M": wl.M, "T_s": wl.T, "members": wl.members,
                    "cheb_tol": 1e-6, "cg_rtol": 1e-10, "backward": args.backward,
                    "precision": "fp64", "preconditioner": "jacobi", "lambda_bar": lam,
+                   "mass_solver": args.solver,
                    "kmax": stats["kmax"], "ksum": stats["ksum"], "terms": stats["terms"],
                    "cg_iters_max": stats["cg_iters_max"], "solves": stats["solves"],
                    "graph": bool(stats["graph"]), "cg_budget": stats["budget"],

@@ -133,8 +133,15 @@ typedef struct {
   int32_t use_graph;   /* 1: capture pa_phase_avg_rhs into a HIP graph once an
                           iteration budget is known and replay it while its
                           inputs (pointers, sizes, settings) stay the same */
-  int32_t reserved;
+  int32_t solver;      /* mass solves: PA_SOLVER_CG (Jacobi-preconditioned
+                          CG, as in the paper's method) or PA_SOLVER_CHEBYSHEV
+                          (Jacobi-preconditioned Chebyshev semi-iteration over
+                          Lanczos bounds of the spectrum of D^-1 M: no inner
+                          products, step count fixed by the bounds, final FP64
+                          residual checked against cg_rtol; a failed check
+                          repeats the call with CG) */
 } pa_solve_cfg;
+enum { PA_SOLVER_CG = 0, PA_SOLVER_CHEBYSHEV = 1 };
 void pa_solve_cfg_default(pa_solve_cfg *cfg);
 
 /* Statistics of the last call (valid when the call returns). */

@@ -326,7 +326,7 @@ void pa_solve_cfg_default(pa_solve_cfg *cfg) {
   cfg->weight_cut = 1e-16;
   cfg->inner_rtol = 1e-6;
   cfg->use_graph = 0;
-  cfg->reserved = 0;
+  cfg->solver = PA_SOLVER_CG;
 }
 
 }  // extern "C"
@@ -411,6 +411,20 @@ void run_with_budget(pa_ctx *ctx, double rtol, bool allowed, F &&f) {
   }
   f(false);
 }
+
+// A Chebyshev mass solve whose final residual missed the tolerance makes
+// the whole call run again with CG (possible only when outputs do not alias
+// inputs; otherwise the failure is reported).
+template <class F>
+void run_with_fallback(pa_solve_cfg cfg, bool rerun_ok, F &&f) {
+  try {
+    f(cfg);
+  } catch (const pa::SolverCheckFailed &) {
+    if (!rerun_ok) throw;
+    cfg.solver = PA_SOLVER_CG;
+    f(cfg);
+  }
+}
 }  // namespace
 
 extern "C" {
@@ -436,13 +450,15 @@ int pa_expL_apply(pa_ctx *ctx, const pa_ops *ops, int B, const double *t_host,
   return guard([&] {
     check_call(ctx, ops, ws);
     need(t_host && U_in_dev && U_out_dev && B >= 1, "bad arguments");
-    const pa_solve_cfg c = cfg_or_default(cfg);
+    const pa_solve_cfg c0 = cfg_or_default(cfg);
     const bool may = U_in_dev != U_out_dev;
-    run_with_budget(ctx, c.cg_rtol, may, [&](bool budget) {
-      pa::Engine e(ctx, ops, cfg_or_default(cfg), ws, ws_bytes);
-      e.allow_budget(budget, may);
-      e.expL_apply(B, t_host, U_in_dev, U_out_dev);
-      out_stats(stats, e);
+    run_with_fallback(c0, may, [&](const pa_solve_cfg &c) {
+      run_with_budget(ctx, c.cg_rtol, may, [&](bool budget) {
+        pa::Engine e(ctx, ops, c, ws, ws_bytes);
+        e.allow_budget(budget, may);
+        e.expL_apply(B, t_host, U_in_dev, U_out_dev);
+        out_stats(stats, e);
+      });
     });
   });
 }
@@ -452,13 +468,15 @@ int pa_swe_nonlinear(pa_ctx *ctx, const pa_ops *ops, int B, const double *U_dev,
   return guard([&] {
     check_call(ctx, ops, ws);
     need(U_dev && NU_dev && B >= 1, "bad arguments");
-    const pa_solve_cfg c = cfg_or_default(cfg);
+    const pa_solve_cfg c0 = cfg_or_default(cfg);
     const bool may = U_dev != NU_dev;
-    run_with_budget(ctx, c.cg_rtol, may, [&](bool budget) {
-      pa::Engine e(ctx, ops, cfg_or_default(cfg), ws, ws_bytes);
-      e.allow_budget(budget, may);
-      e.swe_nonlinear(B, U_dev, NU_dev);
-      out_stats(stats, e);
+    run_with_fallback(c0, may, [&](const pa_solve_cfg &c) {
+      run_with_budget(ctx, c.cg_rtol, may, [&](bool budget) {
+        pa::Engine e(ctx, ops, c, ws, ws_bytes);
+        e.allow_budget(budget, may);
+        e.swe_nonlinear(B, U_dev, NU_dev);
+        out_stats(stats, e);
+      });
     });
   });
 }
@@ -469,13 +487,15 @@ int pa_phase_avg_rhs(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int memb
   return guard([&] {
     check_call(ctx, ops, ws);
     need(avg && U_dev && Nbar_dev && members >= 1, "bad arguments");
-    const pa_solve_cfg c = cfg_or_default(cfg);
+    const pa_solve_cfg c0 = cfg_or_default(cfg);
     const bool may = U_dev != Nbar_dev;
-    run_with_budget(ctx, c.cg_rtol, may, [&](bool budget) {
-      pa::Engine e(ctx, ops, cfg_or_default(cfg), ws, ws_bytes);
-      e.allow_budget(budget, may);
-      e.phase_avg_rhs(avg, members, U_dev, Nbar_dev);
-      out_stats(stats, e);
+    run_with_fallback(c0, may, [&](const pa_solve_cfg &c) {
+      run_with_budget(ctx, c.cg_rtol, may, [&](bool budget) {
+        pa::Engine e(ctx, ops, c, ws, ws_bytes);
+        e.allow_budget(budget, may);
+        e.phase_avg_rhs(avg, members, U_dev, Nbar_dev);
+        out_stats(stats, e);
+      });
     });
   });
 }
@@ -486,7 +506,9 @@ int pa_step(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, double dt, int me
   return guard([&] {
     check_call(ctx, ops, ws);
     need(avg && U_dev_inout && members >= 1 && dt > 0, "bad arguments");
-    pa::Engine e(ctx, ops, cfg_or_default(cfg), ws, ws_bytes);
+    pa_solve_cfg c = cfg_or_default(cfg);
+    c.solver = PA_SOLVER_CG;  // in place: no repeat possible, keep CG
+    pa::Engine e(ctx, ops, c, ws, ws_bytes);
     e.step(avg, dt, members, U_dev_inout);
     out_stats(stats, e);
   });
@@ -528,11 +550,13 @@ int pa_autotune(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int members, 
     pa::LaunchTune best_t = keep;
     auto time_once = [&]() {
       pa_stats st{};
-      run_with_budget(ctx, c.cg_rtol, true, [&](bool budget) {
-        pa::Engine e(ctx, ops, c, ws, ws_bytes);
-        e.allow_budget(budget, true);
-        e.phase_avg_rhs(avg, members, U_dev, out_dev);
-        st = e.stats;
+      run_with_fallback(c, true, [&](const pa_solve_cfg &cc) {
+        run_with_budget(ctx, cc.cg_rtol, true, [&](bool budget) {
+          pa::Engine e(ctx, ops, cc, ws, ws_bytes);
+          e.allow_budget(budget, true);
+          e.phase_avg_rhs(avg, members, U_dev, out_dev);
+          st = e.stats;
+        });
       });
       return st.device_ms;
     };

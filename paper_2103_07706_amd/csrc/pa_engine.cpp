@@ -37,6 +37,71 @@ Engine::Engine(pa_ctx *ctx, const pa_ops *ops, const pa_solve_cfg &cfg, void *ws
   if (!(cfg_.cg_rtol > 0)) throw Error(PA_EINVAL, "cg_rtol must be positive");
   if (!(cfg_.cheb_tol > 0)) throw Error(PA_EINVAL, "cheb_tol must be positive");
   if (cfg_.precision != PA_FP64) throw Error(PA_ENOTSUP, "only PA_FP64 is implemented");
+  if (cfg_.solver != PA_SOLVER_CG && cfg_.solver != PA_SOLVER_CHEBYSHEV)
+    throw Error(PA_EINVAL, "unknown solver");
+  if (cheb()) plan_cheb();
+}
+
+// Chebyshev semi-iteration on D^-1 M over [a, b] = Lanczos bounds widened
+// by 5% below and 2% above; the number of steps makes the Chebyshev error
+// factor 1/T_k(theta/delta) reach cg_rtol, plus two.
+void Engine::plan_cheb() {
+  const double a = 0.95 * ops_->mass_eig_min, b = 1.02 * ops_->mass_eig_max;
+  if (!(a > 0) || !(b > a)) throw Error(PA_EINVAL, "no spectral bounds for the mass matrix");
+  cheb_theta_ = 0.5 * (a + b);
+  cheb_delta_ = 0.5 * (b - a);
+  const double sigma = cheb_theta_ / cheb_delta_;
+  int k = (int)std::ceil(std::acosh(2.0 / cfg_.cg_rtol) / std::acosh(sigma)) + 2;
+  k = std::min(k, cfg_.maxit);
+  cheb_c1_.resize(k);
+  cheb_c2_.resize(k);
+  double rho = 1.0 / sigma;
+  for (int i = 0; i < k; i++) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    cheb_c1_[i] = rn * rho;
+    cheb_c2_[i] = 2.0 * rn / cheb_delta_;
+    rho = rn;
+  }
+}
+
+// Reduction-free mass solve: the set-up kernel wrote r_0 (r), x_0 (x),
+// d_0 = D^-1 r_0 / theta (p) and partials of |r_0|^2 (partA).
+void Engine::cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_init) {
+  ChebArgs a{};
+  a.ops = ops_->d;
+  a.Bs = Bs;
+  a.x = x;
+  a.r = r_;
+  a.colK = colK;
+  a.kneed = kneed;
+  a.part = rb_.partB;
+  a.max_wg = rb_.max_wg;
+  double *d[2] = {p_, s0_};
+  const int k = (int)cheb_c1_.size();
+  for (int i = 0; i < k; i++) {
+    a.d_in = d[i & 1];
+    a.d_out = d[(i + 1) & 1];
+    a.c1 = cheb_c1_[i];
+    a.c2 = cheb_c2_[i];
+    a.last = i + 1 == k ? 1 : 0;
+    launch_cheb_iter(a, s_);
+  }
+  CheckArgs ca{};
+  ca.Bs = Bs;
+  ca.nwg_init = nwg_init;
+  ca.nwg_last = launch_rows_grid(ne_, Bs);
+  ca.max_wg = rb_.max_wg;
+  ca.part_init = rb_.partA;
+  ca.part_last = rb_.partB;
+  ca.colK = colK;
+  ca.kneed = kneed;
+  ca.rtol2 = cfg_.cg_rtol * cfg_.cg_rtol;
+  ca.fail = st_.cheb_fail;
+  ca.resid = st_.resid;
+  launch_cheb_check(ca, s_);
+  stats.solves++;
+  stats.cg_iters += k;
+  stats.cg_iters_max = std::max(stats.cg_iters_max, k);
 }
 
 void Engine::plan_common(int BsMax) {
@@ -75,6 +140,7 @@ void Engine::plan_common(int BsMax) {
     st_.iter_max = (int *)(z + 3);
     st_.prof = z + 4;
     st_.budget_fail = (int *)(z + 6);
+    st_.cheb_fail = (int *)(z + 7);
   }
 }
 
@@ -102,8 +168,8 @@ void Engine::begin() {
 
 void Engine::finish() {
   PA_HIP(hipEventRecord(ev1_, s_));
-  int h[5] = {0, 0, 0, 0, 0};
-  PA_HIP(hipMemcpyAsync(h, st_.fail, 5 * sizeof(int), hipMemcpyDeviceToHost, s_));
+  int h[6] = {0, 0, 0, 0, 0, 0};
+  PA_HIP(hipMemcpyAsync(h, st_.fail, 6 * sizeof(int), hipMemcpyDeviceToHost, s_));
   PA_HIP(hipStreamSynchronize(s_));
   if (ctx_->prof_kernel != PA_KERNEL_NONE) {
     for (size_t i = 0; i + 1 < prof_ev_.size(); i += 2) {
@@ -133,6 +199,7 @@ void Engine::finish() {
   if (h[0] > 0)
     throw Error(PA_ENOCONV, std::to_string(h[0]) + " mass-solve column(s) did not converge within maxit");
   if (h[4] > 0) throw BudgetExceeded();
+  if (h[5] > 0) throw SolverCheckFailed();
   // next calls on this context run without polling, with this budget
   if (learn_budget_) ctx_->cg_budget[cfg_.cg_rtol] = std::min(cfg_.maxit, h[1] + 2);
 }
@@ -326,8 +393,18 @@ void Engine::lstep(Blk in, Blk out, const Blk *A, const Blk *B, double scale, co
   }
   a.st = st_;
   a.rb = rb_;
+  a.max_wg = rb_.max_wg;
+  if (cheb()) {
+    a.d0 = p_;
+    a.theta_inv = 1.0 / cheb_theta_;
+    a.part_rr = rb_.partA;
+  }
   launch_stiff(a, s_);
-  cg(out.p, in.Bs, colK, kneed, launch_rows_grid(std::max(ne_, nc_), in.Bs));
+  const int nwg_init = launch_rows_grid(std::max(ne_, nc_), in.Bs);
+  if (cheb())
+    cheb_solve(out.p, in.Bs, colK, kneed, nwg_init);
+  else
+    cg(out.p, in.Bs, colK, kneed, nwg_init);
 }
 
 // acc = sum_k coef_k (.) R_k(X) over the real Chebyshev recurrence, with the
@@ -386,8 +463,17 @@ void Engine::nonlinear_block(Blk E, Blk Y, const int *colK) {
   gth.kneed = 0;
   gth.st = st_;
   gth.rb = rb_;
+  gth.max_wg = rb_.max_wg;
+  if (cheb()) {
+    gth.d0 = p_;
+    gth.theta_inv = 1.0 / cheb_theta_;
+    gth.part_rr = rb_.partA;
+  }
   launch_nl_gather(gth, s_);
-  cg(Y.p, E.Bs, colK, 0, launch_rows_grid(ne_, E.Bs));
+  if (cheb())
+    cheb_solve(Y.p, E.Bs, colK, 0, launch_rows_grid(ne_, E.Bs));
+  else
+    cg(Y.p, E.Bs, colK, 0, launch_rows_grid(ne_, E.Bs));
 }
 
 // ------------------------------------------------------------- exponential
@@ -629,7 +715,7 @@ void Engine::phase_avg_rhs(const pa_avg *avg, int members, const double *U, doub
     auto itb = ctx_->cg_budget.find(cfg_.cg_rtol);
     if (itb != ctx_->cg_budget.end()) budget = itb->second;
   }
-  if (cfg_.use_graph && budget > 0 && ctx_->prof_kernel == PA_KERNEL_NONE) {
+  if (cfg_.use_graph && (budget > 0 || cheb()) && ctx_->prof_kernel == PA_KERNEL_NONE) {
     GraphKey key;
     key.ops = ops_;
     key.avg = avg;

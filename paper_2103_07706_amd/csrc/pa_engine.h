@@ -24,6 +24,12 @@ struct BudgetExceeded : Error {
   BudgetExceeded() : Error(PA_ENOCONV, "iteration budget exceeded") {}
 };
 
+// Raised when a Chebyshev mass solve missed its residual tolerance; the
+// call is then repeated with CG.
+struct SolverCheckFailed : Error {
+  SolverCheckFailed() : Error(PA_ENOCONV, "Chebyshev mass solve missed the residual tolerance") {}
+};
+
 class Arena {
  public:
   Arena(void *base, size_t cap) : base_((char *)base), cap_(cap) {}
@@ -92,6 +98,12 @@ class Engine {
   void lstep(Blk in, Blk out, const Blk *A, const Blk *B, double scale, const int *colK,
              int kneed, const AccSpec *acc);
   void cg(double *x, int Bs, const int *colK, int kneed, int nwg_init);
+  void cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_init);
+  bool cheb() const { return cfg_.solver == PA_SOLVER_CHEBYSHEV; }
+  // Chebyshev plan: step coefficients from the spectral bounds
+  double cheb_theta_ = 0, cheb_delta_ = 0;
+  std::vector<double> cheb_c1_, cheb_c2_;
+  void plan_cheb();
   void poly_apply(Blk X, Blk W, const double *coef, const int *colK, int kmax, int G, Blk acc);
   void nonlinear_block(Blk E, Blk Y, const int *colK);
   void axpy(size_t n, double *out, double a0, const double *x0, double a1 = 0,

@@ -132,6 +132,8 @@ Mesh build_icosahedral(int level, double radius) {
   return m;
 }
 
+void mass_spectrum(pa_ops *o, int steps, double *lmin, double *lmax);
+
 namespace {
 
 double coriolis(double omega, V3 x) { return 2.0 * omega * x.z / norm(x); }
@@ -266,6 +268,85 @@ void assemble_ops(pa_ops *o, const Mesh &m, const pa_phys &ph) {
     o->dinv32[e] = (float)o->dinv[e];
   }
   for (int i = 0; i < 5 * ne; i++) o->mass32[i] = (float)o->mass[i];
+  mass_spectrum(o, 120, &o->mass_eig_min, &o->mass_eig_max);
+}
+
+namespace {
+// Number of eigenvalues of the symmetric tridiagonal (alpha, beta) below x
+// (Sturm sequence count).
+int sturm_count(const std::vector<double> &al, const std::vector<double> &be, double x) {
+  int cnt = 0;
+  double d = 1.0;
+  for (size_t i = 0; i < al.size(); i++) {
+    const double b2 = i ? be[i - 1] * be[i - 1] : 0.0;
+    d = al[i] - x - (i ? b2 / d : 0.0);
+    if (d == 0.0) d = -1e-300;
+    if (d < 0) cnt++;
+  }
+  return cnt;
+}
+}  // namespace
+
+// Extreme eigenvalues of D^-1 M (same spectrum as D^-1/2 M D^-1/2) by Lanczos
+// on the symmetric form from a fixed start vector, eigenvalues of the
+// tridiagonal matrix by bisection.  The Ritz values lie inside the spectrum
+// and approach its ends quickly; callers widen them by a margin.
+void mass_spectrum(pa_ops *o, int steps, double *lmin, double *lmax) {
+  const int n = o->ne;
+  std::vector<double> sq(n), v(n), vp(n, 0.0), w(n);
+  for (int i = 0; i < n; i++) sq[i] = std::sqrt(o->dinv[i]);
+  double nv = 0.0;
+  for (int i = 0; i < n; i++) {
+    v[i] = 1.0 + 0.5 * std::sin(0.7 * i + 0.3);
+    nv += v[i] * v[i];
+  }
+  nv = std::sqrt(nv);
+  for (auto &x : v) x /= nv;
+  std::vector<double> al, be;
+  double bprev = 0.0;
+  for (int k = 0; k < steps; k++) {
+    for (int i = 0; i < n; i++) {  // w = S v, S = D^-1/2 M D^-1/2
+      double s = 0.0;
+      for (int j = 0; j < 5; j++) {
+        const int c = o->ell_col[5 * i + j];
+        s += o->mass[5 * i + j] * sq[c] * v[c];
+      }
+      w[i] = sq[i] * s;
+    }
+    double a = 0.0;
+    for (int i = 0; i < n; i++) a += w[i] * v[i];
+    double b = 0.0;
+    for (int i = 0; i < n; i++) {
+      w[i] -= a * v[i] + bprev * vp[i];
+      b += w[i] * w[i];
+    }
+    b = std::sqrt(b);
+    al.push_back(a);
+    if (b < 1e-14 || k + 1 == steps) break;
+    be.push_back(b);
+    for (int i = 0; i < n; i++) {
+      vp[i] = v[i];
+      v[i] = w[i] / b;
+    }
+    bprev = b;
+  }
+  be.resize(al.size() > 0 ? al.size() - 1 : 0);
+  double lo = 1e300, hi = -1e300;  // Gershgorin interval of T
+  for (size_t i = 0; i < al.size(); i++) {
+    const double r = (i ? std::fabs(be[i - 1]) : 0.0) + (i + 1 < al.size() ? std::fabs(be[i]) : 0.0);
+    lo = std::min(lo, al[i] - r);
+    hi = std::max(hi, al[i] + r);
+  }
+  auto kth = [&](int k) {  // k-th smallest eigenvalue of T (0-based)
+    double a = lo, b = hi;
+    for (int it = 0; it < 200; it++) {
+      const double m = 0.5 * (a + b);
+      if (sturm_count(al, be, m) > k) b = m; else a = m;
+    }
+    return 0.5 * (a + b);
+  };
+  *lmin = kth(0);
+  *lmax = kth((int)al.size() - 1);
 }
 
 // Chebyshev weights of exp(i theta x): (2 - delta_k0) J_k(theta), k = 0..kcap,

@@ -126,6 +126,7 @@ struct pa_ops {
   const pa_mesh *mesh = nullptr;
   int ne = 0, nc = 0;
   double g = 0, H = 0, omega = 0, lambda_bar = 0;
+  double mass_eig_min = 0, mass_eig_max = 0;  // Ritz bounds of D^-1 M
   // host copies, in upload order
   std::vector<int32_t> ell_col, ecell, cidx, side_edges, cedge, csgn, cnbr;
   std::vector<double> mass, cor, dinv, area, inv_area, bottom, cgeo, tau;

@@ -24,6 +24,7 @@ struct SolveState {
   int *act2, *it2;        // [2][4]
   int *cnt;               // [2]: active columns after the last finalize, by parity
   int *budget_fail;       // 1: columns still active when an iteration budget ran out
+  int *cheb_fail;         // 1: Chebyshev solves that missed the residual tolerance
   int *fail;              // 1 (accumulates over solves)
   int *iter_max;          // 1 (accumulates over solves)
   unsigned *prof;         // [2]: active columns summed over launches, work launches
@@ -39,6 +40,11 @@ struct StiffArgs {
   const int *colK;
   int kneed;
   double *r;
+  // Chebyshev solver: also d_0 = theta_inv D^-1 r_0 and partials of r_0.r_0
+  double *d0;
+  double theta_inv;
+  double *part_rr;
+  int max_wg;
   // optional grouped accumulation acc += coef * in
   double *acc_u, *acc_eta;
   const double *coef;
@@ -65,6 +71,31 @@ struct CgArgs {
   int kneed;
   SolveState st;
   RedBuf rb;
+};
+
+// Chebyshev semi-iteration step on the mass matrix (see k_cheb_iter).
+struct ChebArgs {
+  DevOps ops;
+  int Bs;
+  double *x, *r;
+  const double *d_in;
+  double *d_out;
+  double c1, c2;
+  const int *colK;
+  int kneed, last;
+  double *part;  // last step: partials of r.r
+  int max_wg;
+};
+
+// Residual check after a Chebyshev solve.
+struct CheckArgs {
+  int Bs, nwg_init, nwg_last, max_wg;
+  const double *part_init, *part_last;
+  const int *colK;
+  int kneed;
+  double rtol2;
+  int *fail;
+  double *resid;
 };
 
 enum { FIN_INIT = 0, FIN_STEP = 1, FIN_OUT = 2 };
@@ -107,6 +138,10 @@ struct GatherArgs {
   int Bs;
   const double *C;
   double *r, *x;
+  double *d0;
+  double theta_inv;
+  double *part_rr;
+  int max_wg;
   const int *colK;
   int kneed;
   SolveState st;
@@ -148,6 +183,8 @@ int launch_rows_grid(int rows, int Bs);
 void launch_finalize(const FinArgs &a, hipStream_t s);
 void launch_stiff(const StiffArgs &a, hipStream_t s);
 void launch_cg_init(const CgArgs &a, hipStream_t s);
+void launch_cheb_iter(const ChebArgs &a, hipStream_t s);
+void launch_cheb_check(const CheckArgs &a, hipStream_t s);
 void launch_cg_iter(const CgArgs &a, hipStream_t s);
 void launch_combine(const CombineArgs &a, hipStream_t s);
 void launch_reduce_terms(const ReduceTermsArgs &a, hipStream_t s);

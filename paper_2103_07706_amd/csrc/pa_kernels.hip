@@ -108,6 +108,7 @@ __global__ __launch_bounds__(kWG) void k_stiff(StiffArgs a) {
   const bool act = a.colK[c] >= a.kneed;
   const bool acc_on = a.acc_u != nullptr && a.colK[c] >= a.acc_k;
   const double coef = acc_on ? a.coef[c] : 0.0;
+  double rr = 0.0;
   for (int base = L.row0 - L.lane / L.ct; base < L.rend; base += L.rstride) {
     const int e = base + L.lane / L.ct;
     // edges
@@ -126,6 +127,10 @@ __global__ __launch_bounds__(kWG) void k_stiff(StiffArgs a) {
         if (a.addB_u) x0 += a.addB_u[ie];
         a.r[ie] = r;
         a.out_u[ie] = x0;
+        if (a.d0) {
+          a.d0[ie] = a.theta_inv * o.dinv[e] * r;
+          rr += r * r;
+        }
       }
       if (acc_on) accv = coef * a.in_u[ie];
     }
@@ -158,6 +163,64 @@ __global__ __launch_bounds__(kWG) void k_stiff(StiffArgs a) {
     }
   }
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) a.st.cnt[1] = 0;
+  if (a.d0) {
+    double v[1] = {rr};
+    wg_partials<1>(L, v, a.part_rr, a.max_wg);
+  }
+}
+
+// -------------------------------------------- Chebyshev semi-iteration
+// Reduction-free solver for the velocity mass matrix M: with spectral bounds
+// [lmin, lmax] of D^-1 M (theta, delta their centre and half-width,
+// sigma = theta/delta), from r_0 and d_0 = D^-1 r_0 / theta,
+//   x += d_k,  r -= M d_k,  d_{k+1} = rho_{k+1} rho_k d_k + (2 rho_{k+1}/delta) D^-1 r,
+//   rho_0 = 1/sigma,  rho_{k+1} = 1/(2 sigma - rho_k)
+// (Saad, Iterative Methods for Sparse Linear Systems, Alg. 12.1).  The step
+// count follows from the bounds; the final residual is checked in FP64.  One
+// kernel per step, gathering only d.
+__global__ __launch_bounds__(kWG) void k_cheb_iter(ChebArgs a) {
+  const Lane L = lane_map(a.Bs, a.ops.ne);
+  const DevOps &o = a.ops;
+  const int c = L.col, Bs = a.Bs;
+  double sums[1] = {0.0};
+  if (a.colK[c] >= a.kneed) {
+    for (int e = L.row0; e < L.rend; e += L.rstride) {
+      double q = 0.0;
+#pragma unroll
+      for (int j = 0; j < 5; j++) q += o.mass[5 * e + j] * a.d_in[(size_t)o.ell_col[5 * e + j] * Bs + c];
+      const size_t ie = (size_t)e * Bs + c;
+      const double d = a.d_in[ie];
+      a.x[ie] += d;
+      const double r = a.r[ie] - q;
+      a.r[ie] = r;
+      if (a.last)
+        sums[0] += r * r;
+      else
+        a.d_out[ie] = a.c1 * d + a.c2 * o.dinv[e] * r;
+    }
+  }
+  if (a.last) wg_partials<1>(L, sums, a.part, a.max_wg);
+}
+
+// Per column: |r_final|^2 <= rtol^2 |r_0|^2, else count a failure.
+__global__ __launch_bounds__(kWG) void k_cheb_check(CheckArgs a) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ct = a.Bs < 64 ? a.Bs : 64;
+  const int cpb = ct < 4 ? ct : 4;
+  const int bpt = ct / cpb;
+  const int tile = blockIdx.x / bpt;
+  const int cl = (blockIdx.x % bpt) * cpb + wave;
+  if (wave >= cpb) return;
+  const int c = tile * ct + cl;
+  double b = 0.0, r = 0.0;
+  for (int w = lane; w < a.nwg_init; w += 64) b += a.part_init[((size_t)tile * a.max_wg + w) * 64 + cl];
+  for (int w = lane; w < a.nwg_last; w += 64) r += a.part_last[((size_t)tile * a.max_wg + w) * 64 + cl];
+  b = wave_col_sum(b, 1);
+  r = wave_col_sum(r, 1);
+  if (lane == 0 && a.colK[c] >= a.kneed && b > 0.0) {
+    a.resid[c] = sqrt(r / b);
+    if (!(r <= a.rtol2 * b)) atomicAdd(a.fail, 1);
+  }
 }
 
 // -------------------------------------------------- CG (Chronopoulos-Gear)
@@ -540,14 +603,24 @@ __global__ __launch_bounds__(kWG) void k_nl_gather(GatherArgs a) {
   const Lane L = lane_map(a.Bs, a.ops.ne);
   const DevOps &o = a.ops;
   const int c = L.col, Bs = a.Bs;
+  double rr = 0.0;
   if (a.colK[c] >= a.kneed) {
     for (int e = L.row0; e < L.rend; e += L.rstride) {
       const size_t ie = (size_t)e * Bs + c;
-      a.r[ie] = a.C[(size_t)o.cidx[2 * e] * Bs + c] + a.C[(size_t)o.cidx[2 * e + 1] * Bs + c];
+      const double r = a.C[(size_t)o.cidx[2 * e] * Bs + c] + a.C[(size_t)o.cidx[2 * e + 1] * Bs + c];
+      a.r[ie] = r;
       a.x[ie] = 0.0;
+      if (a.d0) {
+        a.d0[ie] = a.theta_inv * o.dinv[e] * r;
+        rr += r * r;
+      }
     }
   }
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) a.st.cnt[1] = 0;
+  if (a.d0) {
+    double v[1] = {rr};
+    wg_partials<1>(L, v, a.part_rr, a.max_wg);
+  }
 }
 
 // ----------------------------------------------------------- elementwise
@@ -736,6 +809,15 @@ void launch_stiff(const StiffArgs &a, hipStream_t s) {
 }
 void launch_cg_init(const CgArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_init, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+}
+void launch_cheb_iter(const ChebArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_cheb_iter, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+}
+void launch_cheb_check(const CheckArgs &a, hipStream_t s) {
+  const int ct = a.Bs < 64 ? a.Bs : 64;
+  const int cpb = ct < 4 ? ct : 4;
+  const int tiles = (a.Bs + 63) / 64;
+  hipLaunchKernelGGL(k_cheb_check, dim3(tiles * (ct / cpb)), dim3(kWG), 0, s, a);
 }
 void launch_cg_iter(const CgArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_iter, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);

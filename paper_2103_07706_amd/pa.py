@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libpa.so")
 
 PA_FP64, PA_FP32_REFINED = 0, 1
 PA_BACKWARD_PER_TERM, PA_BACKWARD_CLENSHAW = 0, 1
+PA_SOLVER_CG, PA_SOLVER_CHEBYSHEV = 0, 1
 _STATUS = {0: "PA_OK", 1: "PA_EINVAL", 2: "PA_ENOMEM", 3: "PA_EHIP", 4: "PA_ENOCONV",
            5: "PA_ENOTSUP", 6: "PA_EGROWTH"}
 
@@ -42,7 +43,7 @@ class SolveCfg(ctypes.Structure):
                 ("maxit", ctypes.c_int32), ("growth_guard", ctypes.c_int32),
                 ("cg_rtol", ctypes.c_double), ("cheb_tol", ctypes.c_double),
                 ("weight_cut", ctypes.c_double), ("inner_rtol", ctypes.c_double),
-                ("use_graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("solver", ctypes.c_int32)]
 
 
 PA_KERNEL_NONE, PA_KERNEL_CG_ITER = 0, 1
@@ -156,9 +157,11 @@ def _dp(a):
 
 
 def solve_cfg(precision=PA_FP64, backward=PA_BACKWARD_PER_TERM, maxit=None, cg_rtol=None,
-              cheb_tol=None, weight_cut=None, inner_rtol=None, use_graph=False) -> SolveCfg:
+              cheb_tol=None, weight_cut=None, inner_rtol=None, use_graph=False,
+              solver=PA_SOLVER_CG) -> SolveCfg:
     c = SolveCfg()
     lib().pa_solve_cfg_default(ctypes.byref(c))
+    c.solver = solver
     c.precision = precision
     c.backward = backward
     c.use_graph = 1 if use_graph else 0
@@ -363,7 +366,8 @@ class Ops:
         cfg = cfg or solve_cfg()
         members = U.shape[0]
         key = (f"level{self.mesh.level}_members{members}_M{avg.M}_rtol{cfg.cg_rtol:g}_"
-               f"tol{cfg.cheb_tol:g}_bw{cfg.backward}_prec{cfg.precision}_graph{cfg.use_graph}")
+               f"tol{cfg.cheb_tol:g}_bw{cfg.backward}_prec{cfg.precision}_graph{cfg.use_graph}_"
+               f"solver{cfg.solver}")
         table = {}
         if cache and os.path.exists(cache):
             table = json.load(open(cache))

@@ -193,3 +193,45 @@ def test_gpu_autotune_keeps_parity(tmp_path):
     got = mm.back(out.cpu().numpy())[0]
     ref = oo.phase_avg_rhs(lb, avg.s, avg.w, U[0], tol=1e-13, rtol=1e-14)
     assert rel_w(oo, got, ref) < TOL
+
+
+CHEB = dict(solver=1)
+
+
+@pytest.mark.parametrize("backward", [0, 1])
+def test_gpu_chebyshev_solver_parity(backward):
+    """Reduction-free Chebyshev mass solves reach the same FP64 residual
+    tolerance as CG: the averaged RHS and the exponential agree with the
+    oracle (which uses CG) to the same bar."""
+    from paper_2103_07706_amd import pa
+    om, oo, lm, lo, mm, lb = pair(3)
+    U = bumps(om, [0])
+    avg = pa.Avg(8, 3600.0)
+    cfg = pa.solve_cfg(backward=backward, weight_cut=0.0, **PARITY, **CHEB)
+    out, st = lo.phase_avg_rhs(avg, to_dev(mm.state(U)), cfg)
+    got = mm.back(out.cpu().numpy())[0]
+    ref = oo.phase_avg_rhs(lb, avg.s, avg.w, U[0], tol=1e-13, rtol=1e-14)
+    assert rel_w(oo, got, ref) < TOL
+    ts = [900.0, -2700.0]
+    U2 = bumps(om, [1, 2])
+    out, _ = lo.expL_apply(ts, to_dev(mm.state(U2)), cfg)
+    got = mm.back(out.cpu().numpy())
+    for j, t in enumerate(ts):
+        ref, _ = oo.expL(lb, t, U2[j], tol=1e-13, rtol=1e-14)
+        assert rel_w(oo, got[j], ref) < TOL
+
+
+def test_gpu_chebyshev_check_failure_falls_back():
+    """Too few Chebyshev steps (maxit caps them) fail the final residual
+    check; the call is repeated with CG, which then reports non-convergence
+    under the same cap."""
+    from paper_2103_07706_amd import pa
+    om, oo, lm, lo, mm, lb = pair(2)
+    U = to_dev(mm.state(bumps(om, [0])))
+    cfg = pa.solve_cfg(maxit=4, cg_rtol=1e-12, **CHEB)
+    with pytest.raises(pa.PAError) as ei:
+        lo.swe_nonlinear(U, cfg)
+    assert ei.value.code == 4
+    ok, _ = lo.swe_nonlinear(U, pa.solve_cfg(cg_rtol=1e-12, **CHEB))
+    ref, _ = lo.swe_nonlinear(U, pa.solve_cfg(cg_rtol=1e-12))
+    assert np.abs(ok.cpu().numpy() - ref.cpu().numpy()).max() <= 1e-9 * np.abs(ref.cpu().numpy()).max()
