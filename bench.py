@@ -123,7 +123,8 @@ def main():
     # the dominant kernel, timed with HIP events around each of its launches
     # over the same number of steps (events add small gaps between kernels,
     # so this pass is kept apart from the throughput measurement)
-    ctx.profile(pa.PA_KERNEL_CG_ITER)
+    kernel = "k_cheb_iter" if args.solver == "chebyshev" else "k_cg_iter"
+    ctx.profile(pa.PA_KERNEL_CHEB_ITER if args.solver == "chebyshev" else pa.PA_KERNEL_CG_ITER)
     for i in range(args.steps):
         ops.phase_avg_rhs(avg, U, cfg, out=out)
     prof = ctx.profile_read()
@@ -131,7 +132,7 @@ def main():
     value = wl.members * args.steps / elapsed
     avg_ms = prof["total_ms"] / max(1, prof["launches"])
     achieved = prof["bytes"] / (prof["total_ms"] * 1e-3) / 1e9 if prof["total_ms"] > 0 else 0.0
-    traffic = traffic_from_profiles("cg_iter", args.workload, args.backward)
+    traffic = traffic_from_profiles(kernel, args.workload, args.backward)
     rec = {
         "metric": "phase-avg RHS evals/s (L6 mesh, M=64)",
         "value": value,
@@ -154,7 +155,7 @@ def main():
                    "cg_iters_max": stats["cg_iters_max"], "solves": stats["solves"],
                    "graph": bool(stats["graph"]), "cg_budget": stats["budget"],
                    "launch_tune": tune},
-        "roofline": {"bound": "hbm", "kernel": "k_cg_iter", "achieved": achieved,
+        "roofline": {"bound": "hbm", "kernel": kernel, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "avg_launch_us": 1e3 * avg_ms,
                      "launches": prof["launches"],

@@ -78,13 +78,24 @@ void Engine::cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_i
   a.max_wg = rb_.max_wg;
   double *d[2] = {p_, s0_};
   const int k = (int)cheb_c1_.size();
+  const bool prof = ctx_->prof_kernel == PA_KERNEL_CHEB_ITER;
+  a.prof = prof ? st_.prof : nullptr;
   for (int i = 0; i < k; i++) {
     a.d_in = d[i & 1];
     a.d_out = d[(i + 1) & 1];
     a.c1 = cheb_c1_[i];
     a.c2 = cheb_c2_[i];
     a.last = i + 1 == k ? 1 : 0;
-    launch_cheb_iter(a, s_);
+    if (prof) {
+      hipEvent_t e0 = take_event(), e1 = take_event();
+      PA_HIP(hipEventRecord(e0, s_));
+      launch_cheb_iter(a, s_);
+      PA_HIP(hipEventRecord(e1, s_));
+      prof_ev_.push_back(e0);
+      prof_ev_.push_back(e1);
+    } else {
+      launch_cheb_iter(a, s_);
+    }
   }
   CheckArgs ca{};
   ca.Bs = Bs;
@@ -139,8 +150,9 @@ void Engine::plan_common(int BsMax) {
     st_.fail = (int *)(z + 2);
     st_.iter_max = (int *)(z + 3);
     st_.prof = z + 4;
-    st_.budget_fail = (int *)(z + 6);
-    st_.cheb_fail = (int *)(z + 7);
+    st_.prof_last = z + 6;
+    st_.budget_fail = (int *)(z + 7);
+    st_.cheb_fail = (int *)(z + 8);
   }
 }
 
@@ -168,8 +180,8 @@ void Engine::begin() {
 
 void Engine::finish() {
   PA_HIP(hipEventRecord(ev1_, s_));
-  int h[6] = {0, 0, 0, 0, 0, 0};
-  PA_HIP(hipMemcpyAsync(h, st_.fail, 6 * sizeof(int), hipMemcpyDeviceToHost, s_));
+  int h[7] = {0, 0, 0, 0, 0, 0, 0};
+  PA_HIP(hipMemcpyAsync(h, st_.fail, 7 * sizeof(int), hipMemcpyDeviceToHost, s_));
   PA_HIP(hipStreamSynchronize(s_));
   if (ctx_->prof_kernel != PA_KERNEL_NONE) {
     for (size_t i = 0; i + 1 < prof_ev_.size(); i += 2) {
@@ -187,6 +199,9 @@ void Engine::finish() {
     // and the Jacobi diagonal once per launch
     if (ctx_->prof_kernel == PA_KERNEL_CG_ITER)
       ctx_->prof_bytes += (double)ne_ * (80.0 * cols + 68.0 * work);
+    // Chebyshev step: x, r, d in; x, r, d' out (d' not on the last step)
+    if (ctx_->prof_kernel == PA_KERNEL_CHEB_ITER)
+      ctx_->prof_bytes += (double)ne_ * (48.0 * cols + 40.0 * (unsigned)h[4] + 68.0 * work);
     ctx_->prof_work += (int64_t)work;
   }
   float ms = 0;
@@ -198,8 +213,8 @@ void Engine::finish() {
   stats.cg_iters_max = std::max(stats.cg_iters_max, h[1]);
   if (h[0] > 0)
     throw Error(PA_ENOCONV, std::to_string(h[0]) + " mass-solve column(s) did not converge within maxit");
-  if (h[4] > 0) throw BudgetExceeded();
-  if (h[5] > 0) throw SolverCheckFailed();
+  if (h[5] > 0) throw BudgetExceeded();
+  if (h[6] > 0) throw SolverCheckFailed();
   // next calls on this context run without polling, with this budget
   if (learn_budget_) ctx_->cg_budget[cfg_.cg_rtol] = std::min(cfg_.maxit, h[1] + 2);
 }

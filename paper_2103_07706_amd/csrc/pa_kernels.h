@@ -27,7 +27,9 @@ struct SolveState {
   int *cheb_fail;         // 1: Chebyshev solves that missed the residual tolerance
   int *fail;              // 1 (accumulates over solves)
   int *iter_max;          // 1 (accumulates over solves)
-  unsigned *prof;         // [2]: active columns summed over launches, work launches
+  unsigned *prof;         // [3]: active columns summed over launches, work launches,
+                          //      columns of last Chebyshev steps
+  unsigned *prof_last;    // = prof + 2
 };
 
 struct StiffArgs {
@@ -85,6 +87,7 @@ struct ChebArgs {
   int kneed, last;
   double *part;  // last step: partials of r.r
   int max_wg;
+  unsigned *prof;  // measurement hook: [0] active columns, [1] launches, [2] columns of last steps
 };
 
 // Residual check after a Chebyshev solve.

@@ -182,6 +182,12 @@ __global__ __launch_bounds__(kWG) void k_cheb_iter(ChebArgs a) {
   const Lane L = lane_map(a.Bs, a.ops.ne);
   const DevOps &o = a.ops;
   const int c = L.col, Bs = a.Bs;
+  if (a.prof && blockIdx.x == 0 && threadIdx.x == 0) {
+    unsigned n = 0;
+    for (int j = 0; j < L.ct; j++) n += a.colK[L.tile * L.ct + j] >= a.kneed ? 1u : 0u;
+    atomicAdd(&a.prof[a.last ? 2 : 0], n);
+    if (L.tile == 0) atomicAdd(&a.prof[1], 1u);
+  }
   double sums[1] = {0.0};
   if (a.colK[c] >= a.kneed) {
     for (int e = L.row0; e < L.rend; e += L.rstride) {
@@ -400,34 +406,76 @@ __global__ __launch_bounds__(kWG) void k_cg_iter(CgArgs a) {
 }
 
 // ------------------------------------------- forward combination of a basis
-// E[row][m*1 + mem*G] = sum_k cf[k][m] R_k[row][mem] for both row ranges.
+// E[row][mem*G + m] = sum_k cf[k][m] R_k[row][mem], both row ranges.  One
+// thread per (row, member): it reads that member's basis values R_0..R_kmax
+// (consecutive threads, consecutive addresses) and writes its G outputs as
+// one contiguous run; the coefficients sit in LDS.  Chunks of 16 outputs keep
+// the accumulators in registers.
+constexpr int kCoefLds = 6144;  // doubles of coefficient table held in LDS
+
 __global__ __launch_bounds__(kWG) void k_combine(CombineArgs a) {
-  const size_t total = (size_t)a.nrows * a.BsE;
-  for (size_t i = (size_t)blockIdx.x * kWG + threadIdx.x; i < total; i += (size_t)gridDim.x * kWG) {
-    const int row = (int)(i / a.BsE), col = (int)(i % a.BsE);
-    const int mem = col / a.G, m = col % a.G;
-    double s = 0.0;
-    if (mem < a.members) {
-      const double *Rk = a.basis + (size_t)row * a.BsR + mem;
-      for (int k = 0; k <= a.kmax; k++) s += a.cf[k * a.G + m] * Rk[(size_t)k * a.basis_stride];
+  __shared__ double cf[kCoefLds];
+  const int ncoef = (a.kmax + 1) * a.G;
+  const bool lds = ncoef <= kCoefLds;
+  if (lds)
+    for (int i = threadIdx.x; i < ncoef; i += kWG) cf[i] = a.cf[i];
+  __syncthreads();
+  const double *C = lds ? cf : a.cf;
+  const long total = (long)a.nrows * a.BsR;
+  for (long t = (long)blockIdx.x * kWG + threadIdx.x; t < total; t += (long)gridDim.x * kWG) {
+    const long row = t / a.BsR;
+    const int mem = (int)(t - row * a.BsR);
+    double *out = a.E + t * a.G;
+    if (mem >= a.members) {
+      for (int m = 0; m < a.G; m++) out[m] = 0.0;
+      continue;
     }
-    a.E[i] = s;
+    const double *R = a.basis + t;
+    for (int m0 = 0; m0 < a.G; m0 += 16) {
+      double acc[16];
+#pragma unroll
+      for (int j = 0; j < 16; j++) acc[j] = 0.0;
+      for (int k = 0; k <= a.kmax; k++) {
+        const double r = R[(size_t)k * a.basis_stride];
+        const double *ck = C + k * a.G + m0;
+#pragma unroll
+        for (int j = 0; j < 16; j++)
+          if (m0 + j < a.G) acc[j] += ck[j] * r;
+      }
+#pragma unroll
+      for (int j = 0; j < 16; j++)
+        if (m0 + j < a.G) out[m0 + j] = acc[j];
+    }
   }
 }
 
-// Z_k[row][mem] = sum_m cb[k][m] Y[row][mem*G + m], k = 0..kmax.
+// Z_k[row][mem] = sum_m cb[k][m] Y[row][mem*G + m], k = 0..kmax.  One thread
+// per (row, member): it reads its G contiguous values of Y once per chunk of
+// 16 degrees and writes Z_k for consecutive (row, member) across threads.
 __global__ __launch_bounds__(kWG) void k_reduce_terms(ReduceTermsArgs a) {
-  const size_t total = (size_t)a.nrows * a.BsY;
-  const int BsZ = a.BsZ;
-  for (size_t base = (size_t)blockIdx.x * kWG; base < total; base += (size_t)gridDim.x * kWG) {
-    const size_t i = base + threadIdx.x;
-    const bool in = i < total;
-    const int row = in ? (int)(i / a.BsY) : 0, col = in ? (int)(i % a.BsY) : 0;
-    const int mem = col / a.G, m = col % a.G;
-    const double y = in ? a.Y[i] : 0.0;
-    for (int k = 0; k <= a.kmax; k++) {
-      double v = lane_group_sum(in ? a.cb[k * a.G + m] * y : 0.0, a.G);
-      if (in && m == 0 && mem < BsZ) a.Z[(size_t)k * a.zstride + (size_t)row * BsZ + mem] = v;
+  __shared__ double cb[kCoefLds];
+  const int ncoef = (a.kmax + 1) * a.G;
+  const bool lds = ncoef <= kCoefLds;
+  if (lds)
+    for (int i = threadIdx.x; i < ncoef; i += kWG) cb[i] = a.cb[i];
+  __syncthreads();
+  const double *C = lds ? cb : a.cb;
+  const long total = (long)a.nrows * a.BsZ;
+  for (long t = (long)blockIdx.x * kWG + threadIdx.x; t < total; t += (long)gridDim.x * kWG) {
+    const double *y = a.Y + t * a.G;
+    for (int k0 = 0; k0 <= a.kmax; k0 += 16) {
+      double acc[16];
+#pragma unroll
+      for (int j = 0; j < 16; j++) acc[j] = 0.0;
+      for (int m = 0; m < a.G; m++) {
+        const double v = y[m];
+#pragma unroll
+        for (int j = 0; j < 16; j++)
+          if (k0 + j <= a.kmax) acc[j] += C[(k0 + j) * a.G + m] * v;
+      }
+#pragma unroll
+      for (int j = 0; j < 16; j++)
+        if (k0 + j <= a.kmax) a.Z[(size_t)(k0 + j) * a.zstride + t] = acc[j];
     }
   }
 }
@@ -823,10 +871,10 @@ void launch_cg_iter(const CgArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_iter, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
 }
 void launch_combine(const CombineArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_combine, dim3(grid_flat((size_t)a.nrows * a.BsE)), dim3(kWG), 0, s, a);
+  hipLaunchKernelGGL(k_combine, dim3(grid_flat((size_t)a.nrows * a.BsR)), dim3(kWG), 0, s, a);
 }
 void launch_reduce_terms(const ReduceTermsArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_terms, dim3(grid_flat((size_t)a.nrows * a.BsY)), dim3(kWG), 0, s, a);
+  hipLaunchKernelGGL(k_reduce_terms, dim3(grid_flat((size_t)a.nrows * a.BsZ)), dim3(kWG), 0, s, a);
 }
 void launch_nl_upwind(const NlArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_nl_upwind, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);

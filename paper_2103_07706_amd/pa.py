@@ -46,7 +46,7 @@ class SolveCfg(ctypes.Structure):
                 ("use_graph", ctypes.c_int32), ("solver", ctypes.c_int32)]
 
 
-PA_KERNEL_NONE, PA_KERNEL_CG_ITER = 0, 1
+PA_KERNEL_NONE, PA_KERNEL_CG_ITER, PA_KERNEL_CHEB_ITER = 0, 1, 2
 
 
 class KernelProfile(ctypes.Structure):

@@ -1,0 +1,71 @@
+"""GPU checks at the throughput workload's full size (level 6, 81920 cells,
+122880 edges), in the configuration the benchmark times (M = 64, T = 2 h,
+Chebyshev threshold 1e-6, mass solves to 1e-10, graph replay, Chebyshev
+semi-iteration for the mass solves).
+
+The oracle cannot evaluate all 64 terms here in reasonable time, so:
+  * one averaging term at the largest phase shift (the longest
+    exponentials) is compared with the oracle in parity mode;
+  * the full 64-term result is checked through properties that hold at any
+    size: zero mass of the depth tendency, agreement of the two independent
+    backward formulations (per-term recurrences with fused weighted sum vs.
+    one Clenshaw recurrence over term-combined right-hand sides), agreement
+    of the two mass solvers, and invariance under graph replay.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import PARITY, pair, rel_w, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def l6():
+    from paper_2103_07706_amd import inputs
+    om, oo, lm, lo, mm, lb = pair(6, lambda_iters=120)
+    U = inputs.gaussian_bumps_state(om.verts, om.cell_verts, om.edge_verts, 40, 0)
+    return om, oo, lm, lo, mm, lb, U
+
+
+def test_level6_single_term_matches_oracle(l6):
+    from paper_2103_07706_amd import pa
+    om, oo, lm, lo, mm, lb, U = l6
+    s_all, _ = pa.Avg(64, 7200.0).s, None
+    s = np.array([s_all[-1]])
+    w = np.array([1.0])
+    avg = pa.Avg(s=s, w=w)
+    for solver in (0, 1):
+        cfg = pa.solve_cfg(solver=solver, weight_cut=0.0, **PARITY)
+        out, st = lo.phase_avg_rhs(avg, to_dev(mm.state(U)[None]), cfg)
+        got = mm.back(out.cpu().numpy()[0])
+        if solver == 0:
+            ref = oo.phase_avg_rhs(lb, s, w, U, tol=1e-13, rtol=1e-14)
+        assert rel_w(oo, got, ref) < 1e-12, (solver, rel_w(oo, got, ref))
+
+
+def test_level6_full_average_properties(l6):
+    import torch
+    from paper_2103_07706_amd import pa
+    om, oo, lm, lo, mm, lb, U = l6
+    avg = pa.Avg(64, 7200.0)
+    Ud = to_dev(mm.state(U)[None])
+    res = {}
+    for name, bw, solver, graph in [("clenshaw_cheb_graph", 1, 1, True),
+                                    ("clenshaw_cheb", 1, 1, False),
+                                    ("per_term_cheb", 0, 1, False),
+                                    ("clenshaw_cg", 1, 0, False)]:
+        cfg = pa.solve_cfg(backward=bw, solver=solver, cheb_tol=1e-6, cg_rtol=1e-10,
+                           use_graph=graph)
+        out = torch.empty_like(Ud)
+        for _ in range(2 if graph else 1):
+            lo.phase_avg_rhs(avg, Ud, cfg, out=out)
+        res[name] = mm.back(out.cpu().numpy()[0])
+    ref = res["clenshaw_cheb"]
+    area = oo.export()["area"]
+    for name, v in res.items():
+        # mass of the depth tendency vanishes
+        assert abs(np.sum(area * v[om.ne:])) <= 1e-12 * np.sum(np.abs(area * v[om.ne:])), name
+        # the formulations agree to the solve tolerance
+        assert rel_w(oo, v, ref) < 1e-8, (name, rel_w(oo, v, ref))
+    assert np.array_equal(res["clenshaw_cheb_graph"], ref)
