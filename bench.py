@@ -33,6 +33,7 @@ def parse():
     ap.add_argument("--backward", default="clenshaw", choices=["per_term", "clenshaw"])
     ap.add_argument("--graph", type=int, default=1)
     ap.add_argument("--solver", default="chebyshev", choices=["cg", "chebyshev"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_refined"])
     ap.add_argument("--autotune", type=int, default=1)
     ap.add_argument("--cpu-baseline", dest="cpu", type=int, default=1)
     ap.add_argument("--cpu-terms", type=int, default=4)
@@ -101,8 +102,9 @@ def main():
     avg = pa.Avg(wl.M, wl.T)
     bw = pa.PA_BACKWARD_PER_TERM if args.backward == "per_term" else pa.PA_BACKWARD_CLENSHAW
     solver = pa.PA_SOLVER_CG if args.solver == "cg" else pa.PA_SOLVER_CHEBYSHEV
+    prec = pa.PA_FP64 if args.precision == "fp64" else pa.PA_FP32_REFINED
     cfg = pa.solve_cfg(backward=bw, cheb_tol=1e-6, cg_rtol=1e-10, use_graph=bool(args.graph),
-                       solver=solver)
+                       solver=solver, precision=prec)
     out = torch.empty_like(U)
     tune = None
     if args.autotune:
@@ -149,7 +151,7 @@ def main():
         "config": {"workload": args.workload, "level": wl.level, "cells": mesh.nc,
                    "edges": mesh.ne, "M": wl.M, "T_s": wl.T, "members": wl.members,
                    "cheb_tol": 1e-6, "cg_rtol": 1e-10, "backward": args.backward,
-                   "precision": "fp64", "preconditioner": "jacobi", "lambda_bar": lam,
+                   "precision": args.precision, "preconditioner": "jacobi", "lambda_bar": lam,
                    "mass_solver": args.solver,
                    "kmax": stats["kmax"], "ksum": stats["ksum"], "terms": stats["terms"],
                    "cg_iters_max": stats["cg_iters_max"], "solves": stats["solves"],

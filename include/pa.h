@@ -122,7 +122,13 @@ int pa_avg_destroy(pa_avg *avg);
 enum { PA_FP64 = 0, PA_FP32_REFINED = 1 };
 enum { PA_BACKWARD_PER_TERM = 0, PA_BACKWARD_CLENSHAW = 1 };
 typedef struct {
-  int32_t precision;   /* PA_FP64 | PA_FP32_REFINED */
+  int32_t precision;   /* PA_FP64, or PA_FP32_REFINED: every mass solve runs
+                          FP32 Chebyshev inner solves (FP32 copy of M_u,
+                          to max(inner_rtol, 1e-6)) inside FP64 refinement
+                          (x += x32, r -= M x32 with the FP64 matrix); the
+                          final FP64 residual is checked against cg_rtol and
+                          a failed check repeats the call in FP64.  The
+                          recurrences, stiffness, N and all sums stay FP64. */
   int32_t backward;    /* how the M backward exponentials are summed */
   int32_t maxit;       /* CG iterations per mass solve (FP64) */
   int32_t growth_guard;/* 1: fail with PA_EGROWTH if the recurrence grows */

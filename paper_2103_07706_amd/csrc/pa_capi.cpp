@@ -422,6 +422,7 @@ void run_with_fallback(pa_solve_cfg cfg, bool rerun_ok, F &&f) {
   } catch (const pa::SolverCheckFailed &) {
     if (!rerun_ok) throw;
     cfg.solver = PA_SOLVER_CG;
+    cfg.precision = PA_FP64;
     f(cfg);
   }
 }
@@ -507,7 +508,8 @@ int pa_step(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, double dt, int me
     check_call(ctx, ops, ws);
     need(avg && U_dev_inout && members >= 1 && dt > 0, "bad arguments");
     pa_solve_cfg c = cfg_or_default(cfg);
-    c.solver = PA_SOLVER_CG;  // in place: no repeat possible, keep CG
+    c.solver = PA_SOLVER_CG;  // in place: no repeat possible, keep FP64 CG
+    c.precision = PA_FP64;
     pa::Engine e(ctx, ops, c, ws, ws_bytes);
     e.step(avg, dt, members, U_dev_inout);
     out_stats(stats, e);

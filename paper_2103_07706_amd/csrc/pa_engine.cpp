@@ -36,10 +36,12 @@ Engine::Engine(pa_ctx *ctx, const pa_ops *ops, const pa_solve_cfg &cfg, void *ws
   if (cfg_.maxit <= 0) throw Error(PA_EINVAL, "maxit must be positive");
   if (!(cfg_.cg_rtol > 0)) throw Error(PA_EINVAL, "cg_rtol must be positive");
   if (!(cfg_.cheb_tol > 0)) throw Error(PA_EINVAL, "cheb_tol must be positive");
-  if (cfg_.precision != PA_FP64) throw Error(PA_ENOTSUP, "only PA_FP64 is implemented");
+  if (cfg_.precision != PA_FP64 && cfg_.precision != PA_FP32_REFINED)
+    throw Error(PA_EINVAL, "unknown precision");
   if (cfg_.solver != PA_SOLVER_CG && cfg_.solver != PA_SOLVER_CHEBYSHEV)
     throw Error(PA_EINVAL, "unknown solver");
-  if (cheb()) plan_cheb();
+  if (mixed() && !(cfg_.inner_rtol > 0 && cfg_.inner_rtol < 1)) throw Error(PA_EINVAL, "inner_rtol in (0, 1)");
+  if (cheb() || mixed()) plan_cheb();
 }
 
 // Chebyshev semi-iteration on D^-1 M over [a, b] = Lanczos bounds widened
@@ -62,6 +64,80 @@ void Engine::plan_cheb() {
     cheb_c2_[i] = 2.0 * rn / cheb_delta_;
     rho = rn;
   }
+  if (mixed()) {
+    // FP32 inner solves to eps = max(inner_rtol, 1e-6) (single-precision
+    // floor), outer FP64 refinements until eps^n_out reaches cg_rtol
+    const double eps = std::max(cfg_.inner_rtol, 1e-6);
+    const int kin = std::min(cfg_.maxit, (int)std::ceil(std::acosh(2.0 / eps) / std::acosh(sigma)) + 1);
+    mixed_outer_ = std::max(1, (int)std::ceil(std::log(cfg_.cg_rtol) / std::log(10.0 * eps)));
+    mix_c1_.assign(cheb_c1_.begin(), cheb_c1_.begin() + std::min(kin, (int)cheb_c1_.size()));
+    mix_c2_.assign(cheb_c2_.begin(), cheb_c2_.begin() + mix_c1_.size());
+    while ((int)mix_c1_.size() < kin) {  // more steps than the FP64 plan
+      const double rn = 1.0 / (2.0 * sigma - rho);
+      mix_c1_.push_back(rn * rho);
+      mix_c2_.push_back(2.0 * rn / cheb_delta_);
+      rho = rn;
+    }
+  }
+}
+
+// Mixed-precision mass solve (FP32 inner Chebyshev, FP64 refinement); the
+// set-up kernel wrote r_0, x_0 and the partials of |r_0|^2 (partA).
+void Engine::mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_init) {
+  RefineArgs ra{};
+  ra.ops = ops_->d;
+  ra.Bs = Bs;
+  ra.x = x;
+  ra.r = r_;
+  ra.x32 = x32_;
+  ra.r32 = r32_;
+  ra.d32 = d32_[0];
+  ra.theta_inv = (float)(1.0 / cheb_theta_);
+  ra.colK = colK;
+  ra.kneed = kneed;
+  ra.part = rb_.partB;
+  ra.max_wg = rb_.max_wg;
+  ra.first = 1;
+  launch_refine(ra, s_);
+  Cheb32Args ca{};
+  ca.ops = ops_->d;
+  ca.Bs = Bs;
+  ca.x32 = x32_;
+  ca.r32 = r32_;
+  ca.colK = colK;
+  ca.kneed = kneed;
+  const int kin = (int)mix_c1_.size();
+  for (int o = 0; o < mixed_outer_; o++) {
+    for (int i = 0; i < kin; i++) {
+      ca.d_in = d32_[i & 1];
+      ca.d_out = d32_[(i + 1) & 1];
+      ca.c1 = (float)mix_c1_[i];
+      ca.c2 = (float)mix_c2_[i];
+      ca.first = i == 0 ? 1 : 0;
+      ca.last = i + 1 == kin ? 1 : 0;
+      launch_cheb32_iter(ca, s_);
+    }
+    ra.first = 0;
+    ra.last = o + 1 == mixed_outer_ ? 1 : 0;
+    launch_refine(ra, s_);
+  }
+  CheckArgs ck{};
+  ck.Bs = Bs;
+  ck.nwg_init = nwg_init;
+  ck.nwg_last = launch_rows_grid(ne_, Bs);
+  ck.max_wg = rb_.max_wg;
+  ck.part_init = rb_.partA;
+  ck.part_last = rb_.partB;
+  ck.colK = colK;
+  ck.kneed = kneed;
+  ck.rtol2 = cfg_.cg_rtol * cfg_.cg_rtol;
+  ck.fail = st_.cheb_fail;
+  ck.resid = st_.resid;
+  launch_cheb_check(ck, s_);
+  stats.solves++;
+  stats.refinements += mixed_outer_;
+  stats.cg_iters += kin * mixed_outer_;
+  stats.cg_iters_max = std::max(stats.cg_iters_max, kin * mixed_outer_);
 }
 
 // Reduction-free mass solve: the set-up kernel wrote r_0 (r), x_0 (x),
@@ -119,6 +195,12 @@ void Engine::plan_common(int BsMax) {
   BsMax_ = BsMax;
   const int tiles = tiles_of(BsMax);
   const size_t ebs = (size_t)ne_ * BsMax;
+  if (mixed()) {
+    x32_ = ar_.take<float>(ebs);
+    r32_ = ar_.take<float>(ebs);
+    d32_[0] = ar_.take<float>(ebs);
+    d32_[1] = ar_.take<float>(ebs);
+  }
   r_ = ar_.take<double>(ebs);   // r[0]; the set-up kernels write r_0 here
   r1_ = ar_.take<double>(ebs);
   w0_ = ar_.take<double>(ebs);
@@ -409,14 +491,16 @@ void Engine::lstep(Blk in, Blk out, const Blk *A, const Blk *B, double scale, co
   a.st = st_;
   a.rb = rb_;
   a.max_wg = rb_.max_wg;
-  if (cheb()) {
+  if (cheb() || mixed()) {
     a.d0 = p_;
     a.theta_inv = 1.0 / cheb_theta_;
     a.part_rr = rb_.partA;
   }
   launch_stiff(a, s_);
   const int nwg_init = launch_rows_grid(std::max(ne_, nc_), in.Bs);
-  if (cheb())
+  if (mixed())
+    mixed_solve(out.p, in.Bs, colK, kneed, nwg_init);
+  else if (cheb())
     cheb_solve(out.p, in.Bs, colK, kneed, nwg_init);
   else
     cg(out.p, in.Bs, colK, kneed, nwg_init);
@@ -479,13 +563,15 @@ void Engine::nonlinear_block(Blk E, Blk Y, const int *colK) {
   gth.st = st_;
   gth.rb = rb_;
   gth.max_wg = rb_.max_wg;
-  if (cheb()) {
+  if (cheb() || mixed()) {
     gth.d0 = p_;
     gth.theta_inv = 1.0 / cheb_theta_;
     gth.part_rr = rb_.partA;
   }
   launch_nl_gather(gth, s_);
-  if (cheb())
+  if (mixed())
+    mixed_solve(Y.p, E.Bs, colK, 0, launch_rows_grid(ne_, E.Bs));
+  else if (cheb())
     cheb_solve(Y.p, E.Bs, colK, 0, launch_rows_grid(ne_, E.Bs));
   else
     cg(Y.p, E.Bs, colK, 0, launch_rows_grid(ne_, E.Bs));
@@ -730,7 +816,7 @@ void Engine::phase_avg_rhs(const pa_avg *avg, int members, const double *U, doub
     auto itb = ctx_->cg_budget.find(cfg_.cg_rtol);
     if (itb != ctx_->cg_budget.end()) budget = itb->second;
   }
-  if (cfg_.use_graph && (budget > 0 || cheb()) && ctx_->prof_kernel == PA_KERNEL_NONE) {
+  if (cfg_.use_graph && (budget > 0 || cheb() || mixed()) && ctx_->prof_kernel == PA_KERNEL_NONE) {
     GraphKey key;
     key.ops = ops_;
     key.avg = avg;

@@ -100,6 +100,11 @@ class Engine {
   void cg(double *x, int Bs, const int *colK, int kneed, int nwg_init);
   void cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_init);
   bool cheb() const { return cfg_.solver == PA_SOLVER_CHEBYSHEV; }
+  bool mixed() const { return cfg_.precision == PA_FP32_REFINED; }
+  void mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_init);
+  std::vector<double> mix_c1_, mix_c2_;
+  int mixed_outer_ = 0;
+  float *x32_ = nullptr, *r32_ = nullptr, *d32_[2] = {nullptr, nullptr};
   // Chebyshev plan: step coefficients from the spectral bounds
   double cheb_theta_ = 0, cheb_delta_ = 0;
   std::vector<double> cheb_c1_, cheb_c2_;

@@ -90,6 +90,35 @@ struct ChebArgs {
   unsigned *prof;  // measurement hook: [0] active columns, [1] launches, [2] columns of last steps
 };
 
+// FP32 inner Chebyshev step (mixed precision): x32 (+)= d, r32 -= M32 d,
+// d' = c1 d + c2 D^-1 r32, all in FP32.
+struct Cheb32Args {
+  DevOps ops;
+  int Bs;
+  float *x32, *r32;
+  const float *d_in;
+  float *d_out;
+  float c1, c2;
+  const int *colK;
+  int kneed, first, last;
+};
+
+// FP64 refinement: x += x32, r -= M x32 (FP64 matrix), then FP32 copies for
+// the next inner solve: r32 = r, d32 = D^-1 r32 / theta.  first = 1: only the
+// conversion (x32 not yet formed).  last = 1: partials of r.r, no copies.
+struct RefineArgs {
+  DevOps ops;
+  int Bs;
+  double *x, *r;
+  const float *x32;
+  float *r32, *d32;
+  float theta_inv;
+  const int *colK;
+  int kneed, first, last;
+  double *part;
+  int max_wg;
+};
+
 // Residual check after a Chebyshev solve.
 struct CheckArgs {
   int Bs, nwg_init, nwg_last, max_wg;
@@ -188,6 +217,8 @@ void launch_stiff(const StiffArgs &a, hipStream_t s);
 void launch_cg_init(const CgArgs &a, hipStream_t s);
 void launch_cheb_iter(const ChebArgs &a, hipStream_t s);
 void launch_cheb_check(const CheckArgs &a, hipStream_t s);
+void launch_cheb32_iter(const Cheb32Args &a, hipStream_t s);
+void launch_refine(const RefineArgs &a, hipStream_t s);
 void launch_cg_iter(const CgArgs &a, hipStream_t s);
 void launch_combine(const CombineArgs &a, hipStream_t s);
 void launch_reduce_terms(const ReduceTermsArgs &a, hipStream_t s);

@@ -229,6 +229,60 @@ __global__ __launch_bounds__(kWG) void k_cheb_check(CheckArgs a) {
   }
 }
 
+// ----------------------------------- FP32 inner solves, FP64 refinement
+// Mixed-precision mass solve: the correction equation M d = r is solved
+// approximately by the Chebyshev semi-iteration in FP32 (FP32 copy of M,
+// FP32 vectors), the correction is added to x in FP64 and the residual
+// updated with the FP64 matrix, r -= M x32, so the outer residual is a true
+// FP64 residual; a final check compares it with the tolerance.
+__global__ __launch_bounds__(kWG) void k_cheb32_iter(Cheb32Args a) {
+  const Lane L = lane_map(a.Bs, a.ops.ne);
+  const DevOps &o = a.ops;
+  const int c = L.col, Bs = a.Bs;
+  if (a.colK[c] < a.kneed) return;
+  for (int e = L.row0; e < L.rend; e += L.rstride) {
+    float q = 0.0f;
+#pragma unroll
+    for (int j = 0; j < 5; j++) q += o.mass32[5 * e + j] * a.d_in[(size_t)o.ell_col[5 * e + j] * Bs + c];
+    const size_t ie = (size_t)e * Bs + c;
+    const float d = a.d_in[ie];
+    a.x32[ie] = a.first ? d : a.x32[ie] + d;
+    const float r = a.r32[ie] - q;
+    a.r32[ie] = r;
+    if (!a.last) a.d_out[ie] = a.c1 * d + a.c2 * o.dinv32[e] * r;
+  }
+}
+
+__global__ __launch_bounds__(kWG) void k_refine(RefineArgs a) {
+  const Lane L = lane_map(a.Bs, a.ops.ne);
+  const DevOps &o = a.ops;
+  const int c = L.col, Bs = a.Bs;
+  double sums[1] = {0.0};
+  if (a.colK[c] >= a.kneed) {
+    for (int e = L.row0; e < L.rend; e += L.rstride) {
+      const size_t ie = (size_t)e * Bs + c;
+      double r = a.r[ie];
+      if (!a.first) {
+        double q = 0.0;
+#pragma unroll
+        for (int j = 0; j < 5; j++)
+          q += o.mass[5 * e + j] * (double)a.x32[(size_t)o.ell_col[5 * e + j] * Bs + c];
+        a.x[ie] += (double)a.x32[ie];
+        r -= q;
+        a.r[ie] = r;
+      }
+      if (a.last) {
+        sums[0] += r * r;
+      } else {
+        const float r32 = (float)r;
+        a.r32[ie] = r32;
+        a.d32[ie] = a.theta_inv * o.dinv32[e] * r32;
+      }
+    }
+  }
+  if (a.last) wg_partials<1>(L, sums, a.part, a.max_wg);
+}
+
 // -------------------------------------------------- CG (Chronopoulos-Gear)
 // Jacobi-preconditioned CG in the single-reduction form of Chronopoulos and
 // Gear: with u = D^-1 r and w = M u,
@@ -866,6 +920,12 @@ void launch_cheb_check(const CheckArgs &a, hipStream_t s) {
   const int cpb = ct < 4 ? ct : 4;
   const int tiles = (a.Bs + 63) / 64;
   hipLaunchKernelGGL(k_cheb_check, dim3(tiles * (ct / cpb)), dim3(kWG), 0, s, a);
+}
+void launch_cheb32_iter(const Cheb32Args &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_cheb32_iter, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+}
+void launch_refine(const RefineArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_refine, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
 }
 void launch_cg_iter(const CgArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_iter, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);

@@ -51,12 +51,14 @@ def test_level6_full_average_properties(l6):
     avg = pa.Avg(64, 7200.0)
     Ud = to_dev(mm.state(U)[None])
     res = {}
-    for name, bw, solver, graph in [("clenshaw_cheb_graph", 1, 1, True),
-                                    ("clenshaw_cheb", 1, 1, False),
-                                    ("per_term_cheb", 0, 1, False),
-                                    ("clenshaw_cg", 1, 0, False)]:
+    for name, bw, solver, graph, prec in [("clenshaw_cheb_graph", 1, 1, True, 0),
+                                          ("clenshaw_cheb", 1, 1, False, 0),
+                                          ("per_term_cheb", 0, 1, False, 0),
+                                          ("clenshaw_cg", 1, 0, False, 0),
+                                          ("clenshaw_fp32_refined", 1, 1, False, 1),
+                                          ("per_term_fp32_refined", 0, 1, False, 1)]:
         cfg = pa.solve_cfg(backward=bw, solver=solver, cheb_tol=1e-6, cg_rtol=1e-10,
-                           use_graph=graph)
+                           use_graph=graph, precision=prec)
         out = torch.empty_like(Ud)
         for _ in range(2 if graph else 1):
             lo.phase_avg_rhs(avg, Ud, cfg, out=out)
