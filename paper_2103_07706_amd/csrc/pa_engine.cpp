@@ -222,7 +222,7 @@ void Engine::plan_common(int BsMax) {
   st_.it2 = ar_.take<int>(8);
   rb_.max_wg = launch_max_wg();
   rb_.partA = ar_.take<double>((size_t)tiles * rb_.max_wg * 3 * 64);
-  rb_.partB = ar_.take<double>((size_t)tiles * rb_.max_wg * 3 * 64);
+  rb_.partB = ar_.take<double>((size_t)tiles * rb_.max_wg * 5 * 64);
   // counters, cleared at the start of each call
   zero_words_ = 64;
   zero_base_ = ar_.take<unsigned>(zero_words_);
@@ -301,13 +301,23 @@ void Engine::finish() {
   if (learn_budget_) ctx_->cg_budget[cfg_.cg_rtol] = std::min(cfg_.maxit, h[1] + 2);
 }
 
-void Engine::wdot_out(int Bs, double *out) {
+// Diagnostics of every column of X into out[5][Bs] (see k_diag).
+void Engine::diag(Blk X, double *out) {
+  DiagArgs d{};
+  d.ops = ops_->d;
+  d.Bs = X.Bs;
+  d.H = ops_->H;
+  d.u = X.p;
+  d.eta = X.p + (size_t)ne_ * X.Bs;
+  d.part = rb_.partB;
+  d.max_wg = rb_.max_wg;
+  launch_diag(d, s_);
   FinArgs f{};
   f.mode = FIN_OUT;
-  f.Bs = Bs;
-  f.nwg = launch_rows_grid(std::max(ne_, nc_), Bs);
+  f.Bs = X.Bs;
+  f.nwg = launch_rows_grid(std::max(ne_, nc_), X.Bs);
   f.max_wg = rb_.max_wg;
-  f.nq = 2;
+  f.nq = 5;
   f.part = rb_.partB;
   f.st = st_;
   f.out = out;
@@ -788,35 +798,53 @@ void Engine::run_nbar(NbarBufs &nb, Blk X, Blk out, bool uploaded) {
   }
 }
 
-void Engine::phase_avg_rhs(const pa_avg *avg, int members, const double *U, double *Nbar) {
+void Engine::nbar_plan(NbarCall &c, const pa_avg *avg, int members, const double *U,
+                       double *Nbar) {
   if (members <= 0) throw Error(PA_EINVAL, "members must be positive");
-  NbarBufs nb;
-  plan_nbar(nb, avg, members);  // sizes first (needs G, BsE)
-  plan_common(nb.BsE);
-  ut0_ = ar_.take<double>((size_t)ne_ * nb.BsE);
-  ut1_ = ar_.take<double>((size_t)ne_ * nb.BsE);
-  C_ = ar_.take<double>((size_t)3 * nc_ * nb.BsE);
-  Blk X = block(nb.Bm), out = block(nb.Bm);
-  if (ar_.sizing()) return;
+  c.avg = avg;
+  c.members = members;
+  c.U = U;
+  c.Nbar = Nbar;
+  plan_nbar(c.nb, avg, members);  // sizes first (needs G, BsE)
+  plan_common(c.nb.BsE);
+  ut0_ = ar_.take<double>((size_t)ne_ * c.nb.BsE);
+  ut1_ = ar_.take<double>((size_t)ne_ * c.nb.BsE);
+  C_ = ar_.take<double>((size_t)3 * nc_ * c.nb.BsE);
+  c.X = block(c.nb.Bm);
+  c.out = block(c.nb.Bm);
+}
+
+void Engine::nbar_begin(NbarCall &c) {
   begin();
-  upload_nbar(nb);
-  auto body = [&] {
-    TransArgs tr{n_, members, nb.Bm, const_cast<double *>(U), X.p};
-    launch_to_block(tr, s_);
-    run_nbar(nb, X, out, true);
-    TransArgs tb{n_, members, nb.Bm, Nbar, out.p};
-    launch_from_block(tb, s_);
-  };
-  // Graph replay: with an iteration budget the whole call is a fixed kernel
-  // sequence with no host synchronisation, so it is captured once (on the
-  // context's own capture stream) and replayed while nothing it depends on
-  // changes.
-  int budget = 0;
-  if (budget_ok_) {
-    auto itb = ctx_->cg_budget.find(cfg_.cg_rtol);
-    if (itb != ctx_->cg_budget.end()) budget = itb->second;
-  }
-  if (cfg_.use_graph && (budget > 0 || cheb() || mixed()) && ctx_->prof_kernel == PA_KERNEL_NONE) {
+  upload_nbar(c.nb);
+}
+
+void Engine::nbar_body(NbarCall &c) {
+  TransArgs tr{n_, c.members, c.nb.Bm, const_cast<double *>(c.U), c.X.p};
+  launch_to_block(tr, s_);
+  run_nbar(c.nb, c.X, c.out, true);
+  TransArgs tb{n_, c.members, c.nb.Bm, c.Nbar, c.out.p};
+  launch_from_block(tb, s_);
+}
+
+// A call is a fixed kernel sequence with no host synchronisation when the
+// mass solves need no polling (Chebyshev, mixed, or a known CG budget).
+int Engine::current_budget() const {
+  if (!budget_ok_) return 0;
+  auto itb = ctx_->cg_budget.find(cfg_.cg_rtol);
+  return itb != ctx_->cg_budget.end() ? itb->second : 0;
+}
+
+bool Engine::sync_free() const { return current_budget() > 0 || cheb() || mixed(); }
+
+void Engine::phase_avg_rhs(const pa_avg *avg, int members, const double *U, double *Nbar) {
+  NbarCall c;
+  nbar_plan(c, avg, members, U, Nbar);
+  if (ar_.sizing()) return;
+  nbar_begin(c);
+  // Graph replay: a sync-free call is captured once (on the context's own
+  // capture stream) and replayed while nothing it depends on changes.
+  if (cfg_.use_graph && sync_free() && ctx_->prof_kernel == PA_KERNEL_NONE) {
     GraphKey key;
     key.ops = ops_;
     key.avg = avg;
@@ -824,13 +852,13 @@ void Engine::phase_avg_rhs(const pa_avg *avg, int members, const double *U, doub
     key.in = U;
     key.out = Nbar;
     key.ws = ws_base_;
-    key.budget = budget;
+    key.budget = current_budget();
     key.lambda_bar = ops_->lambda_bar;
     key.cfg = cfg_;
     key.tune = launch_tuning();
-    run_graph(key, body);
+    run_graph(key, [&] { nbar_body(c); });
   } else {
-    body();
+    nbar_body(c);
   }
   finish();
 }
@@ -930,7 +958,7 @@ void Engine::step(const pa_avg *avg, double dt, int members, double *U) {
 double Engine::estimate_lambda(int iters) {
   plan_common(1);
   Blk v = block(1), a = block(1), b = block(1);
-  double *wd = ar_.take<double>(2);
+  double *wd = ar_.take<double>(5);
   if (ar_.sizing()) return 0.0;
   begin();
   // start vector from a counter hash (SplitMix64 of the index), in [-1, 1)
@@ -944,23 +972,11 @@ double Engine::estimate_lambda(int iters) {
   }
   upload(v.p, h.data(), sizeof(double) * n_);
   auto wnorm2 = [&](Blk x) {
-    WdotArgs w{};
-    w.ops = ops_->d;
-    w.Bs = 1;
-    w.H = ops_->H;
-    w.g = ops_->g;
-    w.xu = x.p;
-    w.xe = x.p + ne_;
-    w.yu = x.p;
-    w.ye = x.p + ne_;
-    w.out = wd;
-    w.rb = rb_;
-    launch_wdot(w, s_);
-    wdot_out(1, wd);
-    double hv[2];
-    PA_HIP(hipMemcpyAsync(hv, wd, 2 * sizeof(double), hipMemcpyDeviceToHost, s_));
+    diag(x, wd);
+    double hv[5];
+    PA_HIP(hipMemcpyAsync(hv, wd, 5 * sizeof(double), hipMemcpyDeviceToHost, s_));
     PA_HIP(hipStreamSynchronize(s_));
-    return hv[0];
+    return ops_->H * hv[0] + ops_->g * hv[2];
   };
   double rho2 = 0.0;
   for (int it = 0; it < iters; it++) {
@@ -979,33 +995,24 @@ void Engine::diagnostics(int B, const double *U, double *out_host) {
   const int Bs = pad_cols(B);
   plan_common(Bs);
   Blk X = block(Bs);
-  double *wd = ar_.take<double>(2 * (size_t)Bs);
+  double *wd = ar_.take<double>(5 * (size_t)Bs);
   if (ar_.sizing()) return;
   begin();
   TransArgs tr{n_, B, Bs, const_cast<double *>(U), X.p};
   launch_to_block(tr, s_);
-  WdotArgs w{};
-  w.ops = ops_->d;
-  w.Bs = Bs;
-  w.H = ops_->H;
-  w.g = ops_->g;
-  w.xu = X.p;
-  w.xe = X.p + (size_t)ne_ * Bs;
-  w.yu = X.p;
-  w.ye = X.p + (size_t)ne_ * Bs;
-  w.out = wd;
-  w.rb = rb_;
-  launch_wdot(w, s_);
-  wdot_out(Bs, wd);
-  std::vector<double> h(2 * (size_t)Bs);
+  diag(X, wd);
+  std::vector<double> h(5 * (size_t)Bs);
   PA_HIP(hipMemcpyAsync(h.data(), wd, h.size() * sizeof(double), hipMemcpyDeviceToHost, s_));
   finish();
+  const double H = ops_->H, g = ops_->g;
   for (int j = 0; j < B; j++) {
-    out_host[5 * j + 0] = h[Bs + j];
-    out_host[5 * j + 1] = 0.5 * h[j];
-    out_host[5 * j + 2] = NAN;
-    out_host[5 * j + 3] = NAN;
-    out_host[5 * j + 4] = NAN;
+    const double uMu = h[j], mass = h[Bs + j], e2 = h[2 * Bs + j], div2 = h[3 * Bs + j];
+    const double ke = h[4 * Bs + j];
+    out_host[5 * j + 0] = mass;
+    out_host[5 * j + 1] = 0.5 * (H * uMu + g * e2);
+    out_host[5 * j + 2] = ke + 0.5 * g * e2;
+    out_host[5 * j + 3] = std::sqrt(uMu + div2);
+    out_host[5 * j + 4] = std::sqrt(e2);
   }
 }
 

@@ -80,6 +80,7 @@ class Engine {
   void diagnostics(int B, const double *U, double *out_host);
 
   size_t used() const { return ar_.used(); }
+
   // allow the learned CG iteration budget (no host polling) for this call
   // use: launch the learned budget without polling; learn: record the
   // largest iteration count of this call as the next budget
@@ -93,7 +94,6 @@ class Engine {
   struct NbarPlan;
   void plan_common(int BsMax);
   void begin();
-  void finish();
   Blk block(int Bs);
   void lstep(Blk in, Blk out, const Blk *A, const Blk *B, double scale, const int *colK,
              int kneed, const AccSpec *acc);
@@ -115,10 +115,11 @@ class Engine {
             const double *x1 = nullptr, double a2 = 0, const double *x2 = nullptr);
   void upload(void *dst, const void *src, size_t bytes);
   hipEvent_t take_event();
-  void wdot_out(int Bs, double *out);
+  void diag(Blk X, double *out);
   std::vector<hipEvent_t> prof_ev_;
 
   // phase average on a block of member columns X -> out (both [n][Bm])
+ public:
   struct NbarBufs {
     int members = 0, Bm = 0, G = 0, BsE = 0, kmax = 0, M = 0;
     double *basis = nullptr, *E = nullptr, *Y = nullptr, *W = nullptr, *Z = nullptr;
@@ -129,6 +130,27 @@ class Engine {
     std::vector<int> hcolK_E, hcolK_fwd, hcolK_mem;
     int ksum = 0;
   };
+  struct NbarCall {
+    NbarBufs nb;
+    Blk X, out;
+    const pa_avg *avg = nullptr;
+    int members = 0;
+    const double *U = nullptr;
+    double *Nbar = nullptr;
+  };
+  // averaged RHS in pieces (used by batches of problems): plan the
+  // workspace, enqueue the set-up on the caller's stream, enqueue the kernel
+  // sequence on the engine's current stream, then finish()
+  void nbar_plan(NbarCall &c, const pa_avg *avg, int members, const double *U, double *Nbar);
+  void nbar_begin(NbarCall &c);
+  void nbar_body(NbarCall &c);
+  void finish();
+  bool sync_free() const;
+  int current_budget() const;
+  void set_stream(hipStream_t s) { s_ = s; }
+  hipStream_t stream() const { return s_; }
+
+ private:
   void plan_nbar(NbarBufs &nb, const pa_avg *avg, int members);
   void upload_nbar(NbarBufs &nb);
   void run_nbar(NbarBufs &nb, Blk X, Blk out, bool uploaded);

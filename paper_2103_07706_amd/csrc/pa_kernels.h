@@ -199,13 +199,13 @@ struct TransArgs {
   double *states, *blk;
 };
 
-struct WdotArgs {
+struct DiagArgs {
   DevOps ops;
   int Bs;
-  double H, g;
-  const double *xu, *xe, *yu, *ye;
-  double *out;  // [2][Bs]
-  RedBuf rb;
+  double H;
+  const double *u, *eta;
+  double *part;
+  int max_wg;
 };
 
 int launch_max_wg();
@@ -229,7 +229,7 @@ void launch_acc(const AccArgs &a, hipStream_t s);
 void launch_axpy(const AxpyArgs &a, hipStream_t s);
 void launch_to_block(const TransArgs &a, hipStream_t s);
 void launch_from_block(const TransArgs &a, hipStream_t s);
-void launch_wdot(const WdotArgs &a, hipStream_t s);
+void launch_diag(const DiagArgs &a, hipStream_t s);
 void launch_zero(unsigned *p, size_t n, hipStream_t s);
 
 }  // namespace pa

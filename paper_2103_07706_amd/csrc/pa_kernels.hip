@@ -74,8 +74,8 @@ __device__ void wg_partials(const Lane &L, double (&v)[NQ], double *part, int ma
     if (L.lane < L.ct) red[q][L.wave][L.lane] = s;
   }
   __syncthreads();
-  if (threadIdx.x < NQ * 64) {
-    const int q = threadIdx.x / 64, c = threadIdx.x % 64;
+  for (int idx = threadIdx.x; idx < NQ * 64; idx += kWG) {
+    const int q = idx / 64, c = idx % 64;
     if (c < L.ct) {
       double s = 0;
       for (int w = 0; w < kWG / 64; w++) s += red[q][w][c];
@@ -769,27 +769,52 @@ __global__ __launch_bounds__(kWG) void k_from_block(TransArgs a) {
   }
 }
 
-// Per-column energy inner products <X, Y>_W = H x_u' M y_u + g sum |c| x_eta y_eta
-// and the mass sum |c| x_eta, reduced deterministically into out[3][Bs].
-__global__ __launch_bounds__(kWG) void k_wdot(WdotArgs a) {
+// Per-column diagnostics, reduced deterministically (finalize FIN_OUT):
+//   q0 = u' M u, q1 = sum |c| eta, q2 = sum |c| eta^2, q3 = sum (D u)^2 / |c|,
+//   q4 = sum_c (H + eta - b) int_c |u|^2 / 2   (RT0 velocity, side midpoints).
+__global__ __launch_bounds__(kWG) void k_diag(DiagArgs a) {
   const Lane L = lane_map(a.Bs, a.ops.ne > a.ops.nc ? a.ops.ne : a.ops.nc);
   const DevOps &o = a.ops;
   const int c = L.col, Bs = a.Bs;
-  double sums[2] = {0.0, 0.0};
+  double sums[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   for (int r = L.row0; r < L.rend; r += L.rstride) {
     if (r < o.ne) {
-      double my = 0.0;
+      double mu = 0.0;
 #pragma unroll
-      for (int j = 0; j < 5; j++) my += o.mass[5 * r + j] * a.yu[(size_t)o.ell_col[5 * r + j] * Bs + c];
-      sums[0] += a.H * a.xu[(size_t)r * Bs + c] * my;
+      for (int j = 0; j < 5; j++) mu += o.mass[5 * r + j] * a.u[(size_t)o.ell_col[5 * r + j] * Bs + c];
+      sums[0] += a.u[(size_t)r * Bs + c] * mu;
     }
     if (r < o.nc) {
-      const size_t it = (size_t)r * Bs + c;
-      sums[0] += a.g * o.area[r] * a.xe[it] * a.ye[it];
-      sums[1] += o.area[r] * a.xe[it];
+      const double A = o.area[r], eta = a.eta[(size_t)r * Bs + c];
+      sums[1] += A * eta;
+      sums[2] += A * eta * eta;
+      const double *g = o.cgeo + (size_t)r * kCellGeo;
+      double U[3], div = 0.0;
+#pragma unroll
+      for (int j = 0; j < 3; j++) {
+        U[j] = o.csgn[3 * r + j] * a.u[(size_t)o.cedge[3 * r + j] * Bs + c];
+        div += U[j];
+      }
+      sums[3] += div * div / A;
+      double ke = 0.0;
+#pragma unroll
+      for (int q = 0; q < 3; q++) {
+        double u2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < 3; d++) {
+          const double x = 0.5 * (g[3 * ((q + 1) % 3) + d] + g[3 * ((q + 2) % 3) + d]);
+          double v = 0.0;
+#pragma unroll
+          for (int j = 0; j < 3; j++) v += U[j] * (x - g[3 * j + d]);
+          v *= 0.5 / A;
+          u2 += v * v;
+        }
+        ke += (A / 3.0) * 0.5 * u2;
+      }
+      sums[4] += (a.H + eta - o.bottom[r]) * ke;
     }
   }
-  wg_partials<2>(L, sums, a.rb.partB, a.rb.max_wg);
+  wg_partials<5>(L, sums, a.part, a.max_wg);
 }
 
 // Clear small integer/double buffers (used instead of memset so that the
@@ -818,7 +843,7 @@ __global__ __launch_bounds__(kWG) void k_finalize(FinArgs a) {
   const int cl = (blockIdx.x % blocks_per_tile) * cpb + wave;  // column in tile
   if (wave >= cpb) return;
   const int c = tile * ct + cl;
-  double v[3] = {0.0, 0.0, 0.0};
+  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int w = lane; w < a.nwg; w += 64)
     for (int q = 0; q < a.nq; q++)
       v[q] += a.part[(((size_t)tile * a.max_wg + w) * a.nq + q) * 64 + cl];
@@ -857,8 +882,7 @@ __global__ __launch_bounds__(kWG) void k_finalize(FinArgs a) {
       atomicMax(st.iter_max, it);
     }
   } else {
-    a.out[c] = v[0];
-    a.out[a.Bs + c] = v[1];
+    for (int q = 0; q < a.nq; q++) a.out[q * a.Bs + c] = v[q];
   }
   if (on) atomicAdd(&st.cnt[a.slot_out], 1);
 }
@@ -957,9 +981,9 @@ void launch_to_block(const TransArgs &a, hipStream_t s) {
 void launch_from_block(const TransArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_from_block, dim3(grid_flat((size_t)a.n * a.B)), dim3(kWG), 0, s, a);
 }
-void launch_wdot(const WdotArgs &a, hipStream_t s) {
+void launch_diag(const DiagArgs &a, hipStream_t s) {
   const int nrow = a.ops.ne > a.ops.nc ? a.ops.ne : a.ops.nc;
-  hipLaunchKernelGGL(k_wdot, rows_grid(nrow, a.Bs), dim3(kWG), 0, s, a);
+  hipLaunchKernelGGL(k_diag, rows_grid(nrow, a.Bs), dim3(kWG), 0, s, a);
 }
 void launch_finalize(const FinArgs &a, hipStream_t s) {
   const int ct = a.Bs < 64 ? a.Bs : 64;

@@ -111,10 +111,11 @@ def test_gpu_diagnostics_mass_energy():
     om, oo, lm, lo, mm, lb = pair(3)
     U = bumps(om, [0, 1])
     d = lo.diagnostics(to_dev(mm.state(U)))
+    keys = ["mass", "energy_linear", "energy_nonlinear", "hdiv_u", "l2_eta"]
     for j in range(2):
         ref = oo.diagnostics(U[j])
-        assert abs(d[j, 0] / ref["mass"] - 1) < 1e-13
-        assert abs(d[j, 1] / ref["energy_linear"] - 1) < 1e-13
+        for q, k in enumerate(keys):
+            assert abs(d[j, q] / ref[k] - 1) < 1e-13, (k, d[j, q], ref[k])
 
 
 @pytest.mark.parametrize("B", [1, 2, 3, 4, 5, 64, 65])
