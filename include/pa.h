@@ -250,6 +250,50 @@ int pa_autotune(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int members,
                 size_t ws_bytes, const pa_solve_cfg *cfg, pa_launch_tune *out);
 int pa_ctx_profile_read(pa_ctx *ctx, pa_kernel_profile *out);
 
+
+/* ---- batches of problems -------------------------------------------------
+ * Independent problems evaluated together (the terms of the average are
+ * independent, Sec. 2.2, and were spread over an ensemble of processes,
+ * end of Sec. 2.5; members and meshes are independent too): a batch holds
+ * n_items averaged right-hand-side problems, item i being `members[i]`
+ * states on the operators `ops[i]` (meshes may differ), all with the same
+ * averaging nodes `avg`.  pa_batch_run evaluates Nbar for every item:
+ * U_dev[i] and Nbar_dev[i] are FP64 device arrays [members[i]][n_i] as in
+ * pa_phase_avg_rhs.
+ *
+ * Execution: when no mass solve needs host polling (Chebyshev or mixed
+ * precision solver, or a learned CG budget), the items run concurrently on
+ * streams owned by the batch, joined back into the context stream; with
+ * cfg->use_graph the whole batch is captured on the first run into one HIP
+ * graph and replayed on later runs with the same pointers, configuration,
+ * operators and launch shapes (any change recaptures).  Otherwise the items
+ * run one after another on the context stream.  Each item uses its own
+ * launch shape (pa_batch_set_tune / pa_batch_autotune), default the
+ * process-wide one.
+ *
+ * Workspace: pa_batch_workspace_size gives the bytes for `cfg`, the items
+ * carved one after another (256-byte aligned).  The batch does not own the
+ * operators or the averaging nodes, which must outlive it.  `stats` (may be
+ * NULL) receives n_items entries.  Errors as pa_phase_avg_rhs; calls on one
+ * batch are not thread-safe. */
+typedef struct pa_batch pa_batch;
+int pa_batch_create(int n_items, const pa_ops *const *ops, const int *members,
+                    const pa_avg *avg, pa_batch **out);
+int pa_batch_workspace_size(const pa_batch *b, const pa_solve_cfg *cfg, size_t *bytes);
+int pa_batch_run(pa_ctx *ctx, pa_batch *b, const double *const *U_dev,
+                 double *const *Nbar_dev, void *ws_dev, size_t ws_bytes,
+                 const pa_solve_cfg *cfg, pa_stats *stats);
+/* Launch shape of one item (best_ms ignored). */
+int pa_batch_set_tune(pa_batch *b, int item, const pa_launch_tune *t);
+int pa_batch_get_tune(const pa_batch *b, int item, pa_launch_tune *out);
+/* Times each item alone over the launch shapes of pa_autotune (outputs must
+ * not alias inputs) and keeps each item's fastest; out (may be NULL)
+ * receives n_items entries.  The process-wide shape is left unchanged. */
+int pa_batch_autotune(pa_ctx *ctx, pa_batch *b, const double *const *U_dev,
+                      double *const *Nbar_dev, void *ws_dev, size_t ws_bytes,
+                      const pa_solve_cfg *cfg, pa_launch_tune *out);
+int pa_batch_destroy(pa_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -5,28 +5,15 @@
 
 #include "pa_engine.h"
 
-namespace {
-thread_local std::string g_err;
-
-template <class F>
-int guard(F &&f) {
-  try {
-    f();
-    return PA_OK;
-  } catch (const pa::Error &e) {
-    g_err = e.what();
-    return e.code;
-  } catch (const std::bad_alloc &) {
-    g_err = "host out of memory";
-    return PA_ENOMEM;
-  } catch (const std::exception &e) {
-    g_err = e.what();
-    return PA_EINVAL;
-  } catch (...) {
-    g_err = "unknown error";
-    return PA_EINVAL;
-  }
+namespace pa {
+std::string &last_error() {
+  thread_local std::string msg;
+  return msg;
 }
+}  // namespace pa
+
+namespace {
+using pa::guard;
 
 void need(bool ok, const char *msg) {
   if (!ok) throw pa::Error(PA_EINVAL, msg);
@@ -37,7 +24,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 extern "C" {
 
-const char *pa_last_error(void) { return g_err.c_str(); }
+const char *pa_last_error(void) { return pa::last_error().c_str(); }
 
 int pa_ctx_create(int device, void *stream, pa_ctx **out) {
   return guard([&] {

@@ -44,6 +44,11 @@ Engine::Engine(pa_ctx *ctx, const pa_ops *ops, const pa_solve_cfg &cfg, void *ws
   if (cheb() || mixed()) plan_cheb();
 }
 
+Engine::~Engine() {
+  if (ev0_) (void)hipEventDestroy(ev0_);
+  if (ev1_) (void)hipEventDestroy(ev1_);
+}
+
 // Chebyshev semi-iteration on D^-1 M over [a, b] = Lanczos bounds widened
 // by 5% below and 2% above; the number of steps makes the Chebyshev error
 // factor 1/T_k(theta/delta) reach cg_rtol, plus two.

@@ -70,6 +70,9 @@ struct ChebPlan {
 class Engine {
  public:
   Engine(pa_ctx *ctx, const pa_ops *ops, const pa_solve_cfg &cfg, void *ws, size_t ws_bytes);
+  ~Engine();
+  Engine(const Engine &) = delete;
+  Engine &operator=(const Engine &) = delete;
 
   // planning + execution of the public calls (plan only when sizing)
   void expL_apply(int B, const double *t, const double *Uin, double *Uout);

@@ -5,6 +5,7 @@
 #include <cstddef>
 #include <cstring>
 #include <map>
+#include <new>
 #include <cstdint>
 #include <stdexcept>
 #include <string>
@@ -19,6 +20,30 @@ struct Error : std::runtime_error {
   int code;
   Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
 };
+
+// Thread-local message returned by pa_last_error.
+std::string &last_error();
+
+// Runs f, turning any exception into a status code and the error message.
+template <class F>
+int guard(F &&f) {
+  try {
+    f();
+    return PA_OK;
+  } catch (const Error &e) {
+    last_error() = e.what();
+    return e.code;
+  } catch (const std::bad_alloc &) {
+    last_error() = "host out of memory";
+    return PA_ENOMEM;
+  } catch (const std::exception &e) {
+    last_error() = e.what();
+    return PA_EINVAL;
+  } catch (...) {
+    last_error() = "unknown error";
+    return PA_EINVAL;
+  }
+}
 
 #define PA_HIP(call)                                                          \
   do {                                                                        \

@@ -19,7 +19,6 @@
 namespace pa {
 
 constexpr int kWG = 256;
-constexpr int kGroup = 32;
 
 struct Lane {
   int ct, rw, col, tile, row0, rstride, rend, lane, wave;

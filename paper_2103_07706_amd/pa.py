@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libpa.so")
 PA_FP64, PA_FP32_REFINED = 0, 1
 PA_BACKWARD_PER_TERM, PA_BACKWARD_CLENSHAW = 0, 1
 PA_SOLVER_CG, PA_SOLVER_CHEBYSHEV = 0, 1
+PA_OK, PA_EINVAL, PA_ENOMEM, PA_EHIP, PA_ENOCONV, PA_ENOTSUP, PA_EGROWTH = range(7)
 _STATUS = {0: "PA_OK", 1: "PA_EINVAL", 2: "PA_ENOMEM", 3: "PA_EHIP", 4: "PA_ENOCONV",
            5: "PA_ENOTSUP", 6: "PA_EGROWTH"}
 
@@ -117,6 +118,16 @@ EXPORTS = {
     "pa_set_launch_tune": (ctypes.c_int, [ctypes.POINTER(LaunchTune)]),
     "pa_autotune": (ctypes.c_int, [_V, _V, _V, ctypes.c_int, _V, _V, _V, _SZ,
                                    ctypes.POINTER(SolveCfg), ctypes.POINTER(LaunchTune)]),
+    "pa_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_V), _I, _V,
+                                       ctypes.POINTER(_V)]),
+    "pa_batch_workspace_size": (ctypes.c_int, [_V, ctypes.POINTER(SolveCfg), ctypes.POINTER(_SZ)]),
+    "pa_batch_run": (ctypes.c_int, [_V, _V, ctypes.POINTER(_V), ctypes.POINTER(_V), _V, _SZ,
+                                    ctypes.POINTER(SolveCfg), ctypes.POINTER(Stats)]),
+    "pa_batch_set_tune": (ctypes.c_int, [_V, ctypes.c_int, ctypes.POINTER(LaunchTune)]),
+    "pa_batch_get_tune": (ctypes.c_int, [_V, ctypes.c_int, ctypes.POINTER(LaunchTune)]),
+    "pa_batch_autotune": (ctypes.c_int, [_V, _V, ctypes.POINTER(_V), ctypes.POINTER(_V), _V, _SZ,
+                                         ctypes.POINTER(SolveCfg), ctypes.POINTER(LaunchTune)]),
+    "pa_batch_destroy": (ctypes.c_int, [_V]),
 }
 
 
@@ -398,4 +409,99 @@ class Ops:
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
             _lib.pa_ops_destroy(self._h)
+            self._h = None
+
+
+class Batch:
+    """Several averaged right-hand-side problems (meshes and ensembles) run
+    together (pa_batch_*): items[i] = (ops, members)."""
+
+    def __init__(self, ctx: Context, items, avg: Avg):
+        self.ctx, self.avg = ctx, avg
+        self.items = list(items)
+        n = len(self.items)
+        self._ops = [o for o, _ in self.items]  # keep the operators alive
+        opsv = (_V * n)(*[o._h for o in self._ops])
+        mem = np.ascontiguousarray([m for _, m in self.items], np.int32)
+        h = _V()
+        _check(lib().pa_batch_create(n, opsv, mem.ctypes.data_as(_I), avg._h, ctypes.byref(h)))
+        self._h = h
+        self._ws = None
+
+    def __len__(self):
+        return len(self.items)
+
+    def workspace(self, cfg=None):
+        import torch
+        cfg = cfg or solve_cfg()
+        sz = _SZ()
+        _check(lib().pa_batch_workspace_size(self._h, ctypes.byref(cfg), ctypes.byref(sz)))
+        if self._ws is None or self._ws.numel() < sz.value + 256:
+            self._ws = None
+            self._ws = torch.empty(sz.value + 256, dtype=torch.uint8,
+                                   device=f"cuda:{self.ctx.device}")
+        base = self._ws.data_ptr()
+        off = (-base) % 256
+        return _V(base + off), self._ws.numel() - off
+
+    def _ptrs(self, Us, outs):
+        n = len(self.items)
+        if len(Us) != n or len(outs) != n:
+            raise ValueError(f"need {n} inputs and outputs")
+        for (o, m), U, out in zip(self.items, Us, outs):
+            if tuple(U.shape) != (m, o.n) or tuple(out.shape) != (m, o.n):
+                raise ValueError(f"state shape must be ({m}, {o.n})")
+        return (_V * n)(*[U.data_ptr() for U in Us]), (_V * n)(*[x.data_ptr() for x in outs])
+
+    def run(self, Us, cfg=None, outs=None):
+        """Nbar of every item; returns (outputs, per-item stats)."""
+        cfg = cfg or solve_cfg()
+        outs = [U.new_empty(U.shape) for U in Us] if outs is None else outs
+        up, op = self._ptrs(Us, outs)
+        ws, nb = self.workspace(cfg)
+        st = (Stats * len(self.items))()
+        _check(lib().pa_batch_run(self.ctx._h, self._h, up, op, ws, nb, ctypes.byref(cfg), st))
+        return outs, [s.as_dict() for s in st]
+
+    def set_tune(self, item, narrow_rows_per_thread, wide_max_wg):
+        t = LaunchTune(narrow_rows_per_thread, wide_max_wg, 0.0)
+        _check(lib().pa_batch_set_tune(self._h, item, ctypes.byref(t)))
+
+    def get_tune(self, item):
+        t = LaunchTune()
+        _check(lib().pa_batch_get_tune(self._h, item, ctypes.byref(t)))
+        return {"narrow_rows_per_thread": t.narrow_rows_per_thread, "wide_max_wg": t.wide_max_wg}
+
+    def autotune(self, Us, cfg=None, cache=None):
+        """Per-item launch shapes (pa_batch_autotune).  With a JSON cache, an
+        item whose key (level, members, M, configuration) is stored takes the
+        stored shape; the others are searched and stored."""
+        import json
+        cfg = cfg or solve_cfg()
+        keys = [f"level{o.mesh.level}_members{m}_M{self.avg.M}_rtol{cfg.cg_rtol:g}_"
+                f"tol{cfg.cheb_tol:g}_bw{cfg.backward}_prec{cfg.precision}_"
+                f"solver{cfg.solver}_batch" for o, m in self.items]
+        table = {}
+        if cache and os.path.exists(cache):
+            table = json.load(open(cache))
+        if all(k in table for k in keys):
+            for i, k in enumerate(keys):
+                self.set_tune(i, table[k]["narrow_rows_per_thread"], table[k]["wide_max_wg"])
+            return [dict(table[k], cached=True) for k in keys]
+        outs = [U.new_empty(U.shape) for U in Us]
+        up, op = self._ptrs(Us, outs)
+        ws, nb = self.workspace(cfg)
+        t = (LaunchTune * len(self.items))()
+        _check(lib().pa_batch_autotune(self.ctx._h, self._h, up, op, ws, nb, ctypes.byref(cfg), t))
+        res = [{"narrow_rows_per_thread": x.narrow_rows_per_thread, "wide_max_wg": x.wide_max_wg,
+                "best_ms": x.best_ms} for x in t]
+        if cache:
+            table.update(dict(zip(keys, res)))
+            with open(cache, "w") as f:
+                json.dump(table, f, indent=1)
+        return [dict(r, cached=False) for r in res]
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.pa_batch_destroy(self._h)
             self._h = None
