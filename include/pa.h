@@ -146,7 +146,17 @@ typedef struct {
                           products, step count fixed by the bounds, final FP64
                           residual checked against cg_rtol; a failed check
                           repeats the call with CG) */
+  int32_t precond;     /* PA_PRECOND_JACOBI, or PA_PRECOND_LEARNED: the
+                          Chebyshev mass solves (solver PA_SOLVER_CHEBYSHEV,
+                          precision PA_FP64) use the learned P = G G^T bound
+                          to the operators (pa_ops_lp_attach + pa_ops_lp_bind;
+                          PA_EINVAL if none is bound) over the Ritz bounds of
+                          P M, unless those bounds need at least as many
+                          steps as Jacobi, in which case Jacobi is used.  The
+                          final FP64 residual check and its CG repeat are as
+                          for Jacobi.  CG and FP32-refined solves use Jacobi. */
 } pa_solve_cfg;
+enum { PA_PRECOND_JACOBI = 0, PA_PRECOND_LEARNED = 1 };
 enum { PA_SOLVER_CG = 0, PA_SOLVER_CHEBYSHEV = 1 };
 void pa_solve_cfg_default(pa_solve_cfg *cfg);
 
@@ -164,6 +174,7 @@ typedef struct {
   double device_ms;      /* device time of the call */
   int32_t graph;         /* 1 if the call ran as a graph replay or capture */
   int32_t budget;        /* CG iterations per solve launched (0: polled) */
+  int32_t precond;       /* preconditioner the Chebyshev solves used */
 } pa_stats;
 
 /* Device workspace bytes for calls on 'batch' states (expL_apply,
@@ -214,7 +225,8 @@ int pa_diagnostics(pa_ctx *ctx, const pa_ops *ops, int B, const double *U_dev,
  * pa_ctx_profile starts a new tally (PA_KERNEL_NONE switches it off);
  * pa_ctx_profile_read returns the tally so far.  The calls made while the
  * hook is on fill it; reading needs no further synchronisation. */
-enum { PA_KERNEL_NONE = 0, PA_KERNEL_CG_ITER = 1, PA_KERNEL_CHEB_ITER = 2 };
+enum { PA_KERNEL_NONE = 0, PA_KERNEL_CG_ITER = 1, PA_KERNEL_CHEB_ITER = 2,
+       PA_KERNEL_CHEB_LP_ITER = 3 };
 typedef struct {
   int64_t launches;   /* launches of the kernel */
   int64_t work_launches; /* launches that found active columns */
@@ -250,6 +262,89 @@ int pa_autotune(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int members,
                 size_t ws_bytes, const pa_solve_cfg *cfg, pa_launch_tune *out);
 int pa_ctx_profile_read(pa_ctx *ctx, pa_kernel_profile *out);
 
+
+/* ---- learned mass-matrix preconditioner -----------------------------------
+ * The paper solves the velocity mass systems by preconditioned conjugate
+ * gradients (end of Sec. 2.5); this preconditioner is an addition to it.  A
+ * message-passing network on the edge-cell graph of the mesh maps local
+ * geometry to a sparse factor Ghat with the mass-matrix pattern; the
+ * preconditioner is P = D^-1/2 Ghat Ghat^T D^-1/2 (D = diag M_u), symmetric
+ * positive definite whenever Ghat is non-singular.
+ *
+ * Network (width 32, relu):
+ *   edge features (8): M_ee; |e| / mean edge length; (|c0| + |c1|) / (2 mean
+ *     area); z/|x| at the midpoint; mean and |difference| of the cosines of
+ *     the two angles opposite e; mean and (max - min) of the four cosines of
+ *     the angles at the endpoints of e;
+ *   cell features (4): |c| / mean area; z/|x| at the centroid; max - min of
+ *     the cosines of its angles; mean M_ee over its edges;
+ *   he = relu(Fe W_ee + b_ee), hc = relu(Fc W_ce + b_ce); three rounds of
+ *     hc = relu([hc, mean he over the cell's edges] W_cl + b_cl),
+ *     he = relu([he, mean hc over the edge's cells] W_el + b_el);
+ *   Ghat_ii = softplus(he_i . w_hd + b_hd); for distinct edges i, j of a
+ *     cell c: Ghat_ij = (relu([he_i, he_j, hc_c] W_p1 + b_p1) . w_p2 + b_p2)
+ *     * M_ij / sqrt(M_ii M_jj).
+ * Parameters (16098 floats) in storage order W_ee [8][32], b_ee, W_ce
+ * [4][32], b_ce, then per round W_cl [64][32], b_cl, W_el [64][32], b_el,
+ * then w_hd [32], b_hd, W_p1 [96][32], b_p1, w_p2 [32], b_p2.  Initial
+ * values: Glorot-uniform weights from SplitMix64(seed), zero biases and
+ * head weights, b_hd = log(e - 1): Ghat = I, i.e. Jacobi.
+ * Loss over probe vectors z_p: (1/P) sum_p |Ghat^T Mhat Ghat z_p - z_p|^2 /
+ * |z_p|^2 with Mhat = D^-1/2 M_u D^-1/2 (zero iff P M_u = I).
+ * Dense layers run on the matrix cores: BF16 inputs and weights with FP32
+ * accumulation (bf16 = 1) or FP32 (bf16 = 0); the loss and the heads in
+ * FP64.  Network state is a host object; every call uploads what it needs. */
+typedef struct pa_lp pa_lp;
+int pa_lp_create(int layers, int width, uint64_t seed, pa_lp **out); /* 3, 32 only */
+int pa_lp_param_count(const pa_lp *lp, int *n);
+int pa_lp_get_params(const pa_lp *lp, float *out);
+int pa_lp_set_params(pa_lp *lp, const float *in);
+int pa_lp_save(const pa_lp *lp, const char *path);   /* raw little-endian file */
+int pa_lp_load(pa_lp *lp, const char *path);
+int pa_lp_destroy(pa_lp *lp);
+
+typedef struct {
+  int32_t steps;     /* Adam steps; each takes one Rademacher probe block per operator */
+  int32_t probes;    /* probe vectors per block, 1..16 */
+  double lr;         /* Adam step size (beta1 0.9, beta2 0.999, eps 1e-8) */
+  int32_t bf16;      /* 1: BF16 matrix-core layers, 0: FP32 */
+  uint64_t seed;     /* probe seed */
+} pa_train_cfg;
+typedef struct {
+  double loss_first, loss_last;  /* mean loss over operators, first and last step */
+  double ms;                     /* wall time of the call */
+  int32_t steps;
+} pa_train_stats;
+/* Device workspace for training on (or evaluating) the given operators. */
+int pa_lp_workspace_size(const pa_ops *const *ops, int n_ops, int probes, int steps,
+                         size_t *bytes);
+/* Trains lp in place on the GPU: every step sums the loss gradient over the
+ * operators (fresh probes each) and applies one Adam update. */
+int pa_lp_train(pa_ctx *ctx, pa_lp *lp, const pa_ops *const *ops, int n_ops,
+                const pa_train_cfg *cfg, void *ws_dev, size_t ws_bytes,
+                pa_train_stats *stats);
+/* Test hooks: the loss and its gradient (n_params doubles) for probes given
+ * on the host as [n_e][n_probe]; and Ghat (diagonal [n_e], off-diagonal
+ * [n_e][4] in the operator's mass-pattern slot order: the other two edges
+ * of the edge's first cell, then of its second cell). */
+int pa_lp_loss_grad(pa_ctx *ctx, const pa_lp *lp, const pa_ops *ops, int n_probe,
+                    const double *probes_host, int bf16, void *ws_dev, size_t ws_bytes,
+                    double *loss, double *grad_host);
+int pa_lp_ghat(pa_ctx *ctx, const pa_lp *lp, const pa_ops *ops, int bf16, void *ws_dev,
+               size_t ws_bytes, double *gdiag_host, double *goff_host);
+
+/* Attaching: inference on the operator's graph, then on the host P and P M
+ * as ELL tables (FP32 values) and the Ritz bounds of P M (Lanczos).  The
+ * tables are then bound to caller-owned device memory like the operators. */
+typedef struct {
+  double eig_min, eig_max;                /* Ritz bounds of P M */
+  double jacobi_eig_min, jacobi_eig_max;  /* Ritz bounds of D^-1 M */
+  int32_t width_p, width_pm;              /* ELL widths of P and P M */
+} pa_lp_info;
+int pa_ops_lp_attach(pa_ctx *ctx, pa_ops *ops, const pa_lp *lp, int bf16, void *ws_dev,
+                     size_t ws_bytes, pa_lp_info *info);
+int pa_ops_lp_device_size(const pa_ops *ops, size_t *bytes);
+int pa_ops_lp_bind(pa_ctx *ctx, pa_ops *ops, void *dev_buf);
 
 /* ---- batches of problems -------------------------------------------------
  * Independent problems evaluated together (the terms of the average are

@@ -108,11 +108,22 @@ std::vector<unsigned char> batch_key(const pa_batch *b, const double *const *U,
   std::vector<unsigned char> k;
   put(k, b->avg);
   put(k, ws);
-  put(k, c);
+  put(k, c.precision);
+  put(k, c.backward);
+  put(k, c.maxit);
+  put(k, c.growth_guard);
+  put(k, c.cg_rtol);
+  put(k, c.cheb_tol);
+  put(k, c.weight_cut);
+  put(k, c.inner_rtol);
+  put(k, c.use_graph);
+  put(k, c.solver);
+  put(k, c.precond);
   put(k, budget);
   for (int i = 0; i < b->n(); i++) {
     put(k, b->ops[i]);
     put(k, b->ops[i]->lambda_bar);
+    put(k, b->ops[i]->lp_dev);
     put(k, b->members[i]);
     put(k, U[i]);
     put(k, Nbar[i]);

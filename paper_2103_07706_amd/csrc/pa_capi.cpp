@@ -55,7 +55,7 @@ int pa_ctx_set_stream(pa_ctx *ctx, void *stream) {
 int pa_ctx_profile(pa_ctx *ctx, int kernel) {
   return guard([&] {
     need(ctx != nullptr, "ctx is NULL");
-    need(kernel >= PA_KERNEL_NONE && kernel <= PA_KERNEL_CHEB_ITER, "unknown kernel id");
+    need(kernel >= PA_KERNEL_NONE && kernel <= PA_KERNEL_CHEB_LP_ITER, "unknown kernel id");
     ctx->prof_kernel = kernel;
     ctx->prof_launches = ctx->prof_work = 0;
     ctx->prof_ms = ctx->prof_bytes = 0.0;
@@ -314,6 +314,7 @@ void pa_solve_cfg_default(pa_solve_cfg *cfg) {
   cfg->inner_rtol = 1e-6;
   cfg->use_graph = 0;
   cfg->solver = PA_SOLVER_CG;
+  cfg->precond = PA_PRECOND_JACOBI;
 }
 
 }  // extern "C"

@@ -52,13 +52,36 @@ Engine::~Engine() {
 // Chebyshev semi-iteration on D^-1 M over [a, b] = Lanczos bounds widened
 // by 5% below and 2% above; the number of steps makes the Chebyshev error
 // factor 1/T_k(theta/delta) reach cg_rtol, plus two.
+namespace {
+// Chebyshev steps for the error factor 1/T_k(theta/delta) to reach rtol, plus two.
+int cheb_steps(double a, double b, double rtol) {
+  const double sigma = (a + b) / (b - a);
+  return (int)std::ceil(std::acosh(2.0 / rtol) / std::acosh(sigma)) + 2;
+}
+}  // namespace
+
 void Engine::plan_cheb() {
-  const double a = 0.95 * ops_->mass_eig_min, b = 1.02 * ops_->mass_eig_max;
+  double a = 0.95 * ops_->mass_eig_min, b = 1.02 * ops_->mass_eig_max;
   if (!(a > 0) || !(b > a)) throw Error(PA_EINVAL, "no spectral bounds for the mass matrix");
+  // learned preconditioner: its own widened bounds, kept only if it needs
+  // fewer steps than Jacobi
+  lp_ = false;
+  if (cfg_.precond == PA_PRECOND_LEARNED && cheb() && !mixed()) {
+    if (!ops_->lp_ready || !ops_->lp_dev)
+      throw Error(PA_EINVAL, "no learned preconditioner bound to the operators");
+    const double la = 0.95 * ops_->lp_eig_min, lb = 1.02 * ops_->lp_eig_max;
+    if (la > 0 && lb > la && cheb_steps(la, lb, cfg_.cg_rtol) < cheb_steps(a, b, cfg_.cg_rtol)) {
+      lp_ = true;
+      a = la;
+      b = lb;
+    }
+  } else if (cfg_.precond != PA_PRECOND_JACOBI && cfg_.precond != PA_PRECOND_LEARNED) {
+    throw Error(PA_EINVAL, "unknown preconditioner");
+  }
   cheb_theta_ = 0.5 * (a + b);
   cheb_delta_ = 0.5 * (b - a);
   const double sigma = cheb_theta_ / cheb_delta_;
-  int k = (int)std::ceil(std::acosh(2.0 / cfg_.cg_rtol) / std::acosh(sigma)) + 2;
+  int k = cheb_steps(a, b, cfg_.cg_rtol);
   k = std::min(k, cfg_.maxit);
   cheb_c1_.resize(k);
   cheb_c2_.resize(k);
@@ -148,36 +171,82 @@ void Engine::mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_
 // Reduction-free mass solve: the set-up kernel wrote r_0 (r), x_0 (x),
 // d_0 = D^-1 r_0 / theta (p) and partials of |r_0|^2 (partA).
 void Engine::cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_init) {
-  ChebArgs a{};
-  a.ops = ops_->d;
-  a.Bs = Bs;
-  a.x = x;
-  a.r = r_;
-  a.colK = colK;
-  a.kneed = kneed;
-  a.part = rb_.partB;
-  a.max_wg = rb_.max_wg;
-  double *d[2] = {p_, s0_};
   const int k = (int)cheb_c1_.size();
-  const bool prof = ctx_->prof_kernel == PA_KERNEL_CHEB_ITER;
-  a.prof = prof ? st_.prof : nullptr;
-  for (int i = 0; i < k; i++) {
-    a.d_in = d[i & 1];
-    a.d_out = d[(i + 1) & 1];
-    a.c1 = cheb_c1_[i];
-    a.c2 = cheb_c2_[i];
-    a.last = i + 1 == k ? 1 : 0;
-    if (prof) {
-      hipEvent_t e0 = take_event(), e1 = take_event();
-      PA_HIP(hipEventRecord(e0, s_));
-      launch_cheb_iter(a, s_);
-      PA_HIP(hipEventRecord(e1, s_));
-      prof_ev_.push_back(e0);
-      prof_ev_.push_back(e1);
-    } else {
-      launch_cheb_iter(a, s_);
+  double *d[2] = {p_, s0_};
+  if (lp_) {
+    // d_0 = theta^-1 P r_0 replaces the Jacobi direction of the set-up kernel
+    LpD0Args a0{};
+    a0.ops = ops_->d;
+    a0.lp = ops_->lp;
+    a0.Bs = Bs;
+    a0.r = r_;
+    a0.d = d[0];
+    a0.theta_inv = 1.0 / cheb_theta_;
+    a0.colK = colK;
+    a0.kneed = kneed;
+    launch_lp_d0(a0, s_);
+    ChebLpArgs a{};
+    a.ops = ops_->d;
+    a.lp = ops_->lp;
+    a.Bs = Bs;
+    a.x = x;
+    a.colK = colK;
+    a.kneed = kneed;
+    a.part = rb_.partB;
+    a.max_wg = rb_.max_wg;
+    double *r[2] = {r_, r1_};
+    const bool prof = ctx_->prof_kernel == PA_KERNEL_CHEB_LP_ITER;
+    a.prof = prof ? st_.prof : nullptr;
+    for (int i = 0; i < k; i++) {
+      a.d_in = d[i & 1];
+      a.d_out = d[(i + 1) & 1];
+      a.r_in = r[i & 1];
+      a.r_out = r[(i + 1) & 1];
+      a.c1 = cheb_c1_[i];
+      a.c2 = cheb_c2_[i];
+      a.last = i + 1 == k ? 1 : 0;
+      if (prof) {
+        hipEvent_t e0 = take_event(), e1 = take_event();
+        PA_HIP(hipEventRecord(e0, s_));
+        launch_cheb_lp_iter(a, s_);
+        PA_HIP(hipEventRecord(e1, s_));
+        prof_ev_.push_back(e0);
+        prof_ev_.push_back(e1);
+      } else {
+        launch_cheb_lp_iter(a, s_);
+      }
+    }
+  } else {
+    ChebArgs a{};
+    a.ops = ops_->d;
+    a.Bs = Bs;
+    a.x = x;
+    a.r = r_;
+    a.colK = colK;
+    a.kneed = kneed;
+    a.part = rb_.partB;
+    a.max_wg = rb_.max_wg;
+    const bool prof = ctx_->prof_kernel == PA_KERNEL_CHEB_ITER;
+    a.prof = prof ? st_.prof : nullptr;
+    for (int i = 0; i < k; i++) {
+      a.d_in = d[i & 1];
+      a.d_out = d[(i + 1) & 1];
+      a.c1 = cheb_c1_[i];
+      a.c2 = cheb_c2_[i];
+      a.last = i + 1 == k ? 1 : 0;
+      if (prof) {
+        hipEvent_t e0 = take_event(), e1 = take_event();
+        PA_HIP(hipEventRecord(e0, s_));
+        launch_cheb_iter(a, s_);
+        PA_HIP(hipEventRecord(e1, s_));
+        prof_ev_.push_back(e0);
+        prof_ev_.push_back(e1);
+      } else {
+        launch_cheb_iter(a, s_);
+      }
     }
   }
+  stats.precond = lp_ ? PA_PRECOND_LEARNED : PA_PRECOND_JACOBI;
   CheckArgs ca{};
   ca.Bs = Bs;
   ca.nwg_init = nwg_init;
@@ -289,6 +358,11 @@ void Engine::finish() {
     // Chebyshev step: x, r, d in; x, r, d' out (d' not on the last step)
     if (ctx_->prof_kernel == PA_KERNEL_CHEB_ITER)
       ctx_->prof_bytes += (double)ne_ * (48.0 * cols + 40.0 * (unsigned)h[4] + 68.0 * work);
+    // learned step: x, r, d in; x, r', d' out (d' not on the last step); the
+    // mass ELL row and the P, P M rows (int32 column + FP32 value each)
+    if (ctx_->prof_kernel == PA_KERNEL_CHEB_LP_ITER)
+      ctx_->prof_bytes += (double)ne_ * (48.0 * cols + 40.0 * (unsigned)h[4] +
+                                         (60.0 + 8.0 * (ops_->lp_wp + ops_->lp_wpm)) * work);
     ctx_->prof_work += (int64_t)work;
   }
   float ms = 0;
@@ -859,6 +933,7 @@ void Engine::phase_avg_rhs(const pa_avg *avg, int members, const double *U, doub
     key.ws = ws_base_;
     key.budget = current_budget();
     key.lambda_bar = ops_->lambda_bar;
+    key.lp_dev = ops_->lp_dev;
     key.cfg = cfg_;
     key.tune = launch_tuning();
     run_graph(key, [&] { nbar_body(c); });

@@ -110,6 +110,7 @@ class Engine {
   float *x32_ = nullptr, *r32_ = nullptr, *d32_[2] = {nullptr, nullptr};
   // Chebyshev plan: step coefficients from the spectral bounds
   double cheb_theta_ = 0, cheb_delta_ = 0;
+  bool lp_ = false;  // learned preconditioner in the Chebyshev solves
   std::vector<double> cheb_c1_, cheb_c2_;
   void plan_cheb();
   void poly_apply(Blk X, Blk W, const double *coef, const int *colK, int kmax, int G, Blk acc);

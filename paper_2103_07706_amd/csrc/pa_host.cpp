@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <unordered_map>
 
 #include "pa_internal.h"
@@ -287,14 +288,13 @@ int sturm_count(const std::vector<double> &al, const std::vector<double> &be, do
 }
 }  // namespace
 
-// Extreme eigenvalues of D^-1 M (same spectrum as D^-1/2 M D^-1/2) by Lanczos
-// on the symmetric form from a fixed start vector, eigenvalues of the
-// tridiagonal matrix by bisection.  The Ritz values lie inside the spectrum
-// and approach its ends quickly; callers widen them by a margin.
-void mass_spectrum(pa_ops *o, int steps, double *lmin, double *lmax) {
-  const int n = o->ne;
-  std::vector<double> sq(n), v(n), vp(n, 0.0), w(n);
-  for (int i = 0; i < n; i++) sq[i] = std::sqrt(o->dinv[i]);
+// Ritz bounds of a symmetric operator S (y = S x) by Lanczos from a fixed
+// start vector, eigenvalues of the tridiagonal matrix by bisection.  The
+// Ritz values lie inside the spectrum and approach its ends quickly; callers
+// widen them by a margin.
+void ritz_bounds(int n, const std::function<void(const std::vector<double> &, std::vector<double> &)> &S,
+                 int steps, double *lmin, double *lmax) {
+  std::vector<double> v(n), vp(n, 0.0), w(n);
   double nv = 0.0;
   for (int i = 0; i < n; i++) {
     v[i] = 1.0 + 0.5 * std::sin(0.7 * i + 0.3);
@@ -305,14 +305,7 @@ void mass_spectrum(pa_ops *o, int steps, double *lmin, double *lmax) {
   std::vector<double> al, be;
   double bprev = 0.0;
   for (int k = 0; k < steps; k++) {
-    for (int i = 0; i < n; i++) {  // w = S v, S = D^-1/2 M D^-1/2
-      double s = 0.0;
-      for (int j = 0; j < 5; j++) {
-        const int c = o->ell_col[5 * i + j];
-        s += o->mass[5 * i + j] * sq[c] * v[c];
-      }
-      w[i] = sq[i] * s;
-    }
+    S(v, w);
     double a = 0.0;
     for (int i = 0; i < n; i++) a += w[i] * v[i];
     double b = 0.0;
@@ -347,6 +340,26 @@ void mass_spectrum(pa_ops *o, int steps, double *lmin, double *lmax) {
   };
   *lmin = kth(0);
   *lmax = kth((int)al.size() - 1);
+}
+
+// Extreme eigenvalues of D^-1 M, through its symmetric form D^-1/2 M D^-1/2.
+void mass_spectrum(pa_ops *o, int steps, double *lmin, double *lmax) {
+  const int n = o->ne;
+  std::vector<double> sq(n);
+  for (int i = 0; i < n; i++) sq[i] = std::sqrt(o->dinv[i]);
+  ritz_bounds(
+      n,
+      [&](const std::vector<double> &v, std::vector<double> &w) {
+        for (int i = 0; i < n; i++) {
+          double s = 0.0;
+          for (int j = 0; j < 5; j++) {
+            const int c = o->ell_col[5 * i + j];
+            s += o->mass[5 * i + j] * sq[c] * v[c];
+          }
+          w[i] = sq[i] * s;
+        }
+      },
+      steps, lmin, lmax);
 }
 
 // Chebyshev weights of exp(i theta x): (2 - delta_k0) J_k(theta), k = 0..kcap,

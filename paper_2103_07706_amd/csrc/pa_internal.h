@@ -7,6 +7,7 @@
 #include <map>
 #include <new>
 #include <cstdint>
+#include <functional>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -20,6 +21,11 @@ struct Error : std::runtime_error {
   int code;
   Error(int c, const std::string &m) : std::runtime_error(m), code(c) {}
 };
+
+// Ritz bounds of the symmetric operator y = S(x) of size n (Lanczos, fixed
+// start vector, 'steps' steps).
+void ritz_bounds(int n, const std::function<void(const std::vector<double> &, std::vector<double> &)> &S,
+                 int steps, double *lmin, double *lmax);
 
 // Thread-local message returned by pa_last_error.
 std::string &last_error();
@@ -98,6 +104,16 @@ struct DevOps {
   const double *cgeo = nullptr;       // nc*kCellGeo
 };
 
+// Learned preconditioner on the device: P = G G^T and P M as column-major
+// ELL tables ([slot][row], padding col = row, value 0), FP32 values.
+struct DevLp {
+  int wp = 0, wpm = 0;
+  const int32_t *pcol = nullptr;
+  const float *pval = nullptr;
+  const int32_t *pmcol = nullptr;
+  const float *pmval = nullptr;
+};
+
 // Launch shape of the row-parallel kernels (set by the autotuner).
 struct LaunchTune {
   int narrow_rows_per_thread = 4;  // batches of <= 4 columns
@@ -108,16 +124,25 @@ struct LaunchTune {
 };
 
 // What a captured averaged-RHS graph depends on.
+// Field-wise equality of solve configurations (no padding compared).
+inline bool same_cfg(const pa_solve_cfg &a, const pa_solve_cfg &b) {
+  return a.precision == b.precision && a.backward == b.backward && a.maxit == b.maxit &&
+         a.growth_guard == b.growth_guard && a.cg_rtol == b.cg_rtol && a.cheb_tol == b.cheb_tol &&
+         a.weight_cut == b.weight_cut && a.inner_rtol == b.inner_rtol && a.use_graph == b.use_graph &&
+         a.solver == b.solver && a.precond == b.precond;
+}
+
 struct GraphKey {
   const void *ops = nullptr, *avg = nullptr, *in = nullptr, *out = nullptr, *ws = nullptr;
+  const void *lp_dev = nullptr;
   int members = 0, budget = 0;
   double lambda_bar = 0;
   pa_solve_cfg cfg{};
   LaunchTune tune{};
   bool operator==(const GraphKey &o) const {
     return ops == o.ops && avg == o.avg && in == o.in && out == o.out && ws == o.ws &&
-           members == o.members && budget == o.budget && lambda_bar == o.lambda_bar &&
-           tune == o.tune && std::memcmp(&cfg, &o.cfg, sizeof(cfg)) == 0;
+           lp_dev == o.lp_dev && members == o.members && budget == o.budget &&
+           lambda_bar == o.lambda_bar && tune == o.tune && same_cfg(cfg, o.cfg);
   }
 };
 
@@ -159,6 +184,14 @@ struct pa_ops {
   size_t dev_bytes = 0;
   void *dev = nullptr;
   pa::DevOps d;
+  // learned preconditioner (pa_ops_lp_attach / pa_ops_lp_bind)
+  int lp_wp = 0, lp_wpm = 0;
+  std::vector<int32_t> lp_pcol, lp_pmcol;
+  std::vector<float> lp_pval, lp_pmval;
+  double lp_eig_min = 0, lp_eig_max = 0;
+  bool lp_ready = false;   // tables built
+  void *lp_dev = nullptr;  // bound device copy
+  pa::DevLp lp;
 };
 
 struct pa_avg {

@@ -90,6 +90,35 @@ struct ChebArgs {
   unsigned *prof;  // measurement hook: [0] active columns, [1] launches, [2] columns of last steps
 };
 
+// Chebyshev step with the learned preconditioner P (see k_cheb_lp_iter):
+// residuals ping-pong between r_in and r_out.
+struct ChebLpArgs {
+  DevOps ops;
+  DevLp lp;
+  int Bs;
+  double *x;
+  const double *r_in, *d_in;
+  double *r_out, *d_out;
+  double c1, c2;
+  const int *colK;
+  int kneed, last;
+  double *part;
+  int max_wg;
+  unsigned *prof;
+};
+
+// d_0 = theta^-1 P r_0 (first direction of a learned-preconditioned solve).
+struct LpD0Args {
+  DevOps ops;
+  DevLp lp;
+  int Bs;
+  const double *r;
+  double *d;
+  double theta_inv;
+  const int *colK;
+  int kneed;
+};
+
 // FP32 inner Chebyshev step (mixed precision): x32 (+)= d, r32 -= M32 d,
 // d' = c1 d + c2 D^-1 r32, all in FP32.
 struct Cheb32Args {
@@ -217,6 +246,8 @@ void launch_stiff(const StiffArgs &a, hipStream_t s);
 void launch_cg_init(const CgArgs &a, hipStream_t s);
 void launch_cheb_iter(const ChebArgs &a, hipStream_t s);
 void launch_cheb_check(const CheckArgs &a, hipStream_t s);
+void launch_cheb_lp_iter(const ChebLpArgs &a, hipStream_t s);
+void launch_lp_d0(const LpD0Args &a, hipStream_t s);
 void launch_cheb32_iter(const Cheb32Args &a, hipStream_t s);
 void launch_refine(const RefineArgs &a, hipStream_t s);
 void launch_cg_iter(const CgArgs &a, hipStream_t s);

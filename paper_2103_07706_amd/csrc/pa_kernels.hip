@@ -207,6 +207,67 @@ __global__ __launch_bounds__(kWG) void k_cheb_iter(ChebArgs a) {
   if (a.last) wg_partials<1>(L, sums, a.part, a.max_wg);
 }
 
+// The same semi-iteration preconditioned by the learned P = G G^T:
+//   x += d_k,  r_{k+1} = r_k - M d_k,  d_{k+1} = c1 d_k + c2 P r_{k+1},
+// with P r_{k+1} formed as P r_k - (P M) d_k so that one kernel per step
+// suffices (both products gather only values of the previous step; P and
+// P M are stored explicitly, column-major ELL, FP32 values).  M d_k and the
+// residual update stay FP64 with the FP64 matrix, so r is a true FP64
+// residual; the FP32 rounding of P and P M only perturbs the preconditioner.
+__global__ __launch_bounds__(kWG) void k_cheb_lp_iter(ChebLpArgs a) {
+  const Lane L = lane_map(a.Bs, a.ops.ne);
+  const DevOps &o = a.ops;
+  const int c = L.col, Bs = a.Bs, ne = o.ne;
+  if (a.prof && blockIdx.x == 0 && threadIdx.x == 0) {
+    unsigned n = 0;
+    for (int j = 0; j < L.ct; j++) n += a.colK[L.tile * L.ct + j] >= a.kneed ? 1u : 0u;
+    atomicAdd(&a.prof[a.last ? 2 : 0], n);
+    if (L.tile == 0) atomicAdd(&a.prof[1], 1u);
+  }
+  double sums[1] = {0.0};
+  if (a.colK[c] >= a.kneed) {
+    for (int e = L.row0; e < L.rend; e += L.rstride) {
+      double q = 0.0;
+#pragma unroll
+      for (int j = 0; j < 5; j++) q += o.mass[5 * e + j] * a.d_in[(size_t)o.ell_col[5 * e + j] * Bs + c];
+      const size_t ie = (size_t)e * Bs + c;
+      const double d = a.d_in[ie];
+      a.x[ie] += d;
+      const double r = a.r_in[ie] - q;
+      a.r_out[ie] = r;
+      if (a.last) {
+        sums[0] += r * r;
+      } else {
+        double z = 0.0;
+        for (int j = 0; j < a.lp.wp; j++) {
+          const size_t k = (size_t)j * ne + e;
+          z += (double)a.lp.pval[k] * a.r_in[(size_t)a.lp.pcol[k] * Bs + c];
+        }
+        for (int j = 0; j < a.lp.wpm; j++) {
+          const size_t k = (size_t)j * ne + e;
+          z -= (double)a.lp.pmval[k] * a.d_in[(size_t)a.lp.pmcol[k] * Bs + c];
+        }
+        a.d_out[ie] = a.c1 * d + a.c2 * z;
+      }
+    }
+  }
+  if (a.last) wg_partials<1>(L, sums, a.part, a.max_wg);
+}
+
+__global__ __launch_bounds__(kWG) void k_lp_d0(LpD0Args a) {
+  const Lane L = lane_map(a.Bs, a.ops.ne);
+  const int c = L.col, Bs = a.Bs, ne = a.ops.ne;
+  if (a.colK[c] < a.kneed) return;
+  for (int e = L.row0; e < L.rend; e += L.rstride) {
+    double z = 0.0;
+    for (int j = 0; j < a.lp.wp; j++) {
+      const size_t k = (size_t)j * ne + e;
+      z += (double)a.lp.pval[k] * a.r[(size_t)a.lp.pcol[k] * Bs + c];
+    }
+    a.d[(size_t)e * Bs + c] = a.theta_inv * z;
+  }
+}
+
 // Per column: |r_final|^2 <= rtol^2 |r_0|^2, else count a failure.
 __global__ __launch_bounds__(kWG) void k_cheb_check(CheckArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -937,6 +998,12 @@ void launch_cg_init(const CgArgs &a, hipStream_t s) {
 }
 void launch_cheb_iter(const ChebArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_cheb_iter, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+}
+void launch_cheb_lp_iter(const ChebLpArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_cheb_lp_iter, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+}
+void launch_lp_d0(const LpD0Args &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_lp_d0, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
 }
 void launch_cheb_check(const CheckArgs &a, hipStream_t s) {
   const int ct = a.Bs < 64 ? a.Bs : 64;

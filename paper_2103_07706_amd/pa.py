@@ -44,10 +44,28 @@ class SolveCfg(ctypes.Structure):
                 ("maxit", ctypes.c_int32), ("growth_guard", ctypes.c_int32),
                 ("cg_rtol", ctypes.c_double), ("cheb_tol", ctypes.c_double),
                 ("weight_cut", ctypes.c_double), ("inner_rtol", ctypes.c_double),
-                ("use_graph", ctypes.c_int32), ("solver", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("solver", ctypes.c_int32),
+                ("precond", ctypes.c_int32)]
 
 
-PA_KERNEL_NONE, PA_KERNEL_CG_ITER, PA_KERNEL_CHEB_ITER = 0, 1, 2
+PA_PRECOND_JACOBI, PA_PRECOND_LEARNED = 0, 1
+PA_KERNEL_NONE, PA_KERNEL_CG_ITER, PA_KERNEL_CHEB_ITER, PA_KERNEL_CHEB_LP_ITER = 0, 1, 2, 3
+
+
+class TrainCfg(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("probes", ctypes.c_int32), ("lr", ctypes.c_double),
+                ("bf16", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class TrainStats(ctypes.Structure):
+    _fields_ = [("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double),
+                ("ms", ctypes.c_double), ("steps", ctypes.c_int32)]
+
+
+class LpInfo(ctypes.Structure):
+    _fields_ = [("eig_min", ctypes.c_double), ("eig_max", ctypes.c_double),
+                ("jacobi_eig_min", ctypes.c_double), ("jacobi_eig_max", ctypes.c_double),
+                ("width_p", ctypes.c_int32), ("width_pm", ctypes.c_int32)]
 
 
 class KernelProfile(ctypes.Structure):
@@ -66,7 +84,8 @@ class Stats(ctypes.Structure):
                 ("ksum", ctypes.c_int32), ("terms", ctypes.c_int32),
                 ("refinements", ctypes.c_int32), ("guard_trips", ctypes.c_int32),
                 ("resid_max", ctypes.c_double), ("device_ms", ctypes.c_double),
-                ("graph", ctypes.c_int32), ("budget", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("budget", ctypes.c_int32),
+                ("precond", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -128,6 +147,25 @@ EXPORTS = {
     "pa_batch_autotune": (ctypes.c_int, [_V, _V, ctypes.POINTER(_V), ctypes.POINTER(_V), _V, _SZ,
                                          ctypes.POINTER(SolveCfg), ctypes.POINTER(LaunchTune)]),
     "pa_batch_destroy": (ctypes.c_int, [_V]),
+    "pa_lp_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                    ctypes.POINTER(_V)]),
+    "pa_lp_param_count": (ctypes.c_int, [_V, ctypes.POINTER(ctypes.c_int)]),
+    "pa_lp_get_params": (ctypes.c_int, [_V, ctypes.POINTER(ctypes.c_float)]),
+    "pa_lp_set_params": (ctypes.c_int, [_V, ctypes.POINTER(ctypes.c_float)]),
+    "pa_lp_save": (ctypes.c_int, [_V, ctypes.c_char_p]),
+    "pa_lp_load": (ctypes.c_int, [_V, ctypes.c_char_p]),
+    "pa_lp_destroy": (ctypes.c_int, [_V]),
+    "pa_lp_workspace_size": (ctypes.c_int, [ctypes.POINTER(_V), ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_int, ctypes.POINTER(_SZ)]),
+    "pa_lp_train": (ctypes.c_int, [_V, _V, ctypes.POINTER(_V), ctypes.c_int,
+                                   ctypes.POINTER(TrainCfg), _V, _SZ, ctypes.POINTER(TrainStats)]),
+    "pa_lp_loss_grad": (ctypes.c_int, [_V, _V, _V, ctypes.c_int, _D, ctypes.c_int, _V, _SZ, _D,
+                                       _D]),
+    "pa_lp_ghat": (ctypes.c_int, [_V, _V, _V, ctypes.c_int, _V, _SZ, _D, _D]),
+    "pa_ops_lp_attach": (ctypes.c_int, [_V, _V, _V, ctypes.c_int, _V, _SZ,
+                                        ctypes.POINTER(LpInfo)]),
+    "pa_ops_lp_device_size": (ctypes.c_int, [_V, ctypes.POINTER(_SZ)]),
+    "pa_ops_lp_bind": (ctypes.c_int, [_V, _V, _V]),
 }
 
 
@@ -169,10 +207,11 @@ def _dp(a):
 
 def solve_cfg(precision=PA_FP64, backward=PA_BACKWARD_PER_TERM, maxit=None, cg_rtol=None,
               cheb_tol=None, weight_cut=None, inner_rtol=None, use_graph=False,
-              solver=PA_SOLVER_CG) -> SolveCfg:
+              solver=PA_SOLVER_CG, precond=PA_PRECOND_JACOBI) -> SolveCfg:
     c = SolveCfg()
     lib().pa_solve_cfg_default(ctypes.byref(c))
     c.solver = solver
+    c.precond = precond
     c.precision = precision
     c.backward = backward
     c.use_graph = 1 if use_graph else 0
@@ -505,3 +544,100 @@ class Batch:
         if getattr(self, "_h", None) and _lib is not None:
             _lib.pa_batch_destroy(self._h)
             self._h = None
+
+
+def _dev_buffer(nbytes, device):
+    """256-byte aligned device buffer: (tensor keeping it alive, address)."""
+    import torch
+    t = torch.empty(nbytes + 256, dtype=torch.uint8, device=f"cuda:{device}")
+    base = t.data_ptr()
+    return t, base + ((-base) % 256)
+
+
+class LearnedPrecond:
+    """Parameters of the learned mass-matrix preconditioner (pa_lp_*)."""
+
+    def __init__(self, seed: int = 0):
+        h = _V()
+        _check(lib().pa_lp_create(3, 32, seed, ctypes.byref(h)))
+        self._h = h
+        n = ctypes.c_int()
+        _check(lib().pa_lp_param_count(h, ctypes.byref(n)))
+        self.n_params = n.value
+
+    @property
+    def params(self):
+        out = np.zeros(self.n_params, np.float32)
+        _check(lib().pa_lp_get_params(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+        return out
+
+    @params.setter
+    def params(self, value):
+        v = np.ascontiguousarray(value, np.float32)
+        assert v.size == self.n_params
+        _check(lib().pa_lp_set_params(self._h, v.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+
+    def save(self, path):
+        _check(lib().pa_lp_save(self._h, str(path).encode()))
+
+    def load(self, path):
+        _check(lib().pa_lp_load(self._h, str(path).encode()))
+
+    @staticmethod
+    def _ops_array(ops_list):
+        return (_V * len(ops_list))(*[o._h for o in ops_list])
+
+    def _workspace(self, ops_list, probes, steps, device):
+        sz = _SZ()
+        _check(lib().pa_lp_workspace_size(self._ops_array(ops_list), len(ops_list), probes, steps,
+                                          ctypes.byref(sz)))
+        return _dev_buffer(sz.value, device) + (sz.value,)
+
+    def train(self, ops_list, steps=300, probes=8, lr=3e-3, bf16=True, seed=1):
+        """Train on the GPU over the given operators; returns the statistics."""
+        ctx = ops_list[0].ctx
+        buf, ws, nb = self._workspace(ops_list, probes, steps, ctx.device)
+        cfg = TrainCfg(steps, probes, lr, 1 if bf16 else 0, seed)
+        st = TrainStats()
+        _check(lib().pa_lp_train(ctx._h, self._h, self._ops_array(ops_list), len(ops_list),
+                                 ctypes.byref(cfg), _V(ws), nb, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in st._fields_}
+
+    def loss_grad(self, ops, probes, bf16=False):
+        """Loss and gradient for host probes [n_e][P] (library numbering)."""
+        Z = np.ascontiguousarray(probes, np.float64)
+        buf, ws, nb = self._workspace([ops], Z.shape[1], 1, ops.ctx.device)
+        loss = ctypes.c_double()
+        grad = np.zeros(self.n_params)
+        _check(lib().pa_lp_loss_grad(ops.ctx._h, self._h, ops._h, Z.shape[1], _dp(Z),
+                                     1 if bf16 else 0, _V(ws), nb, ctypes.byref(loss), _dp(grad)))
+        return loss.value, grad
+
+    def ghat(self, ops, bf16=False):
+        """(diagonal [n_e], off-diagonal [n_e][4] in mass-pattern slot order)."""
+        buf, ws, nb = self._workspace([ops], 1, 1, ops.ctx.device)
+        gd = np.zeros(ops.mesh.ne)
+        go = np.zeros((ops.mesh.ne, 4))
+        _check(lib().pa_lp_ghat(ops.ctx._h, self._h, ops._h, 1 if bf16 else 0, _V(ws), nb,
+                                _dp(gd), _dp(go)))
+        return gd, go
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.pa_lp_destroy(self._h)
+            self._h = None
+
+
+def attach_learned(ops, lp: LearnedPrecond, bf16=True):
+    """Inference on ops' graph, P = G G^T and P M on the host, bound to a
+    device buffer owned by ops; returns the spectral information."""
+    buf, ws, nb = lp._workspace([ops], 1, 1, ops.ctx.device)
+    info = LpInfo()
+    _check(lib().pa_ops_lp_attach(ops.ctx._h, ops._h, lp._h, 1 if bf16 else 0, _V(ws), nb,
+                                  ctypes.byref(info)))
+    del buf
+    sz = _SZ()
+    _check(lib().pa_ops_lp_device_size(ops._h, ctypes.byref(sz)))
+    ops._lp_buf, addr = _dev_buffer(sz.value, ops.ctx.device)
+    _check(lib().pa_ops_lp_bind(ops.ctx._h, ops._h, _V(addr)))
+    return {f: getattr(info, f) for f, _ in info._fields_}

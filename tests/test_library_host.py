@@ -54,3 +54,31 @@ def test_library_rejects_bad_arguments():
         pa.Mesh(12)
     with pytest.raises(pa.PAError):
         pa.Avg(0, 100.0)
+
+
+def test_learned_preconditioner_parameters_host(tmp_path):
+    """The library's initial parameters are the definition's (FP64 values of
+    the reference rounded to FP32); save/load round-trips; only the built
+    network shape is accepted."""
+    import ctypes
+
+    import numpy as np
+
+    from oracle import lp_ref
+    from paper_2103_07706_amd import pa
+    lp = pa.LearnedPrecond(seed=42)
+    assert lp.n_params == lp_ref.n_params()
+    ref = lp_ref.init_params(42).astype(np.float32)
+    assert np.array_equal(lp.params, ref)
+    th = ref + np.float32(0.25)
+    lp.params = th
+    path = tmp_path / "net.bin"
+    lp.save(path)
+    lp2 = pa.LearnedPrecond(seed=1)
+    lp2.load(path)
+    assert np.array_equal(lp2.params, th)
+    h = ctypes.c_void_p()
+    assert pa.lib().pa_lp_create(2, 32, 0, ctypes.byref(h)) == pa.PA_ENOTSUP
+    (tmp_path / "bad.bin").write_bytes(b"nonsense")
+    with pytest.raises(pa.PAError):
+        lp2.load(tmp_path / "bad.bin")
