@@ -6,6 +6,12 @@ averaging terms over T = 2 h, FP64, Chebyshev threshold 1e-6 and every mass
 solve to a relative residual of 1e-10 (the throughput workload), with the
 input state already resident in device memory.  Prints one JSON line.
 
+Two forms are timed on the same input: the mass solves preconditioned by
+Jacobi (plain) and with the learned preconditioner available (trained on
+the GPU on level 4-6 meshes before the timed region; each solve takes the
+learned or the Jacobi steps by a byte model); `value` is the faster form's
+throughput and both are listed under config.forms.
+
 Also reported: the roofline position of the dominant kernel (HIP events
 around each of its launches during the timed region, algorithmic bytes from
 the library's count of active columns), and the oracle timed on a bounded
@@ -29,12 +35,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="l6_m64")
+    ap.add_argument("--workload", default="l6_m64",
+                    help="a single-mesh workload or a batch name (mixed_l4l5l6)")
     ap.add_argument("--backward", default="clenshaw", choices=["per_term", "clenshaw"])
     ap.add_argument("--graph", type=int, default=1)
     ap.add_argument("--solver", default="chebyshev", choices=["cg", "chebyshev"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_refined"])
     ap.add_argument("--autotune", type=int, default=1)
+    ap.add_argument("--precond", default="both", choices=["jacobi", "learned", "both"])
+    ap.add_argument("--lp-steps", dest="lp_steps", type=int, default=200)
     ap.add_argument("--cpu-baseline", dest="cpu", type=int, default=1)
     ap.add_argument("--cpu-terms", type=int, default=4)
     return ap.parse_args()
@@ -79,6 +88,126 @@ def cpu_baseline(wl, lam, nterms):
                       f"level {wl.level}, scaled by {wl.M}/{len(idx)}; {dt:.1f} s measured"}
 
 
+def measure(ops, avg, U, cfg, out, steps, warmup):
+    """Untimed warm-up, then `steps` timed evaluations bracketed by device
+    synchronisation; returns (seconds, stats of the last step)."""
+    import torch
+    for _ in range(warmup):
+        ops.phase_avg_rhs(avg, U, cfg, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = None
+    for i in range(steps):
+        _, stats = ops.phase_avg_rhs(avg, U, cfg, out=out)
+        print(f"step {i} {stats['device_ms']:.2f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, stats
+
+
+def kernel_profile(ctx, ops, avg, U, cfg, out, steps, kernel_id):
+    """Every launch of one kernel bracketed by HIP events on the stream it is
+    launched on, over `steps` evaluations (kept apart from the timed run:
+    the events add small gaps between kernels)."""
+    from paper_2103_07706_amd import pa
+    ctx.profile(kernel_id)
+    for _ in range(steps):
+        ops.phase_avg_rhs(avg, U, cfg, out=out)
+    prof = ctx.profile_read()
+    ctx.profile(pa.PA_KERNEL_NONE)
+    return prof
+
+
+def train_learned(pa, ctx, phys, have, steps):
+    """Train the learned preconditioner on the GPU on level 4-6 operators
+    (reusing those in `have`, a level -> Ops map)."""
+    train_ops = []
+    for lev in (4, 5, 6):
+        if lev in have:
+            train_ops.append(have[lev])
+        else:
+            train_ops.append(pa.Ops(ctx, pa.Mesh(lev), g=phys.g, H=phys.H, omega=phys.omega))
+    lp = pa.LearnedPrecond(seed=5)
+    tst = lp.train(train_ops, steps=steps, probes=8, lr=3e-3, bf16=True, seed=11)
+    rec = {"train_levels": [o.mesh.level for o in train_ops], "train_steps": steps,
+           "train_ms": tst["ms"], "loss_first": tst["loss_first"], "loss_last": tst["loss_last"]}
+    return lp, rec
+
+
+def bench_batch(args):
+    """A batch of meshes of uneven size (pa_batch_*): every item's Nbar per
+    step, items concurrent and captured as one graph; value = member-Nbar/s."""
+    import numpy as np
+    import torch
+
+    from paper_2103_07706_amd import inputs, pa
+    items = inputs.BATCHES[args.workload]
+    phys = inputs.Physics()
+    M, T, nb = 64, 7200.0, 40
+    ctx = pa.Context(0)
+    ops, Us = [], []
+    for lev, mem in items:
+        mesh = pa.Mesh(lev)
+        o = pa.Ops(ctx, mesh, g=phys.g, H=phys.H, omega=phys.omega)
+        o.estimate_lambda(iters=200, safety=1.05)
+        ops.append(o)
+        Us.append(torch.tensor(np.stack([inputs.gaussian_bumps_state(
+            mesh.verts, mesh.cell_verts, mesh.edge_verts, nb, m, phys) for m in range(mem)]),
+            dtype=torch.float64, device="cuda:0"))
+    avg = pa.Avg(M, T)
+    batch = pa.Batch(ctx, [(o, m) for o, (_, m) in zip(ops, items)], avg)
+    bw = pa.PA_BACKWARD_PER_TERM if args.backward == "per_term" else pa.PA_BACKWARD_CLENSHAW
+    base = dict(backward=bw, cheb_tol=1e-6, cg_rtol=1e-10, use_graph=bool(args.graph),
+                solver=pa.PA_SOLVER_CHEBYSHEV if args.solver == "chebyshev" else pa.PA_SOLVER_CG,
+                precision=pa.PA_FP64 if args.precision == "fp64" else pa.PA_FP32_REFINED)
+    forms = {}
+    if args.precond in ("jacobi", "both"):
+        forms["plain"] = (pa.solve_cfg(precond=pa.PA_PRECOND_JACOBI, **base), None)
+    lp_rec = None
+    if args.precond in ("learned", "both"):
+        lp, lp_rec = train_learned(pa, ctx, phys, {o.mesh.level: o for o in ops}, args.lp_steps)
+        for o in ops:
+            pa.attach_learned(o, lp, bf16=True)
+        lcfg = pa.solve_cfg(precond=pa.PA_PRECOND_LEARNED, **base)
+        forms["learned"] = (lcfg, 1)
+        forms["hybrid"] = (lcfg, None)
+    outs = [torch.empty_like(U) for U in Us]
+    members = sum(m for _, m in items)
+    res = {}
+    for name, (cfg, lmin) in forms.items():
+        tune = batch.autotune(Us, cfg) if args.autotune else None
+        if lmin is not None:
+            for i in range(len(items)):
+                t = batch.get_tune(i)
+                batch.set_tune(i, t["narrow_rows_per_thread"], t["wide_max_wg"], lmin)
+            tune = [batch.get_tune(i) for i in range(len(items))]
+        for _ in range(args.warmup):
+            batch.run(Us, cfg, outs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            _, st = batch.run(Us, cfg, outs)
+            print(f"{name} step {i} {st[0]['device_ms']:.2f} ms", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res[name] = {"value": members * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
+                     "lp_solves": [x["lp_solves"] for x in st], "solves": [x["solves"] for x in st],
+                     "graph": [x["graph"] for x in st], "launch_tune": tune}
+    for name in ("learned", "hybrid"):
+        if name in res and "plain" in res:
+            res[f"{name}_over_plain"] = res[name]["value"] / res["plain"]["value"]
+    head = max((k for k in res if k in forms), key=lambda k: res[k]["value"])
+    rec = {"metric": f"member phase-avg RHS evals/s ({args.workload}, M=64)",
+           "value": res[head]["value"], "unit": "member-Nbar/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": res[head]["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": args.workload, "items": items, "M": M, "T_s": T,
+                      "members": members, "cheb_tol": 1e-6, "cg_rtol": 1e-10,
+                      "backward": args.backward, "mass_solver": args.solver, "form": head,
+                      "forms": res, "learned_preconditioner": lp_rec}}
+    print(json.dumps(rec))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -86,6 +215,11 @@ def main():
               "(the path shards over averaging terms or members, see the design notes)",
               file=sys.stderr)
         sys.exit(2)
+    from paper_2103_07706_amd import inputs
+    if args.workload in inputs.BATCHES:
+        bench_batch(args)
+        return
+    import numpy as np
     import torch
 
     from paper_2103_07706_amd import inputs, pa
@@ -94,7 +228,6 @@ def main():
     mesh = pa.Mesh(wl.level)
     ops = pa.Ops(ctx, mesh, g=wl.phys.g, H=wl.phys.H, omega=wl.phys.omega)
     lam = ops.estimate_lambda(iters=200, safety=1.05)
-    import numpy as np
     U = torch.tensor(
         np.stack([inputs.gaussian_bumps_state(mesh.verts, mesh.cell_verts, mesh.edge_verts,
                                               wl.nbumps, m, wl.phys) for m in range(wl.members)]),
@@ -103,40 +236,63 @@ def main():
     bw = pa.PA_BACKWARD_PER_TERM if args.backward == "per_term" else pa.PA_BACKWARD_CLENSHAW
     solver = pa.PA_SOLVER_CG if args.solver == "cg" else pa.PA_SOLVER_CHEBYSHEV
     prec = pa.PA_FP64 if args.precision == "fp64" else pa.PA_FP32_REFINED
-    cfg = pa.solve_cfg(backward=bw, cheb_tol=1e-6, cg_rtol=1e-10, use_graph=bool(args.graph),
-                       solver=solver, precision=prec)
+    base = dict(backward=bw, cheb_tol=1e-6, cg_rtol=1e-10, use_graph=bool(args.graph),
+                solver=solver, precision=prec)
     out = torch.empty_like(U)
-    tune = None
-    if args.autotune:
-        tune = ops.autotune(avg, U, cfg)
-        print(f"autotune {tune}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        ops.phase_avg_rhs(avg, U, cfg, out=out)
-        print("warmup step done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = None
-    for i in range(args.steps):
-        _, stats = ops.phase_avg_rhs(avg, U, cfg, out=out)
-        print(f"step {i} {stats['device_ms']:.1f} ms", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    # the dominant kernel, timed with HIP events around each of its launches
-    # over the same number of steps (events add small gaps between kernels,
-    # so this pass is kept apart from the throughput measurement)
-    kernel = "k_cheb_iter" if args.solver == "chebyshev" else "k_cg_iter"
-    ctx.profile(pa.PA_KERNEL_CHEB_ITER if args.solver == "chebyshev" else pa.PA_KERNEL_CG_ITER)
-    for i in range(args.steps):
-        ops.phase_avg_rhs(avg, U, cfg, out=out)
-    prof = ctx.profile_read()
-    ctx.profile(pa.PA_KERNEL_NONE)
+    # forms: name -> (solve configuration, learned-step threshold or None =
+    # autotuned); "learned" takes learned steps in every mass solve,
+    # "hybrid" lets the autotuner choose the narrowest block that takes them
+    forms = {}
+    if args.precond in ("jacobi", "both"):
+        forms["plain"] = (pa.solve_cfg(precond=pa.PA_PRECOND_JACOBI, **base), None)
+    lp_rec = None
+    if args.precond in ("learned", "both"):
+        # the network is trained on the GPU on meshes of levels 4 to 6 (this
+        # workload's own operator among them) before the measurement
+        lp, lp_rec = train_learned(pa, ctx, wl.phys, {wl.level: ops}, args.lp_steps)
+        lp_rec.update(pa.attach_learned(ops, lp, bf16=True))
+        print(f"learned preconditioner {lp_rec}", file=sys.stderr, flush=True)
+        lcfg = pa.solve_cfg(precond=pa.PA_PRECOND_LEARNED, **base)
+        forms["learned"] = (lcfg, 1)
+        forms["hybrid"] = (lcfg, None)
+    results = {}
+    for name, (cfg, lmin) in forms.items():
+        tune = None
+        if args.autotune:
+            tune = ops.autotune(avg, U, cfg)
+        if lmin is not None:
+            pa.set_launch_tune(lp_min_cols=lmin)
+            tune = dict(tune or {}, **pa.get_launch_tune())
+        print(f"form {name} launch tune {tune}", file=sys.stderr, flush=True)
+        elapsed, stats = measure(ops, avg, U, cfg, out, args.steps, args.warmup)
+        learned = stats["lp_solves"] > 0
+        if args.solver == "chebyshev":
+            kernel = "k_cheb_lp_iter" if learned else "k_cheb_iter"
+            kid = pa.PA_KERNEL_CHEB_LP_ITER if learned else pa.PA_KERNEL_CHEB_ITER
+        else:
+            kernel, kid = "k_cg_iter", pa.PA_KERNEL_CG_ITER
+        prof = kernel_profile(ctx, ops, avg, U, cfg, out, args.steps, kid)
+        results[name] = dict(elapsed=elapsed, stats=stats, tune=tune, kernel=kernel, prof=prof,
+                             learned=learned)
+    # value: the faster form on this workload (both are listed in config.forms)
+    head = results[max(results, key=lambda k: 1.0 / results[k]["elapsed"])]
+    elapsed, stats, prof, kernel = head["elapsed"], head["stats"], head["prof"], head["kernel"]
     value = wl.members * args.steps / elapsed
     avg_ms = prof["total_ms"] / max(1, prof["launches"])
     achieved = prof["bytes"] / (prof["total_ms"] * 1e-3) / 1e9 if prof["total_ms"] > 0 else 0.0
     traffic = traffic_from_profiles(kernel, args.workload, args.backward)
+    forms_rec = {name: {"value": wl.members * args.steps / r["elapsed"],
+                        "ms_per_step": 1e3 * r["elapsed"] / args.steps,
+                        "mass_solves": r["stats"]["solves"],
+                        "learned_solves": r["stats"]["lp_solves"],
+                        "mass_solve_steps_total": r["stats"]["cg_iters"],
+                        "launch_tune": r["tune"]}
+                 for name, r in results.items()}
+    for name in ("learned", "hybrid"):
+        if name in forms_rec and "plain" in forms_rec:
+            forms_rec[f"{name}_over_plain"] = forms_rec[name]["value"] / forms_rec["plain"]["value"]
     rec = {
-        "metric": "phase-avg RHS evals/s (L6 mesh, M=64)",
+        "metric": "phase-avg RHS evals/s (L6 mesh, M=64); learned vs plain at 1e-10 resid",
         "value": value,
         "unit": "Nbar/s",
         "n_gpus": 1,
@@ -151,12 +307,13 @@ def main():
         "config": {"workload": args.workload, "level": wl.level, "cells": mesh.nc,
                    "edges": mesh.ne, "M": wl.M, "T_s": wl.T, "members": wl.members,
                    "cheb_tol": 1e-6, "cg_rtol": 1e-10, "backward": args.backward,
-                   "precision": args.precision, "preconditioner": "jacobi", "lambda_bar": lam,
-                   "mass_solver": args.solver,
-                   "kmax": stats["kmax"], "ksum": stats["ksum"], "terms": stats["terms"],
-                   "cg_iters_max": stats["cg_iters_max"], "solves": stats["solves"],
-                   "graph": bool(stats["graph"]), "cg_budget": stats["budget"],
-                   "launch_tune": tune},
+                   "precision": args.precision, "mass_solver": args.solver,
+                   "form": [k for k, v in results.items() if v is head][0],
+                   "preconditioner": "learned" if head["learned"] else "jacobi",
+                   "lambda_bar": lam, "kmax": stats["kmax"], "ksum": stats["ksum"],
+                   "terms": stats["terms"], "solves": stats["solves"],
+                   "graph": bool(stats["graph"]), "forms": forms_rec,
+                   "learned_preconditioner": lp_rec},
         "roofline": {"bound": "hbm", "kernel": kernel, "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "avg_launch_us": 1e3 * avg_ms,

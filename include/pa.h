@@ -148,13 +148,18 @@ typedef struct {
                           repeats the call with CG) */
   int32_t precond;     /* PA_PRECOND_JACOBI, or PA_PRECOND_LEARNED: the
                           Chebyshev mass solves (solver PA_SOLVER_CHEBYSHEV,
-                          precision PA_FP64) use the learned P = G G^T bound
-                          to the operators (pa_ops_lp_attach + pa_ops_lp_bind;
-                          PA_EINVAL if none is bound) over the Ritz bounds of
-                          P M, unless those bounds need at least as many
-                          steps as Jacobi, in which case Jacobi is used.  The
-                          final FP64 residual check and its CG repeat are as
-                          for Jacobi.  CG and FP32-refined solves use Jacobi. */
+                          precision PA_FP64) may use the learned P = G G^T
+                          bound to the operators (pa_ops_lp_attach +
+                          pa_ops_lp_bind; PA_EINVAL if none is bound), with
+                          steps from the Ritz bounds of P M.  Each solve
+                          takes the learned or the Jacobi steps, whichever
+                          moves fewer bytes: steps x (48 bytes per row and
+                          column for x, r, d in and out, plus the matrix rows
+                          of one launch: 68 bytes for Jacobi, 60 + 8 (w_P +
+                          w_PM) learned), so learned for wide column blocks.
+                          The final FP64 residual check and its CG repeat
+                          are as for Jacobi.  CG and FP32-refined solves use
+                          Jacobi. */
 } pa_solve_cfg;
 enum { PA_PRECOND_JACOBI = 0, PA_PRECOND_LEARNED = 1 };
 enum { PA_SOLVER_CG = 0, PA_SOLVER_CHEBYSHEV = 1 };
@@ -174,7 +179,8 @@ typedef struct {
   double device_ms;      /* device time of the call */
   int32_t graph;         /* 1 if the call ran as a graph replay or capture */
   int32_t budget;        /* CG iterations per solve launched (0: polled) */
-  int32_t precond;       /* preconditioner the Chebyshev solves used */
+  int32_t precond;       /* PA_PRECOND_LEARNED if any solve used it */
+  int32_t lp_solves;     /* mass solves that used the learned preconditioner */
 } pa_stats;
 
 /* Device workspace bytes for calls on 'batch' states (expL_apply,
@@ -246,14 +252,19 @@ int pa_ctx_set_cg_budget(pa_ctx *ctx, double cg_rtol, int iters);
 /* ---- launch shape and autotuner -------------------------------------------
  * Row-parallel kernels take their grid from a process-wide launch shape:
  * rows per thread for batches of at most 4 columns (latency-bound), and the
- * workgroup cap per column tile for wider batches.  pa_autotune times
- * pa_phase_avg_rhs over a small set of shapes on the given problem (the
- * workspace must fit it) and keeps the fastest; it returns the choice and
- * the best time. */
+ * workgroup cap per column tile for wider batches.  lp_min_cols is the
+ * narrowest column block whose mass solves take learned steps when the
+ * learned preconditioner is enabled (narrower blocks take Jacobi steps; a
+ * learned step costs more than a Jacobi step, so fewer steps pay only on
+ * wide enough blocks).  pa_autotune times pa_phase_avg_rhs over a small set
+ * of shapes on the given problem (the workspace must fit it), then, with
+ * the learned preconditioner enabled in cfg, over lp_min_cols in {1, 8, 64,
+ * never}, and keeps the fastest; it returns the choice and the best time. */
 typedef struct {
   int32_t narrow_rows_per_thread;
   int32_t wide_max_wg;
   double best_ms;
+  int32_t lp_min_cols;
 } pa_launch_tune;
 int pa_get_launch_tune(pa_launch_tune *out);
 int pa_set_launch_tune(const pa_launch_tune *t);

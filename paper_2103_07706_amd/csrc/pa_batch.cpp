@@ -130,6 +130,7 @@ std::vector<unsigned char> batch_key(const pa_batch *b, const double *const *U,
     const pa::LaunchTune t = b->item_tune(i);
     put(k, t.narrow_rows_per_thread);
     put(k, t.wide_max_wg);
+    put(k, t.lp_min_cols);
   }
   return k;
 }
@@ -324,8 +325,10 @@ int pa_batch_set_tune(pa_batch *b, int item, const pa_launch_tune *t) {
     bneed(b && t && item >= 0 && item < b->n(), "bad arguments");
     bneed(t->narrow_rows_per_thread >= 1 && t->narrow_rows_per_thread <= 64, "rows per thread in [1, 64]");
     bneed(t->wide_max_wg >= 8 && t->wide_max_wg <= 2048, "wide_max_wg in [8, 2048]");
+    bneed(t->lp_min_cols >= 1, "lp_min_cols >= 1");
     b->tune[item].narrow_rows_per_thread = t->narrow_rows_per_thread;
     b->tune[item].wide_max_wg = t->wide_max_wg;
+    b->tune[item].lp_min_cols = t->lp_min_cols;
     b->tuned[item] = true;
   });
 }
@@ -336,6 +339,7 @@ int pa_batch_get_tune(const pa_batch *b, int item, pa_launch_tune *out) {
     const pa::LaunchTune t = b->item_tune(item);
     out->narrow_rows_per_thread = t.narrow_rows_per_thread;
     out->wide_max_wg = t.wide_max_wg;
+    out->lp_min_cols = t.lp_min_cols;
     out->best_ms = 0.0;
   });
 }
@@ -366,27 +370,39 @@ int pa_batch_autotune(pa_ctx *ctx, pa_batch *b, const double *const *U_dev,
       const size_t wb = off[i + 1] - off[i];
       double best = 1e300;
       pa::LaunchTune best_t = b->item_tune(i);
+      auto trial = [&](const pa::LaunchTune &t) {
+        one.tune[0] = t;
+        pa_stats st{};
+        run_batch(ctx, &one, u1, o1, w1, wb, c, &st);  // warm-up / capture
+        double ms = 1e300;
+        for (int r = 0; r < 2; r++) {
+          run_batch(ctx, &one, u1, o1, w1, wb, c, &st);
+          ms = std::min(ms, (double)st.device_ms);
+        }
+        if (ms < best) {
+          best = ms;
+          best_t = t;
+        }
+      };
       for (int rpt : {1, 2, 4, 8})
         for (int cap : {512, 1024, 2048}) {
-          one.tune[0].narrow_rows_per_thread = rpt;
-          one.tune[0].wide_max_wg = cap;
-          pa_stats st{};
-          run_batch(ctx, &one, u1, o1, w1, wb, c, &st);  // warm-up / capture
-          double ms = 1e300;
-          for (int r = 0; r < 2; r++) {
-            run_batch(ctx, &one, u1, o1, w1, wb, c, &st);
-            ms = std::min(ms, (double)st.device_ms);
-          }
-          if (ms < best) {
-            best = ms;
-            best_t = one.tune[0];
-          }
+          pa::LaunchTune t = b->item_tune(i);
+          t.narrow_rows_per_thread = rpt;
+          t.wide_max_wg = cap;
+          trial(t);
+        }
+      if (c.precond == PA_PRECOND_LEARNED)
+        for (int lmin : {1, 8, 64, 1 << 30}) {
+          pa::LaunchTune t = best_t;
+          t.lp_min_cols = lmin;
+          trial(t);
         }
       b->tune[i] = best_t;
       b->tuned[i] = true;
       if (out) {
         out[i].narrow_rows_per_thread = best_t.narrow_rows_per_thread;
         out[i].wide_max_wg = best_t.wide_max_wg;
+        out[i].lp_min_cols = best_t.lp_min_cols;
         out[i].best_ms = best;
       }
     }

@@ -20,6 +20,9 @@ void need(bool ok, const char *msg) {
 }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// lp_min_cols that no column block reaches
+constexpr int kLpNever = 1 << 30;
 }  // namespace
 
 extern "C" {
@@ -510,6 +513,7 @@ int pa_get_launch_tune(pa_launch_tune *out) {
     pa::LaunchTune t = pa::launch_tuning();
     out->narrow_rows_per_thread = t.narrow_rows_per_thread;
     out->wide_max_wg = t.wide_max_wg;
+    out->lp_min_cols = t.lp_min_cols;
     out->best_ms = 0.0;
   });
 }
@@ -519,9 +523,11 @@ int pa_set_launch_tune(const pa_launch_tune *t) {
     need(t != nullptr, "t is NULL");
     need(t->narrow_rows_per_thread >= 1 && t->narrow_rows_per_thread <= 64, "rows per thread in [1, 64]");
     need(t->wide_max_wg >= 8 && t->wide_max_wg <= 2048, "wide_max_wg in [8, 2048]");
+    need(t->lp_min_cols >= 1, "lp_min_cols >= 1");
     pa::LaunchTune lt;
     lt.narrow_rows_per_thread = t->narrow_rows_per_thread;
     lt.wide_max_wg = t->wide_max_wg;
+    lt.lp_min_cols = t->lp_min_cols;
     pa::set_launch_tuning(lt);
   });
 }
@@ -553,11 +559,23 @@ int pa_autotune(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int members, 
     try {
       for (int rpt : rpts)
         for (int cap : caps) {
-          pa::LaunchTune t;
+          pa::LaunchTune t = keep;
           t.narrow_rows_per_thread = rpt;
           t.wide_max_wg = cap;
           pa::set_launch_tuning(t);
           time_once();  // warm-up (and graph capture when enabled)
+          double ms = std::min(time_once(), time_once());
+          if (ms < best) {
+            best = ms;
+            best_t = t;
+          }
+        }
+      if (c.precond == PA_PRECOND_LEARNED)
+        for (int lmin : {1, 8, 64, kLpNever}) {
+          pa::LaunchTune t = best_t;
+          t.lp_min_cols = lmin;
+          pa::set_launch_tuning(t);
+          time_once();
           double ms = std::min(time_once(), time_once());
           if (ms < best) {
             best = ms;
@@ -571,6 +589,7 @@ int pa_autotune(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int members, 
     pa::set_launch_tuning(best_t);
     out->narrow_rows_per_thread = best_t.narrow_rows_per_thread;
     out->wide_max_wg = best_t.wide_max_wg;
+    out->lp_min_cols = best_t.lp_min_cols;
     out->best_ms = best;
   });
 }

@@ -60,52 +60,53 @@ int cheb_steps(double a, double b, double rtol) {
 }
 }  // namespace
 
+namespace {
+// Chebyshev semi-iteration coefficients over [a, b]: x += d_k, r -= M d_k,
+// d_{k+1} = c1_k d_k + c2_k B r (B the preconditioner).
+void cheb_coefs(double a, double b, int k, std::vector<double> &c1, std::vector<double> &c2) {
+  const double theta = 0.5 * (a + b), delta = 0.5 * (b - a), sigma = theta / delta;
+  c1.resize(k);
+  c2.resize(k);
+  double rho = 1.0 / sigma;
+  for (int i = 0; i < k; i++) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    c1[i] = rn * rho;
+    c2[i] = 2.0 * rn / delta;
+    rho = rn;
+  }
+}
+}  // namespace
+
 void Engine::plan_cheb() {
-  double a = 0.95 * ops_->mass_eig_min, b = 1.02 * ops_->mass_eig_max;
+  const double a = 0.95 * ops_->mass_eig_min, b = 1.02 * ops_->mass_eig_max;
   if (!(a > 0) || !(b > a)) throw Error(PA_EINVAL, "no spectral bounds for the mass matrix");
-  // learned preconditioner: its own widened bounds, kept only if it needs
-  // fewer steps than Jacobi
-  lp_ = false;
+  if (cfg_.precond != PA_PRECOND_JACOBI && cfg_.precond != PA_PRECOND_LEARNED)
+    throw Error(PA_EINVAL, "unknown preconditioner");
+  // learned preconditioner: its own widened bounds; whether a solve uses it
+  // is decided per solve by lp_cheaper()
+  lp_avail_ = false;
   if (cfg_.precond == PA_PRECOND_LEARNED && cheb() && !mixed()) {
     if (!ops_->lp_ready || !ops_->lp_dev)
       throw Error(PA_EINVAL, "no learned preconditioner bound to the operators");
     const double la = 0.95 * ops_->lp_eig_min, lb = 1.02 * ops_->lp_eig_max;
-    if (la > 0 && lb > la && cheb_steps(la, lb, cfg_.cg_rtol) < cheb_steps(a, b, cfg_.cg_rtol)) {
-      lp_ = true;
-      a = la;
-      b = lb;
+    if (la > 0 && lb > la) {
+      lp_avail_ = true;
+      lp_theta_ = 0.5 * (la + lb);
+      cheb_coefs(la, lb, std::min(cheb_steps(la, lb, cfg_.cg_rtol), cfg_.maxit), lp_c1_, lp_c2_);
     }
-  } else if (cfg_.precond != PA_PRECOND_JACOBI && cfg_.precond != PA_PRECOND_LEARNED) {
-    throw Error(PA_EINVAL, "unknown preconditioner");
   }
   cheb_theta_ = 0.5 * (a + b);
   cheb_delta_ = 0.5 * (b - a);
   const double sigma = cheb_theta_ / cheb_delta_;
-  int k = cheb_steps(a, b, cfg_.cg_rtol);
-  k = std::min(k, cfg_.maxit);
-  cheb_c1_.resize(k);
-  cheb_c2_.resize(k);
-  double rho = 1.0 / sigma;
-  for (int i = 0; i < k; i++) {
-    const double rn = 1.0 / (2.0 * sigma - rho);
-    cheb_c1_[i] = rn * rho;
-    cheb_c2_[i] = 2.0 * rn / cheb_delta_;
-    rho = rn;
-  }
+  cheb_coefs(a, b, std::min(cheb_steps(a, b, cfg_.cg_rtol), cfg_.maxit), cheb_c1_, cheb_c2_);
   if (mixed()) {
     // FP32 inner solves to eps = max(inner_rtol, 1e-6) (single-precision
     // floor), outer FP64 refinements until eps^n_out reaches cg_rtol
     const double eps = std::max(cfg_.inner_rtol, 1e-6);
     const int kin = std::min(cfg_.maxit, (int)std::ceil(std::acosh(2.0 / eps) / std::acosh(sigma)) + 1);
     mixed_outer_ = std::max(1, (int)std::ceil(std::log(cfg_.cg_rtol) / std::log(10.0 * eps)));
-    mix_c1_.assign(cheb_c1_.begin(), cheb_c1_.begin() + std::min(kin, (int)cheb_c1_.size()));
-    mix_c2_.assign(cheb_c2_.begin(), cheb_c2_.begin() + mix_c1_.size());
-    while ((int)mix_c1_.size() < kin) {  // more steps than the FP64 plan
-      const double rn = 1.0 / (2.0 * sigma - rho);
-      mix_c1_.push_back(rn * rho);
-      mix_c2_.push_back(2.0 * rn / cheb_delta_);
-      rho = rn;
-    }
+    // the first kin coefficients of the same recurrence
+    cheb_coefs(a, b, kin, mix_c1_, mix_c2_);
   }
 }
 
@@ -170,21 +171,30 @@ void Engine::mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_
 
 // Reduction-free mass solve: the set-up kernel wrote r_0 (r), x_0 (x),
 // d_0 = D^-1 r_0 / theta (p) and partials of |r_0|^2 (partA).
+// Learned or Jacobi steps for a solve on Bs columns.  A learned step moves
+// more bytes than a Jacobi step (the P and P M rows, and gathers over two and
+// three rings of neighbours against one), so fewer steps pay only on wide
+// enough blocks; the threshold is part of the launch shape, which the
+// autotuner measures.
+bool Engine::lp_cheaper(int Bs) const { return lp_avail_ && Bs >= launch_tuning().lp_min_cols; }
+
 void Engine::cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_init) {
-  const int k = (int)cheb_c1_.size();
+  const bool lp = lp_cheaper(Bs);
+  const std::vector<double> &c1 = lp ? lp_c1_ : cheb_c1_, &c2 = lp ? lp_c2_ : cheb_c2_;
+  const int k = (int)c1.size();
   double *d[2] = {p_, s0_};
-  if (lp_) {
-    // d_0 = theta^-1 P r_0 replaces the Jacobi direction of the set-up kernel
-    LpD0Args a0{};
+  if (lp && Bs <= 4) {
+    // narrow blocks: one kernel per step, P r_{k+1} = P r_k - (P M) d_k
+    LpDirArgs a0{};  // d_0 = theta^-1 P r_0 replaces the set-up kernel's Jacobi direction
     a0.ops = ops_->d;
     a0.lp = ops_->lp;
     a0.Bs = Bs;
     a0.r = r_;
-    a0.d = d[0];
-    a0.theta_inv = 1.0 / cheb_theta_;
+    a0.d_out = d[0];
+    a0.c2 = 1.0 / lp_theta_;
     a0.colK = colK;
     a0.kneed = kneed;
-    launch_lp_d0(a0, s_);
+    launch_lp_dir(a0, s_);
     ChebLpArgs a{};
     a.ops = ops_->d;
     a.lp = ops_->lp;
@@ -202,8 +212,8 @@ void Engine::cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_i
       a.d_out = d[(i + 1) & 1];
       a.r_in = r[i & 1];
       a.r_out = r[(i + 1) & 1];
-      a.c1 = cheb_c1_[i];
-      a.c2 = cheb_c2_[i];
+      a.c1 = c1[i];
+      a.c2 = c2[i];
       a.last = i + 1 == k ? 1 : 0;
       if (prof) {
         hipEvent_t e0 = take_event(), e1 = take_event();
@@ -214,6 +224,56 @@ void Engine::cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_i
         prof_ev_.push_back(e1);
       } else {
         launch_cheb_lp_iter(a, s_);
+      }
+    }
+  } else if (lp) {
+    // wide blocks: x and r updated in place by the Jacobi step kernel without
+    // its direction, then d_{k+1} = c1 d_k + c2 P r_{k+1} (fewer gathers
+    // than the one-kernel form, which also gathers d over P M)
+    LpDirArgs b{};
+    b.ops = ops_->d;
+    b.lp = ops_->lp;
+    b.Bs = Bs;
+    b.r = r_;
+    b.colK = colK;
+    b.kneed = kneed;
+    b.d_out = d[0];
+    b.c1 = 0.0;
+    b.c2 = 1.0 / lp_theta_;
+    launch_lp_dir(b, s_);
+    ChebArgs a{};
+    a.ops = ops_->d;
+    a.Bs = Bs;
+    a.x = x;
+    a.r = r_;
+    a.colK = colK;
+    a.kneed = kneed;
+    a.part = rb_.partB;
+    a.max_wg = rb_.max_wg;
+    a.nodir = 1;
+    const bool prof = ctx_->prof_kernel == PA_KERNEL_CHEB_LP_ITER;
+    a.prof = prof ? st_.prof : nullptr;
+    for (int i = 0; i < k; i++) {
+      a.d_in = d[i & 1];
+      a.last = i + 1 == k ? 1 : 0;
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (prof) {
+        e0 = take_event();
+        e1 = take_event();
+        PA_HIP(hipEventRecord(e0, s_));
+      }
+      launch_cheb_iter(a, s_);
+      if (!a.last) {
+        b.d_in = d[i & 1];
+        b.d_out = d[(i + 1) & 1];
+        b.c1 = c1[i];
+        b.c2 = c2[i];
+        launch_lp_dir(b, s_);
+      }
+      if (prof) {
+        PA_HIP(hipEventRecord(e1, s_));
+        prof_ev_.push_back(e0);
+        prof_ev_.push_back(e1);
       }
     }
   } else {
@@ -228,25 +288,30 @@ void Engine::cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_i
     a.max_wg = rb_.max_wg;
     const bool prof = ctx_->prof_kernel == PA_KERNEL_CHEB_ITER;
     a.prof = prof ? st_.prof : nullptr;
-    for (int i = 0; i < k; i++) {
-      a.d_in = d[i & 1];
-      a.d_out = d[(i + 1) & 1];
-      a.c1 = cheb_c1_[i];
-      a.c2 = cheb_c2_[i];
-      a.last = i + 1 == k ? 1 : 0;
+    auto timed = [&](auto &&launch) {
       if (prof) {
         hipEvent_t e0 = take_event(), e1 = take_event();
         PA_HIP(hipEventRecord(e0, s_));
-        launch_cheb_iter(a, s_);
+        launch();
         PA_HIP(hipEventRecord(e1, s_));
         prof_ev_.push_back(e0);
         prof_ev_.push_back(e1);
       } else {
-        launch_cheb_iter(a, s_);
+        launch();
       }
+    };
+    for (int i = 0; i < k; i++) {
+      a.d_in = d[i & 1];
+      a.d_out = d[(i + 1) & 1];
+      a.c1 = c1[i];
+      a.c2 = c2[i];
+      a.last = i + 1 == k ? 1 : 0;
+      timed([&] { launch_cheb_iter(a, s_); });
     }
   }
-  stats.precond = lp_ ? PA_PRECOND_LEARNED : PA_PRECOND_JACOBI;
+  if (lp) stats.precond = PA_PRECOND_LEARNED;
+  if (lp) lp_prof_wide_ = Bs > 4;
+  stats.lp_solves += lp ? 1 : 0;
   CheckArgs ca{};
   ca.Bs = Bs;
   ca.nwg_init = nwg_init;
@@ -358,11 +423,16 @@ void Engine::finish() {
     // Chebyshev step: x, r, d in; x, r, d' out (d' not on the last step)
     if (ctx_->prof_kernel == PA_KERNEL_CHEB_ITER)
       ctx_->prof_bytes += (double)ne_ * (48.0 * cols + 40.0 * (unsigned)h[4] + 68.0 * work);
-    // learned step: x, r, d in; x, r', d' out (d' not on the last step); the
-    // mass ELL row and the P, P M rows (int32 column + FP32 value each)
+    // learned step, per active column and row: x, r, d in and x, r, d' out
+    // (d' not on the last step); per row and launch: the mass ELL row and
+    // the packed P and P M rows (8 bytes per entry; the wide two-kernel form
+    // reads P only, and r and d once more)
     if (ctx_->prof_kernel == PA_KERNEL_CHEB_LP_ITER)
-      ctx_->prof_bytes += (double)ne_ * (48.0 * cols + 40.0 * (unsigned)h[4] +
-                                         (60.0 + 8.0 * (ops_->lp_wp + ops_->lp_wpm)) * work);
+      ctx_->prof_bytes += lp_prof_wide_
+                              ? (double)ne_ * (64.0 * cols + 40.0 * (unsigned)h[4] +
+                                               (68.0 + 8.0 * ops_->lp_wp) * work)
+                              : (double)ne_ * (48.0 * cols + 40.0 * (unsigned)h[4] +
+                                               (60.0 + 8.0 * (ops_->lp_wp + ops_->lp_wpm)) * work);
     ctx_->prof_work += (int64_t)work;
   }
   float ms = 0;

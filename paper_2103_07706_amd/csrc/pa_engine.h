@@ -110,7 +110,12 @@ class Engine {
   float *x32_ = nullptr, *r32_ = nullptr, *d32_[2] = {nullptr, nullptr};
   // Chebyshev plan: step coefficients from the spectral bounds
   double cheb_theta_ = 0, cheb_delta_ = 0;
-  bool lp_ = false;  // learned preconditioner in the Chebyshev solves
+  // learned preconditioner plan (Chebyshev solves), chosen per solve
+  bool lp_avail_ = false;
+  double lp_theta_ = 0;
+  std::vector<double> lp_c1_, lp_c2_;
+  bool lp_cheaper(int Bs) const;
+  bool lp_prof_wide_ = false;  // measurement hook: form of the profiled learned steps
   std::vector<double> cheb_c1_, cheb_c2_;
   void plan_cheb();
   void poly_apply(Blk X, Blk W, const double *coef, const int *colK, int kmax, int G, Blk acc);

@@ -105,21 +105,22 @@ struct DevOps {
 };
 
 // Learned preconditioner on the device: P = G G^T and P M as column-major
-// ELL tables ([slot][row], padding col = row, value 0), FP32 values.
+// ELL tables ([slot][row], padding col = row, value 0) of packed entries
+// (x = column, y = FP32 value bits), one 8-byte load per entry.
 struct DevLp {
   int wp = 0, wpm = 0;
-  const int32_t *pcol = nullptr;
-  const float *pval = nullptr;
-  const int32_t *pmcol = nullptr;
-  const float *pmval = nullptr;
+  const uint2 *p = nullptr;
+  const uint2 *pm = nullptr;
 };
 
 // Launch shape of the row-parallel kernels (set by the autotuner).
 struct LaunchTune {
   int narrow_rows_per_thread = 4;  // batches of <= 4 columns
   int wide_max_wg = 2048;          // workgroups per column tile, wider batches
+  int lp_min_cols = 8;             // learned mass-solve steps on blocks this wide or wider
   bool operator==(const LaunchTune &o) const {
-    return narrow_rows_per_thread == o.narrow_rows_per_thread && wide_max_wg == o.wide_max_wg;
+    return narrow_rows_per_thread == o.narrow_rows_per_thread && wide_max_wg == o.wide_max_wg &&
+           lp_min_cols == o.lp_min_cols;
   }
 };
 

@@ -88,6 +88,7 @@ struct ChebArgs {
   double *part;  // last step: partials of r.r
   int max_wg;
   unsigned *prof;  // measurement hook: [0] active columns, [1] launches, [2] columns of last steps
+  int nodir;       // 1: update x and r only (the direction comes from another kernel)
 };
 
 // Chebyshev step with the learned preconditioner P (see k_cheb_lp_iter):
@@ -107,14 +108,14 @@ struct ChebLpArgs {
   unsigned *prof;
 };
 
-// d_0 = theta^-1 P r_0 (first direction of a learned-preconditioned solve).
-struct LpD0Args {
+// d_out = c1 d_in + c2 P r (learned direction; c1 = 0: d_in not read).
+struct LpDirArgs {
   DevOps ops;
   DevLp lp;
   int Bs;
-  const double *r;
-  double *d;
-  double theta_inv;
+  const double *r, *d_in;
+  double *d_out;
+  double c1, c2;
   const int *colK;
   int kneed;
 };
@@ -247,7 +248,7 @@ void launch_cg_init(const CgArgs &a, hipStream_t s);
 void launch_cheb_iter(const ChebArgs &a, hipStream_t s);
 void launch_cheb_check(const CheckArgs &a, hipStream_t s);
 void launch_cheb_lp_iter(const ChebLpArgs &a, hipStream_t s);
-void launch_lp_d0(const LpD0Args &a, hipStream_t s);
+void launch_lp_dir(const LpDirArgs &a, hipStream_t s);
 void launch_cheb32_iter(const Cheb32Args &a, hipStream_t s);
 void launch_refine(const RefineArgs &a, hipStream_t s);
 void launch_cg_iter(const CgArgs &a, hipStream_t s);

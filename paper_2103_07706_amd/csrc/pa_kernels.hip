@@ -37,13 +37,19 @@ __device__ inline Lane lane_map(int Bs, int nrows) {
   L.wave = threadIdx.x >> 6;
   L.tile = blockIdx.y;
   L.col = L.tile * L.ct + (L.lane % L.ct);
-  const int G = gridDim.x;
-  const int v = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
-  const int rpw = (nrows + G - 1) / G;
-  const int rbeg = v * rpw;
-  L.rend = min(nrows, rbeg + rpw);
+  // Workgroups are dispatched round-robin over the 8 XCDs: XCD k = b & 7
+  // owns the contiguous row slice k, and its G/8 workgroups take that slice
+  // in interleaved passes (workgroup w: passes w, w + G/8, ...), so the rows
+  // an XCD works on at any moment form one window and the neighbour gathers
+  // stay in its L2.
+  const int G = gridDim.x, per = G >> 3;
+  const int xcd = blockIdx.x & 7, w = blockIdx.x >> 3;
+  const int slice = (nrows + 7) >> 3;
+  const int rpp = (kWG / 64) * L.rw;  // rows of one workgroup pass
+  const int rbeg = xcd * slice + w * rpp;
+  L.rend = min(nrows, (xcd + 1) * slice);
   L.row0 = rbeg + L.wave * L.rw + L.lane / L.ct;
-  L.rstride = (kWG / 64) * L.rw;
+  L.rstride = per * rpp;
   return L;
 }
 
@@ -177,6 +183,11 @@ __global__ __launch_bounds__(kWG) void k_stiff(StiffArgs a) {
 // (Saad, Iterative Methods for Sparse Linear Systems, Alg. 12.1).  The step
 // count follows from the bounds; the final residual is checked in FP64.  One
 // kernel per step, gathering only d.
+// Direction update of the Jacobi Chebyshev step.
+__device__ inline double cheb_dir(double c1, double c2, double d, double dinv, double r) {
+  return c1 * d + c2 * dinv * r;
+}
+
 __global__ __launch_bounds__(kWG) void k_cheb_iter(ChebArgs a) {
   const Lane L = lane_map(a.Bs, a.ops.ne);
   const DevOps &o = a.ops;
@@ -200,8 +211,8 @@ __global__ __launch_bounds__(kWG) void k_cheb_iter(ChebArgs a) {
       a.r[ie] = r;
       if (a.last)
         sums[0] += r * r;
-      else
-        a.d_out[ie] = a.c1 * d + a.c2 * o.dinv[e] * r;
+      else if (!a.nodir)
+        a.d_out[ie] = cheb_dir(a.c1, a.c2, d, o.dinv[e], r);
     }
   }
   if (a.last) wg_partials<1>(L, sums, a.part, a.max_wg);
@@ -214,6 +225,27 @@ __global__ __launch_bounds__(kWG) void k_cheb_iter(ChebArgs a) {
 // P M are stored explicitly, column-major ELL, FP32 values).  M d_k and the
 // residual update stay FP64 with the FP64 matrix, so r is a true FP64
 // residual; the FP32 rounding of P and P M only perturbs the preconditioner.
+// sum_j val_j v[col_j] over W packed entries of row e (column-major table);
+// W > 0: fixed width, every load issued before the first use.
+template <int W>
+__device__ inline double lp_row_dot(const uint2 *t, int w, int ne, int e, const double *v, int Bs, int c) {
+  double z = 0.0;
+  if constexpr (W > 0) {
+    uint2 q[W];
+#pragma unroll
+    for (int j = 0; j < W; j++) q[j] = t[(size_t)j * ne + e];
+#pragma unroll
+    for (int j = 0; j < W; j++) z += (double)__uint_as_float(q[j].y) * v[(size_t)q[j].x * Bs + c];
+  } else {
+    for (int j = 0; j < w; j++) {
+      const uint2 q = t[(size_t)j * ne + e];
+      z += (double)__uint_as_float(q.y) * v[(size_t)q.x * Bs + c];
+    }
+  }
+  return z;
+}
+
+template <int WP, int WPM>
 __global__ __launch_bounds__(kWG) void k_cheb_lp_iter(ChebLpArgs a) {
   const Lane L = lane_map(a.Bs, a.ops.ne);
   const DevOps &o = a.ops;
@@ -224,47 +256,70 @@ __global__ __launch_bounds__(kWG) void k_cheb_lp_iter(ChebLpArgs a) {
     atomicAdd(&a.prof[a.last ? 2 : 0], n);
     if (L.tile == 0) atomicAdd(&a.prof[1], 1u);
   }
+  const double *__restrict__ rin = a.r_in;
+  const double *__restrict__ din = a.d_in;
+  const uint2 *__restrict__ tp = a.lp.p;
+  const uint2 *__restrict__ tpm = a.lp.pm;
   double sums[1] = {0.0};
   if (a.colK[c] >= a.kneed) {
     for (int e = L.row0; e < L.rend; e += L.rstride) {
+      // every table entry and gathered operand is loaded before any store
+      int mc[5];
+      double mv[5], dg[5];
+#pragma unroll
+      for (int j = 0; j < 5; j++) {
+        mc[j] = o.ell_col[5 * e + j];
+        mv[j] = o.mass[5 * e + j];
+      }
+      const size_t ie = (size_t)e * Bs + c;
+      const double d = din[ie], r0 = rin[ie], x0 = a.x[ie];
+#pragma unroll
+      for (int j = 0; j < 5; j++) dg[j] = din[(size_t)mc[j] * Bs + c];
+      double z = 0.0;
+      if (!a.last) {
+        if constexpr (WP > 0 && WPM > 0) {
+          uint2 qp[WP], qm[WPM];
+#pragma unroll
+          for (int j = 0; j < WP; j++) qp[j] = tp[(size_t)j * ne + e];
+#pragma unroll
+          for (int j = 0; j < WPM; j++) qm[j] = tpm[(size_t)j * ne + e];
+          double gp[WP], gm[WPM];
+#pragma unroll
+          for (int j = 0; j < WP; j++) gp[j] = rin[(size_t)qp[j].x * Bs + c];
+#pragma unroll
+          for (int j = 0; j < WPM; j++) gm[j] = din[(size_t)qm[j].x * Bs + c];
+#pragma unroll
+          for (int j = 0; j < WP; j++) z += (double)__uint_as_float(qp[j].y) * gp[j];
+#pragma unroll
+          for (int j = 0; j < WPM; j++) z -= (double)__uint_as_float(qm[j].y) * gm[j];
+        } else {
+          z = lp_row_dot<0>(tp, a.lp.wp, ne, e, rin, Bs, c) - lp_row_dot<0>(tpm, a.lp.wpm, ne, e, din, Bs, c);
+        }
+      }
       double q = 0.0;
 #pragma unroll
-      for (int j = 0; j < 5; j++) q += o.mass[5 * e + j] * a.d_in[(size_t)o.ell_col[5 * e + j] * Bs + c];
-      const size_t ie = (size_t)e * Bs + c;
-      const double d = a.d_in[ie];
-      a.x[ie] += d;
-      const double r = a.r_in[ie] - q;
+      for (int j = 0; j < 5; j++) q += mv[j] * dg[j];
+      const double r = r0 - q;
+      a.x[ie] = x0 + d;
       a.r_out[ie] = r;
-      if (a.last) {
+      if (a.last)
         sums[0] += r * r;
-      } else {
-        double z = 0.0;
-        for (int j = 0; j < a.lp.wp; j++) {
-          const size_t k = (size_t)j * ne + e;
-          z += (double)a.lp.pval[k] * a.r_in[(size_t)a.lp.pcol[k] * Bs + c];
-        }
-        for (int j = 0; j < a.lp.wpm; j++) {
-          const size_t k = (size_t)j * ne + e;
-          z -= (double)a.lp.pmval[k] * a.d_in[(size_t)a.lp.pmcol[k] * Bs + c];
-        }
+      else
         a.d_out[ie] = a.c1 * d + a.c2 * z;
-      }
     }
   }
   if (a.last) wg_partials<1>(L, sums, a.part, a.max_wg);
 }
 
-__global__ __launch_bounds__(kWG) void k_lp_d0(LpD0Args a) {
+template <int WP>
+__global__ __launch_bounds__(kWG) void k_lp_dir(LpDirArgs a) {
   const Lane L = lane_map(a.Bs, a.ops.ne);
   const int c = L.col, Bs = a.Bs, ne = a.ops.ne;
   if (a.colK[c] < a.kneed) return;
   for (int e = L.row0; e < L.rend; e += L.rstride) {
-    double z = 0.0;
-    for (int j = 0; j < a.lp.wp; j++) {
-      const size_t k = (size_t)j * ne + e;
-      z += (double)a.lp.pval[k] * a.r[(size_t)a.lp.pcol[k] * Bs + c];
-    }
-    a.d[(size_t)e * Bs + c] = a.theta_inv * z;
+    const size_t ie = (size_t)e * Bs + c;
+    const double z = lp_row_dot<WP>(a.lp.p, a.lp.wp, ne, e, a.r, Bs, c);
+    a.d_out[ie] = (a.c1 != 0.0 ? a.c1 * a.d_in[ie] : 0.0) + a.c2 * z;
   }
 }
 
@@ -986,6 +1041,7 @@ void set_launch_tuning(const LaunchTune &t) {
   if (g_tune.narrow_rows_per_thread < 1) g_tune.narrow_rows_per_thread = 1;
   if (g_tune.wide_max_wg < 8) g_tune.wide_max_wg = 8;
   if (g_tune.wide_max_wg > 2048) g_tune.wide_max_wg = 2048;
+  if (g_tune.lp_min_cols < 1) g_tune.lp_min_cols = 1;
 }
 int launch_rows_grid(int rows, int Bs) { return grid_rows(rows, Bs); }
 
@@ -999,11 +1055,20 @@ void launch_cg_init(const CgArgs &a, hipStream_t s) {
 void launch_cheb_iter(const ChebArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_cheb_iter, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
 }
+// The icosahedral meshes give P and P M widths 13 and 27 at every level;
+// other widths take the generic loop.
 void launch_cheb_lp_iter(const ChebLpArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_cheb_lp_iter, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+  const bool fixed = a.lp.wp == 13 && a.lp.wpm == 27;
+  if (fixed)
+    hipLaunchKernelGGL((k_cheb_lp_iter<13, 27>), rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_cheb_lp_iter<0, 0>), rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
 }
-void launch_lp_d0(const LpD0Args &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_lp_d0, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+void launch_lp_dir(const LpDirArgs &a, hipStream_t s) {
+  if (a.lp.wp == 13)
+    hipLaunchKernelGGL((k_lp_dir<13>), rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_lp_dir<0>), rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
 }
 void launch_cheb_check(const CheckArgs &a, hipStream_t s) {
   const int ct = a.Bs < 64 ? a.Bs : 64;

@@ -530,7 +530,7 @@ int pa_ops_lp_device_size(const pa_ops *ops, size_t *bytes) {
     pa::lneed(ops && bytes, "NULL argument");
     pa::lneed(ops->lp_ready, "no learned preconditioner attached (pa_ops_lp_attach)");
     const size_t n1 = (size_t)ops->lp_wp * ops->ne, n2 = (size_t)ops->lp_wpm * ops->ne;
-    *bytes = pa::al256(n1 * 4) + pa::al256(n1 * 4) + pa::al256(n2 * 4) + pa::al256(n2 * 4);
+    *bytes = pa::al256(n1 * 8) + pa::al256(n2 * 8);
   });
 }
 
@@ -540,24 +540,26 @@ int pa_ops_lp_bind(pa_ctx *ctx, pa_ops *ops, void *dev_buf) {
     pa::lneed(ops->lp_ready, "no learned preconditioner attached (pa_ops_lp_attach)");
     pa::lneed(((uintptr_t)dev_buf & 255) == 0, "device buffer must be 256-byte aligned");
     PA_HIP(hipSetDevice(ctx->device));
-    char *b = (char *)dev_buf;
     const size_t n1 = (size_t)ops->lp_wp * ops->ne, n2 = (size_t)ops->lp_wpm * ops->ne;
+    auto pack = [](const std::vector<int32_t> &c, const std::vector<float> &v) {
+      std::vector<uint2> out(c.size());
+      for (size_t i = 0; i < c.size(); i++) {
+        uint32_t bits;
+        std::memcpy(&bits, &v[i], 4);
+        out[i] = make_uint2((uint32_t)c[i], bits);
+      }
+      return out;
+    };
+    const std::vector<uint2> hp = pack(ops->lp_pcol, ops->lp_pval), hpm = pack(ops->lp_pmcol, ops->lp_pmval);
+    char *b = (char *)dev_buf;
     pa::DevLp d;
     d.wp = ops->lp_wp;
     d.wpm = ops->lp_wpm;
-    size_t off = 0;
-    d.pcol = (const int32_t *)(b + off);
-    off += pa::al256(n1 * 4);
-    d.pval = (const float *)(b + off);
-    off += pa::al256(n1 * 4);
-    d.pmcol = (const int32_t *)(b + off);
-    off += pa::al256(n2 * 4);
-    d.pmval = (const float *)(b + off);
+    d.p = (const uint2 *)b;
+    d.pm = (const uint2 *)(b + pa::al256(n1 * 8));
     hipStream_t s = ctx->stream;
-    PA_HIP(hipMemcpyAsync((void *)d.pcol, ops->lp_pcol.data(), n1 * 4, hipMemcpyHostToDevice, s));
-    PA_HIP(hipMemcpyAsync((void *)d.pval, ops->lp_pval.data(), n1 * 4, hipMemcpyHostToDevice, s));
-    PA_HIP(hipMemcpyAsync((void *)d.pmcol, ops->lp_pmcol.data(), n2 * 4, hipMemcpyHostToDevice, s));
-    PA_HIP(hipMemcpyAsync((void *)d.pmval, ops->lp_pmval.data(), n2 * 4, hipMemcpyHostToDevice, s));
+    PA_HIP(hipMemcpyAsync((void *)d.p, hp.data(), n1 * 8, hipMemcpyHostToDevice, s));
+    PA_HIP(hipMemcpyAsync((void *)d.pm, hpm.data(), n2 * 8, hipMemcpyHostToDevice, s));
     PA_HIP(hipStreamSynchronize(s));
     ops->lp = d;
     ops->lp_dev = dev_buf;

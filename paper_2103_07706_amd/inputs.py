@@ -145,3 +145,9 @@ WORKLOADS = {
     # level 7, M=64, T=2 h
     "l7_m64": Workload("l7_m64", level=7, nbumps=40, M=64, T=7200.0, dt=3600.0),
 }
+
+# Batches of meshes of uneven size: (level, members) items, M = 64, T = 2 h,
+# 40 bumps, member seeds 0, 1, ... per item.
+BATCHES = {
+    "mixed_l4l5l6": [(4, 16), (5, 8), (6, 4)],
+}

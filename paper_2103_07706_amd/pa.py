@@ -75,7 +75,7 @@ class KernelProfile(ctypes.Structure):
 
 class LaunchTune(ctypes.Structure):
     _fields_ = [("narrow_rows_per_thread", ctypes.c_int32), ("wide_max_wg", ctypes.c_int32),
-                ("best_ms", ctypes.c_double)]
+                ("best_ms", ctypes.c_double), ("lp_min_cols", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -85,7 +85,7 @@ class Stats(ctypes.Structure):
                 ("refinements", ctypes.c_int32), ("guard_trips", ctypes.c_int32),
                 ("resid_max", ctypes.c_double), ("device_ms", ctypes.c_double),
                 ("graph", ctypes.c_int32), ("budget", ctypes.c_int32),
-                ("precond", ctypes.c_int32)]
+                ("precond", ctypes.c_int32), ("lp_solves", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -203,6 +203,22 @@ def _ptr(t):
 
 def _dp(a):
     return a.ctypes.data_as(_D)
+
+
+def get_launch_tune() -> dict:
+    """Process-wide launch shape (pa_get_launch_tune)."""
+    t = LaunchTune()
+    _check(lib().pa_get_launch_tune(ctypes.byref(t)))
+    return {"narrow_rows_per_thread": t.narrow_rows_per_thread, "wide_max_wg": t.wide_max_wg,
+            "lp_min_cols": t.lp_min_cols}
+
+
+def set_launch_tune(**changes):
+    """Change fields of the process-wide launch shape (pa_set_launch_tune)."""
+    cur = get_launch_tune()
+    cur.update(changes)
+    t = LaunchTune(cur["narrow_rows_per_thread"], cur["wide_max_wg"], 0.0, cur["lp_min_cols"])
+    _check(lib().pa_set_launch_tune(ctypes.byref(t)))
 
 
 def solve_cfg(precision=PA_FP64, backward=PA_BACKWARD_PER_TERM, maxit=None, cg_rtol=None,
@@ -417,12 +433,14 @@ class Ops:
         members = U.shape[0]
         key = (f"level{self.mesh.level}_members{members}_M{avg.M}_rtol{cfg.cg_rtol:g}_"
                f"tol{cfg.cheb_tol:g}_bw{cfg.backward}_prec{cfg.precision}_graph{cfg.use_graph}_"
-               f"solver{cfg.solver}")
+               f"solver{cfg.solver}_precond{cfg.precond}")
         table = {}
         if cache and os.path.exists(cache):
             table = json.load(open(cache))
             if key in table:
-                t = LaunchTune(table[key]["narrow_rows_per_thread"], table[key]["wide_max_wg"], 0.0)
+                e = table[key]
+                t = LaunchTune(e["narrow_rows_per_thread"], e["wide_max_wg"], 0.0,
+                               e.get("lp_min_cols", 8))
                 _check(lib().pa_set_launch_tune(ctypes.byref(t)))
                 return dict(table[key], cached=True)
         out = U.new_empty(U.shape)
@@ -431,7 +449,7 @@ class Ops:
         _check(lib().pa_autotune(self.ctx._h, self._h, avg._h, members, _ptr(U), _ptr(out), ws,
                                  nb, ctypes.byref(cfg), ctypes.byref(t)))
         res = {"narrow_rows_per_thread": t.narrow_rows_per_thread, "wide_max_wg": t.wide_max_wg,
-               "best_ms": t.best_ms}
+               "lp_min_cols": t.lp_min_cols, "best_ms": t.best_ms}
         if cache:
             table[key] = res
             with open(cache, "w") as f:
@@ -502,14 +520,15 @@ class Batch:
         _check(lib().pa_batch_run(self.ctx._h, self._h, up, op, ws, nb, ctypes.byref(cfg), st))
         return outs, [s.as_dict() for s in st]
 
-    def set_tune(self, item, narrow_rows_per_thread, wide_max_wg):
-        t = LaunchTune(narrow_rows_per_thread, wide_max_wg, 0.0)
+    def set_tune(self, item, narrow_rows_per_thread, wide_max_wg, lp_min_cols=8):
+        t = LaunchTune(narrow_rows_per_thread, wide_max_wg, 0.0, lp_min_cols)
         _check(lib().pa_batch_set_tune(self._h, item, ctypes.byref(t)))
 
     def get_tune(self, item):
         t = LaunchTune()
         _check(lib().pa_batch_get_tune(self._h, item, ctypes.byref(t)))
-        return {"narrow_rows_per_thread": t.narrow_rows_per_thread, "wide_max_wg": t.wide_max_wg}
+        return {"narrow_rows_per_thread": t.narrow_rows_per_thread, "wide_max_wg": t.wide_max_wg,
+                "lp_min_cols": t.lp_min_cols}
 
     def autotune(self, Us, cfg=None, cache=None):
         """Per-item launch shapes (pa_batch_autotune).  With a JSON cache, an
@@ -519,13 +538,14 @@ class Batch:
         cfg = cfg or solve_cfg()
         keys = [f"level{o.mesh.level}_members{m}_M{self.avg.M}_rtol{cfg.cg_rtol:g}_"
                 f"tol{cfg.cheb_tol:g}_bw{cfg.backward}_prec{cfg.precision}_"
-                f"solver{cfg.solver}_batch" for o, m in self.items]
+                f"solver{cfg.solver}_precond{cfg.precond}_batch" for o, m in self.items]
         table = {}
         if cache and os.path.exists(cache):
             table = json.load(open(cache))
         if all(k in table for k in keys):
             for i, k in enumerate(keys):
-                self.set_tune(i, table[k]["narrow_rows_per_thread"], table[k]["wide_max_wg"])
+                self.set_tune(i, table[k]["narrow_rows_per_thread"], table[k]["wide_max_wg"],
+                              table[k].get("lp_min_cols", 8))
             return [dict(table[k], cached=True) for k in keys]
         outs = [U.new_empty(U.shape) for U in Us]
         up, op = self._ptrs(Us, outs)
@@ -533,7 +553,7 @@ class Batch:
         t = (LaunchTune * len(self.items))()
         _check(lib().pa_batch_autotune(self.ctx._h, self._h, up, op, ws, nb, ctypes.byref(cfg), t))
         res = [{"narrow_rows_per_thread": x.narrow_rows_per_thread, "wide_max_wg": x.wide_max_wg,
-                "best_ms": x.best_ms} for x in t]
+                "lp_min_cols": x.lp_min_cols, "best_ms": x.best_ms} for x in t]
         if cache:
             table.update(dict(zip(keys, res)))
             with open(cache, "w") as f:

@@ -126,45 +126,64 @@ def test_gpu_lp_attach_narrows_the_spectrum():
     assert kl < kj, (kl, kj)
 
 
-def test_gpu_lp_solves_parity():
+def _set_lp_min_cols(pa, n):
+    t = pa.LaunchTune()
+    pa._check(pa.lib().pa_get_launch_tune(t))
+    keep = t.lp_min_cols
+    t.lp_min_cols = n
+    pa._check(pa.lib().pa_set_launch_tune(t))
+    return keep
+
+
+@pytest.mark.parametrize("lp_min_cols", [1, 8])
+def test_gpu_lp_solves_parity(lp_min_cols):
     """Averaged right-hand side with the learned preconditioner in the
     Chebyshev mass solves: parity with the oracle (Jacobi CG) at 1e-12, same
     result as the Jacobi Chebyshev path to the solve tolerance, fewer steps
-    per solve, graph replays equal to eager."""
+    in the learned solves, graph replays equal to eager.  lp_min_cols = 1:
+    every solve learned (single-column recurrences take the one-kernel step);
+    8: only the 16-column nonlinear solves (two-kernel step)."""
     import torch
     from paper_2103_07706_amd import pa
     lp, _ = _trained()
     om, oo, lm, lo, mm, lb = pair(3)
     pa.attach_learned(lo, lp, bf16=True)
-    U = bumps(om, [2])
-    Ud = to_dev(mm.state(U))
-    avg = pa.Avg(8, 3600.0)
-    base = dict(backward=pa.PA_BACKWARD_CLENSHAW, weight_cut=0.0, solver=pa.PA_SOLVER_CHEBYSHEV)
-    out_l, st_l = lo.phase_avg_rhs(avg, Ud, pa.solve_cfg(precond=pa.PA_PRECOND_LEARNED, **base,
-                                                         **PARITY))
-    out_j, st_j = lo.phase_avg_rhs(avg, Ud, pa.solve_cfg(**base, **PARITY))
-    assert st_l["precond"] == pa.PA_PRECOND_LEARNED and st_j["precond"] == pa.PA_PRECOND_JACOBI
-    assert st_l["cg_iters_max"] < st_j["cg_iters_max"]
-    ref = oo.phase_avg_rhs(lb, avg.s, avg.w, U[0], tol=1e-13, rtol=1e-14)
-    got = mm.back(out_l.cpu().numpy())[0]
-    assert rel_w(oo, got, ref) < 1e-12
-    gj = mm.back(out_j.cpu().numpy())[0]
-    assert rel_w(oo, got, gj) < 1e-12
-    # metric tolerances, graph capture and replay
-    gcfg = pa.solve_cfg(precond=pa.PA_PRECOND_LEARNED, use_graph=True, cheb_tol=1e-6,
-                        cg_rtol=1e-10, **{k: v for k, v in base.items() if k != "weight_cut"})
-    eager, _ = lo.phase_avg_rhs(avg, Ud, pa.solve_cfg(
-        precond=pa.PA_PRECOND_LEARNED, cheb_tol=1e-6, cg_rtol=1e-10,
-        **{k: v for k, v in base.items() if k != "weight_cut"}))
-    eager = eager.cpu().numpy()
-    out = torch.empty_like(Ud)
-    for i in range(3):
-        out.fill_(float("nan"))
-        _, st = lo.phase_avg_rhs(avg, Ud, gcfg, out=out)
-        assert st["graph"] == 1 and st["precond"] == pa.PA_PRECOND_LEARNED
-        assert np.array_equal(out.cpu().numpy(), eager), i
-        lo.swe_nonlinear(Ud)
-        torch.cuda.synchronize()
+    keep = _set_lp_min_cols(pa, lp_min_cols)
+    try:
+        U = bumps(om, [2])
+        Ud = to_dev(mm.state(U))
+        avg = pa.Avg(16, 3600.0)
+        base = dict(backward=pa.PA_BACKWARD_CLENSHAW, solver=pa.PA_SOLVER_CHEBYSHEV)
+        out_l, st_l = lo.phase_avg_rhs(avg, Ud, pa.solve_cfg(
+            precond=pa.PA_PRECOND_LEARNED, weight_cut=0.0, **base, **PARITY))
+        out_j, st_j = lo.phase_avg_rhs(avg, Ud, pa.solve_cfg(weight_cut=0.0, **base, **PARITY))
+        assert st_l["precond"] == pa.PA_PRECOND_LEARNED and st_j["precond"] == pa.PA_PRECOND_JACOBI
+        if lp_min_cols == 1:
+            assert st_l["lp_solves"] == st_l["solves"]
+        else:
+            assert 1 <= st_l["lp_solves"] < st_l["solves"]
+        assert st_j["lp_solves"] == 0
+        assert st_l["cg_iters"] < st_j["cg_iters"]  # fewer steps in total
+        ref = oo.phase_avg_rhs(lb, avg.s, avg.w, U[0], tol=1e-13, rtol=1e-14)
+        got = mm.back(out_l.cpu().numpy())[0]
+        assert rel_w(oo, got, ref) < 1e-12
+        gj = mm.back(out_j.cpu().numpy())[0]
+        assert rel_w(oo, got, gj) < 1e-12
+        # metric tolerances, graph capture and replay
+        mcfg = dict(precond=pa.PA_PRECOND_LEARNED, cheb_tol=1e-6, cg_rtol=1e-10, **base)
+        eager, _ = lo.phase_avg_rhs(avg, Ud, pa.solve_cfg(**mcfg))
+        eager = eager.cpu().numpy()
+        gcfg = pa.solve_cfg(use_graph=True, **mcfg)
+        out = torch.empty_like(Ud)
+        for i in range(3):
+            out.fill_(float("nan"))
+            _, st = lo.phase_avg_rhs(avg, Ud, gcfg, out=out)
+            assert st["graph"] == 1 and st["precond"] == pa.PA_PRECOND_LEARNED
+            assert np.array_equal(out.cpu().numpy(), eager), i
+            lo.swe_nonlinear(Ud)
+            torch.cuda.synchronize()
+    finally:
+        _set_lp_min_cols(pa, keep)
 
 
 def test_gpu_lp_requires_binding():
