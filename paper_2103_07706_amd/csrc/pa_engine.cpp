@@ -215,17 +215,10 @@ void Engine::cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_i
       a.c1 = c1[i];
       a.c2 = c2[i];
       a.last = i + 1 == k ? 1 : 0;
-      if (prof) {
-        hipEvent_t e0 = take_event(), e1 = take_event();
-        PA_HIP(hipEventRecord(e0, s_));
-        launch_cheb_lp_iter(a, s_);
-        PA_HIP(hipEventRecord(e1, s_));
-        prof_ev_.push_back(e0);
-        prof_ev_.push_back(e1);
-      } else {
-        launch_cheb_lp_iter(a, s_);
-      }
+      if (prof && i == 0) bracket_begin();
+      launch_cheb_lp_iter(a, s_);
     }
+    if (prof) bracket_end(k);
   } else if (lp) {
     // wide blocks: x and r updated in place by the Jacobi step kernel without
     // its direction, then d_{k+1} = c1 d_k + c2 P r_{k+1} (fewer gathers
@@ -256,12 +249,7 @@ void Engine::cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_i
     for (int i = 0; i < k; i++) {
       a.d_in = d[i & 1];
       a.last = i + 1 == k ? 1 : 0;
-      hipEvent_t e0 = nullptr, e1 = nullptr;
-      if (prof) {
-        e0 = take_event();
-        e1 = take_event();
-        PA_HIP(hipEventRecord(e0, s_));
-      }
+      if (prof && i == 0) bracket_begin();
       launch_cheb_iter(a, s_);
       if (!a.last) {
         b.d_in = d[i & 1];
@@ -270,12 +258,8 @@ void Engine::cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_i
         b.c2 = c2[i];
         launch_lp_dir(b, s_);
       }
-      if (prof) {
-        PA_HIP(hipEventRecord(e1, s_));
-        prof_ev_.push_back(e0);
-        prof_ev_.push_back(e1);
-      }
     }
+    if (prof) bracket_end(2 * k - 1);
   } else {
     ChebArgs a{};
     a.ops = ops_->d;
@@ -288,26 +272,16 @@ void Engine::cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_i
     a.max_wg = rb_.max_wg;
     const bool prof = ctx_->prof_kernel == PA_KERNEL_CHEB_ITER;
     a.prof = prof ? st_.prof : nullptr;
-    auto timed = [&](auto &&launch) {
-      if (prof) {
-        hipEvent_t e0 = take_event(), e1 = take_event();
-        PA_HIP(hipEventRecord(e0, s_));
-        launch();
-        PA_HIP(hipEventRecord(e1, s_));
-        prof_ev_.push_back(e0);
-        prof_ev_.push_back(e1);
-      } else {
-        launch();
-      }
-    };
     for (int i = 0; i < k; i++) {
       a.d_in = d[i & 1];
       a.d_out = d[(i + 1) & 1];
       a.c1 = c1[i];
       a.c2 = c2[i];
       a.last = i + 1 == k ? 1 : 0;
-      timed([&] { launch_cheb_iter(a, s_); });
+      if (prof && i == 0) bracket_begin();
+      launch_cheb_iter(a, s_);
     }
+    if (prof) bracket_end(k);
   }
   if (lp) stats.precond = PA_PRECOND_LEARNED;
   if (lp) lp_prof_wide_ = Bs > 4;
@@ -405,13 +379,14 @@ void Engine::finish() {
   PA_HIP(hipMemcpyAsync(h, st_.fail, 7 * sizeof(int), hipMemcpyDeviceToHost, s_));
   PA_HIP(hipStreamSynchronize(s_));
   if (ctx_->prof_kernel != PA_KERNEL_NONE) {
-    for (size_t i = 0; i + 1 < prof_ev_.size(); i += 2) {
+    for (const ProfSpan &p : prof_ev_) {
       float t = 0;
-      PA_HIP(hipEventElapsedTime(&t, prof_ev_[i], prof_ev_[i + 1]));
+      PA_HIP(hipEventElapsedTime(&t, p.e0, p.e1));
       ctx_->prof_ms += t;
+      ctx_->prof_launches += p.n;
+      ctx_->prof_pool.push_back(p.e0);
+      ctx_->prof_pool.push_back(p.e1);
     }
-    ctx_->prof_launches += (int64_t)prof_ev_.size() / 2;
-    for (auto ev : prof_ev_) ctx_->prof_pool.push_back(ev);
     prof_ev_.clear();
     // algorithmic bytes: per active column and row, the vectors the kernel
     // must stream once; per row and launch, the matrix row it reads
@@ -473,6 +448,35 @@ void Engine::diag(Blk X, double *out) {
   launch_finalize(f, s_);
 }
 
+// Measurement hook.  The steps of one mass solve are launched back to back
+// with nothing between them, so one event pair around the sequence times n
+// launches (kernel time plus the dispatch gaps between them); events around
+// each launch would add their own overhead to every launch.  CG iterations
+// alternate with other kernels and are timed one by one with events that
+// the dispatch itself records (arm_events).
+void Engine::bracket_begin() {
+  ProfSpan p;
+  p.e0 = take_event();
+  p.e1 = take_event();
+  PA_HIP(hipEventRecord(p.e0, s_));
+  prof_ev_.push_back(p);
+}
+
+void Engine::bracket_end(int n) {
+  ProfSpan &p = prof_ev_.back();
+  PA_HIP(hipEventRecord(p.e1, s_));
+  p.n = n;
+}
+
+void Engine::arm_events() {
+  ProfSpan p;
+  p.e0 = take_event();
+  p.e1 = take_event();
+  p.n = 1;
+  arm_launch_events(p.e0, p.e1);
+  prof_ev_.push_back(p);
+}
+
 hipEvent_t Engine::take_event() {
   if (!ctx_->prof_pool.empty()) {
     hipEvent_t e = ctx_->prof_pool.back();
@@ -523,16 +527,8 @@ void Engine::cg(double *x, int Bs, const int *colK, int kneed, int nwg_init) {
   double *part[2] = {rb_.partA, rb_.partB};
   int *hflag = (int *)ctx_->host_flag;
   auto timed = [&](auto launch) {
-    if (ctx_->prof_kernel != PA_KERNEL_CG_ITER) {
-      launch();
-      return;
-    }
-    hipEvent_t e0 = take_event(), e1 = take_event();
-    PA_HIP(hipEventRecord(e0, s_));
+    if (ctx_->prof_kernel == PA_KERNEL_CG_ITER) arm_events();
     launch();
-    PA_HIP(hipEventRecord(e1, s_));
-    prof_ev_.push_back(e0);
-    prof_ev_.push_back(e1);
   };
   auto poll = [&](int slot) {
     PA_HIP(hipMemcpyAsync(hflag, st_.cnt + slot, sizeof(int), hipMemcpyDeviceToHost, s_));

@@ -124,8 +124,15 @@ class Engine {
             const double *x1 = nullptr, double a2 = 0, const double *x2 = nullptr);
   void upload(void *dst, const void *src, size_t bytes);
   hipEvent_t take_event();
+  void arm_events();
+  void bracket_begin();
+  void bracket_end(int n);
+  struct ProfSpan {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int n = 0;  // launches between the two events
+  };
   void diag(Blk X, double *out);
-  std::vector<hipEvent_t> prof_ev_;
+  std::vector<ProfSpan> prof_ev_;
 
   // phase average on a block of member columns X -> out (both [n][Bm])
  public:

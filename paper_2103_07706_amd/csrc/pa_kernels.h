@@ -239,6 +239,11 @@ struct DiagArgs {
 };
 
 int launch_max_wg();
+// Measurement hook: the next launch of a profiled kernel (Chebyshev, learned
+// and CG steps) records e0 and e1 as part of its dispatch, so that their
+// elapsed time is the kernel's own duration.
+void arm_launch_events(hipEvent_t e0, hipEvent_t e1);
+bool launch_events_armed();
 LaunchTune launch_tuning();
 void set_launch_tuning(const LaunchTune &t);
 int launch_rows_grid(int rows, int Bs);

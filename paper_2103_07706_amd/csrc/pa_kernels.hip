@@ -14,6 +14,8 @@
 // (ticket counters, no floating-point atomics).
 #include <hip/hip_runtime.h>
 
+#include <hip/hip_ext.h>
+
 #include "pa_kernels.h"
 
 namespace pa {
@@ -1009,6 +1011,19 @@ namespace {
 // thread keeps the launch short and the partial sums few.  Wider ones fill
 // the 256 CUs several times over, split over the column tiles.
 LaunchTune g_tune;  // process-wide launch shape (see set_launch_tuning)
+// measurement hook: events that the next launch of a profiled kernel
+// records as part of its dispatch (start and end of the kernel itself)
+hipEvent_t g_ev0 = nullptr, g_ev1 = nullptr;
+
+template <typename K, typename A>
+void launch_timed(K kernel, dim3 grid, hipStream_t s, const A &a) {
+  if (g_ev0) {
+    hipExtLaunchKernelGGL(kernel, grid, dim3(kWG), 0, s, g_ev0, g_ev1, 0, a);
+    g_ev0 = g_ev1 = nullptr;
+  } else {
+    hipLaunchKernelGGL(kernel, grid, dim3(kWG), 0, s, a);
+  }
+}
 
 int grid_rows(int rows, int Bs) {
   const int ct = Bs < 64 ? Bs : 64;
@@ -1052,23 +1067,28 @@ void launch_stiff(const StiffArgs &a, hipStream_t s) {
 void launch_cg_init(const CgArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_init, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
 }
+void arm_launch_events(hipEvent_t e0, hipEvent_t e1) {
+  g_ev0 = e0;
+  g_ev1 = e1;
+}
+bool launch_events_armed() { return g_ev0 != nullptr; }
 void launch_cheb_iter(const ChebArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_cheb_iter, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+  launch_timed(k_cheb_iter, rows_grid(a.ops.ne, a.Bs), s, a);
 }
 // The icosahedral meshes give P and P M widths 13 and 27 at every level;
 // other widths take the generic loop.
 void launch_cheb_lp_iter(const ChebLpArgs &a, hipStream_t s) {
   const bool fixed = a.lp.wp == 13 && a.lp.wpm == 27;
   if (fixed)
-    hipLaunchKernelGGL((k_cheb_lp_iter<13, 27>), rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+    launch_timed(k_cheb_lp_iter<13, 27>, rows_grid(a.ops.ne, a.Bs), s, a);
   else
-    hipLaunchKernelGGL((k_cheb_lp_iter<0, 0>), rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+    launch_timed(k_cheb_lp_iter<0, 0>, rows_grid(a.ops.ne, a.Bs), s, a);
 }
 void launch_lp_dir(const LpDirArgs &a, hipStream_t s) {
   if (a.lp.wp == 13)
-    hipLaunchKernelGGL((k_lp_dir<13>), rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+    launch_timed(k_lp_dir<13>, rows_grid(a.ops.ne, a.Bs), s, a);
   else
-    hipLaunchKernelGGL((k_lp_dir<0>), rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+    launch_timed(k_lp_dir<0>, rows_grid(a.ops.ne, a.Bs), s, a);
 }
 void launch_cheb_check(const CheckArgs &a, hipStream_t s) {
   const int ct = a.Bs < 64 ? a.Bs : 64;
@@ -1083,7 +1103,7 @@ void launch_refine(const RefineArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_refine, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
 }
 void launch_cg_iter(const CgArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_iter, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+  launch_timed(k_cg_iter, rows_grid(a.ops.ne, a.Bs), s, a);
 }
 void launch_combine(const CombineArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_combine, dim3(grid_flat((size_t)a.nrows * a.BsR)), dim3(kWG), 0, s, a);
