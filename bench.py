@@ -162,6 +162,9 @@ def bench_batch(args):
     forms = {}
     if args.precond in ("jacobi", "both"):
         forms["plain"] = (pa.solve_cfg(precond=pa.PA_PRECOND_JACOBI, **base), None)
+        if args.precision == "fp64" and args.solver == "chebyshev":
+            forms["fp32_refined"] = (pa.solve_cfg(
+                precond=pa.PA_PRECOND_JACOBI, **dict(base, precision=pa.PA_FP32_REFINED)), None)
     lp_rec = None
     if args.precond in ("learned", "both"):
         lp, lp_rec = train_learned(pa, ctx, phys, {o.mesh.level: o for o in ops}, args.lp_steps)
@@ -178,7 +181,8 @@ def bench_batch(args):
         if lmin is not None:
             for i in range(len(items)):
                 t = batch.get_tune(i)
-                batch.set_tune(i, t["narrow_rows_per_thread"], t["wide_max_wg"], lmin)
+                batch.set_tune(i, t["narrow_rows_per_thread"], t["wide_max_wg"], lmin,
+                               t["mixed_min_cols"])
             tune = [batch.get_tune(i) for i in range(len(items))]
         for _ in range(args.warmup):
             batch.run(Us, cfg, outs)
@@ -192,7 +196,7 @@ def bench_batch(args):
         res[name] = {"value": members * args.steps / el, "ms_per_step": 1e3 * el / args.steps,
                      "lp_solves": [x["lp_solves"] for x in st], "solves": [x["solves"] for x in st],
                      "graph": [x["graph"] for x in st], "launch_tune": tune}
-    for name in ("learned", "hybrid"):
+    for name in ("learned", "hybrid", "fp32_refined"):
         if name in res and "plain" in res:
             res[f"{name}_over_plain"] = res[name]["value"] / res["plain"]["value"]
     head = max((k for k in res if k in forms), key=lambda k: res[k]["value"])
@@ -245,6 +249,11 @@ def main():
     forms = {}
     if args.precond in ("jacobi", "both"):
         forms["plain"] = (pa.solve_cfg(precond=pa.PA_PRECOND_JACOBI, **base), None)
+        if args.precision == "fp64" and args.solver == "chebyshev":
+            # FP32 solves with FP64 refinement on the blocks where the
+            # autotuner finds them faster, FP64 steps elsewhere
+            forms["fp32_refined"] = (pa.solve_cfg(
+                precond=pa.PA_PRECOND_JACOBI, **dict(base, precision=pa.PA_FP32_REFINED)), None)
     lp_rec = None
     if args.precond in ("learned", "both"):
         # the network is trained on the GPU on meshes of levels 4 to 6 (this
@@ -292,7 +301,7 @@ def main():
                         "mass_solve_steps_total": r["stats"]["cg_iters"],
                         "launch_tune": r["tune"], "autotune": r["autotune"]}
                  for name, r in results.items()}
-    for name in ("learned", "hybrid"):
+    for name in ("learned", "hybrid", "fp32_refined"):
         if name in forms_rec and "plain" in forms_rec:
             forms_rec[f"{name}_over_plain"] = forms_rec[name]["value"] / forms_rec["plain"]["value"]
     rec = {
@@ -306,12 +315,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if head["cfg"].precision == pa.PA_FP64 else "f64+f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "level": wl.level, "cells": mesh.nc,
                    "edges": mesh.ne, "M": wl.M, "T_s": wl.T, "members": wl.members,
                    "cheb_tol": 1e-6, "cg_rtol": 1e-10, "backward": args.backward,
-                   "precision": args.precision, "mass_solver": args.solver,
+                   "precision": "fp64" if head["cfg"].precision == pa.PA_FP64 else "fp32_refined",
+                   "mass_solver": args.solver,
                    "form": head_name,
                    "preconditioner": "learned" if head["learned"] else "jacobi",
                    "lambda_bar": lam, "kmax": stats["kmax"], "ksum": stats["ksum"],

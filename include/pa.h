@@ -122,10 +122,12 @@ int pa_avg_destroy(pa_avg *avg);
 enum { PA_FP64 = 0, PA_FP32_REFINED = 1 };
 enum { PA_BACKWARD_PER_TERM = 0, PA_BACKWARD_CLENSHAW = 1 };
 typedef struct {
-  int32_t precision;   /* PA_FP64, or PA_FP32_REFINED: every mass solve runs
-                          FP32 Chebyshev inner solves (FP32 copy of M_u,
-                          to max(inner_rtol, 1e-6)) inside FP64 refinement
-                          (x += x32, r -= M x32 with the FP64 matrix); the
+  int32_t precision;   /* PA_FP64, or PA_FP32_REFINED: mass solves on column
+                          blocks at least mixed_min_cols wide (launch shape,
+                          below) run FP32 Chebyshev inner solves (FP32 copy
+                          of M_u, to max(inner_rtol, 1e-6)) inside FP64
+                          refinement (x += x32, r -= M x32 with the FP64
+                          matrix), narrower ones FP64 Chebyshev steps; the
                           final FP64 residual is checked against cg_rtol and
                           a failed check repeats the call in FP64.  The
                           recurrences, stiffness, N and all sums stay FP64. */
@@ -256,15 +258,21 @@ int pa_ctx_set_cg_budget(pa_ctx *ctx, double cg_rtol, int iters);
  * narrowest column block whose mass solves take learned steps when the
  * learned preconditioner is enabled (narrower blocks take Jacobi steps; a
  * learned step costs more than a Jacobi step, so fewer steps pay only on
- * wide enough blocks).  pa_autotune times pa_phase_avg_rhs over a small set
- * of shapes on the given problem (the workspace must fit it), then, with
- * the learned preconditioner enabled in cfg, over lp_min_cols in {1, 8, 64,
- * never}, and keeps the fastest; it returns the choice and the best time. */
+ * wide enough blocks).  mixed_min_cols likewise is the narrowest block
+ * whose mass solves run as FP32 solves with FP64 refinement when cfg asks
+ * for PA_FP32_REFINED (narrower blocks take FP64 steps, which are launch
+ * bound there; the FP64 residual check is the same).  pa_autotune times
+ * pa_phase_avg_rhs over a small set of shapes on the given problem (the
+ * workspace must fit it), then, with the learned preconditioner or FP32
+ * refinement enabled in cfg, over lp_min_cols and mixed_min_cols in {1, 8,
+ * 64, never}, and keeps the fastest; it returns the choice and the best
+ * time. */
 typedef struct {
   int32_t narrow_rows_per_thread;
   int32_t wide_max_wg;
   double best_ms;
   int32_t lp_min_cols;
+  int32_t mixed_min_cols;
 } pa_launch_tune;
 int pa_get_launch_tune(pa_launch_tune *out);
 int pa_set_launch_tune(const pa_launch_tune *t);

@@ -131,6 +131,7 @@ std::vector<unsigned char> batch_key(const pa_batch *b, const double *const *U,
     put(k, t.narrow_rows_per_thread);
     put(k, t.wide_max_wg);
     put(k, t.lp_min_cols);
+    put(k, t.mixed_min_cols);
   }
   return k;
 }
@@ -325,10 +326,11 @@ int pa_batch_set_tune(pa_batch *b, int item, const pa_launch_tune *t) {
     bneed(b && t && item >= 0 && item < b->n(), "bad arguments");
     bneed(t->narrow_rows_per_thread >= 1 && t->narrow_rows_per_thread <= 64, "rows per thread in [1, 64]");
     bneed(t->wide_max_wg >= 8 && t->wide_max_wg <= 2048, "wide_max_wg in [8, 2048]");
-    bneed(t->lp_min_cols >= 1, "lp_min_cols >= 1");
+    bneed(t->lp_min_cols >= 1 && t->mixed_min_cols >= 1, "lp_min_cols, mixed_min_cols >= 1");
     b->tune[item].narrow_rows_per_thread = t->narrow_rows_per_thread;
     b->tune[item].wide_max_wg = t->wide_max_wg;
     b->tune[item].lp_min_cols = t->lp_min_cols;
+    b->tune[item].mixed_min_cols = t->mixed_min_cols;
     b->tuned[item] = true;
   });
 }
@@ -340,6 +342,7 @@ int pa_batch_get_tune(const pa_batch *b, int item, pa_launch_tune *out) {
     out->narrow_rows_per_thread = t.narrow_rows_per_thread;
     out->wide_max_wg = t.wide_max_wg;
     out->lp_min_cols = t.lp_min_cols;
+    out->mixed_min_cols = t.mixed_min_cols;
     out->best_ms = 0.0;
   });
 }
@@ -391,18 +394,27 @@ int pa_batch_autotune(pa_ctx *ctx, pa_batch *b, const double *const *U_dev,
           t.wide_max_wg = cap;
           trial(t);
         }
-      if (c.precond == PA_PRECOND_LEARNED)
-        for (int lmin : {1, 8, 64, 1 << 30}) {
-          pa::LaunchTune t = best_t;
+      for (int lmin : {1, 8, 64, 1 << 30}) {
+        pa::LaunchTune t = best_t;
+        if (c.precond == PA_PRECOND_LEARNED) {
           t.lp_min_cols = lmin;
           trial(t);
         }
+      }
+      for (int lmin : {1, 8, 64, 1 << 30}) {
+        pa::LaunchTune t = best_t;
+        if (c.precision == PA_FP32_REFINED) {
+          t.mixed_min_cols = lmin;
+          trial(t);
+        }
+      }
       b->tune[i] = best_t;
       b->tuned[i] = true;
       if (out) {
         out[i].narrow_rows_per_thread = best_t.narrow_rows_per_thread;
         out[i].wide_max_wg = best_t.wide_max_wg;
         out[i].lp_min_cols = best_t.lp_min_cols;
+        out[i].mixed_min_cols = best_t.mixed_min_cols;
         out[i].best_ms = best;
       }
     }

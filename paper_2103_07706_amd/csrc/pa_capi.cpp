@@ -514,6 +514,7 @@ int pa_get_launch_tune(pa_launch_tune *out) {
     out->narrow_rows_per_thread = t.narrow_rows_per_thread;
     out->wide_max_wg = t.wide_max_wg;
     out->lp_min_cols = t.lp_min_cols;
+    out->mixed_min_cols = t.mixed_min_cols;
     out->best_ms = 0.0;
   });
 }
@@ -523,11 +524,12 @@ int pa_set_launch_tune(const pa_launch_tune *t) {
     need(t != nullptr, "t is NULL");
     need(t->narrow_rows_per_thread >= 1 && t->narrow_rows_per_thread <= 64, "rows per thread in [1, 64]");
     need(t->wide_max_wg >= 8 && t->wide_max_wg <= 2048, "wide_max_wg in [8, 2048]");
-    need(t->lp_min_cols >= 1, "lp_min_cols >= 1");
+    need(t->lp_min_cols >= 1 && t->mixed_min_cols >= 1, "lp_min_cols, mixed_min_cols >= 1");
     pa::LaunchTune lt;
     lt.narrow_rows_per_thread = t->narrow_rows_per_thread;
     lt.wide_max_wg = t->wide_max_wg;
     lt.lp_min_cols = t->lp_min_cols;
+    lt.mixed_min_cols = t->mixed_min_cols;
     pa::set_launch_tuning(lt);
   });
 }
@@ -570,10 +572,10 @@ int pa_autotune(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int members, 
             best_t = t;
           }
         }
-      if (c.precond == PA_PRECOND_LEARNED)
+      auto search = [&](int pa::LaunchTune::*field) {
         for (int lmin : {1, 8, 64, kLpNever}) {
           pa::LaunchTune t = best_t;
-          t.lp_min_cols = lmin;
+          t.*field = lmin;
           pa::set_launch_tuning(t);
           time_once();
           double ms = std::min(time_once(), time_once());
@@ -582,6 +584,9 @@ int pa_autotune(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int members, 
             best_t = t;
           }
         }
+      };
+      if (c.precond == PA_PRECOND_LEARNED) search(&pa::LaunchTune::lp_min_cols);
+      if (c.precision == PA_FP32_REFINED) search(&pa::LaunchTune::mixed_min_cols);
     } catch (...) {
       pa::set_launch_tuning(keep);
       throw;
@@ -590,6 +595,7 @@ int pa_autotune(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int members, 
     out->narrow_rows_per_thread = best_t.narrow_rows_per_thread;
     out->wide_max_wg = best_t.wide_max_wg;
     out->lp_min_cols = best_t.lp_min_cols;
+    out->mixed_min_cols = best_t.mixed_min_cols;
     out->best_ms = best;
   });
 }

@@ -171,6 +171,19 @@ void Engine::mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_
 
 // Reduction-free mass solve: the set-up kernel wrote r_0 (r), x_0 (x),
 // d_0 = D^-1 r_0 / theta (p) and partials of |r_0|^2 (partA).
+// The mass solve after a set-up kernel.  With FP32 refinement enabled, the
+// refined solve runs on blocks at least mixed_min_cols wide (its FP32 steps
+// halve the bytes of a step, which pays where steps are bandwidth bound);
+// narrower blocks, whose steps are launch-latency bound, take FP64 steps.
+void Engine::mass_solve(double *x, int Bs, const int *colK, int kneed, int nwg_init) {
+  if (mixed() && Bs >= launch_tuning().mixed_min_cols)
+    mixed_solve(x, Bs, colK, kneed, nwg_init);
+  else if (cheb() || mixed())
+    cheb_solve(x, Bs, colK, kneed, nwg_init);
+  else
+    cg(x, Bs, colK, kneed, nwg_init);
+}
+
 // Learned or Jacobi steps for a solve on Bs columns.  A learned step moves
 // more bytes than a Jacobi step (the P and P M rows, and gathers over two and
 // three rings of neighbours against one), so fewer steps pay only on wide
@@ -652,13 +665,7 @@ void Engine::lstep(Blk in, Blk out, const Blk *A, const Blk *B, double scale, co
     a.part_rr = rb_.partA;
   }
   launch_stiff(a, s_);
-  const int nwg_init = launch_rows_grid(std::max(ne_, nc_), in.Bs);
-  if (mixed())
-    mixed_solve(out.p, in.Bs, colK, kneed, nwg_init);
-  else if (cheb())
-    cheb_solve(out.p, in.Bs, colK, kneed, nwg_init);
-  else
-    cg(out.p, in.Bs, colK, kneed, nwg_init);
+  mass_solve(out.p, in.Bs, colK, kneed, launch_rows_grid(std::max(ne_, nc_), in.Bs));
 }
 
 // acc = sum_k coef_k (.) R_k(X) over the real Chebyshev recurrence, with the
@@ -724,12 +731,7 @@ void Engine::nonlinear_block(Blk E, Blk Y, const int *colK) {
     gth.part_rr = rb_.partA;
   }
   launch_nl_gather(gth, s_);
-  if (mixed())
-    mixed_solve(Y.p, E.Bs, colK, 0, launch_rows_grid(ne_, E.Bs));
-  else if (cheb())
-    cheb_solve(Y.p, E.Bs, colK, 0, launch_rows_grid(ne_, E.Bs));
-  else
-    cg(Y.p, E.Bs, colK, 0, launch_rows_grid(ne_, E.Bs));
+  mass_solve(Y.p, E.Bs, colK, 0, launch_rows_grid(ne_, E.Bs));
 }
 
 // ------------------------------------------------------------- exponential

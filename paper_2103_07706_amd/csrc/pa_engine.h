@@ -102,6 +102,7 @@ class Engine {
              int kneed, const AccSpec *acc);
   void cg(double *x, int Bs, const int *colK, int kneed, int nwg_init);
   void cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_init);
+  void mass_solve(double *x, int Bs, const int *colK, int kneed, int nwg_init);
   bool cheb() const { return cfg_.solver == PA_SOLVER_CHEBYSHEV; }
   bool mixed() const { return cfg_.precision == PA_FP32_REFINED; }
   void mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_init);

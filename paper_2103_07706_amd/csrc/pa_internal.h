@@ -118,9 +118,10 @@ struct LaunchTune {
   int narrow_rows_per_thread = 4;  // batches of <= 4 columns
   int wide_max_wg = 2048;          // workgroups per column tile, wider batches
   int lp_min_cols = 8;             // learned mass-solve steps on blocks this wide or wider
+  int mixed_min_cols = 8;          // FP32-refined mass solves on blocks this wide or wider
   bool operator==(const LaunchTune &o) const {
     return narrow_rows_per_thread == o.narrow_rows_per_thread && wide_max_wg == o.wide_max_wg &&
-           lp_min_cols == o.lp_min_cols;
+           lp_min_cols == o.lp_min_cols && mixed_min_cols == o.mixed_min_cols;
   }
 };
 

@@ -1057,6 +1057,7 @@ void set_launch_tuning(const LaunchTune &t) {
   if (g_tune.wide_max_wg < 8) g_tune.wide_max_wg = 8;
   if (g_tune.wide_max_wg > 2048) g_tune.wide_max_wg = 2048;
   if (g_tune.lp_min_cols < 1) g_tune.lp_min_cols = 1;
+  if (g_tune.mixed_min_cols < 1) g_tune.mixed_min_cols = 1;
 }
 int launch_rows_grid(int rows, int Bs) { return grid_rows(rows, Bs); }
 

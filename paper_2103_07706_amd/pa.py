@@ -75,7 +75,8 @@ class KernelProfile(ctypes.Structure):
 
 class LaunchTune(ctypes.Structure):
     _fields_ = [("narrow_rows_per_thread", ctypes.c_int32), ("wide_max_wg", ctypes.c_int32),
-                ("best_ms", ctypes.c_double), ("lp_min_cols", ctypes.c_int32)]
+                ("best_ms", ctypes.c_double), ("lp_min_cols", ctypes.c_int32),
+                ("mixed_min_cols", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -210,14 +211,15 @@ def get_launch_tune() -> dict:
     t = LaunchTune()
     _check(lib().pa_get_launch_tune(ctypes.byref(t)))
     return {"narrow_rows_per_thread": t.narrow_rows_per_thread, "wide_max_wg": t.wide_max_wg,
-            "lp_min_cols": t.lp_min_cols}
+            "lp_min_cols": t.lp_min_cols, "mixed_min_cols": t.mixed_min_cols}
 
 
 def set_launch_tune(**changes):
     """Change fields of the process-wide launch shape (pa_set_launch_tune)."""
     cur = get_launch_tune()
     cur.update(changes)
-    t = LaunchTune(cur["narrow_rows_per_thread"], cur["wide_max_wg"], 0.0, cur["lp_min_cols"])
+    t = LaunchTune(cur["narrow_rows_per_thread"], cur["wide_max_wg"], 0.0, cur["lp_min_cols"],
+                   cur["mixed_min_cols"])
     _check(lib().pa_set_launch_tune(ctypes.byref(t)))
 
 
@@ -440,7 +442,7 @@ class Ops:
             if key in table:
                 e = table[key]
                 t = LaunchTune(e["narrow_rows_per_thread"], e["wide_max_wg"], 0.0,
-                               e.get("lp_min_cols", 8))
+                               e.get("lp_min_cols", 8), e.get("mixed_min_cols", 8))
                 _check(lib().pa_set_launch_tune(ctypes.byref(t)))
                 return dict(table[key], cached=True)
         out = U.new_empty(U.shape)
@@ -449,7 +451,8 @@ class Ops:
         _check(lib().pa_autotune(self.ctx._h, self._h, avg._h, members, _ptr(U), _ptr(out), ws,
                                  nb, ctypes.byref(cfg), ctypes.byref(t)))
         res = {"narrow_rows_per_thread": t.narrow_rows_per_thread, "wide_max_wg": t.wide_max_wg,
-               "lp_min_cols": t.lp_min_cols, "best_ms": t.best_ms}
+               "lp_min_cols": t.lp_min_cols, "mixed_min_cols": t.mixed_min_cols,
+               "best_ms": t.best_ms}
         if cache:
             table[key] = res
             with open(cache, "w") as f:
@@ -520,15 +523,16 @@ class Batch:
         _check(lib().pa_batch_run(self.ctx._h, self._h, up, op, ws, nb, ctypes.byref(cfg), st))
         return outs, [s.as_dict() for s in st]
 
-    def set_tune(self, item, narrow_rows_per_thread, wide_max_wg, lp_min_cols=8):
-        t = LaunchTune(narrow_rows_per_thread, wide_max_wg, 0.0, lp_min_cols)
+    def set_tune(self, item, narrow_rows_per_thread, wide_max_wg, lp_min_cols=8,
+                 mixed_min_cols=8):
+        t = LaunchTune(narrow_rows_per_thread, wide_max_wg, 0.0, lp_min_cols, mixed_min_cols)
         _check(lib().pa_batch_set_tune(self._h, item, ctypes.byref(t)))
 
     def get_tune(self, item):
         t = LaunchTune()
         _check(lib().pa_batch_get_tune(self._h, item, ctypes.byref(t)))
         return {"narrow_rows_per_thread": t.narrow_rows_per_thread, "wide_max_wg": t.wide_max_wg,
-                "lp_min_cols": t.lp_min_cols}
+                "lp_min_cols": t.lp_min_cols, "mixed_min_cols": t.mixed_min_cols}
 
     def autotune(self, Us, cfg=None, cache=None):
         """Per-item launch shapes (pa_batch_autotune).  With a JSON cache, an
@@ -545,7 +549,7 @@ class Batch:
         if all(k in table for k in keys):
             for i, k in enumerate(keys):
                 self.set_tune(i, table[k]["narrow_rows_per_thread"], table[k]["wide_max_wg"],
-                              table[k].get("lp_min_cols", 8))
+                              table[k].get("lp_min_cols", 8), table[k].get("mixed_min_cols", 8))
             return [dict(table[k], cached=True) for k in keys]
         outs = [U.new_empty(U.shape) for U in Us]
         up, op = self._ptrs(Us, outs)
@@ -553,7 +557,8 @@ class Batch:
         t = (LaunchTune * len(self.items))()
         _check(lib().pa_batch_autotune(self.ctx._h, self._h, up, op, ws, nb, ctypes.byref(cfg), t))
         res = [{"narrow_rows_per_thread": x.narrow_rows_per_thread, "wide_max_wg": x.wide_max_wg,
-                "lp_min_cols": x.lp_min_cols, "best_ms": x.best_ms} for x in t]
+                "lp_min_cols": x.lp_min_cols, "mixed_min_cols": x.mixed_min_cols,
+                "best_ms": x.best_ms} for x in t]
         if cache:
             table.update(dict(zip(keys, res)))
             with open(cache, "w") as f:

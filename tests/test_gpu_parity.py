@@ -238,21 +238,28 @@ def test_gpu_chebyshev_check_failure_falls_back():
     assert np.abs(ok.cpu().numpy() - ref.cpu().numpy()).max() <= 1e-9 * np.abs(ref.cpu().numpy()).max()
 
 
-@pytest.mark.parametrize("backward", [0, 1])
-def test_gpu_fp32_refined_parity(backward):
+@pytest.mark.parametrize("backward,mixed_min_cols", [(0, 1), (1, 1), (1, 8)])
+def test_gpu_fp32_refined_parity(backward, mixed_min_cols):
     """FP32 inner mass solves with FP64 residual refinement (to 1e-12):
-    the averaged RHS agrees with the FP64 oracle to 1e-10 (energy norm)."""
+    the averaged RHS agrees with the FP64 oracle to 1e-10 (energy norm).
+    mixed_min_cols = 1: every solve refined; 8: only the 8-column solves of
+    N (the single-column recurrences take FP64 steps)."""
     from paper_2103_07706_amd import pa
-    om, oo, lm, lo, mm, lb = pair(3)
-    U = bumps(om, [0])
-    avg = pa.Avg(8, 3600.0)
-    cfg = pa.solve_cfg(backward=backward, weight_cut=0.0, precision=pa.PA_FP32_REFINED,
-                       cheb_tol=1e-13, cg_rtol=1e-12)
-    out, st = lo.phase_avg_rhs(avg, to_dev(mm.state(U)), cfg)
-    assert st["refinements"] > 0
-    got = mm.back(out.cpu().numpy())[0]
-    ref = oo.phase_avg_rhs(lb, avg.s, avg.w, U[0], tol=1e-13, rtol=1e-14)
-    assert rel_w(oo, got, ref) < 1e-10, rel_w(oo, got, ref)
-    out2, _ = lo.swe_nonlinear(to_dev(mm.state(U)), cfg)
-    ref2 = oo.nonlinear(U[0], rtol=1e-14)
-    assert rel_w(oo, mm.back(out2.cpu().numpy())[0], ref2) < 1e-10
+    keep = pa.get_launch_tune()
+    pa.set_launch_tune(mixed_min_cols=mixed_min_cols)
+    try:
+        om, oo, lm, lo, mm, lb = pair(3)
+        U = bumps(om, [0])
+        avg = pa.Avg(8, 3600.0)
+        cfg = pa.solve_cfg(backward=backward, weight_cut=0.0, precision=pa.PA_FP32_REFINED,
+                           cheb_tol=1e-13, cg_rtol=1e-12)
+        out, st = lo.phase_avg_rhs(avg, to_dev(mm.state(U)), cfg)
+        assert st["refinements"] > 0
+        got = mm.back(out.cpu().numpy())[0]
+        ref = oo.phase_avg_rhs(lb, avg.s, avg.w, U[0], tol=1e-13, rtol=1e-14)
+        assert rel_w(oo, got, ref) < 1e-10, rel_w(oo, got, ref)
+        out2, _ = lo.swe_nonlinear(to_dev(mm.state(U)), cfg)
+        ref2 = oo.nonlinear(U[0], rtol=1e-14)
+        assert rel_w(oo, mm.back(out2.cpu().numpy())[0], ref2) < 1e-10
+    finally:
+        pa.set_launch_tune(**keep)
