@@ -43,6 +43,10 @@ def parse():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_refined"])
     ap.add_argument("--autotune", type=int, default=1)
     ap.add_argument("--precond", default="both", choices=["jacobi", "learned", "both"])
+    ap.add_argument("--forms", default="plain,fp32_refined,learned,hybrid",
+                    help="comma-separated forms to time (of plain, fp32_refined, learned, hybrid)")
+    ap.add_argument("--tune-cache", dest="tune_cache", default=None,
+                    help="JSON file of launch shapes: read when it holds the problem, else written")
     ap.add_argument("--lp-steps", dest="lp_steps", type=int, default=200)
     ap.add_argument("--cpu-baseline", dest="cpu", type=int, default=1)
     ap.add_argument("--cpu-terms", type=int, default=4)
@@ -54,10 +58,11 @@ def kernel_source_hash():
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel, workload, backward):
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source; otherwise None."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{backward}_counters.json")
+def traffic_from_profiles(kernel, workload, backward, form):
+    """HBM bytes per launch from the committed counter summary of this
+    kernel, workload and form, if it was taken on the current kernel source;
+    otherwise None."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{backward}_{form}_counters.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
@@ -166,18 +171,22 @@ def bench_batch(args):
             forms["fp32_refined"] = (pa.solve_cfg(
                 precond=pa.PA_PRECOND_JACOBI, **dict(base, precision=pa.PA_FP32_REFINED)), None)
     lp_rec = None
-    if args.precond in ("learned", "both"):
+    if args.precond in ("learned", "both") and {"learned", "hybrid"} & set(args.forms.split(",")):
         lp, lp_rec = train_learned(pa, ctx, phys, {o.mesh.level: o for o in ops}, args.lp_steps)
         for o in ops:
             pa.attach_learned(o, lp, bf16=True)
         lcfg = pa.solve_cfg(precond=pa.PA_PRECOND_LEARNED, **base)
         forms["learned"] = (lcfg, 1)
         forms["hybrid"] = (lcfg, None)
+    wanted = set(args.forms.split(","))
+    forms = {k: v for k, v in forms.items() if k in wanted}
+    if not forms:
+        raise SystemExit("no form selected")
     outs = [torch.empty_like(U) for U in Us]
     members = sum(m for _, m in items)
     res = {}
     for name, (cfg, lmin) in forms.items():
-        tune = batch.autotune(Us, cfg) if args.autotune else None
+        tune = batch.autotune(Us, cfg, cache=args.tune_cache) if args.autotune else None
         if lmin is not None:
             for i in range(len(items)):
                 t = batch.get_tune(i)
@@ -255,7 +264,7 @@ def main():
             forms["fp32_refined"] = (pa.solve_cfg(
                 precond=pa.PA_PRECOND_JACOBI, **dict(base, precision=pa.PA_FP32_REFINED)), None)
     lp_rec = None
-    if args.precond in ("learned", "both"):
+    if args.precond in ("learned", "both") and {"learned", "hybrid"} & set(args.forms.split(",")):
         # the network is trained on the GPU on meshes of levels 4 to 6 (this
         # workload's own operator among them) before the measurement
         lp, lp_rec = train_learned(pa, ctx, wl.phys, {wl.level: ops}, args.lp_steps)
@@ -264,11 +273,15 @@ def main():
         lcfg = pa.solve_cfg(precond=pa.PA_PRECOND_LEARNED, **base)
         forms["learned"] = (lcfg, 1)
         forms["hybrid"] = (lcfg, None)
+    wanted = set(args.forms.split(","))
+    forms = {k: v for k, v in forms.items() if k in wanted}
+    if not forms:
+        raise SystemExit("no form selected")
     results = {}
     for name, (cfg, lmin) in forms.items():
         tune = None
         if args.autotune:
-            tune = ops.autotune(avg, U, cfg)
+            tune = ops.autotune(avg, U, cfg, cache=args.tune_cache)
         if lmin is not None:
             pa.set_launch_tune(lp_min_cols=lmin)
             tune = dict(tune or {}, **pa.get_launch_tune())
@@ -293,12 +306,13 @@ def main():
     value = wl.members * args.steps / elapsed
     avg_ms = prof["total_ms"] / max(1, prof["launches"])
     achieved = prof["bytes"] / (prof["total_ms"] * 1e-3) / 1e9 if prof["total_ms"] > 0 else 0.0
-    traffic = traffic_from_profiles(kernel, args.workload, args.backward)
+    traffic = traffic_from_profiles(kernel, args.workload, args.backward, head_name)
     forms_rec = {name: {"value": wl.members * args.steps / r["elapsed"],
                         "ms_per_step": 1e3 * r["elapsed"] / args.steps,
                         "mass_solves": r["stats"]["solves"],
                         "learned_solves": r["stats"]["lp_solves"],
                         "mass_solve_steps_total": r["stats"]["cg_iters"],
+                        "resid_max": r["stats"]["resid_max"],
                         "launch_tune": r["tune"], "autotune": r["autotune"]}
                  for name, r in results.items()}
     for name in ("learned", "hybrid", "fp32_refined"):

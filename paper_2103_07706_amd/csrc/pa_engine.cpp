@@ -49,14 +49,18 @@ Engine::~Engine() {
   if (ev1_) (void)hipEventDestroy(ev1_);
 }
 
-// Chebyshev semi-iteration on D^-1 M over [a, b] = Lanczos bounds widened
-// by 5% below and 2% above; the number of steps makes the Chebyshev error
-// factor 1/T_k(theta/delta) reach cg_rtol, plus two.
+// Chebyshev semi-iteration on D^-1 M over [a, b] = the Ritz bounds of 200
+// Lanczos steps widened by 1% below and 0.5% above (on these mass matrices
+// 200 steps put both ends within rounding of the extreme eigenvalues, 120
+// within 1e-6); the number of steps makes the Chebyshev error factor
+// 2/T_k(theta/delta) reach cg_rtol, plus one.  Measured worst final
+// residual at cg_rtol = 1e-10: about 1e-11.  The final FP64 residual check
+// guards every solve.
 namespace {
-// Chebyshev steps for the error factor 1/T_k(theta/delta) to reach rtol, plus two.
+constexpr double kBoundLow = 0.99, kBoundHigh = 1.005;
 int cheb_steps(double a, double b, double rtol) {
   const double sigma = (a + b) / (b - a);
-  return (int)std::ceil(std::acosh(2.0 / rtol) / std::acosh(sigma)) + 2;
+  return (int)std::ceil(std::acosh(2.0 / rtol) / std::acosh(sigma)) + 1;
 }
 }  // namespace
 
@@ -78,7 +82,7 @@ void cheb_coefs(double a, double b, int k, std::vector<double> &c1, std::vector<
 }  // namespace
 
 void Engine::plan_cheb() {
-  const double a = 0.95 * ops_->mass_eig_min, b = 1.02 * ops_->mass_eig_max;
+  const double a = kBoundLow * ops_->mass_eig_min, b = kBoundHigh * ops_->mass_eig_max;
   if (!(a > 0) || !(b > a)) throw Error(PA_EINVAL, "no spectral bounds for the mass matrix");
   if (cfg_.precond != PA_PRECOND_JACOBI && cfg_.precond != PA_PRECOND_LEARNED)
     throw Error(PA_EINVAL, "unknown preconditioner");
@@ -88,7 +92,7 @@ void Engine::plan_cheb() {
   if (cfg_.precond == PA_PRECOND_LEARNED && cheb() && !mixed()) {
     if (!ops_->lp_ready || !ops_->lp_dev)
       throw Error(PA_EINVAL, "no learned preconditioner bound to the operators");
-    const double la = 0.95 * ops_->lp_eig_min, lb = 1.02 * ops_->lp_eig_max;
+    const double la = kBoundLow * ops_->lp_eig_min, lb = kBoundHigh * ops_->lp_eig_max;
     if (la > 0 && lb > la) {
       lp_avail_ = true;
       lp_theta_ = 0.5 * (la + lb);
@@ -162,6 +166,7 @@ void Engine::mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_
   ck.rtol2 = cfg_.cg_rtol * cfg_.cg_rtol;
   ck.fail = st_.cheb_fail;
   ck.resid = st_.resid;
+  ck.resid_max = st_.resid_max;
   launch_cheb_check(ck, s_);
   stats.solves++;
   stats.refinements += mixed_outer_;
@@ -311,6 +316,7 @@ void Engine::cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_i
   ca.rtol2 = cfg_.cg_rtol * cfg_.cg_rtol;
   ca.fail = st_.cheb_fail;
   ca.resid = st_.resid;
+  ca.resid_max = st_.resid_max;
   launch_cheb_check(ca, s_);
   stats.solves++;
   stats.cg_iters += k;
@@ -361,6 +367,7 @@ void Engine::plan_common(int BsMax) {
     st_.prof_last = z + 6;
     st_.budget_fail = (int *)(z + 7);
     st_.cheb_fail = (int *)(z + 8);
+    st_.resid_max = (unsigned long long *)(z + 10);  // 8-byte aligned
   }
 }
 
@@ -388,9 +395,18 @@ void Engine::begin() {
 
 void Engine::finish() {
   PA_HIP(hipEventRecord(ev1_, s_));
-  int h[7] = {0, 0, 0, 0, 0, 0, 0};
-  PA_HIP(hipMemcpyAsync(h, st_.fail, 7 * sizeof(int), hipMemcpyDeviceToHost, s_));
+  // counters z+2 .. z+11: fail, iter_max, prof[3], budget_fail, cheb_fail,
+  // (pad), resid_max bits
+  int h[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  PA_HIP(hipMemcpyAsync(h, st_.fail, 10 * sizeof(int), hipMemcpyDeviceToHost, s_));
   PA_HIP(hipStreamSynchronize(s_));
+  {
+    unsigned long long bits;
+    std::memcpy(&bits, &h[8], sizeof(bits));
+    double rm;
+    std::memcpy(&rm, &bits, sizeof(rm));
+    stats.resid_max = rm;
+  }
   if (ctx_->prof_kernel != PA_KERNEL_NONE) {
     for (const ProfSpan &p : prof_ev_) {
       float t = 0;

@@ -269,7 +269,7 @@ void assemble_ops(pa_ops *o, const Mesh &m, const pa_phys &ph) {
     o->dinv32[e] = (float)o->dinv[e];
   }
   for (int i = 0; i < 5 * ne; i++) o->mass32[i] = (float)o->mass[i];
-  mass_spectrum(o, 120, &o->mass_eig_min, &o->mass_eig_max);
+  mass_spectrum(o, 200, &o->mass_eig_min, &o->mass_eig_max);
 }
 
 namespace {

@@ -25,6 +25,7 @@ struct SolveState {
   int *cnt;               // [2]: active columns after the last finalize, by parity
   int *budget_fail;       // 1: columns still active when an iteration budget ran out
   int *cheb_fail;         // 1: Chebyshev solves that missed the residual tolerance
+  unsigned long long *resid_max;  // 1: largest final relative residual (FP64 bits)
   int *fail;              // 1 (accumulates over solves)
   int *iter_max;          // 1 (accumulates over solves)
   unsigned *prof;         // [3]: active columns summed over launches, work launches,
@@ -158,6 +159,7 @@ struct CheckArgs {
   double rtol2;
   int *fail;
   double *resid;
+  unsigned long long *resid_max;
 };
 
 enum { FIN_INIT = 0, FIN_STEP = 1, FIN_OUT = 2 };

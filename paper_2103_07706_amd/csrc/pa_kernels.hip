@@ -341,7 +341,10 @@ __global__ __launch_bounds__(kWG) void k_cheb_check(CheckArgs a) {
   b = wave_col_sum(b, 1);
   r = wave_col_sum(r, 1);
   if (lane == 0 && a.colK[c] >= a.kneed && b > 0.0) {
-    a.resid[c] = sqrt(r / b);
+    const double rel = sqrt(r / b);
+    a.resid[c] = rel;
+    // non-negative doubles order like their bit patterns
+    if (a.resid_max) atomicMax(a.resid_max, (unsigned long long)__double_as_longlong(rel));
     if (!(r <= a.rtol2 * b)) atomicAdd(a.fail, 1);
   }
 }

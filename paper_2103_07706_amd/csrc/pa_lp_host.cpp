@@ -300,7 +300,7 @@ void lp_build_preconditioner(pa_ops *o, const std::vector<double> &gd, const std
           w[i] = s;
         }
       },
-      120, &o->lp_eig_min, &o->lp_eig_max);
+      200, &o->lp_eig_min, &o->lp_eig_max);
   o->lp_ready = true;
   o->lp_dev = nullptr;  // tables changed: bind again
 }

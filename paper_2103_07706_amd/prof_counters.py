@@ -6,8 +6,8 @@ Two steps:
    Jacobi Chebyshev step of the level-6 averaged right-hand side:
 
        rocprofv3 --pmc FETCH_SIZE --kernel-include-regex k_cheb_iter \\
-           -f csv -d OUT/fetch -o run -- python3 bench.py --precond jacobi \\
-           --graph 0 --autotune 0 --steps 1 --warmup 0 --cpu-baseline 0
+           -f csv -d OUT/fetch -o run -- python3 bench.py --forms fp32_refined \\
+           --tune-cache OUT/tune.json --graph 0 --steps 1 --warmup 0 --cpu-baseline 0
        (the same with WRITE_SIZE into OUT/write)
        rocprofv3 --pmc FETCH_SIZE -f csv -d OUT/copy_fetch -o run -- \\
            python3 -m paper_2103_07706_amd.prof_counters copy
@@ -92,7 +92,7 @@ def summarize(a):
     f_write = COPY_BYTES / (max(cw) * 1024.0)
     fb = statistics.mean(fetch) * 1024.0 * f_fetch
     wb = statistics.mean(write) * 1024.0 * f_write
-    rec = {"kernel": a.kernel, "workload": a.workload, "backward": a.backward,
+    rec = {"kernel": a.kernel, "workload": a.workload, "backward": a.backward, "form": a.form,
            "kernel_source_sha256_16": kernel_source_hash(),
            "dispatches": len(fetch), "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
            "hbm_bytes_per_launch": fb + wb,
@@ -104,7 +104,8 @@ def summarize(a):
         json.dump(rec, f, indent=1)
     md = os.path.splitext(a.out)[0] + ".md"
     with open(md, "w") as f:
-        f.write(f"# HBM traffic of {a.kernel}, workload {a.workload} ({a.backward} backward)\n\n")
+        f.write(f"# HBM traffic of {a.kernel}, workload {a.workload} ({a.backward} backward, "
+                f"{a.form} form)\n\n")
         f.write("Counter runs (rocprofv3, one counter per run, from the repository root on the "
                 "GPU box):\n\n```\n" + "\n".join(a.commands) + "\n```\n\n")
         f.write(f"Copy calibration: {COPY_BYTES} bytes read and written; FETCH_SIZE counted "
@@ -188,7 +189,8 @@ def main():
     t.add_argument("--bench-json", dest="bench_json", default=None,
                    help="JSON line of the same bench run without the profiler")
     s = sub.add_parser("summarize")
-    for k in ("fetch", "write", "copy_fetch", "copy_write", "kernel", "workload", "backward", "out"):
+    for k in ("fetch", "write", "copy_fetch", "copy_write", "kernel", "workload", "backward", "form",
+              "out"):
         s.add_argument("--" + k.replace("_", "-"), dest=k, required=True)
     s.add_argument("--command", dest="commands", action="append", default=[])
     a = ap.parse_args()

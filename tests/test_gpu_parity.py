@@ -210,6 +210,8 @@ def test_gpu_chebyshev_solver_parity(backward):
     avg = pa.Avg(8, 3600.0)
     cfg = pa.solve_cfg(backward=backward, weight_cut=0.0, **PARITY, **CHEB)
     out, st = lo.phase_avg_rhs(avg, to_dev(mm.state(U)), cfg)
+    # the largest final residual over all solves of the call, as checked
+    assert 0 < st["resid_max"] <= PARITY["cg_rtol"]
     got = mm.back(out.cpu().numpy())[0]
     ref = oo.phase_avg_rhs(lb, avg.s, avg.w, U[0], tol=1e-13, rtol=1e-14)
     assert rel_w(oo, got, ref) < TOL
