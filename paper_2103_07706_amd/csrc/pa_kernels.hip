@@ -332,20 +332,39 @@ __global__ __launch_bounds__(kWG) void k_cheb_check(CheckArgs a) {
   const int cpb = ct < 4 ? ct : 4;
   const int bpt = ct / cpb;
   const int tile = blockIdx.x / bpt;
-  const int cl = (blockIdx.x % bpt) * cpb + wave;
-  if (wave >= cpb) return;
+  // the waves of a block share its cpb columns: column cl = base + (wave % cpb),
+  // and the 4 / cpb waves of one column split the workgroup partials
+  const int split = 4 / cpb;
+  const int cl = (blockIdx.x % bpt) * cpb + wave % cpb;
+  const int part = wave / cpb;
   const int c = tile * ct + cl;
   double b = 0.0, r = 0.0;
-  for (int w = lane; w < a.nwg_init; w += 64) b += a.part_init[((size_t)tile * a.max_wg + w) * 64 + cl];
-  for (int w = lane; w < a.nwg_last; w += 64) r += a.part_last[((size_t)tile * a.max_wg + w) * 64 + cl];
+  for (int w = part * 64 + lane; w < a.nwg_init; w += 64 * split)
+    b += a.part_init[((size_t)tile * a.max_wg + w) * 64 + cl];
+  for (int w = part * 64 + lane; w < a.nwg_last; w += 64 * split)
+    r += a.part_last[((size_t)tile * a.max_wg + w) * 64 + cl];
   b = wave_col_sum(b, 1);
   r = wave_col_sum(r, 1);
-  if (lane == 0 && a.colK[c] >= a.kneed && b > 0.0) {
-    const double rel = sqrt(r / b);
-    a.resid[c] = rel;
-    // non-negative doubles order like their bit patterns
-    if (a.resid_max) atomicMax(a.resid_max, (unsigned long long)__double_as_longlong(rel));
-    if (!(r <= a.rtol2 * b)) atomicAdd(a.fail, 1);
+  __shared__ double red[2][4];
+  if (lane == 0) {
+    red[0][wave] = b;
+    red[1][wave] = r;
+  }
+  __syncthreads();
+  if (part == 0 && lane == 0) {
+    b = 0.0;
+    r = 0.0;
+    for (int p = 0; p < split; p++) {  // fixed order
+      b += red[0][p * cpb + wave];
+      r += red[1][p * cpb + wave];
+    }
+    if (a.colK[c] >= a.kneed && b > 0.0) {
+      const double rel = sqrt(r / b);
+      a.resid[c] = rel;
+      // non-negative doubles order like their bit patterns
+      if (a.resid_max) atomicMax(a.resid_max, (unsigned long long)__double_as_longlong(rel));
+      if (!(r <= a.rtol2 * b)) atomicAdd(a.fail, 1);
+    }
   }
 }
 
