@@ -133,7 +133,12 @@ typedef struct {
                           recurrences, stiffness, N and all sums stay FP64. */
   int32_t backward;    /* how the M backward exponentials are summed */
   int32_t maxit;       /* CG iterations per mass solve (FP64) */
-  int32_t growth_guard;/* 1: fail with PA_EGROWTH if the recurrence grows */
+  int32_t growth_guard;/* 1: after the forward Chebyshev basis of each averaged
+                          right-hand side (up to four per call), compare the
+                          energy norm of the last basis vector with that of
+                          the state (never larger when lambda_bar >= rho(L),
+                          Sec. 2.4); growth above 1% fails the call with
+                          PA_EGROWTH, stats.guard_trips counting the states */
   double cg_rtol;      /* ||r||_2 <= cg_rtol ||b||_2 for every mass solve */
   double cheb_tol;     /* Chebyshev truncation threshold (paper: 1e-6) */
   double weight_cut;   /* skip terms with w_m < weight_cut * max_j w_j */

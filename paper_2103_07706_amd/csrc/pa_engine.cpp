@@ -391,6 +391,7 @@ void Engine::begin() {
   PA_HIP(hipEventCreate(&ev1_));
   PA_HIP(hipEventRecord(ev0_, s_));
   stats = pa_stats{};
+  guard_next_ = 0;
 }
 
 void Engine::finish() {
@@ -446,6 +447,22 @@ void Engine::finish() {
   ev0_ = ev1_ = nullptr;
   stats.device_ms = ms;
   stats.cg_iters_max = std::max(stats.cg_iters_max, h[1]);
+  if (guard_ && guard_bm_ > 0) {
+    const int used = std::min(guard_calls_, kGuardSlots);
+    std::vector<double> g((size_t)used * 10 * guard_bm_);
+    PA_HIP(hipMemcpy(g.data(), guard_, g.size() * sizeof(double), hipMemcpyDeviceToHost));
+    const double H = ops_->H, gr = ops_->g;
+    for (int sl = 0; sl < used; sl++) {
+      const double *q = g.data() + (size_t)sl * 10 * guard_bm_;
+      for (int c = 0; c < guard_members_; c++) {
+        const double w0 = H * q[c] + gr * q[2 * guard_bm_ + c];
+        const double wk = H * q[5 * guard_bm_ + c] + gr * q[7 * guard_bm_ + c];
+        if (w0 > 0 && wk > 1.0201 * w0) stats.guard_trips++;  // 1% growth of the norm
+      }
+    }
+    if (stats.guard_trips > 0)
+      throw Error(PA_EGROWTH, "Chebyshev basis grows: lambda_bar is below the spectral radius of L");
+  }
   if (h[0] > 0)
     throw Error(PA_ENOCONV, std::to_string(h[0]) + " mass-solve column(s) did not converge within maxit");
   if (h[5] > 0) throw BudgetExceeded();
@@ -925,6 +942,14 @@ void Engine::run_nbar(NbarBufs &nb, Blk X, Blk out, bool uploaded) {
     Blk rm = R(k - 1);
     lstep(R(k), R(k + 1), &rm, nullptr, 2.0 / lb, nb.colK_fwd, k + 1, nullptr);
   }
+  // growth guard: with lambda_bar >= rho(L) every R_k = i^k T_k(-iL/lambda_bar) U
+  // has W-norm at most that of U (T_k is bounded by 1 on the real spectrum of
+  // -iL/lambda_bar); an underestimated lambda_bar makes the outer modes grow
+  if (guard_) {
+    double *slot = guard_ + (size_t)std::min(guard_next_++, kGuardSlots - 1) * 10 * Bm;
+    diag(R(0), slot);
+    diag(R(kmax), slot + 5 * (size_t)Bm);
+  }
   // shifted states E[:, mem*G + m] = sum_k cF[k][m] R_k[:, mem]
   CombineArgs ca{n_, nb.BsE, Bm, nb.G, nb.members, kmax, blkm, nb.basis, nb.cF, nb.E};
   launch_combine(ca, s_);
@@ -970,6 +995,12 @@ void Engine::nbar_plan(NbarCall &c, const pa_avg *avg, int members, const double
   c.Nbar = Nbar;
   plan_nbar(c.nb, avg, members);  // sizes first (needs G, BsE)
   plan_common(c.nb.BsE);
+  if (cfg_.growth_guard) {
+    guard_ = ar_.take<double>((size_t)kGuardSlots * 10 * c.nb.Bm);
+    guard_bm_ = c.nb.Bm;
+    guard_members_ = members;
+    guard_calls_ = 1;
+  }
   ut0_ = ar_.take<double>((size_t)ne_ * c.nb.BsE);
   ut1_ = ar_.take<double>((size_t)ne_ * c.nb.BsE);
   C_ = ar_.take<double>((size_t)3 * nc_ * c.nb.BsE);
@@ -1083,6 +1114,12 @@ void Engine::step(const pa_avg *avg, double dt, int members, double *U) {
   plan_nbar(nb, avg, members);
   const int Bm = nb.Bm;
   plan_common(nb.BsE);
+  if (cfg_.growth_guard) {  // the four averaged right-hand sides of a step
+    guard_ = ar_.take<double>((size_t)kGuardSlots * 10 * nb.Bm);
+    guard_bm_ = nb.Bm;
+    guard_members_ = members;
+    guard_calls_ = 4;
+  }
   ut0_ = ar_.take<double>((size_t)ne_ * nb.BsE);
   ut1_ = ar_.take<double>((size_t)ne_ * nb.BsE);
   C_ = ar_.take<double>((size_t)3 * nc_ * nb.BsE);

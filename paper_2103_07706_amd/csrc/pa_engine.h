@@ -116,7 +116,12 @@ class Engine {
   double lp_theta_ = 0;
   std::vector<double> lp_c1_, lp_c2_;
   bool lp_cheaper(int Bs) const;
-  bool lp_prof_wide_ = false;  // measurement hook: form of the profiled learned steps
+  bool lp_prof_wide_ = false;
+  // growth guard: diagnostics of R_0 and R_kmax of up to kGuardSlots
+  // averaged right-hand sides per call (the four of a step)
+  static constexpr int kGuardSlots = 4;
+  double *guard_ = nullptr;
+  int guard_bm_ = 0, guard_members_ = 0, guard_calls_ = 0, guard_next_ = 0;  // measurement hook: form of the profiled learned steps
   std::vector<double> cheb_c1_, cheb_c2_;
   void plan_cheb();
   void poly_apply(Blk X, Blk W, const double *coef, const int *colK, int kmax, int G, Blk acc);

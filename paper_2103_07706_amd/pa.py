@@ -225,9 +225,10 @@ def set_launch_tune(**changes):
 
 def solve_cfg(precision=PA_FP64, backward=PA_BACKWARD_PER_TERM, maxit=None, cg_rtol=None,
               cheb_tol=None, weight_cut=None, inner_rtol=None, use_graph=False,
-              solver=PA_SOLVER_CG, precond=PA_PRECOND_JACOBI) -> SolveCfg:
+              solver=PA_SOLVER_CG, precond=PA_PRECOND_JACOBI, growth_guard=0) -> SolveCfg:
     c = SolveCfg()
     lib().pa_solve_cfg_default(ctypes.byref(c))
+    c.growth_guard = growth_guard
     c.solver = solver
     c.precond = precond
     c.precision = precision
