@@ -188,6 +188,9 @@ typedef struct {
   int32_t budget;        /* CG iterations per solve launched (0: polled) */
   int32_t precond;       /* PA_PRECOND_LEARNED if any solve used it */
   int32_t lp_solves;     /* mass solves that used the learned preconditioner */
+  int32_t fallbacks;     /* repeats of the call: a CG budget overrun (with
+                            polling) or a failed Chebyshev check (with FP64
+                            CG); the other fields describe the last run */
 } pa_stats;
 
 /* Device workspace bytes for calls on 'batch' states (expL_apply,

@@ -258,6 +258,7 @@ void run_batch(pa_ctx *ctx, pa_batch *b, const double *const *U, double *const *
     bneed(U[i] && Nbar[i], "NULL state pointer");
     may = may && (const double *)Nbar[i] != U[i];
   }
+  int repeats = 0;
   auto with_budget = [&](const pa_solve_cfg &c) {
     const bool cg64 = c.solver == PA_SOLVER_CG && c.precision == PA_FP64;
     if (may && cg64 && ctx->cg_budget.count(c.cg_rtol)) {
@@ -266,6 +267,7 @@ void run_batch(pa_ctx *ctx, pa_batch *b, const double *const *U, double *const *
         return;
       } catch (const pa::BudgetExceeded &) {
         ctx->cg_budget.erase(c.cg_rtol);
+        repeats++;
       }
     }
     run_once(ctx, b, U, Nbar, (char *)ws, off, c, false, may, stats);
@@ -274,11 +276,14 @@ void run_batch(pa_ctx *ctx, pa_batch *b, const double *const *U, double *const *
     with_budget(c0);
   } catch (const pa::SolverCheckFailed &) {
     if (!may) throw;
+    repeats++;
     pa_solve_cfg c = c0;
     c.solver = PA_SOLVER_CG;
     c.precision = PA_FP64;
     with_budget(c);
   }
+  if (stats)
+    for (int i = 0; i < b->n(); i++) stats[i].fallbacks = repeats;
 }
 }  // namespace
 

@@ -387,6 +387,9 @@ void out_stats(pa_stats *stats, const pa::Engine &e) {
   if (stats) *stats = e.stats;
 }
 
+// Repeats of the current call (budget overrun, failed Chebyshev check).
+thread_local int g_repeats = 0;
+
 // Run a call with the context's learned CG iteration budget when allowed
 // (outputs not aliasing inputs); if a solve outlives the budget, run it
 // again with host polling, which also relearns the budget.
@@ -398,6 +401,7 @@ void run_with_budget(pa_ctx *ctx, double rtol, bool allowed, F &&f) {
       return;
     } catch (const pa::BudgetExceeded &) {
       ctx->cg_budget.erase(rtol);
+      g_repeats++;
     }
   }
   f(false);
@@ -412,6 +416,7 @@ void run_with_fallback(pa_solve_cfg cfg, bool rerun_ok, F &&f) {
     f(cfg);
   } catch (const pa::SolverCheckFailed &) {
     if (!rerun_ok) throw;
+    g_repeats++;
     cfg.solver = PA_SOLVER_CG;
     cfg.precision = PA_FP64;
     f(cfg);
@@ -444,6 +449,7 @@ int pa_expL_apply(pa_ctx *ctx, const pa_ops *ops, int B, const double *t_host,
     need(t_host && U_in_dev && U_out_dev && B >= 1, "bad arguments");
     const pa_solve_cfg c0 = cfg_or_default(cfg);
     const bool may = U_in_dev != U_out_dev;
+    g_repeats = 0;
     run_with_fallback(c0, may, [&](const pa_solve_cfg &c) {
       run_with_budget(ctx, c.cg_rtol, may, [&](bool budget) {
         pa::Engine e(ctx, ops, c, ws, ws_bytes);
@@ -452,6 +458,7 @@ int pa_expL_apply(pa_ctx *ctx, const pa_ops *ops, int B, const double *t_host,
         out_stats(stats, e);
       });
     });
+    if (stats) stats->fallbacks = g_repeats;
   });
 }
 
@@ -462,6 +469,7 @@ int pa_swe_nonlinear(pa_ctx *ctx, const pa_ops *ops, int B, const double *U_dev,
     need(U_dev && NU_dev && B >= 1, "bad arguments");
     const pa_solve_cfg c0 = cfg_or_default(cfg);
     const bool may = U_dev != NU_dev;
+    g_repeats = 0;
     run_with_fallback(c0, may, [&](const pa_solve_cfg &c) {
       run_with_budget(ctx, c.cg_rtol, may, [&](bool budget) {
         pa::Engine e(ctx, ops, c, ws, ws_bytes);
@@ -470,6 +478,7 @@ int pa_swe_nonlinear(pa_ctx *ctx, const pa_ops *ops, int B, const double *U_dev,
         out_stats(stats, e);
       });
     });
+    if (stats) stats->fallbacks = g_repeats;
   });
 }
 
@@ -481,6 +490,7 @@ int pa_phase_avg_rhs(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int memb
     need(avg && U_dev && Nbar_dev && members >= 1, "bad arguments");
     const pa_solve_cfg c0 = cfg_or_default(cfg);
     const bool may = U_dev != Nbar_dev;
+    g_repeats = 0;
     run_with_fallback(c0, may, [&](const pa_solve_cfg &c) {
       run_with_budget(ctx, c.cg_rtol, may, [&](bool budget) {
         pa::Engine e(ctx, ops, c, ws, ws_bytes);
@@ -489,6 +499,7 @@ int pa_phase_avg_rhs(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int memb
         out_stats(stats, e);
       });
     });
+    if (stats) stats->fallbacks = g_repeats;
   });
 }
 

@@ -86,7 +86,8 @@ class Stats(ctypes.Structure):
                 ("refinements", ctypes.c_int32), ("guard_trips", ctypes.c_int32),
                 ("resid_max", ctypes.c_double), ("device_ms", ctypes.c_double),
                 ("graph", ctypes.c_int32), ("budget", ctypes.c_int32),
-                ("precond", ctypes.c_int32), ("lp_solves", ctypes.c_int32)]
+                ("precond", ctypes.c_int32), ("lp_solves", ctypes.c_int32),
+                ("fallbacks", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

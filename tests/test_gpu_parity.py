@@ -144,12 +144,14 @@ def test_gpu_budget_mode_and_repeat():
     avg = pa.Avg(8, 3600.0)
     cfg = pa.solve_cfg(cg_rtol=1e-11)
     lo.ctx.set_cg_budget(1e-11, 0)
-    a, _ = lo.phase_avg_rhs(avg, U, cfg)   # polling, learns the budget
-    b, _ = lo.phase_avg_rhs(avg, U, cfg)   # budget
+    a, sa = lo.phase_avg_rhs(avg, U, cfg)   # polling, learns the budget
+    b, sb = lo.phase_avg_rhs(avg, U, cfg)   # budget
     assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+    assert sa["budget"] == 0 and sb["budget"] > 0 and sb["fallbacks"] == 0
     lo.ctx.set_cg_budget(1e-11, 3)         # far too small: repeat with polling
-    c, _ = lo.phase_avg_rhs(avg, U, cfg)
+    c, sc = lo.phase_avg_rhs(avg, U, cfg)
     assert np.array_equal(a.cpu().numpy(), c.cpu().numpy())
+    assert sc["fallbacks"] == 1
 
 
 def test_gpu_graph_replay_matches_eager():
@@ -235,7 +237,8 @@ def test_gpu_chebyshev_check_failure_falls_back():
     with pytest.raises(pa.PAError) as ei:
         lo.swe_nonlinear(U, cfg)
     assert ei.value.code == 4
-    ok, _ = lo.swe_nonlinear(U, pa.solve_cfg(cg_rtol=1e-12, **CHEB))
+    ok, st = lo.swe_nonlinear(U, pa.solve_cfg(cg_rtol=1e-12, **CHEB))
+    assert st["fallbacks"] == 0
     ref, _ = lo.swe_nonlinear(U, pa.solve_cfg(cg_rtol=1e-12))
     assert np.abs(ok.cpu().numpy() - ref.cpu().numpy()).max() <= 1e-9 * np.abs(ref.cpu().numpy()).max()
 
