@@ -128,7 +128,7 @@ void Engine::mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_
   ra.theta_inv = (float)(1.0 / cheb_theta_);
   ra.colK = colK;
   ra.kneed = kneed;
-  ra.part = rb_.partB;
+  ra.part = chk_last_[chk_par_];
   ra.max_wg = rb_.max_wg;
   ra.first = 1;
   launch_refine(ra, s_);
@@ -154,20 +154,7 @@ void Engine::mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_
     ra.last = o + 1 == mixed_outer_ ? 1 : 0;
     launch_refine(ra, s_);
   }
-  CheckArgs ck{};
-  ck.Bs = Bs;
-  ck.nwg_init = nwg_init;
-  ck.nwg_last = launch_rows_grid(ne_, Bs);
-  ck.max_wg = rb_.max_wg;
-  ck.part_init = rb_.partA;
-  ck.part_last = rb_.partB;
-  ck.colK = colK;
-  ck.kneed = kneed;
-  ck.rtol2 = cfg_.cg_rtol * cfg_.cg_rtol;
-  ck.fail = st_.cheb_fail;
-  ck.resid = st_.resid;
-  ck.resid_max = st_.resid_max;
-  launch_cheb_check(ck, s_);
+  defer_check(Bs, nwg_init, colK, kneed);
   stats.solves++;
   stats.refinements += mixed_outer_;
   stats.cg_iters += kin * mixed_outer_;
@@ -176,6 +163,48 @@ void Engine::mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_
 
 // Reduction-free mass solve: the set-up kernel wrote r_0 (r), x_0 (x),
 // d_0 = D^-1 r_0 / theta (p) and partials of |r_0|^2 (partA).
+// Residual check of the solve just enqueued: deferred to the next set-up
+// kernel (take_check) or to flush_check at the end of the call.
+void Engine::defer_check(int Bs, int nwg_init, const int *colK, int kneed) {
+  CheckArgs &ck = pend_args_;
+  ck = CheckArgs{};
+  ck.Bs = Bs;
+  ck.nwg_init = nwg_init;
+  ck.nwg_last = launch_rows_grid(ne_, Bs);
+  ck.max_wg = rb_.max_wg;
+  ck.part_init = chk_init_[chk_par_];
+  ck.part_last = chk_last_[chk_par_];
+  ck.colK = colK;
+  ck.kneed = kneed;
+  ck.rtol2 = cfg_.cg_rtol * cfg_.cg_rtol;
+  ck.fail = st_.cheb_fail;
+  ck.resid = st_.resid;
+  ck.resid_max = st_.resid_max;
+  pend_ = true;
+  chk_par_ ^= 1;
+}
+
+// Hands the pending check to a set-up kernel of `grid_blocks` workgroups
+// (enough for the check), else launches it on its own first.
+void Engine::take_check(CheckArgs &chk, int &blocks, int grid_blocks) {
+  blocks = 0;
+  if (!pend_) return;
+  const int need = cheb_check_blocks(pend_args_);
+  if (grid_blocks >= need) {
+    chk = pend_args_;
+    blocks = need;
+    pend_ = false;
+  } else {
+    flush_check();
+  }
+}
+
+void Engine::flush_check() {
+  if (!pend_) return;
+  launch_cheb_check(pend_args_, s_);
+  pend_ = false;
+}
+
 // The mass solve after a set-up kernel.  With FP32 refinement enabled, the
 // refined solve runs on blocks at least mixed_min_cols wide (its FP32 steps
 // halve the bytes of a step, which pays where steps are bandwidth bound);
@@ -220,7 +249,7 @@ void Engine::cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_i
     a.x = x;
     a.colK = colK;
     a.kneed = kneed;
-    a.part = rb_.partB;
+    a.part = chk_last_[chk_par_];
     a.max_wg = rb_.max_wg;
     double *r[2] = {r_, r1_};
     const bool prof = ctx_->prof_kernel == PA_KERNEL_CHEB_LP_ITER;
@@ -259,7 +288,7 @@ void Engine::cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_i
     a.r = r_;
     a.colK = colK;
     a.kneed = kneed;
-    a.part = rb_.partB;
+    a.part = chk_last_[chk_par_];
     a.max_wg = rb_.max_wg;
     a.nodir = 1;
     const bool prof = ctx_->prof_kernel == PA_KERNEL_CHEB_LP_ITER;
@@ -286,7 +315,7 @@ void Engine::cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_i
     a.r = r_;
     a.colK = colK;
     a.kneed = kneed;
-    a.part = rb_.partB;
+    a.part = chk_last_[chk_par_];
     a.max_wg = rb_.max_wg;
     const bool prof = ctx_->prof_kernel == PA_KERNEL_CHEB_ITER;
     a.prof = prof ? st_.prof : nullptr;
@@ -304,20 +333,7 @@ void Engine::cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_i
   if (lp) stats.precond = PA_PRECOND_LEARNED;
   if (lp) lp_prof_wide_ = Bs > 4;
   stats.lp_solves += lp ? 1 : 0;
-  CheckArgs ca{};
-  ca.Bs = Bs;
-  ca.nwg_init = nwg_init;
-  ca.nwg_last = launch_rows_grid(ne_, Bs);
-  ca.max_wg = rb_.max_wg;
-  ca.part_init = rb_.partA;
-  ca.part_last = rb_.partB;
-  ca.colK = colK;
-  ca.kneed = kneed;
-  ca.rtol2 = cfg_.cg_rtol * cfg_.cg_rtol;
-  ca.fail = st_.cheb_fail;
-  ca.resid = st_.resid;
-  ca.resid_max = st_.resid_max;
-  launch_cheb_check(ca, s_);
+  defer_check(Bs, nwg_init, colK, kneed);
   stats.solves++;
   stats.cg_iters += k;
   stats.cg_iters_max = std::max(stats.cg_iters_max, k);
@@ -355,6 +371,12 @@ void Engine::plan_common(int BsMax) {
   rb_.max_wg = launch_max_wg();
   rb_.partA = ar_.take<double>((size_t)tiles * rb_.max_wg * 3 * 64);
   rb_.partB = ar_.take<double>((size_t)tiles * rb_.max_wg * 5 * 64);
+  // residual partials of Chebyshev solves by solve parity, so that a
+  // solve's check can run inside the next solve's set-up kernel
+  for (int p = 0; p < 2; p++) {
+    chk_init_[p] = ar_.take<double>((size_t)tiles * rb_.max_wg * 64);
+    chk_last_[p] = ar_.take<double>((size_t)tiles * rb_.max_wg * 64);
+  }
   // counters, cleared at the start of each call
   zero_words_ = 64;
   zero_base_ = ar_.take<unsigned>(zero_words_);
@@ -392,6 +414,8 @@ void Engine::begin() {
   PA_HIP(hipEventRecord(ev0_, s_));
   stats = pa_stats{};
   guard_next_ = 0;
+  pend_ = false;
+  chk_par_ = 0;
 }
 
 void Engine::finish() {
@@ -695,7 +719,9 @@ void Engine::lstep(Blk in, Blk out, const Blk *A, const Blk *B, double scale, co
   if (cheb() || mixed()) {
     a.d0 = p_;
     a.theta_inv = 1.0 / cheb_theta_;
-    a.part_rr = rb_.partA;
+    a.part_rr = chk_init_[chk_par_];
+    take_check(a.chk, a.chk_blocks,
+               launch_rows_grid(std::max(ne_, nc_), in.Bs) * tiles_of(in.Bs));
   }
   launch_stiff(a, s_);
   mass_solve(out.p, in.Bs, colK, kneed, launch_rows_grid(std::max(ne_, nc_), in.Bs));
@@ -761,7 +787,8 @@ void Engine::nonlinear_block(Blk E, Blk Y, const int *colK) {
   if (cheb() || mixed()) {
     gth.d0 = p_;
     gth.theta_inv = 1.0 / cheb_theta_;
-    gth.part_rr = rb_.partA;
+    gth.part_rr = chk_init_[chk_par_];
+    take_check(gth.chk, gth.chk_blocks, launch_rows_grid(ne_, E.Bs) * tiles_of(E.Bs));
   }
   launch_nl_gather(gth, s_);
   mass_solve(Y.p, E.Bs, colK, 0, launch_rows_grid(ne_, E.Bs));
@@ -816,6 +843,7 @@ void Engine::expL_apply(int B, const double *t, const double *Uin, double *Uout)
   TransArgs tr{n_, B, Bs, const_cast<double *>(Uin), in.p};
   launch_to_block(tr, s_);
   run_exp(eb, in, out);
+  flush_check();
   TransArgs tb{n_, B, Bs, Uout, out.p};
   launch_from_block(tb, s_);
   finish();
@@ -839,6 +867,7 @@ void Engine::swe_nonlinear(int B, const double *U, double *NU) {
   TransArgs tr{n_, B, Bs, const_cast<double *>(U), E.p};
   launch_to_block(tr, s_);
   nonlinear_block(E, Y, colK);
+  flush_check();
   TransArgs tb{n_, B, Bs, NU, Y.p};
   launch_from_block(tb, s_);
   finish();
@@ -1017,6 +1046,7 @@ void Engine::nbar_body(NbarCall &c) {
   TransArgs tr{n_, c.members, c.nb.Bm, const_cast<double *>(c.U), c.X.p};
   launch_to_block(tr, s_);
   run_nbar(c.nb, c.X, c.out, true);
+  flush_check();
   TransArgs tb{n_, c.members, c.nb.Bm, c.Nbar, c.out.p};
   launch_from_block(tb, s_);
 }
@@ -1150,6 +1180,7 @@ void Engine::step(const pa_avg *avg, double dt, int members, double *U) {
   axpy(nb_, T.p, dt / 3.0, k2.p, dt / 3.0, k3.p);
   run_exp(eh, T, Eh);                         // exp(L dt/2)(dt/3 (k2 + k3))
   axpy(nb_, X.p, 1.0, S.p, 1.0, Eh.p, dt / 6.0, k4.p);
+  flush_check();
   TransArgs tb{n_, members, Bm, U, X.p};
   launch_from_block(tb, s_);
   finish();
@@ -1188,6 +1219,7 @@ double Engine::estimate_lambda(int iters) {
     lstep(a, b, nullptr, nullptr, 1.0, colK0_, 0, nullptr);  // b = L a
     axpy(n_, v.p, -1.0, b.p);
   }
+  flush_check();
   finish();
   return std::sqrt(rho2);
 }

@@ -103,6 +103,14 @@ class Engine {
   void cg(double *x, int Bs, const int *colK, int kneed, int nwg_init);
   void cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_init);
   void mass_solve(double *x, int Bs, const int *colK, int kneed, int nwg_init);
+  // residual checks of Chebyshev solves, deferred into the next set-up kernel
+  double *chk_init_[2] = {nullptr, nullptr}, *chk_last_[2] = {nullptr, nullptr};
+  int chk_par_ = 0;
+  bool pend_ = false;
+  CheckArgs pend_args_{};
+  void defer_check(int Bs, int nwg_init, const int *colK, int kneed);
+  void take_check(CheckArgs &chk, int &blocks, int grid_blocks);
+  void flush_check();
   bool cheb() const { return cfg_.solver == PA_SOLVER_CHEBYSHEV; }
   bool mixed() const { return cfg_.precision == PA_FP32_REFINED; }
   void mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_init);

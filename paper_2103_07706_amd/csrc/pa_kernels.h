@@ -33,6 +33,19 @@ struct SolveState {
   unsigned *prof_last;    // = prof + 2
 };
 
+// Residual check after a Chebyshev solve (a kernel of its own, or folded
+// into the next solve's set-up kernel: blocks = tiles x columns/4).
+struct CheckArgs {
+  int Bs, nwg_init, nwg_last, max_wg;
+  const double *part_init, *part_last;
+  const int *colK;
+  int kneed;
+  double rtol2;
+  int *fail;
+  double *resid;
+  unsigned long long *resid_max;
+};
+
 struct StiffArgs {
   DevOps ops;
   int Bs;
@@ -54,6 +67,8 @@ struct StiffArgs {
   int acc_k, G;
   SolveState st;
   RedBuf rb;
+  CheckArgs chk;   // the previous solve's residual check, done by the first
+  int chk_blocks;  // chk_blocks workgroups (0: none)
 };
 
 struct CgArgs {
@@ -150,17 +165,6 @@ struct RefineArgs {
   int max_wg;
 };
 
-// Residual check after a Chebyshev solve.
-struct CheckArgs {
-  int Bs, nwg_init, nwg_last, max_wg;
-  const double *part_init, *part_last;
-  const int *colK;
-  int kneed;
-  double rtol2;
-  int *fail;
-  double *resid;
-  unsigned long long *resid_max;
-};
 
 enum { FIN_INIT = 0, FIN_STEP = 1, FIN_OUT = 2 };
 struct FinArgs {
@@ -210,6 +214,8 @@ struct GatherArgs {
   int kneed;
   SolveState st;
   RedBuf rb;
+  CheckArgs chk;   // as in StiffArgs
+  int chk_blocks;
 };
 
 struct AccArgs {
@@ -254,6 +260,7 @@ void launch_stiff(const StiffArgs &a, hipStream_t s);
 void launch_cg_init(const CgArgs &a, hipStream_t s);
 void launch_cheb_iter(const ChebArgs &a, hipStream_t s);
 void launch_cheb_check(const CheckArgs &a, hipStream_t s);
+int cheb_check_blocks(const CheckArgs &a);  // workgroups of a residual check
 void launch_cheb_lp_iter(const ChebLpArgs &a, hipStream_t s);
 void launch_lp_dir(const LpDirArgs &a, hipStream_t s);
 void launch_cheb32_iter(const Cheb32Args &a, hipStream_t s);

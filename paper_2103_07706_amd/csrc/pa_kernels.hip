@@ -102,6 +102,59 @@ __device__ void count_active(const Lane &L, SolveState st) {
   }
 }
 
+// Per column: |r_final|^2 <= rtol^2 |r_0|^2, else count a failure.
+__device__ void check_block(const CheckArgs &a, int blk) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ct = a.Bs < 64 ? a.Bs : 64;
+  const int cpb = ct < 4 ? ct : 4;
+  const int bpt = ct / cpb;
+  const int tile = blk / bpt;
+  // the waves of a block share its cpb columns: column cl = base + (wave % cpb),
+  // and the 4 / cpb waves of one column split the workgroup partials
+  const int split = 4 / cpb;
+  const int cl = (blk % bpt) * cpb + wave % cpb;
+  const int part = wave / cpb;
+  const int c = tile * ct + cl;
+  double b = 0.0, r = 0.0;
+  for (int w = part * 64 + lane; w < a.nwg_init; w += 64 * split)
+    b += a.part_init[((size_t)tile * a.max_wg + w) * 64 + cl];
+  for (int w = part * 64 + lane; w < a.nwg_last; w += 64 * split)
+    r += a.part_last[((size_t)tile * a.max_wg + w) * 64 + cl];
+  b = wave_col_sum(b, 1);
+  r = wave_col_sum(r, 1);
+  __shared__ double red[2][4];
+  if (lane == 0) {
+    red[0][wave] = b;
+    red[1][wave] = r;
+  }
+  __syncthreads();
+  if (part == 0 && lane == 0) {
+    b = 0.0;
+    r = 0.0;
+    for (int p = 0; p < split; p++) {  // fixed order
+      b += red[0][p * cpb + wave];
+      r += red[1][p * cpb + wave];
+    }
+    if (a.colK[c] >= a.kneed && b > 0.0) {
+      const double rel = sqrt(r / b);
+      a.resid[c] = rel;
+      // non-negative doubles order like their bit patterns
+      if (a.resid_max) atomicMax(a.resid_max, (unsigned long long)__double_as_longlong(rel));
+      if (!(r <= a.rtol2 * b)) atomicAdd(a.fail, 1);
+    }
+  }
+}
+
+__global__ __launch_bounds__(kWG) void k_cheb_check(CheckArgs a) { check_block(a, blockIdx.x); }
+
+// The previous solve's check, folded into a set-up kernel: its first
+// chk_blocks workgroups (over the whole grid) each do one check block.
+__device__ inline void folded_check(const CheckArgs &a, int blocks) {
+  if (blocks <= 0) return;
+  const int bi = blockIdx.y * gridDim.x + blockIdx.x;
+  if (bi < blocks) check_block(a, bi);
+}
+
 // ---------------------------------------------------------------- stiffness
 // One application of the linear operator with the mass solve set up:
 //   velocity: r = scale (-F u + g D' eta), out_u = addA_u + addB_u (CG start),
@@ -109,6 +162,7 @@ __device__ void count_active(const Lane &L, SolveState st) {
 // for columns with colK[c] >= kneed; optionally acc += coef * in (grouped
 // column sums of G columns) for columns with colK[c] >= acc_k.
 __global__ __launch_bounds__(kWG) void k_stiff(StiffArgs a) {
+  folded_check(a.chk, a.chk_blocks);
   const Lane L = lane_map(a.Bs, a.ops.ne > a.ops.nc ? a.ops.ne : a.ops.nc);
   const DevOps &o = a.ops;
   const int c = L.col, Bs = a.Bs;
@@ -325,48 +379,6 @@ __global__ __launch_bounds__(kWG) void k_lp_dir(LpDirArgs a) {
   }
 }
 
-// Per column: |r_final|^2 <= rtol^2 |r_0|^2, else count a failure.
-__global__ __launch_bounds__(kWG) void k_cheb_check(CheckArgs a) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int ct = a.Bs < 64 ? a.Bs : 64;
-  const int cpb = ct < 4 ? ct : 4;
-  const int bpt = ct / cpb;
-  const int tile = blockIdx.x / bpt;
-  // the waves of a block share its cpb columns: column cl = base + (wave % cpb),
-  // and the 4 / cpb waves of one column split the workgroup partials
-  const int split = 4 / cpb;
-  const int cl = (blockIdx.x % bpt) * cpb + wave % cpb;
-  const int part = wave / cpb;
-  const int c = tile * ct + cl;
-  double b = 0.0, r = 0.0;
-  for (int w = part * 64 + lane; w < a.nwg_init; w += 64 * split)
-    b += a.part_init[((size_t)tile * a.max_wg + w) * 64 + cl];
-  for (int w = part * 64 + lane; w < a.nwg_last; w += 64 * split)
-    r += a.part_last[((size_t)tile * a.max_wg + w) * 64 + cl];
-  b = wave_col_sum(b, 1);
-  r = wave_col_sum(r, 1);
-  __shared__ double red[2][4];
-  if (lane == 0) {
-    red[0][wave] = b;
-    red[1][wave] = r;
-  }
-  __syncthreads();
-  if (part == 0 && lane == 0) {
-    b = 0.0;
-    r = 0.0;
-    for (int p = 0; p < split; p++) {  // fixed order
-      b += red[0][p * cpb + wave];
-      r += red[1][p * cpb + wave];
-    }
-    if (a.colK[c] >= a.kneed && b > 0.0) {
-      const double rel = sqrt(r / b);
-      a.resid[c] = rel;
-      // non-negative doubles order like their bit patterns
-      if (a.resid_max) atomicMax(a.resid_max, (unsigned long long)__double_as_longlong(rel));
-      if (!(r <= a.rtol2 * b)) atomicAdd(a.fail, 1);
-    }
-  }
-}
 
 // ----------------------------------- FP32 inner solves, FP64 refinement
 // Mixed-precision mass solve: the correction equation M d = r is solved
@@ -841,6 +853,7 @@ __global__ __launch_bounds__(kWG) void k_nl_cell(NlArgs a) {
 
 // Velocity right-hand side r_e = C[c0][l0] + C[c1][l1] and CG start x = 0.
 __global__ __launch_bounds__(kWG) void k_nl_gather(GatherArgs a) {
+  folded_check(a.chk, a.chk_blocks);
   const Lane L = lane_map(a.Bs, a.ops.ne);
   const DevOps &o = a.ops;
   const int c = L.col, Bs = a.Bs;
@@ -1112,6 +1125,11 @@ void launch_lp_dir(const LpDirArgs &a, hipStream_t s) {
     launch_timed(k_lp_dir<13>, rows_grid(a.ops.ne, a.Bs), s, a);
   else
     launch_timed(k_lp_dir<0>, rows_grid(a.ops.ne, a.Bs), s, a);
+}
+int cheb_check_blocks(const CheckArgs &a) {
+  const int ct = a.Bs < 64 ? a.Bs : 64;
+  const int cpb = ct < 4 ? ct : 4;
+  return ((a.Bs + 63) / 64) * (ct / cpb);
 }
 void launch_cheb_check(const CheckArgs &a, hipStream_t s) {
   const int ct = a.Bs < 64 ? a.Bs : 64;
