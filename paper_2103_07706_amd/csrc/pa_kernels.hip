@@ -404,6 +404,55 @@ __global__ __launch_bounds__(kWG) void k_cheb32_iter(Cheb32Args a) {
   }
 }
 
+// The same step on four adjacent columns per lane (blocks of at least eight
+// columns): a row of Bs FP32 values is Bs/4 float4s, so the row mapping of a
+// block of Bs/4 columns applies and every load and store moves 16 bytes.
+// A group with any active column is computed whole: the FP32 scratch of
+// inactive columns is never read back (the refinement and the final check
+// skip them).
+__device__ inline float4 f4_fma(float m, float4 v, float4 q) {
+  q.x += m * v.x;
+  q.y += m * v.y;
+  q.z += m * v.z;
+  q.w += m * v.w;
+  return q;
+}
+
+__global__ __launch_bounds__(kWG) void k_cheb32_iter4(Cheb32Args a) {
+  const int Bq = a.Bs >> 2;
+  const Lane L = lane_map(Bq, a.ops.ne);
+  const DevOps &o = a.ops;
+  const int cq = L.col, c0 = 4 * cq;
+  if (a.colK[c0] < a.kneed && a.colK[c0 + 1] < a.kneed && a.colK[c0 + 2] < a.kneed &&
+      a.colK[c0 + 3] < a.kneed)
+    return;
+  const float4 *__restrict__ din = (const float4 *)a.d_in;
+  float4 *dout = (float4 *)a.d_out;
+  float4 *x = (float4 *)a.x32;
+  float4 *rr = (float4 *)a.r32;
+  for (int e = L.row0; e < L.rend; e += L.rstride) {
+    float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+#pragma unroll
+    for (int j = 0; j < 5; j++) q = f4_fma(o.mass32[5 * e + j], din[(size_t)o.ell_col[5 * e + j] * Bq + cq], q);
+    const size_t ie = (size_t)e * Bq + cq;
+    const float4 d = din[ie];
+    if (a.first) {
+      x[ie] = d;
+    } else {
+      const float4 xv = x[ie];
+      x[ie] = make_float4(xv.x + d.x, xv.y + d.y, xv.z + d.z, xv.w + d.w);
+    }
+    const float4 r0 = rr[ie];
+    const float4 r = make_float4(r0.x - q.x, r0.y - q.y, r0.z - q.z, r0.w - q.w);
+    rr[ie] = r;
+    if (!a.last) {
+      const float g = o.dinv32[e];
+      dout[ie] = make_float4(a.c1 * d.x + a.c2 * g * r.x, a.c1 * d.y + a.c2 * g * r.y,
+                             a.c1 * d.z + a.c2 * g * r.z, a.c1 * d.w + a.c2 * g * r.w);
+    }
+  }
+}
+
 __global__ __launch_bounds__(kWG) void k_refine(RefineArgs a) {
   const Lane L = lane_map(a.Bs, a.ops.ne);
   const DevOps &o = a.ops;
@@ -1138,7 +1187,12 @@ void launch_cheb_check(const CheckArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_cheb_check, dim3(tiles * (ct / cpb)), dim3(kWG), 0, s, a);
 }
 void launch_cheb32_iter(const Cheb32Args &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_cheb32_iter, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+  // the row mapping needs a power-of-two width up to 64, or a multiple of 64
+  const int bq = a.Bs / 4;
+  if (a.Bs >= 8 && a.Bs % 4 == 0 && ((bq & (bq - 1)) == 0 || bq % 64 == 0))
+    hipLaunchKernelGGL(k_cheb32_iter4, rows_grid(a.ops.ne, a.Bs / 4), dim3(kWG), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_cheb32_iter, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
 }
 void launch_refine(const RefineArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_refine, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
