@@ -189,9 +189,8 @@ def bench_batch(args):
         tune = batch.autotune(Us, cfg, cache=args.tune_cache) if args.autotune else None
         if lmin is not None:
             for i in range(len(items)):
-                t = batch.get_tune(i)
-                batch.set_tune(i, t["narrow_rows_per_thread"], t["wide_max_wg"], lmin,
-                               t["mixed_min_cols"])
+                t = dict(batch.get_tune(i), lp_min_cols=lmin)
+                batch.set_tune(i, **t)
             tune = [batch.get_tune(i) for i in range(len(items))]
         for _ in range(args.warmup):
             batch.run(Us, cfg, outs)
@@ -296,12 +295,19 @@ def main():
     # each launch carries its own start and end events
     pa.set_launch_tune(**head["tune"])
     if args.solver == "chebyshev":
-        kernel = "k_cheb_lp_iter" if head["learned"] and head["tune"]["lp_min_cols"] <= 4 \
-            else "k_cheb_iter"
-        kid = pa.PA_KERNEL_CHEB_LP_ITER if kernel == "k_cheb_lp_iter" else pa.PA_KERNEL_CHEB_ITER
+        if head["learned"] and head["tune"]["lp_min_cols"] <= 4:
+            cands = {"k_cheb_lp_iter": pa.PA_KERNEL_CHEB_LP_ITER}
+        else:
+            cands = {"k_cheb_iter": pa.PA_KERNEL_CHEB_ITER}
+            if head["tune"]["pair_steps"]:
+                cands["k_cheb_pair"] = pa.PA_KERNEL_CHEB_PAIR
     else:
-        kernel, kid = "k_cg_iter", pa.PA_KERNEL_CG_ITER
-    prof = kernel_profile(ctx, ops, avg, U, head["cfg"], out, args.steps, kid)
+        cands = {"k_cg_iter": pa.PA_KERNEL_CG_ITER}
+    # the candidate with the most event time is the dominant kernel
+    profs = {k: kernel_profile(ctx, ops, avg, U, head["cfg"], out, args.steps, kid)
+             for k, kid in cands.items()}
+    kernel = max(profs, key=lambda k: profs[k]["total_ms"])
+    prof = profs[kernel]
     elapsed, stats = head["elapsed"], head["stats"]
     value = wl.members * args.steps / elapsed
     avg_ms = prof["total_ms"] / max(1, prof["launches"])

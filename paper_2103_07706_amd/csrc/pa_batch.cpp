@@ -132,6 +132,7 @@ std::vector<unsigned char> batch_key(const pa_batch *b, const double *const *U,
     put(k, t.wide_max_wg);
     put(k, t.lp_min_cols);
     put(k, t.mixed_min_cols);
+    put(k, t.pair_steps);
   }
   return k;
 }
@@ -332,10 +333,12 @@ int pa_batch_set_tune(pa_batch *b, int item, const pa_launch_tune *t) {
     bneed(t->narrow_rows_per_thread >= 1 && t->narrow_rows_per_thread <= 64, "rows per thread in [1, 64]");
     bneed(t->wide_max_wg >= 8 && t->wide_max_wg <= 2048, "wide_max_wg in [8, 2048]");
     bneed(t->lp_min_cols >= 1 && t->mixed_min_cols >= 1, "lp_min_cols, mixed_min_cols >= 1");
+    bneed(t->pair_steps == 0 || t->pair_steps == 1, "pair_steps is 0 or 1");
     b->tune[item].narrow_rows_per_thread = t->narrow_rows_per_thread;
     b->tune[item].wide_max_wg = t->wide_max_wg;
     b->tune[item].lp_min_cols = t->lp_min_cols;
     b->tune[item].mixed_min_cols = t->mixed_min_cols;
+    b->tune[item].pair_steps = t->pair_steps;
     b->tuned[item] = true;
   });
 }
@@ -348,6 +351,7 @@ int pa_batch_get_tune(const pa_batch *b, int item, pa_launch_tune *out) {
     out->wide_max_wg = t.wide_max_wg;
     out->lp_min_cols = t.lp_min_cols;
     out->mixed_min_cols = t.mixed_min_cols;
+    out->pair_steps = t.pair_steps;
     out->best_ms = 0.0;
   });
 }
@@ -413,6 +417,12 @@ int pa_batch_autotune(pa_ctx *ctx, pa_batch *b, const double *const *U_dev,
           trial(t);
         }
       }
+      if (c.solver == PA_SOLVER_CHEBYSHEV)
+        for (int ps : {0, 1}) {
+          pa::LaunchTune t = best_t;
+          t.pair_steps = ps;
+          trial(t);
+        }
       b->tune[i] = best_t;
       b->tuned[i] = true;
       if (out) {
@@ -420,6 +430,7 @@ int pa_batch_autotune(pa_ctx *ctx, pa_batch *b, const double *const *U_dev,
         out[i].wide_max_wg = best_t.wide_max_wg;
         out[i].lp_min_cols = best_t.lp_min_cols;
         out[i].mixed_min_cols = best_t.mixed_min_cols;
+        out[i].pair_steps = best_t.pair_steps;
         out[i].best_ms = best;
       }
     }

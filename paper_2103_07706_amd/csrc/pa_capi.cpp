@@ -58,7 +58,7 @@ int pa_ctx_set_stream(pa_ctx *ctx, void *stream) {
 int pa_ctx_profile(pa_ctx *ctx, int kernel) {
   return guard([&] {
     need(ctx != nullptr, "ctx is NULL");
-    need(kernel >= PA_KERNEL_NONE && kernel <= PA_KERNEL_CHEB_LP_ITER, "unknown kernel id");
+    need(kernel >= PA_KERNEL_NONE && kernel <= PA_KERNEL_CHEB_PAIR, "unknown kernel id");
     ctx->prof_kernel = kernel;
     ctx->prof_launches = ctx->prof_work = 0;
     ctx->prof_ms = ctx->prof_bytes = 0.0;
@@ -171,7 +171,11 @@ size_t layout(pa_ops *o, char *base) {
   place(off, o->inv_area, &d.inv_area, base);
   place(off, o->bottom, &d.bottom, base);
   place(off, o->cgeo, &d.cgeo, base);
+  place(off, o->halo_off, &d.halo_off, base);
+  place(off, o->halo_row, &d.halo_row, base);
+  place(off, o->hloc, &d.hloc, base);
   if (base) {
+    d.hparts = o->hparts;
     d.ne = o->ne;
     d.nc = o->nc;
     d.g = o->g;
@@ -241,6 +245,9 @@ int pa_ops_bind(pa_ctx *ctx, pa_ops *ops, void *dev_buf) {
     up(s, d.inv_area, ops->inv_area);
     up(s, d.bottom, ops->bottom);
     up(s, d.cgeo, ops->cgeo);
+    up(s, d.halo_off, ops->halo_off);
+    up(s, d.halo_row, ops->halo_row);
+    up(s, d.hloc, ops->hloc);
     PA_HIP(hipStreamSynchronize(s));
   });
 }
@@ -526,6 +533,7 @@ int pa_get_launch_tune(pa_launch_tune *out) {
     out->wide_max_wg = t.wide_max_wg;
     out->lp_min_cols = t.lp_min_cols;
     out->mixed_min_cols = t.mixed_min_cols;
+    out->pair_steps = t.pair_steps;
     out->best_ms = 0.0;
   });
 }
@@ -536,11 +544,13 @@ int pa_set_launch_tune(const pa_launch_tune *t) {
     need(t->narrow_rows_per_thread >= 1 && t->narrow_rows_per_thread <= 64, "rows per thread in [1, 64]");
     need(t->wide_max_wg >= 8 && t->wide_max_wg <= 2048, "wide_max_wg in [8, 2048]");
     need(t->lp_min_cols >= 1 && t->mixed_min_cols >= 1, "lp_min_cols, mixed_min_cols >= 1");
+    need(t->pair_steps == 0 || t->pair_steps == 1, "pair_steps is 0 or 1");
     pa::LaunchTune lt;
     lt.narrow_rows_per_thread = t->narrow_rows_per_thread;
     lt.wide_max_wg = t->wide_max_wg;
     lt.lp_min_cols = t->lp_min_cols;
     lt.mixed_min_cols = t->mixed_min_cols;
+    lt.pair_steps = t->pair_steps;
     pa::set_launch_tuning(lt);
   });
 }
@@ -583,8 +593,8 @@ int pa_autotune(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int members, 
             best_t = t;
           }
         }
-      auto search = [&](int pa::LaunchTune::*field) {
-        for (int lmin : {1, 8, 64, kLpNever}) {
+      auto search = [&](int pa::LaunchTune::*field, std::initializer_list<int> vals) {
+        for (int lmin : vals) {
           pa::LaunchTune t = best_t;
           t.*field = lmin;
           pa::set_launch_tuning(t);
@@ -596,8 +606,9 @@ int pa_autotune(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int members, 
           }
         }
       };
-      if (c.precond == PA_PRECOND_LEARNED) search(&pa::LaunchTune::lp_min_cols);
-      if (c.precision == PA_FP32_REFINED) search(&pa::LaunchTune::mixed_min_cols);
+      if (c.precond == PA_PRECOND_LEARNED) search(&pa::LaunchTune::lp_min_cols, {1, 8, 64, kLpNever});
+      if (c.precision == PA_FP32_REFINED) search(&pa::LaunchTune::mixed_min_cols, {1, 8, 64, kLpNever});
+      if (c.solver == PA_SOLVER_CHEBYSHEV) search(&pa::LaunchTune::pair_steps, {0, 1});
     } catch (...) {
       pa::set_launch_tuning(keep);
       throw;
@@ -607,6 +618,7 @@ int pa_autotune(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int members, 
     out->wide_max_wg = best_t.wide_max_wg;
     out->lp_min_cols = best_t.lp_min_cols;
     out->mixed_min_cols = best_t.mixed_min_cols;
+    out->pair_steps = best_t.pair_steps;
     out->best_ms = best;
   });
 }

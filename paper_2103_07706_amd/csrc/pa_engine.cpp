@@ -165,12 +165,12 @@ void Engine::mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_
 // d_0 = D^-1 r_0 / theta (p) and partials of |r_0|^2 (partA).
 // Residual check of the solve just enqueued: deferred to the next set-up
 // kernel (take_check) or to flush_check at the end of the call.
-void Engine::defer_check(int Bs, int nwg_init, const int *colK, int kneed) {
+void Engine::defer_check(int Bs, int nwg_init, const int *colK, int kneed, int nwg_last) {
   CheckArgs &ck = pend_args_;
   ck = CheckArgs{};
   ck.Bs = Bs;
   ck.nwg_init = nwg_init;
-  ck.nwg_last = launch_rows_grid(ne_, Bs);
+  ck.nwg_last = nwg_last >= 0 ? nwg_last : launch_rows_grid(ne_, Bs);
   ck.max_wg = rb_.max_wg;
   ck.part_init = chk_init_[chk_par_];
   ck.part_last = chk_last_[chk_par_];
@@ -225,8 +225,75 @@ void Engine::mass_solve(double *x, int Bs, const int *colK, int kneed, int nwg_i
 // autotuner measures.
 bool Engine::lp_cheaper(int Bs) const { return lp_avail_ && Bs >= launch_tuning().lp_min_cols; }
 
+// Jacobi semi-iteration of a single column, two steps per launch
+// (k_cheb_pair) after one single step when the step count is odd.  r and d
+// move between two buffers each from one pair to the next.
+void Engine::cheb_pairs(double *x, const int *colK, int kneed, int nwg_init, int grid) {
+  const std::vector<double> &c1 = cheb_c1_, &c2 = cheb_c2_;
+  const int k = (int)c1.size();
+  double *d[2] = {p_, s0_};
+  double *r[2] = {r_, r1_};
+  int i = 0, di = 0, ri = 0;
+  if (k % 2) {
+    ChebArgs a{};
+    a.ops = ops_->d;
+    a.Bs = 1;
+    a.x = x;
+    a.r = r_;
+    a.colK = colK;
+    a.kneed = kneed;
+    a.part = chk_last_[chk_par_];
+    a.max_wg = rb_.max_wg;
+    a.d_in = d[0];
+    a.d_out = d[1];
+    a.c1 = c1[0];
+    a.c2 = c2[0];
+    a.last = k == 1 ? 1 : 0;
+    const bool prof = ctx_->prof_kernel == PA_KERNEL_CHEB_ITER;
+    a.prof = prof ? st_.prof : nullptr;
+    if (prof) bracket_begin();
+    launch_cheb_iter(a, s_);
+    if (prof) bracket_end(1);
+    i = 1;
+    di = 1;
+  }
+  ChebPairArgs a{};
+  a.ops = ops_->d;
+  a.x = x;
+  a.colK = colK;
+  a.kneed = kneed;
+  a.part = chk_last_[chk_par_];
+  const bool prof = ctx_->prof_kernel == PA_KERNEL_CHEB_PAIR;
+  a.prof = prof ? st_.prof : nullptr;
+  const int pairs = (k - i) / 2;
+  if (prof && pairs > 0) bracket_begin();
+  for (; i < k; i += 2) {
+    a.d_in = d[di];
+    a.d_out = d[di ^ 1];
+    a.r_in = r[ri];
+    a.r_out = r[ri ^ 1];
+    a.c1a = c1[i];
+    a.c2a = c2[i];
+    a.c1b = c1[i + 1];
+    a.c2b = c2[i + 1];
+    a.last = i + 2 == k ? 1 : 0;
+    launch_cheb_pair(a, s_);
+    di ^= 1;
+    ri ^= 1;
+  }
+  if (prof && pairs > 0) bracket_end(pairs);
+  defer_check(1, nwg_init, colK, kneed, pairs > 0 ? grid : -1);
+  stats.solves++;
+  stats.cg_iters += k;
+  stats.cg_iters_max = std::max(stats.cg_iters_max, k);
+}
+
 void Engine::cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_init) {
   const bool lp = lp_cheaper(Bs);
+  if (!lp && Bs == 1 && launch_tuning().pair_steps) {
+    const int grid = cheb_pair_grid(ops_->d);
+    if (grid > 0) return cheb_pairs(x, colK, kneed, nwg_init, grid);
+  }
   const std::vector<double> &c1 = lp ? lp_c1_ : cheb_c1_, &c2 = lp ? lp_c2_ : cheb_c2_;
   const int k = (int)c1.size();
   double *d[2] = {p_, s0_};
@@ -462,6 +529,15 @@ void Engine::finish() {
                                                (68.0 + 8.0 * ops_->lp_wp) * work)
                               : (double)ne_ * (48.0 * cols + 40.0 * (unsigned)h[4] +
                                                (60.0 + 8.0 * (ops_->lp_wp + ops_->lp_wpm)) * work);
+    // two steps on one column, per row: the ELL row, its part-local
+    // columns (2 bytes each) and the Jacobi diagonal; x in and out, r and d
+    // in, r' out, and d' out except on the solve's last pair; per launch the
+    // part's halo list
+    if (ctx_->prof_kernel == PA_KERNEL_CHEB_PAIR) {
+      const double halo = 4.0 * (ops_->halo_row.size() + ops_->halo_off.size());
+      ctx_->prof_bytes += (double)ne_ * (126.0 * cols + 118.0 * (unsigned)h[4]) +
+                          halo * (cols + (unsigned)h[4]);
+    }
     ctx_->prof_work += (int64_t)work;
   }
   float ms = 0;

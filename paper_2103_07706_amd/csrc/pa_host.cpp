@@ -134,6 +134,7 @@ Mesh build_icosahedral(int level, double radius) {
 }
 
 void mass_spectrum(pa_ops *o, int steps, double *lmin, double *lmax);
+void build_row_parts(pa_ops *o);
 
 namespace {
 
@@ -269,7 +270,42 @@ void assemble_ops(pa_ops *o, const Mesh &m, const pa_phys &ph) {
     o->dinv32[e] = (float)o->dinv[e];
   }
   for (int i = 0; i < 5 * ne; i++) o->mass32[i] = (float)o->mass[i];
+  build_row_parts(o);
   mass_spectrum(o, 200, &o->mass_eig_min, &o->mass_eig_max);
+}
+
+// Row parts of the edge mass matrix for the two-step solve kernel: halo of
+// each part (ELL columns outside it, ascending) and every ELL column of
+// every row as an index into its part's local numbering.
+void build_row_parts(pa_ops *o) {
+  const int ne = o->ne, P = (ne + kPartRows - 1) / kPartRows;
+  o->halo_off.assign(P + 1, 0);
+  o->halo_row.clear();
+  o->hloc.assign((size_t)5 * ne, 0);
+  bool ok = true;
+  std::vector<int32_t> h;
+  for (int p = 0; p < P; p++) {
+    const int e0 = p * kPartRows, e1 = std::min(ne, e0 + kPartRows);
+    h.clear();
+    for (int e = e0; e < e1; e++)
+      for (int j = 0; j < 5; j++) {
+        const int c = o->ell_col[5 * e + j];
+        if (c < e0 || c >= e1) h.push_back(c);
+      }
+    std::sort(h.begin(), h.end());
+    h.erase(std::unique(h.begin(), h.end()), h.end());
+    if ((int)h.size() > kHaloMax) ok = false;
+    for (int e = e0; e < e1; e++)
+      for (int j = 0; j < 5; j++) {
+        const int c = o->ell_col[5 * e + j];
+        int loc = c - e0;
+        if (c < e0 || c >= e1) loc = kPartRows + (int)(std::lower_bound(h.begin(), h.end(), c) - h.begin());
+        o->hloc[(size_t)j * ne + e] = (uint16_t)std::min(loc, 65535);
+      }
+    o->halo_row.insert(o->halo_row.end(), h.begin(), h.end());
+    o->halo_off[p + 1] = (int32_t)o->halo_row.size();
+  }
+  o->hparts = ok ? P : 0;
 }
 
 namespace {

@@ -80,6 +80,12 @@ Mesh build_icosahedral(int level, double radius);
 constexpr int kCellGeo = 32;
 // Per-edge tangential-trace table: tau[side][gauss][j] (2*2*3).
 constexpr int kEdgeTau = 12;
+// Row parts of the two-step mass-solve kernel: part p holds the kPartRows
+// edges [p kPartRows, (p + 1) kPartRows); its halo is the other edges its
+// rows' ELL columns reach, at most kHaloMax per part (else the kernel is not
+// used on that mesh).
+constexpr int kPartRows = 256;
+constexpr int kHaloMax = 256;
 
 // Device-resident operator arrays (pointers into the caller's buffer).
 struct DevOps {
@@ -102,6 +108,12 @@ struct DevOps {
   const double *inv_area = nullptr;   // nc
   const double *bottom = nullptr;     // nc
   const double *cgeo = nullptr;       // nc*kCellGeo
+  // row parts (see kPartRows): hparts parts, 0 if a halo exceeds kHaloMax
+  int hparts = 0;
+  const int32_t *halo_off = nullptr;  // hparts+1: part p's halo rows are halo_row[halo_off[p]..)
+  const int32_t *halo_row = nullptr;  // ascending within a part
+  const uint16_t *hloc = nullptr;     // 5*ne, [slot][row]: ELL column as a part-local index
+                                      // (row offset in the part, or kPartRows + halo position)
 };
 
 // Learned preconditioner on the device: P = G G^T and P M as column-major
@@ -119,9 +131,11 @@ struct LaunchTune {
   int wide_max_wg = 2048;          // workgroups per column tile, wider batches
   int lp_min_cols = 8;             // learned mass-solve steps on blocks this wide or wider
   int mixed_min_cols = 8;          // FP32-refined mass solves on blocks this wide or wider
+  int pair_steps = 1;              // single-column Jacobi Chebyshev solves: two steps per launch
   bool operator==(const LaunchTune &o) const {
     return narrow_rows_per_thread == o.narrow_rows_per_thread && wide_max_wg == o.wide_max_wg &&
-           lp_min_cols == o.lp_min_cols && mixed_min_cols == o.mixed_min_cols;
+           lp_min_cols == o.lp_min_cols && mixed_min_cols == o.mixed_min_cols &&
+           pair_steps == o.pair_steps;
   }
 };
 
@@ -183,6 +197,9 @@ struct pa_ops {
   std::vector<int32_t> ell_col, ecell, cidx, side_edges, cedge, csgn, cnbr;
   std::vector<double> mass, cor, dinv, area, inv_area, bottom, cgeo, tau;
   std::vector<float> mass32, dinv32;
+  int hparts = 0;
+  std::vector<int32_t> halo_off, halo_row;
+  std::vector<uint16_t> hloc;
   size_t dev_bytes = 0;
   void *dev = nullptr;
   pa::DevOps d;

@@ -107,6 +107,21 @@ struct ChebArgs {
   int nodir;       // 1: update x and r only (the direction comes from another kernel)
 };
 
+// Two Jacobi Chebyshev steps of a single-column solve in one launch (see
+// k_cheb_pair): steps with (c1a, c2a) then (c1b, c2b); r and d each move
+// from an input to an output buffer (other workgroups still read the inputs).
+struct ChebPairArgs {
+  DevOps ops;
+  double *x;
+  const double *r_in, *d_in;
+  double *r_out, *d_out;
+  double c1a, c2a, c1b, c2b;
+  const int *colK;
+  int kneed, last;  // last: the second step is the solve's last (partials of r.r, no direction)
+  double *part;
+  unsigned *prof;   // measurement hook, as ChebArgs
+};
+
 // Chebyshev step with the learned preconditioner P (see k_cheb_lp_iter):
 // residuals ping-pong between r_in and r_out.
 struct ChebLpArgs {
@@ -259,6 +274,8 @@ void launch_finalize(const FinArgs &a, hipStream_t s);
 void launch_stiff(const StiffArgs &a, hipStream_t s);
 void launch_cg_init(const CgArgs &a, hipStream_t s);
 void launch_cheb_iter(const ChebArgs &a, hipStream_t s);
+void launch_cheb_pair(const ChebPairArgs &a, hipStream_t s);
+int cheb_pair_grid(const DevOps &o);  // workgroups of k_cheb_pair (0: not available)
 void launch_cheb_check(const CheckArgs &a, hipStream_t s);
 int cheb_check_blocks(const CheckArgs &a);  // workgroups of a residual check
 void launch_cheb_lp_iter(const ChebLpArgs &a, hipStream_t s);

@@ -274,6 +274,92 @@ __global__ __launch_bounds__(kWG) void k_cheb_iter(ChebArgs a) {
   if (a.last) wg_partials<1>(L, sums, a.part, a.max_wg);
 }
 
+// Two steps of the single-column Jacobi semi-iteration in one launch.  A
+// step costs little beyond its launch and the latency of its dependent
+// gather, so pairs of steps halve both.  Workgroup p owns the kPartRows rows
+// of part p.  First step: every row of the part and of its halo (the rows its
+// ELL columns reach outside the part) forms
+//   r' = r - M d,  d' = c1a d + c2a D^-1 r'
+// from the previous launch's r and d, with d' kept in LDS (the halo rows'
+// values are formed again by the workgroup that owns them, in the same
+// order, hence bit for bit the same).  Second step, on the part's rows only,
+// gathers d' from LDS:
+//   x += d + d',  r'' = r' - M d',  d'' = c1b d' + c2b D^-1 r''.
+// Halo rows are read from r and d, which other workgroups do not write in
+// this launch: r'' and d'' go to separate output buffers.  Parts are laid
+// over the XCDs like lane_map's slices (XCD k takes parts k per .. k per + per
+// - 1), so neighbouring parts and their halos share an L2.
+__global__ __launch_bounds__(kWG) void k_cheb_pair(ChebPairArgs a) {
+  const DevOps &o = a.ops;
+  const int t = threadIdx.x;
+  if (a.prof && blockIdx.x == 0 && t == 0) {
+    atomicAdd(&a.prof[a.last ? 2 : 0], a.colK[0] >= a.kneed ? 1u : 0u);
+    atomicAdd(&a.prof[1], 1u);
+  }
+  if (a.colK[0] < a.kneed) return;  // inactive column: its partials are not read
+  const int per = gridDim.x >> 3;
+  const int p = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  __shared__ double dA[kPartRows + kHaloMax];
+  __shared__ double red[kWG / 64];
+  double s = 0.0;
+  if (p < o.hparts) {
+    const int e0 = p * kPartRows;
+    const int nrow = min(kPartRows, o.ne - e0);
+    const int h0 = o.halo_off[p], nh = o.halo_off[p + 1] - h0;
+    double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, x1 = 0.0, r1 = 0.0;
+    if (t < nrow) {
+      const int e = e0 + t;
+      int col[5];
+#pragma unroll
+      for (int j = 0; j < 5; j++) {
+        col[j] = o.ell_col[5 * e + j];
+        m[j] = o.mass[5 * e + j];
+      }
+      double q = 0.0;
+#pragma unroll
+      for (int j = 0; j < 5; j++) q += m[j] * a.d_in[col[j]];
+      const double d = a.d_in[e];
+      x1 = a.x[e] + d;
+      r1 = a.r_in[e] - q;
+      dA[t] = cheb_dir(a.c1a, a.c2a, d, o.dinv[e], r1);
+    }
+    if (t < nh) {
+      const int g = o.halo_row[h0 + t];
+      double q = 0.0;
+#pragma unroll
+      for (int j = 0; j < 5; j++) q += o.mass[5 * g + j] * a.d_in[o.ell_col[5 * g + j]];
+      dA[kPartRows + t] = cheb_dir(a.c1a, a.c2a, a.d_in[g], o.dinv[g], a.r_in[g] - q);
+    }
+    __syncthreads();
+    if (t < nrow) {
+      const int e = e0 + t;
+      double q = 0.0;
+#pragma unroll
+      for (int j = 0; j < 5; j++) q += m[j] * dA[o.hloc[(size_t)j * o.ne + e]];
+      const double d = dA[t];
+      const double r2 = r1 - q;
+      a.x[e] = x1 + d;
+      a.r_out[e] = r2;
+      if (a.last)
+        s = r2 * r2;
+      else
+        a.d_out[e] = cheb_dir(a.c1b, a.c2b, d, o.dinv[e], r2);
+    }
+  }
+  if (a.last) {
+    // partial of r.r per workgroup, at the place of tile 0, column 0 of
+    // wg_partials' layout
+    s = wave_col_sum(s, 1);
+    if ((t & 63) == 0) red[t >> 6] = s;
+    __syncthreads();
+    if (t == 0) {
+      double w = 0.0;
+      for (int i = 0; i < kWG / 64; i++) w += red[i];
+      a.part[(size_t)blockIdx.x * 64] = w;
+    }
+  }
+}
+
 // The same semi-iteration preconditioned by the learned P = G G^T:
 //   x += d_k,  r_{k+1} = r_k - M d_k,  d_{k+1} = c1 d_k + c2 P r_{k+1},
 // with P r_{k+1} formed as P r_k - (P M) d_k so that one kernel per step
@@ -1142,6 +1228,7 @@ void set_launch_tuning(const LaunchTune &t) {
   if (g_tune.wide_max_wg > 2048) g_tune.wide_max_wg = 2048;
   if (g_tune.lp_min_cols < 1) g_tune.lp_min_cols = 1;
   if (g_tune.mixed_min_cols < 1) g_tune.mixed_min_cols = 1;
+  g_tune.pair_steps = g_tune.pair_steps ? 1 : 0;
 }
 int launch_rows_grid(int rows, int Bs) { return grid_rows(rows, Bs); }
 
@@ -1159,6 +1246,14 @@ void arm_launch_events(hipEvent_t e0, hipEvent_t e1) {
 bool launch_events_armed() { return g_ev0 != nullptr; }
 void launch_cheb_iter(const ChebArgs &a, hipStream_t s) {
   launch_timed(k_cheb_iter, rows_grid(a.ops.ne, a.Bs), s, a);
+}
+int cheb_pair_grid(const DevOps &o) {
+  if (o.hparts <= 0) return 0;
+  const int g = (o.hparts + 7) / 8 * 8;
+  return g <= launch_max_wg() ? g : 0;
+}
+void launch_cheb_pair(const ChebPairArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_cheb_pair, dim3(cheb_pair_grid(a.ops)), dim3(kWG), 0, s, a);
 }
 // The icosahedral meshes give P and P M widths 13 and 27 at every level;
 // other widths take the generic loop.

@@ -50,6 +50,7 @@ class SolveCfg(ctypes.Structure):
 
 PA_PRECOND_JACOBI, PA_PRECOND_LEARNED = 0, 1
 PA_KERNEL_NONE, PA_KERNEL_CG_ITER, PA_KERNEL_CHEB_ITER, PA_KERNEL_CHEB_LP_ITER = 0, 1, 2, 3
+PA_KERNEL_CHEB_PAIR = 4
 
 
 class TrainCfg(ctypes.Structure):
@@ -76,7 +77,23 @@ class KernelProfile(ctypes.Structure):
 class LaunchTune(ctypes.Structure):
     _fields_ = [("narrow_rows_per_thread", ctypes.c_int32), ("wide_max_wg", ctypes.c_int32),
                 ("best_ms", ctypes.c_double), ("lp_min_cols", ctypes.c_int32),
-                ("mixed_min_cols", ctypes.c_int32)]
+                ("mixed_min_cols", ctypes.c_int32), ("pair_steps", ctypes.c_int32)]
+
+
+TUNE_FIELDS = ("narrow_rows_per_thread", "wide_max_wg", "lp_min_cols", "mixed_min_cols",
+               "pair_steps")
+TUNE_DEFAULTS = {"lp_min_cols": 8, "mixed_min_cols": 8, "pair_steps": 1}
+
+
+def _tune_dict(t) -> dict:
+    return {k: getattr(t, k) for k in TUNE_FIELDS}
+
+
+def _tune_struct(d) -> "LaunchTune":
+    t = LaunchTune()
+    for k in TUNE_FIELDS:
+        setattr(t, k, d[k] if k in d else TUNE_DEFAULTS[k])
+    return t
 
 
 class Stats(ctypes.Structure):
@@ -211,17 +228,14 @@ def get_launch_tune() -> dict:
     """Process-wide launch shape (pa_get_launch_tune)."""
     t = LaunchTune()
     _check(lib().pa_get_launch_tune(ctypes.byref(t)))
-    return {"narrow_rows_per_thread": t.narrow_rows_per_thread, "wide_max_wg": t.wide_max_wg,
-            "lp_min_cols": t.lp_min_cols, "mixed_min_cols": t.mixed_min_cols}
+    return _tune_dict(t)
 
 
 def set_launch_tune(**changes):
     """Change fields of the process-wide launch shape (pa_set_launch_tune)."""
     cur = get_launch_tune()
     cur.update(changes)
-    t = LaunchTune(cur["narrow_rows_per_thread"], cur["wide_max_wg"], 0.0, cur["lp_min_cols"],
-                   cur["mixed_min_cols"])
-    _check(lib().pa_set_launch_tune(ctypes.byref(t)))
+    _check(lib().pa_set_launch_tune(ctypes.byref(_tune_struct(cur))))
 
 
 def solve_cfg(precision=PA_FP64, backward=PA_BACKWARD_PER_TERM, maxit=None, cg_rtol=None,
@@ -442,19 +456,14 @@ class Ops:
         if cache and os.path.exists(cache):
             table = json.load(open(cache))
             if key in table:
-                e = table[key]
-                t = LaunchTune(e["narrow_rows_per_thread"], e["wide_max_wg"], 0.0,
-                               e.get("lp_min_cols", 8), e.get("mixed_min_cols", 8))
-                _check(lib().pa_set_launch_tune(ctypes.byref(t)))
+                _check(lib().pa_set_launch_tune(ctypes.byref(_tune_struct(table[key]))))
                 return dict(table[key], cached=True)
         out = U.new_empty(U.shape)
         ws, nb = self.workspace(avg, members, cfg)
         t = LaunchTune()
         _check(lib().pa_autotune(self.ctx._h, self._h, avg._h, members, _ptr(U), _ptr(out), ws,
                                  nb, ctypes.byref(cfg), ctypes.byref(t)))
-        res = {"narrow_rows_per_thread": t.narrow_rows_per_thread, "wide_max_wg": t.wide_max_wg,
-               "lp_min_cols": t.lp_min_cols, "mixed_min_cols": t.mixed_min_cols,
-               "best_ms": t.best_ms}
+        res = dict(_tune_dict(t), best_ms=t.best_ms)
         if cache:
             table[key] = res
             with open(cache, "w") as f:
@@ -526,15 +535,16 @@ class Batch:
         return outs, [s.as_dict() for s in st]
 
     def set_tune(self, item, narrow_rows_per_thread, wide_max_wg, lp_min_cols=8,
-                 mixed_min_cols=8):
-        t = LaunchTune(narrow_rows_per_thread, wide_max_wg, 0.0, lp_min_cols, mixed_min_cols)
+                 mixed_min_cols=8, pair_steps=1):
+        t = _tune_struct(dict(narrow_rows_per_thread=narrow_rows_per_thread,
+                              wide_max_wg=wide_max_wg, lp_min_cols=lp_min_cols,
+                              mixed_min_cols=mixed_min_cols, pair_steps=pair_steps))
         _check(lib().pa_batch_set_tune(self._h, item, ctypes.byref(t)))
 
     def get_tune(self, item):
         t = LaunchTune()
         _check(lib().pa_batch_get_tune(self._h, item, ctypes.byref(t)))
-        return {"narrow_rows_per_thread": t.narrow_rows_per_thread, "wide_max_wg": t.wide_max_wg,
-                "lp_min_cols": t.lp_min_cols, "mixed_min_cols": t.mixed_min_cols}
+        return _tune_dict(t)
 
     def autotune(self, Us, cfg=None, cache=None):
         """Per-item launch shapes (pa_batch_autotune).  With a JSON cache, an
@@ -550,17 +560,14 @@ class Batch:
             table = json.load(open(cache))
         if all(k in table for k in keys):
             for i, k in enumerate(keys):
-                self.set_tune(i, table[k]["narrow_rows_per_thread"], table[k]["wide_max_wg"],
-                              table[k].get("lp_min_cols", 8), table[k].get("mixed_min_cols", 8))
+                _check(lib().pa_batch_set_tune(self._h, i, ctypes.byref(_tune_struct(table[k]))))
             return [dict(table[k], cached=True) for k in keys]
         outs = [U.new_empty(U.shape) for U in Us]
         up, op = self._ptrs(Us, outs)
         ws, nb = self.workspace(cfg)
         t = (LaunchTune * len(self.items))()
         _check(lib().pa_batch_autotune(self.ctx._h, self._h, up, op, ws, nb, ctypes.byref(cfg), t))
-        res = [{"narrow_rows_per_thread": x.narrow_rows_per_thread, "wide_max_wg": x.wide_max_wg,
-                "lp_min_cols": x.lp_min_cols, "mixed_min_cols": x.mixed_min_cols,
-                "best_ms": x.best_ms} for x in t]
+        res = [dict(_tune_dict(x), best_ms=x.best_ms) for x in t]
         if cache:
             table.update(dict(zip(keys, res)))
             with open(cache, "w") as f:

@@ -124,8 +124,7 @@ def test_gpu_batch_autotune_and_replay(tmp_path):
     again = b2.autotune(states, cfg, cache=cache)
     assert all(t["cached"] for t in again)
     assert [b2.get_tune(i) for i in range(len(ITEMS))] == \
-        [{k: t[k] for k in ("narrow_rows_per_thread", "wide_max_wg", "lp_min_cols",
-                            "mixed_min_cols")} for t in tunes]
+        [{k: t[k] for k in pa.TUNE_FIELDS} for t in tunes]
 
 
 def test_gpu_batch_errors():

@@ -226,14 +226,16 @@ def test_gpu_chebyshev_solver_parity(backward):
         assert rel_w(oo, got[j], ref) < TOL
 
 
-def test_gpu_chebyshev_check_failure_falls_back():
+@pytest.mark.parametrize("maxit", [3, 4])
+def test_gpu_chebyshev_check_failure_falls_back(maxit):
     """Too few Chebyshev steps (maxit caps them) fail the final residual
     check; the call is repeated with CG, which then reports non-convergence
-    under the same cap."""
+    under the same cap.  maxit 3 and 4: the single-column solves end with
+    one pair of steps after a single step, or with two pairs."""
     from paper_2103_07706_amd import pa
     om, oo, lm, lo, mm, lb = pair(2)
     U = to_dev(mm.state(bumps(om, [0])))
-    cfg = pa.solve_cfg(maxit=4, cg_rtol=1e-12, **CHEB)
+    cfg = pa.solve_cfg(maxit=maxit, cg_rtol=1e-12, **CHEB)
     with pytest.raises(pa.PAError) as ei:
         lo.swe_nonlinear(U, cfg)
     assert ei.value.code == 4
@@ -266,5 +268,43 @@ def test_gpu_fp32_refined_parity(backward, mixed_min_cols):
         out2, _ = lo.swe_nonlinear(to_dev(mm.state(U)), cfg)
         ref2 = oo.nonlinear(U[0], rtol=1e-14)
         assert rel_w(oo, mm.back(out2.cpu().numpy())[0], ref2) < 1e-10
+    finally:
+        pa.set_launch_tune(**keep)
+
+
+@pytest.mark.parametrize("level", [2, 3, 4])
+@pytest.mark.parametrize("tol", ["parity", "metric"])
+def test_gpu_cheb_pair_steps(level, tol):
+    """Single-column Jacobi Chebyshev solves two steps per launch (each
+    workgroup forms the first step again on its halo rows) against one step
+    per launch: the same Nbar bit for bit (every row's arithmetic is the
+    same), residuals within the tolerance, and parity with the oracle.
+    Parts of 256 rows, the last one ragged at levels 3 and 4; the parity
+    tolerance gives an even step count here and the metric one an odd one
+    (a single step before the pairs); the metric case also runs captured."""
+    from paper_2103_07706_amd import pa
+    keep = pa.get_launch_tune()
+    try:
+        om, oo, lm, lo, mm, lb = pair(level)
+        U = bumps(om, [4])
+        avg = pa.Avg(8, 3600.0)
+        kw = PARITY if tol == "parity" else dict(cheb_tol=1e-6, cg_rtol=1e-10)
+        cfg = pa.solve_cfg(backward=pa.PA_BACKWARD_CLENSHAW, weight_cut=0.0,
+                           use_graph=tol == "metric", **kw, **CHEB)
+        res = {}
+        for ps in (0, 1):
+            pa.set_launch_tune(pair_steps=ps)
+            for rep in range(2 if tol == "metric" else 1):
+                out, st = lo.phase_avg_rhs(avg, to_dev(mm.state(U)), cfg)
+                assert 0 < st["resid_max"] <= kw["cg_rtol"], st["resid_max"]
+                assert st["fallbacks"] == 0
+                got = out.cpu().numpy()
+                if ps in res:
+                    assert np.array_equal(got, res[ps])  # graph replay
+                res[ps] = got
+        assert np.array_equal(res[0], res[1])
+        if tol == "parity":
+            ref = oo.phase_avg_rhs(lb, avg.s, avg.w, U[0], tol=1e-13, rtol=1e-14)
+            assert rel_w(oo, mm.back(res[1])[0], ref) < TOL
     finally:
         pa.set_launch_tune(**keep)
