@@ -746,76 +746,104 @@ __global__ __launch_bounds__(kWG) void k_cg_iter(CgArgs a) {
 }
 
 // ------------------------------------------- forward combination of a basis
-// E[row][mem*G + m] = sum_k cf[k][m] R_k[row][mem], both row ranges.  One
-// thread per (row, member): it reads that member's basis values R_0..R_kmax
-// (consecutive threads, consecutive addresses) and writes its G outputs as
-// one contiguous run; the coefficients sit in LDS.  Chunks of 16 outputs keep
-// the accumulators in registers.
-constexpr int kCoefLds = 6144;  // doubles of coefficient table held in LDS
+// E[row][mem*G + m] = sum_k cf[k][m] R_k[row][mem], both row ranges, with
+// t = row * BsR + mem.  A workgroup takes tiles of kTT consecutive t: it
+// stages R_k[t] (k in chunks of kKC) and the matching coefficients in LDS,
+// then lane m of wave w forms E[t][m] for the 16 t of the wave, so each
+// t's G outputs leave as one contiguous store of the wave.  k runs in
+// ascending order as in the definition.
+constexpr int kTT = 64;  // t per tile
+constexpr int kKC = 64;  // k (or m) per LDS chunk
 
 __global__ __launch_bounds__(kWG) void k_combine(CombineArgs a) {
-  __shared__ double cf[kCoefLds];
-  const int ncoef = (a.kmax + 1) * a.G;
-  const bool lds = ncoef <= kCoefLds;
-  if (lds)
-    for (int i = threadIdx.x; i < ncoef; i += kWG) cf[i] = a.cf[i];
-  __syncthreads();
-  const double *C = lds ? cf : a.cf;
+  __shared__ double bt[kKC][kTT];
+  __shared__ double cs[kKC][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const long total = (long)a.nrows * a.BsR;
-  for (long t = (long)blockIdx.x * kWG + threadIdx.x; t < total; t += (long)gridDim.x * kWG) {
-    const long row = t / a.BsR;
-    const int mem = (int)(t - row * a.BsR);
-    double *out = a.E + t * a.G;
-    if (mem >= a.members) {
-      for (int m = 0; m < a.G; m++) out[m] = 0.0;
-      continue;
-    }
-    const double *R = a.basis + t;
-    for (int m0 = 0; m0 < a.G; m0 += 16) {
+  const long ntiles = (total + kTT - 1) / kTT;
+  for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long t0 = tile * kTT;
+    const int nt = (int)min((long)kTT, total - t0);
+    for (int mc = 0; mc < a.G; mc += 64) {
+      const int m = mc + lane;
       double acc[16];
 #pragma unroll
-      for (int j = 0; j < 16; j++) acc[j] = 0.0;
-      for (int k = 0; k <= a.kmax; k++) {
-        const double r = R[(size_t)k * a.basis_stride];
-        const double *ck = C + k * a.G + m0;
+      for (int i = 0; i < 16; i++) acc[i] = 0.0;
+      for (int k0 = 0; k0 <= a.kmax; k0 += kKC) {
+        const int nk = min(kKC, a.kmax + 1 - k0);
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < nk * kTT; idx += kWG) {
+          const int kk = idx / kTT, i = idx % kTT;
+          bt[kk][i] = i < nt ? a.basis[(size_t)(k0 + kk) * a.basis_stride + t0 + i] : 0.0;
+        }
+        for (int idx = threadIdx.x; idx < nk * 64; idx += kWG) {
+          const int kk = idx / 64, j = idx % 64;
+          cs[kk][j] = mc + j < a.G ? a.cf[(size_t)(k0 + kk) * a.G + mc + j] : 0.0;
+        }
+        __syncthreads();
+        for (int kk = 0; kk < nk; kk++) {
+          const double c = cs[kk][lane];
 #pragma unroll
-        for (int j = 0; j < 16; j++)
-          if (m0 + j < a.G) acc[j] += ck[j] * r;
+          for (int i = 0; i < 16; i++) acc[i] += c * bt[kk][w * 16 + i];
+        }
       }
+      if (m < a.G) {
 #pragma unroll
-      for (int j = 0; j < 16; j++)
-        if (m0 + j < a.G) out[m0 + j] = acc[j];
+        for (int i = 0; i < 16; i++) {
+          const int ti = w * 16 + i;
+          if (ti < nt) {
+            const long t = t0 + ti;
+            a.E[t * a.G + m] = (int)(t % a.BsR) < a.members ? acc[i] : 0.0;
+          }
+        }
+      }
     }
   }
 }
 
-// Z_k[row][mem] = sum_m cb[k][m] Y[row][mem*G + m], k = 0..kmax.  One thread
-// per (row, member): it reads its G contiguous values of Y once per chunk of
-// 16 degrees and writes Z_k for consecutive (row, member) across threads.
+// Z[k][t] = sum_m cb[k][m] Y[t][m] (backward terms reduced to one series per
+// member).  A workgroup stages kTT rows Y[t][.] (m in chunks of 64, rows
+// padded against bank conflicts) and cb for a chunk of kKC values of k; lane
+// i of wave w forms Z[k][t0 + i] for k = k0 + w + 4 j, and the wave stores
+// each k's 64 values as one contiguous run.  m runs in ascending order.
 __global__ __launch_bounds__(kWG) void k_reduce_terms(ReduceTermsArgs a) {
-  __shared__ double cb[kCoefLds];
-  const int ncoef = (a.kmax + 1) * a.G;
-  const bool lds = ncoef <= kCoefLds;
-  if (lds)
-    for (int i = threadIdx.x; i < ncoef; i += kWG) cb[i] = a.cb[i];
-  __syncthreads();
-  const double *C = lds ? cb : a.cb;
+  __shared__ double ys[kTT][65];
+  __shared__ double cs[kKC][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const long total = (long)a.nrows * a.BsZ;
-  for (long t = (long)blockIdx.x * kWG + threadIdx.x; t < total; t += (long)gridDim.x * kWG) {
-    const double *y = a.Y + t * a.G;
-    for (int k0 = 0; k0 <= a.kmax; k0 += 16) {
+  const long ntiles = (total + kTT - 1) / kTT;
+  for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long t0 = tile * kTT;
+    const int nt = (int)min((long)kTT, total - t0);
+    for (int k0 = 0; k0 <= a.kmax; k0 += kKC) {
+      const int nk = min(kKC, a.kmax + 1 - k0);
       double acc[16];
 #pragma unroll
       for (int j = 0; j < 16; j++) acc[j] = 0.0;
-      for (int m = 0; m < a.G; m++) {
-        const double v = y[m];
+      for (int mc = 0; mc < a.G; mc += 64) {
+        const int nm = min(64, a.G - mc);
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < kTT * 64; idx += kWG) {
+          const int i = idx / 64, j = idx % 64;
+          ys[i][j] = i < nt && j < nm ? a.Y[(t0 + i) * a.G + mc + j] : 0.0;
+        }
+        for (int idx = threadIdx.x; idx < nk * 64; idx += kWG) {
+          const int kk = idx / 64, j = idx % 64;
+          cs[kk][j] = j < nm ? a.cb[(size_t)(k0 + kk) * a.G + mc + j] : 0.0;
+        }
+        __syncthreads();
+        for (int j = 0; j < nm; j++) {
+          const double y = ys[lane][j];
 #pragma unroll
-        for (int j = 0; j < 16; j++)
-          if (k0 + j <= a.kmax) acc[j] += C[(k0 + j) * a.G + m] * v;
+          for (int q = 0; q < 16; q++)
+            if (w + 4 * q < nk) acc[q] += cs[w + 4 * q][j] * y;
+        }
       }
+      if (lane < nt) {
 #pragma unroll
-      for (int j = 0; j < 16; j++)
-        if (k0 + j <= a.kmax) a.Z[(size_t)(k0 + j) * a.zstride + t] = acc[j];
+        for (int q = 0; q < 16; q++)
+          if (w + 4 * q < nk) a.Z[(size_t)(k0 + w + 4 * q) * a.zstride + t0 + lane] = acc[q];
+      }
     }
   }
 }
@@ -1216,6 +1244,12 @@ int grid_flat(size_t n) {
   size_t g = (n + kWG - 1) / kWG;
   return (int)(g < 4096 ? (g > 0 ? g : 1) : 4096);
 }
+// workgroups of the tile kernels (kTT values of t per tile), grid-stride
+// beyond 2048
+int grid_tiles(size_t n) {
+  const size_t g = (n + kTT - 1) / kTT;
+  return (int)(g < 2048 ? (g > 0 ? g : 1) : 2048);
+}
 dim3 rows_grid(int rows, int Bs) { return dim3(grid_rows(rows, Bs), (Bs + 63) / 64); }
 }  // namespace
 
@@ -1296,10 +1330,10 @@ void launch_cg_iter(const CgArgs &a, hipStream_t s) {
   launch_timed(k_cg_iter, rows_grid(a.ops.ne, a.Bs), s, a);
 }
 void launch_combine(const CombineArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_combine, dim3(grid_flat((size_t)a.nrows * a.BsR)), dim3(kWG), 0, s, a);
+  hipLaunchKernelGGL(k_combine, dim3(grid_tiles((size_t)a.nrows * a.BsR)), dim3(kWG), 0, s, a);
 }
 void launch_reduce_terms(const ReduceTermsArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_terms, dim3(grid_flat((size_t)a.nrows * a.BsZ)), dim3(kWG), 0, s, a);
+  hipLaunchKernelGGL(k_reduce_terms, dim3(grid_tiles((size_t)a.nrows * a.BsZ)), dim3(kWG), 0, s, a);
 }
 void launch_nl_upwind(const NlArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_nl_upwind, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
