@@ -299,8 +299,8 @@ def main():
             cands = {"k_cheb_lp_iter": pa.PA_KERNEL_CHEB_LP_ITER}
         else:
             cands = {"k_cheb_iter": pa.PA_KERNEL_CHEB_ITER}
-            if head["tune"]["pair_steps"]:
-                cands["k_cheb_pair"] = pa.PA_KERNEL_CHEB_PAIR
+            if head["tune"]["fused_steps"] > 1:
+                cands["k_cheb_fused"] = pa.PA_KERNEL_CHEB_FUSED
     else:
         cands = {"k_cg_iter": pa.PA_KERNEL_CG_ITER}
     # the candidate with the most event time is the dominant kernel

@@ -242,7 +242,7 @@ int pa_diagnostics(pa_ctx *ctx, const pa_ops *ops, int B, const double *U_dev,
  * pa_ctx_profile_read returns the tally so far.  The calls made while the
  * hook is on fill it; reading needs no further synchronisation. */
 enum { PA_KERNEL_NONE = 0, PA_KERNEL_CG_ITER = 1, PA_KERNEL_CHEB_ITER = 2,
-       PA_KERNEL_CHEB_LP_ITER = 3, PA_KERNEL_CHEB_PAIR = 4 };
+       PA_KERNEL_CHEB_LP_ITER = 3, PA_KERNEL_CHEB_FUSED = 4 };
 typedef struct {
   int64_t launches;   /* launches of the kernel */
   int64_t work_launches; /* launches that found active columns */
@@ -274,17 +274,18 @@ int pa_ctx_set_cg_budget(pa_ctx *ctx, double cg_rtol, int iters);
  * workspace must fit it), then, with the learned preconditioner or FP32
  * refinement enabled in cfg, over lp_min_cols and mixed_min_cols in {1, 8,
  * 64, never}, and keeps the fastest; it returns the choice and the best
- * time.  pair_steps = 1 runs the Jacobi Chebyshev mass solves of single
- * columns two steps per launch (each workgroup forms the first step again on
- * the halo rows its second step reads), 0 one step per launch; the
- * autotuner tries both. */
+ * time.  fused_steps (1 to 4) is the number of Jacobi Chebyshev steps of a
+ * single-column mass solve per launch (a workgroup owns a part of 256 rows
+ * and forms the earlier steps again on the rings of rows its later steps
+ * read; the results are the same as one step per launch); the autotuner
+ * tries each. */
 typedef struct {
   int32_t narrow_rows_per_thread;
   int32_t wide_max_wg;
   double best_ms;
   int32_t lp_min_cols;
   int32_t mixed_min_cols;
-  int32_t pair_steps;
+  int32_t fused_steps;
 } pa_launch_tune;
 int pa_get_launch_tune(pa_launch_tune *out);
 int pa_set_launch_tune(const pa_launch_tune *t);

@@ -132,7 +132,7 @@ std::vector<unsigned char> batch_key(const pa_batch *b, const double *const *U,
     put(k, t.wide_max_wg);
     put(k, t.lp_min_cols);
     put(k, t.mixed_min_cols);
-    put(k, t.pair_steps);
+    put(k, t.fused_steps);
   }
   return k;
 }
@@ -333,12 +333,12 @@ int pa_batch_set_tune(pa_batch *b, int item, const pa_launch_tune *t) {
     bneed(t->narrow_rows_per_thread >= 1 && t->narrow_rows_per_thread <= 64, "rows per thread in [1, 64]");
     bneed(t->wide_max_wg >= 8 && t->wide_max_wg <= 2048, "wide_max_wg in [8, 2048]");
     bneed(t->lp_min_cols >= 1 && t->mixed_min_cols >= 1, "lp_min_cols, mixed_min_cols >= 1");
-    bneed(t->pair_steps == 0 || t->pair_steps == 1, "pair_steps is 0 or 1");
+    bneed(t->fused_steps >= 1 && t->fused_steps <= 4, "fused_steps in [1, 4]");
     b->tune[item].narrow_rows_per_thread = t->narrow_rows_per_thread;
     b->tune[item].wide_max_wg = t->wide_max_wg;
     b->tune[item].lp_min_cols = t->lp_min_cols;
     b->tune[item].mixed_min_cols = t->mixed_min_cols;
-    b->tune[item].pair_steps = t->pair_steps;
+    b->tune[item].fused_steps = t->fused_steps;
     b->tuned[item] = true;
   });
 }
@@ -351,7 +351,7 @@ int pa_batch_get_tune(const pa_batch *b, int item, pa_launch_tune *out) {
     out->wide_max_wg = t.wide_max_wg;
     out->lp_min_cols = t.lp_min_cols;
     out->mixed_min_cols = t.mixed_min_cols;
-    out->pair_steps = t.pair_steps;
+    out->fused_steps = t.fused_steps;
     out->best_ms = 0.0;
   });
 }
@@ -418,9 +418,9 @@ int pa_batch_autotune(pa_ctx *ctx, pa_batch *b, const double *const *U_dev,
         }
       }
       if (c.solver == PA_SOLVER_CHEBYSHEV)
-        for (int ps : {0, 1}) {
+        for (int ps : {1, 2, 3, 4}) {
           pa::LaunchTune t = best_t;
-          t.pair_steps = ps;
+          t.fused_steps = ps;
           trial(t);
         }
       b->tune[i] = best_t;
@@ -430,7 +430,7 @@ int pa_batch_autotune(pa_ctx *ctx, pa_batch *b, const double *const *U_dev,
         out[i].wide_max_wg = best_t.wide_max_wg;
         out[i].lp_min_cols = best_t.lp_min_cols;
         out[i].mixed_min_cols = best_t.mixed_min_cols;
-        out[i].pair_steps = best_t.pair_steps;
+        out[i].fused_steps = best_t.fused_steps;
         out[i].best_ms = best;
       }
     }

@@ -58,7 +58,7 @@ int pa_ctx_set_stream(pa_ctx *ctx, void *stream) {
 int pa_ctx_profile(pa_ctx *ctx, int kernel) {
   return guard([&] {
     need(ctx != nullptr, "ctx is NULL");
-    need(kernel >= PA_KERNEL_NONE && kernel <= PA_KERNEL_CHEB_PAIR, "unknown kernel id");
+    need(kernel >= PA_KERNEL_NONE && kernel <= PA_KERNEL_CHEB_FUSED, "unknown kernel id");
     ctx->prof_kernel = kernel;
     ctx->prof_launches = ctx->prof_work = 0;
     ctx->prof_ms = ctx->prof_bytes = 0.0;
@@ -171,11 +171,13 @@ size_t layout(pa_ops *o, char *base) {
   place(off, o->inv_area, &d.inv_area, base);
   place(off, o->bottom, &d.bottom, base);
   place(off, o->cgeo, &d.cgeo, base);
-  place(off, o->halo_off, &d.halo_off, base);
-  place(off, o->halo_row, &d.halo_row, base);
+  place(off, o->ring_cnt, &d.ring_cnt, base);
+  place(off, o->ring_row, &d.ring_row, base);
   place(off, o->hloc, &d.hloc, base);
+  place(off, o->ring_loc, &d.ring_loc, base);
   if (base) {
     d.hparts = o->hparts;
+    d.fused_max = o->fused_max;
     d.ne = o->ne;
     d.nc = o->nc;
     d.g = o->g;
@@ -245,9 +247,10 @@ int pa_ops_bind(pa_ctx *ctx, pa_ops *ops, void *dev_buf) {
     up(s, d.inv_area, ops->inv_area);
     up(s, d.bottom, ops->bottom);
     up(s, d.cgeo, ops->cgeo);
-    up(s, d.halo_off, ops->halo_off);
-    up(s, d.halo_row, ops->halo_row);
+    up(s, d.ring_cnt, ops->ring_cnt);
+    up(s, d.ring_row, ops->ring_row);
     up(s, d.hloc, ops->hloc);
+    up(s, d.ring_loc, ops->ring_loc);
     PA_HIP(hipStreamSynchronize(s));
   });
 }
@@ -533,7 +536,7 @@ int pa_get_launch_tune(pa_launch_tune *out) {
     out->wide_max_wg = t.wide_max_wg;
     out->lp_min_cols = t.lp_min_cols;
     out->mixed_min_cols = t.mixed_min_cols;
-    out->pair_steps = t.pair_steps;
+    out->fused_steps = t.fused_steps;
     out->best_ms = 0.0;
   });
 }
@@ -544,13 +547,13 @@ int pa_set_launch_tune(const pa_launch_tune *t) {
     need(t->narrow_rows_per_thread >= 1 && t->narrow_rows_per_thread <= 64, "rows per thread in [1, 64]");
     need(t->wide_max_wg >= 8 && t->wide_max_wg <= 2048, "wide_max_wg in [8, 2048]");
     need(t->lp_min_cols >= 1 && t->mixed_min_cols >= 1, "lp_min_cols, mixed_min_cols >= 1");
-    need(t->pair_steps == 0 || t->pair_steps == 1, "pair_steps is 0 or 1");
+    need(t->fused_steps >= 1 && t->fused_steps <= 4, "fused_steps in [1, 4]");
     pa::LaunchTune lt;
     lt.narrow_rows_per_thread = t->narrow_rows_per_thread;
     lt.wide_max_wg = t->wide_max_wg;
     lt.lp_min_cols = t->lp_min_cols;
     lt.mixed_min_cols = t->mixed_min_cols;
-    lt.pair_steps = t->pair_steps;
+    lt.fused_steps = t->fused_steps;
     pa::set_launch_tuning(lt);
   });
 }
@@ -608,7 +611,7 @@ int pa_autotune(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int members, 
       };
       if (c.precond == PA_PRECOND_LEARNED) search(&pa::LaunchTune::lp_min_cols, {1, 8, 64, kLpNever});
       if (c.precision == PA_FP32_REFINED) search(&pa::LaunchTune::mixed_min_cols, {1, 8, 64, kLpNever});
-      if (c.solver == PA_SOLVER_CHEBYSHEV) search(&pa::LaunchTune::pair_steps, {0, 1});
+      if (c.solver == PA_SOLVER_CHEBYSHEV) search(&pa::LaunchTune::fused_steps, {1, 2, 3, 4});
     } catch (...) {
       pa::set_launch_tuning(keep);
       throw;
@@ -618,7 +621,7 @@ int pa_autotune(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int members, 
     out->wide_max_wg = best_t.wide_max_wg;
     out->lp_min_cols = best_t.lp_min_cols;
     out->mixed_min_cols = best_t.mixed_min_cols;
-    out->pair_steps = best_t.pair_steps;
+    out->fused_steps = best_t.fused_steps;
     out->best_ms = best;
   });
 }

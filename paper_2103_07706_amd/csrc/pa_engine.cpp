@@ -225,74 +225,74 @@ void Engine::mass_solve(double *x, int Bs, const int *colK, int kneed, int nwg_i
 // autotuner measures.
 bool Engine::lp_cheaper(int Bs) const { return lp_avail_ && Bs >= launch_tuning().lp_min_cols; }
 
-// Jacobi semi-iteration of a single column, two steps per launch
-// (k_cheb_pair) after one single step when the step count is odd.  r and d
-// move between two buffers each from one pair to the next.
-void Engine::cheb_pairs(double *x, const int *colK, int kneed, int nwg_init, int grid) {
+// Jacobi semi-iteration of a single column, S steps per launch
+// (k_cheb_fused): the remainder of the step count first, then launches of S
+// steps.  r and d move between two buffers each from one launch to the next.
+void Engine::cheb_fused(double *x, const int *colK, int kneed, int nwg_init, int grid, int S) {
   const std::vector<double> &c1 = cheb_c1_, &c2 = cheb_c2_;
   const int k = (int)c1.size();
   double *d[2] = {p_, s0_};
   double *r[2] = {r_, r1_};
-  int i = 0, di = 0, ri = 0;
-  if (k % 2) {
-    ChebArgs a{};
-    a.ops = ops_->d;
-    a.Bs = 1;
-    a.x = x;
-    a.r = r_;
-    a.colK = colK;
-    a.kneed = kneed;
-    a.part = chk_last_[chk_par_];
-    a.max_wg = rb_.max_wg;
-    a.d_in = d[0];
-    a.d_out = d[1];
-    a.c1 = c1[0];
-    a.c2 = c2[0];
-    a.last = k == 1 ? 1 : 0;
-    const bool prof = ctx_->prof_kernel == PA_KERNEL_CHEB_ITER;
-    a.prof = prof ? st_.prof : nullptr;
-    if (prof) bracket_begin();
-    launch_cheb_iter(a, s_);
-    if (prof) bracket_end(1);
-    i = 1;
-    di = 1;
-  }
-  ChebPairArgs a{};
+  ChebFusedArgs a{};
   a.ops = ops_->d;
   a.x = x;
   a.colK = colK;
   a.kneed = kneed;
   a.part = chk_last_[chk_par_];
-  const bool prof = ctx_->prof_kernel == PA_KERNEL_CHEB_PAIR;
+  const bool prof = ctx_->prof_kernel == PA_KERNEL_CHEB_FUSED;
   a.prof = prof ? st_.prof : nullptr;
-  const int pairs = (k - i) / 2;
-  if (prof && pairs > 0) bracket_begin();
-  for (; i < k; i += 2) {
-    a.d_in = d[di];
-    a.d_out = d[di ^ 1];
-    a.r_in = r[ri];
-    a.r_out = r[ri ^ 1];
-    a.c1a = c1[i];
-    a.c2a = c2[i];
-    a.c1b = c1[i + 1];
-    a.c2b = c2[i + 1];
-    a.last = i + 2 == k ? 1 : 0;
-    launch_cheb_pair(a, s_);
-    di ^= 1;
-    ri ^= 1;
+  a.prof_bytes = st_.prof_bytes;
+  int launches = 0, i = 0, buf = 0;
+  if (prof) bracket_begin();
+  while (i < k) {
+    const int n = i == 0 && k % S ? k % S : S;
+    a.S = n;
+    for (int s = 0; s < n; s++) {
+      a.c1[s] = c1[i + s];
+      a.c2[s] = c2[i + s];
+    }
+    a.d_in = d[buf];
+    a.d_out = d[buf ^ 1];
+    a.r_in = r[buf];
+    a.r_out = r[buf ^ 1];
+    a.last = i + n == k ? 1 : 0;
+    a.bytes = prof ? fused_bytes(n, a.last) : 0;
+    launch_cheb_fused(a, s_);
+    buf ^= 1;
+    i += n;
+    launches++;
   }
-  if (prof && pairs > 0) bracket_end(pairs);
-  defer_check(1, nwg_init, colK, kneed, pairs > 0 ? grid : -1);
+  if (prof) bracket_end(launches);
+  defer_check(1, nwg_init, colK, kneed, grid);
   stats.solves++;
   stats.cg_iters += k;
   stats.cg_iters_max = std::max(stats.cg_iters_max, k);
 }
 
+// Algorithmic bytes of one k_cheb_fused launch of n steps: per row the ELL
+// row (5 columns, 5 values), the Jacobi diagonal, x in and out, r and d in,
+// r out, d out unless the launch ends the solve, and with n > 1 the row's
+// part-local columns (2 bytes each); per part its ring lists for rings
+// 1..n-1 (4 bytes a row) and the local columns of rings 1..n-2.  Ring rows'
+// own data are other parts' rows, counted once.
+unsigned long long Engine::fused_bytes(int n, int last) const {
+  double b = (double)ne_ * (108.0 + (last ? 0.0 : 8.0) + (n > 1 ? 10.0 : 0.0));
+  const pa_ops *o = ops_;
+  for (int p = 0; p < o->hparts; p++) {
+    const int32_t *c = &o->ring_cnt[(size_t)p * 4];
+    b += 16.0;
+    if (n >= 2) b += 4.0 * c[n - 2];
+    if (n >= 3) b += 10.0 * c[n - 3];
+  }
+  return (unsigned long long)b;
+}
+
 void Engine::cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_init) {
   const bool lp = lp_cheaper(Bs);
-  if (!lp && Bs == 1 && launch_tuning().pair_steps) {
-    const int grid = cheb_pair_grid(ops_->d);
-    if (grid > 0) return cheb_pairs(x, colK, kneed, nwg_init, grid);
+  const int S = std::min(launch_tuning().fused_steps, ops_->fused_max);
+  if (!lp && Bs == 1 && S > 1) {
+    const int grid = cheb_fused_grid(ops_->d);
+    if (grid > 0) return cheb_fused(x, colK, kneed, nwg_init, grid, S);
   }
   const std::vector<double> &c1 = lp ? lp_c1_ : cheb_c1_, &c2 = lp ? lp_c2_ : cheb_c2_;
   const int k = (int)c1.size();
@@ -457,6 +457,7 @@ void Engine::plan_common(int BsMax) {
     st_.budget_fail = (int *)(z + 7);
     st_.cheb_fail = (int *)(z + 8);
     st_.resid_max = (unsigned long long *)(z + 10);  // 8-byte aligned
+    st_.prof_bytes = (unsigned long long *)(z + 12);
   }
 }
 
@@ -489,8 +490,8 @@ void Engine::finish() {
   PA_HIP(hipEventRecord(ev1_, s_));
   // counters z+2 .. z+11: fail, iter_max, prof[3], budget_fail, cheb_fail,
   // (pad), resid_max bits
-  int h[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
-  PA_HIP(hipMemcpyAsync(h, st_.fail, 10 * sizeof(int), hipMemcpyDeviceToHost, s_));
+  int h[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  PA_HIP(hipMemcpyAsync(h, st_.fail, 12 * sizeof(int), hipMemcpyDeviceToHost, s_));
   PA_HIP(hipStreamSynchronize(s_));
   {
     unsigned long long bits;
@@ -529,14 +530,12 @@ void Engine::finish() {
                                                (68.0 + 8.0 * ops_->lp_wp) * work)
                               : (double)ne_ * (48.0 * cols + 40.0 * (unsigned)h[4] +
                                                (60.0 + 8.0 * (ops_->lp_wp + ops_->lp_wpm)) * work);
-    // two steps on one column, per row: the ELL row, its part-local
-    // columns (2 bytes each) and the Jacobi diagonal; x in and out, r and d
-    // in, r' out, and d' out except on the solve's last pair; per launch the
-    // part's halo list
-    if (ctx_->prof_kernel == PA_KERNEL_CHEB_PAIR) {
-      const double halo = 4.0 * (ops_->halo_row.size() + ops_->halo_off.size());
-      ctx_->prof_bytes += (double)ne_ * (126.0 * cols + 118.0 * (unsigned)h[4]) +
-                          halo * (cols + (unsigned)h[4]);
+    // fused steps: summed by the kernel from the launches' own figures
+    // (fused_bytes)
+    if (ctx_->prof_kernel == PA_KERNEL_CHEB_FUSED) {
+      unsigned long long fb;
+      std::memcpy(&fb, &h[10], sizeof(fb));
+      ctx_->prof_bytes += (double)fb;
     }
     ctx_->prof_work += (int64_t)work;
   }

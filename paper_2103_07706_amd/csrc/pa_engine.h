@@ -109,7 +109,8 @@ class Engine {
   bool pend_ = false;
   CheckArgs pend_args_{};
   void defer_check(int Bs, int nwg_init, const int *colK, int kneed, int nwg_last = -1);
-  void cheb_pairs(double *x, const int *colK, int kneed, int nwg_init, int grid);
+  void cheb_fused(double *x, const int *colK, int kneed, int nwg_init, int grid, int S);
+  unsigned long long fused_bytes(int n, int last) const;
   void take_check(CheckArgs &chk, int &blocks, int grid_blocks);
   void flush_check();
   bool cheb() const { return cfg_.solver == PA_SOLVER_CHEBYSHEV; }

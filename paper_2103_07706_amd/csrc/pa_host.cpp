@@ -18,6 +18,7 @@
 #include <unordered_map>
 
 #include "pa_internal.h"
+#include "pa_kernels.h"
 
 namespace pa {
 namespace {
@@ -274,38 +275,78 @@ void assemble_ops(pa_ops *o, const Mesh &m, const pa_phys &ph) {
   mass_spectrum(o, 200, &o->mass_eig_min, &o->mass_eig_max);
 }
 
-// Row parts of the edge mass matrix for the two-step solve kernel: halo of
-// each part (ELL columns outside it, ascending) and every ELL column of
-// every row as an index into its part's local numbering.
+// Row parts of the edge mass matrix for the fused-step solve kernel: rings
+// 1..kFusedMax-1 of each part (ELL columns of the previous ring, or of the
+// part, outside the part and the earlier rings; ascending within a ring) and
+// every ELL column of the part's rows and of its rings 1..kFusedMax-2 as an
+// index into the part's local numbering (part rows, then the rings in order).
+// A mesh whose rings do not fit kHaloMax rows keeps fewer rings.
 void build_row_parts(pa_ops *o) {
   const int ne = o->ne, P = (ne + kPartRows - 1) / kPartRows;
-  o->halo_off.assign(P + 1, 0);
-  o->halo_row.clear();
-  o->hloc.assign((size_t)5 * ne, 0);
-  bool ok = true;
-  std::vector<int32_t> h;
+  std::vector<std::vector<int32_t>> rings((size_t)P * (kFusedMax - 1));
+  int fmax = kFusedMax;
+  std::vector<uint8_t> mark(ne, 0);
   for (int p = 0; p < P; p++) {
     const int e0 = p * kPartRows, e1 = std::min(ne, e0 + kPartRows);
-    h.clear();
-    for (int e = e0; e < e1; e++)
-      for (int j = 0; j < 5; j++) {
-        const int c = o->ell_col[5 * e + j];
-        if (c < e0 || c >= e1) h.push_back(c);
-      }
-    std::sort(h.begin(), h.end());
-    h.erase(std::unique(h.begin(), h.end()), h.end());
-    if ((int)h.size() > kHaloMax) ok = false;
-    for (int e = e0; e < e1; e++)
-      for (int j = 0; j < 5; j++) {
-        const int c = o->ell_col[5 * e + j];
-        int loc = c - e0;
-        if (c < e0 || c >= e1) loc = kPartRows + (int)(std::lower_bound(h.begin(), h.end(), c) - h.begin());
-        o->hloc[(size_t)j * ne + e] = (uint16_t)std::min(loc, 65535);
-      }
-    o->halo_row.insert(o->halo_row.end(), h.begin(), h.end());
-    o->halo_off[p + 1] = (int32_t)o->halo_row.size();
+    std::vector<int32_t> front;
+    for (int e = e0; e < e1; e++) {
+      mark[e] = 1;
+      front.push_back(e);
+    }
+    int total = 0;
+    std::vector<int32_t> touched(front);
+    for (int r = 0; r < kFusedMax - 1; r++) {
+      std::vector<int32_t> &ring = rings[(size_t)p * (kFusedMax - 1) + r];
+      for (int e : front)
+        for (int j = 0; j < 5; j++) {
+          const int c = o->ell_col[5 * e + j];
+          if (!mark[c]) {
+            mark[c] = 1;
+            ring.push_back(c);
+          }
+        }
+      std::sort(ring.begin(), ring.end());
+      touched.insert(touched.end(), ring.begin(), ring.end());
+      total += (int)ring.size();
+      if (total > kHaloMax) fmax = std::min(fmax, r + 1);
+      front = ring;
+    }
+    for (int e : touched) mark[e] = 0;
   }
-  o->hparts = ok ? P : 0;
+  // one workgroup per part, and per-workgroup partials for the residual check
+  if ((P + 7) / 8 * 8 > launch_max_wg()) fmax = 1;
+  o->fused_max = fmax;
+  o->hparts = fmax >= 2 ? P : 0;
+  o->ring_cnt.assign((size_t)P * 4, 0);
+  o->ring_row.assign((size_t)P * kHaloMax, 0);
+  o->ring_loc.assign((size_t)P * kHaloMax * 5, 0);
+  o->hloc.assign((size_t)5 * ne, 0);
+  if (!o->hparts) return;
+  std::unordered_map<int32_t, int> loc;
+  for (int p = 0; p < P; p++) {
+    const int e0 = p * kPartRows, e1 = std::min(ne, e0 + kPartRows);
+    loc.clear();
+    for (int e = e0; e < e1; e++) loc[e] = e - e0;
+    int n = 0;
+    for (int r = 0; r < fmax - 1; r++) {
+      for (int c : rings[(size_t)p * (kFusedMax - 1) + r]) {
+        o->ring_row[(size_t)p * kHaloMax + n] = c;
+        loc[c] = kPartRows + n;
+        n++;
+      }
+      o->ring_cnt[(size_t)p * 4 + r] = n;
+    }
+    for (int r = fmax - 1; r < 3; r++) o->ring_cnt[(size_t)p * 4 + r] = n;
+    for (int e = e0; e < e1; e++)
+      for (int j = 0; j < 5; j++) o->hloc[(size_t)j * ne + e] = (uint16_t)loc.at(o->ell_col[5 * e + j]);
+    // rings whose rows take later steps: all but the outermost kept ring
+    const int inner = fmax >= 3 ? o->ring_cnt[(size_t)p * 4 + fmax - 3] : 0;
+    for (int h = 0; h < inner; h++) {
+      const int g = o->ring_row[(size_t)p * kHaloMax + h];
+      for (int j = 0; j < 5; j++)
+        o->ring_loc[((size_t)p * kHaloMax + h) * 5 + j] = (uint16_t)loc.at(o->ell_col[5 * g + j]);
+    }
+  }
 }
 
 namespace {

@@ -80,12 +80,15 @@ Mesh build_icosahedral(int level, double radius);
 constexpr int kCellGeo = 32;
 // Per-edge tangential-trace table: tau[side][gauss][j] (2*2*3).
 constexpr int kEdgeTau = 12;
-// Row parts of the two-step mass-solve kernel: part p holds the kPartRows
-// edges [p kPartRows, (p + 1) kPartRows); its halo is the other edges its
-// rows' ELL columns reach, at most kHaloMax per part (else the kernel is not
-// used on that mesh).
+// Row parts of the fused-step mass-solve kernel: part p holds the kPartRows
+// edges [p kPartRows, (p + 1) kPartRows).  Ring 1 of a part is the set of
+// other edges its rows' ELL columns reach, ring r + 1 the edges ring r's
+// columns reach outside the part and rings 1..r.  kFusedMax - 1 rings are
+// kept, at most kHaloMax rows in all per part (fewer rings on a mesh where
+// they do not fit).
 constexpr int kPartRows = 256;
-constexpr int kHaloMax = 256;
+constexpr int kHaloMax = 512;
+constexpr int kFusedMax = 4;
 
 // Device-resident operator arrays (pointers into the caller's buffer).
 struct DevOps {
@@ -108,12 +111,15 @@ struct DevOps {
   const double *inv_area = nullptr;   // nc
   const double *bottom = nullptr;     // nc
   const double *cgeo = nullptr;       // nc*kCellGeo
-  // row parts (see kPartRows): hparts parts, 0 if a halo exceeds kHaloMax
-  int hparts = 0;
-  const int32_t *halo_off = nullptr;  // hparts+1: part p's halo rows are halo_row[halo_off[p]..)
-  const int32_t *halo_row = nullptr;  // ascending within a part
+  // row parts (see kPartRows): hparts parts, rings 1..fused_max-1 kept
+  int hparts = 0, fused_max = 1;
+  const int32_t *ring_cnt = nullptr;  // hparts*4: rows of rings 1..r of part p, r = 1..3
+  const int32_t *ring_row = nullptr;  // hparts*kHaloMax: part p's ring rows from p*kHaloMax,
+                                      // ring by ring, ascending within a ring
   const uint16_t *hloc = nullptr;     // 5*ne, [slot][row]: ELL column as a part-local index
-                                      // (row offset in the part, or kPartRows + halo position)
+                                      // (row offset in the part, or kPartRows + ring position)
+  const uint16_t *ring_loc = nullptr; // hparts*kHaloMax*5: the same for the ring rows
+                                      // (rings 1..fused_max-2; others 0)
 };
 
 // Learned preconditioner on the device: P = G G^T and P M as column-major
@@ -131,11 +137,11 @@ struct LaunchTune {
   int wide_max_wg = 2048;          // workgroups per column tile, wider batches
   int lp_min_cols = 8;             // learned mass-solve steps on blocks this wide or wider
   int mixed_min_cols = 8;          // FP32-refined mass solves on blocks this wide or wider
-  int pair_steps = 1;              // single-column Jacobi Chebyshev solves: two steps per launch
+  int fused_steps = 3;             // single-column Jacobi Chebyshev solves: steps per launch (1-4)
   bool operator==(const LaunchTune &o) const {
     return narrow_rows_per_thread == o.narrow_rows_per_thread && wide_max_wg == o.wide_max_wg &&
            lp_min_cols == o.lp_min_cols && mixed_min_cols == o.mixed_min_cols &&
-           pair_steps == o.pair_steps;
+           fused_steps == o.fused_steps;
   }
 };
 
@@ -197,9 +203,9 @@ struct pa_ops {
   std::vector<int32_t> ell_col, ecell, cidx, side_edges, cedge, csgn, cnbr;
   std::vector<double> mass, cor, dinv, area, inv_area, bottom, cgeo, tau;
   std::vector<float> mass32, dinv32;
-  int hparts = 0;
-  std::vector<int32_t> halo_off, halo_row;
-  std::vector<uint16_t> hloc;
+  int hparts = 0, fused_max = 1;
+  std::vector<int32_t> ring_cnt, ring_row;
+  std::vector<uint16_t> hloc, ring_loc;
   size_t dev_bytes = 0;
   void *dev = nullptr;
   pa::DevOps d;

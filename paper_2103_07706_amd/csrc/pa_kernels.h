@@ -31,6 +31,7 @@ struct SolveState {
   unsigned *prof;         // [3]: active columns summed over launches, work launches,
                           //      columns of last Chebyshev steps
   unsigned *prof_last;    // = prof + 2
+  unsigned long long *prof_bytes;  // 1: algorithmic bytes of the profiled launches
 };
 
 // Residual check after a Chebyshev solve (a kernel of its own, or folded
@@ -107,19 +108,22 @@ struct ChebArgs {
   int nodir;       // 1: update x and r only (the direction comes from another kernel)
 };
 
-// Two Jacobi Chebyshev steps of a single-column solve in one launch (see
-// k_cheb_pair): steps with (c1a, c2a) then (c1b, c2b); r and d each move
-// from an input to an output buffer (other workgroups still read the inputs).
-struct ChebPairArgs {
+// S Jacobi Chebyshev steps of a single-column solve in one launch (see
+// k_cheb_fused), step s with (c1[s], c2[s]); r and d each move from an input
+// to an output buffer (other workgroups still read the inputs).
+struct ChebFusedArgs {
   DevOps ops;
+  int S;            // 1 <= S <= ops.fused_max
   double *x;
   const double *r_in, *d_in;
   double *r_out, *d_out;
-  double c1a, c2a, c1b, c2b;
+  double c1[kFusedMax], c2[kFusedMax];
   const int *colK;
-  int kneed, last;  // last: the second step is the solve's last (partials of r.r, no direction)
+  int kneed, last;  // last: step S is the solve's last (partials of r.r, no direction)
   double *part;
   unsigned *prof;   // measurement hook, as ChebArgs
+  unsigned long long *prof_bytes;  // algorithmic bytes of the launch added here
+  unsigned long long bytes;
 };
 
 // Chebyshev step with the learned preconditioner P (see k_cheb_lp_iter):
@@ -274,8 +278,8 @@ void launch_finalize(const FinArgs &a, hipStream_t s);
 void launch_stiff(const StiffArgs &a, hipStream_t s);
 void launch_cg_init(const CgArgs &a, hipStream_t s);
 void launch_cheb_iter(const ChebArgs &a, hipStream_t s);
-void launch_cheb_pair(const ChebPairArgs &a, hipStream_t s);
-int cheb_pair_grid(const DevOps &o);  // workgroups of k_cheb_pair (0: not available)
+void launch_cheb_fused(const ChebFusedArgs &a, hipStream_t s);
+int cheb_fused_grid(const DevOps &o);  // workgroups of k_cheb_fused (0: not available)
 void launch_cheb_check(const CheckArgs &a, hipStream_t s);
 int cheb_check_blocks(const CheckArgs &a);  // workgroups of a residual check
 void launch_cheb_lp_iter(const ChebLpArgs &a, hipStream_t s);

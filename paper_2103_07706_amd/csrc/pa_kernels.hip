@@ -241,7 +241,9 @@ __global__ __launch_bounds__(kWG) void k_stiff(StiffArgs a) {
 // kernel per step, gathering only d.
 // Direction update of the Jacobi Chebyshev step.
 __device__ inline double cheb_dir(double c1, double c2, double d, double dinv, double r) {
-  return c1 * d + c2 * dinv * r;
+  // one fixed rounding order at every call site (no contraction left to the
+  // compiler), so that a row's direction is the same bits in every kernel
+  return fma(c1, d, (c2 * dinv) * r);
 }
 
 __global__ __launch_bounds__(kWG) void k_cheb_iter(ChebArgs a) {
@@ -259,7 +261,7 @@ __global__ __launch_bounds__(kWG) void k_cheb_iter(ChebArgs a) {
     for (int e = L.row0; e < L.rend; e += L.rstride) {
       double q = 0.0;
 #pragma unroll
-      for (int j = 0; j < 5; j++) q += o.mass[5 * e + j] * a.d_in[(size_t)o.ell_col[5 * e + j] * Bs + c];
+      for (int j = 0; j < 5; j++) q = fma(o.mass[5 * e + j], a.d_in[(size_t)o.ell_col[5 * e + j] * Bs + c], q);
       const size_t ie = (size_t)e * Bs + c;
       const double d = a.d_in[ie];
       a.x[ie] += d;
@@ -274,83 +276,116 @@ __global__ __launch_bounds__(kWG) void k_cheb_iter(ChebArgs a) {
   if (a.last) wg_partials<1>(L, sums, a.part, a.max_wg);
 }
 
-// Two steps of the single-column Jacobi semi-iteration in one launch.  A
-// step costs little beyond its launch and the latency of its dependent
-// gather, so pairs of steps halve both.  Workgroup p owns the kPartRows rows
-// of part p.  First step: every row of the part and of its halo (the rows its
-// ELL columns reach outside the part) forms
-//   r' = r - M d,  d' = c1a d + c2a D^-1 r'
-// from the previous launch's r and d, with d' kept in LDS (the halo rows'
-// values are formed again by the workgroup that owns them, in the same
-// order, hence bit for bit the same).  Second step, on the part's rows only,
-// gathers d' from LDS:
-//   x += d + d',  r'' = r' - M d',  d'' = c1b d' + c2b D^-1 r''.
-// Halo rows are read from r and d, which other workgroups do not write in
-// this launch: r'' and d'' go to separate output buffers.  Parts are laid
-// over the XCDs like lane_map's slices (XCD k takes parts k per .. k per + per
-// - 1), so neighbouring parts and their halos share an L2.
-__global__ __launch_bounds__(kWG) void k_cheb_pair(ChebPairArgs a) {
+// S steps of the single-column Jacobi semi-iteration in one launch.  A step
+// costs little beyond its launch and the latency of its dependent gather, so
+// fusing steps divides both.  Workgroup p owns the kPartRows rows of part p.
+// Step 1 runs on the part and its rings 1..S-1 from the previous launch's r
+// and d (gathered from global memory):
+//   r' = r - M d,  d' = c1 d + c2 D^-1 r',
+// step s > 1 on the part and rings 1..S-s, gathering the previous step's d
+// from LDS; x += d of each step on the part's rows.  A ring row's values are
+// formed again by the workgroup that owns that row, in the same order, hence
+// bit for bit the same as one step per launch.  Ring rows read r and d of the
+// previous launch, which no workgroup writes in this one: the part's new r
+// and d go to separate output buffers.  Parts are laid over the XCDs like
+// lane_map's slices (XCD k takes parts k per .. k per + per - 1), so
+// neighbouring parts and their rings share an L2.
+__global__ __launch_bounds__(kWG) void k_cheb_fused(ChebFusedArgs a) {
   const DevOps &o = a.ops;
   const int t = threadIdx.x;
   if (a.prof && blockIdx.x == 0 && t == 0) {
-    atomicAdd(&a.prof[a.last ? 2 : 0], a.colK[0] >= a.kneed ? 1u : 0u);
+    const bool on = a.colK[0] >= a.kneed;
+    atomicAdd(&a.prof[a.last ? 2 : 0], on ? 1u : 0u);
     atomicAdd(&a.prof[1], 1u);
+    if (on) atomicAdd(a.prof_bytes, a.bytes);
   }
   if (a.colK[0] < a.kneed) return;  // inactive column: its partials are not read
   const int per = gridDim.x >> 3;
   const int p = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  __shared__ double dA[kPartRows + kHaloMax];
+  const int S = a.S;
+  __shared__ double dl[2][kPartRows + kHaloMax];
+  __shared__ double rl[kHaloMax];
   __shared__ double red[kWG / 64];
-  double s = 0.0;
+  double s2 = 0.0;
   if (p < o.hparts) {
     const int e0 = p * kPartRows;
     const int nrow = min(kPartRows, o.ne - e0);
-    const int h0 = o.halo_off[p], nh = o.halo_off[p + 1] - h0;
-    double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, x1 = 0.0, r1 = 0.0;
-    if (t < nrow) {
-      const int e = e0 + t;
+    const int *cnt = o.ring_cnt + 4 * p;
+    const int32_t *rrow = o.ring_row + (size_t)p * kHaloMax;
+    const uint16_t *rloc = o.ring_loc + (size_t)p * kHaloMax * 5;
+    // the part's own row: matrix row, local columns and state kept in registers
+    const int e = e0 + t;
+    const bool own = t < nrow;
+    double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, x = 0.0, r = 0.0, dv = 0.0, dinv = 0.0;
+    int lc[5] = {0, 0, 0, 0, 0};
+    if (own) {
       int col[5];
 #pragma unroll
       for (int j = 0; j < 5; j++) {
         col[j] = o.ell_col[5 * e + j];
         m[j] = o.mass[5 * e + j];
+        if (S > 1) lc[j] = o.hloc[(size_t)j * o.ne + e];
       }
       double q = 0.0;
 #pragma unroll
-      for (int j = 0; j < 5; j++) q += m[j] * a.d_in[col[j]];
-      const double d = a.d_in[e];
-      x1 = a.x[e] + d;
-      r1 = a.r_in[e] - q;
-      dA[t] = cheb_dir(a.c1a, a.c2a, d, o.dinv[e], r1);
+      for (int j = 0; j < 5; j++) q = fma(m[j], a.d_in[col[j]], q);
+      dv = a.d_in[e];
+      dinv = o.dinv[e];
+      x = a.x[e] + dv;
+      r = a.r_in[e] - q;
+      if (S > 1) dl[0][t] = cheb_dir(a.c1[0], a.c2[0], dv, dinv, r);
     }
-    if (t < nh) {
-      const int g = o.halo_row[h0 + t];
+    // step 1 on rings 1..S-1
+    const int n1 = S > 1 ? cnt[S - 2] : 0;
+    for (int h = t; h < n1; h += kWG) {
+      const int g = rrow[h];
       double q = 0.0;
 #pragma unroll
-      for (int j = 0; j < 5; j++) q += o.mass[5 * g + j] * a.d_in[o.ell_col[5 * g + j]];
-      dA[kPartRows + t] = cheb_dir(a.c1a, a.c2a, a.d_in[g], o.dinv[g], a.r_in[g] - q);
+      for (int j = 0; j < 5; j++) q = fma(o.mass[5 * g + j], a.d_in[o.ell_col[5 * g + j]], q);
+      const double rg = a.r_in[g] - q;
+      rl[h] = rg;
+      dl[0][kPartRows + h] = cheb_dir(a.c1[0], a.c2[0], a.d_in[g], o.dinv[g], rg);
     }
-    __syncthreads();
-    if (t < nrow) {
-      const int e = e0 + t;
-      double q = 0.0;
+    for (int st = 1; st < S; st++) {
+      __syncthreads();
+      const double *dp = dl[(st - 1) & 1];
+      double *dn = dl[st & 1];
+      const double c1 = a.c1[st], c2 = a.c2[st];
+      if (own) {
+        double q = 0.0;
 #pragma unroll
-      for (int j = 0; j < 5; j++) q += m[j] * dA[o.hloc[(size_t)j * o.ne + e]];
-      const double d = dA[t];
-      const double r2 = r1 - q;
-      a.x[e] = x1 + d;
-      a.r_out[e] = r2;
+        for (int j = 0; j < 5; j++) q = fma(m[j], dp[lc[j]], q);
+        dv = dp[t];
+        x += dv;
+        r -= q;
+        if (st + 1 < S) dn[t] = cheb_dir(c1, c2, dv, dinv, r);
+      }
+      // rings 1..S-1-st take this step too
+      const int nh = st + 1 < S ? cnt[S - 2 - st] : 0;
+      for (int h = t; h < nh; h += kWG) {
+        const int g = rrow[h];
+        double q = 0.0;
+#pragma unroll
+        for (int j = 0; j < 5; j++) q = fma(o.mass[5 * g + j], dp[rloc[5 * h + j]], q);
+        const double rg = rl[h] - q;
+        rl[h] = rg;
+        dn[kPartRows + h] = cheb_dir(c1, c2, dp[kPartRows + h], o.dinv[g], rg);
+      }
+    }
+    if (own) {
+      a.x[e] = x;
+      a.r_out[e] = r;
       if (a.last)
-        s = r2 * r2;
+        s2 = r * r;
       else
-        a.d_out[e] = cheb_dir(a.c1b, a.c2b, d, o.dinv[e], r2);
+        a.d_out[e] = cheb_dir(a.c1[S - 1], a.c2[S - 1], dv, dinv, r);
     }
   }
   if (a.last) {
     // partial of r.r per workgroup, at the place of tile 0, column 0 of
     // wg_partials' layout
-    s = wave_col_sum(s, 1);
-    if ((t & 63) == 0) red[t >> 6] = s;
+    s2 = wave_col_sum(s2, 1);
+    if ((t & 63) == 0) red[t >> 6] = s2;
     __syncthreads();
     if (t == 0) {
       double w = 0.0;
@@ -771,14 +806,28 @@ __global__ __launch_bounds__(kWG) void k_combine(CombineArgs a) {
       for (int i = 0; i < 16; i++) acc[i] = 0.0;
       for (int k0 = 0; k0 <= a.kmax; k0 += kKC) {
         const int nk = min(kKC, a.kmax + 1 - k0);
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < nk * kTT; idx += kWG) {
-          const int kk = idx / kTT, i = idx % kTT;
-          bt[kk][i] = i < nt ? a.basis[(size_t)(k0 + kk) * a.basis_stride + t0 + i] : 0.0;
+        // staging: every load of the chunk issued before the first LDS store
+        double vb[kKC * kTT / kWG], vc[kKC * 64 / kWG];
+#pragma unroll
+        for (int r = 0; r < kKC * kTT / kWG; r++) {
+          const int idx = threadIdx.x + r * kWG, kk = idx / kTT, i = idx % kTT;
+          vb[r] = kk < nk && i < nt ? a.basis[(size_t)(k0 + kk) * a.basis_stride + t0 + i] : 0.0;
         }
-        for (int idx = threadIdx.x; idx < nk * 64; idx += kWG) {
-          const int kk = idx / 64, j = idx % 64;
-          cs[kk][j] = mc + j < a.G ? a.cf[(size_t)(k0 + kk) * a.G + mc + j] : 0.0;
+#pragma unroll
+        for (int r = 0; r < kKC * 64 / kWG; r++) {
+          const int idx = threadIdx.x + r * kWG, kk = idx / 64, j = idx % 64;
+          vc[r] = kk < nk && mc + j < a.G ? a.cf[(size_t)(k0 + kk) * a.G + mc + j] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kKC * kTT / kWG; r++) {
+          const int idx = threadIdx.x + r * kWG;
+          bt[idx / kTT][idx % kTT] = vb[r];
+        }
+#pragma unroll
+        for (int r = 0; r < kKC * 64 / kWG; r++) {
+          const int idx = threadIdx.x + r * kWG;
+          cs[idx / 64][idx % 64] = vc[r];
         }
         __syncthreads();
         for (int kk = 0; kk < nk; kk++) {
@@ -822,14 +871,28 @@ __global__ __launch_bounds__(kWG) void k_reduce_terms(ReduceTermsArgs a) {
       for (int j = 0; j < 16; j++) acc[j] = 0.0;
       for (int mc = 0; mc < a.G; mc += 64) {
         const int nm = min(64, a.G - mc);
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < kTT * 64; idx += kWG) {
-          const int i = idx / 64, j = idx % 64;
-          ys[i][j] = i < nt && j < nm ? a.Y[(t0 + i) * a.G + mc + j] : 0.0;
+        // staging: every load of the chunk issued before the first LDS store
+        double vy[kTT * 64 / kWG], vc[kKC * 64 / kWG];
+#pragma unroll
+        for (int r = 0; r < kTT * 64 / kWG; r++) {
+          const int idx = threadIdx.x + r * kWG, i = idx / 64, j = idx % 64;
+          vy[r] = i < nt && j < nm ? a.Y[(t0 + i) * a.G + mc + j] : 0.0;
         }
-        for (int idx = threadIdx.x; idx < nk * 64; idx += kWG) {
-          const int kk = idx / 64, j = idx % 64;
-          cs[kk][j] = j < nm ? a.cb[(size_t)(k0 + kk) * a.G + mc + j] : 0.0;
+#pragma unroll
+        for (int r = 0; r < kKC * 64 / kWG; r++) {
+          const int idx = threadIdx.x + r * kWG, kk = idx / 64, j = idx % 64;
+          vc[r] = kk < nk && j < nm ? a.cb[(size_t)(k0 + kk) * a.G + mc + j] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kTT * 64 / kWG; r++) {
+          const int idx = threadIdx.x + r * kWG;
+          ys[idx / 64][idx % 64] = vy[r];
+        }
+#pragma unroll
+        for (int r = 0; r < kKC * 64 / kWG; r++) {
+          const int idx = threadIdx.x + r * kWG;
+          cs[idx / 64][idx % 64] = vc[r];
         }
         __syncthreads();
         for (int j = 0; j < nm; j++) {
@@ -1262,7 +1325,8 @@ void set_launch_tuning(const LaunchTune &t) {
   if (g_tune.wide_max_wg > 2048) g_tune.wide_max_wg = 2048;
   if (g_tune.lp_min_cols < 1) g_tune.lp_min_cols = 1;
   if (g_tune.mixed_min_cols < 1) g_tune.mixed_min_cols = 1;
-  g_tune.pair_steps = g_tune.pair_steps ? 1 : 0;
+  if (g_tune.fused_steps < 1) g_tune.fused_steps = 1;
+  if (g_tune.fused_steps > kFusedMax) g_tune.fused_steps = kFusedMax;
 }
 int launch_rows_grid(int rows, int Bs) { return grid_rows(rows, Bs); }
 
@@ -1281,13 +1345,13 @@ bool launch_events_armed() { return g_ev0 != nullptr; }
 void launch_cheb_iter(const ChebArgs &a, hipStream_t s) {
   launch_timed(k_cheb_iter, rows_grid(a.ops.ne, a.Bs), s, a);
 }
-int cheb_pair_grid(const DevOps &o) {
-  if (o.hparts <= 0) return 0;
+int cheb_fused_grid(const DevOps &o) {
+  if (o.hparts <= 0 || o.fused_max < 2) return 0;
   const int g = (o.hparts + 7) / 8 * 8;
   return g <= launch_max_wg() ? g : 0;
 }
-void launch_cheb_pair(const ChebPairArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_cheb_pair, dim3(cheb_pair_grid(a.ops)), dim3(kWG), 0, s, a);
+void launch_cheb_fused(const ChebFusedArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_cheb_fused, dim3(cheb_fused_grid(a.ops)), dim3(kWG), 0, s, a);
 }
 // The icosahedral meshes give P and P M widths 13 and 27 at every level;
 // other widths take the generic loop.

@@ -50,7 +50,7 @@ class SolveCfg(ctypes.Structure):
 
 PA_PRECOND_JACOBI, PA_PRECOND_LEARNED = 0, 1
 PA_KERNEL_NONE, PA_KERNEL_CG_ITER, PA_KERNEL_CHEB_ITER, PA_KERNEL_CHEB_LP_ITER = 0, 1, 2, 3
-PA_KERNEL_CHEB_PAIR = 4
+PA_KERNEL_CHEB_FUSED = 4
 
 
 class TrainCfg(ctypes.Structure):
@@ -77,12 +77,12 @@ class KernelProfile(ctypes.Structure):
 class LaunchTune(ctypes.Structure):
     _fields_ = [("narrow_rows_per_thread", ctypes.c_int32), ("wide_max_wg", ctypes.c_int32),
                 ("best_ms", ctypes.c_double), ("lp_min_cols", ctypes.c_int32),
-                ("mixed_min_cols", ctypes.c_int32), ("pair_steps", ctypes.c_int32)]
+                ("mixed_min_cols", ctypes.c_int32), ("fused_steps", ctypes.c_int32)]
 
 
 TUNE_FIELDS = ("narrow_rows_per_thread", "wide_max_wg", "lp_min_cols", "mixed_min_cols",
-               "pair_steps")
-TUNE_DEFAULTS = {"lp_min_cols": 8, "mixed_min_cols": 8, "pair_steps": 1}
+               "fused_steps")
+TUNE_DEFAULTS = {"lp_min_cols": 8, "mixed_min_cols": 8, "fused_steps": 3}
 
 
 def _tune_dict(t) -> dict:
@@ -535,10 +535,10 @@ class Batch:
         return outs, [s.as_dict() for s in st]
 
     def set_tune(self, item, narrow_rows_per_thread, wide_max_wg, lp_min_cols=8,
-                 mixed_min_cols=8, pair_steps=1):
+                 mixed_min_cols=8, fused_steps=3):
         t = _tune_struct(dict(narrow_rows_per_thread=narrow_rows_per_thread,
                               wide_max_wg=wide_max_wg, lp_min_cols=lp_min_cols,
-                              mixed_min_cols=mixed_min_cols, pair_steps=pair_steps))
+                              mixed_min_cols=mixed_min_cols, fused_steps=fused_steps))
         _check(lib().pa_batch_set_tune(self._h, item, ctypes.byref(t)))
 
     def get_tune(self, item):

@@ -274,14 +274,15 @@ def test_gpu_fp32_refined_parity(backward, mixed_min_cols):
 
 @pytest.mark.parametrize("level", [2, 3, 4])
 @pytest.mark.parametrize("tol", ["parity", "metric"])
-def test_gpu_cheb_pair_steps(level, tol):
-    """Single-column Jacobi Chebyshev solves two steps per launch (each
-    workgroup forms the first step again on its halo rows) against one step
-    per launch: the same Nbar bit for bit (every row's arithmetic is the
-    same), residuals within the tolerance, and parity with the oracle.
-    Parts of 256 rows, the last one ragged at levels 3 and 4; the parity
-    tolerance gives an even step count here and the metric one an odd one
-    (a single step before the pairs); the metric case also runs captured."""
+def test_gpu_cheb_fused_steps(level, tol):
+    """Single-column Jacobi Chebyshev solves with 2, 3 and 4 steps per
+    launch (each workgroup forms the earlier steps again on the rings of
+    rows its later steps read) against one step per launch: the same Nbar
+    bit for bit (every row's arithmetic is the same), residuals within the
+    tolerance, and parity with the oracle.  Parts of 256 rows, the last one
+    ragged at levels 3 and 4; the step counts of the two tolerances leave
+    different remainders for the first launch of a solve; the metric case
+    also runs captured and replayed."""
     from paper_2103_07706_amd import pa
     keep = pa.get_launch_tune()
     try:
@@ -292,19 +293,22 @@ def test_gpu_cheb_pair_steps(level, tol):
         cfg = pa.solve_cfg(backward=pa.PA_BACKWARD_CLENSHAW, weight_cut=0.0,
                            use_graph=tol == "metric", **kw, **CHEB)
         res = {}
-        for ps in (0, 1):
-            pa.set_launch_tune(pair_steps=ps)
+        for fs in (1, 2, 3, 4):
+            pa.set_launch_tune(fused_steps=fs)
             for rep in range(2 if tol == "metric" else 1):
                 out, st = lo.phase_avg_rhs(avg, to_dev(mm.state(U)), cfg)
                 assert 0 < st["resid_max"] <= kw["cg_rtol"], st["resid_max"]
                 assert st["fallbacks"] == 0
                 got = out.cpu().numpy()
-                if ps in res:
-                    assert np.array_equal(got, res[ps])  # graph replay
-                res[ps] = got
-        assert np.array_equal(res[0], res[1])
+                if fs in res:
+                    assert np.array_equal(got, res[fs])  # graph replay
+                res[fs] = got
         if tol == "parity":
             ref = oo.phase_avg_rhs(lb, avg.s, avg.w, U[0], tol=1e-13, rtol=1e-14)
-            assert rel_w(oo, mm.back(res[1])[0], ref) < TOL
+            for fs in (1, 2, 3, 4):
+                assert rel_w(oo, mm.back(res[fs])[0], ref) < TOL, fs
+        for fs in (2, 3, 4):
+            diff = np.abs(res[fs] - res[1]).max() / np.abs(res[1]).max()
+            assert np.array_equal(res[fs], res[1]), (fs, diff)
     finally:
         pa.set_launch_tune(**keep)
