@@ -274,7 +274,7 @@ int pa_ctx_set_cg_budget(pa_ctx *ctx, double cg_rtol, int iters);
  * workspace must fit it), then, with the learned preconditioner or FP32
  * refinement enabled in cfg, over lp_min_cols and mixed_min_cols in {1, 8,
  * 64, never}, and keeps the fastest; it returns the choice and the best
- * time.  fused_steps (1 to 4) is the number of Jacobi Chebyshev steps of a
+ * time.  fused_steps (1 to 6) is the number of Jacobi Chebyshev steps of a
  * single-column mass solve per launch (a workgroup owns a part of 256 rows
  * and forms the earlier steps again on the rings of rows its later steps
  * read; the results are the same as one step per launch); the autotuner

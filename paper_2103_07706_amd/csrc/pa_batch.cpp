@@ -333,7 +333,7 @@ int pa_batch_set_tune(pa_batch *b, int item, const pa_launch_tune *t) {
     bneed(t->narrow_rows_per_thread >= 1 && t->narrow_rows_per_thread <= 64, "rows per thread in [1, 64]");
     bneed(t->wide_max_wg >= 8 && t->wide_max_wg <= 2048, "wide_max_wg in [8, 2048]");
     bneed(t->lp_min_cols >= 1 && t->mixed_min_cols >= 1, "lp_min_cols, mixed_min_cols >= 1");
-    bneed(t->fused_steps >= 1 && t->fused_steps <= 4, "fused_steps in [1, 4]");
+    bneed(t->fused_steps >= 1 && t->fused_steps <= pa::kFusedMax, "fused_steps in [1, 6]");
     b->tune[item].narrow_rows_per_thread = t->narrow_rows_per_thread;
     b->tune[item].wide_max_wg = t->wide_max_wg;
     b->tune[item].lp_min_cols = t->lp_min_cols;
@@ -418,7 +418,7 @@ int pa_batch_autotune(pa_ctx *ctx, pa_batch *b, const double *const *U_dev,
         }
       }
       if (c.solver == PA_SOLVER_CHEBYSHEV)
-        for (int ps : {1, 2, 3, 4}) {
+        for (int ps = 1; ps <= pa::kFusedMax; ps++) {
           pa::LaunchTune t = best_t;
           t.fused_steps = ps;
           trial(t);

@@ -547,7 +547,7 @@ int pa_set_launch_tune(const pa_launch_tune *t) {
     need(t->narrow_rows_per_thread >= 1 && t->narrow_rows_per_thread <= 64, "rows per thread in [1, 64]");
     need(t->wide_max_wg >= 8 && t->wide_max_wg <= 2048, "wide_max_wg in [8, 2048]");
     need(t->lp_min_cols >= 1 && t->mixed_min_cols >= 1, "lp_min_cols, mixed_min_cols >= 1");
-    need(t->fused_steps >= 1 && t->fused_steps <= 4, "fused_steps in [1, 4]");
+    need(t->fused_steps >= 1 && t->fused_steps <= pa::kFusedMax, "fused_steps in [1, 6]");
     pa::LaunchTune lt;
     lt.narrow_rows_per_thread = t->narrow_rows_per_thread;
     lt.wide_max_wg = t->wide_max_wg;
@@ -611,7 +611,7 @@ int pa_autotune(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int members, 
       };
       if (c.precond == PA_PRECOND_LEARNED) search(&pa::LaunchTune::lp_min_cols, {1, 8, 64, kLpNever});
       if (c.precision == PA_FP32_REFINED) search(&pa::LaunchTune::mixed_min_cols, {1, 8, 64, kLpNever});
-      if (c.solver == PA_SOLVER_CHEBYSHEV) search(&pa::LaunchTune::fused_steps, {1, 2, 3, 4});
+      if (c.solver == PA_SOLVER_CHEBYSHEV) search(&pa::LaunchTune::fused_steps, {1, 2, 3, 4, 5, 6});
     } catch (...) {
       pa::set_launch_tuning(keep);
       throw;

@@ -247,6 +247,7 @@ void Engine::cheb_fused(double *x, const int *colK, int kneed, int nwg_init, int
   while (i < k) {
     const int n = i == 0 && k % S ? k % S : S;
     a.S = n;
+    for (int st = 0; st < kFusedMax; st++) a.slots[st] = ops_->fused_slots[n][st];
     for (int s = 0; s < n; s++) {
       a.c1[s] = c1[i + s];
       a.c2[s] = c2[i + s];
@@ -279,8 +280,8 @@ unsigned long long Engine::fused_bytes(int n, int last) const {
   double b = (double)ne_ * (108.0 + (last ? 0.0 : 8.0) + (n > 1 ? 10.0 : 0.0));
   const pa_ops *o = ops_;
   for (int p = 0; p < o->hparts; p++) {
-    const int32_t *c = &o->ring_cnt[(size_t)p * 4];
-    b += 16.0;
+    const int32_t *c = &o->ring_cnt[(size_t)p * 8];
+    b += 32.0;
     if (n >= 2) b += 4.0 * c[n - 2];
     if (n >= 3) b += 10.0 * c[n - 3];
   }

@@ -317,8 +317,8 @@ void build_row_parts(pa_ops *o) {
   if ((P + 7) / 8 * 8 > launch_max_wg()) fmax = 1;
   o->fused_max = fmax;
   o->hparts = fmax >= 2 ? P : 0;
-  o->ring_cnt.assign((size_t)P * 4, 0);
-  o->ring_row.assign((size_t)P * kHaloMax, 0);
+  o->ring_cnt.assign((size_t)P * 8, 0);
+  o->ring_row.assign((size_t)P * kHaloMax, -1);  // -1: past the part's rings
   o->ring_loc.assign((size_t)P * kHaloMax * 5, 0);
   o->hloc.assign((size_t)5 * ne, 0);
   if (!o->hparts) return;
@@ -334,13 +334,19 @@ void build_row_parts(pa_ops *o) {
         loc[c] = kPartRows + n;
         n++;
       }
-      o->ring_cnt[(size_t)p * 4 + r] = n;
+      o->ring_cnt[(size_t)p * 8 + r] = n;
     }
-    for (int r = fmax - 1; r < 3; r++) o->ring_cnt[(size_t)p * 4 + r] = n;
+    for (int r = fmax - 1; r < kFusedMax - 1; r++) o->ring_cnt[(size_t)p * 8 + r] = n;
+    for (int S = 2; S <= fmax; S++)
+      for (int st = 0; st + 1 < S; st++) {
+        const int c = o->ring_cnt[(size_t)p * 8 + S - 2 - st];
+        int &sl = o->fused_slots[S][st];
+        sl = std::max(sl, (c + kPartRows - 1) / kPartRows);
+      }
     for (int e = e0; e < e1; e++)
       for (int j = 0; j < 5; j++) o->hloc[(size_t)j * ne + e] = (uint16_t)loc.at(o->ell_col[5 * e + j]);
     // rings whose rows take later steps: all but the outermost kept ring
-    const int inner = fmax >= 3 ? o->ring_cnt[(size_t)p * 4 + fmax - 3] : 0;
+    const int inner = fmax >= 3 ? o->ring_cnt[(size_t)p * 8 + fmax - 3] : 0;
     for (int h = 0; h < inner; h++) {
       const int g = o->ring_row[(size_t)p * kHaloMax + h];
       for (int j = 0; j < 5; j++)

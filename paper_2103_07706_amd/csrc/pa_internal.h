@@ -86,9 +86,9 @@ constexpr int kEdgeTau = 12;
 // columns reach outside the part and rings 1..r.  kFusedMax - 1 rings are
 // kept, at most kHaloMax rows in all per part (fewer rings on a mesh where
 // they do not fit).
-constexpr int kPartRows = 256;
-constexpr int kHaloMax = 512;
-constexpr int kFusedMax = 4;
+constexpr int kPartRows = 256;  // also the kernel's workgroup size: one row a thread
+constexpr int kHaloMax = 768;
+constexpr int kFusedMax = 6;
 
 // Device-resident operator arrays (pointers into the caller's buffer).
 struct DevOps {
@@ -113,9 +113,9 @@ struct DevOps {
   const double *cgeo = nullptr;       // nc*kCellGeo
   // row parts (see kPartRows): hparts parts, rings 1..fused_max-1 kept
   int hparts = 0, fused_max = 1;
-  const int32_t *ring_cnt = nullptr;  // hparts*4: rows of rings 1..r of part p, r = 1..3
+  const int32_t *ring_cnt = nullptr;  // hparts*8: rows of rings 1..r of part p, r = 1..kFusedMax-1
   const int32_t *ring_row = nullptr;  // hparts*kHaloMax: part p's ring rows from p*kHaloMax,
-                                      // ring by ring, ascending within a ring
+                                      // ring by ring, ascending within a ring, then -1
   const uint16_t *hloc = nullptr;     // 5*ne, [slot][row]: ELL column as a part-local index
                                       // (row offset in the part, or kPartRows + ring position)
   const uint16_t *ring_loc = nullptr; // hparts*kHaloMax*5: the same for the ring rows
@@ -137,7 +137,7 @@ struct LaunchTune {
   int wide_max_wg = 2048;          // workgroups per column tile, wider batches
   int lp_min_cols = 8;             // learned mass-solve steps on blocks this wide or wider
   int mixed_min_cols = 8;          // FP32-refined mass solves on blocks this wide or wider
-  int fused_steps = 3;             // single-column Jacobi Chebyshev solves: steps per launch (1-4)
+  int fused_steps = 3;             // single-column Jacobi Chebyshev solves: steps per launch (1 to kFusedMax)
   bool operator==(const LaunchTune &o) const {
     return narrow_rows_per_thread == o.narrow_rows_per_thread && wide_max_wg == o.wide_max_wg &&
            lp_min_cols == o.lp_min_cols && mixed_min_cols == o.mixed_min_cols &&
@@ -204,6 +204,8 @@ struct pa_ops {
   std::vector<double> mass, cor, dinv, area, inv_area, bottom, cgeo, tau;
   std::vector<float> mass32, dinv32;
   int hparts = 0, fused_max = 1;
+  int fused_slots[pa::kFusedMax + 1][pa::kFusedMax] = {};  // per S and step: ring slots
+                                                           // (see ChebFusedArgs)
   std::vector<int32_t> ring_cnt, ring_row;
   std::vector<uint16_t> hloc, ring_loc;
   size_t dev_bytes = 0;

@@ -114,6 +114,8 @@ struct ChebArgs {
 struct ChebFusedArgs {
   DevOps ops;
   int S;            // 1 <= S <= ops.fused_max
+  int slots[kFusedMax];  // per step s: ring slots of kPartRows rows that rings
+                        // 1..S-1-s of the largest part fill
   double *x;
   const double *r_in, *d_in;
   double *r_out, *d_out;

@@ -290,6 +290,18 @@ __global__ __launch_bounds__(kWG) void k_cheb_iter(ChebArgs a) {
 // and d go to separate output buffers.  Parts are laid over the XCDs like
 // lane_map's slices (XCD k takes parts k per .. k per + per - 1), so
 // neighbouring parts and their rings share an L2.
+constexpr int kRingSlots = kHaloMax / kWG;  // ring rows per thread
+
+// NSLOT: ring slots of kWG rows the launch's first step covers (every part's
+// rings 1..S-1 fit).  The loads go out in three waves by dependence (indices
+// and row values; the ring rows they name and the own row's gathers; the
+// ring rows' gathers); a ring slot past the part's rings (list entry -1)
+// loads nothing, and a wave skips a slot in a later step when all its rows
+// lie past the rings that take that step.  Ring rows that no later step
+// reads work anyway (nothing reads their results), and the stores to global
+// memory are predicated (an inactive column; the threads past a ragged last
+// part, which work on a copy of its last row).
+template <int NSLOT>
 __global__ __launch_bounds__(kWG) void k_cheb_fused(ChebFusedArgs a) {
   const DevOps &o = a.ops;
   const int t = threadIdx.x;
@@ -299,80 +311,127 @@ __global__ __launch_bounds__(kWG) void k_cheb_fused(ChebFusedArgs a) {
     atomicAdd(&a.prof[1], 1u);
     if (on) atomicAdd(a.prof_bytes, a.bytes);
   }
-  if (a.colK[0] < a.kneed) return;  // inactive column: its partials are not read
+  const bool act = a.colK[0] >= a.kneed;
   const int per = gridDim.x >> 3;
   const int p = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   const int S = a.S;
   __shared__ double dl[2][kPartRows + kHaloMax];
-  __shared__ double rl[kHaloMax];
   __shared__ double red[kWG / 64];
   double s2 = 0.0;
   if (p < o.hparts) {
     const int e0 = p * kPartRows;
-    const int nrow = min(kPartRows, o.ne - e0);
-    const int *cnt = o.ring_cnt + 4 * p;
+    const bool own = e0 + t < o.ne;
+    const int e = own ? e0 + t : o.ne - 1;
     const int32_t *rrow = o.ring_row + (size_t)p * kHaloMax;
     const uint16_t *rloc = o.ring_loc + (size_t)p * kHaloMax * 5;
-    // the part's own row: matrix row, local columns and state kept in registers
-    const int e = e0 + t;
-    const bool own = t < nrow;
-    double m[5] = {0.0, 0.0, 0.0, 0.0, 0.0}, x = 0.0, r = 0.0, dv = 0.0, dinv = 0.0;
-    int lc[5] = {0, 0, 0, 0, 0};
-    if (own) {
-      int col[5];
+    // ring counts of the part (rows of rings 1..r), first needed at step 2
+    int cnt[kFusedMax - 1];
+#pragma unroll
+    for (int i = 0; i < kFusedMax - 1; i++) cnt[i] = o.ring_cnt[8 * p + i];
+    const int wrow = __builtin_amdgcn_readfirstlane(t & ~63);  // the wave's first row in a slot
+    // first wave of loads: the own row (ELL slot 0 is the row itself, whose
+    // d is read once) and the ring rows' numbers
+    double m[5];
+    int col[5], lc[5];
+#pragma unroll
+    for (int j = 0; j < 5; j++) {
+      col[j] = o.ell_col[5 * e + j];
+      m[j] = o.mass[5 * e + j];
+      lc[j] = o.hloc[(size_t)j * o.ne + e];
+    }
+    double dv = a.d_in[e];
+    const double dinv = o.dinv[e];
+    double x = a.x[e];
+    double r = a.r_in[e];
+    int g[NSLOT > 0 ? NSLOT : 1];
+#pragma unroll
+    for (int q = 0; q < NSLOT; q++) g[q] = rrow[t + q * kWG];
+    // second wave: the ring rows, the own row's gathers
+    double rm[NSLOT > 0 ? NSLOT : 1][5], rdinv[NSLOT > 0 ? NSLOT : 1], rr[NSLOT > 0 ? NSLOT : 1];
+    double dg[NSLOT > 0 ? NSLOT : 1];
+    int gc[NSLOT > 0 ? NSLOT : 1][5], rlc[NSLOT > 0 ? NSLOT : 1][5];
+#pragma unroll
+    for (int q = 0; q < NSLOT; q++) {
+      const int h = t + q * kWG;
+      dg[q] = rdinv[q] = rr[q] = 0.0;
 #pragma unroll
       for (int j = 0; j < 5; j++) {
-        col[j] = o.ell_col[5 * e + j];
-        m[j] = o.mass[5 * e + j];
-        if (S > 1) lc[j] = o.hloc[(size_t)j * o.ne + e];
+        gc[q][j] = rlc[q][j] = 0;
+        rm[q][j] = 0.0;
       }
-      double q = 0.0;
+      if (g[q] >= 0) {  // past the part's rings the list holds -1
 #pragma unroll
-      for (int j = 0; j < 5; j++) q = fma(m[j], a.d_in[col[j]], q);
-      dv = a.d_in[e];
-      dinv = o.dinv[e];
-      x = a.x[e] + dv;
-      r = a.r_in[e] - q;
-      if (S > 1) dl[0][t] = cheb_dir(a.c1[0], a.c2[0], dv, dinv, r);
+        for (int j = 0; j < 5; j++) {
+          gc[q][j] = o.ell_col[5 * g[q] + j];
+          rm[q][j] = o.mass[5 * g[q] + j];
+          rlc[q][j] = rloc[5 * h + j];
+        }
+        dg[q] = a.d_in[g[q]];
+        rdinv[q] = o.dinv[g[q]];
+        rr[q] = a.r_in[g[q]];
+      }
     }
-    // step 1 on rings 1..S-1
-    const int n1 = S > 1 ? cnt[S - 2] : 0;
-    for (int h = t; h < n1; h += kWG) {
-      const int g = rrow[h];
-      double q = 0.0;
+    double q0 = fma(m[0], dv, 0.0);
 #pragma unroll
-      for (int j = 0; j < 5; j++) q = fma(o.mass[5 * g + j], a.d_in[o.ell_col[5 * g + j]], q);
-      const double rg = a.r_in[g] - q;
-      rl[h] = rg;
-      dl[0][kPartRows + h] = cheb_dir(a.c1[0], a.c2[0], a.d_in[g], o.dinv[g], rg);
-    }
+    for (int j = 1; j < 5; j++) q0 = fma(m[j], a.d_in[col[j]], q0);
+    x += dv;
+    r -= q0;
+    if (S > 1) dl[0][t] = cheb_dir(a.c1[0], a.c2[0], dv, dinv, r);
+    // third wave: the ring rows' gathers; step 1 on rings 1..S-1 (ring row
+    // h = t + q kWG stays in slot q of thread t, its matrix row, local
+    // columns, diagonal and residual in registers, so that later steps touch
+    // only LDS)
+#pragma unroll
+    for (int q = 0; q < NSLOT; q++)
+      if (g[q] >= 0) {
+        double qs = fma(rm[q][0], dg[q], 0.0);
+#pragma unroll
+        for (int j = 1; j < 5; j++) qs = fma(rm[q][j], a.d_in[gc[q][j]], qs);
+        rr[q] -= qs;
+        dl[0][kPartRows + t + q * kWG] = cheb_dir(a.c1[0], a.c2[0], dg[q], rdinv[q], rr[q]);
+      }
     for (int st = 1; st < S; st++) {
       __syncthreads();
       const double *dp = dl[(st - 1) & 1];
       double *dn = dl[st & 1];
       const double c1 = a.c1[st], c2 = a.c2[st];
-      if (own) {
-        double q = 0.0;
-#pragma unroll
-        for (int j = 0; j < 5; j++) q = fma(m[j], dp[lc[j]], q);
-        dv = dp[t];
-        x += dv;
-        r -= q;
-        if (st + 1 < S) dn[t] = cheb_dir(c1, c2, dv, dinv, r);
-      }
-      // rings 1..S-1-st take this step too
+      // every LDS read of the step before its first write (the compiler
+      // cannot tell the two halves of dl apart)
+      // a wave skips the slots whose 64 rows all lie past the rings that
+      // take this step
       const int nh = st + 1 < S ? cnt[S - 2 - st] : 0;
-      for (int h = t; h < nh; h += kWG) {
-        const int g = rrow[h];
-        double q = 0.0;
+      double dq[5], dr[NSLOT > 0 ? NSLOT : 1][5];
 #pragma unroll
-        for (int j = 0; j < 5; j++) q = fma(o.mass[5 * g + j], dp[rloc[5 * h + j]], q);
-        const double rg = rl[h] - q;
-        rl[h] = rg;
-        dn[kPartRows + h] = cheb_dir(c1, c2, dp[kPartRows + h], o.dinv[g], rg);
-      }
+      for (int j = 0; j < 5; j++) dq[j] = dp[j ? lc[j] : t];
+#pragma unroll
+      for (int k = 0; k < NSLOT; k++)
+        if (k * kWG + wrow < nh) {
+#pragma unroll
+          for (int j = 0; j < 5; j++) dr[k][j] = dp[j ? rlc[k][j] : kPartRows + t + k * kWG];
+        }
+      dv = dq[0];
+      double q = fma(m[0], dv, 0.0);
+#pragma unroll
+      for (int j = 1; j < 5; j++) q = fma(m[j], dq[j], q);
+      x += dv;
+      r -= q;
+      // rings 1..S-1-st take this step too (rows past them are not read)
+      double dnr[NSLOT > 0 ? NSLOT : 1];
+#pragma unroll
+      for (int k = 0; k < NSLOT; k++)
+        if (k * kWG + wrow < nh) {
+          double qs = fma(rm[k][0], dr[k][0], 0.0);
+#pragma unroll
+          for (int j = 1; j < 5; j++) qs = fma(rm[k][j], dr[k][j], qs);
+          rr[k] -= qs;
+          dnr[k] = cheb_dir(c1, c2, dr[k][0], rdinv[k], rr[k]);
+        }
+      if (st + 1 < S) dn[t] = cheb_dir(c1, c2, dv, dinv, r);
+#pragma unroll
+      for (int k = 0; k < NSLOT; k++)
+        if (k * kWG + wrow < nh) dn[kPartRows + t + k * kWG] = dnr[k];
     }
-    if (own) {
+    if (own && act) {
       a.x[e] = x;
       a.r_out[e] = r;
       if (a.last)
@@ -1351,7 +1410,13 @@ int cheb_fused_grid(const DevOps &o) {
   return g <= launch_max_wg() ? g : 0;
 }
 void launch_cheb_fused(const ChebFusedArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_cheb_fused, dim3(cheb_fused_grid(a.ops)), dim3(kWG), 0, s, a);
+  const dim3 grid(cheb_fused_grid(a.ops));
+  switch (a.slots[0]) {
+    case 0: hipLaunchKernelGGL(k_cheb_fused<0>, grid, dim3(kWG), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(k_cheb_fused<1>, grid, dim3(kWG), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_cheb_fused<2>, grid, dim3(kWG), 0, s, a); break;
+    default: hipLaunchKernelGGL(k_cheb_fused<kRingSlots>, grid, dim3(kWG), 0, s, a); break;
+  }
 }
 // The icosahedral meshes give P and P M widths 13 and 27 at every level;
 // other widths take the generic loop.

@@ -275,7 +275,7 @@ def test_gpu_fp32_refined_parity(backward, mixed_min_cols):
 @pytest.mark.parametrize("level", [2, 3, 4])
 @pytest.mark.parametrize("tol", ["parity", "metric"])
 def test_gpu_cheb_fused_steps(level, tol):
-    """Single-column Jacobi Chebyshev solves with 2, 3 and 4 steps per
+    """Single-column Jacobi Chebyshev solves with 2 to 6 steps per
     launch (each workgroup forms the earlier steps again on the rings of
     rows its later steps read) against one step per launch: the same Nbar
     bit for bit (every row's arithmetic is the same), residuals within the
@@ -293,7 +293,7 @@ def test_gpu_cheb_fused_steps(level, tol):
         cfg = pa.solve_cfg(backward=pa.PA_BACKWARD_CLENSHAW, weight_cut=0.0,
                            use_graph=tol == "metric", **kw, **CHEB)
         res = {}
-        for fs in (1, 2, 3, 4):
+        for fs in (1, 2, 3, 4, 5, 6):
             pa.set_launch_tune(fused_steps=fs)
             for rep in range(2 if tol == "metric" else 1):
                 out, st = lo.phase_avg_rhs(avg, to_dev(mm.state(U)), cfg)
@@ -305,9 +305,9 @@ def test_gpu_cheb_fused_steps(level, tol):
                 res[fs] = got
         if tol == "parity":
             ref = oo.phase_avg_rhs(lb, avg.s, avg.w, U[0], tol=1e-13, rtol=1e-14)
-            for fs in (1, 2, 3, 4):
+            for fs in (1, 2, 3, 4, 5, 6):
                 assert rel_w(oo, mm.back(res[fs])[0], ref) < TOL, fs
-        for fs in (2, 3, 4):
+        for fs in (2, 3, 4, 5, 6):
             diff = np.abs(res[fs] - res[1]).max() / np.abs(res[1]).max()
             assert np.array_equal(res[fs], res[1]), (fs, diff)
     finally:
