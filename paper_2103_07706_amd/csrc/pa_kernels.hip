@@ -842,27 +842,29 @@ __global__ __launch_bounds__(kWG) void k_cg_iter(CgArgs a) {
 // ------------------------------------------- forward combination of a basis
 // E[row][mem*G + m] = sum_k cf[k][m] R_k[row][mem], both row ranges, with
 // t = row * BsR + mem.  A workgroup takes tiles of kTT consecutive t: it
-// stages R_k[t] (k in chunks of kKC) and the matching coefficients in LDS,
-// then lane m of wave w forms E[t][m] for the 16 t of the wave, so each
-// t's G outputs leave as one contiguous store of the wave.  k runs in
-// ascending order as in the definition.
+// stages R_k[t] (k in chunks of kKC) and the matching coefficients in LDS;
+// thread (tb, mb) = (tid % 16, tid / 16) forms the 4 x 4 block t = tb + 16 i,
+// m = 4 mb + j (four consecutive outputs of a t leave as one run), so that
+// each pair of LDS reads feeds two multiply-adds.  k runs in ascending order
+// as in the definition.
 constexpr int kTT = 64;  // t per tile
 constexpr int kKC = 64;  // k (or m) per LDS chunk
 
 __global__ __launch_bounds__(kWG) void k_combine(CombineArgs a) {
   __shared__ double bt[kKC][kTT];
   __shared__ double cs[kKC][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int tb = threadIdx.x & 15, mb = threadIdx.x >> 4;
   const long total = (long)a.nrows * a.BsR;
   const long ntiles = (total + kTT - 1) / kTT;
   for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const long t0 = tile * kTT;
     const int nt = (int)min((long)kTT, total - t0);
     for (int mc = 0; mc < a.G; mc += 64) {
-      const int m = mc + lane;
-      double acc[16];
+      double acc[4][4];
 #pragma unroll
-      for (int i = 0; i < 16; i++) acc[i] = 0.0;
+      for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[i][j] = 0.0;
       for (int k0 = 0; k0 <= a.kmax; k0 += kKC) {
         const int nk = min(kKC, a.kmax + 1 - k0);
         // staging: every load of the chunk issued before the first LDS store
@@ -890,18 +892,27 @@ __global__ __launch_bounds__(kWG) void k_combine(CombineArgs a) {
         }
         __syncthreads();
         for (int kk = 0; kk < nk; kk++) {
-          const double c = cs[kk][lane];
+          double b[4], c[4];
 #pragma unroll
-          for (int i = 0; i < 16; i++) acc[i] += c * bt[kk][w * 16 + i];
+          for (int i = 0; i < 4; i++) b[i] = bt[kk][tb + 16 * i];
+#pragma unroll
+          for (int j = 0; j < 4; j++) c[j] = cs[kk][4 * mb + j];
+#pragma unroll
+          for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) acc[i][j] = fma(c[j], b[i], acc[i][j]);
         }
       }
-      if (m < a.G) {
 #pragma unroll
-        for (int i = 0; i < 16; i++) {
-          const int ti = w * 16 + i;
-          if (ti < nt) {
-            const long t = t0 + ti;
-            a.E[t * a.G + m] = (int)(t % a.BsR) < a.members ? acc[i] : 0.0;
+      for (int i = 0; i < 4; i++) {
+        const int ti = tb + 16 * i;
+        if (ti < nt) {
+          const long t = t0 + ti;
+          const bool on = (int)(t % a.BsR) < a.members;
+#pragma unroll
+          for (int j = 0; j < 4; j++) {
+            const int m = mc + 4 * mb + j;
+            if (m < a.G) a.E[t * a.G + m] = on ? acc[i][j] : 0.0;
           }
         }
       }
@@ -910,14 +921,15 @@ __global__ __launch_bounds__(kWG) void k_combine(CombineArgs a) {
 }
 
 // Z[k][t] = sum_m cb[k][m] Y[t][m] (backward terms reduced to one series per
-// member).  A workgroup stages kTT rows Y[t][.] (m in chunks of 64, rows
-// padded against bank conflicts) and cb for a chunk of kKC values of k; lane
-// i of wave w forms Z[k][t0 + i] for k = k0 + w + 4 j, and the wave stores
-// each k's 64 values as one contiguous run.  m runs in ascending order.
+// member).  A workgroup stages kTT rows Y[t][.] (m in chunks of 64) and cb
+// for a chunk of kKC values of k in LDS, both padded to 65 doubles a row
+// against bank conflicts; thread (tb, kb) = (tid % 16, tid / 16) forms the
+// 4 x 4 block t = tb + 16 i, k = k0 + kb + 16 j, so that each pair of LDS
+// reads feeds two multiply-adds.  m runs in ascending order.
 __global__ __launch_bounds__(kWG) void k_reduce_terms(ReduceTermsArgs a) {
   __shared__ double ys[kTT][65];
-  __shared__ double cs[kKC][64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __shared__ double cs[kKC][65];
+  const int tb = threadIdx.x & 15, kb = threadIdx.x >> 4;
   const long total = (long)a.nrows * a.BsZ;
   const long ntiles = (total + kTT - 1) / kTT;
   for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -925,9 +937,11 @@ __global__ __launch_bounds__(kWG) void k_reduce_terms(ReduceTermsArgs a) {
     const int nt = (int)min((long)kTT, total - t0);
     for (int k0 = 0; k0 <= a.kmax; k0 += kKC) {
       const int nk = min(kKC, a.kmax + 1 - k0);
-      double acc[16];
+      double acc[4][4];
 #pragma unroll
-      for (int j = 0; j < 16; j++) acc[j] = 0.0;
+      for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[i][j] = 0.0;
       for (int mc = 0; mc < a.G; mc += 64) {
         const int nm = min(64, a.G - mc);
         // staging: every load of the chunk issued before the first LDS store
@@ -954,18 +968,25 @@ __global__ __launch_bounds__(kWG) void k_reduce_terms(ReduceTermsArgs a) {
           cs[idx / 64][idx % 64] = vc[r];
         }
         __syncthreads();
-        for (int j = 0; j < nm; j++) {
-          const double y = ys[lane][j];
+        for (int m = 0; m < nm; m++) {
+          double y[4], c[4];
 #pragma unroll
-          for (int q = 0; q < 16; q++)
-            if (w + 4 * q < nk) acc[q] += cs[w + 4 * q][j] * y;
+          for (int i = 0; i < 4; i++) y[i] = ys[tb + 16 * i][m];
+#pragma unroll
+          for (int j = 0; j < 4; j++) c[j] = cs[kb + 16 * j][m];
+#pragma unroll
+          for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) acc[i][j] = fma(c[j], y[i], acc[i][j]);
         }
       }
-      if (lane < nt) {
 #pragma unroll
-        for (int q = 0; q < 16; q++)
-          if (w + 4 * q < nk) a.Z[(size_t)(k0 + w + 4 * q) * a.zstride + t0 + lane] = acc[q];
-      }
+      for (int j = 0; j < 4; j++)
+        if (kb + 16 * j < nk) {
+#pragma unroll
+          for (int i = 0; i < 4; i++)
+            if (tb + 16 * i < nt) a.Z[(size_t)(k0 + kb + 16 * j) * a.zstride + t0 + tb + 16 * i] = acc[i][j];
+        }
     }
   }
 }
