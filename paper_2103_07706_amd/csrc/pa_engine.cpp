@@ -228,7 +228,11 @@ bool Engine::lp_cheaper(int Bs) const { return lp_avail_ && Bs >= launch_tuning(
 // Jacobi semi-iteration of a single column, S steps per launch
 // (k_cheb_fused): the remainder of the step count first, then launches of S
 // steps.  r and d move between two buffers each from one launch to the next.
-void Engine::cheb_fused(double *x, const int *colK, int kneed, int nwg_init, int grid, int S) {
+// With `su`, the first launch also does the set-up of the solve (the work of
+// k_stiff) as its step 1 and then as many Chebyshev steps as the remainder
+// (at most S - 1).
+void Engine::cheb_fused(double *x, const int *colK, int kneed, int nwg_init, int grid, int S,
+                        const FusedSetup *su) {
   const std::vector<double> &c1 = cheb_c1_, &c2 = cheb_c2_;
   const int k = (int)c1.size();
   double *d[2] = {p_, s0_};
@@ -244,8 +248,42 @@ void Engine::cheb_fused(double *x, const int *colK, int kneed, int nwg_init, int
   a.prof_bytes = st_.prof_bytes;
   int launches = 0, i = 0, buf = 0;
   if (prof) bracket_begin();
+  if (su) {
+    int c = k % S ? k % S : S - 1;
+    c = std::min(c, k);
+    ChebFusedArgs b = a;
+    b.setup = 1;
+    b.S = c + 1;
+    for (int st = 0; st < kFusedMax; st++) b.slots[st] = ops_->fused_slots[c + 1][st];
+    for (int st = 1; st <= c; st++) {
+      b.c1[st] = c1[st - 1];
+      b.c2[st] = c2[st - 1];
+    }
+    b.in_u = su->in_u;
+    b.in_eta = su->in_eta;
+    b.addA_u = su->addA_u;
+    b.addA_eta = su->addA_eta;
+    b.addB_u = su->addB_u;
+    b.addB_eta = su->addB_eta;
+    b.out_eta = su->out_eta;
+    b.scale = su->scale;
+    b.theta_inv = 1.0 / cheb_theta_;
+    b.cpp = ops_->fused_cpp;
+    b.part_rr = chk_init_[chk_par_];
+    take_check(b.chk, b.chk_blocks, grid);
+    b.r_out = r[1];
+    b.d_out = d[1];
+    b.last = c == k ? 1 : 0;
+    b.bytes = prof ? fused_bytes(c + 1, b.last, true) : 0;
+    launch_cheb_fused(b, s_);
+    buf = 1;
+    i = c;
+    launches++;
+  }
+  // the remainder of the steps left first, then launches of S steps
+  const int i0 = i;
   while (i < k) {
-    const int n = i == 0 && k % S ? k % S : S;
+    const int n = i == i0 && (k - i0) % S ? (k - i0) % S : S;
     a.S = n;
     for (int st = 0; st < kFusedMax; st++) a.slots[st] = ops_->fused_slots[n][st];
     for (int s = 0; s < n; s++) {
@@ -257,7 +295,7 @@ void Engine::cheb_fused(double *x, const int *colK, int kneed, int nwg_init, int
     a.r_in = r[buf];
     a.r_out = r[buf ^ 1];
     a.last = i + n == k ? 1 : 0;
-    a.bytes = prof ? fused_bytes(n, a.last) : 0;
+    a.bytes = prof ? fused_bytes(n, a.last, false) : 0;
     launch_cheb_fused(a, s_);
     buf ^= 1;
     i += n;
@@ -275,9 +313,14 @@ void Engine::cheb_fused(double *x, const int *colK, int kneed, int nwg_init, int
 // r out, d out unless the launch ends the solve, and with n > 1 the row's
 // part-local columns (2 bytes each); per part its ring lists for rings
 // 1..n-1 (4 bytes a row) and the local columns of rings 1..n-2.  Ring rows'
-// own data are other parts' rows, counted once.
-unsigned long long Engine::fused_bytes(int n, int last) const {
-  double b = (double)ne_ * (108.0 + (last ? 0.0 : 8.0) + (n > 1 ? 10.0 : 0.0));
+// own data are other parts' rows, counted once.  A set-up launch reads u
+// and the Coriolis row (40 bytes), the row's two cells (8), and x_0's
+// addends instead of x, r and d (net +40 bytes a row), and per cell its
+// three edges and signs (24), 1/|c| (8), eta (8), two addends (16) and the
+// output (8).
+unsigned long long Engine::fused_bytes(int n, int last, bool setup) const {
+  double b = (double)ne_ * (108.0 + (last ? 0.0 : 8.0) + (n > 1 ? 10.0 : 0.0) + (setup ? 40.0 : 0.0));
+  if (setup) b += (double)nc_ * 64.0;
   const pa_ops *o = ops_;
   for (int p = 0; p < o->hparts; p++) {
     const int32_t *c = &o->ring_cnt[(size_t)p * 8];
@@ -288,12 +331,23 @@ unsigned long long Engine::fused_bytes(int n, int last) const {
   return (unsigned long long)b;
 }
 
+// Steps per fused launch of a single-column solve whose set-up the first
+// launch can do (the solve takes the fused Jacobi path), else 0.
+int Engine::fused_setup_steps() const {
+  if (!cheb() && !mixed()) return 0;
+  if (mixed() && 1 >= launch_tuning().mixed_min_cols) return 0;
+  if (lp_cheaper(1)) return 0;
+  const int S = std::min(launch_tuning().fused_steps, ops_->fused_max);
+  if (S < 2 || ops_->fused_cpp <= 0 || cheb_fused_grid(ops_->d) <= 0) return 0;
+  return S;
+}
+
 void Engine::cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_init) {
   const bool lp = lp_cheaper(Bs);
   const int S = std::min(launch_tuning().fused_steps, ops_->fused_max);
   if (!lp && Bs == 1 && S > 1) {
     const int grid = cheb_fused_grid(ops_->d);
-    if (grid > 0) return cheb_fused(x, colK, kneed, nwg_init, grid, S);
+    if (grid > 0) return cheb_fused(x, colK, kneed, nwg_init, grid, S, nullptr);
   }
   const std::vector<double> &c1 = lp ? lp_c1_ : cheb_c1_, &c2 = lp ? lp_c2_ : cheb_c2_;
   const int k = (int)c1.size();
@@ -792,6 +846,15 @@ void Engine::lstep(Blk in, Blk out, const Blk *A, const Blk *B, double scale, co
   a.st = st_;
   a.rb = rb_;
   a.max_wg = rb_.max_wg;
+  // a single-column Jacobi Chebyshev solve folds this set-up into its first
+  // fused launch
+  const int S = acc || in.Bs != 1 ? 0 : fused_setup_steps();
+  if (S > 0) {
+    const FusedSetup su{a.in_u, a.in_eta, a.addA_u, a.addA_eta, a.addB_u, a.addB_eta, a.out_eta, scale};
+    const int grid = cheb_fused_grid(ops_->d);
+    cheb_fused(out.p, colK, kneed, grid, grid, S, &su);
+    return;
+  }
   if (cheb() || mixed()) {
     a.d0 = p_;
     a.theta_inv = 1.0 / cheb_theta_;

@@ -109,8 +109,16 @@ class Engine {
   bool pend_ = false;
   CheckArgs pend_args_{};
   void defer_check(int Bs, int nwg_init, const int *colK, int kneed, int nwg_last = -1);
-  void cheb_fused(double *x, const int *colK, int kneed, int nwg_init, int grid, int S);
-  unsigned long long fused_bytes(int n, int last) const;
+  // the set-up of a single-column solve done by its first fused launch
+  struct FusedSetup {
+    const double *in_u, *in_eta, *addA_u, *addA_eta, *addB_u, *addB_eta;
+    double *out_eta;
+    double scale;
+  };
+  void cheb_fused(double *x, const int *colK, int kneed, int nwg_init, int grid, int S,
+                  const FusedSetup *su);
+  unsigned long long fused_bytes(int n, int last, bool setup) const;
+  int fused_setup_steps() const;  // steps per launch when lstep may fold its set-up, else 0
   void take_check(CheckArgs &chk, int &blocks, int grid_blocks);
   void flush_check();
   bool cheb() const { return cfg_.solver == PA_SOLVER_CHEBYSHEV; }

@@ -317,6 +317,9 @@ void build_row_parts(pa_ops *o) {
   if ((P + 7) / 8 * 8 > launch_max_wg()) fmax = 1;
   o->fused_max = fmax;
   o->hparts = fmax >= 2 ? P : 0;
+  // a set-up launch also forms the depth rows: nc / parts per workgroup
+  o->fused_cpp = o->hparts ? (o->nc + P - 1) / P : 0;
+  if (o->fused_cpp > kPartRows) o->fused_cpp = 0;
   o->ring_cnt.assign((size_t)P * 8, 0);
   o->ring_row.assign((size_t)P * kHaloMax, -1);  // -1: past the part's rings
   o->ring_loc.assign((size_t)P * kHaloMax * 5, 0);

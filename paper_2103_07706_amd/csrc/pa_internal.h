@@ -204,6 +204,7 @@ struct pa_ops {
   std::vector<double> mass, cor, dinv, area, inv_area, bottom, cgeo, tau;
   std::vector<float> mass32, dinv32;
   int hparts = 0, fused_max = 1;
+  int fused_cpp = 0;  // cells per part in a set-up launch (0: no set-up launches)
   int fused_slots[pa::kFusedMax + 1][pa::kFusedMax] = {};  // per S and step: ring slots
                                                            // (see ChebFusedArgs)
   std::vector<int32_t> ring_cnt, ring_row;

@@ -126,6 +126,21 @@ struct ChebFusedArgs {
   unsigned *prof;   // measurement hook, as ChebArgs
   unsigned long long *prof_bytes;  // algorithmic bytes of the launch added here
   unsigned long long bytes;
+  // setup = 1 (the solve's first launch): step 1 is the set-up of the solve,
+  // as k_stiff does it: r_0 = scale (-F u + g D' eta), d_0 = theta_inv D^-1
+  // r_0, x_0 = addA_u + addB_u (each addend optional), with partials of
+  // r_0.r_0 per workgroup and the depth rows out_eta = scale (-H D u / |c|) +
+  // addA_eta + addB_eta on cpp cells per part; steps 2..S are Chebyshev
+  // steps with c1[1..S-1], c2[1..S-1]; the previous solve's residual check
+  // runs in the first chk_blocks workgroups.  r_in, d_in are not read.
+  int setup;
+  const double *in_u, *in_eta, *addA_u, *addA_eta, *addB_u, *addB_eta;
+  double *out_eta;
+  double scale, theta_inv;
+  int cpp;
+  double *part_rr;
+  CheckArgs chk;
+  int chk_blocks;
 };
 
 // Chebyshev step with the learned preconditioner P (see k_cheb_lp_iter):

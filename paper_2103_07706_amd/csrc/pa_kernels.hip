@@ -156,6 +156,24 @@ __device__ inline void folded_check(const CheckArgs &a, int blocks) {
 }
 
 // ---------------------------------------------------------------- stiffness
+// The stiffness arithmetic of one row, in one fixed rounding order for every
+// kernel that forms it (no contraction left to the compiler).
+#pragma clang fp contract(off)
+// velocity row: scale (-sum_j F_j u_j + g (eta_0 - eta_1)); fu = sum_j F_j u_j
+// accumulated by fma in ELL order
+__device__ inline double stiff_u(double scale, double fu, double g, double eta0, double eta1) {
+  return scale * fma(g, eta0 - eta1, -fu);
+}
+// depth row: scale (-H div / |c|) + addA + addB (an absent addend is 0)
+__device__ inline double stiff_eta(double scale, double H, double div, double inv_area, double addA,
+                                   double addB) {
+  return (scale * ((-H * div) * inv_area) + addA) + addB;
+}
+// d_0 = theta_inv D^-1 r_0
+__device__ inline double stiff_d0(double theta_inv, double dinv, double r) { return (theta_inv * dinv) * r; }
+#pragma clang fp contract(on)
+
+
 // One application of the linear operator with the mass solve set up:
 //   velocity: r = scale (-F u + g D' eta), out_u = addA_u + addB_u (CG start),
 //   depth:    out_eta = scale (-H D u / |c|) + addA_eta + addB_eta,
@@ -179,18 +197,17 @@ __global__ __launch_bounds__(kWG) void k_stiff(StiffArgs a) {
       if (act) {
         double fu = 0.0;
 #pragma unroll
-        for (int j = 0; j < 5; j++)
-          fu += o.cor[5 * e + j] * a.in_u[(size_t)o.ell_col[5 * e + j] * Bs + c];
+        for (int j = 0; j < 5; j++) fu = fma(o.cor[5 * e + j], a.in_u[(size_t)o.ell_col[5 * e + j] * Bs + c], fu);
         const int c0 = o.ecell[2 * e], c1 = o.ecell[2 * e + 1];
-        const double r = a.scale * (-fu + o.g * (a.in_eta[(size_t)c0 * Bs + c] - a.in_eta[(size_t)c1 * Bs + c]));
+        const double r = stiff_u(a.scale, fu, o.g, a.in_eta[(size_t)c0 * Bs + c], a.in_eta[(size_t)c1 * Bs + c]);
         double x0 = 0.0;
         if (a.addA_u) x0 += a.addA_u[ie];
         if (a.addB_u) x0 += a.addB_u[ie];
         a.r[ie] = r;
         a.out_u[ie] = x0;
         if (a.d0) {
-          a.d0[ie] = a.theta_inv * o.dinv[e] * r;
-          rr += r * r;
+          a.d0[ie] = stiff_d0(a.theta_inv, o.dinv[e], r);
+          rr = fma(r, r, rr);
         }
       }
       if (acc_on) accv = coef * a.in_u[ie];
@@ -208,12 +225,9 @@ __global__ __launch_bounds__(kWG) void k_stiff(StiffArgs a) {
       if (act) {
         double div = 0.0;
 #pragma unroll
-        for (int j = 0; j < 3; j++)
-          div += o.csgn[3 * t + j] * a.in_u[(size_t)o.cedge[3 * t + j] * Bs + c];
-        double v = a.scale * (-o.H * div * o.inv_area[t]);
-        if (a.addA_eta) v += a.addA_eta[it];
-        if (a.addB_eta) v += a.addB_eta[it];
-        a.out_eta[it] = v;
+        for (int j = 0; j < 3; j++) div = fma((double)o.csgn[3 * t + j], a.in_u[(size_t)o.cedge[3 * t + j] * Bs + c], div);
+        a.out_eta[it] = stiff_eta(a.scale, o.H, div, o.inv_area[t], a.addA_eta ? a.addA_eta[it] : 0.0,
+                                  a.addB_eta ? a.addB_eta[it] : 0.0);
       }
       if (acc_on) acce = coef * a.in_eta[it];
     }
@@ -301,10 +315,11 @@ constexpr int kRingSlots = kHaloMax / kWG;  // ring rows per thread
 // reads work anyway (nothing reads their results), and the stores to global
 // memory are predicated (an inactive column; the threads past a ragged last
 // part, which work on a copy of its last row).
-template <int NSLOT>
+template <int NSLOT, bool SETUP>
 __global__ __launch_bounds__(kWG) void k_cheb_fused(ChebFusedArgs a) {
   const DevOps &o = a.ops;
   const int t = threadIdx.x;
+  if (SETUP) folded_check(a.chk, a.chk_blocks);
   if (a.prof && blockIdx.x == 0 && t == 0) {
     const bool on = a.colK[0] >= a.kneed;
     atomicAdd(&a.prof[a.last ? 2 : 0], on ? 1u : 0u);
@@ -316,8 +331,8 @@ __global__ __launch_bounds__(kWG) void k_cheb_fused(ChebFusedArgs a) {
   const int p = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   const int S = a.S;
   __shared__ double dl[2][kPartRows + kHaloMax];
-  __shared__ double red[kWG / 64];
-  double s2 = 0.0;
+  __shared__ double red[2][kWG / 64];
+  double s2 = 0.0, s0 = 0.0;
   if (p < o.hparts) {
     const int e0 = p * kPartRows;
     const bool own = e0 + t < o.ne;
@@ -329,27 +344,51 @@ __global__ __launch_bounds__(kWG) void k_cheb_fused(ChebFusedArgs a) {
 #pragma unroll
     for (int i = 0; i < kFusedMax - 1; i++) cnt[i] = o.ring_cnt[8 * p + i];
     const int wrow = __builtin_amdgcn_readfirstlane(t & ~63);  // the wave's first row in a slot
-    // first wave of loads: the own row (ELL slot 0 is the row itself, whose
-    // d is read once) and the ring rows' numbers
-    double m[5];
-    int col[5], lc[5];
+    constexpr int NS = NSLOT > 0 ? NSLOT : 1;
+    // first wave of loads: the own row (ELL slot 0 is the row itself) and
+    // the ring rows' numbers; with SETUP also the Coriolis row, the row's
+    // cells and the addends of x_0, and the part's depth row
+    double m[5], fc[5];
+    int col[5], lc[5], ec[2];
 #pragma unroll
     for (int j = 0; j < 5; j++) {
       col[j] = o.ell_col[5 * e + j];
       m[j] = o.mass[5 * e + j];
       lc[j] = o.hloc[(size_t)j * o.ne + e];
+      if (SETUP) fc[j] = o.cor[5 * e + j];
     }
-    double dv = a.d_in[e];
     const double dinv = o.dinv[e];
-    double x = a.x[e];
-    double r = a.r_in[e];
-    int g[NSLOT > 0 ? NSLOT : 1];
+    double dv = 0.0, x, r;
+    if (SETUP) {
+      ec[0] = o.ecell[2 * e];
+      ec[1] = o.ecell[2 * e + 1];
+      x = 0.0;
+      if (a.addA_u) x += a.addA_u[e];
+      if (a.addB_u) x += a.addB_u[e];
+    } else {
+      dv = a.d_in[e];
+      x = a.x[e];
+      r = a.r_in[e];
+    }
+    const int cell = p * a.cpp + t;
+    const bool cown = SETUP && t < a.cpp && cell < o.nc;
+    const int cc = cown ? cell : 0;
+    int cedge[3];
+    double csg[3], cia = 0.0;
+    if (SETUP) {
+#pragma unroll
+      for (int j = 0; j < 3; j++) {
+        cedge[j] = o.cedge[3 * cc + j];
+        csg[j] = (double)o.csgn[3 * cc + j];
+      }
+      cia = o.inv_area[cc];
+    }
+    int g[NS];
 #pragma unroll
     for (int q = 0; q < NSLOT; q++) g[q] = rrow[t + q * kWG];
     // second wave: the ring rows, the own row's gathers
-    double rm[NSLOT > 0 ? NSLOT : 1][5], rdinv[NSLOT > 0 ? NSLOT : 1], rr[NSLOT > 0 ? NSLOT : 1];
-    double dg[NSLOT > 0 ? NSLOT : 1];
-    int gc[NSLOT > 0 ? NSLOT : 1][5], rlc[NSLOT > 0 ? NSLOT : 1][5];
+    double rm[NS][5], rdinv[NS], rr[NS], dg[NS], rfc[NS][5];
+    int gc[NS][5], rlc[NS][5], rec[NS][2];
 #pragma unroll
     for (int q = 0; q < NSLOT; q++) {
       const int h = t + q * kWG;
@@ -357,26 +396,49 @@ __global__ __launch_bounds__(kWG) void k_cheb_fused(ChebFusedArgs a) {
 #pragma unroll
       for (int j = 0; j < 5; j++) {
         gc[q][j] = rlc[q][j] = 0;
-        rm[q][j] = 0.0;
+        rm[q][j] = rfc[q][j] = 0.0;
       }
+      rec[q][0] = rec[q][1] = 0;
       if (g[q] >= 0) {  // past the part's rings the list holds -1
 #pragma unroll
         for (int j = 0; j < 5; j++) {
           gc[q][j] = o.ell_col[5 * g[q] + j];
           rm[q][j] = o.mass[5 * g[q] + j];
           rlc[q][j] = rloc[5 * h + j];
+          if (SETUP) rfc[q][j] = o.cor[5 * g[q] + j];
         }
-        dg[q] = a.d_in[g[q]];
         rdinv[q] = o.dinv[g[q]];
-        rr[q] = a.r_in[g[q]];
+        if (SETUP) {
+          rec[q][0] = o.ecell[2 * g[q]];
+          rec[q][1] = o.ecell[2 * g[q] + 1];
+        } else {
+          dg[q] = a.d_in[g[q]];
+          rr[q] = a.r_in[g[q]];
+        }
       }
     }
-    double q0 = fma(m[0], dv, 0.0);
+    if (SETUP) {
+      // step 1 = the set-up: r_0, d_0 (own row), and the part's depth rows
+      double fu = 0.0;
 #pragma unroll
-    for (int j = 1; j < 5; j++) q0 = fma(m[j], a.d_in[col[j]], q0);
-    x += dv;
-    r -= q0;
-    if (S > 1) dl[0][t] = cheb_dir(a.c1[0], a.c2[0], dv, dinv, r);
+      for (int j = 0; j < 5; j++) fu = fma(fc[j], a.in_u[col[j]], fu);
+      r = stiff_u(a.scale, fu, o.g, a.in_eta[ec[0]], a.in_eta[ec[1]]);
+      s0 = fma(r, r, s0);
+      dl[0][t] = stiff_d0(a.theta_inv, dinv, r);
+      double div = 0.0;
+#pragma unroll
+      for (int j = 0; j < 3; j++) div = fma(csg[j], a.in_u[cedge[j]], div);
+      if (cown && act)
+        a.out_eta[cc] = stiff_eta(a.scale, o.H, div, cia, a.addA_eta ? a.addA_eta[cc] : 0.0,
+                                  a.addB_eta ? a.addB_eta[cc] : 0.0);
+    } else {
+      double q0 = fma(m[0], dv, 0.0);
+#pragma unroll
+      for (int j = 1; j < 5; j++) q0 = fma(m[j], a.d_in[col[j]], q0);
+      x += dv;
+      r -= q0;
+      if (S > 1) dl[0][t] = cheb_dir(a.c1[0], a.c2[0], dv, dinv, r);
+    }
     // third wave: the ring rows' gathers; step 1 on rings 1..S-1 (ring row
     // h = t + q kWG stays in slot q of thread t, its matrix row, local
     // columns, diagonal and residual in registers, so that later steps touch
@@ -384,11 +446,21 @@ __global__ __launch_bounds__(kWG) void k_cheb_fused(ChebFusedArgs a) {
 #pragma unroll
     for (int q = 0; q < NSLOT; q++)
       if (g[q] >= 0) {
-        double qs = fma(rm[q][0], dg[q], 0.0);
+        double dn1;
+        if (SETUP) {
+          double fu = 0.0;
 #pragma unroll
-        for (int j = 1; j < 5; j++) qs = fma(rm[q][j], a.d_in[gc[q][j]], qs);
-        rr[q] -= qs;
-        dl[0][kPartRows + t + q * kWG] = cheb_dir(a.c1[0], a.c2[0], dg[q], rdinv[q], rr[q]);
+          for (int j = 0; j < 5; j++) fu = fma(rfc[q][j], a.in_u[gc[q][j]], fu);
+          rr[q] = stiff_u(a.scale, fu, o.g, a.in_eta[rec[q][0]], a.in_eta[rec[q][1]]);
+          dn1 = stiff_d0(a.theta_inv, rdinv[q], rr[q]);
+        } else {
+          double qs = fma(rm[q][0], dg[q], 0.0);
+#pragma unroll
+          for (int j = 1; j < 5; j++) qs = fma(rm[q][j], a.d_in[gc[q][j]], qs);
+          rr[q] -= qs;
+          dn1 = cheb_dir(a.c1[0], a.c2[0], dg[q], rdinv[q], rr[q]);
+        }
+        dl[0][kPartRows + t + q * kWG] = dn1;
       }
     for (int st = 1; st < S; st++) {
       __syncthreads();
@@ -396,11 +468,10 @@ __global__ __launch_bounds__(kWG) void k_cheb_fused(ChebFusedArgs a) {
       double *dn = dl[st & 1];
       const double c1 = a.c1[st], c2 = a.c2[st];
       // every LDS read of the step before its first write (the compiler
-      // cannot tell the two halves of dl apart)
-      // a wave skips the slots whose 64 rows all lie past the rings that
-      // take this step
+      // cannot tell the two halves of dl apart); a wave skips the slots whose
+      // 64 rows all lie past the rings that take this step
       const int nh = st + 1 < S ? cnt[S - 2 - st] : 0;
-      double dq[5], dr[NSLOT > 0 ? NSLOT : 1][5];
+      double dq[5], dr[NS][5];
 #pragma unroll
       for (int j = 0; j < 5; j++) dq[j] = dp[j ? lc[j] : t];
 #pragma unroll
@@ -416,7 +487,7 @@ __global__ __launch_bounds__(kWG) void k_cheb_fused(ChebFusedArgs a) {
       x += dv;
       r -= q;
       // rings 1..S-1-st take this step too (rows past them are not read)
-      double dnr[NSLOT > 0 ? NSLOT : 1];
+      double dnr[NS];
 #pragma unroll
       for (int k = 0; k < NSLOT; k++)
         if (k * kWG + wrow < nh) {
@@ -439,17 +510,26 @@ __global__ __launch_bounds__(kWG) void k_cheb_fused(ChebFusedArgs a) {
       else
         a.d_out[e] = cheb_dir(a.c1[S - 1], a.c2[S - 1], dv, dinv, r);
     }
+    if (!own) s0 = 0.0;
   }
-  if (a.last) {
-    // partial of r.r per workgroup, at the place of tile 0, column 0 of
-    // wg_partials' layout
+  if (a.last || SETUP) {
+    // partials of r.r (and with SETUP of r_0.r_0) per workgroup, at the
+    // place of tile 0, column 0 of wg_partials' layout
     s2 = wave_col_sum(s2, 1);
-    if ((t & 63) == 0) red[t >> 6] = s2;
+    s0 = wave_col_sum(s0, 1);
+    if ((t & 63) == 0) {
+      red[0][t >> 6] = s2;
+      red[1][t >> 6] = s0;
+    }
     __syncthreads();
     if (t == 0) {
-      double w = 0.0;
-      for (int i = 0; i < kWG / 64; i++) w += red[i];
-      a.part[(size_t)blockIdx.x * 64] = w;
+      double w = 0.0, w0 = 0.0;
+      for (int i = 0; i < kWG / 64; i++) {
+        w += red[0][i];
+        w0 += red[1][i];
+      }
+      if (a.last) a.part[(size_t)blockIdx.x * 64] = w;
+      if (SETUP) a.part_rr[(size_t)blockIdx.x * 64] = w0;
     }
   }
 }
@@ -1432,11 +1512,20 @@ int cheb_fused_grid(const DevOps &o) {
 }
 void launch_cheb_fused(const ChebFusedArgs &a, hipStream_t s) {
   const dim3 grid(cheb_fused_grid(a.ops));
+  if (a.setup) {
+    switch (a.slots[0]) {
+      case 0: hipLaunchKernelGGL((k_cheb_fused<0, true>), grid, dim3(kWG), 0, s, a); break;
+      case 1: hipLaunchKernelGGL((k_cheb_fused<1, true>), grid, dim3(kWG), 0, s, a); break;
+      case 2: hipLaunchKernelGGL((k_cheb_fused<2, true>), grid, dim3(kWG), 0, s, a); break;
+      default: hipLaunchKernelGGL((k_cheb_fused<kRingSlots, true>), grid, dim3(kWG), 0, s, a); break;
+    }
+    return;
+  }
   switch (a.slots[0]) {
-    case 0: hipLaunchKernelGGL(k_cheb_fused<0>, grid, dim3(kWG), 0, s, a); break;
-    case 1: hipLaunchKernelGGL(k_cheb_fused<1>, grid, dim3(kWG), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(k_cheb_fused<2>, grid, dim3(kWG), 0, s, a); break;
-    default: hipLaunchKernelGGL(k_cheb_fused<kRingSlots>, grid, dim3(kWG), 0, s, a); break;
+    case 0: hipLaunchKernelGGL((k_cheb_fused<0, false>), grid, dim3(kWG), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_cheb_fused<1, false>), grid, dim3(kWG), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_cheb_fused<2, false>), grid, dim3(kWG), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_cheb_fused<kRingSlots, false>), grid, dim3(kWG), 0, s, a); break;
   }
 }
 // The icosahedral meshes give P and P M widths 13 and 27 at every level;
