@@ -122,7 +122,7 @@ void Engine::mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_
   ra.Bs = Bs;
   ra.x = x;
   ra.r = r_;
-  ra.x32 = x32_;
+  ra.x32 = nullptr;  // not read by the first refinement (first = 1)
   ra.r32 = r32_;
   ra.d32 = d32_[0];
   ra.theta_inv = (float)(1.0 / cheb_theta_);
@@ -132,27 +132,35 @@ void Engine::mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_
   ra.max_wg = rb_.max_wg;
   ra.first = 1;
   launch_refine(ra, s_);
+  // inner solves in the three-term form: the refinement writes b = r32 and
+  // x_1 = D^-1 b / theta into the buffer `cur`; steps 1..kin-1 form
+  // x_{i+1} over x_{i-1}; the next refinement reads x_kin and writes the next
+  // round's x_1 into the other buffer
   Cheb32Args ca{};
   ca.ops = ops_->d;
   ca.Bs = Bs;
-  ca.x32 = x32_;
-  ca.r32 = r32_;
+  ca.b32 = r32_;
   ca.colK = colK;
   ca.kneed = kneed;
   const int kin = (int)mix_c1_.size();
+  float *cur = d32_[0], *prev = d32_[1];
   for (int o = 0; o < mixed_outer_; o++) {
-    for (int i = 0; i < kin; i++) {
-      ca.d_in = d32_[i & 1];
-      ca.d_out = d32_[(i + 1) & 1];
-      ca.c1 = (float)mix_c1_[i];
-      ca.c2 = (float)mix_c2_[i];
-      ca.first = i == 0 ? 1 : 0;
-      ca.last = i + 1 == kin ? 1 : 0;
+    for (int i = 1; i < kin; i++) {
+      ca.x_cur = cur;
+      ca.x_prev = prev;
+      ca.x_next = prev;
+      ca.c1 = (float)mix_c1_[i - 1];
+      ca.c2 = (float)mix_c2_[i - 1];
+      ca.zero_prev = i == 1 ? 1 : 0;
       launch_cheb32_iter(ca, s_);
+      std::swap(cur, prev);
     }
     ra.first = 0;
     ra.last = o + 1 == mixed_outer_ ? 1 : 0;
+    ra.x32 = cur;
+    ra.d32 = prev;  // the next x_1, beside the x_kin this kernel gathers
     launch_refine(ra, s_);
+    std::swap(cur, prev);
   }
   defer_check(Bs, nwg_init, colK, kneed);
   stats.solves++;
@@ -466,7 +474,6 @@ void Engine::plan_common(int BsMax) {
   const int tiles = tiles_of(BsMax);
   const size_t ebs = (size_t)ne_ * BsMax;
   if (mixed()) {
-    x32_ = ar_.take<float>(ebs);
     r32_ = ar_.take<float>(ebs);
     d32_[0] = ar_.take<float>(ebs);
     d32_[1] = ar_.take<float>(ebs);

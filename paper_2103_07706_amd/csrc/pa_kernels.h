@@ -172,22 +172,23 @@ struct LpDirArgs {
   int kneed;
 };
 
-// FP32 inner Chebyshev step (mixed precision): x32 (+)= d, r32 -= M32 d,
-// d' = c1 d + c2 D^-1 r32, all in FP32.
+// FP32 inner Chebyshev step (mixed precision), three-term form:
+// x_{i+1} = x_i + c1 (x_i - x_{i-1}) + c2 D^-1 (b - M32 x_i), all in FP32.
 struct Cheb32Args {
   DevOps ops;
   int Bs;
-  float *x32, *r32;
-  const float *d_in;
-  float *d_out;
+  const float *x_cur, *x_prev;  // x_i (gathered), x_{i-1} (own row only)
+  float *x_next;                // x_{i+1}; may alias x_prev
+  const float *b32;             // right-hand side
   float c1, c2;
   const int *colK;
-  int kneed, first, last;
+  int kneed, zero_prev;         // zero_prev: x_{i-1} = 0 (not read)
 };
 
 // FP64 refinement: x += x32, r -= M x32 (FP64 matrix), then FP32 copies for
-// the next inner solve: r32 = r, d32 = D^-1 r32 / theta.  first = 1: only the
-// conversion (x32 not yet formed).  last = 1: partials of r.r, no copies.
+// the next inner solve: its right-hand side r32 = r and its first iterate
+// d32 = D^-1 r32 / theta.  first = 1: only the conversion (x32 not yet
+// formed, not read).  last = 1: partials of r.r, no copies.
 struct RefineArgs {
   DevOps ops;
   int Bs;

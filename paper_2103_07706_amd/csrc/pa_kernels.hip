@@ -646,6 +646,13 @@ __global__ __launch_bounds__(kWG) void k_lp_dir(LpDirArgs a) {
 // FP32 vectors), the correction is added to x in FP64 and the residual
 // updated with the FP64 matrix, r -= M x32, so the outer residual is a true
 // FP64 residual; a final check compares it with the tolerance.
+// The inner FP32 solve in the three-term form of the same semi-iteration:
+// with d_i = x_{i+1} - x_i the step x += d_i, r -= M d_i,
+// d_{i+1} = c1 d_i + c2 D^-1 r becomes
+//   x_{i+1} = x_i + c1 (x_i - x_{i-1}) + c2 D^-1 (b - M x_i),
+// which reads x_i, x_{i-1} and b and writes x_{i+1} (a quarter of the bytes
+// of the two-term step that keeps x, r and d; the residual is formed in
+// registers).  x_1 = D^-1 b / theta comes from the refinement kernel.
 __global__ __launch_bounds__(kWG) void k_cheb32_iter(Cheb32Args a) {
   const Lane L = lane_map(a.Bs, a.ops.ne);
   const DevOps &o = a.ops;
@@ -654,13 +661,11 @@ __global__ __launch_bounds__(kWG) void k_cheb32_iter(Cheb32Args a) {
   for (int e = L.row0; e < L.rend; e += L.rstride) {
     float q = 0.0f;
 #pragma unroll
-    for (int j = 0; j < 5; j++) q += o.mass32[5 * e + j] * a.d_in[(size_t)o.ell_col[5 * e + j] * Bs + c];
+    for (int j = 0; j < 5; j++) q += o.mass32[5 * e + j] * a.x_cur[(size_t)o.ell_col[5 * e + j] * Bs + c];
     const size_t ie = (size_t)e * Bs + c;
-    const float d = a.d_in[ie];
-    a.x32[ie] = a.first ? d : a.x32[ie] + d;
-    const float r = a.r32[ie] - q;
-    a.r32[ie] = r;
-    if (!a.last) a.d_out[ie] = a.c1 * d + a.c2 * o.dinv32[e] * r;
+    const float xc = a.x_cur[ie];
+    const float xp = a.zero_prev ? 0.0f : a.x_prev[ie];
+    a.x_next[ie] = xc + a.c1 * (xc - xp) + a.c2 * o.dinv32[e] * (a.b32[ie] - q);
   }
 }
 
@@ -686,30 +691,23 @@ __global__ __launch_bounds__(kWG) void k_cheb32_iter4(Cheb32Args a) {
   if (a.colK[c0] < a.kneed && a.colK[c0 + 1] < a.kneed && a.colK[c0 + 2] < a.kneed &&
       a.colK[c0 + 3] < a.kneed)
     return;
-  const float4 *__restrict__ din = (const float4 *)a.d_in;
-  float4 *dout = (float4 *)a.d_out;
-  float4 *x = (float4 *)a.x32;
-  float4 *rr = (float4 *)a.r32;
+  const float4 *__restrict__ xcur = (const float4 *)a.x_cur;
+  const float4 *xprev = (const float4 *)a.x_prev;
+  const float4 *b4 = (const float4 *)a.b32;
+  float4 *xnext = (float4 *)a.x_next;
   for (int e = L.row0; e < L.rend; e += L.rstride) {
     float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 #pragma unroll
-    for (int j = 0; j < 5; j++) q = f4_fma(o.mass32[5 * e + j], din[(size_t)o.ell_col[5 * e + j] * Bq + cq], q);
+    for (int j = 0; j < 5; j++) q = f4_fma(o.mass32[5 * e + j], xcur[(size_t)o.ell_col[5 * e + j] * Bq + cq], q);
     const size_t ie = (size_t)e * Bq + cq;
-    const float4 d = din[ie];
-    if (a.first) {
-      x[ie] = d;
-    } else {
-      const float4 xv = x[ie];
-      x[ie] = make_float4(xv.x + d.x, xv.y + d.y, xv.z + d.z, xv.w + d.w);
-    }
-    const float4 r0 = rr[ie];
-    const float4 r = make_float4(r0.x - q.x, r0.y - q.y, r0.z - q.z, r0.w - q.w);
-    rr[ie] = r;
-    if (!a.last) {
-      const float g = o.dinv32[e];
-      dout[ie] = make_float4(a.c1 * d.x + a.c2 * g * r.x, a.c1 * d.y + a.c2 * g * r.y,
-                             a.c1 * d.z + a.c2 * g * r.z, a.c1 * d.w + a.c2 * g * r.w);
-    }
+    const float4 xc = xcur[ie];
+    const float4 xp = a.zero_prev ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : xprev[ie];
+    const float4 bv = b4[ie];
+    const float g = a.c2 * o.dinv32[e];
+    xnext[ie] = make_float4(xc.x + a.c1 * (xc.x - xp.x) + g * (bv.x - q.x),
+                            xc.y + a.c1 * (xc.y - xp.y) + g * (bv.y - q.y),
+                            xc.z + a.c1 * (xc.z - xp.z) + g * (bv.z - q.z),
+                            xc.w + a.c1 * (xc.w - xp.w) + g * (bv.w - q.w));
   }
 }
 
