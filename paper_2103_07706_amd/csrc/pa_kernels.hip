@@ -1098,12 +1098,17 @@ __global__ __launch_bounds__(kWG) void k_nl_upwind(NlArgs a) {
 //   C_i = |T| u(xbar) . grad^perp q_i + (s_i/|T|) int |u|^2/2
 //         - sum_a s_a int_{side a} (t_e . u~) q_i ds,
 //   q_i = (k x u) . phi_i (affine on T), eta2 = -sum_a s_a U_a (eta-b)_up / |T|.
+// UNI (blocks of at least 64 columns): a wave works on one cell, so the cell
+// index is made wave-uniform and the cell's tables load through the scalar
+// unit into scalar registers, which leaves room for more waves.
+template <bool UNI>
 __global__ __launch_bounds__(kWG) void k_nl_cell(NlArgs a) {
   const Lane L = lane_map(a.Bs, a.ops.nc);
   const DevOps &o = a.ops;
   const int c = L.col, Bs = a.Bs;
   const double gq = 0.28867513459481288225;  // 1/(2 sqrt 3)
-  for (int t = L.row0; t < L.rend; t += L.rstride) {
+  for (int tl = L.row0; tl < L.rend; tl += L.rstride) {
+    const int t = UNI ? __builtin_amdgcn_readfirstlane(tl) : tl;
     const double *g = o.cgeo + (size_t)t * kCellGeo;
     double p[3][3], k[3], gl[3][3], len[3];
 #pragma unroll
@@ -1167,24 +1172,8 @@ __global__ __launch_bounds__(kWG) void k_nl_cell(NlArgs a) {
     double kuv[3][3];
 #pragma unroll
     for (int j = 0; j < 3; j++) kxu(p[j], kuv[j]);
-    // k x u and upwind tangential velocity at the six Gauss points
-    double kug[3][2][3], xg[3][2][3], utg[3][2];
-#pragma unroll
-    for (int aa = 0; aa < 3; aa++) {
-      // global order a -> b is the cell's CCW order when s = +1
-      const int ia = s[aa] > 0 ? (aa + 1) % 3 : (aa + 2) % 3;
-      const int ib = s[aa] > 0 ? (aa + 2) % 3 : (aa + 1) % 3;
-      const size_t iedge = (size_t)ed[aa] * Bs + c;
-      utg[aa][0] = a.ut0[iedge];
-      utg[aa][1] = a.ut1[iedge];
-#pragma unroll
-      for (int gp = 0; gp < 2; gp++) {
-        const double xi = gp == 0 ? 0.5 - gq : 0.5 + gq;
-#pragma unroll
-        for (int d = 0; d < 3; d++) xg[aa][gp][d] = p[ia][d] + xi * (p[ib][d] - p[ia][d]);
-        kxu(xg[aa][gp], kug[aa][gp]);
-      }
-    }
+    // volume and kinetic-energy terms of C_i
+    double Cv[3];
 #pragma unroll
     for (int i = 0; i < 3; i++) {
       const double si = s[i] * inv2A;
@@ -1204,22 +1193,40 @@ __global__ __launch_bounds__(kWG) void k_nl_cell(NlArgs a) {
       const double gp0 = k[1] * gqv[2] - k[2] * gqv[1];
       const double gp1 = k[2] * gqv[0] - k[0] * gqv[2];
       const double gp2 = k[0] * gqv[1] - k[1] * gqv[0];
-      double Ci = A * (ubar[0] * gp0 + ubar[1] * gp1 + ubar[2] * gp2);
-      Ci += s[i] * ke / A;
+      Cv[i] = A * (ubar[0] * gp0 + ubar[1] * gp1 + ubar[2] * gp2);
+      Cv[i] += s[i] * ke / A;
+    }
+    // facet terms: side by side, the two Gauss points of a side formed once
+    // for the three test functions (k x u and the upwind tangential velocity
+    // at the point), so that few point values are live at a time
 #pragma unroll
-      for (int aa = 0; aa < 3; aa++) {
-        double f = 0.0;
+    for (int aa = 0; aa < 3; aa++) {
+      // global order a -> b is the cell's CCW order when s = +1
+      const int ia = s[aa] > 0 ? (aa + 1) % 3 : (aa + 2) % 3;
+      const int ib = s[aa] > 0 ? (aa + 2) % 3 : (aa + 1) % 3;
+      const size_t iedge = (size_t)ed[aa] * Bs + c;
+      const double utg[2] = {a.ut0[iedge], a.ut1[iedge]};
+      double f[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-        for (int gp = 0; gp < 2; gp++) {
+      for (int gp = 0; gp < 2; gp++) {
+        const double xi = gp == 0 ? 0.5 - gq : 0.5 + gq;
+        double xg[3], kug[3];
+#pragma unroll
+        for (int d = 0; d < 3; d++) xg[d] = p[ia][d] + xi * (p[ib][d] - p[ia][d]);
+        kxu(xg, kug);
+#pragma unroll
+        for (int i = 0; i < 3; i++) {
           double qv = 0.0;
 #pragma unroll
-          for (int d = 0; d < 3; d++) qv += kug[aa][gp][d] * (xg[aa][gp][d] - p[i][d]);
-          f += utg[aa][gp] * qv * si;
+          for (int d = 0; d < 3; d++) qv += kug[d] * (xg[d] - p[i][d]);
+          f[i] += utg[gp] * qv * (s[i] * inv2A);
         }
-        Ci -= s[aa] * 0.5 * len[aa] * f;
       }
-      a.C[((size_t)3 * t + i) * Bs + c] = Ci;
+#pragma unroll
+      for (int i = 0; i < 3; i++) Cv[i] -= s[aa] * 0.5 * len[aa] * f[i];
     }
+#pragma unroll
+    for (int i = 0; i < 3; i++) a.C[((size_t)3 * t + i) * Bs + c] = Cv[i];
     // depth: upwind (eta - b) on every side
     const size_t it = (size_t)t * Bs + c;
     double r = 0.0;
@@ -1576,7 +1583,10 @@ void launch_nl_upwind(const NlArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_nl_upwind, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
 }
 void launch_nl_cell(const NlArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_nl_cell, rows_grid(a.ops.nc, a.Bs), dim3(kWG), 0, s, a);
+  if (a.Bs >= 64)
+    hipLaunchKernelGGL(k_nl_cell<true>, rows_grid(a.ops.nc, a.Bs), dim3(kWG), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_nl_cell<false>, rows_grid(a.ops.nc, a.Bs), dim3(kWG), 0, s, a);
 }
 void launch_nl_gather(const GatherArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_nl_gather, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
