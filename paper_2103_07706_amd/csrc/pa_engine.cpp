@@ -116,7 +116,7 @@ void Engine::plan_cheb() {
 
 // Mixed-precision mass solve (FP32 inner Chebyshev, FP64 refinement); the
 // set-up kernel wrote r_0, x_0 and the partials of |r_0|^2 (partA).
-void Engine::mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_init) {
+void Engine::mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_init, bool prepared) {
   RefineArgs ra{};
   ra.ops = ops_->d;
   ra.Bs = Bs;
@@ -131,7 +131,7 @@ void Engine::mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_
   ra.part = chk_last_[chk_par_];
   ra.max_wg = rb_.max_wg;
   ra.first = 1;
-  launch_refine(ra, s_);
+  if (!prepared) launch_refine(ra, s_);
   // inner solves in the three-term form: the refinement writes b = r32 and
   // x_1 = D^-1 b / theta into the buffer `cur`; steps 1..kin-1 form
   // x_{i+1} over x_{i-1}; the next refinement reads x_kin and writes the next
@@ -219,7 +219,7 @@ void Engine::flush_check() {
 // narrower blocks, whose steps are launch-latency bound, take FP64 steps.
 void Engine::mass_solve(double *x, int Bs, const int *colK, int kneed, int nwg_init) {
   if (mixed() && Bs >= launch_tuning().mixed_min_cols)
-    mixed_solve(x, Bs, colK, kneed, nwg_init);
+    mixed_solve(x, Bs, colK, kneed, nwg_init, false);
   else if (cheb() || mixed())
     cheb_solve(x, Bs, colK, kneed, nwg_init);
   else
@@ -930,14 +930,25 @@ void Engine::nonlinear_block(Blk E, Blk Y, const int *colK) {
   gth.st = st_;
   gth.rb = rb_;
   gth.max_wg = rb_.max_wg;
+  const bool refined = mixed() && E.Bs >= launch_tuning().mixed_min_cols;
   if (cheb() || mixed()) {
-    gth.d0 = p_;
-    gth.theta_inv = 1.0 / cheb_theta_;
+    if (refined) {
+      // the gather writes the first refinement's outputs
+      gth.r32 = r32_;
+      gth.x1_32 = d32_[0];
+      gth.theta_inv32 = (float)(1.0 / cheb_theta_);
+    } else {
+      gth.d0 = p_;
+      gth.theta_inv = 1.0 / cheb_theta_;
+    }
     gth.part_rr = chk_init_[chk_par_];
     take_check(gth.chk, gth.chk_blocks, launch_rows_grid(ne_, E.Bs) * tiles_of(E.Bs));
   }
   launch_nl_gather(gth, s_);
-  mass_solve(Y.p, E.Bs, colK, 0, launch_rows_grid(ne_, E.Bs));
+  if (refined)
+    mixed_solve(Y.p, E.Bs, colK, 0, launch_rows_grid(ne_, E.Bs), true);
+  else
+    mass_solve(Y.p, E.Bs, colK, 0, launch_rows_grid(ne_, E.Bs));
 }
 
 // ------------------------------------------------------------- exponential

@@ -123,7 +123,7 @@ class Engine {
   void flush_check();
   bool cheb() const { return cfg_.solver == PA_SOLVER_CHEBYSHEV; }
   bool mixed() const { return cfg_.precision == PA_FP32_REFINED; }
-  void mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_init);
+  void mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_init, bool prepared);
   std::vector<double> mix_c1_, mix_c2_;
   int mixed_outer_ = 0;
   float *r32_ = nullptr, *d32_[2] = {nullptr, nullptr};

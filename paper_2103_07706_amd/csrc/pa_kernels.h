@@ -245,7 +245,12 @@ struct GatherArgs {
   double *r, *x;
   double *d0;
   double theta_inv;
-  double *part_rr;
+  // FP32-refined solve next: its first inner right-hand side r32 = r and
+  // first iterate x1_32 = D^-1 r32 / theta (what the first refinement
+  // kernel would write); d0 is then not written
+  float *r32, *x1_32;
+  float theta_inv32;
+  double *part_rr;  // partials of r.r (solves with a residual check)
   int max_wg;
   const int *colK;
   int kneed;

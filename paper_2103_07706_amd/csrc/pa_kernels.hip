@@ -238,7 +238,7 @@ __global__ __launch_bounds__(kWG) void k_stiff(StiffArgs a) {
     }
   }
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) a.st.cnt[1] = 0;
-  if (a.d0) {
+  if (a.part_rr) {
     double v[1] = {rr};
     wg_partials<1>(L, v, a.part_rr, a.max_wg);
   }
@@ -1255,14 +1255,17 @@ __global__ __launch_bounds__(kWG) void k_nl_gather(GatherArgs a) {
       const double r = a.C[(size_t)o.cidx[2 * e] * Bs + c] + a.C[(size_t)o.cidx[2 * e + 1] * Bs + c];
       a.r[ie] = r;
       a.x[ie] = 0.0;
-      if (a.d0) {
-        a.d0[ie] = a.theta_inv * o.dinv[e] * r;
-        rr += r * r;
+      if (a.d0) a.d0[ie] = a.theta_inv * o.dinv[e] * r;
+      if (a.r32) {
+        const float r32 = (float)r;
+        a.r32[ie] = r32;
+        a.x1_32[ie] = a.theta_inv32 * o.dinv32[e] * r32;
       }
+      if (a.part_rr) rr += r * r;
     }
   }
   if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) a.st.cnt[1] = 0;
-  if (a.d0) {
+  if (a.part_rr) {
     double v[1] = {rr};
     wg_partials<1>(L, v, a.part_rr, a.max_wg);
   }
