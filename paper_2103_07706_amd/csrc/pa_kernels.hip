@@ -403,7 +403,7 @@ __global__ __launch_bounds__(kWG) void k_cheb_fused(ChebFusedArgs a) {
 #pragma unroll
         for (int j = 0; j < 5; j++) {
           gc[q][j] = o.ell_col[5 * g[q] + j];
-          rm[q][j] = o.mass[5 * g[q] + j];
+          if (!SETUP) rm[q][j] = o.mass[5 * g[q] + j];
           rlc[q][j] = rloc[5 * h + j];
           if (SETUP) rfc[q][j] = o.cor[5 * g[q] + j];
         }
@@ -462,6 +462,16 @@ __global__ __launch_bounds__(kWG) void k_cheb_fused(ChebFusedArgs a) {
         }
         dl[0][kPartRows + t + q * kWG] = dn1;
       }
+    // with SETUP the ring rows' mass rows load only now, after the Coriolis
+    // rows are done with (fewer registers live at once)
+    if (SETUP) {
+#pragma unroll
+      for (int q = 0; q < NSLOT; q++)
+        if (g[q] >= 0) {
+#pragma unroll
+          for (int j = 0; j < 5; j++) rm[q][j] = o.mass[5 * g[q] + j];
+        }
+    }
     for (int st = 1; st < S; st++) {
       __syncthreads();
       const double *dp = dl[(st - 1) & 1];
