@@ -282,7 +282,17 @@ def main():
         if args.autotune:
             tune = ops.autotune(avg, U, cfg, cache=args.tune_cache)
         if lmin is not None:
-            pa.set_launch_tune(lp_min_cols=lmin)
+            # the autotuner chose the shape with its own learned-step
+            # threshold; with the threshold fixed, the rows per thread of the
+            # (now learned) narrow solves are chosen again by timing
+            best = None
+            for rpt in (1, 2, 4):
+                pa.set_launch_tune(lp_min_cols=lmin, narrow_rows_per_thread=rpt)
+                ops.phase_avg_rhs(avg, U, cfg, out=out)
+                ms = min(ops.phase_avg_rhs(avg, U, cfg, out=out)[1]["device_ms"] for _ in range(2))
+                if best is None or ms < best[0]:
+                    best = (ms, rpt)
+            pa.set_launch_tune(lp_min_cols=lmin, narrow_rows_per_thread=best[1])
             tune = dict(tune or {}, **pa.get_launch_tune())
         print(f"form {name} launch tune {tune}", file=sys.stderr, flush=True)
         elapsed, stats = measure(ops, avg, U, cfg, out, args.steps, args.warmup)
