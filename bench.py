@@ -49,7 +49,7 @@ def parse():
                     help="JSON file of launch shapes: read when it holds the problem, else written")
     ap.add_argument("--lp-steps", dest="lp_steps", type=int, default=200)
     ap.add_argument("--cpu-baseline", dest="cpu", type=int, default=1)
-    ap.add_argument("--cpu-terms", type=int, default=4)
+    ap.add_argument("--cpu-terms", type=int, default=32)
     return ap.parse_args()
 
 
