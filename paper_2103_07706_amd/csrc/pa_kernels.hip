@@ -8,10 +8,14 @@
 // column l % CT.  Columns carry per-column state (CG scalars, activity), so
 // solves of different columns are independent and converged columns freeze.
 //
-// Per-column sums (CG dot products) are deterministic: wave shuffles, then
-// LDS across the four waves, then per-workgroup partials reduced in a fixed
-// order by the last workgroup of a group of 32 and finally by the last group
-// (ticket counters, no floating-point atomics).
+// Per-column sums (CG dot products, residual norms) are deterministic: wave
+// shuffles, then LDS across the four waves, then per-workgroup partials with
+// plain stores, summed in a fixed order by a later kernel (no floating-point
+// atomics).
+//
+// The single-column Jacobi Chebyshev solves run several steps per launch on
+// 256-row parts with rings of halo rows (k_cheb_fused; the row parts and
+// rings are built with the operators).
 #include <hip/hip_runtime.h>
 
 #include <hip/hip_ext.h>
