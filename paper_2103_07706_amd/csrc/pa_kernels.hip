@@ -1012,6 +1012,133 @@ __global__ __launch_bounds__(kWG) void k_combine(CombineArgs a) {
   }
 }
 
+// Single-chunk forms of k_combine and k_reduce_terms (Kmax < kKC, G <= 64,
+// the usual shapes): the coefficients are staged once per workgroup, and
+// each workgroup walks its tiles with the next tile's loads in flight
+// during the current tile's arithmetic (registers, then LDS).  Same
+// arithmetic in the same order as the chunked forms.
+__global__ __launch_bounds__(kWG) void k_combine1(CombineArgs a) {
+  __shared__ double bt[kKC][kTT];
+  __shared__ double cs[kKC][64];
+  const int tb = threadIdx.x & 15, mb = threadIdx.x >> 4;
+  const long total = (long)a.nrows * a.BsR;
+  const long ntiles = (total + kTT - 1) / kTT;
+  const int nk = a.kmax + 1;
+  for (int idx = threadIdx.x; idx < kKC * 64; idx += kWG) {
+    const int kk = idx / 64, j = idx % 64;
+    cs[kk][j] = kk < nk && j < a.G ? a.cf[(size_t)kk * a.G + j] : 0.0;
+  }
+  double vb[kKC * kTT / kWG];
+  auto fetch = [&](long tile) {
+    const long t0 = tile * kTT;
+#pragma unroll
+    for (int r = 0; r < kKC * kTT / kWG; r++) {
+      const int idx = threadIdx.x + r * kWG, kk = idx / kTT, i = idx % kTT;
+      vb[r] = tile < ntiles && kk < nk && t0 + i < total ? a.basis[(size_t)kk * a.basis_stride + t0 + i] : 0.0;
+    }
+  };
+  fetch(blockIdx.x);
+  for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long t0 = tile * kTT;
+    const int nt = (int)min((long)kTT, total - t0);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kKC * kTT / kWG; r++) {
+      const int idx = threadIdx.x + r * kWG;
+      bt[idx / kTT][idx % kTT] = vb[r];
+    }
+    __syncthreads();
+    fetch(tile + gridDim.x);
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+      for (int j = 0; j < 4; j++) acc[i][j] = 0.0;
+    for (int kk = 0; kk < nk; kk++) {
+      double b[4], c[4];
+#pragma unroll
+      for (int i = 0; i < 4; i++) b[i] = bt[kk][tb + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; j++) c[j] = cs[kk][4 * mb + j];
+#pragma unroll
+      for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[i][j] = fma(c[j], b[i], acc[i][j]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+      const int ti = tb + 16 * i;
+      if (ti < nt) {
+        const long t = t0 + ti;
+        const bool on = (int)(t % a.BsR) < a.members;
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          const int m = 4 * mb + j;
+          if (m < a.G) a.E[t * a.G + m] = on ? acc[i][j] : 0.0;
+        }
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kWG) void k_reduce_terms1(ReduceTermsArgs a) {
+  __shared__ double ys[kTT][65];
+  __shared__ double cs[kKC][65];
+  const int tb = threadIdx.x & 15, kb = threadIdx.x >> 4;
+  const long total = (long)a.nrows * a.BsZ;
+  const long ntiles = (total + kTT - 1) / kTT;
+  const int nk = a.kmax + 1, nm = a.G;
+  for (int idx = threadIdx.x; idx < kKC * 64; idx += kWG) {
+    const int kk = idx / 64, j = idx % 64;
+    cs[kk][j] = kk < nk && j < nm ? a.cb[(size_t)kk * a.G + j] : 0.0;
+  }
+  double vy[kTT * 64 / kWG];
+  auto fetch = [&](long tile) {
+    const long t0 = tile * kTT;
+#pragma unroll
+    for (int r = 0; r < kTT * 64 / kWG; r++) {
+      const int idx = threadIdx.x + r * kWG, i = idx / 64, j = idx % 64;
+      vy[r] = tile < ntiles && t0 + i < total && j < nm ? a.Y[(t0 + i) * a.G + j] : 0.0;
+    }
+  };
+  fetch(blockIdx.x);
+  for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const long t0 = tile * kTT;
+    const int nt = (int)min((long)kTT, total - t0);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kTT * 64 / kWG; r++) {
+      const int idx = threadIdx.x + r * kWG;
+      ys[idx / 64][idx % 64] = vy[r];
+    }
+    __syncthreads();
+    fetch(tile + gridDim.x);
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+      for (int j = 0; j < 4; j++) acc[i][j] = 0.0;
+    for (int m = 0; m < nm; m++) {
+      double y[4], c[4];
+#pragma unroll
+      for (int i = 0; i < 4; i++) y[i] = ys[tb + 16 * i][m];
+#pragma unroll
+      for (int j = 0; j < 4; j++) c[j] = cs[kb + 16 * j][m];
+#pragma unroll
+      for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[i][j] = fma(c[j], y[i], acc[i][j]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+      if (kb + 16 * j < nk) {
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+          if (tb + 16 * i < nt) a.Z[(size_t)(kb + 16 * j) * a.zstride + t0 + tb + 16 * i] = acc[i][j];
+      }
+  }
+}
+
 // Z[k][t] = sum_m cb[k][m] Y[t][m] (backward terms reduced to one series per
 // member).  A workgroup stages kTT rows Y[t][.] (m in chunks of 64) and cb
 // for a chunk of kKC values of k in LDS, both padded to 65 doubles a row
@@ -1495,6 +1622,12 @@ int grid_tiles(size_t n) {
   const size_t g = (n + kTT - 1) / kTT;
   return (int)(g < 2048 ? (g > 0 ? g : 1) : 2048);
 }
+// the pipelined single-chunk forms: two workgroups per CU, each walking
+// several tiles
+int grid_tiles_pipe(size_t n) {
+  const size_t g = (n + kTT - 1) / kTT;
+  return (int)(g < 512 ? (g > 0 ? g : 1) : 512);
+}
 dim3 rows_grid(int rows, int Bs) { return dim3(grid_rows(rows, Bs), (Bs + 63) / 64); }
 }  // namespace
 
@@ -1591,10 +1724,16 @@ void launch_cg_iter(const CgArgs &a, hipStream_t s) {
   launch_timed(k_cg_iter, rows_grid(a.ops.ne, a.Bs), s, a);
 }
 void launch_combine(const CombineArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_combine, dim3(grid_tiles((size_t)a.nrows * a.BsR)), dim3(kWG), 0, s, a);
+  if (a.kmax < kKC && a.G <= 64)
+    hipLaunchKernelGGL(k_combine1, dim3(grid_tiles_pipe((size_t)a.nrows * a.BsR)), dim3(kWG), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_combine, dim3(grid_tiles((size_t)a.nrows * a.BsR)), dim3(kWG), 0, s, a);
 }
 void launch_reduce_terms(const ReduceTermsArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_terms, dim3(grid_tiles((size_t)a.nrows * a.BsZ)), dim3(kWG), 0, s, a);
+  if (a.kmax < kKC && a.G <= 64)
+    hipLaunchKernelGGL(k_reduce_terms1, dim3(grid_tiles_pipe((size_t)a.nrows * a.BsZ)), dim3(kWG), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_reduce_terms, dim3(grid_tiles((size_t)a.nrows * a.BsZ)), dim3(kWG), 0, s, a);
 }
 void launch_nl_upwind(const NlArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_nl_upwind, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
