@@ -1013,14 +1013,22 @@ __global__ __launch_bounds__(kWG) void k_combine(CombineArgs a) {
 }
 
 // Single-chunk forms of k_combine and k_reduce_terms (Kmax < kKC, G <= 64,
-// the usual shapes): the coefficients are staged once per workgroup, and
-// each workgroup walks its tiles with the next tile's loads in flight
-// during the current tile's arithmetic (registers, then LDS).  Same
-// arithmetic in the same order as the chunked forms.
+// the usual shapes), on the matrix cores: both are dense contractions over
+// a tile of 64 values of t, done as 16 x 16 x 4 FP64 MFMA blocks (each
+// operand value read once from LDS per block instead of once per
+// multiply-add).  The coefficients are staged once per workgroup, and each
+// workgroup walks its tiles with the next tile's loads in flight during the
+// current tile's arithmetic.  Lane layout of v_mfma_f64_16x16x4f64 (lane l):
+// A[l % 16][l / 16], B[l / 16][l % 16], result register r holds
+// D[4 r + l / 16][l % 16].  The sums run over k (or m) in blocks of four.
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+// E[t][m] = sum_k R_k[t] cf[k][m]: wave w takes t0 + 16 w .. + 15 and all
+// four 16-column blocks of m.
 __global__ __launch_bounds__(kWG) void k_combine1(CombineArgs a) {
   __shared__ double bt[kKC][kTT];
   __shared__ double cs[kKC][64];
-  const int tb = threadIdx.x & 15, mb = threadIdx.x >> 4;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const long total = (long)a.nrows * a.BsR;
   const long ntiles = (total + kTT - 1) / kTT;
   const int nk = a.kmax + 1;
@@ -1038,9 +1046,9 @@ __global__ __launch_bounds__(kWG) void k_combine1(CombineArgs a) {
     }
   };
   fetch(blockIdx.x);
+  const int nk4 = (nk + 3) & ~3;
   for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const long t0 = tile * kTT;
-    const int nt = (int)min((long)kTT, total - t0);
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kKC * kTT / kWG; r++) {
@@ -1049,42 +1057,37 @@ __global__ __launch_bounds__(kWG) void k_combine1(CombineArgs a) {
     }
     __syncthreads();
     fetch(tile + gridDim.x);
-    double acc[4][4];
+    d4v acc[4];
 #pragma unroll
-    for (int i = 0; i < 4; i++)
+    for (int mb = 0; mb < 4; mb++) acc[mb] = d4v{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < nk4; k0 += 4) {
+      const double av = bt[k0 + (lane >> 4)][16 * w + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 4; j++) acc[i][j] = 0.0;
-    for (int kk = 0; kk < nk; kk++) {
-      double b[4], c[4];
-#pragma unroll
-      for (int i = 0; i < 4; i++) b[i] = bt[kk][tb + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; j++) c[j] = cs[kk][4 * mb + j];
-#pragma unroll
-      for (int i = 0; i < 4; i++)
-#pragma unroll
-        for (int j = 0; j < 4; j++) acc[i][j] = fma(c[j], b[i], acc[i][j]);
+      for (int mb = 0; mb < 4; mb++)
+        acc[mb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, cs[k0 + (lane >> 4)][16 * mb + (lane & 15)], acc[mb], 0, 0, 0);
     }
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
-      const int ti = tb + 16 * i;
-      if (ti < nt) {
-        const long t = t0 + ti;
+    for (int r = 0; r < 4; r++) {
+      const long t = t0 + 16 * w + 4 * r + (lane >> 4);
+      if (t < total) {
         const bool on = (int)(t % a.BsR) < a.members;
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
-          const int m = 4 * mb + j;
-          if (m < a.G) a.E[t * a.G + m] = on ? acc[i][j] : 0.0;
+        for (int mb = 0; mb < 4; mb++) {
+          const int m = 16 * mb + (lane & 15);
+          if (m < a.G) a.E[t * a.G + m] = on ? acc[mb][r] : 0.0;
         }
       }
     }
   }
 }
 
+// Z[k][t] = sum_m cb[k][m] Y[t][m]: wave w takes t0 + 16 w .. + 15 and all
+// 16-row blocks of k (D^T = cb Y^T, so that each result row of k leaves as
+// 16 consecutive values of t).
 __global__ __launch_bounds__(kWG) void k_reduce_terms1(ReduceTermsArgs a) {
   __shared__ double ys[kTT][65];
   __shared__ double cs[kKC][65];
-  const int tb = threadIdx.x & 15, kb = threadIdx.x >> 4;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const long total = (long)a.nrows * a.BsZ;
   const long ntiles = (total + kTT - 1) / kTT;
   const int nk = a.kmax + 1, nm = a.G;
@@ -1102,9 +1105,10 @@ __global__ __launch_bounds__(kWG) void k_reduce_terms1(ReduceTermsArgs a) {
     }
   };
   fetch(blockIdx.x);
+  const int nm4 = (nm + 3) & ~3;
+  const int nkb = (nk + 15) >> 4;  // 16-row blocks of k (at most 4)
   for (long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const long t0 = tile * kTT;
-    const int nt = (int)min((long)kTT, total - t0);
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kTT * 64 / kWG; r++) {
@@ -1113,28 +1117,25 @@ __global__ __launch_bounds__(kWG) void k_reduce_terms1(ReduceTermsArgs a) {
     }
     __syncthreads();
     fetch(tile + gridDim.x);
-    double acc[4][4];
+    d4v acc[4];
 #pragma unroll
-    for (int i = 0; i < 4; i++)
+    for (int kb = 0; kb < 4; kb++) acc[kb] = d4v{0.0, 0.0, 0.0, 0.0};
+    for (int m0 = 0; m0 < nm4; m0 += 4) {
+      const double bv = ys[16 * w + (lane & 15)][m0 + (lane >> 4)];
 #pragma unroll
-      for (int j = 0; j < 4; j++) acc[i][j] = 0.0;
-    for (int m = 0; m < nm; m++) {
-      double y[4], c[4];
-#pragma unroll
-      for (int i = 0; i < 4; i++) y[i] = ys[tb + 16 * i][m];
-#pragma unroll
-      for (int j = 0; j < 4; j++) c[j] = cs[kb + 16 * j][m];
-#pragma unroll
-      for (int i = 0; i < 4; i++)
-#pragma unroll
-        for (int j = 0; j < 4; j++) acc[i][j] = fma(c[j], y[i], acc[i][j]);
+      for (int kb = 0; kb < 4; kb++)
+        if (kb < nkb)
+          acc[kb] = __builtin_amdgcn_mfma_f64_16x16x4f64(cs[16 * kb + (lane & 15)][m0 + (lane >> 4)], bv, acc[kb], 0, 0, 0);
     }
 #pragma unroll
-    for (int j = 0; j < 4; j++)
-      if (kb + 16 * j < nk) {
+    for (int kb = 0; kb < 4; kb++)
+      if (kb < nkb) {
 #pragma unroll
-        for (int i = 0; i < 4; i++)
-          if (tb + 16 * i < nt) a.Z[(size_t)(kb + 16 * j) * a.zstride + t0 + tb + 16 * i] = acc[i][j];
+        for (int r = 0; r < 4; r++) {
+          const int k = 16 * kb + 4 * r + (lane >> 4);
+          const long t = t0 + 16 * w + (lane & 15);
+          if (k < nk && t < total) a.Z[(size_t)k * a.zstride + t] = acc[kb][r];
+        }
       }
   }
 }
