@@ -308,7 +308,7 @@ def main():
         if head["learned"] and head["tune"]["lp_min_cols"] <= 4:
             cands = {"k_cheb_lp_iter": pa.PA_KERNEL_CHEB_LP_ITER}
         else:
-            cands = {"k_cheb_iter": pa.PA_KERNEL_CHEB_ITER}
+            cands = {"k_cheb_iter": pa.PA_KERNEL_CHEB_ITER, "k_cheb3_iter": pa.PA_KERNEL_CHEB3_ITER}
             if head["tune"]["fused_steps"] > 1:
                 cands["k_cheb_fused"] = pa.PA_KERNEL_CHEB_FUSED
     else:

@@ -437,7 +437,9 @@ void Engine::cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_i
       }
     }
     if (prof) bracket_end(2 * k - 1);
-  } else {
+  } else if (Bs == 1) {
+    // single column, one step per launch (the fused kernel does the same
+    // arithmetic several steps at a time)
     ChebArgs a{};
     a.ops = ops_->d;
     a.Bs = Bs;
@@ -458,6 +460,38 @@ void Engine::cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_i
       if (prof && i == 0) bracket_begin();
       launch_cheb_iter(a, s_);
     }
+    if (prof) bracket_end(k);
+  } else {
+    // blocks: three-term form on the increment y: y_1 = d_0 (set-up kernel,
+    // in p_), k - 1 steps to y_k, then the finishing launch (x += y_k and
+    // the residual)
+    Cheb3Args a{};
+    a.ops = ops_->d;
+    a.Bs = Bs;
+    a.b = r_;
+    a.x = x;
+    a.colK = colK;
+    a.kneed = kneed;
+    a.part = chk_last_[chk_par_];
+    a.max_wg = rb_.max_wg;
+    const bool prof = ctx_->prof_kernel == PA_KERNEL_CHEB3_ITER;
+    a.prof = prof ? st_.prof : nullptr;
+    a.prof_bytes = st_.prof_bytes;
+    double *cur = d[0], *prev = d[1];
+    if (prof) bracket_begin();
+    for (int i = 1; i < k; i++) {
+      a.y_cur = cur;
+      a.y_prev = prev;
+      a.y_next = prev;
+      a.c1 = c1[i - 1];
+      a.c2 = c2[i - 1];
+      a.zero_prev = i == 1 ? 1 : 0;
+      launch_cheb3_iter(a, s_);
+      std::swap(cur, prev);
+    }
+    a.y_cur = cur;
+    a.finish = 1;
+    launch_cheb3_iter(a, s_);
     if (prof) bracket_end(k);
   }
   if (lp) stats.precond = PA_PRECOND_LEARNED;
@@ -594,7 +628,7 @@ void Engine::finish() {
                                                (60.0 + 8.0 * (ops_->lp_wp + ops_->lp_wpm)) * work);
     // fused steps: summed by the kernel from the launches' own figures
     // (fused_bytes)
-    if (ctx_->prof_kernel == PA_KERNEL_CHEB_FUSED) {
+    if (ctx_->prof_kernel == PA_KERNEL_CHEB_FUSED || ctx_->prof_kernel == PA_KERNEL_CHEB3_ITER) {
       unsigned long long fb;
       std::memcpy(&fb, &h[10], sizeof(fb));
       ctx_->prof_bytes += (double)fb;

@@ -108,6 +108,27 @@ struct ChebArgs {
   int nodir;       // 1: update x and r only (the direction comes from another kernel)
 };
 
+// Jacobi Chebyshev solve of a block in three-term form on the increment y
+// of x (see k_cheb3_iter): a step forms
+//   y_{i+1} = y_i + c1 (y_i - y_{i-1}) + c2 D^-1 (b - M y_i)
+// (y_{i-1} = 0 when zero_prev; y_next may alias y_prev); the finishing
+// launch (finish = 1) adds x += y_cur and leaves partials of r.r with
+// r = b - M y_cur, the true residual of the solve.
+struct Cheb3Args {
+  DevOps ops;
+  int Bs;
+  const double *y_cur, *y_prev, *b;
+  double *y_next, *x;
+  double c1, c2;
+  const int *colK;
+  int kneed, zero_prev, finish;
+  double *part;
+  int max_wg;
+  unsigned *prof;                  // measurement hook: [0] active columns of steps,
+                                   // [1] launches, [2] active columns of finishes
+  unsigned long long *prof_bytes;  // algorithmic bytes of the launches added here
+};
+
 // S Jacobi Chebyshev steps of a single-column solve in one launch (see
 // k_cheb_fused), step s with (c1[s], c2[s]); r and d each move from an input
 // to an output buffer (other workgroups still read the inputs).
@@ -301,6 +322,7 @@ void launch_finalize(const FinArgs &a, hipStream_t s);
 void launch_stiff(const StiffArgs &a, hipStream_t s);
 void launch_cg_init(const CgArgs &a, hipStream_t s);
 void launch_cheb_iter(const ChebArgs &a, hipStream_t s);
+void launch_cheb3_iter(const Cheb3Args &a, hipStream_t s);
 void launch_cheb_fused(const ChebFusedArgs &a, hipStream_t s);
 int cheb_fused_grid(const DevOps &o);  // workgroups of k_cheb_fused (0: not available)
 void launch_cheb_check(const CheckArgs &a, hipStream_t s);

@@ -548,6 +548,49 @@ __global__ __launch_bounds__(kWG) void k_cheb_fused(ChebFusedArgs a) {
   }
 }
 
+// The Jacobi semi-iteration of a block in three-term form.  With y the
+// increment of x over x_0 (y_1 = d_0 from the set-up kernel) and
+// d_i = y_{i+1} - y_i, the two-term step (x += d, r -= M d,
+// d' = c1 d + c2 D^-1 r) becomes
+//   y_{i+1} = y_i + c1 (y_i - y_{i-1}) + c2 D^-1 (b - M y_i),  b = r_0,
+// which reads y_i, y_{i-1} and b and writes y_{i+1} (four vectors a step
+// against six); the residual b - M y_i is formed in registers.  The
+// finishing launch adds x += y_K and sums the true final residual.
+__global__ __launch_bounds__(kWG) void k_cheb3_iter(Cheb3Args a) {
+  const Lane L = lane_map(a.Bs, a.ops.ne);
+  const DevOps &o = a.ops;
+  const int c = L.col, Bs = a.Bs;
+  if (a.prof && blockIdx.x == 0 && threadIdx.x == 0) {
+    unsigned n = 0;
+    for (int j = 0; j < L.ct; j++) n += a.colK[L.tile * L.ct + j] >= a.kneed ? 1u : 0u;
+    atomicAdd(&a.prof[a.finish ? 2 : 0], n);
+    if (L.tile == 0) atomicAdd(&a.prof[1], 1u);
+    // per active column and row: y (and y_prev unless zero), b, y' or x in
+    // and out; per row and tile: the ELL row and (steps) the diagonal
+    const unsigned long long pc = a.finish ? 32 : (a.zero_prev ? 24 : 32);
+    atomicAdd(a.prof_bytes, (unsigned long long)o.ne * (pc * n + (a.finish ? 60 : 68)));
+  }
+  double sums[1] = {0.0};
+  if (a.colK[c] >= a.kneed) {
+    for (int e = L.row0; e < L.rend; e += L.rstride) {
+      const size_t ie = (size_t)e * Bs + c;
+      const double yc = a.y_cur[ie];
+      double q = fma(o.mass[5 * e], yc, 0.0);
+#pragma unroll
+      for (int j = 1; j < 5; j++) q = fma(o.mass[5 * e + j], a.y_cur[(size_t)o.ell_col[5 * e + j] * Bs + c], q);
+      const double r = a.b[ie] - q;
+      if (a.finish) {
+        a.x[ie] += yc;
+        sums[0] = fma(r, r, sums[0]);
+      } else {
+        const double yp = a.zero_prev ? 0.0 : a.y_prev[ie];
+        a.y_next[ie] = fma(a.c1, yc - yp, yc) + (a.c2 * o.dinv[e]) * r;
+      }
+    }
+  }
+  if (a.finish) wg_partials<1>(L, sums, a.part, a.max_wg);
+}
+
 // The same semi-iteration preconditioned by the learned P = G G^T:
 //   x += d_k,  r_{k+1} = r_k - M d_k,  d_{k+1} = c1 d_k + c2 P r_{k+1},
 // with P r_{k+1} formed as P r_k - (P M) d_k so that one kernel per step
@@ -1660,6 +1703,9 @@ void arm_launch_events(hipEvent_t e0, hipEvent_t e1) {
 bool launch_events_armed() { return g_ev0 != nullptr; }
 void launch_cheb_iter(const ChebArgs &a, hipStream_t s) {
   launch_timed(k_cheb_iter, rows_grid(a.ops.ne, a.Bs), s, a);
+}
+void launch_cheb3_iter(const Cheb3Args &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_cheb3_iter, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
 }
 int cheb_fused_grid(const DevOps &o) {
   if (o.hparts <= 0 || o.fused_max < 2) return 0;
