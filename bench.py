@@ -311,6 +311,10 @@ def main():
             cands = {"k_cheb_iter": pa.PA_KERNEL_CHEB_ITER, "k_cheb3_iter": pa.PA_KERNEL_CHEB3_ITER}
             if head["tune"]["fused_steps"] > 1:
                 cands["k_cheb_fused"] = pa.PA_KERNEL_CHEB_FUSED
+            if head["cfg"].precision == pa.PA_FP32_REFINED:
+                # FP32 steps of blocks: the four-column form on every block
+                # width the workloads use
+                cands["k_cheb32_iter4"] = pa.PA_KERNEL_CHEB32_ITER
     else:
         cands = {"k_cg_iter": pa.PA_KERNEL_CG_ITER}
     # the candidate with the most event time is the dominant kernel

@@ -242,7 +242,8 @@ int pa_diagnostics(pa_ctx *ctx, const pa_ops *ops, int B, const double *U_dev,
  * pa_ctx_profile_read returns the tally so far.  The calls made while the
  * hook is on fill it; reading needs no further synchronisation. */
 enum { PA_KERNEL_NONE = 0, PA_KERNEL_CG_ITER = 1, PA_KERNEL_CHEB_ITER = 2,
-       PA_KERNEL_CHEB_LP_ITER = 3, PA_KERNEL_CHEB_FUSED = 4, PA_KERNEL_CHEB3_ITER = 5 };
+       PA_KERNEL_CHEB_LP_ITER = 3, PA_KERNEL_CHEB_FUSED = 4, PA_KERNEL_CHEB3_ITER = 5,
+       PA_KERNEL_CHEB32_ITER = 6 };
 typedef struct {
   int64_t launches;   /* launches of the kernel */
   int64_t work_launches; /* launches that found active columns */

@@ -144,7 +144,11 @@ void Engine::mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_
   ca.kneed = kneed;
   const int kin = (int)mix_c1_.size();
   float *cur = d32_[0], *prev = d32_[1];
+  const bool prof = ctx_->prof_kernel == PA_KERNEL_CHEB32_ITER;
+  ca.prof = prof ? st_.prof : nullptr;
+  ca.prof_bytes = st_.prof_bytes;
   for (int o = 0; o < mixed_outer_; o++) {
+    if (prof && kin > 1) bracket_begin();
     for (int i = 1; i < kin; i++) {
       ca.x_cur = cur;
       ca.x_prev = prev;
@@ -155,6 +159,7 @@ void Engine::mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_
       launch_cheb32_iter(ca, s_);
       std::swap(cur, prev);
     }
+    if (prof && kin > 1) bracket_end(kin - 1);
     ra.first = 0;
     ra.last = o + 1 == mixed_outer_ ? 1 : 0;
     ra.x32 = cur;
@@ -628,7 +633,8 @@ void Engine::finish() {
                                                (60.0 + 8.0 * (ops_->lp_wp + ops_->lp_wpm)) * work);
     // fused steps: summed by the kernel from the launches' own figures
     // (fused_bytes)
-    if (ctx_->prof_kernel == PA_KERNEL_CHEB_FUSED || ctx_->prof_kernel == PA_KERNEL_CHEB3_ITER) {
+    if (ctx_->prof_kernel == PA_KERNEL_CHEB_FUSED || ctx_->prof_kernel == PA_KERNEL_CHEB3_ITER ||
+        ctx_->prof_kernel == PA_KERNEL_CHEB32_ITER) {
       unsigned long long fb;
       std::memcpy(&fb, &h[10], sizeof(fb));
       ctx_->prof_bytes += (double)fb;

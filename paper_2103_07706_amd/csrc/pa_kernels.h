@@ -204,6 +204,8 @@ struct Cheb32Args {
   float c1, c2;
   const int *colK;
   int kneed, zero_prev;         // zero_prev: x_{i-1} = 0 (not read)
+  unsigned *prof;               // measurement hook: [0] active columns, [1] launches
+  unsigned long long *prof_bytes;
 };
 
 // FP64 refinement: x += x32, r -= M x32 (FP64 matrix), then FP32 copies for

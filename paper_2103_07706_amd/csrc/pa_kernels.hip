@@ -710,10 +710,25 @@ __global__ __launch_bounds__(kWG) void k_lp_dir(LpDirArgs a) {
 // which reads x_i, x_{i-1} and b and writes x_{i+1} (a quarter of the bytes
 // of the two-term step that keeps x, r and d; the residual is formed in
 // registers).  x_1 = D^-1 b / theta comes from the refinement kernel.
+// Measurement hook of the FP32 steps: per active column and row x_i,
+// x_{i-1} (unless zero), b and x_{i+1} in FP32; per row the FP32 ELL row
+// (5 columns, 5 values) and diagonal.
+__device__ inline void cheb32_prof(const Cheb32Args &a, int ncols_active) {
+  atomicAdd(&a.prof[0], (unsigned)ncols_active);
+  atomicAdd(&a.prof[1], 1u);
+  const unsigned long long pc = a.zero_prev ? 12 : 16;
+  atomicAdd(a.prof_bytes, (unsigned long long)a.ops.ne * (pc * ncols_active + 44));
+}
+
 __global__ __launch_bounds__(kWG) void k_cheb32_iter(Cheb32Args a) {
   const Lane L = lane_map(a.Bs, a.ops.ne);
   const DevOps &o = a.ops;
   const int c = L.col, Bs = a.Bs;
+  if (a.prof && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    int n = 0;
+    for (int j = 0; j < Bs; j++) n += a.colK[j] >= a.kneed ? 1 : 0;
+    cheb32_prof(a, n);
+  }
   if (a.colK[c] < a.kneed) return;
   for (int e = L.row0; e < L.rend; e += L.rstride) {
     float q = 0.0f;
@@ -745,6 +760,11 @@ __global__ __launch_bounds__(kWG) void k_cheb32_iter4(Cheb32Args a) {
   const Lane L = lane_map(Bq, a.ops.ne);
   const DevOps &o = a.ops;
   const int cq = L.col, c0 = 4 * cq;
+  if (a.prof && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    int n = 0;
+    for (int j = 0; j < a.Bs; j++) n += a.colK[j] >= a.kneed ? 1 : 0;
+    cheb32_prof(a, n);
+  }
   if (a.colK[c0] < a.kneed && a.colK[c0 + 1] < a.kneed && a.colK[c0 + 2] < a.kneed &&
       a.colK[c0 + 3] < a.kneed)
     return;

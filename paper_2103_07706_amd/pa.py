@@ -52,6 +52,7 @@ PA_PRECOND_JACOBI, PA_PRECOND_LEARNED = 0, 1
 PA_KERNEL_NONE, PA_KERNEL_CG_ITER, PA_KERNEL_CHEB_ITER, PA_KERNEL_CHEB_LP_ITER = 0, 1, 2, 3
 PA_KERNEL_CHEB_FUSED = 4
 PA_KERNEL_CHEB3_ITER = 5
+PA_KERNEL_CHEB32_ITER = 6
 
 
 class TrainCfg(ctypes.Structure):
