@@ -137,7 +137,7 @@ struct LaunchTune {
   int wide_max_wg = 2048;          // workgroups per column tile, wider batches
   int lp_min_cols = 8;             // learned mass-solve steps on blocks this wide or wider
   int mixed_min_cols = 8;          // FP32-refined mass solves on blocks this wide or wider
-  int fused_steps = 3;             // single-column Jacobi Chebyshev solves: steps per launch (1 to kFusedMax)
+  int fused_steps = 6;             // single-column Jacobi Chebyshev solves: steps per launch (1 to kFusedMax)
   bool operator==(const LaunchTune &o) const {
     return narrow_rows_per_thread == o.narrow_rows_per_thread && wide_max_wg == o.wide_max_wg &&
            lp_min_cols == o.lp_min_cols && mixed_min_cols == o.mixed_min_cols &&

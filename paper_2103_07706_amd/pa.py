@@ -84,7 +84,7 @@ class LaunchTune(ctypes.Structure):
 
 TUNE_FIELDS = ("narrow_rows_per_thread", "wide_max_wg", "lp_min_cols", "mixed_min_cols",
                "fused_steps")
-TUNE_DEFAULTS = {"lp_min_cols": 8, "mixed_min_cols": 8, "fused_steps": 3}
+TUNE_DEFAULTS = {"lp_min_cols": 8, "mixed_min_cols": 8, "fused_steps": 6}
 
 
 def _tune_dict(t) -> dict:
@@ -537,7 +537,7 @@ class Batch:
         return outs, [s.as_dict() for s in st]
 
     def set_tune(self, item, narrow_rows_per_thread, wide_max_wg, lp_min_cols=8,
-                 mixed_min_cols=8, fused_steps=3):
+                 mixed_min_cols=8, fused_steps=6):
         t = _tune_struct(dict(narrow_rows_per_thread=narrow_rows_per_thread,
                               wide_max_wg=wide_max_wg, lp_min_cols=lp_min_cols,
                               mixed_min_cols=mixed_min_cols, fused_steps=fused_steps))

@@ -35,19 +35,37 @@ def test_level6_single_term_matches_oracle(l6):
     s = np.array([s_all[-1]])
     w = np.array([1.0])
     avg = pa.Avg(s=s, w=w)
-    for solver in (0, 1):
-        cfg = pa.solve_cfg(solver=solver, weight_cut=0.0, **PARITY)
-        out, st = lo.phase_avg_rhs(avg, to_dev(mm.state(U)[None]), cfg)
-        got = mm.back(out.cpu().numpy()[0])
-        if solver == 0:
-            ref = oo.phase_avg_rhs(lb, s, w, U, tol=1e-13, rtol=1e-14)
-        assert rel_w(oo, got, ref) < 1e-12, (solver, rel_w(oo, got, ref))
+    keep = pa.get_launch_tune()
+    ref = oo.phase_avg_rhs(lb, s, w, U, tol=1e-13, rtol=1e-14)
+    try:
+        # CG; Chebyshev with six fused steps per launch (the benchmark's
+        # autotuned shape at this level) and with one step per launch
+        for solver, fs in ((0, 6), (1, 6), (1, 1)):
+            pa.set_launch_tune(fused_steps=fs)
+            cfg = pa.solve_cfg(solver=solver, weight_cut=0.0, **PARITY)
+            out, st = lo.phase_avg_rhs(avg, to_dev(mm.state(U)[None]), cfg)
+            got = mm.back(out.cpu().numpy()[0])
+            assert rel_w(oo, got, ref) < 1e-12, (solver, fs, rel_w(oo, got, ref))
+    finally:
+        pa.set_launch_tune(**keep)
 
 
 def test_level6_full_average_properties(l6):
+    """In the launch shape the benchmark's autotuner picks at this level
+    (six fused steps per launch, one row per thread for narrow blocks,
+    FP32 solves on the 64-column block)."""
     import torch
     from paper_2103_07706_amd import pa
     om, oo, lm, lo, mm, lb, U = l6
+    keep = pa.get_launch_tune()
+    pa.set_launch_tune(fused_steps=6, narrow_rows_per_thread=1, wide_max_wg=2048, mixed_min_cols=64)
+    try:
+        _full_average(pa, torch, om, oo, lo, mm, U)
+    finally:
+        pa.set_launch_tune(**keep)
+
+
+def _full_average(pa, torch, om, oo, lo, mm, U):
     avg = pa.Avg(64, 7200.0)
     Ud = to_dev(mm.state(U)[None])
     res = {}
