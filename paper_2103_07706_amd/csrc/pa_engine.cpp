@@ -162,6 +162,7 @@ void Engine::mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_
     if (prof && kin > 1) bracket_end(kin - 1);
     ra.first = 0;
     ra.last = o + 1 == mixed_outer_ ? 1 : 0;
+    ra.x_zero = prepared && o == 0 ? 1 : 0;  // the gather kernel left x unwritten
     ra.x32 = cur;
     ra.d32 = prev;  // the next x_1, beside the x_kin this kernel gathers
     launch_refine(ra, s_);

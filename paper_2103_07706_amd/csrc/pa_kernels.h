@@ -211,7 +211,7 @@ struct Cheb32Args {
 // FP64 refinement: x += x32, r -= M x32 (FP64 matrix), then FP32 copies for
 // the next inner solve: its right-hand side r32 = r and its first iterate
 // d32 = D^-1 r32 / theta.  first = 1: only the conversion (x32 not yet
-// formed, not read).  last = 1: partials of r.r, no copies.
+// formed, not read).  last = 1: partials of r.r, no copies and r not stored.
 struct RefineArgs {
   DevOps ops;
   int Bs;
@@ -221,6 +221,7 @@ struct RefineArgs {
   float theta_inv;
   const int *colK;
   int kneed, first, last;
+  int x_zero;  // x is still 0 (not read; x = x32 is written)
   double *part;
   int max_wg;
 };

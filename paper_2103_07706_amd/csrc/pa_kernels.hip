@@ -802,9 +802,9 @@ __global__ __launch_bounds__(kWG) void k_refine(RefineArgs a) {
 #pragma unroll
         for (int j = 0; j < 5; j++)
           q += o.mass[5 * e + j] * (double)a.x32[(size_t)o.ell_col[5 * e + j] * Bs + c];
-        a.x[ie] += (double)a.x32[ie];
+        a.x[ie] = a.x_zero ? (double)a.x32[ie] : a.x[ie] + (double)a.x32[ie];
         r -= q;
-        a.r[ie] = r;
+        if (!a.last) a.r[ie] = r;  // the last residual only feeds the check
       }
       if (a.last) {
         sums[0] += r * r;
@@ -1459,7 +1459,7 @@ __global__ __launch_bounds__(kWG) void k_nl_gather(GatherArgs a) {
       const size_t ie = (size_t)e * Bs + c;
       const double r = a.C[(size_t)o.cidx[2 * e] * Bs + c] + a.C[(size_t)o.cidx[2 * e + 1] * Bs + c];
       a.r[ie] = r;
-      a.x[ie] = 0.0;
+      if (!a.r32) a.x[ie] = 0.0;  // the refined solve's first refinement writes x
       if (a.d0) a.d0[ie] = a.theta_inv * o.dinv[e] * r;
       if (a.r32) {
         const float r32 = (float)r;
