@@ -235,12 +235,21 @@ int pa_diagnostics(pa_ctx *ctx, const pa_ops *ops, int B, const double *U_dev,
                    void *ws_dev, size_t ws_bytes, double *out_host);
 
 /* ---- measurement hook -----------------------------------------------------
- * Brackets every launch of one kernel on the context's stream with HIP
- * events and counts the algorithmic bytes it moves (operands it must stream
- * at least once per launch, for the columns still active in the launch).
- * pa_ctx_profile starts a new tally (PA_KERNEL_NONE switches it off);
- * pa_ctx_profile_read returns the tally so far.  The calls made while the
- * hook is on fill it; reading needs no further synchronisation. */
+ * Brackets the launches of one kernel on the context's stream with HIP
+ * events (one pair around the back-to-back launches of each mass solve) and
+ * counts the algorithmic bytes they move (operands each launch must stream
+ * at least once, for the columns still active in it).  Kernels:
+ *   PA_KERNEL_CG_ITER      CG iteration (k_cg_iter)
+ *   PA_KERNEL_CHEB_ITER    two-term Jacobi Chebyshev step (k_cheb_iter)
+ *   PA_KERNEL_CHEB_LP_ITER learned-preconditioner step (k_cheb_lp_iter; the
+ *                          two-kernel wide form counts both kernels)
+ *   PA_KERNEL_CHEB_FUSED   fused single-column steps (k_cheb_fused)
+ *   PA_KERNEL_CHEB3_ITER   three-term block step (k_cheb3_iter)
+ *   PA_KERNEL_CHEB32_ITER  FP32 three-term step (k_cheb32_iter[4])
+ * pa_ctx_profile starts a new tally (PA_KERNEL_NONE switches it off and
+ * graph capture is not used while it is on); pa_ctx_profile_read returns the
+ * tally so far.  The calls made while the hook is on fill it; reading needs
+ * no further synchronisation. */
 enum { PA_KERNEL_NONE = 0, PA_KERNEL_CG_ITER = 1, PA_KERNEL_CHEB_ITER = 2,
        PA_KERNEL_CHEB_LP_ITER = 3, PA_KERNEL_CHEB_FUSED = 4, PA_KERNEL_CHEB3_ITER = 5,
        PA_KERNEL_CHEB32_ITER = 6 };
