@@ -260,7 +260,7 @@ void Engine::cheb_fused(double *x, const int *colK, int kneed, int nwg_init, int
   const bool prof = ctx_->prof_kernel == PA_KERNEL_CHEB_FUSED;
   a.prof = prof ? st_.prof : nullptr;
   a.prof_bytes = st_.prof_bytes;
-  int launches = 0, i = 0, buf = 0;
+  int launches = 0, i = 0, buf = 0, setup_grid = grid;
   if (prof) bracket_begin();
   if (su) {
     int c = k % S ? k % S : S - 1;
@@ -284,7 +284,10 @@ void Engine::cheb_fused(double *x, const int *colK, int kneed, int nwg_init, int
     b.theta_inv = 1.0 / cheb_theta_;
     b.cpp = ops_->fused_cpp;
     b.part_rr = chk_init_[chk_par_];
-    take_check(b.chk, b.chk_blocks, grid);
+    // the pending check gets workgroups of its own past the parts when the
+    // grid has room for them
+    take_check(b.chk, b.chk_blocks, launch_max_wg() - grid);
+    setup_grid = cheb_fused_grid(ops_->d, b.chk_blocks);
     b.r_out = r[1];
     b.d_out = d[1];
     b.last = c == k ? 1 : 0;
@@ -316,7 +319,9 @@ void Engine::cheb_fused(double *x, const int *colK, int kneed, int nwg_init, int
     launches++;
   }
   if (prof) bracket_end(launches);
-  defer_check(1, nwg_init, colK, kneed, grid);
+  // partials of r_0.r_0 come from the set-up launch's grid, those of the
+  // final residual from the last launch's
+  defer_check(1, su ? setup_grid : nwg_init, colK, kneed, su && launches == 1 ? setup_grid : grid);
   stats.solves++;
   stats.cg_iters += k;
   stats.cg_iters_max = std::max(stats.cg_iters_max, k);

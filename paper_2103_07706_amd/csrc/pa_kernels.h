@@ -153,7 +153,8 @@ struct ChebFusedArgs {
   // r_0.r_0 per workgroup and the depth rows out_eta = scale (-H D u / |c|) +
   // addA_eta + addB_eta on cpp cells per part; steps 2..S are Chebyshev
   // steps with c1[1..S-1], c2[1..S-1]; the previous solve's residual check
-  // runs in the first chk_blocks workgroups.  r_in, d_in are not read.
+  // runs in chk_blocks workgroups added past the last part.  r_in, d_in
+  // are not read.
   int setup;
   const double *in_u, *in_eta, *addA_u, *addA_eta, *addB_u, *addB_eta;
   double *out_eta;
@@ -327,7 +328,8 @@ void launch_cg_init(const CgArgs &a, hipStream_t s);
 void launch_cheb_iter(const ChebArgs &a, hipStream_t s);
 void launch_cheb3_iter(const Cheb3Args &a, hipStream_t s);
 void launch_cheb_fused(const ChebFusedArgs &a, hipStream_t s);
-int cheb_fused_grid(const DevOps &o);  // workgroups of k_cheb_fused (0: not available)
+// workgroups of k_cheb_fused with `extra` workgroups past the last part (0: not available)
+int cheb_fused_grid(const DevOps &o, int extra = 0);
 void launch_cheb_check(const CheckArgs &a, hipStream_t s);
 int cheb_check_blocks(const CheckArgs &a);  // workgroups of a residual check
 void launch_cheb_lp_iter(const ChebLpArgs &a, hipStream_t s);

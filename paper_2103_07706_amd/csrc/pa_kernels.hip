@@ -323,7 +323,6 @@ template <int NSLOT, bool SETUP>
 __global__ __launch_bounds__(kWG) void k_cheb_fused(ChebFusedArgs a) {
   const DevOps &o = a.ops;
   const int t = threadIdx.x;
-  if (SETUP) folded_check(a.chk, a.chk_blocks);
   if (a.prof && blockIdx.x == 0 && t == 0) {
     const bool on = a.colK[0] >= a.kneed;
     atomicAdd(&a.prof[a.last ? 2 : 0], on ? 1u : 0u);
@@ -337,6 +336,10 @@ __global__ __launch_bounds__(kWG) void k_cheb_fused(ChebFusedArgs a) {
   __shared__ double dl[2][kPartRows + kHaloMax];
   __shared__ double red[2][kWG / 64];
   double s2 = 0.0, s0 = 0.0;
+  // the previous solve's residual check runs in the workgroups past the last
+  // part (the grid of a set-up launch has chk_blocks of them), beside the
+  // parts' work instead of before one part's
+  if (SETUP && p >= o.hparts && p - o.hparts < a.chk_blocks) check_block(a.chk, p - o.hparts);
   if (p < o.hparts) {
     const int e0 = p * kPartRows;
     const bool own = e0 + t < o.ne;
@@ -1727,13 +1730,13 @@ void launch_cheb_iter(const ChebArgs &a, hipStream_t s) {
 void launch_cheb3_iter(const Cheb3Args &a, hipStream_t s) {
   hipLaunchKernelGGL(k_cheb3_iter, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
 }
-int cheb_fused_grid(const DevOps &o) {
+int cheb_fused_grid(const DevOps &o, int extra) {
   if (o.hparts <= 0 || o.fused_max < 2) return 0;
-  const int g = (o.hparts + 7) / 8 * 8;
+  const int g = (o.hparts + extra + 7) / 8 * 8;
   return g <= launch_max_wg() ? g : 0;
 }
 void launch_cheb_fused(const ChebFusedArgs &a, hipStream_t s) {
-  const dim3 grid(cheb_fused_grid(a.ops));
+  const dim3 grid(cheb_fused_grid(a.ops, a.setup ? a.chk_blocks : 0));
   if (a.setup) {
     switch (a.slots[0]) {
       case 0: hipLaunchKernelGGL((k_cheb_fused<0, true>), grid, dim3(kWG), 0, s, a); break;
