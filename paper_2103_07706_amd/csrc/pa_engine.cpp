@@ -1164,8 +1164,8 @@ void Engine::run_nbar(NbarBufs &nb, Blk X, Blk out, bool uploaded) {
   const int Bm = nb.Bm, kmax = nb.kmax;
   const size_t blkm = (size_t)n_ * Bm;
   auto R = [&](int k) { return Blk{nb.basis + (size_t)k * blkm, Bm}; };
-  // forward basis R_0..R_kmax of the member states
-  axpy(blkm, R(0).p, 1.0, X.p);
+  // forward basis R_0..R_kmax of the member states (X may already be R_0)
+  if (X.p != R(0).p) axpy(blkm, R(0).p, 1.0, X.p);
   if (kmax >= 1) {
     Blk r1 = R(1);
     lstep(R(0), r1, nullptr, nullptr, 1.0 / lb, nb.colK_fwd, 1, nullptr);
@@ -1199,8 +1199,9 @@ void Engine::run_nbar(NbarBufs &nb, Blk X, Blk out, bool uploaded) {
     if (kmax == 0) {
       axpy(blkm, out.p, 1.0, Z(0).p);
     } else {
-      Blk bk1{nb.b1, Bm}, bk2{nb.b2, Bm};  // b_{k+1}, b_{k+2}
-      axpy(blkm, bk1.p, 1.0, Z(kmax).p);   // b_kmax
+      // b_{k+1}, b_{k+2}; b_kmax is Z_kmax itself, whose storage then takes
+      // b_{kmax-2}, ... in turn with b2 (no copy)
+      Blk bk1 = Z(kmax), bk2{nb.b2, Bm};
       bool have2 = false;
       for (int k = kmax - 1; k >= 1; k--) {
         Blk zk = Z(k);
@@ -1236,7 +1237,6 @@ void Engine::nbar_plan(NbarCall &c, const pa_avg *avg, int members, const double
   ut0_ = ar_.take<double>((size_t)ne_ * c.nb.BsE);
   ut1_ = ar_.take<double>((size_t)ne_ * c.nb.BsE);
   C_ = ar_.take<double>((size_t)3 * nc_ * c.nb.BsE);
-  c.X = block(c.nb.Bm);
   c.out = block(c.nb.Bm);
 }
 
@@ -1246,12 +1246,18 @@ void Engine::nbar_begin(NbarCall &c) {
 }
 
 void Engine::nbar_body(NbarCall &c) {
-  TransArgs tr{n_, c.members, c.nb.Bm, const_cast<double *>(c.U), c.X.p};
+  // the members go straight into R_0 of the basis; with one member the block
+  // layout is the state layout, and the result is formed in place
+  const Blk r0{c.nb.basis, c.nb.Bm};
+  TransArgs tr{n_, c.members, c.nb.Bm, const_cast<double *>(c.U), r0.p};
   launch_to_block(tr, s_);
-  run_nbar(c.nb, c.X, c.out, true);
+  const bool direct = c.members == 1 && c.nb.Bm == 1;
+  run_nbar(c.nb, r0, direct ? Blk{c.Nbar, 1} : c.out, true);
   flush_check();
-  TransArgs tb{n_, c.members, c.nb.Bm, c.Nbar, c.out.p};
-  launch_from_block(tb, s_);
+  if (!direct) {
+    TransArgs tb{n_, c.members, c.nb.Bm, c.Nbar, c.out.p};
+    launch_from_block(tb, s_);
+  }
 }
 
 // A call is a fixed kernel sequence with no host synchronisation when the
