@@ -959,11 +959,8 @@ void Engine::nonlinear_block(Blk E, Blk Y, const int *colK) {
   a.Bs = E.Bs;
   a.u = E.p;
   a.eta = E.p + (size_t)ne_ * E.Bs;
-  a.ut0 = ut0_;
-  a.ut1 = ut1_;
   a.C = C_;
   a.out_eta = Y.p + (size_t)ne_ * E.Bs;
-  launch_nl_upwind(a, s_);
   launch_nl_cell(a, s_);
   GatherArgs gth{};
   gth.ops = ops_->d;
@@ -1039,7 +1036,7 @@ void Engine::expL_apply(int B, const double *t, const double *Uin, double *Uout)
   plan_common(Bs);
   ExpBufs eb;
   plan_exp(eb, B, t);
-  ut0_ = ut1_ = C_ = nullptr;
+  C_ = nullptr;
   Blk in = block(Bs), out = block(Bs);
   if (ar_.sizing()) return;
   begin();
@@ -1057,8 +1054,6 @@ void Engine::swe_nonlinear(int B, const double *U, double *NU) {
   if (B <= 0) throw Error(PA_EINVAL, "B must be positive");
   const int Bs = pad_cols(B);
   plan_common(Bs);
-  ut0_ = ar_.take<double>((size_t)ne_ * Bs);
-  ut1_ = ar_.take<double>((size_t)ne_ * Bs);
   C_ = ar_.take<double>((size_t)3 * nc_ * Bs);
   int *colK = ar_.take<int>(Bs);
   Blk E = block(Bs), Y = block(Bs);
@@ -1234,8 +1229,6 @@ void Engine::nbar_plan(NbarCall &c, const pa_avg *avg, int members, const double
     guard_members_ = members;
     guard_calls_ = 1;
   }
-  ut0_ = ar_.take<double>((size_t)ne_ * c.nb.BsE);
-  ut1_ = ar_.take<double>((size_t)ne_ * c.nb.BsE);
   C_ = ar_.take<double>((size_t)3 * nc_ * c.nb.BsE);
   c.out = block(c.nb.Bm);
 }
@@ -1359,8 +1352,6 @@ void Engine::step(const pa_avg *avg, double dt, int members, double *U) {
     guard_members_ = members;
     guard_calls_ = 4;
   }
-  ut0_ = ar_.take<double>((size_t)ne_ * nb.BsE);
-  ut1_ = ar_.take<double>((size_t)ne_ * nb.BsE);
   C_ = ar_.take<double>((size_t)3 * nc_ * nb.BsE);
   std::vector<double> th(members, 0.5 * dt), tf(members, dt);
   ExpBufs eh, ef;

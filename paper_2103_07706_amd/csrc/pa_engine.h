@@ -216,7 +216,7 @@ class Engine {
   int BsMax_ = 0;
   double *r_ = nullptr, *r1_ = nullptr, *w0_ = nullptr, *w1_ = nullptr;
   double *s0_ = nullptr, *s1_ = nullptr, *p_ = nullptr;
-  double *ut0_ = nullptr, *ut1_ = nullptr, *C_ = nullptr;
+  double *C_ = nullptr;
   SolveState st_{};
   RedBuf rb_{};
   unsigned *zero_base_ = nullptr;

@@ -260,7 +260,7 @@ struct NlArgs {
   DevOps ops;
   int Bs;
   const double *u, *eta;
-  double *ut0, *ut1, *C, *out_eta;
+  double *C, *out_eta;
 };
 
 struct GatherArgs {
@@ -339,7 +339,6 @@ void launch_refine(const RefineArgs &a, hipStream_t s);
 void launch_cg_iter(const CgArgs &a, hipStream_t s);
 void launch_combine(const CombineArgs &a, hipStream_t s);
 void launch_reduce_terms(const ReduceTermsArgs &a, hipStream_t s);
-void launch_nl_upwind(const NlArgs &a, hipStream_t s);
 void launch_nl_cell(const NlArgs &a, hipStream_t s);
 void launch_nl_gather(const GatherArgs &a, hipStream_t s);
 void launch_acc(const AccArgs &a, hipStream_t s);

@@ -1278,28 +1278,6 @@ __global__ __launch_bounds__(kWG) void k_reduce_terms(ReduceTermsArgs a) {
 }
 
 // ----------------------------------------------------------- nonlinearity
-// Upwind tangential velocity at the two Gauss points of every edge, from the
-// cell the edge flux leaves (flux > 0: c0, otherwise c1).
-__global__ __launch_bounds__(kWG) void k_nl_upwind(NlArgs a) {
-  const Lane L = lane_map(a.Bs, a.ops.ne);
-  const DevOps &o = a.ops;
-  const int c = L.col, Bs = a.Bs;
-  for (int e = L.row0; e < L.rend; e += L.rstride) {
-    const size_t ie = (size_t)e * Bs + c;
-    const int side = a.u[ie] > 0.0 ? 0 : 1;
-    const double *tau = o.tau + (size_t)kEdgeTau * e + 6 * side;
-    const int *ed = o.side_edges + 6 * e + 3 * side;
-    double u0 = 0.0, u1 = 0.0;
-#pragma unroll
-    for (int j = 0; j < 3; j++) {
-      const double U = a.u[(size_t)ed[j] * Bs + c];
-      u0 += tau[j] * U;
-      u1 += tau[3 + j] * U;
-    }
-    a.ut0[ie] = u0;
-    a.ut1[ie] = u1;
-  }
-}
 
 // Per cell and local edge i, the cell's share of the velocity right-hand side
 // of test function phi_i, and the depth tendency:
@@ -1412,8 +1390,28 @@ __global__ __launch_bounds__(kWG) void k_nl_cell(NlArgs a) {
       // global order a -> b is the cell's CCW order when s = +1
       const int ia = s[aa] > 0 ? (aa + 1) % 3 : (aa + 2) % 3;
       const int ib = s[aa] > 0 ? (aa + 2) % 3 : (aa + 1) % 3;
-      const size_t iedge = (size_t)ed[aa] * Bs + c;
-      const double utg[2] = {a.ut0[iedge], a.ut1[iedge]};
+      // upwind tangential velocity at the side's two Gauss points, from the
+      // cell the edge flux leaves (flux > 0: the edge's first cell, otherwise
+      // its second): that cell's three edges against the edge's trace table;
+      // when the upwind cell is this one, its edge values are U
+      const int E = ed[aa];
+      const int up = U[aa] > 0.0 ? 0 : 1;
+      const double *tau = o.tau + (size_t)kEdgeTau * E + 6 * up;
+      double uu[3];
+      if (o.ecell[2 * E + up] == t) {
+#pragma unroll
+        for (int j = 0; j < 3; j++) uu[j] = U[j];
+      } else {
+        const int *se = o.side_edges + 6 * E + 3 * up;
+#pragma unroll
+        for (int j = 0; j < 3; j++) uu[j] = a.u[(size_t)se[j] * Bs + c];
+      }
+      double utg[2] = {0.0, 0.0};
+#pragma unroll
+      for (int j = 0; j < 3; j++) {
+        utg[0] += tau[j] * uu[j];
+        utg[1] += tau[3 + j] * uu[j];
+      }
       double f[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int gp = 0; gp < 2; gp++) {
@@ -1804,9 +1802,6 @@ void launch_reduce_terms(const ReduceTermsArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_reduce_terms1, dim3(grid_tiles_pipe((size_t)a.nrows * a.BsZ)), dim3(kWG), 0, s, a);
   else
     hipLaunchKernelGGL(k_reduce_terms, dim3(grid_tiles((size_t)a.nrows * a.BsZ)), dim3(kWG), 0, s, a);
-}
-void launch_nl_upwind(const NlArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_nl_upwind, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
 }
 void launch_nl_cell(const NlArgs &a, hipStream_t s) {
   if (a.Bs >= 64)
