@@ -86,8 +86,8 @@ constexpr int kEdgeTau = 12;
 // columns reach outside the part and rings 1..r.  kFusedMax - 1 rings are
 // kept, at most kHaloMax rows in all per part (fewer rings on a mesh where
 // they do not fit).
-constexpr int kPartRows = 256;  // also the kernel's workgroup size: one row a thread
-constexpr int kHaloMax = 768;
+constexpr int kPartRows = 512;  // also the kernel's workgroup size: one row a thread
+constexpr int kHaloMax = 1024;
 constexpr int kFusedMax = 6;
 
 // Device-resident operator arrays (pointers into the caller's buffer).

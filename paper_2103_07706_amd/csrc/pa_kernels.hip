@@ -120,19 +120,21 @@ __device__ void check_block(const CheckArgs &a, int blk) {
   const int part = wave / cpb;
   const int c = tile * ct + cl;
   double b = 0.0, r = 0.0;
-  for (int w = part * 64 + lane; w < a.nwg_init; w += 64 * split)
+  // the first four waves do the check (workgroups of more waves call it too)
+  const bool on = wave < 4;
+  for (int w = part * 64 + lane; on && w < a.nwg_init; w += 64 * split)
     b += a.part_init[((size_t)tile * a.max_wg + w) * 64 + cl];
-  for (int w = part * 64 + lane; w < a.nwg_last; w += 64 * split)
+  for (int w = part * 64 + lane; on && w < a.nwg_last; w += 64 * split)
     r += a.part_last[((size_t)tile * a.max_wg + w) * 64 + cl];
   b = wave_col_sum(b, 1);
   r = wave_col_sum(r, 1);
   __shared__ double red[2][4];
-  if (lane == 0) {
+  if (on && lane == 0) {
     red[0][wave] = b;
     red[1][wave] = r;
   }
   __syncthreads();
-  if (part == 0 && lane == 0) {
+  if (on && part == 0 && lane == 0) {
     b = 0.0;
     r = 0.0;
     for (int p = 0; p < split; p++) {  // fixed order
@@ -308,9 +310,10 @@ __global__ __launch_bounds__(kWG) void k_cheb_iter(ChebArgs a) {
 // and d go to separate output buffers.  Parts are laid over the XCDs like
 // lane_map's slices (XCD k takes parts k per .. k per + per - 1), so
 // neighbouring parts and their rings share an L2.
-constexpr int kRingSlots = kHaloMax / kWG;  // ring rows per thread
+constexpr int kFWG = kPartRows;  // workgroup size of the fused kernel: one row a thread
+constexpr int kRingSlots = kHaloMax / kFWG;  // ring rows per thread
 
-// NSLOT: ring slots of kWG rows the launch's first step covers (every part's
+// NSLOT: ring slots of kFWG rows the launch's first step covers (every part's
 // rings 1..S-1 fit).  The loads go out in three waves by dependence (indices
 // and row values; the ring rows they name and the own row's gathers; the
 // ring rows' gathers); a ring slot past the part's rings (list entry -1)
@@ -320,7 +323,7 @@ constexpr int kRingSlots = kHaloMax / kWG;  // ring rows per thread
 // memory are predicated (an inactive column; the threads past a ragged last
 // part, which work on a copy of its last row).
 template <int NSLOT, bool SETUP>
-__global__ __launch_bounds__(kWG) void k_cheb_fused(ChebFusedArgs a) {
+__global__ __launch_bounds__(kFWG) void k_cheb_fused(ChebFusedArgs a) {
   const DevOps &o = a.ops;
   const int t = threadIdx.x;
   if (a.prof && blockIdx.x == 0 && t == 0) {
@@ -334,7 +337,7 @@ __global__ __launch_bounds__(kWG) void k_cheb_fused(ChebFusedArgs a) {
   const int p = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   const int S = a.S;
   __shared__ double dl[2][kPartRows + kHaloMax];
-  __shared__ double red[2][kWG / 64];
+  __shared__ double red[2][kFWG / 64];
   double s2 = 0.0, s0 = 0.0;
   // the previous solve's residual check runs in the workgroups past the last
   // part (the grid of a set-up launch has chk_blocks of them), beside the
@@ -392,13 +395,13 @@ __global__ __launch_bounds__(kWG) void k_cheb_fused(ChebFusedArgs a) {
     }
     int g[NS];
 #pragma unroll
-    for (int q = 0; q < NSLOT; q++) g[q] = rrow[t + q * kWG];
+    for (int q = 0; q < NSLOT; q++) g[q] = rrow[t + q * kFWG];
     // second wave: the ring rows, the own row's gathers
     double rm[NS][5], rdinv[NS], rr[NS], dg[NS], rfc[NS][5];
     int gc[NS][5], rlc[NS][5], rec[NS][2];
 #pragma unroll
     for (int q = 0; q < NSLOT; q++) {
-      const int h = t + q * kWG;
+      const int h = t + q * kFWG;
       dg[q] = rdinv[q] = rr[q] = 0.0;
 #pragma unroll
       for (int j = 0; j < 5; j++) {
@@ -447,7 +450,7 @@ __global__ __launch_bounds__(kWG) void k_cheb_fused(ChebFusedArgs a) {
       if (S > 1) dl[0][t] = cheb_dir(a.c1[0], a.c2[0], dv, dinv, r);
     }
     // third wave: the ring rows' gathers; step 1 on rings 1..S-1 (ring row
-    // h = t + q kWG stays in slot q of thread t, its matrix row, local
+    // h = t + q kFWG stays in slot q of thread t, its matrix row, local
     // columns, diagonal and residual in registers, so that later steps touch
     // only LDS)
 #pragma unroll
@@ -467,7 +470,7 @@ __global__ __launch_bounds__(kWG) void k_cheb_fused(ChebFusedArgs a) {
           rr[q] -= qs;
           dn1 = cheb_dir(a.c1[0], a.c2[0], dg[q], rdinv[q], rr[q]);
         }
-        dl[0][kPartRows + t + q * kWG] = dn1;
+        dl[0][kPartRows + t + q * kFWG] = dn1;
       }
     // with SETUP the ring rows' mass rows load only now, after the Coriolis
     // rows are done with (fewer registers live at once)
@@ -493,9 +496,9 @@ __global__ __launch_bounds__(kWG) void k_cheb_fused(ChebFusedArgs a) {
       for (int j = 0; j < 5; j++) dq[j] = dp[j ? lc[j] : t];
 #pragma unroll
       for (int k = 0; k < NSLOT; k++)
-        if (k * kWG + wrow < nh) {
+        if (k * kFWG + wrow < nh) {
 #pragma unroll
-          for (int j = 0; j < 5; j++) dr[k][j] = dp[j ? rlc[k][j] : kPartRows + t + k * kWG];
+          for (int j = 0; j < 5; j++) dr[k][j] = dp[j ? rlc[k][j] : kPartRows + t + k * kFWG];
         }
       dv = dq[0];
       double q = fma(m[0], dv, 0.0);
@@ -507,7 +510,7 @@ __global__ __launch_bounds__(kWG) void k_cheb_fused(ChebFusedArgs a) {
       double dnr[NS];
 #pragma unroll
       for (int k = 0; k < NSLOT; k++)
-        if (k * kWG + wrow < nh) {
+        if (k * kFWG + wrow < nh) {
           double qs = fma(rm[k][0], dr[k][0], 0.0);
 #pragma unroll
           for (int j = 1; j < 5; j++) qs = fma(rm[k][j], dr[k][j], qs);
@@ -517,7 +520,7 @@ __global__ __launch_bounds__(kWG) void k_cheb_fused(ChebFusedArgs a) {
       if (st + 1 < S) dn[t] = cheb_dir(c1, c2, dv, dinv, r);
 #pragma unroll
       for (int k = 0; k < NSLOT; k++)
-        if (k * kWG + wrow < nh) dn[kPartRows + t + k * kWG] = dnr[k];
+        if (k * kFWG + wrow < nh) dn[kPartRows + t + k * kFWG] = dnr[k];
     }
     if (own && act) {
       a.x[e] = x;
@@ -541,7 +544,7 @@ __global__ __launch_bounds__(kWG) void k_cheb_fused(ChebFusedArgs a) {
     __syncthreads();
     if (t == 0) {
       double w = 0.0, w0 = 0.0;
-      for (int i = 0; i < kWG / 64; i++) {
+      for (int i = 0; i < kFWG / 64; i++) {
         w += red[0][i];
         w0 += red[1][i];
       }
@@ -1737,18 +1740,18 @@ void launch_cheb_fused(const ChebFusedArgs &a, hipStream_t s) {
   const dim3 grid(cheb_fused_grid(a.ops, a.setup ? a.chk_blocks : 0));
   if (a.setup) {
     switch (a.slots[0]) {
-      case 0: hipLaunchKernelGGL((k_cheb_fused<0, true>), grid, dim3(kWG), 0, s, a); break;
-      case 1: hipLaunchKernelGGL((k_cheb_fused<1, true>), grid, dim3(kWG), 0, s, a); break;
-      case 2: hipLaunchKernelGGL((k_cheb_fused<2, true>), grid, dim3(kWG), 0, s, a); break;
-      default: hipLaunchKernelGGL((k_cheb_fused<kRingSlots, true>), grid, dim3(kWG), 0, s, a); break;
+      case 0: hipLaunchKernelGGL((k_cheb_fused<0, true>), grid, dim3(kFWG), 0, s, a); break;
+      case 1: hipLaunchKernelGGL((k_cheb_fused<1, true>), grid, dim3(kFWG), 0, s, a); break;
+      case 2: hipLaunchKernelGGL((k_cheb_fused<2, true>), grid, dim3(kFWG), 0, s, a); break;
+      default: hipLaunchKernelGGL((k_cheb_fused<kRingSlots, true>), grid, dim3(kFWG), 0, s, a); break;
     }
     return;
   }
   switch (a.slots[0]) {
-    case 0: hipLaunchKernelGGL((k_cheb_fused<0, false>), grid, dim3(kWG), 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_cheb_fused<1, false>), grid, dim3(kWG), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_cheb_fused<2, false>), grid, dim3(kWG), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_cheb_fused<kRingSlots, false>), grid, dim3(kWG), 0, s, a); break;
+    case 0: hipLaunchKernelGGL((k_cheb_fused<0, false>), grid, dim3(kFWG), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_cheb_fused<1, false>), grid, dim3(kFWG), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_cheb_fused<2, false>), grid, dim3(kFWG), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_cheb_fused<kRingSlots, false>), grid, dim3(kFWG), 0, s, a); break;
   }
 }
 // The icosahedral meshes give P and P M widths 13 and 27 at every level;
