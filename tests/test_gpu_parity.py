@@ -279,8 +279,9 @@ def test_gpu_cheb_fused_steps(level, tol):
     launch (each workgroup forms the earlier steps again on the rings of
     rows its later steps read) against one step per launch: the same Nbar
     bit for bit (every row's arithmetic is the same), residuals within the
-    tolerance, and parity with the oracle.  Parts of 256 rows, the last one
-    ragged at levels 3 and 4; the step counts of the two tolerances leave
+    tolerance, and parity with the oracle.  Parts of 512 rows: a single
+    ragged part at level 2, a ragged last part at level 3, whole parts at
+    level 4; the step counts of the two tolerances leave
     different remainders for the first launch of a solve; the metric case
     also runs captured and replayed."""
     from paper_2103_07706_amd import pa
