@@ -162,7 +162,7 @@ size_t layout(pa_ops *o, char *base) {
   place(off, o->dinv32, &d.dinv32, base);
   place(off, o->ecell, &d.ecell, base);
   place(off, o->cidx, &d.cidx, base);
-  place(off, o->side_edges, &d.side_edges, base);
+  place(off, o->cell_edges, &d.cell_edges, base);
   place(off, o->tau, &d.tau, base);
   place(off, o->cedge, &d.cedge, base);
   place(off, o->csgn, &d.csgn, base);
@@ -171,6 +171,7 @@ size_t layout(pa_ops *o, char *base) {
   place(off, o->inv_area, &d.inv_area, base);
   place(off, o->bottom, &d.bottom, base);
   place(off, o->cgeo, &d.cgeo, base);
+  place(off, o->nlform, &d.nlform, base);
   place(off, o->ring_cnt, &d.ring_cnt, base);
   place(off, o->ring_row, &d.ring_row, base);
   place(off, o->hloc, &d.hloc, base);
@@ -238,7 +239,7 @@ int pa_ops_bind(pa_ctx *ctx, pa_ops *ops, void *dev_buf) {
     up(s, d.dinv32, ops->dinv32);
     up(s, d.ecell, ops->ecell);
     up(s, d.cidx, ops->cidx);
-    up(s, d.side_edges, ops->side_edges);
+    up(s, d.cell_edges, ops->cell_edges);
     up(s, d.tau, ops->tau);
     up(s, d.cedge, ops->cedge);
     up(s, d.csgn, ops->csgn);
@@ -247,6 +248,7 @@ int pa_ops_bind(pa_ctx *ctx, pa_ops *ops, void *dev_buf) {
     up(s, d.inv_area, ops->inv_area);
     up(s, d.bottom, ops->bottom);
     up(s, d.cgeo, ops->cgeo);
+    up(s, d.nlform, ops->nlform);
     up(s, d.ring_cnt, ops->ring_cnt);
     up(s, d.ring_row, ops->ring_row);
     up(s, d.hloc, ops->hloc);

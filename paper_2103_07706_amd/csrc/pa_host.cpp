@@ -143,6 +143,85 @@ double coriolis(double omega, V3 x) { return 2.0 * omega * x.z / norm(x); }
 
 }  // namespace
 
+namespace {
+// The nonlinear cell term C_i (Sec. 2.5: volume, kinetic-energy and facet
+// integrals of the cell's share of the velocity right-hand side of test
+// function i) in terms of the cell's edge fluxes U_0..U_2.  With
+// phi_l(x) = s_l/(2A) (x - p_l), u = sum_l U_l phi_l and
+// q_i(x) = s_i/(2A) (k x u(x)) . (x - p_i):
+//   volume + kinetic energy = U^T S_i U, where
+//     S_i = sym(V_i) + (s_i/A) K,
+//     K_jl = (A/6) sum over side midpoints m of phi_j(m) . phi_l(m),
+//     V_i[m][l] = A sum_{j != i} (phi_m(xbar) . (k x grad lambda_j)) G_ijl,
+//     G_ijl = s_i/(2A) (k x phi_l(p_j)) . (p_j - p_i)
+//   (grad q_i taken from q_i's vertex values, u(xbar) at the centroid);
+//   facet of side a = sum_gp utg_gp sum_l H[a][gp][i][l] U_l, where
+//     H = -s_a |side a|/2 s_i/(2A) (k x phi_l(x_gp)) . (x_gp - p_i)
+//   at the side's Gauss points in the edge's direction, and utg_gp is the
+//   upwind tangential velocity there.
+// Layout: per i the six coefficients of (U0^2, U1^2, U2^2, U0 U1, U0 U2,
+// U1 U2) (cross terms doubled), then H[a][gp][i][l] from offset 18.  g is the
+// cell's geometry row (vertices, normal, area, gradients of the barycentric
+// coordinates, side lengths), s the cell's edge signs.
+void nl_cell_forms(const double *g, const int s[3], double *out) {
+  V3 p[3], gl[3];
+  for (int i = 0; i < 3; i++) {
+    p[i] = {g[3 * i], g[3 * i + 1], g[3 * i + 2]};
+    gl[i] = {g[13 + 3 * i], g[14 + 3 * i], g[15 + 3 * i]};
+  }
+  const V3 k = {g[9], g[10], g[11]};
+  const double A = g[12];
+  auto phi = [&](int l, V3 x) { return (s[l] / (2.0 * A)) * (x - p[l]); };
+  double K[3][3];
+  for (int j = 0; j < 3; j++)
+    for (int l = 0; l < 3; l++) {
+      double v = 0.0;
+      for (int q = 0; q < 3; q++) {
+        const V3 mq = 0.5 * (p[(q + 1) % 3] + p[(q + 2) % 3]);
+        v += dot(phi(j, mq), phi(l, mq));
+      }
+      K[j][l] = A / 6.0 * v;
+    }
+  const V3 xb = (1.0 / 3.0) * (p[0] + p[1] + p[2]);
+  for (int i = 0; i < 3; i++) {
+    double V[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int j = 0; j < 3; j++) {
+      if (j == i) continue;
+      const V3 kg = cross(k, gl[j]);
+      for (int m = 0; m < 3; m++) {
+        const double a = A * dot(phi(m, xb), kg);
+        for (int l = 0; l < 3; l++)
+          V[m][l] += a * (s[i] / (2.0 * A)) * dot(cross(k, phi(l, p[j])), p[j] - p[i]);
+      }
+    }
+    double S[3][3];
+    for (int m = 0; m < 3; m++)
+      for (int l = 0; l < 3; l++) S[m][l] = 0.5 * (V[m][l] + V[l][m]) + (s[i] / A) * K[m][l];
+    double *o = out + 6 * i;
+    o[0] = S[0][0];
+    o[1] = S[1][1];
+    o[2] = S[2][2];
+    o[3] = 2.0 * S[0][1];
+    o[4] = 2.0 * S[0][2];
+    o[5] = 2.0 * S[1][2];
+  }
+  const double gq = 0.5 / std::sqrt(3.0);
+  for (int a = 0; a < 3; a++) {
+    // the side's vertices in the edge's direction (the cell's CCW order when s = +1)
+    const int ia = s[a] > 0 ? (a + 1) % 3 : (a + 2) % 3;
+    const int ib = s[a] > 0 ? (a + 2) % 3 : (a + 1) % 3;
+    for (int gp = 0; gp < 2; gp++) {
+      const double xi = gp == 0 ? 0.5 - gq : 0.5 + gq;
+      const V3 xg = p[ia] + xi * (p[ib] - p[ia]);
+      for (int i = 0; i < 3; i++)
+        for (int l = 0; l < 3; l++)
+          out[18 + ((2 * a + gp) * 3 + i) * 3 + l] =
+              -s[a] * 0.5 * g[22 + a] * (s[i] / (2.0 * A)) * dot(cross(k, phi(l, xg)), xg - p[i]);
+    }
+  }
+}
+}  // namespace
+
 // Assemble operators and geometry tables on the host.
 void assemble_ops(pa_ops *o, const Mesh &m, const pa_phys &ph) {
   const int ne = m.ne(), nc = m.nc();
@@ -157,12 +236,13 @@ void assemble_ops(pa_ops *o, const Mesh &m, const pa_phys &ph) {
   o->bottom.assign(nc, 0.0);
   if (ph.b_cell) std::memcpy(o->bottom.data(), ph.b_cell, sizeof(double) * nc);
   o->cgeo.assign((size_t)nc * kCellGeo, 0.0);
+  o->nlform.assign((size_t)nc * kNlForm, 0.0);
   o->cedge = m.cedge;
   o->csgn = m.csgn;
   o->ecell = m.ecell;
   o->cnbr.resize(3 * nc);
   o->cidx.resize(2 * ne);
-  o->side_edges.resize(6 * ne);
+  o->cell_edges.resize(12 * nc);
   o->tau.resize((size_t)kEdgeTau * ne);
   o->ell_col.assign(5 * ne, -1);
   o->mass.assign(5 * ne, 0.0);
@@ -180,7 +260,6 @@ void assemble_ops(pa_ops *o, const Mesh &m, const pa_phys &ph) {
         } else {
           o->ell_col[5 * e + slot++] = ej;
         }
-        o->side_edges[6 * e + 3 * side + j] = ej;
       }
     }
   }
@@ -199,6 +278,8 @@ void assemble_ops(pa_ops *o, const Mesh &m, const pa_phys &ph) {
       ed[i] = m.cedge[3 * c + i];
       int e = ed[i];
       o->cnbr[3 * c + i] = m.ecell[2 * e] == c ? m.ecell[2 * e + 1] : m.ecell[2 * e];
+      o->cell_edges[12 * c + i] = e;
+      for (int j = 0; j < 3; j++) o->cell_edges[12 * c + 3 + 3 * i + j] = m.cedge[3 * o->cnbr[3 * c + i] + j];
     }
     V3 kk = cross(p[1] - p[0], p[2] - p[0]);
     double A = 0.5 * norm(kk);
@@ -243,6 +324,7 @@ void assemble_ops(pa_ops *o, const Mesh &m, const pa_phys &ph) {
       g[15 + 3 * j] = gl.z;
       g[22 + j] = norm(p[(j + 2) % 3] - p[(j + 1) % 3]);
     }
+    nl_cell_forms(g, s, &o->nlform[(size_t)c * kNlForm]);
   }
   // tangential traces t_e . u_c(x_g) = sum_j tau[side][g][j] U_j, at the two
   // Gauss points of the edge taken in the edge's a -> b order

@@ -80,6 +80,10 @@ Mesh build_icosahedral(int level, double radius);
 constexpr int kCellGeo = 32;
 // Per-edge tangential-trace table: tau[side][gauss][j] (2*2*3).
 constexpr int kEdgeTau = 12;
+// Per cell: the nonlinear cell term as forms in the cell's edge fluxes U
+// (three symmetric 3x3 forms, then the facet coefficients of the two Gauss
+// points of each side; built by nl_cell_forms with the operators)
+constexpr int kNlForm = 72;
 // Row parts of the fused-step mass-solve kernel: part p holds the kPartRows
 // edges [p kPartRows, (p + 1) kPartRows).  Ring 1 of a part is the set of
 // other edges its rows' ELL columns reach, ring r + 1 the edges ring r's
@@ -102,7 +106,8 @@ struct DevOps {
   const float *dinv32 = nullptr;      // ne
   const int32_t *ecell = nullptr;     // ne*2
   const int32_t *cidx = nullptr;      // ne*2: 3*c + local index in c0, c1
-  const int32_t *side_edges = nullptr;// ne*6: edges of c0, edges of c1
+  const int32_t *cell_edges = nullptr;// nc*12: the cell's edges, then per local edge a the
+                                      // edges of the cell across a (48-byte records)
   const double *tau = nullptr;        // ne*12
   const int32_t *cedge = nullptr;     // nc*3
   const int32_t *csgn = nullptr;      // nc*3
@@ -111,6 +116,7 @@ struct DevOps {
   const double *inv_area = nullptr;   // nc
   const double *bottom = nullptr;     // nc
   const double *cgeo = nullptr;       // nc*kCellGeo
+  const double *nlform = nullptr;     // nc*kNlForm
   // row parts (see kPartRows): hparts parts, rings 1..fused_max-1 kept
   int hparts = 0, fused_max = 1;
   const int32_t *ring_cnt = nullptr;  // hparts*8: rows of rings 1..r of part p, r = 1..kFusedMax-1
@@ -200,8 +206,8 @@ struct pa_ops {
   double g = 0, H = 0, omega = 0, lambda_bar = 0;
   double mass_eig_min = 0, mass_eig_max = 0;  // Ritz bounds of D^-1 M
   // host copies, in upload order
-  std::vector<int32_t> ell_col, ecell, cidx, side_edges, cedge, csgn, cnbr;
-  std::vector<double> mass, cor, dinv, area, inv_area, bottom, cgeo, tau;
+  std::vector<int32_t> ell_col, ecell, cidx, cell_edges, cedge, csgn, cnbr;
+  std::vector<double> mass, cor, dinv, area, inv_area, bottom, cgeo, nlform, tau;
   std::vector<float> mass32, dinv32;
   int hparts = 0, fused_max = 1;
   int fused_cpp = 0;  // cells per part in a set-up launch (0: no set-up launches)

@@ -59,6 +59,30 @@ __device__ inline Lane lane_map(int Bs, int nrows) {
   return L;
 }
 
+// A read-only table seen through the constant address space: loads at
+// wave-uniform addresses then go through the scalar unit into scalar
+// registers (as vector loads every lane would receive its own copy of the
+// value, through the vector memory path).
+template <typename T>
+__device__ inline const __attribute__((address_space(4))) T *uniform_ro(const T *p) {
+  return (const __attribute__((address_space(4))) T *)p;
+}
+
+// Row tables of the block kernels.  UNI: at least 64 columns (lane_map gives
+// a wave one row), so the row number is made wave-uniform and the row's
+// operator entries load through the scalar unit.
+template <bool UNI>
+__device__ inline int urow(int e) {
+  return UNI ? __builtin_amdgcn_readfirstlane(e) : e;
+}
+template <bool UNI, typename T>
+__device__ inline T rl(const T *p, size_t i) {
+  if constexpr (UNI)
+    return uniform_ro(p)[i];
+  else
+    return p[i];
+}
+
 // Sum v over lanes that share a column (lane % ct), result valid in lanes < ct.
 __device__ inline double wave_col_sum(double v, int ct) {
   for (int off = 32; off >= ct; off >>= 1) v += __shfl_xor(v, off);
@@ -185,6 +209,7 @@ __device__ inline double stiff_d0(double theta_inv, double dinv, double r) { ret
 //   depth:    out_eta = scale (-H D u / |c|) + addA_eta + addB_eta,
 // for columns with colK[c] >= kneed; optionally acc += coef * in (grouped
 // column sums of G columns) for columns with colK[c] >= acc_k.
+template <bool UNI>
 __global__ __launch_bounds__(kWG) void k_stiff(StiffArgs a) {
   folded_check(a.chk, a.chk_blocks);
   const Lane L = lane_map(a.Bs, a.ops.ne > a.ops.nc ? a.ops.ne : a.ops.nc);
@@ -195,7 +220,7 @@ __global__ __launch_bounds__(kWG) void k_stiff(StiffArgs a) {
   const double coef = acc_on ? a.coef[c] : 0.0;
   double rr = 0.0;
   for (int base = L.row0 - L.lane / L.ct; base < L.rend; base += L.rstride) {
-    const int e = base + L.lane / L.ct;
+    const int e = urow<UNI>(base + L.lane / L.ct);
     // edges
     double accv = 0.0;
     if (e < o.ne && e < L.rend) {
@@ -203,8 +228,9 @@ __global__ __launch_bounds__(kWG) void k_stiff(StiffArgs a) {
       if (act) {
         double fu = 0.0;
 #pragma unroll
-        for (int j = 0; j < 5; j++) fu = fma(o.cor[5 * e + j], a.in_u[(size_t)o.ell_col[5 * e + j] * Bs + c], fu);
-        const int c0 = o.ecell[2 * e], c1 = o.ecell[2 * e + 1];
+        for (int j = 0; j < 5; j++)
+          fu = fma(rl<UNI>(o.cor, 5 * e + j), a.in_u[(size_t)rl<UNI>(o.ell_col, 5 * e + j) * Bs + c], fu);
+        const int c0 = rl<UNI>(o.ecell, 2 * e), c1 = rl<UNI>(o.ecell, 2 * e + 1);
         const double r = stiff_u(a.scale, fu, o.g, a.in_eta[(size_t)c0 * Bs + c], a.in_eta[(size_t)c1 * Bs + c]);
         double x0 = 0.0;
         if (a.addA_u) x0 += a.addA_u[ie];
@@ -212,7 +238,7 @@ __global__ __launch_bounds__(kWG) void k_stiff(StiffArgs a) {
         a.r[ie] = r;
         a.out_u[ie] = x0;
         if (a.d0) {
-          a.d0[ie] = stiff_d0(a.theta_inv, o.dinv[e], r);
+          a.d0[ie] = stiff_d0(a.theta_inv, rl<UNI>(o.dinv, e), r);
           rr = fma(r, r, rr);
         }
       }
@@ -231,8 +257,9 @@ __global__ __launch_bounds__(kWG) void k_stiff(StiffArgs a) {
       if (act) {
         double div = 0.0;
 #pragma unroll
-        for (int j = 0; j < 3; j++) div = fma((double)o.csgn[3 * t + j], a.in_u[(size_t)o.cedge[3 * t + j] * Bs + c], div);
-        a.out_eta[it] = stiff_eta(a.scale, o.H, div, o.inv_area[t], a.addA_eta ? a.addA_eta[it] : 0.0,
+        for (int j = 0; j < 3; j++)
+          div = fma((double)rl<UNI>(o.csgn, 3 * t + j), a.in_u[(size_t)rl<UNI>(o.cedge, 3 * t + j) * Bs + c], div);
+        a.out_eta[it] = stiff_eta(a.scale, o.H, div, rl<UNI>(o.inv_area, t), a.addA_eta ? a.addA_eta[it] : 0.0,
                                   a.addB_eta ? a.addB_eta[it] : 0.0);
       }
       if (acc_on) acce = coef * a.in_eta[it];
@@ -562,6 +589,7 @@ __global__ __launch_bounds__(kFWG) void k_cheb_fused(ChebFusedArgs a) {
 // which reads y_i, y_{i-1} and b and writes y_{i+1} (four vectors a step
 // against six); the residual b - M y_i is formed in registers.  The
 // finishing launch adds x += y_K and sums the true final residual.
+template <bool UNI>
 __global__ __launch_bounds__(kWG) void k_cheb3_iter(Cheb3Args a) {
   const Lane L = lane_map(a.Bs, a.ops.ne);
   const DevOps &o = a.ops;
@@ -578,19 +606,21 @@ __global__ __launch_bounds__(kWG) void k_cheb3_iter(Cheb3Args a) {
   }
   double sums[1] = {0.0};
   if (a.colK[c] >= a.kneed) {
-    for (int e = L.row0; e < L.rend; e += L.rstride) {
+    for (int el = L.row0; el < L.rend; el += L.rstride) {
+      const int e = urow<UNI>(el);
       const size_t ie = (size_t)e * Bs + c;
       const double yc = a.y_cur[ie];
-      double q = fma(o.mass[5 * e], yc, 0.0);
+      double q = fma(rl<UNI>(o.mass, 5 * e), yc, 0.0);
 #pragma unroll
-      for (int j = 1; j < 5; j++) q = fma(o.mass[5 * e + j], a.y_cur[(size_t)o.ell_col[5 * e + j] * Bs + c], q);
+      for (int j = 1; j < 5; j++)
+        q = fma(rl<UNI>(o.mass, 5 * e + j), a.y_cur[(size_t)rl<UNI>(o.ell_col, 5 * e + j) * Bs + c], q);
       const double r = a.b[ie] - q;
       if (a.finish) {
         a.x[ie] += yc;
         sums[0] = fma(r, r, sums[0]);
       } else {
         const double yp = a.zero_prev ? 0.0 : a.y_prev[ie];
-        a.y_next[ie] = fma(a.c1, yc - yp, yc) + (a.c2 * o.dinv[e]) * r;
+        a.y_next[ie] = fma(a.c1, yc - yp, yc) + (a.c2 * rl<UNI>(o.dinv, e)) * r;
       }
     }
   }
@@ -761,6 +791,7 @@ __device__ inline float4 f4_fma(float m, float4 v, float4 q) {
   return q;
 }
 
+template <bool UNI>
 __global__ __launch_bounds__(kWG) void k_cheb32_iter4(Cheb32Args a) {
   const int Bq = a.Bs >> 2;
   const Lane L = lane_map(Bq, a.ops.ne);
@@ -778,15 +809,17 @@ __global__ __launch_bounds__(kWG) void k_cheb32_iter4(Cheb32Args a) {
   const float4 *xprev = (const float4 *)a.x_prev;
   const float4 *b4 = (const float4 *)a.b32;
   float4 *xnext = (float4 *)a.x_next;
-  for (int e = L.row0; e < L.rend; e += L.rstride) {
+  for (int el = L.row0; el < L.rend; el += L.rstride) {
+    const int e = urow<UNI>(el);
     float4 q = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 #pragma unroll
-    for (int j = 0; j < 5; j++) q = f4_fma(o.mass32[5 * e + j], xcur[(size_t)o.ell_col[5 * e + j] * Bq + cq], q);
+    for (int j = 0; j < 5; j++)
+      q = f4_fma(rl<UNI>(o.mass32, 5 * e + j), xcur[(size_t)rl<UNI>(o.ell_col, 5 * e + j) * Bq + cq], q);
     const size_t ie = (size_t)e * Bq + cq;
     const float4 xc = xcur[ie];
     const float4 xp = a.zero_prev ? make_float4(0.0f, 0.0f, 0.0f, 0.0f) : xprev[ie];
     const float4 bv = b4[ie];
-    const float g = a.c2 * o.dinv32[e];
+    const float g = a.c2 * rl<UNI>(o.dinv32, e);
     xnext[ie] = make_float4(xc.x + a.c1 * (xc.x - xp.x) + g * (bv.x - q.x),
                             xc.y + a.c1 * (xc.y - xp.y) + g * (bv.y - q.y),
                             xc.z + a.c1 * (xc.z - xp.z) + g * (bv.z - q.z),
@@ -794,20 +827,22 @@ __global__ __launch_bounds__(kWG) void k_cheb32_iter4(Cheb32Args a) {
   }
 }
 
+template <bool UNI>
 __global__ __launch_bounds__(kWG) void k_refine(RefineArgs a) {
   const Lane L = lane_map(a.Bs, a.ops.ne);
   const DevOps &o = a.ops;
   const int c = L.col, Bs = a.Bs;
   double sums[1] = {0.0};
   if (a.colK[c] >= a.kneed) {
-    for (int e = L.row0; e < L.rend; e += L.rstride) {
+    for (int el = L.row0; el < L.rend; el += L.rstride) {
+      const int e = urow<UNI>(el);
       const size_t ie = (size_t)e * Bs + c;
       double r = a.r[ie];
       if (!a.first) {
         double q = 0.0;
 #pragma unroll
         for (int j = 0; j < 5; j++)
-          q += o.mass[5 * e + j] * (double)a.x32[(size_t)o.ell_col[5 * e + j] * Bs + c];
+          q += rl<UNI>(o.mass, 5 * e + j) * (double)a.x32[(size_t)rl<UNI>(o.ell_col, 5 * e + j) * Bs + c];
         a.x[ie] = a.x_zero ? (double)a.x32[ie] : a.x[ie] + (double)a.x32[ie];
         r -= q;
         if (!a.last) a.r[ie] = r;  // the last residual only feeds the check
@@ -817,7 +852,7 @@ __global__ __launch_bounds__(kWG) void k_refine(RefineArgs a) {
       } else {
         const float r32 = (float)r;
         a.r32[ie] = r32;
-        a.d32[ie] = a.theta_inv * o.dinv32[e] * r32;
+        a.d32[ie] = a.theta_inv * rl<UNI>(o.dinv32, e) * r32;
       }
     }
   }
@@ -1287,171 +1322,126 @@ __global__ __launch_bounds__(kWG) void k_reduce_terms(ReduceTermsArgs a) {
 //   C_i = |T| u(xbar) . grad^perp q_i + (s_i/|T|) int |u|^2/2
 //         - sum_a s_a int_{side a} (t_e . u~) q_i ds,
 //   q_i = (k x u) . phi_i (affine on T), eta2 = -sum_a s_a U_a (eta-b)_up / |T|.
+// Everything but the upwind traces u~ is fixed by the cell's geometry, so the
+// operators carry C_i as forms in the cell's edge fluxes U (nlform: a
+// symmetric 3x3 form per i for the volume and kinetic-energy terms, and per
+// side and Gauss point the coefficients of U in q_i); the kernel evaluates
+// the forms (about 120 FP64 operations per cell and column).
 // UNI (blocks of at least 64 columns): a wave works on one cell, so the cell
-// index is made wave-uniform and the cell's tables load through the scalar
-// unit into scalar registers, which leaves room for more waves.
+// index is made wave-uniform and the cell's tables are the same for the
+// whole wave.
 template <bool UNI>
 __global__ __launch_bounds__(kWG) void k_nl_cell(NlArgs a) {
   const Lane L = lane_map(a.Bs, a.ops.nc);
   const DevOps &o = a.ops;
   const int c = L.col, Bs = a.Bs;
-  const double gq = 0.28867513459481288225;  // 1/(2 sqrt 3)
   for (int tl = L.row0; tl < L.rend; tl += L.rstride) {
     const int t = UNI ? __builtin_amdgcn_readfirstlane(tl) : tl;
-    const double *g = o.cgeo + (size_t)t * kCellGeo;
-    double p[3][3], k[3], gl[3][3], len[3];
+    // the cell's edges and its neighbours' edges: one 48-byte record,
+    // loaded whole (12 edge numbers)
+    int s[3], ed[12], nb[3];
+    double F[kNlForm], bt, bn[3], ia;
+    if (UNI) {
+      // the cell's tables, the same for the whole wave: scalar loads
+      const auto *rec = uniform_ro(o.cell_edges) + 12 * (size_t)t;
 #pragma unroll
-    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 12; j++) ed[j] = rec[j];
+      const auto *fr = uniform_ro(o.nlform) + (size_t)kNlForm * t;
 #pragma unroll
-      for (int d = 0; d < 3; d++) {
-        p[i][d] = g[3 * i + d];
-        gl[i][d] = g[13 + 3 * i + d];
+      for (int j = 0; j < kNlForm; j++) F[j] = fr[j];
+#pragma unroll
+      for (int j = 0; j < 3; j++) {
+        s[j] = uniform_ro(o.csgn)[3 * t + j];
+        nb[j] = uniform_ro(o.cnbr)[3 * t + j];
+        bn[j] = uniform_ro(o.bottom)[nb[j]];
       }
-    k[0] = g[9]; k[1] = g[10]; k[2] = g[11];
-    const double A = g[12];
-    len[0] = g[22]; len[1] = g[23]; len[2] = g[24];
-    int s[3], ed[3];
+      bt = uniform_ro(o.bottom)[t];
+      ia = uniform_ro(o.inv_area)[t];
+    } else {
+      const int4 *rec = reinterpret_cast<const int4 *>(o.cell_edges) + 3 * (size_t)t;
+      const int4 q0 = rec[0], q1 = rec[1], q2 = rec[2];
+      ed[0] = q0.x; ed[1] = q0.y; ed[2] = q0.z; ed[3] = q0.w;
+      ed[4] = q1.x; ed[5] = q1.y; ed[6] = q1.z; ed[7] = q1.w;
+      ed[8] = q2.x; ed[9] = q2.y; ed[10] = q2.z; ed[11] = q2.w;
+      const double *fr = o.nlform + (size_t)kNlForm * t;
+#pragma unroll
+      for (int j = 0; j < kNlForm; j++) F[j] = fr[j];
+#pragma unroll
+      for (int j = 0; j < 3; j++) {
+        s[j] = o.csgn[3 * t + j];
+        nb[j] = o.cnbr[3 * t + j];
+        bn[j] = o.bottom[nb[j]];
+      }
+      bt = o.bottom[t];
+      ia = o.inv_area[t];
+    }
     double U[3];
 #pragma unroll
-    for (int j = 0; j < 3; j++) {
-      s[j] = o.csgn[3 * t + j];
-      ed[j] = o.cedge[3 * t + j];
-      U[j] = a.u[(size_t)ed[j] * Bs + c];
-    }
-    // u(x) = al + be x
-    const double inv2A = 0.5 / A;
-    double be = 0.0, al[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int j = 0; j < 3; j++) {
-      const double w = s[j] * U[j] * inv2A;
-      be += w;
-#pragma unroll
-      for (int d = 0; d < 3; d++) al[d] -= w * p[j][d];
-    }
-    auto vel = [&](const double *x, double *u) {
-#pragma unroll
-      for (int d = 0; d < 3; d++) u[d] = al[d] + be * x[d];
-    };
-    // ku(x) = k x u(x); q_i(x) = s_i/(2A) ku(x).(x - p_i)
-    auto kxu = [&](const double *x, double *r) {
-      double u[3];
-      vel(x, u);
-      r[0] = k[1] * u[2] - k[2] * u[1];
-      r[1] = k[2] * u[0] - k[0] * u[2];
-      r[2] = k[0] * u[1] - k[1] * u[0];
-    };
-    // kinetic energy integral (side midpoints, weight A/3)
-    double ke = 0.0;
-#pragma unroll
-    for (int q = 0; q < 3; q++) {
-      double x[3], u[3];
-#pragma unroll
-      for (int d = 0; d < 3; d++) x[d] = 0.5 * (p[(q + 1) % 3][d] + p[(q + 2) % 3][d]);
-      vel(x, u);
-      ke += (A / 3.0) * 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    }
-    double ubar[3];
-    {
-      double xb[3];
-#pragma unroll
-      for (int d = 0; d < 3; d++) xb[d] = (p[0][d] + p[1][d] + p[2][d]) * (1.0 / 3.0);
-      vel(xb, ubar);
-    }
-    // k x u at the vertices (for grad q_i)
-    double kuv[3][3];
-#pragma unroll
-    for (int j = 0; j < 3; j++) kxu(p[j], kuv[j]);
-    // volume and kinetic-energy terms of C_i
+    for (int j = 0; j < 3; j++) U[j] = a.u[(size_t)ed[j] * Bs + c];
+    // volume and kinetic-energy terms: U^T S_i U
+    const double P[6] = {U[0] * U[0], U[1] * U[1], U[2] * U[2], U[0] * U[1], U[0] * U[2], U[1] * U[2]};
     double Cv[3];
 #pragma unroll
     for (int i = 0; i < 3; i++) {
-      const double si = s[i] * inv2A;
-      // grad q_i = sum_j q_i(p_j) grad lambda_j
-      double gqv[3] = {0.0, 0.0, 0.0};
+      double v = F[6 * i] * P[0];
 #pragma unroll
-      for (int j = 0; j < 3; j++) {
-        if (j == i) continue;
-        double qj = 0.0;
-#pragma unroll
-        for (int d = 0; d < 3; d++) qj += kuv[j][d] * (p[j][d] - p[i][d]);
-        qj *= si;
-#pragma unroll
-        for (int d = 0; d < 3; d++) gqv[d] += qj * gl[j][d];
-      }
-      // grad^perp q = k x grad q
-      const double gp0 = k[1] * gqv[2] - k[2] * gqv[1];
-      const double gp1 = k[2] * gqv[0] - k[0] * gqv[2];
-      const double gp2 = k[0] * gqv[1] - k[1] * gqv[0];
-      Cv[i] = A * (ubar[0] * gp0 + ubar[1] * gp1 + ubar[2] * gp2);
-      Cv[i] += s[i] * ke / A;
+      for (int m = 1; m < 6; m++) v = fma(F[6 * i + m], P[m], v);
+      Cv[i] = v;
     }
-    // facet terms: side by side, the two Gauss points of a side formed once
-    // for the three test functions (k x u and the upwind tangential velocity
-    // at the point), so that few point values are live at a time
+    // facet terms, side by side: the upwind tangential velocity at the
+    // side's two Gauss points, from the cell the edge flux leaves (flux > 0:
+    // the edge's first cell, otherwise its second), that cell's three edges
+    // against the edge's trace table.  This cell is the edge's first cell
+    // exactly when s = +1, so the upwind cell is this one when the flux and s
+    // have the same sign, else the neighbour across the side.  The upwind
+    // cell's edges and table are chosen per column as row numbers and
+    // offsets, so that every column loads (no branch around the loads).
+    double uu[3][3];
+    const double *tau[3];
 #pragma unroll
     for (int aa = 0; aa < 3; aa++) {
-      // global order a -> b is the cell's CCW order when s = +1
-      const int ia = s[aa] > 0 ? (aa + 1) % 3 : (aa + 2) % 3;
-      const int ib = s[aa] > 0 ? (aa + 2) % 3 : (aa + 1) % 3;
-      // upwind tangential velocity at the side's two Gauss points, from the
-      // cell the edge flux leaves (flux > 0: the edge's first cell, otherwise
-      // its second): that cell's three edges against the edge's trace table;
-      // when the upwind cell is this one, its edge values are U
-      const int E = ed[aa];
-      const int up = U[aa] > 0.0 ? 0 : 1;
-      const double *tau = o.tau + (size_t)kEdgeTau * E + 6 * up;
-      double uu[3];
-      if (o.ecell[2 * E + up] == t) {
+      const int sid = s[aa] > 0 ? 0 : 1;  // this cell's place in the edge's cell pair
+      const bool self_up = (U[aa] > 0.0) == (s[aa] > 0);
+      tau[aa] = o.tau + (size_t)kEdgeTau * ed[aa] + 6 * (self_up ? sid : 1 - sid);
 #pragma unroll
-        for (int j = 0; j < 3; j++) uu[j] = U[j];
-      } else {
-        const int *se = o.side_edges + 6 * E + 3 * up;
+      for (int j = 0; j < 3; j++) uu[aa][j] = a.u[(size_t)(self_up ? ed[j] : ed[3 + 3 * aa + j]) * Bs + c];
+    }
 #pragma unroll
-        for (int j = 0; j < 3; j++) uu[j] = a.u[(size_t)se[j] * Bs + c];
-      }
-      double utg[2] = {0.0, 0.0};
-#pragma unroll
-      for (int j = 0; j < 3; j++) {
-        utg[0] += tau[j] * uu[j];
-        utg[1] += tau[3 + j] * uu[j];
-      }
-      double f[3] = {0.0, 0.0, 0.0};
+    for (int aa = 0; aa < 3; aa++) {
 #pragma unroll
       for (int gp = 0; gp < 2; gp++) {
-        const double xi = gp == 0 ? 0.5 - gq : 0.5 + gq;
-        double xg[3], kug[3];
-#pragma unroll
-        for (int d = 0; d < 3; d++) xg[d] = p[ia][d] + xi * (p[ib][d] - p[ia][d]);
-        kxu(xg, kug);
+        double utg = tau[aa][3 * gp] * uu[aa][0];
+        utg = fma(tau[aa][3 * gp + 1], uu[aa][1], utg);
+        utg = fma(tau[aa][3 * gp + 2], uu[aa][2], utg);
+        const double *H = F + 18 + (2 * aa + gp) * 9;
 #pragma unroll
         for (int i = 0; i < 3; i++) {
-          double qv = 0.0;
-#pragma unroll
-          for (int d = 0; d < 3; d++) qv += kug[d] * (xg[d] - p[i][d]);
-          f[i] += utg[gp] * qv * (s[i] * inv2A);
+          double q = H[3 * i] * U[0];
+          q = fma(H[3 * i + 1], U[1], q);
+          q = fma(H[3 * i + 2], U[2], q);
+          Cv[i] = fma(utg, q, Cv[i]);
         }
       }
-#pragma unroll
-      for (int i = 0; i < 3; i++) Cv[i] -= s[aa] * 0.5 * len[aa] * f[i];
     }
 #pragma unroll
     for (int i = 0; i < 3; i++) a.C[((size_t)3 * t + i) * Bs + c] = Cv[i];
-    // depth: upwind (eta - b) on every side
+    // depth: upwind (eta - b) on every side (this cell or the neighbour,
+    // chosen per column as a row number as above)
     const size_t it = (size_t)t * Bs + c;
     double r = 0.0;
 #pragma unroll
     for (int aa = 0; aa < 3; aa++) {
-      const bool up_c0 = U[aa] > 0.0;
-      const bool self_c0 = s[aa] > 0;
-      const int cu = (up_c0 == self_c0) ? t : o.cnbr[3 * t + aa];
-      const double hv = a.eta[(size_t)cu * Bs + c] - o.bottom[cu];
+      const bool self_up = (U[aa] > 0.0) == (s[aa] > 0);
+      const int cu = self_up ? t : nb[aa];
+      const double hv = a.eta[(size_t)cu * Bs + c] - (self_up ? bt : bn[aa]);
       r -= s[aa] * U[aa] * hv;
     }
-    a.out_eta[it] = r * o.inv_area[t];
+    a.out_eta[it] = r * ia;
   }
 }
 
 // Velocity right-hand side r_e = C[c0][l0] + C[c1][l1] and CG start x = 0.
+template <bool UNI>
 __global__ __launch_bounds__(kWG) void k_nl_gather(GatherArgs a) {
   folded_check(a.chk, a.chk_blocks);
   const Lane L = lane_map(a.Bs, a.ops.ne);
@@ -1459,16 +1449,17 @@ __global__ __launch_bounds__(kWG) void k_nl_gather(GatherArgs a) {
   const int c = L.col, Bs = a.Bs;
   double rr = 0.0;
   if (a.colK[c] >= a.kneed) {
-    for (int e = L.row0; e < L.rend; e += L.rstride) {
+    for (int el = L.row0; el < L.rend; el += L.rstride) {
+      const int e = urow<UNI>(el);
       const size_t ie = (size_t)e * Bs + c;
-      const double r = a.C[(size_t)o.cidx[2 * e] * Bs + c] + a.C[(size_t)o.cidx[2 * e + 1] * Bs + c];
+      const double r = a.C[(size_t)rl<UNI>(o.cidx, 2 * e) * Bs + c] + a.C[(size_t)rl<UNI>(o.cidx, 2 * e + 1) * Bs + c];
       a.r[ie] = r;
       if (!a.r32) a.x[ie] = 0.0;  // the refined solve's first refinement writes x
-      if (a.d0) a.d0[ie] = a.theta_inv * o.dinv[e] * r;
+      if (a.d0) a.d0[ie] = a.theta_inv * rl<UNI>(o.dinv, e) * r;
       if (a.r32) {
         const float r32 = (float)r;
         a.r32[ie] = r32;
-        a.x1_32[ie] = a.theta_inv32 * o.dinv32[e] * r32;
+        a.x1_32[ie] = a.theta_inv32 * rl<UNI>(o.dinv32, e) * r32;
       }
       if (a.part_rr) rr += r * r;
     }
@@ -1697,6 +1688,16 @@ int grid_tiles_pipe(size_t n) {
   return (int)(g < 512 ? (g > 0 ? g : 1) : 512);
 }
 dim3 rows_grid(int rows, int Bs) { return dim3(grid_rows(rows, Bs), (Bs + 63) / 64); }
+// One pass over the rows, a row (and up to 64 columns) a wave: for kernels
+// that keep no per-workgroup partials and whose rows each wait on dependent
+// gathers (the cell kernel of N), so that as many rows as fit are in flight.
+dim3 rows_grid_full(int rows, int Bs) {
+  const int ct = Bs < 64 ? Bs : 64;
+  const int rows_per_pass = (kWG / 64) * (64 / ct);
+  int g = (rows + rows_per_pass - 1) / rows_per_pass;
+  g = (g + 7) / 8 * 8;
+  return dim3(g > 0 ? g : 8, (Bs + 63) / 64);
+}
 }  // namespace
 
 int launch_max_wg() { return 2048; }
@@ -1715,7 +1716,10 @@ int launch_rows_grid(int rows, int Bs) { return grid_rows(rows, Bs); }
 
 void launch_stiff(const StiffArgs &a, hipStream_t s) {
   const int nrow = a.ops.ne > a.ops.nc ? a.ops.ne : a.ops.nc;
-  hipLaunchKernelGGL(k_stiff, rows_grid(nrow, a.Bs), dim3(kWG), 0, s, a);
+  if (a.Bs >= 64)
+    hipLaunchKernelGGL(k_stiff<true>, rows_grid(nrow, a.Bs), dim3(kWG), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_stiff<false>, rows_grid(nrow, a.Bs), dim3(kWG), 0, s, a);
 }
 void launch_cg_init(const CgArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_cg_init, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
@@ -1729,7 +1733,10 @@ void launch_cheb_iter(const ChebArgs &a, hipStream_t s) {
   launch_timed(k_cheb_iter, rows_grid(a.ops.ne, a.Bs), s, a);
 }
 void launch_cheb3_iter(const Cheb3Args &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_cheb3_iter, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+  if (a.Bs >= 64)
+    hipLaunchKernelGGL(k_cheb3_iter<true>, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_cheb3_iter<false>, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
 }
 int cheb_fused_grid(const DevOps &o, int extra) {
   if (o.hparts <= 0 || o.fused_max < 2) return 0;
@@ -1784,12 +1791,18 @@ void launch_cheb32_iter(const Cheb32Args &a, hipStream_t s) {
   // the row mapping needs a power-of-two width up to 64, or a multiple of 64
   const int bq = a.Bs / 4;
   if (a.Bs >= 8 && a.Bs % 4 == 0 && ((bq & (bq - 1)) == 0 || bq % 64 == 0))
-    hipLaunchKernelGGL(k_cheb32_iter4, rows_grid(a.ops.ne, a.Bs / 4), dim3(kWG), 0, s, a);
+    if (a.Bs / 4 >= 64)
+      hipLaunchKernelGGL(k_cheb32_iter4<true>, rows_grid(a.ops.ne, a.Bs / 4), dim3(kWG), 0, s, a);
+    else
+      hipLaunchKernelGGL(k_cheb32_iter4<false>, rows_grid(a.ops.ne, a.Bs / 4), dim3(kWG), 0, s, a);
   else
     hipLaunchKernelGGL(k_cheb32_iter, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
 }
 void launch_refine(const RefineArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_refine, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+  if (a.Bs >= 64)
+    hipLaunchKernelGGL(k_refine<true>, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_refine<false>, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
 }
 void launch_cg_iter(const CgArgs &a, hipStream_t s) {
   launch_timed(k_cg_iter, rows_grid(a.ops.ne, a.Bs), s, a);
@@ -1808,12 +1821,15 @@ void launch_reduce_terms(const ReduceTermsArgs &a, hipStream_t s) {
 }
 void launch_nl_cell(const NlArgs &a, hipStream_t s) {
   if (a.Bs >= 64)
-    hipLaunchKernelGGL(k_nl_cell<true>, rows_grid(a.ops.nc, a.Bs), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL(k_nl_cell<true>, rows_grid_full(a.ops.nc, a.Bs), dim3(kWG), 0, s, a);
   else
-    hipLaunchKernelGGL(k_nl_cell<false>, rows_grid(a.ops.nc, a.Bs), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL(k_nl_cell<false>, rows_grid_full(a.ops.nc, a.Bs), dim3(kWG), 0, s, a);
 }
 void launch_nl_gather(const GatherArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_nl_gather, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+  if (a.Bs >= 64)
+    hipLaunchKernelGGL(k_nl_gather<true>, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_nl_gather<false>, rows_grid(a.ops.ne, a.Bs), dim3(kWG), 0, s, a);
 }
 void launch_acc(const AccArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_acc, rows_grid(a.nrows, a.Bs), dim3(kWG), 0, s, a);
