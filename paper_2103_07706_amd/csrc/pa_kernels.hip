@@ -14,7 +14,7 @@
 // atomics).
 //
 // The single-column Jacobi Chebyshev solves run several steps per launch on
-// 256-row parts with rings of halo rows (k_cheb_fused; the row parts and
+// 512-row parts with rings of halo rows (k_cheb_fused; the row parts and
 // rings are built with the operators).
 #include <hip/hip_runtime.h>
 
@@ -81,6 +81,16 @@ __device__ inline T rl(const T *p, size_t i) {
     return uniform_ro(p)[i];
   else
     return p[i];
+}
+
+template <bool UNI>
+__device__ inline uint2 rl(const uint2 *p, size_t i) {
+  if constexpr (UNI) {
+    const unsigned long long v = uniform_ro(reinterpret_cast<const unsigned long long *>(p))[i];
+    return make_uint2((unsigned)v, (unsigned)(v >> 32));
+  } else {
+    return p[i];
+  }
 }
 
 // Sum v over lanes that share a column (lane % ct), result valid in lanes < ct.
@@ -636,25 +646,25 @@ __global__ __launch_bounds__(kWG) void k_cheb3_iter(Cheb3Args a) {
 // residual; the FP32 rounding of P and P M only perturbs the preconditioner.
 // sum_j val_j v[col_j] over W packed entries of row e (column-major table);
 // W > 0: fixed width, every load issued before the first use.
-template <int W>
+template <int W, bool UNI>
 __device__ inline double lp_row_dot(const uint2 *t, int w, int ne, int e, const double *v, int Bs, int c) {
   double z = 0.0;
   if constexpr (W > 0) {
     uint2 q[W];
 #pragma unroll
-    for (int j = 0; j < W; j++) q[j] = t[(size_t)j * ne + e];
+    for (int j = 0; j < W; j++) q[j] = rl<UNI>(t, (size_t)j * ne + e);
 #pragma unroll
     for (int j = 0; j < W; j++) z += (double)__uint_as_float(q[j].y) * v[(size_t)q[j].x * Bs + c];
   } else {
     for (int j = 0; j < w; j++) {
-      const uint2 q = t[(size_t)j * ne + e];
+      const uint2 q = rl<UNI>(t, (size_t)j * ne + e);
       z += (double)__uint_as_float(q.y) * v[(size_t)q.x * Bs + c];
     }
   }
   return z;
 }
 
-template <int WP, int WPM>
+template <int WP, int WPM, bool UNI>
 __global__ __launch_bounds__(kWG) void k_cheb_lp_iter(ChebLpArgs a) {
   const Lane L = lane_map(a.Bs, a.ops.ne);
   const DevOps &o = a.ops;
@@ -671,14 +681,15 @@ __global__ __launch_bounds__(kWG) void k_cheb_lp_iter(ChebLpArgs a) {
   const uint2 *__restrict__ tpm = a.lp.pm;
   double sums[1] = {0.0};
   if (a.colK[c] >= a.kneed) {
-    for (int e = L.row0; e < L.rend; e += L.rstride) {
+    for (int el = L.row0; el < L.rend; el += L.rstride) {
+      const int e = urow<UNI>(el);
       // every table entry and gathered operand is loaded before any store
       int mc[5];
       double mv[5], dg[5];
 #pragma unroll
       for (int j = 0; j < 5; j++) {
-        mc[j] = o.ell_col[5 * e + j];
-        mv[j] = o.mass[5 * e + j];
+        mc[j] = rl<UNI>(o.ell_col, 5 * e + j);
+        mv[j] = rl<UNI>(o.mass, 5 * e + j);
       }
       const size_t ie = (size_t)e * Bs + c;
       const double d = din[ie], r0 = rin[ie], x0 = a.x[ie];
@@ -689,9 +700,9 @@ __global__ __launch_bounds__(kWG) void k_cheb_lp_iter(ChebLpArgs a) {
         if constexpr (WP > 0 && WPM > 0) {
           uint2 qp[WP], qm[WPM];
 #pragma unroll
-          for (int j = 0; j < WP; j++) qp[j] = tp[(size_t)j * ne + e];
+          for (int j = 0; j < WP; j++) qp[j] = rl<UNI>(tp, (size_t)j * ne + e);
 #pragma unroll
-          for (int j = 0; j < WPM; j++) qm[j] = tpm[(size_t)j * ne + e];
+          for (int j = 0; j < WPM; j++) qm[j] = rl<UNI>(tpm, (size_t)j * ne + e);
           double gp[WP], gm[WPM];
 #pragma unroll
           for (int j = 0; j < WP; j++) gp[j] = rin[(size_t)qp[j].x * Bs + c];
@@ -702,7 +713,7 @@ __global__ __launch_bounds__(kWG) void k_cheb_lp_iter(ChebLpArgs a) {
 #pragma unroll
           for (int j = 0; j < WPM; j++) z -= (double)__uint_as_float(qm[j].y) * gm[j];
         } else {
-          z = lp_row_dot<0>(tp, a.lp.wp, ne, e, rin, Bs, c) - lp_row_dot<0>(tpm, a.lp.wpm, ne, e, din, Bs, c);
+          z = lp_row_dot<0, UNI>(tp, a.lp.wp, ne, e, rin, Bs, c) - lp_row_dot<0, UNI>(tpm, a.lp.wpm, ne, e, din, Bs, c);
         }
       }
       double q = 0.0;
@@ -720,14 +731,15 @@ __global__ __launch_bounds__(kWG) void k_cheb_lp_iter(ChebLpArgs a) {
   if (a.last) wg_partials<1>(L, sums, a.part, a.max_wg);
 }
 
-template <int WP>
+template <int WP, bool UNI>
 __global__ __launch_bounds__(kWG) void k_lp_dir(LpDirArgs a) {
   const Lane L = lane_map(a.Bs, a.ops.ne);
   const int c = L.col, Bs = a.Bs, ne = a.ops.ne;
   if (a.colK[c] < a.kneed) return;
-  for (int e = L.row0; e < L.rend; e += L.rstride) {
+  for (int el = L.row0; el < L.rend; el += L.rstride) {
+    const int e = urow<UNI>(el);
     const size_t ie = (size_t)e * Bs + c;
-    const double z = lp_row_dot<WP>(a.lp.p, a.lp.wp, ne, e, a.r, Bs, c);
+    const double z = lp_row_dot<WP, UNI>(a.lp.p, a.lp.wp, ne, e, a.r, Bs, c);
     a.d_out[ie] = (a.c1 != 0.0 ? a.c1 * a.d_in[ie] : 0.0) + a.c2 * z;
   }
 }
@@ -1764,17 +1776,28 @@ void launch_cheb_fused(const ChebFusedArgs &a, hipStream_t s) {
 // The icosahedral meshes give P and P M widths 13 and 27 at every level;
 // other widths take the generic loop.
 void launch_cheb_lp_iter(const ChebLpArgs &a, hipStream_t s) {
-  const bool fixed = a.lp.wp == 13 && a.lp.wpm == 27;
-  if (fixed)
-    launch_timed(k_cheb_lp_iter<13, 27>, rows_grid(a.ops.ne, a.Bs), s, a);
+  const bool fixed = a.lp.wp == 13 && a.lp.wpm == 27, uni = a.Bs >= 64;
+  const dim3 g = rows_grid(a.ops.ne, a.Bs);
+  if (fixed && uni)
+    launch_timed(k_cheb_lp_iter<13, 27, true>, g, s, a);
+  else if (fixed)
+    launch_timed(k_cheb_lp_iter<13, 27, false>, g, s, a);
+  else if (uni)
+    launch_timed(k_cheb_lp_iter<0, 0, true>, g, s, a);
   else
-    launch_timed(k_cheb_lp_iter<0, 0>, rows_grid(a.ops.ne, a.Bs), s, a);
+    launch_timed(k_cheb_lp_iter<0, 0, false>, g, s, a);
 }
 void launch_lp_dir(const LpDirArgs &a, hipStream_t s) {
-  if (a.lp.wp == 13)
-    launch_timed(k_lp_dir<13>, rows_grid(a.ops.ne, a.Bs), s, a);
+  const bool uni = a.Bs >= 64;
+  const dim3 g = rows_grid(a.ops.ne, a.Bs);
+  if (a.lp.wp == 13 && uni)
+    launch_timed(k_lp_dir<13, true>, g, s, a);
+  else if (a.lp.wp == 13)
+    launch_timed(k_lp_dir<13, false>, g, s, a);
+  else if (uni)
+    launch_timed(k_lp_dir<0, true>, g, s, a);
   else
-    launch_timed(k_lp_dir<0>, rows_grid(a.ops.ne, a.Bs), s, a);
+    launch_timed(k_lp_dir<0, false>, g, s, a);
 }
 int cheb_check_blocks(const CheckArgs &a) {
   const int ct = a.Bs < 64 ? a.Bs : 64;
