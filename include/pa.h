@@ -283,9 +283,10 @@ int pa_ctx_set_cg_budget(pa_ctx *ctx, double cg_rtol, int iters);
  * pa_phase_avg_rhs over a small set of shapes on the given problem (the
  * workspace must fit it), then, with the learned preconditioner or FP32
  * refinement enabled in cfg, over lp_min_cols and mixed_min_cols in {1, 8,
- * 64, never}, and keeps the fastest; it returns the choice and the best
- * time.  fused_steps (1 to 6) is the number of Jacobi Chebyshev steps of a
- * single-column mass solve per launch (a workgroup owns a part of 256 rows
+ * 64, never}, then over fused_steps, then over the shapes once more with
+ * the fields found, and keeps the fastest; it returns the choice and the
+ * best time.  fused_steps (1 to 6) is the number of Jacobi Chebyshev steps of a
+ * single-column mass solve per launch (a workgroup owns a part of 512 rows
  * and forms the earlier steps again on the rings of rows its later steps
  * read; the results are the same as one step per launch); the autotuner
  * tries each. */

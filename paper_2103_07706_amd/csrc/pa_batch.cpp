@@ -396,13 +396,16 @@ int pa_batch_autotune(pa_ctx *ctx, pa_batch *b, const double *const *U_dev,
           best_t = t;
         }
       };
-      for (int rpt : {1, 2, 4, 8})
-        for (int cap : {512, 1024, 2048}) {
-          pa::LaunchTune t = b->item_tune(i);
-          t.narrow_rows_per_thread = rpt;
-          t.wide_max_wg = cap;
-          trial(t);
-        }
+      auto shapes = [&](const pa::LaunchTune &from) {
+        for (int rpt : {1, 2, 4, 8})
+          for (int cap : {512, 1024, 2048}) {
+            pa::LaunchTune t = from;
+            t.narrow_rows_per_thread = rpt;
+            t.wide_max_wg = cap;
+            trial(t);
+          }
+      };
+      shapes(b->item_tune(i));
       for (int lmin : {1, 8, 64, 1 << 30}) {
         pa::LaunchTune t = best_t;
         if (c.precond == PA_PRECOND_LEARNED) {
@@ -423,6 +426,8 @@ int pa_batch_autotune(pa_ctx *ctx, pa_batch *b, const double *const *U_dev,
           t.fused_steps = ps;
           trial(t);
         }
+      // the shape again for the fields found
+      shapes(best_t);
       b->tune[i] = best_t;
       b->tuned[i] = true;
       if (out) {

@@ -584,10 +584,12 @@ int pa_autotune(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int members, 
       });
       return st.device_ms;
     };
-    try {
+    // the launch shape over rows per thread and workgroup caps, the other
+    // fields as in `from`
+    auto shapes = [&](const pa::LaunchTune &from) {
       for (int rpt : rpts)
         for (int cap : caps) {
-          pa::LaunchTune t = keep;
+          pa::LaunchTune t = from;
           t.narrow_rows_per_thread = rpt;
           t.wide_max_wg = cap;
           pa::set_launch_tuning(t);
@@ -598,6 +600,9 @@ int pa_autotune(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int members, 
             best_t = t;
           }
         }
+    };
+    try {
+      shapes(keep);
       auto search = [&](int pa::LaunchTune::*field, std::initializer_list<int> vals) {
         for (int lmin : vals) {
           pa::LaunchTune t = best_t;
@@ -614,6 +619,9 @@ int pa_autotune(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int members, 
       if (c.precond == PA_PRECOND_LEARNED) search(&pa::LaunchTune::lp_min_cols, {1, 8, 64, kLpNever});
       if (c.precision == PA_FP32_REFINED) search(&pa::LaunchTune::mixed_min_cols, {1, 8, 64, kLpNever});
       if (c.solver == PA_SOLVER_CHEBYSHEV) search(&pa::LaunchTune::fused_steps, {1, 2, 3, 4, 5, 6});
+      // the shape again for the fields found (a learned threshold, a mixed
+      // threshold or a step count can change which shape is fastest)
+      shapes(best_t);
     } catch (...) {
       pa::set_launch_tuning(keep);
       throw;
