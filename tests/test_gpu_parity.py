@@ -77,6 +77,36 @@ def test_gpu_phase_avg_members_independent():
         assert rel_w(oo, mm.back(allm[j]), ref) < 1e-13
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_refined"])
+def test_gpu_wide_ensemble_parity(precision):
+    """64 members in one call (level 3, M = 8): the recurrences run on
+    64-column blocks and the solve of N on a 512-column block, so the block
+    kernels take their one-row-a-wave form (row tables read through the
+    scalar unit), including the FP32 step over four columns a lane at 256 or
+    more columns.  Sampled members against the FP64 oracle, and the state
+    block's member order kept (every member differs from its neighbour)."""
+    from paper_2103_07706_amd import pa
+    om, oo, lm, lo, mm, lb = pair(3)
+    U = bumps(om, range(100, 164))
+    avg = pa.Avg(8, 3600.0)
+    kw = dict(backward=pa.PA_BACKWARD_CLENSHAW, solver=pa.PA_SOLVER_CHEBYSHEV, weight_cut=0.0)
+    if precision == "fp64":
+        cfg = pa.solve_cfg(**kw, **PARITY)
+        tol = TOL
+    else:
+        cfg = pa.solve_cfg(**kw, precision=pa.PA_FP32_REFINED, cheb_tol=1e-13, cg_rtol=1e-12)
+        tol = 1e-10
+    out, st = lo.phase_avg_rhs(avg, to_dev(mm.state(U)), cfg)
+    if precision == "fp32_refined":
+        assert st["refinements"] > 0
+    got = mm.back(out.cpu().numpy())
+    assert np.all(np.isfinite(got))
+    for m in (0, 21, 42, 63):
+        ref = oo.phase_avg_rhs(lb, avg.s, avg.w, U[m], tol=1e-13, rtol=1e-14)
+        assert rel_w(oo, got[m], ref) < tol, (m, rel_w(oo, got[m], ref))
+        assert rel_w(oo, got[m + 1 if m < 63 else m - 1], ref) > 1e-3
+
+
 def test_gpu_step_parity():
     from paper_2103_07706_amd import pa
     om, oo, lm, lo, mm, lb = pair(3)
