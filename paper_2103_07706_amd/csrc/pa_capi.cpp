@@ -253,7 +253,7 @@ int pa_ops_bind(pa_ctx *ctx, pa_ops *ops, void *dev_buf) {
     up(s, d.ring_row, ops->ring_row);
     up(s, d.hloc, ops->hloc);
     up(s, d.ring_loc, ops->ring_loc);
-    PA_HIP(hipStreamSynchronize(s));
+    pa::sync_checked(s);
   });
 }
 

@@ -599,7 +599,7 @@ void Engine::finish() {
   // (pad), resid_max bits
   int h[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
   PA_HIP(hipMemcpyAsync(h, st_.fail, 12 * sizeof(int), hipMemcpyDeviceToHost, s_));
-  PA_HIP(hipStreamSynchronize(s_));
+  sync_checked(s_);
   {
     unsigned long long bits;
     std::memcpy(&bits, &h[8], sizeof(bits));
@@ -785,7 +785,7 @@ void Engine::cg(double *x, int Bs, const int *colK, int kneed, int nwg_init) {
   };
   auto poll = [&](int slot) {
     PA_HIP(hipMemcpyAsync(hflag, st_.cnt + slot, sizeof(int), hipMemcpyDeviceToHost, s_));
-    PA_HIP(hipStreamSynchronize(s_));
+    sync_checked(s_);
     return *hflag;
   };
   // w_0 = M D^-1 r_0 and the first partials
@@ -1407,7 +1407,7 @@ double Engine::estimate_lambda(int iters) {
     diag(x, wd);
     double hv[5];
     PA_HIP(hipMemcpyAsync(hv, wd, 5 * sizeof(double), hipMemcpyDeviceToHost, s_));
-    PA_HIP(hipStreamSynchronize(s_));
+    sync_checked(s_);
     return ops_->H * hv[0] + ops_->g * hv[2];
   };
   double rho2 = 0.0;

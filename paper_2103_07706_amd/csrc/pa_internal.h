@@ -58,6 +58,14 @@ int guard(F &&f) {
       throw ::pa::Error(PA_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// Waits for the stream.  A launch that failed to start (launch
+// configuration, missing code object) leaves its error for hipGetLastError
+// only, so that is checked first.
+inline void sync_checked(hipStream_t s) {
+  PA_HIP(hipGetLastError());
+  PA_HIP(hipStreamSynchronize(s));
+}
+
 // ---------------------------------------------------------------- host mesh
 struct Mesh {
   int level = 0;

@@ -84,7 +84,7 @@ class LpRunner {
   std::vector<float> download_theta() {
     std::vector<float> th(L_.total);
     PA_HIP(hipMemcpyAsync(th.data(), theta_, th.size() * sizeof(float), hipMemcpyDeviceToHost, s_));
-    PA_HIP(hipStreamSynchronize(s_));
+    sync_checked(s_);
     return th;
   }
   void zero_grad() { launch_zero((unsigned *)grad_, (size_t)L_.total * 2, s_); }
@@ -209,7 +209,7 @@ class LpRunner {
     zcur_ = zinv_ + (size_t)kLpProbeMax * graphs_.size();
     PA_HIP(hipMemcpyAsync(Z_, Zh, sizeof(double) * (size_t)graphs_[0].ne * P_, hipMemcpyHostToDevice, s_));
     PA_HIP(hipMemcpyAsync(zcur_, zinv_h, sizeof(double) * P_, hipMemcpyHostToDevice, s_));
-    PA_HIP(hipStreamSynchronize(s_));
+    sync_checked(s_);
   }
   void set_probes_random(int gi, uint64_t seed) {
     launch_lp_rademacher(Z_, graphs_[gi].ne, P_, seed, s_);
@@ -236,13 +236,13 @@ class LpRunner {
   std::vector<double> losses() {
     std::vector<double> h(nslots_);
     PA_HIP(hipMemcpyAsync(h.data(), loss_, sizeof(double) * nslots_, hipMemcpyDeviceToHost, s_));
-    PA_HIP(hipStreamSynchronize(s_));
+    sync_checked(s_);
     return h;
   }
   std::vector<double> grad_host() {
     std::vector<double> h(L_.total);
     PA_HIP(hipMemcpyAsync(h.data(), grad_, sizeof(double) * L_.total, hipMemcpyDeviceToHost, s_));
-    PA_HIP(hipStreamSynchronize(s_));
+    sync_checked(s_);
     return h;
   }
   void ghat_host(std::vector<double> &gd, std::vector<double> &goff) {
@@ -251,9 +251,9 @@ class LpRunner {
     goff.resize(4 * (size_t)ne);
     PA_HIP(hipMemcpyAsync(gd.data(), gd_, sizeof(double) * ne, hipMemcpyDeviceToHost, s_));
     PA_HIP(hipMemcpyAsync(goff.data(), goff_, sizeof(double) * 4 * ne, hipMemcpyDeviceToHost, s_));
-    PA_HIP(hipStreamSynchronize(s_));
+    sync_checked(s_);
   }
-  void sync() { PA_HIP(hipStreamSynchronize(s_)); }
+  void sync() { sync_checked(s_); }
   hipStream_t stream() const { return s_; }
 
  private:
@@ -560,7 +560,7 @@ int pa_ops_lp_bind(pa_ctx *ctx, pa_ops *ops, void *dev_buf) {
     hipStream_t s = ctx->stream;
     PA_HIP(hipMemcpyAsync((void *)d.p, hp.data(), n1 * 8, hipMemcpyHostToDevice, s));
     PA_HIP(hipMemcpyAsync((void *)d.pm, hpm.data(), n2 * 8, hipMemcpyHostToDevice, s));
-    PA_HIP(hipStreamSynchronize(s));
+    pa::sync_checked(s);
     ops->lp = d;
     ops->lp_dev = dev_buf;
   });
