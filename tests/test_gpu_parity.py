@@ -107,6 +107,42 @@ def test_gpu_wide_ensemble_parity(precision):
         assert rel_w(oo, got[m + 1 if m < 63 else m - 1], ref) > 1e-3
 
 
+@pytest.mark.parametrize("solver", [0, 1])
+def test_gpu_rest_states(solver):
+    """Degenerate states.  The zero state: the averaged right-hand side, the
+    nonlinearity, the step and the exponential all return exact zeros (no
+    0/0 in the relative residual checks of zero right-hand sides).  A lake at
+    rest (u = 0, constant depth, no topography): the discrete gradient of a
+    constant and the divergence of zero flux vanish exactly, so every
+    Chebyshev basis vector is +-U or 0 and N of each is exactly zero; the
+    exponential and the step return U up to the Chebyshev truncation.
+    t = 0: the exponential returns U."""
+    from paper_2103_07706_amd import pa
+    om, oo, lm, lo, mm, lb = pair(3)
+    avg = pa.Avg(8, 3600.0)
+    cfg = pa.solve_cfg(solver=solver, weight_cut=0.0, **PARITY)
+    zero = to_dev(np.zeros((2, lo.n)))
+    for out in (lo.phase_avg_rhs(avg, zero, cfg)[0], lo.swe_nonlinear(zero, cfg)[0],
+                lo.expL_apply([1800.0, -900.0], zero, cfg)[0]):
+        assert np.array_equal(out.cpu().numpy(), np.zeros((2, lo.n)))
+    Z = zero.clone()
+    lo.step(avg, 1800.0, Z, cfg)
+    assert np.array_equal(Z.cpu().numpy(), np.zeros((2, lo.n)))
+    rest = np.zeros((2, lo.n))
+    rest[0, lm.ne:] = 7.5
+    rest[1, lm.ne:] = -3.0
+    R = to_dev(rest)
+    nb, _ = lo.phase_avg_rhs(avg, R, cfg)
+    assert np.array_equal(nb.cpu().numpy(), np.zeros((2, lo.n)))
+    e, _ = lo.expL_apply([3600.0, -1800.0], R, cfg)
+    assert np.abs(e.cpu().numpy() - rest).max() <= 1e-12 * 7.5
+    e0, _ = lo.expL_apply(0.0, to_dev(mm.state(bumps(om, [1, 2]))), cfg)
+    U = mm.state(bumps(om, [1, 2]))
+    assert np.abs(e0.cpu().numpy() - U).max() <= 1e-14 * np.abs(U).max()
+    lo.step(avg, 1800.0, R, cfg)
+    assert np.abs(R.cpu().numpy() - rest).max() <= 1e-12 * 7.5
+
+
 def test_gpu_step_parity():
     from paper_2103_07706_amd import pa
     om, oo, lm, lo, mm, lb = pair(3)
