@@ -82,7 +82,8 @@ int pa_mesh_destroy(pa_mesh *m);
 /* ---- operators (Sec. 2.5: discrete L and N) ------------------------------
  * Host assembly of the velocity mass matrix, the Coriolis matrix
  * (f = 2 Omega sin(latitude) at the cell quadrature points), the divergence
- * and the cell areas, plus the per-cell/per-edge geometry N needs.
+ * and the cell areas, plus the per-cell/per-edge geometry N needs (the
+ * nonlinear cell term as per-cell forms in the cell's edge fluxes).
  * b_cell (nc values, may be NULL) is the bottom height.  lambda_bar is the
  * Chebyshev scale |lambda_max| of Sec. 2.4 (an upper estimate of the spectral
  * radius of L); 0 means "estimate it" (pa_ops_estimate_lambda). */
@@ -95,7 +96,9 @@ int pa_ops_create(const pa_mesh *m, const pa_phys *phys, pa_ops **out);
 /* Bytes of device memory the operators occupy. */
 int pa_ops_device_size(const pa_ops *ops, size_t *bytes);
 /* Upload the operators into the caller's device buffer (>= device_size
- * bytes, 256-byte aligned).  The buffer must outlive the ops. */
+ * bytes, 256-byte aligned).  The buffer must outlive the ops and must not
+ * be written by the caller while work of calls on the ops is in flight
+ * (kernels read its tables through the scalar data cache). */
 int pa_ops_bind(pa_ctx *ctx, pa_ops *ops, void *dev_buf);
 /* Power iteration on the GPU, v <- L(L v) in the energy inner product, from
  * a fixed start vector; sets lambda_bar = safety * estimate of rho(L).
