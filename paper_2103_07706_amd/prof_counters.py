@@ -107,7 +107,7 @@ def summarize(a):
         f.write(f"# HBM traffic of {a.kernel}, workload {a.workload} ({a.backward} backward, "
                 f"{a.form} form)\n\n")
         f.write("Counter runs (rocprofv3, one counter per run, from the repository root on the "
-                "GPU box):\n\n```\n" + "\n".join(a.commands) + "\n```\n\n")
+                "GPU machine):\n\n```\n" + "\n".join(a.commands) + "\n```\n\n")
         f.write(f"Copy calibration: {COPY_BYTES} bytes read and written; FETCH_SIZE counted "
                 f"{max(cf):.0f} KiB (factor {f_fetch:.4f}), WRITE_SIZE {max(cw):.0f} KiB "
                 f"(factor {f_write:.4f}).\n\n")
@@ -149,7 +149,7 @@ def trace(a):
     avg_us = sum(dur) / len(dur)
     with open(a.out, "w") as f:
         f.write(f"# Kernel trace: {bench['config']['workload']}, roofline kernel {k}\n\n")
-        f.write("Command (from the repository root on the GPU box):\n\n```\n" + a.command + "\n```\n\n")
+        f.write("Command (from the repository root on the GPU machine):\n\n```\n" + a.command + "\n```\n\n")
         f.write("## Whole run (rocprofv3 --stats, every dispatch: set-up, autotuning and all forms)\n\n")
         f.write("| kernel | calls | total ms | avg us | % |\n|---|---|---|---|---|\n")
         for x in stats[:14]:
