@@ -111,6 +111,18 @@ void Engine::plan_cheb() {
     mixed_outer_ = std::max(1, (int)std::ceil(std::log(cfg_.cg_rtol) / std::log(10.0 * eps)));
     // the first kin coefficients of the same recurrence
     cheb_coefs(a, b, kin, mix_c1_, mix_c2_);
+    // The round count assumes only 10 eps per round; a round of kin steps
+    // reaches eps (its Chebyshev bound, above the FP32 floor), so the last
+    // round needs only the rest, cg_rtol / eps^(rounds - 1), and takes the
+    // steps of that bound (at least half a round).  The FP64 residual check
+    // of every solve still decides.
+    const double rest = cfg_.cg_rtol / std::pow(eps, mixed_outer_ - 1);
+    int klast = kin;
+    if (rest > eps && rest < 1.0)
+      klast = (int)std::ceil(std::acosh(2.0 / rest) / std::acosh(sigma)) + 1;
+    else if (rest >= 1.0)
+      klast = 1;
+    mixed_last_ = std::min(kin, std::max(klast, (kin + 1) / 2));
   }
 }
 
@@ -147,9 +159,12 @@ void Engine::mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_
   const bool prof = ctx_->prof_kernel == PA_KERNEL_CHEB32_ITER;
   ca.prof = prof ? st_.prof : nullptr;
   ca.prof_bytes = st_.prof_bytes;
+  int steps = 0;
   for (int o = 0; o < mixed_outer_; o++) {
-    if (prof && kin > 1) bracket_begin();
-    for (int i = 1; i < kin; i++) {
+    const int kr = o + 1 == mixed_outer_ ? mixed_last_ : kin;
+    steps += kr;
+    if (prof && kr > 1) bracket_begin();
+    for (int i = 1; i < kr; i++) {
       ca.x_cur = cur;
       ca.x_prev = prev;
       ca.x_next = prev;
@@ -159,7 +174,7 @@ void Engine::mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_
       launch_cheb32_iter(ca, s_);
       std::swap(cur, prev);
     }
-    if (prof && kin > 1) bracket_end(kin - 1);
+    if (prof && kr > 1) bracket_end(kr - 1);
     ra.first = 0;
     ra.last = o + 1 == mixed_outer_ ? 1 : 0;
     ra.x_zero = prepared && o == 0 ? 1 : 0;  // the gather kernel left x unwritten
@@ -171,8 +186,8 @@ void Engine::mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_
   defer_check(Bs, nwg_init, colK, kneed);
   stats.solves++;
   stats.refinements += mixed_outer_;
-  stats.cg_iters += kin * mixed_outer_;
-  stats.cg_iters_max = std::max(stats.cg_iters_max, kin * mixed_outer_);
+  stats.cg_iters += steps;
+  stats.cg_iters_max = std::max(stats.cg_iters_max, steps);
 }
 
 // Reduction-free mass solve: the set-up kernel wrote r_0 (r), x_0 (x),

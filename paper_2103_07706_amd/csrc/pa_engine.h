@@ -126,6 +126,7 @@ class Engine {
   void mixed_solve(double *x, int Bs, const int *colK, int kneed, int nwg_init, bool prepared);
   std::vector<double> mix_c1_, mix_c2_;
   int mixed_outer_ = 0;
+  int mixed_last_ = 0;  // steps of the last inner round (the others take mix_c1_.size())
   float *r32_ = nullptr, *d32_[2] = {nullptr, nullptr};
   // Chebyshev plan: step coefficients from the spectral bounds
   double cheb_theta_ = 0, cheb_delta_ = 0;
