@@ -337,6 +337,7 @@ class Avg:
             _check(lib().pa_avg_create(M, T, ctypes.byref(h)))
         self._h = h
         self.M = M
+        self.T = T  # None for explicit nodes
         self.s = np.zeros(M)
         self.w = np.zeros(M)
         _check(lib().pa_avg_nodes(h, _dp(self.s), _dp(self.w)))

@@ -4,7 +4,7 @@ problems evaluated one at a time, and against the oracle."""
 import numpy as np
 import pytest
 
-from gpu_common import PARITY, bumps, pair, rel_w, to_dev
+from gpu_common import PARITY, bumps, check_parity, onodes, pair, rel_w, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -78,12 +78,12 @@ def test_gpu_batch_parity_with_oracle():
         U = bumps(om, [seed])
         ops.append(lo)
         states.append(to_dev(mm.state(U)))
-        refs.append((oo, mm, oo.phase_avg_rhs(lb, avg.s, avg.w, U[0], tol=1e-13, rtol=1e-14)))
+        refs.append((oo, mm, oo.phase_avg_rhs(lb, *onodes(avg), U[0], tol=1e-13, rtol=1e-14)))
     b = pa.Batch(ops[0].ctx, [(o, 1) for o in ops], avg)
     outs, st = b.run(states, cfg)
     for (oo, mm, ref), o in zip(refs, outs):
         got = mm.back(o.cpu().numpy())[0]
-        assert rel_w(oo, got, ref) < 1e-12
+        check_parity(oo, got, ref, 1e-12)
 
 
 def test_gpu_batch_autotune_and_replay(tmp_path):

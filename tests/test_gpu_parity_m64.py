@@ -1,0 +1,113 @@
+"""GPU parity at the throughput workload's averaging size: M = 64 terms over
+T = 2 h, on meshes small enough for the oracle to evaluate all 64 terms
+(levels 3 and 4).
+
+With 64 terms the forward combination E = sum_k c_k(s_m) R_k and the
+backward term reduction Z_k = sum_m w_m c_k(-s_m) Y_m fill all four 16-wide
+m-blocks of the matrix-core tiles, and the per-term backward form sums 64
+weighted recurrences in one group; none of this is reached with M <= 16.
+Both backward forms, in FP64 (parity tolerances, the 1e-12 bar) and with
+FP32 inner solves refined in FP64 (the 1e-10 bar), against the oracle's
+term-by-term evaluation with its own nodes and weights; per-block max-norms
+beside the energy norm.  Also: a batch whose items average over 64 terms,
+and the FP32-refined form at the benchmark's tolerances (every solve to
+1e-10, Chebyshev threshold 1e-6), whose statistics must show a refined solve
+that met its check without a repeat."""
+import functools
+
+import numpy as np
+import pytest
+
+from gpu_common import PARITY, block_max, bumps, check_parity, pair, rel_w, to_dev
+
+pytestmark = pytest.mark.gpu
+
+M, T = 64, 7200.0
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_nbar(level, seed, tol, rtol):
+    om, oo, lm, lo, mm, lb = pair(level)
+    import oracle
+    s, w = oracle.avg_nodes(M, T)
+    U = bumps(om, [seed])[0]
+    print(f"oracle: level {level}, seed {seed}, M = {M}, tol {tol:g}, rtol {rtol:g}", flush=True)
+    return U, oo.phase_avg_rhs(lb, s, w, U, tol=tol, rtol=rtol)
+
+
+FORMS = {
+    "fp64": (dict(**PARITY), 1e-12),
+    "fp32_refined": (dict(cheb_tol=1e-13, cg_rtol=1e-12, precision=1), 1e-10),
+}
+
+
+@pytest.mark.parametrize("form", list(FORMS))
+@pytest.mark.parametrize("backward", ["clenshaw", "per_term"])
+@pytest.mark.parametrize("level", [3, 4])
+def test_gpu_m64_parity(level, backward, form):
+    from paper_2103_07706_amd import pa
+    om, oo, lm, lo, mm, lb = pair(level)
+    U, ref = _oracle_nbar(level, 7, 1e-13, 1e-14)
+    avg = pa.Avg(M, T)
+    kw, bar = FORMS[form]
+    bw = pa.PA_BACKWARD_CLENSHAW if backward == "clenshaw" else pa.PA_BACKWARD_PER_TERM
+    cfg = pa.solve_cfg(backward=bw, solver=pa.PA_SOLVER_CHEBYSHEV, weight_cut=0.0, **kw)
+    out, st = lo.phase_avg_rhs(avg, to_dev(mm.state(U)[None]), cfg)
+    assert st["terms"] == M and st["fallbacks"] == 0
+    if form == "fp32_refined":
+        assert st["refinements"] > 0
+    got = mm.back(out.cpu().numpy()[0])
+    w, mu, me = check_parity(oo, got, ref, bar, what=(level, backward, form))
+    print(f"level {level} {backward} {form}: energy norm {w:.2e}, max-norm u {mu:.2e}, "
+          f"eta {me:.2e}")
+
+
+def test_gpu_m64_batch_parity():
+    """A captured batch of two meshes (levels 3 and 4, two members on the
+    second) averaging over 64 terms, against the oracle term by term."""
+    from paper_2103_07706_amd import pa
+    avg = pa.Avg(M, T)
+    cfg = pa.solve_cfg(backward=pa.PA_BACKWARD_CLENSHAW, solver=pa.PA_SOLVER_CHEBYSHEV,
+                       weight_cut=0.0, use_graph=True, **PARITY)
+    items, states, refs = [], [], []
+    for level, seeds in [(3, [7]), (4, [7, 8])]:
+        om, oo, lm, lo, mm, lb = pair(level)
+        Us = []
+        for sd in seeds:
+            U, ref = _oracle_nbar(level, sd, 1e-13, 1e-14)
+            Us.append(U)
+            refs.append((oo, mm, ref))
+        items.append((lo, len(seeds)))
+        states.append(to_dev(mm.state(np.stack(Us))))
+    b = pa.Batch(items[0][0].ctx, items, avg)
+    for rep in range(2):
+        outs, st = b.run(states, cfg)
+        got = [g for o in outs for g in o.cpu().numpy()]
+        for (oo, mm, ref), g in zip(refs, got):
+            check_parity(oo, mm.back(g), ref, 1e-12, what=("batch", rep))
+        assert all(s["terms"] == M for s in st)
+
+
+def test_gpu_m64_metric_fp32_refined_stats():
+    """The FP32-refined form at the benchmark's tolerances (Chebyshev
+    threshold 1e-6, every solve to 1e-10): no repeat of the call, refined
+    solves taken, the largest final FP64 residual within 1e-10; the result
+    against the oracle at the same tolerances (difference set by the solve
+    tolerance, reported)."""
+    from paper_2103_07706_amd import pa
+    level = 3
+    om, oo, lm, lo, mm, lb = pair(level)
+    U, ref = _oracle_nbar(level, 7, 1e-6, 1e-10)
+    avg = pa.Avg(M, T)
+    cfg = pa.solve_cfg(backward=pa.PA_BACKWARD_CLENSHAW, solver=pa.PA_SOLVER_CHEBYSHEV,
+                       precision=pa.PA_FP32_REFINED, cheb_tol=1e-6, cg_rtol=1e-10,
+                       weight_cut=0.0, use_graph=True)
+    for _ in range(2):
+        out, st = lo.phase_avg_rhs(avg, to_dev(mm.state(U)[None]), cfg)
+        assert st["fallbacks"] == 0 and st["refinements"] > 0
+        assert 0 < st["resid_max"] <= 1e-10, st["resid_max"]
+    got = mm.back(out.cpu().numpy()[0])
+    w = rel_w(oo, got, ref)
+    mx = max(block_max(om.ne, got, ref))
+    print(f"metric tolerances, FP32-refined vs oracle: energy norm {w:.2e}, max-norm {mx:.2e}")
+    assert w < 1e-8 and mx < 1e-7

@@ -82,3 +82,19 @@ def test_learned_preconditioner_parameters_host(tmp_path):
     (tmp_path / "bad.bin").write_bytes(b"nonsense")
     with pytest.raises(pa.PAError):
         lp2.load(tmp_path / "bad.bin")
+
+
+@pytest.mark.parametrize("M", [1, 5, 8, 32, 64])
+@pytest.mark.parametrize("T", [1000.0, 3600.0, 7200.0])
+def test_library_avg_nodes_match_oracle(M, T):
+    """The library's averaging nodes and weights (host code of the HIP
+    library) equal the oracle's, computed separately from the same reading
+    of the averaging formula (midpoints of the support of rho(s/T),
+    weights normalised to sum to one)."""
+    import oracle
+    from paper_2103_07706_amd import pa
+    a = pa.Avg(M, T)
+    s, w = oracle.avg_nodes(M, T)
+    assert np.array_equal(a.s, s)
+    assert np.abs(a.w - w).max() <= 1e-15 * np.abs(w).max()
+    assert abs(a.w.sum() - 1.0) < 1e-14
