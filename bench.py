@@ -71,9 +71,29 @@ def traffic_from_profiles(kernel, workload, backward, form):
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(wl, lam, nterms):
-    """The oracle (single-threaded C, FP64) on a sample of the workload's
-    averaging terms: every (M / nterms)-th term, scaled to a whole Nbar."""
+def host_cpu():
+    """What the host offers: logical CPUs, the ones this process may use,
+    and the CPU model."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "usable": len(os.sched_getaffinity(0)), "model": model}
+
+
+def oracle_sample(wl, lam, nterms, max_threads=16):
+    """The oracle (C, FP64, single-threaded per call) on a sample of the
+    workload's averaging terms, every (M / nterms)-th term, at the metric's
+    tolerances: once on one core, then with the terms spread over the usable
+    host cores (one thread per core, each evaluating its share of the terms
+    term by term, the partial sums added: the paper's ensemble parallelism
+    over terms).  Returns the timings, the sample and the oracle's result."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import numpy as np
 
     import oracle
@@ -85,12 +105,57 @@ def cpu_baseline(wl, lam, nterms):
     s, w = oracle.avg_nodes(wl.M, wl.T)
     idx = list(range(wl.M // (2 * nterms), wl.M, max(1, wl.M // nterms)))[:nterms]
     t0 = time.perf_counter()
-    oo.phase_avg_rhs(lam, s[idx], w[idx], U, tol=1e-6, rtol=1e-10)
-    dt = time.perf_counter() - t0
-    per_eval = dt * wl.M / len(idx)
-    return {"value": 1.0 / per_eval, "unit": "Nbar/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(idx)} of {wl.M} averaging terms (indices {idx}) of one Nbar at "
-                      f"level {wl.level}, scaled by {wl.M}/{len(idx)}; {dt:.1f} s measured"}
+    ref = oo.phase_avg_rhs(lam, s[idx], w[idx], U, tol=1e-6, rtol=1e-10)
+    dt1 = time.perf_counter() - t0
+    P = max(1, min(max_threads, len(os.sched_getaffinity(0)), len(idx)))
+    shares = [idx[p::P] for p in range(P)]
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(P) as ex:
+        parts = list(ex.map(lambda sh: oo.phase_avg_rhs(lam, s[sh], w[sh], U, tol=1e-6,
+                                                        rtol=1e-10), shares))
+    dtP = time.perf_counter() - t0
+    summed = np.sum(parts, axis=0)
+    scale = wl.M / len(idx)
+    return {"om": om, "oo": oo, "U": U, "s": s[idx], "w": w[idx], "ref": ref, "idx": idx,
+            "single_s": dt1, "all_s": dtP, "threads": P, "scale": scale,
+            "split_vs_single": float(oo.wnorm(summed - ref) / oo.wnorm(ref))}
+
+
+def cpu_baseline_record(wl, smp):
+    host = host_cpu()
+    return {"value": 1.0 / (smp["all_s"] * smp["scale"]), "unit": "Nbar/s",
+            "cores": smp["threads"], "kind": "oracle",
+            "sample": f"{len(smp['idx'])} of {wl.M} averaging terms (indices {smp['idx']}) of "
+                      f"one Nbar at level {wl.level}, scaled by {wl.M}/{len(smp['idx'])}; "
+                      f"terms spread over {smp['threads']} threads: {smp['all_s']:.1f} s measured",
+            "single_core": {"value": 1.0 / (smp["single_s"] * smp["scale"]), "cores": 1,
+                            "seconds": smp["single_s"]},
+            "host": host}
+
+
+def errors_vs_oracle(pa, ops, mesh, smp, forms, members):
+    """Every timed form on the oracle's term sample (same nodes, weights,
+    lambda_bar and input), against the oracle's result: relative energy
+    norm and per-block relative max-norm of the difference."""
+    import numpy as np
+    import torch
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from matching import MeshMap
+    mm = MeshMap(smp["om"], mesh)
+    oo, ref, ne = smp["oo"], smp["ref"], smp["om"].ne
+    avg = pa.Avg(s=smp["s"], w=smp["w"])
+    Ud = torch.tensor(mm.state(smp["U"])[None], dtype=torch.float64, device="cuda:0")
+    out = {}
+    for name, (cfg, tune) in forms.items():
+        ops.set_tune(**tune)
+        got, st = ops.phase_avg_rhs(avg, Ud, cfg)
+        g = mm.back(got.cpu().numpy()[0])
+        d = g - ref
+        out[name] = {"energy_norm": float(oo.wnorm(d) / oo.wnorm(ref)),
+                     "max_u": float(np.abs(d[:ne]).max() / np.abs(ref[:ne]).max()),
+                     "max_eta": float(np.abs(d[ne:]).max() / np.abs(ref[ne:]).max()),
+                     "resid_max": st["resid_max"]}
+    return out
 
 
 def measure(ops, avg, U, cfg, out, steps, warmup):
@@ -279,6 +344,7 @@ def main():
     results = {}
     for name, (cfg, lmin) in forms.items():
         tune = None
+        ops.set_tune()  # every form starts its search from the process default
         if args.autotune:
             tune = ops.autotune(avg, U, cfg, cache=args.tune_cache)
         if lmin is not None:
@@ -287,23 +353,23 @@ def main():
             # (now learned) narrow solves are chosen again by timing
             best = None
             for rpt in (1, 2, 4):
-                pa.set_launch_tune(lp_min_cols=lmin, narrow_rows_per_thread=rpt)
+                ops.set_tune(lp_min_cols=lmin, narrow_rows_per_thread=rpt)
                 ops.phase_avg_rhs(avg, U, cfg, out=out)
                 ms = min(ops.phase_avg_rhs(avg, U, cfg, out=out)[1]["device_ms"] for _ in range(2))
                 if best is None or ms < best[0]:
                     best = (ms, rpt)
-            pa.set_launch_tune(lp_min_cols=lmin, narrow_rows_per_thread=best[1])
-            tune = dict(tune or {}, **pa.get_launch_tune())
+            ops.set_tune(lp_min_cols=lmin, narrow_rows_per_thread=best[1])
+            tune = dict(tune or {}, **ops.get_tune())
         print(f"form {name} launch tune {tune}", file=sys.stderr, flush=True)
         elapsed, stats = measure(ops, avg, U, cfg, out, args.steps, args.warmup)
-        results[name] = dict(elapsed=elapsed, stats=stats, tune=pa.get_launch_tune(), cfg=cfg,
+        results[name] = dict(elapsed=elapsed, stats=stats, tune=ops.get_tune(), cfg=cfg,
                              autotune=tune, learned=stats["lp_solves"] > 0)
-    # value: the faster form on this workload (both are listed in config.forms)
+    # value: the faster form on this workload (all are listed in config.forms)
     head_name = max(results, key=lambda k: 1.0 / results[k]["elapsed"])
     head = results[head_name]
     # the dominant kernel of that form, timed last (after every other form):
     # each launch carries its own start and end events
-    pa.set_launch_tune(**head["tune"])
+    ops.set_tune(**head["tune"])
     if args.solver == "chebyshev":
         if head["learned"] and head["tune"]["lp_min_cols"] <= 4:
             cands = {"k_cheb_lp_iter": pa.PA_KERNEL_CHEB_LP_ITER}
@@ -325,7 +391,17 @@ def main():
     elapsed, stats = head["elapsed"], head["stats"]
     value = wl.members * args.steps / elapsed
     avg_ms = prof["total_ms"] / max(1, prof["launches"])
-    achieved = prof["bytes"] / (prof["total_ms"] * 1e-3) / 1e9 if prof["total_ms"] > 0 else 0.0
+    secs = prof["total_ms"] * 1e-3
+    # algorithmic bytes of the solver's iterations: one mass-solve iteration
+    # on one column streams 10 vectors of n_e values (a fused preconditioned
+    # CG iteration: r, p in and p, q out; x, p, r, q in and x, r out), FP64
+    # except in the FP32 inner steps
+    word = 4.0 if kernel == "k_cheb32_iter4" else 8.0
+    iter_bytes = prof["units"] * 10.0 * mesh.ne * word
+    achieved = iter_bytes / secs / 1e9 if secs > 0 else 0.0
+    # the kernel's own compulsory bytes (what its launches must stream at
+    # least once: vectors, matrix rows, ring tables)
+    compulsory = prof["bytes"] / secs / 1e9 if secs > 0 else 0.0
     traffic = traffic_from_profiles(kernel, args.workload, args.backward, head_name)
     forms_rec = {name: {"value": wl.members * args.steps / r["elapsed"],
                         "ms_per_step": 1e3 * r["elapsed"] / args.steps,
@@ -366,11 +442,22 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "avg_launch_us": 1e3 * avg_ms,
                      "launches": prof["launches"],
-                     "algorithmic_bytes_per_launch": prof["bytes"] / max(1, prof["launches"])},
+                     "iterations_per_launch": prof["units"] / max(1, prof["launches"]),
+                     "algorithmic_bytes_per_launch": iter_bytes / max(1, prof["launches"]),
+                     "algorithmic_bytes_per_iteration": 10.0 * mesh.ne * word,
+                     "compulsory_bytes_per_launch": prof["bytes"] / max(1, prof["launches"]),
+                     "compulsory_achieved": compulsory,
+                     "compulsory_frac": compulsory / HBM_PEAK_GBS},
     }
     if args.cpu:
-        print("cpu baseline ...", file=sys.stderr, flush=True)
-        rec["cpu_baseline"] = cpu_baseline(wl, lam, args.cpu_terms)
+        print("oracle sample ...", file=sys.stderr, flush=True)
+        smp = oracle_sample(wl, lam, args.cpu_terms)
+        rec["cpu_baseline"] = cpu_baseline_record(wl, smp)
+        print("errors against the oracle ...", file=sys.stderr, flush=True)
+        rec["err_vs_oracle"] = dict(
+            errors_vs_oracle(pa, ops, mesh, smp,
+                             {k: (r["cfg"], r["tune"]) for k, r in results.items()}, wl.members),
+            sample=f"{len(smp['idx'])} of {wl.M} averaging terms, metric tolerances on both sides")
     print(json.dumps(rec))
 
 

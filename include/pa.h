@@ -173,6 +173,13 @@ typedef struct {
 } pa_solve_cfg;
 enum { PA_PRECOND_JACOBI = 0, PA_PRECOND_LEARNED = 1 };
 enum { PA_SOLVER_CG = 0, PA_SOLVER_CHEBYSHEV = 1 };
+/* Defaults: the fastest FP64 form measured on MI355X at the throughput
+ * workload -- PA_FP64, PA_BACKWARD_CLENSHAW, PA_SOLVER_CHEBYSHEV,
+ * PA_PRECOND_JACOBI, use_graph 1, maxit 100, cg_rtol 1e-10, cheb_tol 1e-6
+ * (the paper's threshold), weight_cut 1e-16, inner_rtol 1e-6, growth_guard
+ * 0.  (PA_FP32_REFINED is faster still on wide column blocks; it is a
+ * precision choice left to the caller.)  pa_step always solves with FP64
+ * CG: it works in place, so a failed check could not be repeated. */
 void pa_solve_cfg_default(pa_solve_cfg *cfg);
 
 /* Statistics of the last call (valid when the call returns). */
@@ -194,6 +201,11 @@ typedef struct {
   int32_t fallbacks;     /* repeats of the call: a CG budget overrun (with
                             polling) or a failed Chebyshev check (with FP64
                             CG); the other fields describe the last run */
+  int32_t graph_captured;/* 1 if this call captured a new graph: the first
+                            graph call, or one after anything the graph
+                            depends on changed (pointers, sizes, settings,
+                            launch shape, operator contents or buffers,
+                            averaging nodes) */
 } pa_stats;
 
 /* Device workspace bytes for calls on 'batch' states (expL_apply,
@@ -261,6 +273,8 @@ typedef struct {
   int64_t work_launches; /* launches that found active columns */
   double total_ms;    /* summed event time of all launches */
   double bytes;       /* algorithmic bytes of all launches */
+  double units;       /* mass-solve steps (iterations) times the columns they
+                         ran on, summed over the launches */
 } pa_kernel_profile;
 int pa_ctx_profile(pa_ctx *ctx, int kernel);
 /* Iteration budget of the mass solves.  After a call whose outputs do not
@@ -273,26 +287,36 @@ int pa_ctx_profile(pa_ctx *ctx, int kernel);
 int pa_ctx_set_cg_budget(pa_ctx *ctx, double cg_rtol, int iters);
 
 /* ---- launch shape and autotuner -------------------------------------------
- * Row-parallel kernels take their grid from a process-wide launch shape:
- * rows per thread for batches of at most 4 columns (latency-bound), and the
- * workgroup cap per column tile for wider batches.  lp_min_cols is the
- * narrowest column block whose mass solves take learned steps when the
- * learned preconditioner is enabled (narrower blocks take Jacobi steps; a
- * learned step costs more than a Jacobi step, so fewer steps pay only on
- * wide enough blocks).  mixed_min_cols likewise is the narrowest block
- * whose mass solves run as FP32 solves with FP64 refinement when cfg asks
- * for PA_FP32_REFINED (narrower blocks take FP64 steps, which are launch
- * bound there; the FP64 residual check is the same).  pa_autotune times
- * pa_phase_avg_rhs over a small set of shapes on the given problem (the
- * workspace must fit it), then, with the learned preconditioner or FP32
- * refinement enabled in cfg, over lp_min_cols and mixed_min_cols in {1, 8,
- * 64, never}, then over fused_steps, then over the shapes once more with
- * the fields found, and keeps the fastest; it returns the choice and the
- * best time.  fused_steps (1 to 6) is the number of Jacobi Chebyshev steps of a
- * single-column mass solve per launch (a workgroup owns a part of 512 rows
- * and forms the earlier steps again on the rings of rows its later steps
- * read; the results are the same as one step per launch); the autotuner
- * tries each. */
+ * Row-parallel kernels take their grid from a launch shape: rows per thread
+ * for batches of at most 4 columns (latency-bound), and the workgroup cap
+ * per column tile for wider batches.  lp_min_cols is the narrowest column
+ * block whose mass solves take learned steps when the learned
+ * preconditioner is enabled (narrower blocks take Jacobi steps; a learned
+ * step costs more than a Jacobi step, so fewer steps pay only on wide
+ * enough blocks).  mixed_min_cols likewise is the narrowest block whose
+ * mass solves run as FP32 solves with FP64 refinement when cfg asks for
+ * PA_FP32_REFINED (narrower blocks take FP64 steps, which are launch bound
+ * there; the FP64 residual check is the same).  fused_steps (1 to 6) is the
+ * number of Jacobi Chebyshev steps of a single-column mass solve per launch
+ * (a workgroup owns a part of 512 rows and forms the earlier steps again on
+ * the rings of rows its later steps read; the results are the same as one
+ * step per launch).
+ *
+ * Which shape a call uses: a batch item's own shape (pa_batch_set_tune),
+ * else the operators' own shape (pa_ops_set_tune, pa_autotune), else the
+ * process default (pa_get/set_launch_tune, guarded by a lock).  A call reads
+ * its shape once when it starts, so calls on different operators from
+ * different threads do not affect each other's shapes.
+ *
+ * pa_autotune times pa_phase_avg_rhs over a small set of shapes on the
+ * given problem (the workspace must fit it), then, with the learned
+ * preconditioner or FP32 refinement enabled in cfg, over lp_min_cols and
+ * mixed_min_cols in {1, 8, 64, never}, then over fused_steps, then over the
+ * shapes once more with the fields found, and stores the fastest as the
+ * operators' own shape (the process default is left as it is); it returns
+ * the choice and the best time.  pa_ops_set_tune with t = NULL drops the
+ * operators' own shape; pa_ops_get_tune returns the shape the operators'
+ * calls use and (own, may be NULL) whether it is their own. */
 typedef struct {
   int32_t narrow_rows_per_thread;
   int32_t wide_max_wg;
@@ -303,6 +327,8 @@ typedef struct {
 } pa_launch_tune;
 int pa_get_launch_tune(pa_launch_tune *out);
 int pa_set_launch_tune(const pa_launch_tune *t);
+int pa_ops_set_tune(pa_ops *ops, const pa_launch_tune *t);
+int pa_ops_get_tune(const pa_ops *ops, pa_launch_tune *out, int *own);
 int pa_autotune(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int members,
                 const double *U_dev, double *out_dev, void *ws_dev,
                 size_t ws_bytes, const pa_solve_cfg *cfg, pa_launch_tune *out);

@@ -22,7 +22,8 @@ struct pa_batch {
   std::vector<pa_stats> graph_stats;
 
   int n() const { return (int)ops.size(); }
-  pa::LaunchTune item_tune(int i) const { return tuned[i] ? tune[i] : pa::launch_tuning(); }
+  // an item's own shape, else its operators' shape, else the process default
+  pa::LaunchTune item_tune(int i) const { return tuned[i] ? tune[i] : ops[i]->effective_tune(); }
 
   void release() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -106,7 +107,7 @@ std::vector<unsigned char> batch_key(const pa_batch *b, const double *const *U,
                                      double *const *Nbar, void *ws, const pa_solve_cfg &c,
                                      int budget) {
   std::vector<unsigned char> k;
-  put(k, b->avg);
+  put(k, b->avg->gen);
   put(k, ws);
   put(k, c.precision);
   put(k, c.backward);
@@ -121,9 +122,8 @@ std::vector<unsigned char> batch_key(const pa_batch *b, const double *const *U,
   put(k, c.precond);
   put(k, budget);
   for (int i = 0; i < b->n(); i++) {
-    put(k, b->ops[i]);
+    put(k, b->ops[i]->gen);
     put(k, b->ops[i]->lambda_bar);
-    put(k, b->ops[i]->lp_dev);
     put(k, b->members[i]);
     put(k, U[i]);
     put(k, Nbar[i]);
@@ -137,24 +137,18 @@ std::vector<unsigned char> batch_key(const pa_batch *b, const double *const *U,
   return k;
 }
 
-// Restores the process-wide launch shape when a batch call ends.
-struct TuneScope {
-  pa::LaunchTune keep = pa::launch_tuning();
-  ~TuneScope() { pa::set_launch_tuning(keep); }
-};
-
 // One evaluation of every item.  budget: use the context's learned CG
 // budget (no polling); learn: record the batch's largest iteration count.
 void run_once(pa_ctx *ctx, pa_batch *b, const double *const *U, double *const *Nbar, char *ws,
               const std::vector<size_t> &off, const pa_solve_cfg &c, bool budget, bool learn,
               pa_stats *stats) {
   const int n = b->n();
-  TuneScope scope;
   std::vector<std::unique_ptr<pa::Engine>> E(n);
   std::vector<pa::Engine::NbarCall> call(n);
   bool sync_free = true;
   for (int i = 0; i < n; i++) {
     E[i].reset(new pa::Engine(ctx, b->ops[i], c, ws + off[i], off[i + 1] - off[i]));
+    E[i]->set_tune(b->item_tune(i));
     E[i]->allow_budget(budget, false);
     E[i]->nbar_plan(call[i], b->avg, b->members[i], U[i], Nbar[i]);
     sync_free = sync_free && E[i]->sync_free();
@@ -165,7 +159,6 @@ void run_once(pa_ctx *ctx, pa_batch *b, const double *const *U, double *const *N
   if (!sync_free || ctx->prof_kernel != PA_KERNEL_NONE) {
     // polled CG solves (or per-launch timing): items in turn on the context stream
     for (int i = 0; i < n; i++) {
-      pa::set_launch_tuning(b->item_tune(i));
       E[i]->nbar_begin(call[i]);
       E[i]->nbar_body(call[i]);
       E[i]->finish();
@@ -176,7 +169,6 @@ void run_once(pa_ctx *ctx, pa_batch *b, const double *const *U, double *const *N
     for (int i = 0; i < n; i++) E[i]->nbar_begin(call[i]);
     auto enqueue = [&] {
       for (int i = 0; i < n; i++) {
-        pa::set_launch_tuning(b->item_tune(i));
         E[i]->set_stream(b->streams[i]);
         E[i]->nbar_body(call[i]);
         E[i]->set_stream(cs);
@@ -220,6 +212,7 @@ void run_once(pa_ctx *ctx, pa_batch *b, const double *const *U, double *const *N
         b->key = key;
         b->graph_stats.resize(n);
         for (int i = 0; i < n; i++) b->graph_stats[i] = E[i]->stats;
+        for (int i = 0; i < n; i++) E[i]->stats.graph_captured = 1;
       } else {
         for (int i = 0; i < n; i++) E[i]->stats = b->graph_stats[i];
       }
@@ -365,7 +358,6 @@ int pa_batch_autotune(pa_ctx *ctx, pa_batch *b, const double *const *U_dev,
     size_t total = 0;
     const std::vector<size_t> off = item_offsets(b, c, &total);
     if (ws_bytes < total) throw pa::Error(PA_ENOMEM, "workspace too small for the batch");
-    TuneScope scope;
     for (int i = 0; i < b->n(); i++) {
       bneed(U_dev[i] && Nbar_dev[i] && (const double *)Nbar_dev[i] != U_dev[i],
             "outputs must not alias inputs");

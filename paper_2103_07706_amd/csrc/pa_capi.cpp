@@ -1,5 +1,6 @@
 // C ABI of libpa (declared in include/pa.h): argument checks, error codes and
 // the thread-local error message; no C++ exception crosses this boundary.
+#include <atomic>
 #include <cstring>
 #include <string>
 
@@ -9,6 +10,10 @@ namespace pa {
 std::string &last_error() {
   thread_local std::string msg;
   return msg;
+}
+uint64_t next_generation() {
+  static std::atomic<uint64_t> counter{0};
+  return ++counter;
 }
 }  // namespace pa
 
@@ -61,7 +66,7 @@ int pa_ctx_profile(pa_ctx *ctx, int kernel) {
     need(kernel >= PA_KERNEL_NONE && kernel <= PA_KERNEL_CHEB32_ITER, "unknown kernel id");
     ctx->prof_kernel = kernel;
     ctx->prof_launches = ctx->prof_work = 0;
-    ctx->prof_ms = ctx->prof_bytes = 0.0;
+    ctx->prof_ms = ctx->prof_bytes = ctx->prof_units = 0.0;
   });
 }
 
@@ -82,6 +87,7 @@ int pa_ctx_profile_read(pa_ctx *ctx, pa_kernel_profile *out) {
     out->work_launches = ctx->prof_work;
     out->total_ms = ctx->prof_ms;
     out->bytes = ctx->prof_bytes;
+    out->units = ctx->prof_units;
   });
 }
 
@@ -205,6 +211,7 @@ int pa_ops_create(const pa_mesh *m, const pa_phys *ph, pa_ops **out) {
     auto *o = new pa_ops;
     try {
       o->mesh = m;
+      o->gen = pa::next_generation();
       pa::assemble_ops(o, m->m, *ph);
       o->dev_bytes = layout(o, nullptr);
     } catch (...) {
@@ -228,6 +235,7 @@ int pa_ops_bind(pa_ctx *ctx, pa_ops *ops, void *dev_buf) {
     need(((uintptr_t)dev_buf & 255) == 0, "device buffer must be 256-byte aligned");
     PA_HIP(hipSetDevice(ctx->device));
     ops->dev = dev_buf;
+    ops->gen = pa::next_generation();
     layout(ops, (char *)dev_buf);
     hipStream_t s = ctx->stream;
     const pa::DevOps &d = ops->d;
@@ -320,15 +328,15 @@ int pa_avg_destroy(pa_avg *avg) {
 void pa_solve_cfg_default(pa_solve_cfg *cfg) {
   if (!cfg) return;
   cfg->precision = PA_FP64;
-  cfg->backward = PA_BACKWARD_PER_TERM;
+  cfg->backward = PA_BACKWARD_CLENSHAW;
   cfg->maxit = 100;
   cfg->growth_guard = 0;
   cfg->cg_rtol = 1e-10;
   cfg->cheb_tol = 1e-6;
   cfg->weight_cut = 1e-16;
   cfg->inner_rtol = 1e-6;
-  cfg->use_graph = 0;
-  cfg->solver = PA_SOLVER_CG;
+  cfg->use_graph = 1;
+  cfg->solver = PA_SOLVER_CHEBYSHEV;
   cfg->precond = PA_PRECOND_JACOBI;
 }
 
@@ -344,47 +352,58 @@ pa_solve_cfg cfg_or_default(const pa_solve_cfg *cfg) {
 
 extern "C" {
 
+}  // extern "C"
+
+namespace pa {
+// Workspace bytes of every call on `batch` states under configuration c
+// (the planning code of the calls, run in its measuring mode).
+size_t workspace_bytes(const pa_ops *ops, const pa_avg *avg, int batch, const pa_solve_cfg &c) {
+  size_t best = 0;
+  {
+    pa::Engine e(nullptr, ops, c, nullptr, 0);
+    std::vector<double> t(batch, 1.0);
+    if (ops->lambda_bar > 0) e.expL_apply(batch, t.data(), nullptr, nullptr);
+    best = std::max(best, e.used());
+  }
+  {
+    pa::Engine e(nullptr, ops, c, nullptr, 0);
+    e.swe_nonlinear(batch, nullptr, nullptr);
+    best = std::max(best, e.used());
+  }
+  {
+    pa::Engine e(nullptr, ops, c, nullptr, 0);
+    e.estimate_lambda(1);
+    best = std::max(best, e.used());
+  }
+  {
+    pa::Engine e(nullptr, ops, c, nullptr, 0);
+    e.diagnostics(batch, nullptr, nullptr);
+    best = std::max(best, e.used());
+  }
+  if (avg) {
+    need(ops->lambda_bar > 0, "lambda_bar must be set before sizing averaged calls");
+    pa::Engine e1(nullptr, ops, c, nullptr, 0);
+    e1.phase_avg_rhs(avg, batch, nullptr, nullptr);
+    best = std::max(best, e1.used());
+    // the step's exponentials use the largest time step the caller may ask
+    // for; size it by phase_avg_rhs plus stage buffers of a 2T step
+    double T = 0;
+    for (double s : avg->s) T = std::max(T, 2.0 * std::fabs(s));
+    pa::Engine e2(nullptr, ops, c, nullptr, 0);
+    e2.step(avg, std::max(T, 1.0), batch, nullptr);
+    best = std::max(best, e2.used());
+  }
+  return best + 4096;
+}
+}  // namespace pa
+
+extern "C" {
+
 int pa_workspace_size(const pa_ops *ops, const pa_avg *avg, int batch, const pa_solve_cfg *cfg,
                       size_t *bytes) {
   return guard([&] {
     need(ops && bytes && batch >= 1, "bad arguments");
-    pa_solve_cfg c = cfg_or_default(cfg);
-    size_t best = 0;
-    {
-      pa::Engine e(nullptr, ops, c, nullptr, 0);
-      std::vector<double> t(batch, 1.0);
-      if (ops->lambda_bar > 0) e.expL_apply(batch, t.data(), nullptr, nullptr);
-      best = std::max(best, e.used());
-    }
-    {
-      pa::Engine e(nullptr, ops, c, nullptr, 0);
-      e.swe_nonlinear(batch, nullptr, nullptr);
-      best = std::max(best, e.used());
-    }
-    {
-      pa::Engine e(nullptr, ops, c, nullptr, 0);
-      e.estimate_lambda(1);
-      best = std::max(best, e.used());
-    }
-    {
-      pa::Engine e(nullptr, ops, c, nullptr, 0);
-      e.diagnostics(batch, nullptr, nullptr);
-      best = std::max(best, e.used());
-    }
-    if (avg) {
-      need(ops->lambda_bar > 0, "lambda_bar must be set before sizing averaged calls");
-      pa::Engine e1(nullptr, ops, c, nullptr, 0);
-      e1.phase_avg_rhs(avg, batch, nullptr, nullptr);
-      best = std::max(best, e1.used());
-      // the step's exponentials use the largest time step the caller may ask
-      // for; size it by phase_avg_rhs plus stage buffers of a 2T step
-      double T = 0;
-      for (double s : avg->s) T = std::max(T, 2.0 * std::fabs(s));
-      pa::Engine e2(nullptr, ops, c, nullptr, 0);
-      e2.step(avg, std::max(T, 1.0), batch, nullptr);
-      best = std::max(best, e2.used());
-    }
-    *bytes = best + 4096;
+    *bytes = pa::workspace_bytes(ops, avg, batch, cfg_or_default(cfg));
   });
 }
 
@@ -435,6 +454,28 @@ void run_with_fallback(pa_solve_cfg cfg, bool rerun_ok, F &&f) {
   }
 }
 }  // namespace
+
+namespace pa {
+// The averaged right-hand side on a workspace, with the repeat rules (a
+// budget overrun repeats with polling, a failed Chebyshev check with FP64
+// CG when outputs do not alias inputs).
+void phase_avg_rhs_call(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int members,
+                        const double *U_dev, double *Nbar_dev, void *ws, size_t ws_bytes,
+                        const pa_solve_cfg &c0, pa_stats *stats) {
+  need(avg && U_dev && Nbar_dev && members >= 1, "bad arguments");
+  const bool may = U_dev != Nbar_dev;
+  g_repeats = 0;
+  run_with_fallback(c0, may, [&](const pa_solve_cfg &c) {
+    run_with_budget(ctx, c.cg_rtol, may, [&](bool budget) {
+      pa::Engine e(ctx, ops, c, ws, ws_bytes);
+      e.allow_budget(budget, may);
+      e.phase_avg_rhs(avg, members, U_dev, Nbar_dev);
+      out_stats(stats, e);
+    });
+  });
+  if (stats) stats->fallbacks = g_repeats;
+}
+}  // namespace pa
 
 extern "C" {
 
@@ -499,19 +540,8 @@ int pa_phase_avg_rhs(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int memb
                      const pa_solve_cfg *cfg, pa_stats *stats) {
   return guard([&] {
     check_call(ctx, ops, ws);
-    need(avg && U_dev && Nbar_dev && members >= 1, "bad arguments");
-    const pa_solve_cfg c0 = cfg_or_default(cfg);
-    const bool may = U_dev != Nbar_dev;
-    g_repeats = 0;
-    run_with_fallback(c0, may, [&](const pa_solve_cfg &c) {
-      run_with_budget(ctx, c.cg_rtol, may, [&](bool budget) {
-        pa::Engine e(ctx, ops, c, ws, ws_bytes);
-        e.allow_budget(budget, may);
-        e.phase_avg_rhs(avg, members, U_dev, Nbar_dev);
-        out_stats(stats, e);
-      });
-    });
-    if (stats) stats->fallbacks = g_repeats;
+    pa::phase_avg_rhs_call(ctx, ops, avg, members, U_dev, Nbar_dev, ws, ws_bytes,
+                           cfg_or_default(cfg), stats);
   });
 }
 
@@ -530,33 +560,66 @@ int pa_step(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, double dt, int me
   });
 }
 
+}  // extern "C"
+
+namespace {
+void tune_out(const pa::LaunchTune &t, pa_launch_tune *out) {
+  out->narrow_rows_per_thread = t.narrow_rows_per_thread;
+  out->wide_max_wg = t.wide_max_wg;
+  out->lp_min_cols = t.lp_min_cols;
+  out->mixed_min_cols = t.mixed_min_cols;
+  out->fused_steps = t.fused_steps;
+  out->best_ms = 0.0;
+}
+
+pa::LaunchTune tune_in(const pa_launch_tune *t) {
+  need(t->narrow_rows_per_thread >= 1 && t->narrow_rows_per_thread <= 64, "rows per thread in [1, 64]");
+  need(t->wide_max_wg >= 8 && t->wide_max_wg <= 2048, "wide_max_wg in [8, 2048]");
+  need(t->lp_min_cols >= 1 && t->mixed_min_cols >= 1, "lp_min_cols, mixed_min_cols >= 1");
+  need(t->fused_steps >= 1 && t->fused_steps <= pa::kFusedMax, "fused_steps in [1, 6]");
+  pa::LaunchTune lt;
+  lt.narrow_rows_per_thread = t->narrow_rows_per_thread;
+  lt.wide_max_wg = t->wide_max_wg;
+  lt.lp_min_cols = t->lp_min_cols;
+  lt.mixed_min_cols = t->mixed_min_cols;
+  lt.fused_steps = t->fused_steps;
+  return lt;
+}
+}  // namespace
+
+extern "C" {
+
 int pa_get_launch_tune(pa_launch_tune *out) {
   return guard([&] {
     need(out != nullptr, "out is NULL");
-    pa::LaunchTune t = pa::launch_tuning();
-    out->narrow_rows_per_thread = t.narrow_rows_per_thread;
-    out->wide_max_wg = t.wide_max_wg;
-    out->lp_min_cols = t.lp_min_cols;
-    out->mixed_min_cols = t.mixed_min_cols;
-    out->fused_steps = t.fused_steps;
-    out->best_ms = 0.0;
+    tune_out(pa::launch_default(), out);
   });
 }
 
 int pa_set_launch_tune(const pa_launch_tune *t) {
   return guard([&] {
     need(t != nullptr, "t is NULL");
-    need(t->narrow_rows_per_thread >= 1 && t->narrow_rows_per_thread <= 64, "rows per thread in [1, 64]");
-    need(t->wide_max_wg >= 8 && t->wide_max_wg <= 2048, "wide_max_wg in [8, 2048]");
-    need(t->lp_min_cols >= 1 && t->mixed_min_cols >= 1, "lp_min_cols, mixed_min_cols >= 1");
-    need(t->fused_steps >= 1 && t->fused_steps <= pa::kFusedMax, "fused_steps in [1, 6]");
-    pa::LaunchTune lt;
-    lt.narrow_rows_per_thread = t->narrow_rows_per_thread;
-    lt.wide_max_wg = t->wide_max_wg;
-    lt.lp_min_cols = t->lp_min_cols;
-    lt.mixed_min_cols = t->mixed_min_cols;
-    lt.fused_steps = t->fused_steps;
-    pa::set_launch_tuning(lt);
+    pa::set_launch_default(tune_in(t));
+  });
+}
+
+int pa_ops_set_tune(pa_ops *ops, const pa_launch_tune *t) {
+  return guard([&] {
+    need(ops != nullptr, "ops is NULL");
+    if (t) {
+      ops->tune = tune_in(t);
+      ops->has_tune = true;
+    } else {
+      ops->has_tune = false;
+    }
+  });
+}
+
+int pa_ops_get_tune(const pa_ops *ops, pa_launch_tune *out, int *own) {
+  return guard([&] {
+    need(ops && out, "NULL argument");
+    tune_out(ops->effective_tune(), out);
+    if (own) *own = ops->has_tune ? 1 : 0;
   });
 }
 
@@ -567,22 +630,33 @@ int pa_autotune(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int members, 
     check_call(ctx, ops, ws);
     need(avg && U_dev && out_dev && out && members >= 1 && U_dev != out_dev, "bad arguments");
     const pa_solve_cfg c = cfg_or_default(cfg);
-    const pa::LaunchTune keep = pa::launch_tuning();
+    const pa::LaunchTune start = ops->effective_tune();
     const int rpts[] = {1, 2, 4, 8};
     const int caps[] = {512, 1024, 2048};
     double best = 1e300;
-    pa::LaunchTune best_t = keep;
-    auto time_once = [&]() {
+    pa::LaunchTune best_t = start;
+    // one timed call in launch shape t (the operators' own shape is not
+    // touched while searching)
+    auto time_once = [&](const pa::LaunchTune &t) {
       pa_stats st{};
       run_with_fallback(c, true, [&](const pa_solve_cfg &cc) {
         run_with_budget(ctx, cc.cg_rtol, true, [&](bool budget) {
           pa::Engine e(ctx, ops, cc, ws, ws_bytes);
+          e.set_tune(t);
           e.allow_budget(budget, true);
           e.phase_avg_rhs(avg, members, U_dev, out_dev);
           st = e.stats;
         });
       });
       return st.device_ms;
+    };
+    auto trial = [&](const pa::LaunchTune &t) {
+      time_once(t);  // warm-up (and graph capture when enabled)
+      double ms = std::min(time_once(t), time_once(t));
+      if (ms < best) {
+        best = ms;
+        best_t = t;
+      }
     };
     // the launch shape over rows per thread and workgroup caps, the other
     // fields as in `from`
@@ -592,46 +666,27 @@ int pa_autotune(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int members, 
           pa::LaunchTune t = from;
           t.narrow_rows_per_thread = rpt;
           t.wide_max_wg = cap;
-          pa::set_launch_tuning(t);
-          time_once();  // warm-up (and graph capture when enabled)
-          double ms = std::min(time_once(), time_once());
-          if (ms < best) {
-            best = ms;
-            best_t = t;
-          }
+          trial(t);
         }
     };
-    try {
-      shapes(keep);
-      auto search = [&](int pa::LaunchTune::*field, std::initializer_list<int> vals) {
-        for (int lmin : vals) {
-          pa::LaunchTune t = best_t;
-          t.*field = lmin;
-          pa::set_launch_tuning(t);
-          time_once();
-          double ms = std::min(time_once(), time_once());
-          if (ms < best) {
-            best = ms;
-            best_t = t;
-          }
-        }
-      };
-      if (c.precond == PA_PRECOND_LEARNED) search(&pa::LaunchTune::lp_min_cols, {1, 8, 64, kLpNever});
-      if (c.precision == PA_FP32_REFINED) search(&pa::LaunchTune::mixed_min_cols, {1, 8, 64, kLpNever});
-      if (c.solver == PA_SOLVER_CHEBYSHEV) search(&pa::LaunchTune::fused_steps, {1, 2, 3, 4, 5, 6});
-      // the shape again for the fields found (a learned threshold, a mixed
-      // threshold or a step count can change which shape is fastest)
-      shapes(best_t);
-    } catch (...) {
-      pa::set_launch_tuning(keep);
-      throw;
-    }
-    pa::set_launch_tuning(best_t);
-    out->narrow_rows_per_thread = best_t.narrow_rows_per_thread;
-    out->wide_max_wg = best_t.wide_max_wg;
-    out->lp_min_cols = best_t.lp_min_cols;
-    out->mixed_min_cols = best_t.mixed_min_cols;
-    out->fused_steps = best_t.fused_steps;
+    shapes(start);
+    auto search = [&](int pa::LaunchTune::*field, std::initializer_list<int> vals) {
+      const pa::LaunchTune from = best_t;
+      for (int v : vals) {
+        pa::LaunchTune t = from;
+        t.*field = v;
+        trial(t);
+      }
+    };
+    if (c.precond == PA_PRECOND_LEARNED) search(&pa::LaunchTune::lp_min_cols, {1, 8, 64, kLpNever});
+    if (c.precision == PA_FP32_REFINED) search(&pa::LaunchTune::mixed_min_cols, {1, 8, 64, kLpNever});
+    if (c.solver == PA_SOLVER_CHEBYSHEV) search(&pa::LaunchTune::fused_steps, {1, 2, 3, 4, 5, 6});
+    // the shape again for the fields found (a learned threshold, a mixed
+    // threshold or a step count can change which shape is fastest)
+    shapes(best_t);
+    ops->tune = best_t;
+    ops->has_tune = true;
+    tune_out(best_t, out);
     out->best_ms = best;
   });
 }

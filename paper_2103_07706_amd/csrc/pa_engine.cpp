@@ -32,7 +32,8 @@ static int tiles_of(int Bs) { return Bs <= 64 ? 1 : Bs / 64; }
 
 Engine::Engine(pa_ctx *ctx, const pa_ops *ops, const pa_solve_cfg &cfg, void *ws, size_t ws_bytes)
     : ctx_(ctx), ops_(ops), cfg_(cfg), s_(ctx ? ctx->stream : nullptr), ne_(ops->ne),
-      nc_(ops->nc), n_(ops->ne + ops->nc), ar_(ws, ws_bytes), ws_base_(ws) {
+      nc_(ops->nc), n_(ops->ne + ops->nc), ar_(ws, ws_bytes), ws_base_(ws),
+      tune_(ops->effective_tune()) {
   if (cfg_.maxit <= 0) throw Error(PA_EINVAL, "maxit must be positive");
   if (!(cfg_.cg_rtol > 0)) throw Error(PA_EINVAL, "cg_rtol must be positive");
   if (!(cfg_.cheb_tol > 0)) throw Error(PA_EINVAL, "cheb_tol must be positive");
@@ -239,7 +240,7 @@ void Engine::flush_check() {
 // halve the bytes of a step, which pays where steps are bandwidth bound);
 // narrower blocks, whose steps are launch-latency bound, take FP64 steps.
 void Engine::mass_solve(double *x, int Bs, const int *colK, int kneed, int nwg_init) {
-  if (mixed() && Bs >= launch_tuning().mixed_min_cols)
+  if (mixed() && Bs >= tune_.mixed_min_cols)
     mixed_solve(x, Bs, colK, kneed, nwg_init, false);
   else if (cheb() || mixed())
     cheb_solve(x, Bs, colK, kneed, nwg_init);
@@ -252,7 +253,7 @@ void Engine::mass_solve(double *x, int Bs, const int *colK, int kneed, int nwg_i
 // three rings of neighbours against one), so fewer steps pay only on wide
 // enough blocks; the threshold is part of the launch shape, which the
 // autotuner measures.
-bool Engine::lp_cheaper(int Bs) const { return lp_avail_ && Bs >= launch_tuning().lp_min_cols; }
+bool Engine::lp_cheaper(int Bs) const { return lp_avail_ && Bs >= tune_.lp_min_cols; }
 
 // Jacobi semi-iteration of a single column, S steps per launch
 // (k_cheb_fused): the remainder of the step count first, then launches of S
@@ -307,6 +308,7 @@ void Engine::cheb_fused(double *x, const int *colK, int kneed, int nwg_init, int
     b.d_out = d[1];
     b.last = c == k ? 1 : 0;
     b.bytes = prof ? fused_bytes(c + 1, b.last, true) : 0;
+    if (prof) prof_units_ += c;
     launch_cheb_fused(b, s_);
     buf = 1;
     i = c;
@@ -328,6 +330,7 @@ void Engine::cheb_fused(double *x, const int *colK, int kneed, int nwg_init, int
     a.r_out = r[buf ^ 1];
     a.last = i + n == k ? 1 : 0;
     a.bytes = prof ? fused_bytes(n, a.last, false) : 0;
+    if (prof) prof_units_ += n;
     launch_cheb_fused(a, s_);
     buf ^= 1;
     i += n;
@@ -369,16 +372,16 @@ unsigned long long Engine::fused_bytes(int n, int last, bool setup) const {
 // launch can do (the solve takes the fused Jacobi path), else 0.
 int Engine::fused_setup_steps() const {
   if (!cheb() && !mixed()) return 0;
-  if (mixed() && 1 >= launch_tuning().mixed_min_cols) return 0;
+  if (mixed() && 1 >= tune_.mixed_min_cols) return 0;
   if (lp_cheaper(1)) return 0;
-  const int S = std::min(launch_tuning().fused_steps, ops_->fused_max);
+  const int S = std::min(tune_.fused_steps, ops_->fused_max);
   if (S < 2 || ops_->fused_cpp <= 0 || cheb_fused_grid(ops_->d) <= 0) return 0;
   return S;
 }
 
 void Engine::cheb_solve(double *x, int Bs, const int *colK, int kneed, int nwg_init) {
   const bool lp = lp_cheaper(Bs);
-  const int S = std::min(launch_tuning().fused_steps, ops_->fused_max);
+  const int S = std::min(tune_.fused_steps, ops_->fused_max);
   if (!lp && Bs == 1 && S > 1) {
     const int grid = cheb_fused_grid(ops_->d);
     if (grid > 0) return cheb_fused(x, colK, kneed, nwg_init, grid, S, nullptr);
@@ -609,6 +612,7 @@ void Engine::begin() {
 }
 
 void Engine::finish() {
+  TuneScope tune_scope(tune_);
   PA_HIP(hipEventRecord(ev1_, s_));
   // counters z+2 .. z+11: fail, iter_max, prof[3], budget_fail, cheb_fail,
   // (pad), resid_max bits
@@ -660,6 +664,11 @@ void Engine::finish() {
       std::memcpy(&fb, &h[10], sizeof(fb));
       ctx_->prof_bytes += (double)fb;
     }
+    // mass-solve steps times the columns they ran on: counted on the host
+    // for the fused steps (a launch runs several), from the kernels' count
+    // of active columns for the one-step kernels
+    ctx_->prof_units += ctx_->prof_kernel == PA_KERNEL_CHEB_FUSED ? prof_units_ : cols;
+    prof_units_ = 0;
     ctx_->prof_work += (int64_t)work;
   }
   float ms = 0;
@@ -988,7 +997,7 @@ void Engine::nonlinear_block(Blk E, Blk Y, const int *colK) {
   gth.st = st_;
   gth.rb = rb_;
   gth.max_wg = rb_.max_wg;
-  const bool refined = mixed() && E.Bs >= launch_tuning().mixed_min_cols;
+  const bool refined = mixed() && E.Bs >= tune_.mixed_min_cols;
   if (cheb() || mixed()) {
     if (refined) {
       // the gather writes the first refinement's outputs
@@ -1045,6 +1054,7 @@ void Engine::run_exp(ExpBufs &eb, Blk in, Blk out) {
 }
 
 void Engine::expL_apply(int B, const double *t, const double *Uin, double *Uout) {
+  TuneScope tune_scope(tune_);
   if (B <= 0) throw Error(PA_EINVAL, "B must be positive");
   if (!(ops_->lambda_bar > 0)) throw Error(PA_EINVAL, "lambda_bar is not set");
   const int Bs = pad_cols(B);
@@ -1066,6 +1076,7 @@ void Engine::expL_apply(int B, const double *t, const double *Uin, double *Uout)
 
 // ---------------------------------------------------------- nonlinearity
 void Engine::swe_nonlinear(int B, const double *U, double *NU) {
+  TuneScope tune_scope(tune_);
   if (B <= 0) throw Error(PA_EINVAL, "B must be positive");
   const int Bs = pad_cols(B);
   plan_common(Bs);
@@ -1231,6 +1242,7 @@ void Engine::run_nbar(NbarBufs &nb, Blk X, Blk out, bool uploaded) {
 
 void Engine::nbar_plan(NbarCall &c, const pa_avg *avg, int members, const double *U,
                        double *Nbar) {
+  TuneScope tune_scope(tune_);
   if (members <= 0) throw Error(PA_EINVAL, "members must be positive");
   c.avg = avg;
   c.members = members;
@@ -1249,11 +1261,13 @@ void Engine::nbar_plan(NbarCall &c, const pa_avg *avg, int members, const double
 }
 
 void Engine::nbar_begin(NbarCall &c) {
+  TuneScope tune_scope(tune_);
   begin();
   upload_nbar(c.nb);
 }
 
 void Engine::nbar_body(NbarCall &c) {
+  TuneScope tune_scope(tune_);
   // the members go straight into R_0 of the basis; with one member the block
   // layout is the state layout, and the result is formed in place
   const Blk r0{c.nb.basis, c.nb.Bm};
@@ -1279,6 +1293,7 @@ int Engine::current_budget() const {
 bool Engine::sync_free() const { return current_budget() > 0 || cheb() || mixed(); }
 
 void Engine::phase_avg_rhs(const pa_avg *avg, int members, const double *U, double *Nbar) {
+  TuneScope tune_scope(tune_);
   NbarCall c;
   nbar_plan(c, avg, members, U, Nbar);
   if (ar_.sizing()) return;
@@ -1287,17 +1302,16 @@ void Engine::phase_avg_rhs(const pa_avg *avg, int members, const double *U, doub
   // capture stream) and replayed while nothing it depends on changes.
   if (cfg_.use_graph && sync_free() && ctx_->prof_kernel == PA_KERNEL_NONE) {
     GraphKey key;
-    key.ops = ops_;
-    key.avg = avg;
+    key.ops_gen = ops_->gen;
+    key.avg_gen = avg->gen;
     key.members = members;
     key.in = U;
     key.out = Nbar;
     key.ws = ws_base_;
     key.budget = current_budget();
     key.lambda_bar = ops_->lambda_bar;
-    key.lp_dev = ops_->lp_dev;
     key.cfg = cfg_;
-    key.tune = launch_tuning();
+    key.tune = tune_;
     run_graph(key, [&] { nbar_body(c); });
   } else {
     nbar_body(c);
@@ -1337,6 +1351,7 @@ void Engine::run_graph(const GraphKey &key, const std::function<void()> &body) {
     ctx_->graph_exec = ex;
     ctx_->graph_key = key;
     ctx_->graph_stats = stats;
+    stats.graph_captured = 1;
   } else {
     stats = ctx_->graph_stats;
   }
@@ -1356,6 +1371,7 @@ void Engine::run_graph(const GraphKey &key, const std::function<void()> &body) {
 // (exp(L dt/2) exp(L s) = exp(L s) exp(L dt/2) as polynomials in L, and the
 // exponentials are linear, so the printed stage-4 sum regroups this way).
 void Engine::step(const pa_avg *avg, double dt, int members, double *U) {
+  TuneScope tune_scope(tune_);
   if (members <= 0) throw Error(PA_EINVAL, "members must be positive");
   NbarBufs nb;
   plan_nbar(nb, avg, members);
@@ -1403,6 +1419,7 @@ void Engine::step(const pa_avg *avg, double dt, int members, double *U) {
 
 // ------------------------------------------------------------ lambda_bar
 double Engine::estimate_lambda(int iters) {
+  TuneScope tune_scope(tune_);
   plan_common(1);
   Blk v = block(1), a = block(1), b = block(1);
   double *wd = ar_.take<double>(5);
@@ -1440,6 +1457,7 @@ double Engine::estimate_lambda(int iters) {
 }
 
 void Engine::diagnostics(int B, const double *U, double *out_host) {
+  TuneScope tune_scope(tune_);
   const int Bs = pad_cols(B);
   plan_common(Bs);
   Blk X = block(Bs);

@@ -13,6 +13,13 @@ std::vector<double> bessel_weights(double theta, int kcap);
 int truncate_degree(const std::vector<double> &c, double tol);
 void assemble_ops(pa_ops *o, const Mesh &m, const pa_phys &ph);
 
+// Workspace bytes of every call on `batch` states under configuration c.
+size_t workspace_bytes(const pa_ops *ops, const pa_avg *avg, int batch, const pa_solve_cfg &c);
+// pa_phase_avg_rhs on a given workspace (argument checks, repeat rules).
+void phase_avg_rhs_call(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, int members,
+                        const double *U_dev, double *Nbar_dev, void *ws, size_t ws_bytes,
+                        const pa_solve_cfg &cfg, pa_stats *stats);
+
 // Columns of a block: next power of two up to 64, then multiples of 64.
 int pad_cols(int B);
 
@@ -158,6 +165,7 @@ class Engine {
   };
   void diag(Blk X, double *out);
   std::vector<ProfSpan> prof_ev_;
+  double prof_units_ = 0;  // fused mass-solve steps launched while profiling
 
   // phase average on a block of member columns X -> out (both [n][Bm])
  public:
@@ -189,6 +197,10 @@ class Engine {
   bool sync_free() const;
   int current_budget() const;
   void set_stream(hipStream_t s) { s_ = s; }
+  // launch shape of this call's kernels (default: the operators' own shape,
+  // else the process default)
+  void set_tune(const LaunchTune &t) { tune_ = clamp_tune(t); }
+  const LaunchTune &tune() const { return tune_; }
   hipStream_t stream() const { return s_; }
 
  private:
@@ -225,6 +237,7 @@ class Engine {
   int *colK0_ = nullptr;  // all zeros
   int predicted_ = 8;
   void *ws_base_ = nullptr;
+  LaunchTune tune_;
   bool budget_ok_ = false, learn_budget_ = false;
   hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
 };

@@ -168,18 +168,40 @@ inline bool same_cfg(const pa_solve_cfg &a, const pa_solve_cfg &b) {
          a.solver == b.solver && a.precond == b.precond;
 }
 
+// Objects whose contents a captured graph bakes in (operators and their
+// bound buffers, averaging nodes) carry a generation number, unique over
+// the process and renewed whenever the contents or the device buffers
+// change: a new object at a freed object's address never matches a key.
+uint64_t next_generation();
+
 struct GraphKey {
-  const void *ops = nullptr, *avg = nullptr, *in = nullptr, *out = nullptr, *ws = nullptr;
-  const void *lp_dev = nullptr;
+  const void *in = nullptr, *out = nullptr, *ws = nullptr;
+  uint64_t ops_gen = 0, avg_gen = 0;
   int members = 0, budget = 0;
   double lambda_bar = 0;
   pa_solve_cfg cfg{};
   LaunchTune tune{};
   bool operator==(const GraphKey &o) const {
-    return ops == o.ops && avg == o.avg && in == o.in && out == o.out && ws == o.ws &&
-           lp_dev == o.lp_dev && members == o.members && budget == o.budget &&
+    return ops_gen == o.ops_gen && avg_gen == o.avg_gen && in == o.in && out == o.out &&
+           ws == o.ws && members == o.members && budget == o.budget &&
            lambda_bar == o.lambda_bar && tune == o.tune && same_cfg(cfg, o.cfg);
   }
+};
+
+// Launch shape in force for the kernels the calling thread enqueues: set by
+// each call for its duration (TuneScope) from the operators' own shape, a
+// batch item's shape or the process default.
+LaunchTune launch_default();
+void set_launch_default(const LaunchTune &t);
+LaunchTune clamp_tune(LaunchTune t);
+struct TuneScope {
+  explicit TuneScope(const LaunchTune &t);
+  ~TuneScope();
+  TuneScope(const TuneScope &) = delete;
+  TuneScope &operator=(const TuneScope &) = delete;
+
+ private:
+  const LaunchTune *prev_;
 };
 
 }  // namespace pa
@@ -201,7 +223,7 @@ struct pa_ctx {
   int prof_kernel = 0;
   std::vector<hipEvent_t> prof_pool;
   int64_t prof_launches = 0, prof_work = 0;
-  double prof_ms = 0.0, prof_bytes = 0.0;
+  double prof_ms = 0.0, prof_bytes = 0.0, prof_units = 0.0;
 };
 
 struct pa_mesh {
@@ -210,6 +232,12 @@ struct pa_mesh {
 
 struct pa_ops {
   const pa_mesh *mesh = nullptr;
+  uint64_t gen = 0;  // renewed at creation, bind, learned-table attach and bind
+  // the operators' own launch shape (pa_ops_set_tune, pa_autotune); without
+  // one, calls take the process default
+  mutable pa::LaunchTune tune{};
+  mutable bool has_tune = false;
+  pa::LaunchTune effective_tune() const { return has_tune ? tune : pa::launch_default(); }
   int ne = 0, nc = 0;
   double g = 0, H = 0, omega = 0, lambda_bar = 0;
   double mass_eig_min = 0, mass_eig_max = 0;  // Ritz bounds of D^-1 M
@@ -237,5 +265,6 @@ struct pa_ops {
 };
 
 struct pa_avg {
+  uint64_t gen = pa::next_generation();  // nodes and weights never change
   std::vector<double> s, w;
 };

@@ -319,8 +319,9 @@ int launch_max_wg();
 // elapsed time is the kernel's own duration.
 void arm_launch_events(hipEvent_t e0, hipEvent_t e1);
 bool launch_events_armed();
+// the launch shape in force for the calling thread (the enclosing
+// TuneScope's, else the process default)
 LaunchTune launch_tuning();
-void set_launch_tuning(const LaunchTune &t);
 int launch_rows_grid(int rows, int Bs);
 void launch_finalize(const FinArgs &a, hipStream_t s);
 void launch_stiff(const StiffArgs &a, hipStream_t s);

@@ -20,6 +20,8 @@
 
 #include <hip/hip_ext.h>
 
+#include <mutex>
+
 #include "pa_kernels.h"
 
 namespace pa {
@@ -1651,7 +1653,11 @@ namespace {
 // lane_map).  Narrow batches (Bs <= 4) are latency-bound: about four rows per
 // thread keeps the launch short and the partial sums few.  Wider ones fill
 // the 256 CUs several times over, split over the column tiles.
-LaunchTune g_tune;  // process-wide launch shape (see set_launch_tuning)
+// process default launch shape (pa_set_launch_tune), and the shape of the
+// call the calling thread is enqueueing (TuneScope)
+LaunchTune g_default_tune;
+std::mutex g_default_mu;
+thread_local const LaunchTune *t_tune = nullptr;
 // measurement hook: events that the next launch of a profiled kernel
 // records as part of its dispatch (start and end of the kernel itself)
 hipEvent_t g_ev0 = nullptr, g_ev1 = nullptr;
@@ -1671,13 +1677,14 @@ int grid_rows(int rows, int Bs) {
   const int rows_per_pass = (kWG / 64) * (64 / ct);
   const int ctiles = (Bs + 63) / 64;
   int want, cap;
+  const LaunchTune tune = launch_tuning();
   if (Bs <= 4) {
-    const int rpt = g_tune.narrow_rows_per_thread;
+    const int rpt = tune.narrow_rows_per_thread;
     want = (rows + rpt * rows_per_pass - 1) / (rpt * rows_per_pass);
     cap = 2048;
   } else {
     want = (rows + rows_per_pass - 1) / rows_per_pass;
-    cap = ctiles >= 8 ? 256 : g_tune.wide_max_wg / ctiles;
+    cap = ctiles >= 8 ? 256 : tune.wide_max_wg / ctiles;
   }
   int g = want < cap ? want : cap;
   g = (g + 7) / 8 * 8;
@@ -1713,17 +1720,27 @@ dim3 rows_grid_full(int rows, int Bs) {
 }  // namespace
 
 int launch_max_wg() { return 2048; }
-LaunchTune launch_tuning() { return g_tune; }
-void set_launch_tuning(const LaunchTune &t) {
-  g_tune = t;
-  if (g_tune.narrow_rows_per_thread < 1) g_tune.narrow_rows_per_thread = 1;
-  if (g_tune.wide_max_wg < 8) g_tune.wide_max_wg = 8;
-  if (g_tune.wide_max_wg > 2048) g_tune.wide_max_wg = 2048;
-  if (g_tune.lp_min_cols < 1) g_tune.lp_min_cols = 1;
-  if (g_tune.mixed_min_cols < 1) g_tune.mixed_min_cols = 1;
-  if (g_tune.fused_steps < 1) g_tune.fused_steps = 1;
-  if (g_tune.fused_steps > kFusedMax) g_tune.fused_steps = kFusedMax;
+LaunchTune launch_default() {
+  std::lock_guard<std::mutex> lk(g_default_mu);
+  return g_default_tune;
 }
+void set_launch_default(const LaunchTune &t) {
+  std::lock_guard<std::mutex> lk(g_default_mu);
+  g_default_tune = clamp_tune(t);
+}
+LaunchTune launch_tuning() { return t_tune ? *t_tune : launch_default(); }
+LaunchTune clamp_tune(LaunchTune t) {
+  if (t.narrow_rows_per_thread < 1) t.narrow_rows_per_thread = 1;
+  if (t.wide_max_wg < 8) t.wide_max_wg = 8;
+  if (t.wide_max_wg > 2048) t.wide_max_wg = 2048;
+  if (t.lp_min_cols < 1) t.lp_min_cols = 1;
+  if (t.mixed_min_cols < 1) t.mixed_min_cols = 1;
+  if (t.fused_steps < 1) t.fused_steps = 1;
+  if (t.fused_steps > kFusedMax) t.fused_steps = kFusedMax;
+  return t;
+}
+TuneScope::TuneScope(const LaunchTune &t) : prev_(t_tune) { t_tune = &t; }
+TuneScope::~TuneScope() { t_tune = prev_; }
 int launch_rows_grid(int rows, int Bs) { return grid_rows(rows, Bs); }
 
 void launch_stiff(const StiffArgs &a, hipStream_t s) {

@@ -563,6 +563,7 @@ int pa_ops_lp_bind(pa_ctx *ctx, pa_ops *ops, void *dev_buf) {
     pa::sync_checked(s);
     ops->lp = d;
     ops->lp_dev = dev_buf;
+    ops->gen = pa::next_generation();
   });
 }
 

@@ -302,6 +302,7 @@ void lp_build_preconditioner(pa_ops *o, const std::vector<double> &gd, const std
       },
       200, &o->lp_eig_min, &o->lp_eig_max);
   o->lp_ready = true;
+  o->gen = next_generation();
   o->lp_dev = nullptr;  // tables changed: bind again
 }
 

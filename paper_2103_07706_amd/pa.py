@@ -73,7 +73,8 @@ class LpInfo(ctypes.Structure):
 
 class KernelProfile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64), ("work_launches", ctypes.c_int64),
-                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double),
+                ("units", ctypes.c_double)]
 
 
 class LaunchTune(ctypes.Structure):
@@ -106,7 +107,7 @@ class Stats(ctypes.Structure):
                 ("resid_max", ctypes.c_double), ("device_ms", ctypes.c_double),
                 ("graph", ctypes.c_int32), ("budget", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("lp_solves", ctypes.c_int32),
-                ("fallbacks", ctypes.c_int32)]
+                ("fallbacks", ctypes.c_int32), ("graph_captured", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -156,6 +157,8 @@ EXPORTS = {
     "pa_diagnostics": (ctypes.c_int, [_V, _V, ctypes.c_int, _V, _V, _SZ, _D]),
     "pa_get_launch_tune": (ctypes.c_int, [ctypes.POINTER(LaunchTune)]),
     "pa_set_launch_tune": (ctypes.c_int, [ctypes.POINTER(LaunchTune)]),
+    "pa_ops_set_tune": (ctypes.c_int, [_V, ctypes.POINTER(LaunchTune)]),
+    "pa_ops_get_tune": (ctypes.c_int, [_V, ctypes.POINTER(LaunchTune), ctypes.POINTER(ctypes.c_int)]),
     "pa_autotune": (ctypes.c_int, [_V, _V, _V, ctypes.c_int, _V, _V, _V, _SZ,
                                    ctypes.POINTER(SolveCfg), ctypes.POINTER(LaunchTune)]),
     "pa_batch_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_V), _I, _V,
@@ -240,27 +243,23 @@ def set_launch_tune(**changes):
     _check(lib().pa_set_launch_tune(ctypes.byref(_tune_struct(cur))))
 
 
-def solve_cfg(precision=PA_FP64, backward=PA_BACKWARD_PER_TERM, maxit=None, cg_rtol=None,
-              cheb_tol=None, weight_cut=None, inner_rtol=None, use_graph=False,
-              solver=PA_SOLVER_CG, precond=PA_PRECOND_JACOBI, growth_guard=0) -> SolveCfg:
+def solve_cfg(precision=None, backward=None, maxit=None, cg_rtol=None, cheb_tol=None,
+              weight_cut=None, inner_rtol=None, use_graph=None, solver=None, precond=None,
+              growth_guard=None) -> SolveCfg:
+    """A solve configuration: the library's defaults (pa_solve_cfg_default:
+    FP64, Clenshaw backward sum, Chebyshev mass solves, graph replay, Jacobi
+    preconditioning, cg_rtol 1e-10, Chebyshev threshold 1e-6) with the given
+    fields changed."""
     c = SolveCfg()
     lib().pa_solve_cfg_default(ctypes.byref(c))
-    c.growth_guard = growth_guard
-    c.solver = solver
-    c.precond = precond
-    c.precision = precision
-    c.backward = backward
-    c.use_graph = 1 if use_graph else 0
-    if maxit is not None:
-        c.maxit = maxit
-    if cg_rtol is not None:
-        c.cg_rtol = cg_rtol
-    if cheb_tol is not None:
-        c.cheb_tol = cheb_tol
-    if weight_cut is not None:
-        c.weight_cut = weight_cut
-    if inner_rtol is not None:
-        c.inner_rtol = inner_rtol
+    for name, v in (("precision", precision), ("backward", backward), ("maxit", maxit),
+                    ("cg_rtol", cg_rtol), ("cheb_tol", cheb_tol), ("weight_cut", weight_cut),
+                    ("inner_rtol", inner_rtol), ("solver", solver), ("precond", precond),
+                    ("growth_guard", growth_guard)):
+        if v is not None:
+            setattr(c, name, v)
+    if use_graph is not None:
+        c.use_graph = 1 if use_graph else 0
     return c
 
 
@@ -361,13 +360,20 @@ class Ops:
         h = _V()
         _check(lib().pa_ops_create(mesh._h, ctypes.byref(ph), ctypes.byref(h)))
         self._h = h
-        sz = _SZ()
-        _check(lib().pa_ops_device_size(h, ctypes.byref(sz)))
-        self._buf = torch.empty(sz.value + 256, dtype=torch.uint8, device=f"cuda:{ctx.device}")
-        base = self._buf.data_ptr()
-        off = (-base) % 256
-        _check(lib().pa_ops_bind(ctx._h, h, _V(base + off)))
         self._ws = None
+        self.rebind()
+
+    def rebind(self):
+        """Upload the operators into a newly allocated device buffer
+        (pa_ops_bind); the previous buffer may then be freed."""
+        import torch
+        sz = _SZ()
+        _check(lib().pa_ops_device_size(self._h, ctypes.byref(sz)))
+        buf = torch.empty(sz.value + 256, dtype=torch.uint8, device=f"cuda:{self.ctx.device}")
+        base = buf.data_ptr()
+        off = (-base) % 256
+        _check(lib().pa_ops_bind(self.ctx._h, self._h, _V(base + off)))
+        self._buf = buf
 
     @property
     def n(self):
@@ -459,7 +465,7 @@ class Ops:
         if cache and os.path.exists(cache):
             table = json.load(open(cache))
             if key in table:
-                _check(lib().pa_set_launch_tune(ctypes.byref(_tune_struct(table[key]))))
+                self.set_tune(**{k: table[key][k] for k in TUNE_FIELDS})
                 return dict(table[key], cached=True)
         out = U.new_empty(U.shape)
         ws, nb = self.workspace(avg, members, cfg)
@@ -472,6 +478,30 @@ class Ops:
             with open(cache, "w") as f:
                 json.dump(table, f, indent=1)
         return dict(res, cached=False)
+
+    def set_tune(self, **fields):
+        """Give these operators their own launch shape (pa_ops_set_tune):
+        the fields given, the others from the shape in use now.  With no
+        fields, drop the own shape (calls take the process default)."""
+        if not fields:
+            _check(lib().pa_ops_set_tune(self._h, None))
+            return
+        cur = self.get_tune()
+        cur.update(fields)
+        _check(lib().pa_ops_set_tune(self._h, ctypes.byref(_tune_struct(cur))))
+
+    def get_tune(self):
+        """The launch shape calls on these operators use (pa_ops_get_tune)."""
+        t = LaunchTune()
+        own = ctypes.c_int()
+        _check(lib().pa_ops_get_tune(self._h, ctypes.byref(t), ctypes.byref(own)))
+        return _tune_dict(t)
+
+    def has_own_tune(self):
+        t = LaunchTune()
+        own = ctypes.c_int()
+        _check(lib().pa_ops_get_tune(self._h, ctypes.byref(t), ctypes.byref(own)))
+        return bool(own.value)
 
     def diagnostics(self, U):
         B = U.shape[0]

@@ -27,9 +27,9 @@ def _singles(ops, avg, states, cfg):
 
 
 CFGS = {
-    "cg_polled": dict(),
-    "cg_graph": dict(use_graph=True),
-    "cheb_eager": dict(solver=1),
+    "cg_polled": dict(solver=0, use_graph=False),
+    "cg_graph": dict(solver=0, use_graph=True),
+    "cheb_eager": dict(solver=1, use_graph=False),
     "cheb_graph": dict(solver=1, use_graph=True),
     "fp32_refined_graph": dict(solver=1, precision=1, use_graph=True),
 }
@@ -45,10 +45,6 @@ def test_gpu_batch_equals_single_calls(name):
     ops, states = _problem()
     avg = pa.Avg(8, 3600.0)
     kw = dict(CFGS[name])
-    if "solver" in kw:
-        kw["solver"] = pa.PA_SOLVER_CHEBYSHEV
-    if "precision" in kw:
-        kw["precision"] = pa.PA_FP32_REFINED
     cfg = pa.solve_cfg(backward=pa.PA_BACKWARD_CLENSHAW, cg_rtol=1e-12, **kw)
     ref = _singles(ops, avg, states, cfg)
     b = pa.Batch(ops[0].ctx, list(zip(ops, [m for _, m in ITEMS])), avg)

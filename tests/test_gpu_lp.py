@@ -171,7 +171,7 @@ def test_gpu_lp_solves_parity(lp_min_cols):
         assert rel_w(oo, got, gj) < 1e-12
         # metric tolerances, graph capture and replay
         mcfg = dict(precond=pa.PA_PRECOND_LEARNED, cheb_tol=1e-6, cg_rtol=1e-10, **base)
-        eager, _ = lo.phase_avg_rhs(avg, Ud, pa.solve_cfg(**mcfg))
+        eager, _ = lo.phase_avg_rhs(avg, Ud, pa.solve_cfg(use_graph=False, **mcfg))
         eager = eager.cpu().numpy()
         gcfg = pa.solve_cfg(use_graph=True, **mcfg)
         out = torch.empty_like(Ud)

@@ -46,15 +46,16 @@ def test_gpu_nonlinear_parity():
         assert _maxrel(got[j], ref, om.ne) < 1e-11
 
 
+@pytest.mark.parametrize("solver", [0, 1])
 @pytest.mark.parametrize("backward", ["per_term", "clenshaw"])
 @pytest.mark.parametrize("M,T", [(8, 3600.0), (5, 2000.0), (1, 1000.0)])
-def test_gpu_phase_avg_rhs_parity(backward, M, T):
+def test_gpu_phase_avg_rhs_parity(backward, M, T, solver):
     from paper_2103_07706_amd import pa
     om, oo, lm, lo, mm, lb = pair(3)
     U = bumps(om, [0])
     avg = pa.Avg(M, T)
     bw = pa.PA_BACKWARD_PER_TERM if backward == "per_term" else pa.PA_BACKWARD_CLENSHAW
-    cfg = pa.solve_cfg(backward=bw, weight_cut=0.0, **PARITY)
+    cfg = pa.solve_cfg(backward=bw, solver=solver, weight_cut=0.0, **PARITY)
     out, st = lo.phase_avg_rhs(avg, to_dev(mm.state(U)), cfg)
     got = mm.back(out.cpu().numpy())[0]
     ref = oo.phase_avg_rhs(lb, *onodes(avg), U[0], tol=1e-13, rtol=1e-14)
@@ -193,7 +194,7 @@ def test_gpu_expL_batch_shapes(B):
     rng = np.random.default_rng(B)
     ts = rng.uniform(-5000.0, 5000.0, B)
     U = bumps(om, [j % 7 for j in range(B)])
-    out, st = lo.expL_apply(ts, to_dev(mm.state(U)), pa.solve_cfg(**PARITY))
+    out, st = lo.expL_apply(ts, to_dev(mm.state(U)), pa.solve_cfg(solver=0, **PARITY))
     got = mm.back(out.cpu().numpy())
     for j in range(0, B, max(1, B // 6)):
         ref, _ = oo.expL(lb, ts[j], U[j], tol=1e-13, rtol=1e-14)
@@ -208,7 +209,7 @@ def test_gpu_budget_mode_and_repeat():
     om, oo, lm, lo, mm, lb = pair(3)
     U = to_dev(mm.state(bumps(om, [2])))
     avg = pa.Avg(8, 3600.0)
-    cfg = pa.solve_cfg(cg_rtol=1e-11)
+    cfg = pa.solve_cfg(cg_rtol=1e-11, solver=0, use_graph=False)
     lo.ctx.set_cg_budget(1e-11, 0)
     a, sa = lo.phase_avg_rhs(avg, U, cfg)   # polling, learns the budget
     b, sb = lo.phase_avg_rhs(avg, U, cfg)   # budget
@@ -229,9 +230,9 @@ def test_gpu_graph_replay_matches_eager():
     om, oo, lm, lo, mm, lb = pair(3)
     U = to_dev(mm.state(bumps(om, [1])))
     avg = pa.Avg(8, 3600.0)
-    ref, _ = lo.phase_avg_rhs(avg, U, pa.solve_cfg(cg_rtol=1e-12))
+    ref, _ = lo.phase_avg_rhs(avg, U, pa.solve_cfg(cg_rtol=1e-12, solver=0, use_graph=False))
     ref = ref.cpu().numpy()
-    gcfg = pa.solve_cfg(cg_rtol=1e-12, use_graph=True)
+    gcfg = pa.solve_cfg(cg_rtol=1e-12, solver=0, use_graph=True)
     out = torch.empty_like(U)
     graphs = 0
     for i in range(4):
@@ -255,13 +256,107 @@ def test_gpu_autotune_keeps_parity(tmp_path):
     cfg = pa.solve_cfg(weight_cut=0.0, use_graph=True, **PARITY)
     Ud = to_dev(mm.state(U))
     cache = str(tmp_path / "tune.json")
-    res = lo.autotune(avg, Ud, cfg, cache=cache)
-    assert res["narrow_rows_per_thread"] in (1, 2, 4, 8) and not res["cached"]
-    assert lo.autotune(avg, Ud, cfg, cache=cache)["cached"]
-    out, _ = lo.phase_avg_rhs(avg, Ud, cfg)
-    got = mm.back(out.cpu().numpy())[0]
-    ref = oo.phase_avg_rhs(lb, *onodes(avg), U[0], tol=1e-13, rtol=1e-14)
-    check_parity(oo, got, ref, TOL)
+    default = pa.get_launch_tune()
+    try:
+        res = lo.autotune(avg, Ud, cfg, cache=cache)
+        assert res["narrow_rows_per_thread"] in (1, 2, 4, 8) and not res["cached"]
+        # the choice belongs to these operators; the process default is untouched
+        assert lo.has_own_tune() and pa.get_launch_tune() == default
+        assert lo.get_tune() == {k: res[k] for k in pa.TUNE_FIELDS}
+        lo.set_tune()
+        assert not lo.has_own_tune()
+        assert lo.autotune(avg, Ud, cfg, cache=cache)["cached"]
+        assert lo.get_tune() == {k: res[k] for k in pa.TUNE_FIELDS}
+        out, _ = lo.phase_avg_rhs(avg, Ud, cfg)
+        got = mm.back(out.cpu().numpy())[0]
+        ref = oo.phase_avg_rhs(lb, *onodes(avg), U[0], tol=1e-13, rtol=1e-14)
+        check_parity(oo, got, ref, TOL)
+    finally:
+        lo.set_tune()
+
+
+def test_gpu_launch_shapes_belong_to_operators():
+    """Two operator objects with different launch shapes (CG solves, whose
+    reductions group their partial sums by the grid, so the shape shows in
+    the bits), run alternately and from two threads at once, each give
+    exactly the result they give alone; graph replays of both keep theirs."""
+    import threading
+    from paper_2103_07706_amd import pa
+    from gpu_common import _ctx
+    om, oo, lm, lo, mm, lb = pair(3)
+    A = pa.Ops(_ctx(), lm)
+    B = pa.Ops(_ctx(), lm)
+    for o in (A, B):
+        o.lambda_bar = lb
+    A.set_tune(narrow_rows_per_thread=1, wide_max_wg=512)
+    B.set_tune(narrow_rows_per_thread=8, wide_max_wg=2048)
+    U = to_dev(mm.state(bumps(om, [3])))
+    avg = pa.Avg(8, 3600.0)
+    cfg = pa.solve_cfg(solver=0, cg_rtol=1e-12, use_graph=False)
+    a0 = A.phase_avg_rhs(avg, U, cfg)[0].cpu().numpy()
+    b0 = B.phase_avg_rhs(avg, U, cfg)[0].cpu().numpy()
+    assert not np.array_equal(a0, b0)  # the shapes are visible in the bits
+    for _ in range(2):
+        assert np.array_equal(A.phase_avg_rhs(avg, U, cfg)[0].cpu().numpy(), a0)
+        assert np.array_equal(B.phase_avg_rhs(avg, U, cfg)[0].cpu().numpy(), b0)
+    results = {}
+
+    def run(name, o, ref):
+        import torch
+        ctx = pa.Context(0, stream=torch.cuda.Stream(0).cuda_stream)
+        mine = pa.Ops(ctx, lm)
+        mine.lambda_bar = lb
+        mine.set_tune(**o.get_tune())
+        ok = True
+        for _ in range(4):
+            out = mine.phase_avg_rhs(avg, U, cfg)[0]
+            torch.cuda.synchronize()
+            ok = ok and np.array_equal(out.cpu().numpy(), ref)
+        results[name] = ok
+
+    th = [threading.Thread(target=run, args=("A", A, a0)),
+          threading.Thread(target=run, args=("B", B, b0))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert results == {"A": True, "B": True}
+    gcfg = pa.solve_cfg(solver=0, cg_rtol=1e-12, use_graph=True)
+    ga = A.phase_avg_rhs(avg, U, gcfg)[0].cpu().numpy()
+    gb = B.phase_avg_rhs(avg, U, gcfg)[0].cpu().numpy()
+    assert np.array_equal(A.phase_avg_rhs(avg, U, gcfg)[0].cpu().numpy(), ga)
+    assert np.array_equal(B.phase_avg_rhs(avg, U, gcfg)[0].cpu().numpy(), gb)
+
+
+def test_gpu_graph_cache_follows_object_contents():
+    """A captured graph is not replayed for different averaging nodes or
+    rebound operators that happen to reuse a freed object's address: each
+    result equals the oracle for its own nodes."""
+    import gc
+    from paper_2103_07706_amd import pa
+    om, oo, lm, lo, mm, lb = pair(3)
+    U = bumps(om, [4])
+    Ud = to_dev(mm.state(U))
+    cfg = pa.solve_cfg(weight_cut=0.0, use_graph=True, **PARITY)
+    for T in (3600.0, 1200.0, 3600.0, 600.0):
+        avg = pa.Avg(8, T)
+        out, st = lo.phase_avg_rhs(avg, Ud, cfg)
+        assert st["graph"] == 1 and st["graph_captured"] == 1
+        out, st = lo.phase_avg_rhs(avg, Ud, cfg)
+        assert st["graph"] == 1 and st["graph_captured"] == 0
+        ref = oo.phase_avg_rhs(lb, *onodes(avg), U[0], tol=1e-13, rtol=1e-14)
+        check_parity(oo, mm.back(out.cpu().numpy())[0], ref, TOL, what=T)
+        del avg
+        gc.collect()
+    # the operators moved to a new device buffer: the graph is captured
+    # again (a replay would read the old buffer, which the caller may free)
+    avg = pa.Avg(8, 3600.0)
+    first = lo.phase_avg_rhs(avg, Ud, cfg)[0].cpu().numpy()
+    assert lo.phase_avg_rhs(avg, Ud, cfg)[1]["graph_captured"] == 0
+    lo.rebind()
+    again, st = lo.phase_avg_rhs(avg, Ud, cfg)
+    assert st["graph"] == 1 and st["graph_captured"] == 1
+    assert np.array_equal(again.cpu().numpy(), first)
 
 
 CHEB = dict(solver=1)
@@ -307,7 +402,7 @@ def test_gpu_chebyshev_check_failure_falls_back(maxit):
     assert ei.value.code == 4
     ok, st = lo.swe_nonlinear(U, pa.solve_cfg(cg_rtol=1e-12, **CHEB))
     assert st["fallbacks"] == 0
-    ref, _ = lo.swe_nonlinear(U, pa.solve_cfg(cg_rtol=1e-12))
+    ref, _ = lo.swe_nonlinear(U, pa.solve_cfg(cg_rtol=1e-12, solver=0))
     assert np.abs(ok.cpu().numpy() - ref.cpu().numpy()).max() <= 1e-9 * np.abs(ref.cpu().numpy()).max()
 
 
