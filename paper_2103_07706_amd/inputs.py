@@ -118,6 +118,34 @@ def balanced_zonal_state(verts, cell_verts, edge_verts, u0: float = 20.0,
     return np.concatenate([u, eta])
 
 
+def williamson5_bottom(verts, cell_verts, b0: float = 2000.0, r0: float = math.pi / 9.0,
+                       lat_c: float = math.pi / 6.0, lon_c: float = -math.pi / 2.0):
+    """The isolated mountain of the paper's test case (Sec. 3): a cone of
+    height b0 over the radius r0 in (latitude, longitude), centred at
+    (lat_c, lon_c), at the radially projected cell centroids."""
+    verts = np.asarray(verts, dtype=np.float64)
+    c = verts[np.asarray(cell_verts)].mean(axis=1)
+    c /= np.linalg.norm(c, axis=1, keepdims=True)
+    lat = np.arcsin(np.clip(c[:, 2], -1.0, 1.0))
+    lon = np.arctan2(c[:, 1], c[:, 0])
+    r = np.sqrt(np.minimum(r0 * r0, (lat - lat_c) ** 2 + (lon - lon_c) ** 2))
+    return b0 * (1.0 - r / r0)
+
+
+def williamson5_state(verts, cell_verts, edge_verts, phys: Physics = None, u0: float = 20.0):
+    """Initial state of the paper's test case (Sec. 3, flow over a mountain):
+    the zonal flow u = (u0/R)(-y, x, 0) and the free surface in geostrophic
+    balance with it, H + eta = H - (R Omega u0 + u0^2/2) z^2 / (g R^2), the
+    bottom (williamson5_bottom) left out of eta (the layer depth is
+    H + eta - b).  Physics: R = 6.37122e6 m, Omega = 7.292e-5 1/s, g = 9.8
+    m/s^2, H = 5960 m (TC5_PHYSICS)."""
+    return balanced_zonal_state(verts, cell_verts, edge_verts, u0=u0,
+                                phys=TC5_PHYSICS if phys is None else phys)
+
+
+TC5_PHYSICS = Physics(g=9.8, H=5960.0)
+
+
 @dataclass
 class Workload:
     """One synthetic workload: mesh level, members, bumps, averaging."""

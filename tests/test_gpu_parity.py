@@ -283,7 +283,7 @@ def test_gpu_launch_shapes_belong_to_operators():
     import threading
     from paper_2103_07706_amd import pa
     from gpu_common import _ctx
-    om, oo, lm, lo, mm, lb = pair(3)
+    om, oo, lm, lo, mm, lb = pair(4)  # 7680 rows: one and eight rows a thread differ in grid
     A = pa.Ops(_ctx(), lm)
     B = pa.Ops(_ctx(), lm)
     for o in (A, B):
@@ -333,16 +333,19 @@ def test_gpu_graph_cache_follows_object_contents():
     rebound operators that happen to reuse a freed object's address: each
     result equals the oracle for its own nodes."""
     import gc
+
+    import torch
     from paper_2103_07706_amd import pa
     om, oo, lm, lo, mm, lb = pair(3)
     U = bumps(om, [4])
     Ud = to_dev(mm.state(U))
     cfg = pa.solve_cfg(weight_cut=0.0, use_graph=True, **PARITY)
+    out = torch.empty_like(Ud)
     for T in (3600.0, 1200.0, 3600.0, 600.0):
         avg = pa.Avg(8, T)
-        out, st = lo.phase_avg_rhs(avg, Ud, cfg)
+        _, st = lo.phase_avg_rhs(avg, Ud, cfg, out=out)
         assert st["graph"] == 1 and st["graph_captured"] == 1
-        out, st = lo.phase_avg_rhs(avg, Ud, cfg)
+        _, st = lo.phase_avg_rhs(avg, Ud, cfg, out=out)
         assert st["graph"] == 1 and st["graph_captured"] == 0
         ref = oo.phase_avg_rhs(lb, *onodes(avg), U[0], tol=1e-13, rtol=1e-14)
         check_parity(oo, mm.back(out.cpu().numpy())[0], ref, TOL, what=T)
@@ -351,10 +354,10 @@ def test_gpu_graph_cache_follows_object_contents():
     # the operators moved to a new device buffer: the graph is captured
     # again (a replay would read the old buffer, which the caller may free)
     avg = pa.Avg(8, 3600.0)
-    first = lo.phase_avg_rhs(avg, Ud, cfg)[0].cpu().numpy()
-    assert lo.phase_avg_rhs(avg, Ud, cfg)[1]["graph_captured"] == 0
+    first = lo.phase_avg_rhs(avg, Ud, cfg, out=out)[0].cpu().numpy()
+    assert lo.phase_avg_rhs(avg, Ud, cfg, out=out)[1]["graph_captured"] == 0
     lo.rebind()
-    again, st = lo.phase_avg_rhs(avg, Ud, cfg)
+    again, st = lo.phase_avg_rhs(avg, Ud, cfg, out=out)
     assert st["graph"] == 1 and st["graph_captured"] == 1
     assert np.array_equal(again.cpu().numpy(), first)
 

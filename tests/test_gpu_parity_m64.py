@@ -85,7 +85,7 @@ def test_gpu_m64_batch_parity():
         got = [g for o in outs for g in o.cpu().numpy()]
         for (oo, mm, ref), g in zip(refs, got):
             check_parity(oo, mm.back(g), ref, 1e-12, what=("batch", rep))
-        assert all(s["terms"] == M for s in st)
+        assert [s["terms"] for s in st] == [M * m for _, m in items]
 
 
 def test_gpu_m64_metric_fp32_refined_stats():

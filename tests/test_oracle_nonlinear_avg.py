@@ -78,6 +78,30 @@ def test_depth_flux_constant_depth(oracle_mesh, oracle_ops):
     assert np.abs(N[m.ne:] - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
+def test_depth_flux_over_bottom_topography(oracle_mesh):
+    """The depth tendency is -div(u (eta - b)) (Sec. 2.1): with the
+    perturbation depth eta - b = c constant over the paper's mountain (Sec. 3)
+    it is exactly -c (D u) / |c| whatever eta and b are on their own; the
+    velocity part does not see b.  Dropping or flipping b fails this."""
+    m = oracle_mesh(3)
+    b = inputs.williamson5_bottom(m.verts, m.cell_verts)
+    assert b.max() > 1000.0
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal(m.ne) * 1e6
+    c = -250.0
+    ob = oracle.Ops(m, H=5960.0, g=9.8, b=b)
+    o0 = oracle.Ops(m, H=5960.0, g=9.8)
+    U = np.concatenate([u, b + c])
+    N = ob.nonlinear(U)
+    _, area = _mass_matrix(ob)
+    ref = -c * _D(m, u) / area
+    assert np.abs(N[m.ne:] - ref).max() <= 1e-13 * np.abs(ref).max()
+    N0 = o0.nonlinear(U)
+    assert np.array_equal(N[:m.ne], N0[:m.ne])
+    # and the flat-bottom operators see eta itself as the depth perturbation
+    assert np.abs(N0[m.ne:] - ref).max() > 1e-3 * np.abs(ref).max()
+
+
 def test_vorticity_terms_vanish_against_u(oracle_mesh, oracle_ops):
     """Testing the velocity equation with w = u: (u^perp . u) = 0 kills the
     volume and facet vorticity terms whatever the upwind value, and the
