@@ -236,6 +236,24 @@ int pa_phase_avg_rhs(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg,
                      void *ws_dev, size_t ws_bytes, const pa_solve_cfg *cfg,
                      pa_stats *stats);
 
+/* pa_phase_avg_rhs without a workspace argument, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid allocation).  The workspace is a static device array
+ * of 256 MiB inside the library (each GPU the library runs on holds its own
+ * copy until the process ends; its address is looked up once per device);
+ * the call allocates no device memory and captures no graph (cfg->use_graph
+ * is ignored: instantiating a graph allocates).  A problem whose workspace
+ * (pa_workspace_size, for cfg and for the FP64 CG repeat) exceeds 256 MiB
+ * fails with PA_ENOMEM before anything is launched: one member at level 4
+ * with M = 64 fits, one member at level 5 with M = 32 in FP64 fits, level 6
+ * does not.  The scratch keeps the last call's contents; every call clears
+ * what must start at zero.  Calls on one GPU share the scratch, so calls that
+ * overlap on one GPU (two threads, two streams) race: serialise them.
+ * Arguments, results and errors otherwise as pa_phase_avg_rhs. */
+int pa_phase_avg_rhs_noalloc(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg,
+                             int members, const double *U_dev, double *Nbar_dev,
+                             const pa_solve_cfg *cfg, pa_stats *stats);
+
 /* One step of the averaged Lawson RK4 scheme (Sec. 2.3, four stages), in
  * place on 'members' states. */
 int pa_step(pa_ctx *ctx, const pa_ops *ops, const pa_avg *avg, double dt,

@@ -157,6 +157,8 @@ EXPORTS = {
     "pa_diagnostics": (ctypes.c_int, [_V, _V, ctypes.c_int, _V, _V, _SZ, _D]),
     "pa_get_launch_tune": (ctypes.c_int, [ctypes.POINTER(LaunchTune)]),
     "pa_set_launch_tune": (ctypes.c_int, [ctypes.POINTER(LaunchTune)]),
+    "pa_phase_avg_rhs_noalloc": (ctypes.c_int, [_V, _V, _V, ctypes.c_int, _V, _V,
+                                                ctypes.POINTER(SolveCfg), ctypes.POINTER(Stats)]),
     "pa_ops_set_tune": (ctypes.c_int, [_V, ctypes.POINTER(LaunchTune)]),
     "pa_ops_get_tune": (ctypes.c_int, [_V, ctypes.POINTER(LaunchTune), ctypes.POINTER(ctypes.c_int)]),
     "pa_autotune": (ctypes.c_int, [_V, _V, _V, ctypes.c_int, _V, _V, _V, _SZ,
@@ -440,6 +442,16 @@ class Ops:
         st = Stats()
         _check(lib().pa_phase_avg_rhs(self.ctx._h, self._h, avg._h, members, _ptr(U), _ptr(out),
                                       ws, nb, ctypes.byref(cfg), ctypes.byref(st)))
+        return out, st.as_dict()
+
+    def phase_avg_rhs_noalloc(self, avg: Avg, U, cfg=None, out=None):
+        """pa_phase_avg_rhs_noalloc: the library's static device scratch
+        instead of a workspace (no device allocation by the call)."""
+        cfg = cfg or solve_cfg()
+        out = U.new_empty(U.shape) if out is None else out
+        st = Stats()
+        _check(lib().pa_phase_avg_rhs_noalloc(self.ctx._h, self._h, avg._h, U.shape[0], _ptr(U),
+                                              _ptr(out), ctypes.byref(cfg), ctypes.byref(st)))
         return out, st.as_dict()
 
     def step(self, avg: Avg, dt: float, U, cfg=None):
