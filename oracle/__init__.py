@@ -17,7 +17,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ["om_mesh.c", "om_ops.c", "om_cheb.c", "om_nonlin.c", "om_avg.c"]
+_SOURCES = ["om_mesh.c", "om_ops.c", "om_cheb.c", "om_rexi.c", "om_nonlin.c", "om_avg.c"]
 
 
 def build(force: bool = True) -> str:
@@ -61,6 +61,10 @@ def _load():
             "om_expL": (ctypes.c_int, [_V, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_double, _D, _D]),
             "om_nonlinear": (ctypes.c_int, [_V, _D, _D, ctypes.c_double]),
+            "om_rexi_coeffs": (None, [ctypes.c_double, ctypes.c_int, ctypes.c_double, _D, _D]),
+            "om_rexi_expL": (ctypes.c_int, [_V, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                            ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                            _D, _D]),
             "om_avg_nodes": (None, [ctypes.c_int, ctypes.c_double, _D, _D]),
             "om_phase_avg_rhs": (ctypes.c_int, [_V, ctypes.c_double, ctypes.c_int, _D, _D,
                                                 ctypes.c_double, ctypes.c_double, ctypes.c_int,
@@ -180,6 +184,17 @@ class Ops:
             raise OracleError("exponential failed")
         return out, K
 
+    def rexi_expL(self, lambda_bar, t, U, N, eta0, gm_rtol=1e-13, rtol=1e-14):
+        """exp(t L) U by the rational (REXI) sum with N nodes on the ellipse
+        of parameter eta0; returns (result, largest GMRES iteration count)."""
+        U = _f64(U)
+        out = np.zeros_like(U)
+        it = _load().om_rexi_expL(self._h, lambda_bar, t, N, eta0, gm_rtol, rtol, _dp(U),
+                                  _dp(out))
+        if it < 0:
+            raise OracleError("rational exponential failed")
+        return out, it
+
     def nonlinear(self, U, rtol=1e-14):
         U = _f64(U)
         out = np.zeros_like(U)
@@ -236,6 +251,15 @@ def cheb_truncate(a, tol: float) -> int:
     buf = np.zeros(2 * len(a))
     buf[0::2], buf[1::2] = a.real, a.imag
     return _load().om_cheb_truncate(_dp(buf), len(a) - 1, tol)
+
+
+def rexi_coeffs(theta: float, N: int, eta0: float):
+    """Nodes X_j and coefficients c_j (complex arrays) of the rational
+    approximation r(x) = sum_j c_j / (X_j - x) of exp(i theta x)."""
+    X = np.zeros(2 * N)
+    c = np.zeros(2 * N)
+    _load().om_rexi_coeffs(theta, N, eta0, _dp(X), _dp(c))
+    return X[0::2] + 1j * X[1::2], c[0::2] + 1j * c[1::2]
 
 
 def avg_nodes(M: int, T: float):

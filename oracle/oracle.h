@@ -18,10 +18,11 @@
  *
  * Parity status per function (what pins it is in tests/test_oracle_*.py):
  *   mesh, operators, mass solve, Chebyshev coefficients and truncation,
- *   exponential, nonlinearity, nodes/weights, averaged RHS, RK4 step:
- *   all pinned.  The velocity upwind direction inside N is a reading of the
- *   paper (its printed inequality selects the downwind side) that no pin
- *   distinguishes from the alternative: parity unpinned for that choice.
+ *   exponential, rational exponential, nonlinearity, nodes/weights, averaged
+ *   RHS, RK4 step, diagnostics: all pinned.  The velocity upwind direction
+ *   inside N is a reading of the paper (its printed inequality selects the
+ *   downwind side) that no pin distinguishes from the alternative: parity
+ *   unpinned for that choice.
  */
 #ifndef ORACLE_H
 #define ORACLE_H
@@ -79,6 +80,17 @@ int om_cheb_truncate(const double *a, int npts, double tol);
  * Lbar = lambda_bar*|t|.  Returns the degree K used (>=0), -1 on failure. */
 int om_expL(const om_ops *o, double lambda_bar, double t, double tol,
             double rtol, const double *U, double *out);
+
+/* ---- rational exponential (REXI, Sec. 2.4 and Sec. 4) ------------------ */
+/* Nodes X[N] and coefficients c[N] (complex, interleaved re/im) of the
+ * trapezoidal rule of the Cauchy integral of exp(i theta X) over the
+ * ellipse X = cosh(eta0 + i phi): r(x) = sum_j c_j / (X_j - x). */
+void om_rexi_coeffs(double theta, int N, double eta0, double *X, double *c);
+/* out = Re sum_j c_j (X_j I + (i / lambda_bar) L)^{-1} U with theta =
+ * lambda_bar t, each shifted system solved by GMRES to gm_rtol (mass solves
+ * to rtol).  Returns the largest GMRES iteration count, -1 on failure. */
+int om_rexi_expL(const om_ops *o, double lambda_bar, double t, int N, double eta0,
+                 double gm_rtol, double rtol, const double *U, double *out);
 
 /* ---- nonlinearity (Sec. 2.5, discrete N) ------------------------------- */
 int om_nonlinear(const om_ops *o, const double *U, double *out, double rtol);
