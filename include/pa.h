@@ -192,7 +192,10 @@ typedef struct {
   int32_t terms;         /* averaging terms evaluated */
   int32_t refinements;   /* FP64 refinement sweeps (PA_FP32_REFINED) */
   int32_t guard_trips;
-  double resid_max;      /* largest final relative residual of a solve */
+  double resid_max;      /* largest final relative residual of a Chebyshev
+                            mass solve (its true residual, checked); CG
+                            solves stop on their own recursive residual and
+                            leave it 0 */
   double device_ms;      /* device time of the call */
   int32_t graph;         /* 1 if the call ran as a graph replay or capture */
   int32_t budget;        /* CG iterations per solve launched (0: polled) */
