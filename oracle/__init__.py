@@ -72,6 +72,14 @@ def _load():
             "om_step": (ctypes.c_int, [_V, ctypes.c_double, ctypes.c_int, _D, _D,
                                        ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                        ctypes.c_int, _D]),
+            "om_rexi_phase_avg_rhs": (ctypes.c_int, [_V, ctypes.c_double, ctypes.c_int, _D, _D,
+                                                     ctypes.c_int, ctypes.c_double,
+                                                     ctypes.c_double, ctypes.c_double,
+                                                     ctypes.c_int, _D, _D]),
+            "om_rexi_step": (ctypes.c_int, [_V, ctypes.c_double, ctypes.c_int, _D, _D,
+                                            ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                            ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                            _D]),
             "om_diagnostics": (None, [_V, _D, _D]),
         }
         for name, (res, args) in sig.items():
@@ -218,6 +226,27 @@ class Ops:
                              _dp(U))
         if st < 0:
             raise OracleError("step failed")
+        return U
+
+    def rexi_phase_avg_rhs(self, lambda_bar, s, w, U, N, eta0, gm_rtol=1e-13, rtol=1e-14,
+                           which=0):
+        """Nbar with every exponential the rational (REXI) sum of rexi_expL."""
+        U, s, w = _f64(U), _f64(s), _f64(w)
+        out = np.zeros_like(U)
+        st = _load().om_rexi_phase_avg_rhs(self._h, lambda_bar, len(s), _dp(s), _dp(w), N, eta0,
+                                           gm_rtol, rtol, which, _dp(U), _dp(out))
+        if st < 0:
+            raise OracleError("rational averaged RHS failed")
+        return out
+
+    def rexi_step(self, lambda_bar, s, w, dt, U, N, eta0, gm_rtol=1e-13, rtol=1e-14, which=0):
+        """One averaged RK4 step with every exponential the REXI sum."""
+        U = _f64(U).copy()
+        s, w = _f64(s), _f64(w)
+        st = _load().om_rexi_step(self._h, lambda_bar, len(s), _dp(s), _dp(w), dt, N, eta0,
+                                  gm_rtol, rtol, which, _dp(U))
+        if st < 0:
+            raise OracleError("rational step failed")
         return U
 
     def diagnostics(self, U):

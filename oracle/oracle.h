@@ -105,11 +105,22 @@ int om_phase_avg_rhs(const om_ops *o, double lambda_bar, int nnodes,
                      const double *s, const double *w, double tol,
                      double rtol, int which_n, const double *U, double *out);
 
+/* The same with every exponential the rational (REXI) sum of om_rexi_expL
+ * (N nodes, ellipse parameter eta0, GMRES to gm_rtol). */
+int om_rexi_phase_avg_rhs(const om_ops *o, double lambda_bar, int nnodes,
+                          const double *s, const double *w, int N, double eta0,
+                          double gm_rtol, double rtol, int which_n,
+                          const double *U, double *out);
+
 /* ---- averaged Lawson RK4 step (Sec. 2.3) ------------------------------- */
 /* which_n as for om_phase_avg_rhs. */
 int om_step(const om_ops *o, double lambda_bar, int nnodes, const double *s,
             const double *w, double dt, double tol, double rtol, int which_n,
             double *U);
+/* The same with every exponential (stages and averages) the REXI sum. */
+int om_rexi_step(const om_ops *o, double lambda_bar, int nnodes, const double *s,
+                 const double *w, double dt, int N, double eta0, double gm_rtol,
+                 double rtol, int which_n, double *U);
 
 /* ---- diagnostics -------------------------------------------------------- */
 /* out[0] mass, out[1] linear energy, out[2] nonlinear energy,

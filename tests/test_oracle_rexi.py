@@ -101,3 +101,40 @@ def test_rexi_matches_chebyshev_and_invariants(oracle_mesh, oracle_ops):
     A, _ = o.rexi_expL(lb, 0.5 * t, U, 36, 0.79)
     B, _ = o.rexi_expL(lb, 0.5 * t, A, 36, 0.79)
     assert o.wnorm(B - E) <= 1e-11 * o.wnorm(U)
+
+
+def _level(oracle_mesh, oracle_ops, level):
+    m = oracle_mesh(level)
+    o = oracle_ops(level)
+    lb = oracle.lambda_bar(o, iters=200)
+    U = inputs.gaussian_bumps_state(m.verts, m.cell_verts, m.edge_verts, 10, 0)
+    return m, o, lb, U
+
+
+def test_rexi_average_matches_chebyshev_average(oracle_mesh, oracle_ops):
+    """Nbar with REXI exponentials against Nbar with Chebyshev exponentials
+    (the same averaged operator, Sec. 2.2, by two constructions of exp(sL))."""
+    m, o, lb, U = _level(oracle_mesh, oracle_ops, 2)
+    s, w = oracle.avg_nodes(8, 3600.0)
+    assert lb * 1800.0 <= 5.41
+    R = o.rexi_phase_avg_rhs(lb, s, w, U, 36, 0.79, gm_rtol=1e-14, rtol=1e-15)
+    C = o.phase_avg_rhs(lb, s, w, U, tol=1e-14, rtol=1e-15)
+    assert o.wnorm(R - C) <= 1e-10 * o.wnorm(C), o.wnorm(R - C) / o.wnorm(C)
+    # with the identity in place of N the average is U itself (sum w = 1 and
+    # exp(-sL) exp(sL) = I up to the rational approximation); level 1
+    m, o, lb, U = _level(oracle_mesh, oracle_ops, 1)
+    I = o.rexi_phase_avg_rhs(lb, s, w, U, 36, 0.79, gm_rtol=1e-14, rtol=1e-15, which=1)
+    assert o.wnorm(I - U) <= 1e-11 * o.wnorm(U)
+    # with L in place of N: L U (the group property and sum w = 1)
+    LU = o.apply_L(U, rtol=1e-15)
+    A = o.rexi_phase_avg_rhs(lb, s, w, U, 36, 0.79, gm_rtol=1e-14, rtol=1e-15, which=2)
+    assert o.wnorm(A - LU) <= 1e-10 * o.wnorm(LU)
+
+
+def test_rexi_step_matches_chebyshev_step(oracle_mesh, oracle_ops):
+    m, o, lb, U = _level(oracle_mesh, oracle_ops, 1)
+    s, w = oracle.avg_nodes(8, 3600.0)
+    R = o.rexi_step(lb, s, w, 1800.0, U, 36, 0.79, gm_rtol=1e-14, rtol=1e-15)
+    C = o.step(lb, s, w, 1800.0, U, tol=1e-14, rtol=1e-15)
+    assert o.wnorm(R - C) <= 1e-10 * o.wnorm(U), o.wnorm(R - C) / o.wnorm(U)
+    assert o.wnorm(R - U) > 1e-3 * o.wnorm(U)  # the step moved the state
