@@ -170,7 +170,47 @@ typedef struct {
                           The final FP64 residual check and its CG repeat
                           are as for Jacobi.  CG and FP32-refined solves use
                           Jacobi. */
+  int32_t exponential; /* PA_EXP_CHEBYSHEV: the Chebyshev polynomial of
+                          Sec. 2.4 (above).  PA_EXP_REXI: the rational sum
+                          that Sec. 2.4 and Sec. 4 name as the parallel
+                          alternative, every exponential of the call (those
+                          of the average, the stages of pa_step) as
+                            exp(t L) U ~ Re sum_{j<N} c_j (X_j + (i/lb) L)^-1 U,
+                            X_j = cosh(eta0 + i phi_j), phi_j = 2 pi (j+1/2)/N,
+                            c_j = exp(i theta X_j) sinh(eta0 + i phi_j) / N,
+                          theta = lb t, lb = lambda_bar: the N-point
+                          trapezoidal rule of the Cauchy integral of
+                          exp(i theta x) over the ellipse with foci -1, 1
+                          through X_0 (Trefethen and Weideman, SIAM Review
+                          56, 2014).  The nodes pair up as X and -conj(X)
+                          with conjugate terms, so N/2 complex solves carry
+                          the sum.  The poles do not depend on t: the M
+                          forward exponentials of the average share the N/2
+                          solves of U, and the weighted backward sum is N/2
+                          solves of complex combinations of the N(E_m).
+                          Each shifted system is solved through its velocity
+                          Schur complement
+                            (X M_u - (i/lb) F - gH/(lb^2 X) D' A^-1 D) y_u
+                              = M_u U_u - i g/(lb X) D' U_eta,
+                            y_eta = (U_eta + i H/lb A^-1 D y_u) / X
+                          (A the cell areas), by Jacobi-preconditioned
+                          BiCGStab with the true residual checked against
+                          cg_rtol (a failed check restarts from the iterate,
+                          maxit iterations at most).  precision, solver,
+                          precond, backward and use_graph then concern the
+                          mass solves of N only, and calls do not capture
+                          graphs (convergence is polled). */
+  int32_t rexi_nodes;  /* PA_EXP_REXI: N, a multiple of 4 in [8, 256], with
+                          rexi_eta0 in (0, 3]; 0: the library takes the pair
+                          of smallest N / eta0 (the solves' iteration count
+                          grows like 1/eta0) whose rational function is
+                          within cheb_tol / 2 of exp(i theta x) on [-1, 1] at
+                          the largest theta of the call and whose solve
+                          error, sum_j |c_j| / dist(X_j, [-1, 1]) cg_rtol,
+                          stays below cheb_tol / 2 */
+  double rexi_eta0;
 } pa_solve_cfg;
+enum { PA_EXP_CHEBYSHEV = 0, PA_EXP_REXI = 1 };
 enum { PA_PRECOND_JACOBI = 0, PA_PRECOND_LEARNED = 1 };
 enum { PA_SOLVER_CG = 0, PA_SOLVER_CHEBYSHEV = 1 };
 /* Defaults: the fastest FP64 form measured on MI355X at the throughput
@@ -209,11 +249,25 @@ typedef struct {
                             depends on changed (pointers, sizes, settings,
                             launch shape, operator contents or buffers,
                             averaging nodes) */
+  int32_t rexi_nodes;    /* PA_EXP_REXI: N of the call's rational sums */
+  int32_t rexi_solves;   /* PA_EXP_REXI: batched shifted solves issued */
+  int32_t rexi_iters;    /* BiCGStab iterations summed over those solves
+                            (the batch's count each) */
+  int32_t rexi_iters_max;/* largest iteration count of one column */
+  int32_t rexi_restarts; /* restarts after a failed true-residual check */
+  int32_t rexi_pad;
+  double rexi_eta0;      /* ellipse parameter of the call's rational sums */
+  double rexi_resid_max; /* largest final true relative residual of a
+                            shifted solve */
 } pa_stats;
 
 /* Device workspace bytes for calls on 'batch' states (expL_apply,
  * swe_nonlinear: batch = B; phase_avg_rhs, step: batch = members, avg given).
- * Pass avg = NULL for calls that do not average. */
+ * Pass avg = NULL for calls that do not average.  With PA_EXP_REXI the
+ * node count of the rational sum, and so the workspace, grows with
+ * lambda_bar |t|: for expL_apply the size covers the largest node count
+ * (256) unless cfg->rexi_nodes fixes it, and for pa_step it covers dt up to
+ * max |s_m| (a call that needs more fails with PA_ENOMEM). */
 int pa_workspace_size(const pa_ops *ops, const pa_avg *avg, int batch,
                       const pa_solve_cfg *cfg, size_t *bytes);
 

@@ -244,6 +244,8 @@ void run_once(pa_ctx *ctx, pa_batch *b, const double *const *U, double *const *N
 // with polling; a failed Chebyshev check repeats with FP64 CG.
 void run_batch(pa_ctx *ctx, pa_batch *b, const double *const *U, double *const *Nbar, void *ws,
                size_t ws_bytes, const pa_solve_cfg &c0, pa_stats *stats) {
+  if (c0.exponential != PA_EXP_CHEBYSHEV)
+    throw pa::Error(PA_ENOTSUP, "batches run the Chebyshev exponential only");
   size_t total = 0;
   const std::vector<size_t> off = item_offsets(b, c0, &total);
   if (ws_bytes < total) throw pa::Error(PA_ENOMEM, "workspace too small for the batch");

@@ -163,6 +163,7 @@ size_t layout(pa_ops *o, char *base) {
   place(off, o->ell_col, &d.ell_col, base);
   place(off, o->mass, &d.mass, base);
   place(off, o->cor, &d.cor, base);
+  place(off, o->graddiv, &d.graddiv, base);
   place(off, o->mass32, &d.mass32, base);
   place(off, o->dinv, &d.dinv, base);
   place(off, o->dinv32, &d.dinv32, base);
@@ -242,6 +243,7 @@ int pa_ops_bind(pa_ctx *ctx, pa_ops *ops, void *dev_buf) {
     up(s, d.ell_col, ops->ell_col);
     up(s, d.mass, ops->mass);
     up(s, d.cor, ops->cor);
+    up(s, d.graddiv, ops->graddiv);
     up(s, d.mass32, ops->mass32);
     up(s, d.dinv, ops->dinv);
     up(s, d.dinv32, ops->dinv32);
@@ -338,6 +340,9 @@ void pa_solve_cfg_default(pa_solve_cfg *cfg) {
   cfg->use_graph = 1;
   cfg->solver = PA_SOLVER_CHEBYSHEV;
   cfg->precond = PA_PRECOND_JACOBI;
+  cfg->exponential = PA_EXP_CHEBYSHEV;
+  cfg->rexi_nodes = 0;
+  cfg->rexi_eta0 = 0.0;
 }
 
 }  // extern "C"
@@ -360,7 +365,14 @@ namespace pa {
 size_t workspace_bytes(const pa_ops *ops, const pa_avg *avg, int batch, const pa_solve_cfg &c) {
   size_t best = 0;
   {
-    pa::Engine e(nullptr, ops, c, nullptr, 0);
+    // the rational exponential's node count follows the times of the call:
+    // without a given node set, size for the largest (256 nodes)
+    pa_solve_cfg ce = c;
+    if (ce.exponential == PA_EXP_REXI && ce.rexi_nodes == 0) {
+      ce.rexi_nodes = 256;
+      ce.rexi_eta0 = 1.0;
+    }
+    pa::Engine e(nullptr, ops, ce, nullptr, 0);
     std::vector<double> t(batch, 1.0);
     if (ops->lambda_bar > 0) e.expL_apply(batch, t.data(), nullptr, nullptr);
     best = std::max(best, e.used());
@@ -386,11 +398,14 @@ size_t workspace_bytes(const pa_ops *ops, const pa_avg *avg, int batch, const pa
     e1.phase_avg_rhs(avg, batch, nullptr, nullptr);
     best = std::max(best, e1.used());
     // the step's exponentials use the largest time step the caller may ask
-    // for; size it by phase_avg_rhs plus stage buffers of a 2T step
+    // for; size it by phase_avg_rhs plus stage buffers of a 2T step (with
+    // the rational exponential the node count grows with the step: sized for
+    // steps up to the averaging half-width max |s_m|)
     double T = 0;
     for (double s : avg->s) T = std::max(T, 2.0 * std::fabs(s));
+    const double dt = c.exponential == PA_EXP_REXI ? 0.5 * T : T;
     pa::Engine e2(nullptr, ops, c, nullptr, 0);
-    e2.step(avg, std::max(T, 1.0), batch, nullptr);
+    e2.step(avg, std::max(dt, 1.0), batch, nullptr);
     best = std::max(best, e2.used());
   }
   return best + 4096;

@@ -42,6 +42,8 @@ Engine::Engine(pa_ctx *ctx, const pa_ops *ops, const pa_solve_cfg &cfg, void *ws
   if (cfg_.solver != PA_SOLVER_CG && cfg_.solver != PA_SOLVER_CHEBYSHEV)
     throw Error(PA_EINVAL, "unknown solver");
   if (mixed() && !(cfg_.inner_rtol > 0 && cfg_.inner_rtol < 1)) throw Error(PA_EINVAL, "inner_rtol in (0, 1)");
+  if (cfg_.exponential != PA_EXP_CHEBYSHEV && cfg_.exponential != PA_EXP_REXI)
+    throw Error(PA_EINVAL, "unknown exponential");
   if (cheb() || mixed()) plan_cheb();
 }
 
@@ -1057,6 +1059,7 @@ void Engine::expL_apply(int B, const double *t, const double *Uin, double *Uout)
   TuneScope tune_scope(tune_);
   if (B <= 0) throw Error(PA_EINVAL, "B must be positive");
   if (!(ops_->lambda_bar > 0)) throw Error(PA_EINVAL, "lambda_bar is not set");
+  if (cfg_.exponential == PA_EXP_REXI) return rexi_expL_apply(B, t, Uin, Uout);
   const int Bs = pad_cols(B);
   plan_common(Bs);
   ExpBufs eb;
@@ -1294,6 +1297,7 @@ bool Engine::sync_free() const { return current_budget() > 0 || cheb() || mixed(
 
 void Engine::phase_avg_rhs(const pa_avg *avg, int members, const double *U, double *Nbar) {
   TuneScope tune_scope(tune_);
+  if (cfg_.exponential == PA_EXP_REXI) return rexi_phase_avg_rhs(avg, members, U, Nbar);
   NbarCall c;
   nbar_plan(c, avg, members, U, Nbar);
   if (ar_.sizing()) return;
@@ -1372,6 +1376,7 @@ void Engine::run_graph(const GraphKey &key, const std::function<void()> &body) {
 // exponentials are linear, so the printed stage-4 sum regroups this way).
 void Engine::step(const pa_avg *avg, double dt, int members, double *U) {
   TuneScope tune_scope(tune_);
+  if (cfg_.exponential == PA_EXP_REXI) return rexi_step(avg, dt, members, U);
   if (members <= 0) throw Error(PA_EINVAL, "members must be positive");
   NbarBufs nb;
   plan_nbar(nb, avg, members);

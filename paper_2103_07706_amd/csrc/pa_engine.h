@@ -2,10 +2,12 @@
 // sequences of kernels for the exponential, the nonlinearity, the averaged
 // right-hand side and the RK4 step.
 #pragma once
+#include <complex>
 #include <functional>
 #include <vector>
 
 #include "pa_kernels.h"
+#include "pa_rexi.h"
 
 namespace pa {
 
@@ -90,6 +92,12 @@ class Engine {
   void diagnostics(int B, const double *U, double *out_host);
 
   size_t used() const { return ar_.used(); }
+
+  // the same calls with every exponential the rational (REXI) sum
+  // (cfg.exponential == PA_EXP_REXI; pa_rexi.cpp)
+  void rexi_expL_apply(int B, const double *t, const double *Uin, double *Uout);
+  void rexi_phase_avg_rhs(const pa_avg *avg, int members, const double *U, double *Nbar);
+  void rexi_step(const pa_avg *avg, double dt, int members, double *U);
 
   // allow the learned CG iteration budget (no host polling) for this call
   // use: launch the learned budget without polling; learn: record the
@@ -218,6 +226,45 @@ class Engine {
   };
   void plan_exp(ExpBufs &eb, int B, const double *t);
   void run_exp(ExpBufs &eb, Blk in, Blk out);
+
+  // rational exponential: one batch of shifted solves (P poles x members
+  // complex columns) and its device buffers
+  struct RexiSys {
+    int N = 0, P = 0, members = 0, ncols = 0, Bc = 0, nwg = 0;
+    double eta0 = 0.0;
+    std::vector<std::complex<double>> X, W;  // poles, trapezoidal weights
+    std::vector<double> hcoef;               // a, c, q, h, xinv per column
+    double2 *coef = nullptr, *rho = nullptr, *alpha = nullptr, *omega = nullptr, *beta = nullptr;
+    double *bb = nullptr, *ff = nullptr, *tau2 = nullptr, *res2 = nullptr, *part = nullptr;
+    int *active = nullptr, *iters = nullptr, *fresh = nullptr, *restarts = nullptr, *fail = nullptr;
+    double2 *Y = nullptr, *r = nullptr, *p[2] = {nullptr, nullptr}, *v[2] = {nullptr, nullptr};
+    double2 *s = nullptr, *t = nullptr;
+  };
+  struct RexiExp {
+    int B = 0, Bs = 0;
+    std::vector<double2> hC;
+    double2 *C = nullptr;
+  };
+  struct RexiNbar {
+    int M = 0, G = 0, Bm = 0, BsE = 0, members = 0;
+    std::vector<double2> hCf, hCb, hCs;
+    std::vector<int> hcolK;
+    double2 *Cf = nullptr, *Cb = nullptr, *Cs = nullptr, *Z = nullptr;
+    int *colK = nullptr;
+    double *E = nullptr, *Yn = nullptr;
+  };
+  void rexi_plan(RexiSys &rs, double theta_max, int members);
+  void rexi_coefs(const RexiSys &rs, double theta, double scale, double2 *out) const;
+  void rexi_upload(RexiSys &rs);
+  void rexi_solve(RexiSys &rs, const RexiSrc &src);
+  void rexi_combine(const RexiSys &rs, const double2 *C, int Go, int Mo, bool per_member, double *out,
+                    int ostride);
+  void rexi_exp_plan(RexiExp &x, RexiSys &rs, int B, const double *t);
+  void rexi_exp_run(RexiExp &x, RexiSys &rs, Blk in, Blk out);
+  double rexi_theta_max(const pa_avg *avg) const;
+  void rexi_nbar_plan(RexiNbar &nb, RexiSys &rs, const pa_avg *avg, int members);
+  void rexi_nbar_upload(RexiNbar &nb);
+  void rexi_nbar_run(RexiNbar &nb, RexiSys &rs, Blk X, Blk out);
 
   pa_ctx *ctx_;
   const pa_ops *ops_;

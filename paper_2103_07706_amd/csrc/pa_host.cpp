@@ -247,6 +247,7 @@ void assemble_ops(pa_ops *o, const Mesh &m, const pa_phys &ph) {
   o->ell_col.assign(5 * ne, -1);
   o->mass.assign(5 * ne, 0.0);
   o->cor.assign(5 * ne, 0.0);
+  o->graddiv.assign(5 * ne, 0.0);
 
   // ELL pattern: self, then the other two edges of c0, then those of c1
   for (int e = 0; e < ne; e++) {
@@ -295,6 +296,10 @@ void assemble_ops(pa_ops *o, const Mesh &m, const pa_phys &ph) {
         double I = A / 12.0 * (sv + dot(sumv - 3.0 * p[i], sumv - 3.0 * p[j]));
         o->mass[ell_slot(ed[i], ed[j])] += s[i] * s[j] * I / (4.0 * A * A);
       }
+    // grad-div D' A^-1 D (the depth elimination of the rational form's
+    // shifted systems): s_i s_j / A for every pair of the cell's edges
+    for (int i = 0; i < 3; i++)
+      for (int j = 0; j < 3; j++) o->graddiv[ell_slot(ed[i], ed[j])] += s[i] * s[j] / A;
     // Coriolis: midpoints of the sides, weight A/3
     for (int q = 0; q < 3; q++) {
       V3 x = 0.5 * (p[(q + 1) % 3] + p[(q + 2) % 3]);

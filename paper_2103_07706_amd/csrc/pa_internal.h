@@ -109,6 +109,7 @@ struct DevOps {
   const int32_t *ell_col = nullptr;   // ne*5: self, two of c0, two of c1
   const double *mass = nullptr;       // ne*5
   const double *cor = nullptr;        // ne*5
+  const double *graddiv = nullptr;    // ne*5: D' A^-1 D on the same pattern
   const float *mass32 = nullptr;      // ne*5
   const double *dinv = nullptr;       // ne
   const float *dinv32 = nullptr;      // ne
@@ -165,7 +166,8 @@ inline bool same_cfg(const pa_solve_cfg &a, const pa_solve_cfg &b) {
   return a.precision == b.precision && a.backward == b.backward && a.maxit == b.maxit &&
          a.growth_guard == b.growth_guard && a.cg_rtol == b.cg_rtol && a.cheb_tol == b.cheb_tol &&
          a.weight_cut == b.weight_cut && a.inner_rtol == b.inner_rtol && a.use_graph == b.use_graph &&
-         a.solver == b.solver && a.precond == b.precond;
+         a.solver == b.solver && a.precond == b.precond && a.exponential == b.exponential &&
+         a.rexi_nodes == b.rexi_nodes && a.rexi_eta0 == b.rexi_eta0;
 }
 
 // Objects whose contents a captured graph bakes in (operators and their
@@ -213,6 +215,8 @@ struct pa_ctx {
   void *host_flag = nullptr;  // pinned host word for convergence polling
   // learned CG iterations per solve, per tolerance (absent: poll)
   std::map<double, int> cg_budget;
+  // iterations of the last rational-exponential solve (first poll point)
+  int rexi_pred = 0;
   // graph replay of the averaged right-hand side
   hipStream_t cap_stream = nullptr;
   hipEvent_t ev_a = nullptr, ev_b = nullptr;
@@ -243,7 +247,7 @@ struct pa_ops {
   double mass_eig_min = 0, mass_eig_max = 0;  // Ritz bounds of D^-1 M
   // host copies, in upload order
   std::vector<int32_t> ell_col, ecell, cidx, cell_edges, cedge, csgn, cnbr;
-  std::vector<double> mass, cor, dinv, area, inv_area, bottom, cgeo, nlform, tau;
+  std::vector<double> mass, cor, graddiv, dinv, area, inv_area, bottom, cgeo, nlform, tau;
   std::vector<float> mass32, dinv32;
   int hparts = 0, fused_max = 1;
   int fused_cpp = 0;  // cells per part in a set-up launch (0: no set-up launches)

@@ -1,0 +1,501 @@
+// HIP kernels of the rational (REXI) exponential of libpa for gfx950.
+//
+// The P independent shifted systems of a call (times the members) are the
+// complex columns of one block, row-major [row][Bc] of double2, so that a
+// gathered ELL neighbour row is one contiguous run of 16-byte values.  A
+// launch covers a tile of CT = min(Bc, 64) columns (blockIdx.y) and an
+// XCD-aware grid-stride range of velocity rows (as the real block kernels:
+// each XCD takes one contiguous slice of rows, so ELL neighbours meet in its
+// L2).  Every column runs its own BiCGStab (left Jacobi preconditioning,
+// Hermitian inner products, a counter-hash shadow residual); converged
+// columns freeze.  Column sums go through per-workgroup partials with plain
+// stores and a finalize kernel per reduction point (one workgroup per column,
+// fixed summation order), so results do not depend on scheduling.
+#include <hip/hip_runtime.h>
+
+#include "pa_rexi.h"
+
+namespace pa {
+
+namespace {
+constexpr int kRWG = 256;
+
+struct RLane {
+  int ct, rw, col, tile, row0, rstride, rend, lane, wave;
+};
+
+__device__ inline RLane rlane(int Bc, int nrows) {
+  RLane L;
+  L.ct = Bc < 64 ? Bc : 64;
+  L.rw = 64 / L.ct;
+  L.lane = threadIdx.x & 63;
+  L.wave = threadIdx.x >> 6;
+  L.tile = blockIdx.y;
+  L.col = L.tile * L.ct + (L.lane % L.ct);
+  const int per = gridDim.x >> 3;
+  const int xcd = blockIdx.x & 7, w = blockIdx.x >> 3;
+  const int slice = (nrows + 7) >> 3;
+  const int rpp = (kRWG / 64) * L.rw;
+  L.rend = min(nrows, (xcd + 1) * slice);
+  L.row0 = xcd * slice + w * rpp + L.wave * L.rw + L.lane / L.ct;
+  L.rstride = per * rpp;
+  return L;
+}
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ inline double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+__device__ inline double2 cdiv(double2 a, double2 b) {
+  const double d = b.x * b.x + b.y * b.y;
+  return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+__device__ inline double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+// conj(a) b
+__device__ inline double2 cdotc(double2 a, double2 b) {
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+
+// Shadow residual of BiCGStab: a counter hash (SplitMix64 finaliser) of the
+// row, the column and the seed, in [-1, 1)^2.
+__device__ inline double2 shadow(uint32_t seed, int e, int col) {
+  uint64_t z = (((uint64_t)(uint32_t)e << 32) | (uint32_t)col) + (uint64_t)(seed + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  const double sc = 1.0 / 8388608.0;  // 2^-23
+  return make_double2((double)((z >> 40) & 0xFFFFFF) * sc - 1.0, (double)((z >> 8) & 0xFFFFFF) * sc - 1.0);
+}
+
+// Per-workgroup column sums of NQ quantities into part[wg][q][Bc].
+template <int NQ>
+__device__ void rexi_partials(const RLane &L, double (&v)[NQ], double *part, int Bc) {
+  __shared__ double red[NQ][kRWG / 64][64];
+  for (int q = 0; q < NQ; q++) {
+    double s = v[q];
+    for (int off = 32; off >= L.ct; off >>= 1) s += __shfl_xor(s, off);
+    if (L.lane < L.ct) red[q][L.wave][L.lane] = s;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < NQ * L.ct; idx += kRWG) {
+    const int q = idx / L.ct, c = idx % L.ct;
+    double s = 0;
+    for (int w = 0; w < kRWG / 64; w++) s += red[q][w][c];
+    part[((size_t)blockIdx.x * NQ + q) * Bc + L.tile * L.ct + c] = s;
+  }
+}
+
+// Sum of quantity q of column col over nwg workgroup partials (one
+// workgroup per column; fixed order).  Result valid in thread 0.
+__device__ double col_sum(const double *part, int nq, int q, int Bc, int col, int nwg) {
+  __shared__ double red[kRWG];
+  double s = 0;
+  for (int w = threadIdx.x; w < nwg; w += kRWG) s += part[((size_t)w * nq + q) * Bc + col];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = kRWG / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Velocity part of the right-hand side of column col at edge e:
+// f = M_u U_u + q (U_eta(c0) - U_eta(c1)).
+__device__ inline double2 rhs_u(const RexiArgs &a, int e, int col, double2 q) {
+  const DevOps &o = a.ops;
+  const int c0 = o.ecell[2 * e], c1 = o.ecell[2 * e + 1];
+  if (a.src.real_blk) {
+    const int Bm = a.src.Bm, mem = col / a.P;
+    const double *U = a.src.real_blk;
+    double mu = 0.0;
+#pragma unroll
+    for (int k = 0; k < 5; k++) mu = fma(o.mass[5 * e + k], U[(size_t)o.ell_col[5 * e + k] * Bm + mem], mu);
+    const double de = U[(size_t)(o.ne + c0) * Bm + mem] - U[(size_t)(o.ne + c1) * Bm + mem];
+    return make_double2(mu + q.x * de, q.y * de);
+  }
+  const double2 *Z = a.src.cplx_blk;
+  const int Bc = a.Bc;
+  double2 mu = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int k = 0; k < 5; k++) {
+    const double m = o.mass[5 * e + k];
+    const double2 z = Z[(size_t)o.ell_col[5 * e + k] * Bc + col];
+    mu.x = fma(m, z.x, mu.x);
+    mu.y = fma(m, z.y, mu.y);
+  }
+  const double2 de = csub(Z[(size_t)(o.ne + c0) * Bc + col], Z[(size_t)(o.ne + c1) * Bc + col]);
+  return cadd(mu, cmul(q, de));
+}
+
+// (S z)_e for column col, S = a M + b F + c G (b = -i binv), with z read by
+// the gather g(row); also the diagonal of S at e.
+template <class Gz>
+__device__ inline double2 schur_row(const RexiArgs &a, int e, double2 ca, double2 cc, Gz g, double2 &diag) {
+  const DevOps &o = a.ops;
+  double2 mz = make_double2(0.0, 0.0), fz = mz, gz = mz;
+#pragma unroll
+  for (int k = 0; k < 5; k++) {
+    const int j = o.ell_col[5 * e + k];
+    const double2 z = g(j);
+    const double m = o.mass[5 * e + k], f = o.cor[5 * e + k], gg = o.graddiv[5 * e + k];
+    mz.x = fma(m, z.x, mz.x);
+    mz.y = fma(m, z.y, mz.y);
+    fz.x = fma(f, z.x, fz.x);
+    fz.y = fma(f, z.y, fz.y);
+    gz.x = fma(gg, z.x, gz.x);
+    gz.y = fma(gg, z.y, gz.y);
+  }
+  diag = cadd(cscale(o.mass[5 * e], ca), cscale(o.graddiv[5 * e], cc));
+  // b F z = -i binv F z = binv (Im Fz, -Re Fz)
+  return cadd(cadd(cmul(ca, mz), cmul(cc, gz)), make_double2(a.binv * fz.y, -a.binv * fz.x));
+}
+
+// ---------------------------------------------------------------- kernels
+// Start (mode 0: x = 0, residual f) or check-and-restart (mode 1: residual
+// f - S x) of every valid column: r = D^-1 res, p = r.  Partials: |res|^2,
+// |r|^2, (r~, r).
+__global__ __launch_bounds__(kRWG) void k_rexi_init(RexiArgs a, double2 *p_out) {
+  const RLane L = rlane(a.Bc, a.ops.ne);
+  const int col = L.col;
+  const bool on = col < a.ncols;
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  if (on) {
+    const double2 ca = a.co.a[col], cc = a.co.c[col], cq = a.co.q[col];
+    for (int e = L.row0; e < L.rend; e += L.rstride) {
+      const size_t ie = (size_t)e * a.Bc + col;
+      double2 res = rhs_u(a, e, col, cq);
+      double2 d;
+      if (a.mode == 1) {
+        const double2 *x = a.x;
+        const int Bc = a.Bc;
+        const double2 sx = schur_row(a, e, ca, cc, [&](int j) { return x[(size_t)j * Bc + col]; }, d);
+        res = csub(res, sx);
+      } else {
+        d = cadd(cscale(a.ops.mass[5 * e], ca), cscale(a.ops.graddiv[5 * e], cc));
+        a.x[ie] = make_double2(0.0, 0.0);
+      }
+      const double2 r = cdiv(res, d);
+      a.r[ie] = r;
+      p_out[ie] = r;
+      v[0] += cabs2(res);
+      v[1] += cabs2(r);
+      const double2 rr = cdotc(shadow(a.seed, e, col), r);
+      v[2] += rr.x;
+      v[3] += rr.y;
+    }
+  }
+  rexi_partials<4>(L, v, a.part, a.Bc);
+}
+
+__global__ __launch_bounds__(kRWG) void k_rexi_fin_init(RexiArgs a, int nwg) {
+  const int col = blockIdx.x;
+  const double res2 = col_sum(a.part, 4, 0, a.Bc, col, nwg);
+  const double r2 = col_sum(a.part, 4, 1, a.Bc, col, nwg);
+  const double rre = col_sum(a.part, 4, 2, a.Bc, col, nwg);
+  const double rim = col_sum(a.part, 4, 3, a.Bc, col, nwg);
+  if (threadIdx.x != 0) return;
+  RexiState st = a.st;
+  if (col >= a.ncols) {
+    st.active[col] = 0;
+    return;
+  }
+  if (a.mode == 0) {
+    st.ff[col] = res2;
+    st.bb[col] = r2;
+    st.res2[col] = res2;
+    st.tau2[col] = a.rtol2;
+    st.rho[col] = make_double2(rre, rim);
+    st.active[col] = res2 > 0.0 ? 1 : 0;
+    st.iters[col] = 0;
+    st.fresh[col] = 1;
+    st.restarts[col] = 0;
+    return;
+  }
+  st.res2[col] = res2;
+  if (st.ff[col] == 0.0 || res2 <= a.rtol2 * st.ff[col]) {
+    st.active[col] = 0;
+    return;
+  }
+  if (st.iters[col] >= a.maxit) {  // no iterations left to restart with
+    st.active[col] = 0;
+    atomicAdd(st.fail, 1);
+    return;
+  }
+  // restart from x with a target tightened by the miss of the true residual
+  st.tau2[col] = st.tau2[col] * fmin(0.25, 0.25 * a.rtol2 * st.ff[col] / res2);
+  st.rho[col] = make_double2(rre, rim);
+  st.active[col] = 1;
+  st.fresh[col] = 1;
+  st.restarts[col] += 1;
+}
+
+// p' = r + beta (p - omega v) (p' = p on a fresh start), v' = D^-1 S p'.
+// Partials: (r~, v').
+__global__ __launch_bounds__(kRWG) void k_rexi_v(RexiArgs a, const double2 *p_in, const double2 *v_in,
+                                                   double2 *p_out, double2 *v_out) {
+  const RLane L = rlane(a.Bc, a.ops.ne);
+  const int col = L.col, Bc = a.Bc;
+  const bool on = col < a.ncols && a.st.active[col];
+  double v[2] = {0.0, 0.0};
+  if (on) {
+    const double2 ca = a.co.a[col], cc = a.co.c[col];
+    const bool fresh = a.st.fresh[col] != 0;
+    const double2 beta = a.st.beta[col], omega = a.st.omega[col];
+    const double2 *r = a.r;
+    auto pnew = [&](int j) {
+      const size_t ij = (size_t)j * Bc + col;
+      if (fresh) return p_in[ij];
+      return cadd(r[ij], cmul(beta, csub(p_in[ij], cmul(omega, v_in[ij]))));
+    };
+    for (int e = L.row0; e < L.rend; e += L.rstride) {
+      const size_t ie = (size_t)e * Bc + col;
+      double2 d;
+      const double2 sp = schur_row(a, e, ca, cc, pnew, d);
+      const double2 vv = cdiv(sp, d);
+      p_out[ie] = pnew(e);
+      v_out[ie] = vv;
+      const double2 rv = cdotc(shadow(a.seed, e, col), vv);
+      v[0] += rv.x;
+      v[1] += rv.y;
+    }
+  }
+  rexi_partials<2>(L, v, a.part, a.Bc);
+}
+
+__global__ __launch_bounds__(kRWG) void k_rexi_fin_v(RexiArgs a, int nwg) {
+  const int col = blockIdx.x;
+  const double re = col_sum(a.part, 2, 0, a.Bc, col, nwg);
+  const double im = col_sum(a.part, 2, 1, a.Bc, col, nwg);
+  if (threadIdx.x != 0 || col >= a.ncols || !a.st.active[col]) return;
+  const double2 rv = make_double2(re, im);
+  if (cabs2(rv) == 0.0) {  // breakdown: leave the column to the residual check
+    a.st.alpha[col] = make_double2(0.0, 0.0);
+    a.st.active[col] = 0;
+    return;
+  }
+  a.st.alpha[col] = cdiv(a.st.rho[col], rv);
+}
+
+// s = r - alpha v, t = D^-1 S s.  Partials: (t, s), |t|^2.
+__global__ __launch_bounds__(kRWG) void k_rexi_t(RexiArgs a, const double2 *v_in) {
+  const RLane L = rlane(a.Bc, a.ops.ne);
+  const int col = L.col, Bc = a.Bc;
+  const bool on = col < a.ncols && a.st.active[col];
+  double v[3] = {0.0, 0.0, 0.0};
+  if (on) {
+    const double2 ca = a.co.a[col], cc = a.co.c[col];
+    const double2 alpha = a.st.alpha[col];
+    const double2 *r = a.r;
+    auto snew = [&](int j) {
+      const size_t ij = (size_t)j * Bc + col;
+      return csub(r[ij], cmul(alpha, v_in[ij]));
+    };
+    for (int e = L.row0; e < L.rend; e += L.rstride) {
+      const size_t ie = (size_t)e * Bc + col;
+      double2 d;
+      const double2 ss = snew(e);
+      const double2 tt = cdiv(schur_row(a, e, ca, cc, snew, d), d);
+      a.s[ie] = ss;
+      a.t[ie] = tt;
+      const double2 ts = cdotc(tt, ss);
+      v[0] += ts.x;
+      v[1] += ts.y;
+      v[2] += cabs2(tt);
+    }
+  }
+  rexi_partials<3>(L, v, a.part, a.Bc);
+}
+
+__global__ __launch_bounds__(kRWG) void k_rexi_fin_t(RexiArgs a, int nwg) {
+  const int col = blockIdx.x;
+  const double re = col_sum(a.part, 3, 0, a.Bc, col, nwg);
+  const double im = col_sum(a.part, 3, 1, a.Bc, col, nwg);
+  const double tt = col_sum(a.part, 3, 2, a.Bc, col, nwg);
+  if (threadIdx.x != 0 || col >= a.ncols || !a.st.active[col]) return;
+  a.st.omega[col] = tt > 0.0 ? make_double2(re / tt, im / tt) : make_double2(0.0, 0.0);
+}
+
+// x += alpha p + omega s, r = s - omega t.  Partials: (r~, r), |r|^2.
+__global__ __launch_bounds__(kRWG) void k_rexi_x(RexiArgs a, const double2 *p_in) {
+  const RLane L = rlane(a.Bc, a.ops.ne);
+  const int col = L.col, Bc = a.Bc;
+  const bool on = col < a.ncols && a.st.active[col];
+  double v[3] = {0.0, 0.0, 0.0};
+  if (on) {
+    const double2 alpha = a.st.alpha[col], omega = a.st.omega[col];
+    for (int e = L.row0; e < L.rend; e += L.rstride) {
+      const size_t ie = (size_t)e * Bc + col;
+      const double2 ss = a.s[ie];
+      a.x[ie] = cadd(a.x[ie], cadd(cmul(alpha, p_in[ie]), cmul(omega, ss)));
+      const double2 rn = csub(ss, cmul(omega, a.t[ie]));
+      a.r[ie] = rn;
+      const double2 rr = cdotc(shadow(a.seed, e, col), rn);
+      v[0] += rr.x;
+      v[1] += rr.y;
+      v[2] += cabs2(rn);
+    }
+  }
+  rexi_partials<3>(L, v, a.part, a.Bc);
+}
+
+__global__ __launch_bounds__(kRWG) void k_rexi_fin_x(RexiArgs a, int nwg) {
+  const int col = blockIdx.x;
+  const double re = col_sum(a.part, 3, 0, a.Bc, col, nwg);
+  const double im = col_sum(a.part, 3, 1, a.Bc, col, nwg);
+  const double r2 = col_sum(a.part, 3, 2, a.Bc, col, nwg);
+  if (threadIdx.x != 0 || col >= a.ncols || !a.st.active[col]) return;
+  RexiState st = a.st;
+  const int it = ++st.iters[col];
+  st.fresh[col] = 0;
+  const double2 rho_new = make_double2(re, im), omega = st.omega[col];
+  if (r2 <= st.tau2[col] * st.bb[col]) {  // to the true-residual check
+    st.active[col] = 0;
+    return;
+  }
+  if (cabs2(omega) == 0.0 || cabs2(rho_new) == 0.0) {  // breakdown: check and restart
+    st.active[col] = 0;
+    return;
+  }
+  if (it >= a.maxit) {
+    st.active[col] = 0;
+    atomicAdd(st.fail, 1);
+    return;
+  }
+  st.beta[col] = cmul(cdiv(rho_new, st.rho[col]), cdiv(st.alpha[col], omega));
+  st.rho[col] = rho_new;
+}
+
+// Depth rows: y_eta = xinv src_eta + h (D y_u) / |c|.
+__global__ __launch_bounds__(kRWG) void k_rexi_eta(RexiEtaArgs a) {
+  const RLane L = rlane(a.Bc, a.ops.nc);
+  const int col = L.col, Bc = a.Bc;
+  if (col >= Bc) return;
+  const DevOps &o = a.ops;
+  const bool on = col < a.ncols;
+  const double2 xinv = on ? a.co.xinv[col] : make_double2(0.0, 0.0);
+  const double2 h = on ? a.co.h[col] : make_double2(0.0, 0.0);
+  for (int t = L.row0; t < L.rend; t += L.rstride) {
+    const size_t it = (size_t)t * Bc + col;
+    if (!on) {
+      a.yeta[it] = make_double2(0.0, 0.0);
+      continue;
+    }
+    double2 div = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+      const double sg = (double)o.csgn[3 * t + j];
+      const double2 y = a.yu[(size_t)o.cedge[3 * t + j] * Bc + col];
+      div.x = fma(sg, y.x, div.x);
+      div.y = fma(sg, y.y, div.y);
+    }
+    double2 src;
+    if (a.src.real_blk)
+      src = make_double2(a.src.real_blk[(size_t)(o.ne + t) * a.src.Bm + col / a.P], 0.0);
+    else
+      src = a.src.cplx_blk[(size_t)(o.ne + t) * Bc + col];
+    a.yeta[it] = cadd(cmul(xinv, src), cscale(o.inv_area[t], cmul(h, div)));
+  }
+}
+
+__global__ __launch_bounds__(kRWG) void k_rexi_combine(RexiCombineArgs a) {
+  const int Bo = a.members * a.Go, So = a.ostride;
+  const size_t total = (size_t)a.n * So;
+  for (size_t i = (size_t)blockIdx.x * kRWG + threadIdx.x; i < total; i += (size_t)gridDim.x * kRWG) {
+    const int row = (int)(i / So), oc = (int)(i % So);
+    const int mem = oc / a.Go, m = oc % a.Go;
+    double acc = 0.0;
+    if (oc < Bo && m < a.Mo) {
+      const double2 *C = a.C + ((size_t)(a.per_member ? mem : 0) * a.Go + m) * a.P;
+      const double2 *Y = a.Y + (size_t)row * a.Bc + (size_t)mem * a.P;
+      for (int j = 0; j < a.P; j++) {
+        const double2 c = C[j], y = Y[j];
+        acc = fma(c.x, y.x, acc);
+        acc = fma(-c.y, y.y, acc);
+      }
+    }
+    a.out[i] = acc;
+  }
+}
+
+__global__ __launch_bounds__(kRWG) void k_rexi_back(RexiBackArgs a) {
+  const size_t total = (size_t)a.n * a.Bc;
+  const int Bi = a.istride;
+  for (size_t i = (size_t)blockIdx.x * kRWG + threadIdx.x; i < total; i += (size_t)gridDim.x * kRWG) {
+    const int row = (int)(i / a.Bc), col = (int)(i % a.Bc);
+    double2 z = make_double2(0.0, 0.0);
+    if (col < a.members * a.P) {
+      const int mem = col / a.P, j = col % a.P;
+      const double *Yn = a.Yn + (size_t)row * Bi + (size_t)mem * a.Gi;
+      for (int m = 0; m < a.Mi; m++) {
+        const double2 c = a.C[(size_t)m * a.P + j];
+        const double y = Yn[m];
+        z.x = fma(c.x, y, z.x);
+        z.y = fma(c.y, y, z.y);
+      }
+    }
+    a.Z[i] = z;
+  }
+}
+}  // namespace
+
+// ------------------------------------------------------------ launchers
+int rexi_grid(int ne, int Bc) {
+  const int ct = Bc < 64 ? Bc : 64;
+  const int rows_per_pass = (kRWG / 64) * (64 / ct);
+  const int tiles = (Bc + 63) / 64;
+  int want = (ne + rows_per_pass - 1) / rows_per_pass;
+  int cap = 1024 / tiles;
+  if (cap < 64) cap = 64;
+  int g = want < cap ? want : cap;
+  g = (g + 7) / 8 * 8;
+  return g > 0 ? g : 8;
+}
+
+namespace {
+dim3 rgrid(int rows, int Bc) { return dim3(rexi_grid(rows, Bc), (Bc + 63) / 64); }
+int flat_grid(size_t n) {
+  size_t g = (n + kRWG - 1) / kRWG;
+  return (int)(g < 8192 ? (g > 0 ? g : 1) : 8192);
+}
+}  // namespace
+
+void launch_rexi_init(const RexiArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_rexi_init, rgrid(a.ops.ne, a.Bc), dim3(kRWG), 0, s, a, a.p);
+}
+void launch_rexi_fin_init(const RexiArgs &a, int nwg, hipStream_t s) {
+  hipLaunchKernelGGL(k_rexi_fin_init, dim3(a.Bc), dim3(kRWG), 0, s, a, nwg);
+}
+void launch_rexi_v(const RexiArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_rexi_v, rgrid(a.ops.ne, a.Bc), dim3(kRWG), 0, s, a, a.p, a.v, a.p_next, a.v_next);
+}
+void launch_rexi_fin_v(const RexiArgs &a, int nwg, hipStream_t s) {
+  hipLaunchKernelGGL(k_rexi_fin_v, dim3(a.Bc), dim3(kRWG), 0, s, a, nwg);
+}
+void launch_rexi_t(const RexiArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_rexi_t, rgrid(a.ops.ne, a.Bc), dim3(kRWG), 0, s, a, a.v_next);
+}
+void launch_rexi_fin_t(const RexiArgs &a, int nwg, hipStream_t s) {
+  hipLaunchKernelGGL(k_rexi_fin_t, dim3(a.Bc), dim3(kRWG), 0, s, a, nwg);
+}
+void launch_rexi_x(const RexiArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_rexi_x, rgrid(a.ops.ne, a.Bc), dim3(kRWG), 0, s, a, a.p_next);
+}
+void launch_rexi_fin_x(const RexiArgs &a, int nwg, hipStream_t s) {
+  hipLaunchKernelGGL(k_rexi_fin_x, dim3(a.Bc), dim3(kRWG), 0, s, a, nwg);
+}
+void launch_rexi_eta(const RexiEtaArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_rexi_eta, rgrid(a.ops.nc, a.Bc), dim3(kRWG), 0, s, a);
+}
+void launch_rexi_combine(const RexiCombineArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_rexi_combine, dim3(flat_grid((size_t)a.n * a.ostride)), dim3(kRWG), 0, s, a);
+}
+void launch_rexi_back(const RexiBackArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_rexi_back, dim3(flat_grid((size_t)a.n * a.Bc)), dim3(kRWG), 0, s, a);
+}
+
+}  // namespace pa

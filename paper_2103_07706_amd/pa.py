@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libpa.so")
 PA_FP64, PA_FP32_REFINED = 0, 1
 PA_BACKWARD_PER_TERM, PA_BACKWARD_CLENSHAW = 0, 1
 PA_SOLVER_CG, PA_SOLVER_CHEBYSHEV = 0, 1
+PA_EXP_CHEBYSHEV, PA_EXP_REXI = 0, 1
 PA_OK, PA_EINVAL, PA_ENOMEM, PA_EHIP, PA_ENOCONV, PA_ENOTSUP, PA_EGROWTH = range(7)
 _STATUS = {0: "PA_OK", 1: "PA_EINVAL", 2: "PA_ENOMEM", 3: "PA_EHIP", 4: "PA_ENOCONV",
            5: "PA_ENOTSUP", 6: "PA_EGROWTH"}
@@ -45,7 +46,8 @@ class SolveCfg(ctypes.Structure):
                 ("cg_rtol", ctypes.c_double), ("cheb_tol", ctypes.c_double),
                 ("weight_cut", ctypes.c_double), ("inner_rtol", ctypes.c_double),
                 ("use_graph", ctypes.c_int32), ("solver", ctypes.c_int32),
-                ("precond", ctypes.c_int32)]
+                ("precond", ctypes.c_int32), ("exponential", ctypes.c_int32),
+                ("rexi_nodes", ctypes.c_int32), ("rexi_eta0", ctypes.c_double)]
 
 
 PA_PRECOND_JACOBI, PA_PRECOND_LEARNED = 0, 1
@@ -107,7 +109,11 @@ class Stats(ctypes.Structure):
                 ("resid_max", ctypes.c_double), ("device_ms", ctypes.c_double),
                 ("graph", ctypes.c_int32), ("budget", ctypes.c_int32),
                 ("precond", ctypes.c_int32), ("lp_solves", ctypes.c_int32),
-                ("fallbacks", ctypes.c_int32), ("graph_captured", ctypes.c_int32)]
+                ("fallbacks", ctypes.c_int32), ("graph_captured", ctypes.c_int32),
+                ("rexi_nodes", ctypes.c_int32), ("rexi_solves", ctypes.c_int32),
+                ("rexi_iters", ctypes.c_int32), ("rexi_iters_max", ctypes.c_int32),
+                ("rexi_restarts", ctypes.c_int32), ("rexi_pad", ctypes.c_int32),
+                ("rexi_eta0", ctypes.c_double), ("rexi_resid_max", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -247,17 +253,19 @@ def set_launch_tune(**changes):
 
 def solve_cfg(precision=None, backward=None, maxit=None, cg_rtol=None, cheb_tol=None,
               weight_cut=None, inner_rtol=None, use_graph=None, solver=None, precond=None,
-              growth_guard=None) -> SolveCfg:
+              growth_guard=None, exponential=None, rexi_nodes=None,
+              rexi_eta0=None) -> SolveCfg:
     """A solve configuration: the library's defaults (pa_solve_cfg_default:
-    FP64, Clenshaw backward sum, Chebyshev mass solves, graph replay, Jacobi
-    preconditioning, cg_rtol 1e-10, Chebyshev threshold 1e-6) with the given
-    fields changed."""
+    FP64, Chebyshev exponential, Clenshaw backward sum, Chebyshev mass
+    solves, graph replay, Jacobi preconditioning, cg_rtol 1e-10, Chebyshev
+    threshold 1e-6) with the given fields changed."""
     c = SolveCfg()
     lib().pa_solve_cfg_default(ctypes.byref(c))
     for name, v in (("precision", precision), ("backward", backward), ("maxit", maxit),
                     ("cg_rtol", cg_rtol), ("cheb_tol", cheb_tol), ("weight_cut", weight_cut),
                     ("inner_rtol", inner_rtol), ("solver", solver), ("precond", precond),
-                    ("growth_guard", growth_guard)):
+                    ("growth_guard", growth_guard), ("exponential", exponential),
+                    ("rexi_nodes", rexi_nodes), ("rexi_eta0", rexi_eta0)):
         if v is not None:
             setattr(c, name, v)
     if use_graph is not None:

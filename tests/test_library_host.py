@@ -98,3 +98,59 @@ def test_library_avg_nodes_match_oracle(M, T):
     assert np.array_equal(a.s, s)
     assert np.abs(a.w - w).max() <= 1e-15 * np.abs(w).max()
     assert abs(a.w.sum() - 1.0) < 1e-14
+
+
+def test_solve_cfg_defaults_and_layout():
+    """The ctypes mirror of pa_solve_cfg matches the C layout: the library's
+    defaults read back field by field (a shifted field would read garbage)."""
+    from paper_2103_07706_amd import pa
+    c = pa.solve_cfg()
+    assert (c.precision, c.backward, c.maxit, c.growth_guard) == (pa.PA_FP64, pa.PA_BACKWARD_CLENSHAW,
+                                                                  100, 0)
+    assert (c.cg_rtol, c.cheb_tol, c.weight_cut, c.inner_rtol) == (1e-10, 1e-6, 1e-16, 1e-6)
+    assert (c.use_graph, c.solver, c.precond) == (1, pa.PA_SOLVER_CHEBYSHEV, pa.PA_PRECOND_JACOBI)
+    assert (c.exponential, c.rexi_nodes, c.rexi_eta0) == (pa.PA_EXP_CHEBYSHEV, 0, 0.0)
+
+
+def _host_ops(level, lambda_bar):
+    """Operators on the host only (pa_ops_create needs no device)."""
+    import ctypes
+
+    from paper_2103_07706_amd import pa
+    m = pa.Mesh(level)
+    ph = pa.Phys(9.80616, 1000.0, 7.292e-5, None, lambda_bar)
+    h = ctypes.c_void_p()
+    assert pa.lib().pa_ops_create(m._h, ctypes.byref(ph), ctypes.byref(h)) == pa.PA_OK
+    return m, h
+
+
+def test_rexi_workspace_sizing_host():
+    """Planning of the rational exponential on the host: the library picks
+    a node set for the call's largest time (sizing runs the same planning
+    code as the call), honours an explicit one, and refuses node counts
+    that are not multiples of 4 or an ellipse parameter out of range."""
+    import ctypes
+
+    from paper_2103_07706_amd import pa
+    m, h = _host_ops(3, 7.2e-4)
+    try:
+        avg = pa.Avg(8, 3600.0)
+        sz = ctypes.c_size_t()
+        cheb = pa.solve_cfg()
+        assert pa.lib().pa_workspace_size(h, avg._h, 1, ctypes.byref(cheb), ctypes.byref(sz)) == 0
+        auto = pa.solve_cfg(exponential=pa.PA_EXP_REXI)
+        assert pa.lib().pa_workspace_size(h, avg._h, 2, ctypes.byref(auto), ctypes.byref(sz)) == 0
+        assert sz.value > 0
+        fixed = pa.solve_cfg(exponential=pa.PA_EXP_REXI, rexi_nodes=36, rexi_eta0=0.79)
+        assert pa.lib().pa_workspace_size(h, avg._h, 1, ctypes.byref(fixed), ctypes.byref(sz)) == 0
+        # 18 poles a member: 32 complex columns, eight blocks of them at level 3
+        assert sz.value > 8 * 32 * 16 * (1920 + 1280)
+        for N, eta0 in [(30, 0.79), (4, 0.79), (260, 0.5), (36, 0.0), (36, 3.5)]:
+            bad = pa.solve_cfg(exponential=pa.PA_EXP_REXI, rexi_nodes=N, rexi_eta0=eta0)
+            assert pa.lib().pa_workspace_size(h, avg._h, 1, ctypes.byref(bad),
+                                              ctypes.byref(sz)) == pa.PA_EINVAL, (N, eta0)
+        bad = pa.solve_cfg(exponential=7)
+        assert pa.lib().pa_workspace_size(h, avg._h, 1, ctypes.byref(bad),
+                                          ctypes.byref(sz)) == pa.PA_EINVAL
+    finally:
+        pa.lib().pa_ops_destroy(h)
