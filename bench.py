@@ -6,11 +6,13 @@ averaging terms over T = 2 h, FP64, Chebyshev threshold 1e-6 and every mass
 solve to a relative residual of 1e-10 (the throughput workload), with the
 input state already resident in device memory.  Prints one JSON line.
 
-Two forms are timed on the same input: the mass solves preconditioned by
-Jacobi (plain) and with the learned preconditioner available (trained on
-the GPU on level 4-6 meshes before the timed region; each solve takes the
-learned or the Jacobi steps by a byte model); `value` is the faster form's
-throughput and both are listed under config.forms.
+Several forms are timed on the same input: the Chebyshev exponential with
+the mass solves preconditioned by Jacobi (plain), with FP32 solves refined
+in FP64 (fp32_refined), with the learned preconditioner (learned, hybrid:
+trained on the GPU on level 4-6 meshes before the timed region), and the
+rational (REXI) exponential (rexi).  `value` is the fastest Chebyshev
+form's throughput; all are listed under config.forms, each with its
+difference to the oracle on a sample of the averaging terms.
 
 Also reported: the roofline position of the dominant kernel (HIP events
 around each of its launches during the timed region, algorithmic bytes from
@@ -43,8 +45,9 @@ def parse():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_refined"])
     ap.add_argument("--autotune", type=int, default=1)
     ap.add_argument("--precond", default="both", choices=["jacobi", "learned", "both"])
-    ap.add_argument("--forms", default="plain,fp32_refined,learned,hybrid",
-                    help="comma-separated forms to time (of plain, fp32_refined, learned, hybrid)")
+    ap.add_argument("--forms", default="plain,fp32_refined,learned,hybrid,rexi",
+                    help="comma-separated forms to time (of plain, fp32_refined, learned, "
+                         "hybrid, rexi)")
     ap.add_argument("--tune-cache", dest="tune_cache", default=None,
                     help="JSON file of launch shapes: read when it holds the problem, else written")
     ap.add_argument("--lp-steps", dest="lp_steps", type=int, default=200)
@@ -154,7 +157,7 @@ def errors_vs_oracle(pa, ops, mesh, smp, forms, members):
         out[name] = {"energy_norm": float(oo.wnorm(d) / oo.wnorm(ref)),
                      "max_u": float(np.abs(d[:ne]).max() / np.abs(ref[:ne]).max()),
                      "max_eta": float(np.abs(d[ne:]).max() / np.abs(ref[ne:]).max()),
-                     "resid_max": st["resid_max"]}
+                     "resid_max": max(st["resid_max"], st["rexi_resid_max"])}
     return out
 
 
@@ -243,7 +246,7 @@ def bench_batch(args):
         lcfg = pa.solve_cfg(precond=pa.PA_PRECOND_LEARNED, **base)
         forms["learned"] = (lcfg, 1)
         forms["hybrid"] = (lcfg, None)
-    wanted = set(args.forms.split(","))
+    wanted = set(args.forms.split(",")) - {"rexi"}  # batches run the Chebyshev exponential
     forms = {k: v for k, v in forms.items() if k in wanted}
     if not forms:
         raise SystemExit("no form selected")
@@ -327,6 +330,10 @@ def main():
             # autotuner finds them faster, FP64 steps elsewhere
             forms["fp32_refined"] = (pa.solve_cfg(
                 precond=pa.PA_PRECOND_JACOBI, **dict(base, precision=pa.PA_FP32_REFINED)), None)
+        # every exponential the rational (REXI) sum: shifted solves batched
+        # over the poles, node set chosen by the library for the threshold
+        forms["rexi"] = (pa.solve_cfg(precond=pa.PA_PRECOND_JACOBI, exponential=pa.PA_EXP_REXI,
+                                      **base), None)
     lp_rec = None
     if args.precond in ("learned", "both") and {"learned", "hybrid"} & set(args.forms.split(",")):
         # the network is trained on the GPU on meshes of levels 4 to 6 (this
@@ -345,7 +352,8 @@ def main():
     for name, (cfg, lmin) in forms.items():
         tune = None
         ops.set_tune()  # every form starts its search from the process default
-        if args.autotune:
+        # (the launch shapes tuned concern the Chebyshev exponential's solves)
+        if args.autotune and cfg.exponential == pa.PA_EXP_CHEBYSHEV:
             tune = ops.autotune(avg, U, cfg, cache=args.tune_cache)
         if lmin is not None:
             # the autotuner chose the shape with its own learned-step
@@ -365,7 +373,10 @@ def main():
         results[name] = dict(elapsed=elapsed, stats=stats, tune=ops.get_tune(), cfg=cfg,
                              autotune=tune, learned=stats["lp_solves"] > 0)
     # value: the faster form on this workload (all are listed in config.forms)
-    head_name = max(results, key=lambda k: 1.0 / results[k]["elapsed"])
+    # among those of the Chebyshev exponential, whose solver kernels the
+    # roofline below follows (the rational form is reported beside them)
+    cheb_forms = [k for k in results if results[k]["cfg"].exponential == pa.PA_EXP_CHEBYSHEV]
+    head_name = max(cheb_forms or results, key=lambda k: 1.0 / results[k]["elapsed"])
     head = results[head_name]
     # the dominant kernel of that form, timed last (after every other form):
     # each launch carries its own start and end events
@@ -411,6 +422,15 @@ def main():
                         "resid_max": r["stats"]["resid_max"],
                         "launch_tune": r["tune"], "autotune": r["autotune"]}
                  for name, r in results.items()}
+    for name, r in results.items():
+        st = r["stats"]
+        if r["cfg"].exponential == pa.PA_EXP_REXI:
+            forms_rec[name].update(rexi_nodes=st["rexi_nodes"], rexi_eta0=st["rexi_eta0"],
+                                   rexi_solves=st["rexi_solves"],
+                                   rexi_iterations=st["rexi_iters"],
+                                   rexi_iterations_max=st["rexi_iters_max"],
+                                   rexi_restarts=st["rexi_restarts"],
+                                   rexi_resid_max=st["rexi_resid_max"])
     for name in ("learned", "hybrid", "fp32_refined"):
         if name in forms_rec and "plain" in forms_rec:
             forms_rec[f"{name}_over_plain"] = forms_rec[name]["value"] / forms_rec["plain"]["value"]

@@ -94,6 +94,7 @@ struct RexiBackArgs {
 
 void launch_rexi_init(const RexiArgs &a, hipStream_t s);
 void launch_rexi_fin_init(const RexiArgs &a, int nwg, hipStream_t s);
+// p_next = r + beta (p - omega v), then v_next = D^-1 S p_next (two kernels)
 void launch_rexi_v(const RexiArgs &a, hipStream_t s);
 void launch_rexi_fin_v(const RexiArgs &a, int nwg, hipStream_t s);
 void launch_rexi_t(const RexiArgs &a, hipStream_t s);

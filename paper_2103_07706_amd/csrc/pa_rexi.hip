@@ -42,15 +42,65 @@ __device__ inline RLane rlane(int Bc, int nrows) {
   return L;
 }
 
+// One row per wave (UNI: blocks of 64 or more columns, lane = column of a
+// 64-column tile): the row number is wave-uniform, so the row's operator
+// entries load through the scalar unit instead of once per lane.
+__device__ inline RLane rlane_uni(int nrows) {
+  RLane L;
+  L.ct = 64;
+  L.rw = 1;
+  L.lane = threadIdx.x & 63;
+  L.wave = threadIdx.x >> 6;
+  L.tile = blockIdx.y;
+  L.col = L.tile * 64 + L.lane;
+  const int per = gridDim.x >> 3;
+  const int xcd = blockIdx.x & 7, w = blockIdx.x >> 3;
+  const int slice = (nrows + 7) >> 3;
+  const int rpp = kRWG / 64;
+  L.rend = min(nrows, (xcd + 1) * slice);
+  L.row0 = xcd * slice + w * rpp + L.wave;
+  L.rstride = per * rpp;
+  return L;
+}
+template <bool UNI>
+__device__ inline RLane rlane_t(int Bc, int nrows) {
+  return UNI ? rlane_uni(nrows) : rlane(Bc, nrows);
+}
+
+// Row-table loads: through the constant address space (scalar loads) when
+// the row is wave-uniform.
+template <bool UNI, typename T>
+__device__ inline T rld(const T *p, size_t i) {
+  if constexpr (UNI)
+    return ((const __attribute__((address_space(4))) T *)p)[i];
+  else
+    return p[i];
+}
+template <bool UNI>
+__device__ inline int urow(int e) {
+  return UNI ? __builtin_amdgcn_readfirstlane(e) : e;
+}
+
 __device__ inline double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 __device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 __device__ inline double2 cscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
+// a / b through the hardware reciprocal of |b|^2 and two Newton steps (full
+// FP64 accuracy from its estimate; |b|^2 is a positive normal number here:
+// a diagonal of a shifted system)
 __device__ inline double2 cdiv(double2 a, double2 b) {
-  const double d = b.x * b.x + b.y * b.y;
-  return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+  const double n = b.x * b.x + b.y * b.y;
+  double inv = __builtin_amdgcn_rcp(n);
+  inv = fma(inv, fma(-n, inv, 1.0), inv);
+  inv = fma(inv, fma(-n, inv, 1.0), inv);
+  return make_double2((a.x * b.x + a.y * b.y) * inv, (a.y * b.x - a.x * b.y) * inv);
+}
+// a / b with IEEE division (the scalars of the iteration, of any magnitude)
+__device__ inline double2 cdiv_ieee(double2 a, double2 b) {
+  const double n = b.x * b.x + b.y * b.y;
+  return make_double2((a.x * b.x + a.y * b.y) / n, (a.y * b.x - a.x * b.y) / n);
 }
 __device__ inline double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
 // conj(a) b
@@ -58,15 +108,18 @@ __device__ inline double2 cdotc(double2 a, double2 b) {
   return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
 }
 
-// Shadow residual of BiCGStab: a counter hash (SplitMix64 finaliser) of the
-// row, the column and the seed, in [-1, 1)^2.
+// Shadow residual of BiCGStab: a 32-bit counter hash (multiply-xorshift
+// rounds) of the row, the column and the seed, two 16-bit halves mapped to
+// [-1, 1).
 __device__ inline double2 shadow(uint32_t seed, int e, int col) {
-  uint64_t z = (((uint64_t)(uint32_t)e << 32) | (uint32_t)col) + (uint64_t)(seed + 1) * 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  z ^= z >> 31;
-  const double sc = 1.0 / 8388608.0;  // 2^-23
-  return make_double2((double)((z >> 40) & 0xFFFFFF) * sc - 1.0, (double)((z >> 8) & 0xFFFFFF) * sc - 1.0);
+  uint32_t h = (uint32_t)e * 0x9E3779B1u ^ ((uint32_t)col + 1u) * 0x85EBCA77u ^ seed;
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 12;
+  h *= 0x297A2D39u;
+  h ^= h >> 15;
+  const double sc = 1.0 / 32768.0;
+  return make_double2((double)(h & 0xFFFFu) * sc - 1.0, (double)(h >> 16) * sc - 1.0);
 }
 
 // Per-workgroup column sums of NQ quantities into part[wg][q][Bc].
@@ -81,6 +134,7 @@ __device__ void rexi_partials(const RLane &L, double (&v)[NQ], double *part, int
   __syncthreads();
   for (int idx = threadIdx.x; idx < NQ * L.ct; idx += kRWG) {
     const int q = idx / L.ct, c = idx % L.ct;
+    if (L.tile * L.ct + c >= Bc) continue;  // lanes past the block (one-row-a-wave form)
     double s = 0;
     for (int w = 0; w < kRWG / 64; w++) s += red[q][w][c];
     part[((size_t)blockIdx.x * NQ + q) * Bc + L.tile * L.ct + c] = s;
@@ -106,15 +160,17 @@ __device__ double col_sum(const double *part, int nq, int q, int Bc, int col, in
 
 // Velocity part of the right-hand side of column col at edge e:
 // f = M_u U_u + q (U_eta(c0) - U_eta(c1)).
+template <bool UNI>
 __device__ inline double2 rhs_u(const RexiArgs &a, int e, int col, double2 q) {
   const DevOps &o = a.ops;
-  const int c0 = o.ecell[2 * e], c1 = o.ecell[2 * e + 1];
+  const int c0 = rld<UNI>(o.ecell, 2 * e), c1 = rld<UNI>(o.ecell, 2 * e + 1);
   if (a.src.real_blk) {
     const int Bm = a.src.Bm, mem = col / a.P;
     const double *U = a.src.real_blk;
     double mu = 0.0;
 #pragma unroll
-    for (int k = 0; k < 5; k++) mu = fma(o.mass[5 * e + k], U[(size_t)o.ell_col[5 * e + k] * Bm + mem], mu);
+    for (int k = 0; k < 5; k++)
+      mu = fma(rld<UNI>(o.mass, 5 * e + k), U[(size_t)rld<UNI>(o.ell_col, 5 * e + k) * Bm + mem], mu);
     const double de = U[(size_t)(o.ne + c0) * Bm + mem] - U[(size_t)(o.ne + c1) * Bm + mem];
     return make_double2(mu + q.x * de, q.y * de);
   }
@@ -123,8 +179,8 @@ __device__ inline double2 rhs_u(const RexiArgs &a, int e, int col, double2 q) {
   double2 mu = make_double2(0.0, 0.0);
 #pragma unroll
   for (int k = 0; k < 5; k++) {
-    const double m = o.mass[5 * e + k];
-    const double2 z = Z[(size_t)o.ell_col[5 * e + k] * Bc + col];
+    const double m = rld<UNI>(o.mass, 5 * e + k);
+    const double2 z = Z[(size_t)rld<UNI>(o.ell_col, 5 * e + k) * Bc + col];
     mu.x = fma(m, z.x, mu.x);
     mu.y = fma(m, z.y, mu.y);
   }
@@ -134,15 +190,16 @@ __device__ inline double2 rhs_u(const RexiArgs &a, int e, int col, double2 q) {
 
 // (S z)_e for column col, S = a M + b F + c G (b = -i binv), with z read by
 // the gather g(row); also the diagonal of S at e.
-template <class Gz>
+template <bool UNI, class Gz>
 __device__ inline double2 schur_row(const RexiArgs &a, int e, double2 ca, double2 cc, Gz g, double2 &diag) {
   const DevOps &o = a.ops;
   double2 mz = make_double2(0.0, 0.0), fz = mz, gz = mz;
 #pragma unroll
   for (int k = 0; k < 5; k++) {
-    const int j = o.ell_col[5 * e + k];
+    const int j = rld<UNI>(o.ell_col, 5 * e + k);
     const double2 z = g(j);
-    const double m = o.mass[5 * e + k], f = o.cor[5 * e + k], gg = o.graddiv[5 * e + k];
+    const double m = rld<UNI>(o.mass, 5 * e + k), f = rld<UNI>(o.cor, 5 * e + k);
+    const double gg = rld<UNI>(o.graddiv, 5 * e + k);
     mz.x = fma(m, z.x, mz.x);
     mz.y = fma(m, z.y, mz.y);
     fz.x = fma(f, z.x, fz.x);
@@ -150,7 +207,7 @@ __device__ inline double2 schur_row(const RexiArgs &a, int e, double2 ca, double
     gz.x = fma(gg, z.x, gz.x);
     gz.y = fma(gg, z.y, gz.y);
   }
-  diag = cadd(cscale(o.mass[5 * e], ca), cscale(o.graddiv[5 * e], cc));
+  diag = cadd(cscale(rld<UNI>(o.mass, 5 * e), ca), cscale(rld<UNI>(o.graddiv, 5 * e), cc));
   // b F z = -i binv F z = binv (Im Fz, -Re Fz)
   return cadd(cadd(cmul(ca, mz), cmul(cc, gz)), make_double2(a.binv * fz.y, -a.binv * fz.x));
 }
@@ -159,24 +216,26 @@ __device__ inline double2 schur_row(const RexiArgs &a, int e, double2 ca, double
 // Start (mode 0: x = 0, residual f) or check-and-restart (mode 1: residual
 // f - S x) of every valid column: r = D^-1 res, p = r.  Partials: |res|^2,
 // |r|^2, (r~, r).
+template <bool UNI>
 __global__ __launch_bounds__(kRWG) void k_rexi_init(RexiArgs a, double2 *p_out) {
-  const RLane L = rlane(a.Bc, a.ops.ne);
+  const RLane L = rlane_t<UNI>(a.Bc, a.ops.ne);
   const int col = L.col;
   const bool on = col < a.ncols;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   if (on) {
     const double2 ca = a.co.a[col], cc = a.co.c[col], cq = a.co.q[col];
-    for (int e = L.row0; e < L.rend; e += L.rstride) {
+    for (int base = L.row0; base < L.rend; base += L.rstride) {
+      const int e = urow<UNI>(base);
       const size_t ie = (size_t)e * a.Bc + col;
-      double2 res = rhs_u(a, e, col, cq);
+      double2 res = rhs_u<UNI>(a, e, col, cq);
       double2 d;
       if (a.mode == 1) {
         const double2 *x = a.x;
         const int Bc = a.Bc;
-        const double2 sx = schur_row(a, e, ca, cc, [&](int j) { return x[(size_t)j * Bc + col]; }, d);
+        const double2 sx = schur_row<UNI>(a, e, ca, cc, [&](int j) { return x[(size_t)j * Bc + col]; }, d);
         res = csub(res, sx);
       } else {
-        d = cadd(cscale(a.ops.mass[5 * e], ca), cscale(a.ops.graddiv[5 * e], cc));
+        d = cadd(cscale(rld<UNI>(a.ops.mass, 5 * e), ca), cscale(rld<UNI>(a.ops.graddiv, 5 * e), cc));
         a.x[ie] = make_double2(0.0, 0.0);
       }
       const double2 r = cdiv(res, d);
@@ -234,31 +293,36 @@ __global__ __launch_bounds__(kRWG) void k_rexi_fin_init(RexiArgs a, int nwg) {
   st.restarts[col] += 1;
 }
 
-// p' = r + beta (p - omega v) (p' = p on a fresh start), v' = D^-1 S p'.
-// Partials: (r~, v').
-__global__ __launch_bounds__(kRWG) void k_rexi_v(RexiArgs a, const double2 *p_in, const double2 *v_in,
-                                                   double2 *p_out, double2 *v_out) {
+// p' = r + beta (p - omega v) (p' = p on a fresh start): a streaming pass,
+// so that the operator application gathers one vector only.
+__global__ __launch_bounds__(kRWG) void k_rexi_p(RexiArgs a, const double2 *p_in, const double2 *v_in,
+                                                   double2 *p_out) {
   const RLane L = rlane(a.Bc, a.ops.ne);
+  const int col = L.col, Bc = a.Bc;
+  if (col >= a.ncols || !a.st.active[col]) return;
+  const bool fresh = a.st.fresh[col] != 0;
+  const double2 beta = a.st.beta[col], omega = a.st.omega[col];
+  for (int e = L.row0; e < L.rend; e += L.rstride) {
+    const size_t ie = (size_t)e * Bc + col;
+    p_out[ie] = fresh ? p_in[ie] : cadd(a.r[ie], cmul(beta, csub(p_in[ie], cmul(omega, v_in[ie]))));
+  }
+}
+
+// v' = D^-1 S p'.  Partials: (r~, v').
+template <bool UNI>
+__global__ __launch_bounds__(kRWG) void k_rexi_sv(RexiArgs a, const double2 *p_in, double2 *v_out) {
+  const RLane L = rlane_t<UNI>(a.Bc, a.ops.ne);
   const int col = L.col, Bc = a.Bc;
   const bool on = col < a.ncols && a.st.active[col];
   double v[2] = {0.0, 0.0};
   if (on) {
     const double2 ca = a.co.a[col], cc = a.co.c[col];
-    const bool fresh = a.st.fresh[col] != 0;
-    const double2 beta = a.st.beta[col], omega = a.st.omega[col];
-    const double2 *r = a.r;
-    auto pnew = [&](int j) {
-      const size_t ij = (size_t)j * Bc + col;
-      if (fresh) return p_in[ij];
-      return cadd(r[ij], cmul(beta, csub(p_in[ij], cmul(omega, v_in[ij]))));
-    };
-    for (int e = L.row0; e < L.rend; e += L.rstride) {
-      const size_t ie = (size_t)e * Bc + col;
+    for (int base = L.row0; base < L.rend; base += L.rstride) {
+      const int e = urow<UNI>(base);
       double2 d;
-      const double2 sp = schur_row(a, e, ca, cc, pnew, d);
+      const double2 sp = schur_row<UNI>(a, e, ca, cc, [&](int j) { return p_in[(size_t)j * Bc + col]; }, d);
       const double2 vv = cdiv(sp, d);
-      p_out[ie] = pnew(e);
-      v_out[ie] = vv;
+      v_out[(size_t)e * Bc + col] = vv;
       const double2 rv = cdotc(shadow(a.seed, e, col), vv);
       v[0] += rv.x;
       v[1] += rv.y;
@@ -278,12 +342,13 @@ __global__ __launch_bounds__(kRWG) void k_rexi_fin_v(RexiArgs a, int nwg) {
     a.st.active[col] = 0;
     return;
   }
-  a.st.alpha[col] = cdiv(a.st.rho[col], rv);
+  a.st.alpha[col] = cdiv_ieee(a.st.rho[col], rv);
 }
 
 // s = r - alpha v, t = D^-1 S s.  Partials: (t, s), |t|^2.
+template <bool UNI>
 __global__ __launch_bounds__(kRWG) void k_rexi_t(RexiArgs a, const double2 *v_in) {
-  const RLane L = rlane(a.Bc, a.ops.ne);
+  const RLane L = rlane_t<UNI>(a.Bc, a.ops.ne);
   const int col = L.col, Bc = a.Bc;
   const bool on = col < a.ncols && a.st.active[col];
   double v[3] = {0.0, 0.0, 0.0};
@@ -295,11 +360,12 @@ __global__ __launch_bounds__(kRWG) void k_rexi_t(RexiArgs a, const double2 *v_in
       const size_t ij = (size_t)j * Bc + col;
       return csub(r[ij], cmul(alpha, v_in[ij]));
     };
-    for (int e = L.row0; e < L.rend; e += L.rstride) {
+    for (int base = L.row0; base < L.rend; base += L.rstride) {
+      const int e = urow<UNI>(base);
       const size_t ie = (size_t)e * Bc + col;
       double2 d;
       const double2 ss = snew(e);
-      const double2 tt = cdiv(schur_row(a, e, ca, cc, snew, d), d);
+      const double2 tt = cdiv(schur_row<UNI>(a, e, ca, cc, snew, d), d);
       a.s[ie] = ss;
       a.t[ie] = tt;
       const double2 ts = cdotc(tt, ss);
@@ -366,7 +432,7 @@ __global__ __launch_bounds__(kRWG) void k_rexi_fin_x(RexiArgs a, int nwg) {
     atomicAdd(st.fail, 1);
     return;
   }
-  st.beta[col] = cmul(cdiv(rho_new, st.rho[col]), cdiv(st.alpha[col], omega));
+  st.beta[col] = cmul(cdiv_ieee(rho_new, st.rho[col]), cdiv_ieee(st.alpha[col], omega));
   st.rho[col] = rho_new;
 }
 
@@ -449,7 +515,7 @@ int rexi_grid(int ne, int Bc) {
   const int rows_per_pass = (kRWG / 64) * (64 / ct);
   const int tiles = (Bc + 63) / 64;
   int want = (ne + rows_per_pass - 1) / rows_per_pass;
-  int cap = 1024 / tiles;
+  int cap = 2048 / tiles;
   if (cap < 64) cap = 64;
   int g = want < cap ? want : cap;
   g = (g + 7) / 8 * 8;
@@ -462,22 +528,36 @@ int flat_grid(size_t n) {
   size_t g = (n + kRWG - 1) / kRWG;
   return (int)(g < 8192 ? (g > 0 ? g : 1) : 8192);
 }
+// the gather kernels run one row a wave for blocks of 64 or more columns (a
+// narrower block would leave lanes idle)
+bool uni(int Bc) { return Bc >= 64; }
 }  // namespace
 
 void launch_rexi_init(const RexiArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_rexi_init, rgrid(a.ops.ne, a.Bc), dim3(kRWG), 0, s, a, a.p);
+  if (uni(a.Bc))
+    hipLaunchKernelGGL(k_rexi_init<true>, rgrid(a.ops.ne, a.Bc), dim3(kRWG), 0, s, a, a.p);
+  else
+    hipLaunchKernelGGL(k_rexi_init<false>, rgrid(a.ops.ne, a.Bc), dim3(kRWG), 0, s, a, a.p);
 }
 void launch_rexi_fin_init(const RexiArgs &a, int nwg, hipStream_t s) {
   hipLaunchKernelGGL(k_rexi_fin_init, dim3(a.Bc), dim3(kRWG), 0, s, a, nwg);
 }
 void launch_rexi_v(const RexiArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_rexi_v, rgrid(a.ops.ne, a.Bc), dim3(kRWG), 0, s, a, a.p, a.v, a.p_next, a.v_next);
+  const dim3 g = rgrid(a.ops.ne, a.Bc);
+  hipLaunchKernelGGL(k_rexi_p, g, dim3(kRWG), 0, s, a, a.p, a.v, a.p_next);
+  if (uni(a.Bc))
+    hipLaunchKernelGGL(k_rexi_sv<true>, g, dim3(kRWG), 0, s, a, a.p_next, a.v_next);
+  else
+    hipLaunchKernelGGL(k_rexi_sv<false>, g, dim3(kRWG), 0, s, a, a.p_next, a.v_next);
 }
 void launch_rexi_fin_v(const RexiArgs &a, int nwg, hipStream_t s) {
   hipLaunchKernelGGL(k_rexi_fin_v, dim3(a.Bc), dim3(kRWG), 0, s, a, nwg);
 }
 void launch_rexi_t(const RexiArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_rexi_t, rgrid(a.ops.ne, a.Bc), dim3(kRWG), 0, s, a, a.v_next);
+  if (uni(a.Bc))
+    hipLaunchKernelGGL(k_rexi_t<true>, rgrid(a.ops.ne, a.Bc), dim3(kRWG), 0, s, a, a.v_next);
+  else
+    hipLaunchKernelGGL(k_rexi_t<false>, rgrid(a.ops.ne, a.Bc), dim3(kRWG), 0, s, a, a.v_next);
 }
 void launch_rexi_fin_t(const RexiArgs &a, int nwg, hipStream_t s) {
   hipLaunchKernelGGL(k_rexi_fin_t, dim3(a.Bc), dim3(kRWG), 0, s, a, nwg);
