@@ -45,9 +45,9 @@ def parse():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_refined"])
     ap.add_argument("--autotune", type=int, default=1)
     ap.add_argument("--precond", default="both", choices=["jacobi", "learned", "both"])
-    ap.add_argument("--forms", default="plain,fp32_refined,learned,hybrid,rexi",
+    ap.add_argument("--forms", default="plain,fp32_refined,learned,hybrid,rexi,rexi_learned",
                     help="comma-separated forms to time (of plain, fp32_refined, learned, "
-                         "hybrid, rexi)")
+                         "hybrid, rexi, rexi_learned)")
     ap.add_argument("--tune-cache", dest="tune_cache", default=None,
                     help="JSON file of launch shapes: read when it holds the problem, else written")
     ap.add_argument("--lp-steps", dest="lp_steps", type=int, default=200)
@@ -246,7 +246,7 @@ def bench_batch(args):
         lcfg = pa.solve_cfg(precond=pa.PA_PRECOND_LEARNED, **base)
         forms["learned"] = (lcfg, 1)
         forms["hybrid"] = (lcfg, None)
-    wanted = set(args.forms.split(",")) - {"rexi"}  # batches run the Chebyshev exponential
+    wanted = set(args.forms.split(",")) - {"rexi", "rexi_learned"}  # Chebyshev exponential only
     forms = {k: v for k, v in forms.items() if k in wanted}
     if not forms:
         raise SystemExit("no form selected")
@@ -335,7 +335,8 @@ def main():
         forms["rexi"] = (pa.solve_cfg(precond=pa.PA_PRECOND_JACOBI, exponential=pa.PA_EXP_REXI,
                                       **base), None)
     lp_rec = None
-    if args.precond in ("learned", "both") and {"learned", "hybrid"} & set(args.forms.split(",")):
+    if args.precond in ("learned", "both") and \
+            {"learned", "hybrid", "rexi_learned"} & set(args.forms.split(",")):
         # the network is trained on the GPU on meshes of levels 4 to 6 (this
         # workload's own operator among them) before the measurement
         lp, lp_rec = train_learned(pa, ctx, wl.phys, {wl.level: ops}, args.lp_steps)
@@ -344,6 +345,10 @@ def main():
         lcfg = pa.solve_cfg(precond=pa.PA_PRECOND_LEARNED, **base)
         forms["learned"] = (lcfg, 1)
         forms["hybrid"] = (lcfg, None)
+        # the rational exponential's shifted solves left-preconditioned by
+        # the learned P (scaled by each pole) instead of Jacobi
+        forms["rexi_learned"] = (pa.solve_cfg(precond=pa.PA_PRECOND_LEARNED,
+                                              exponential=pa.PA_EXP_REXI, **base), None)
     wanted = set(args.forms.split(","))
     forms = {k: v for k, v in forms.items() if k in wanted}
     if not forms:
@@ -431,9 +436,12 @@ def main():
                                    rexi_iterations_max=st["rexi_iters_max"],
                                    rexi_restarts=st["rexi_restarts"],
                                    rexi_resid_max=st["rexi_resid_max"])
-    for name in ("learned", "hybrid", "fp32_refined"):
+    for name in ("learned", "hybrid", "fp32_refined", "rexi", "rexi_learned"):
         if name in forms_rec and "plain" in forms_rec:
             forms_rec[f"{name}_over_plain"] = forms_rec[name]["value"] / forms_rec["plain"]["value"]
+    if "rexi_learned" in forms_rec and "rexi" in forms_rec:
+        forms_rec["rexi_learned_over_rexi"] = (forms_rec["rexi_learned"]["value"] /
+                                               forms_rec["rexi"]["value"])
     rec = {
         "metric": "phase-avg RHS evals/s (L6 mesh, M=64); learned vs plain at 1e-10 resid",
         "value": value,

@@ -239,6 +239,8 @@ class Engine {
     int *active = nullptr, *iters = nullptr, *fresh = nullptr, *restarts = nullptr, *fail = nullptr;
     double2 *Y = nullptr, *r = nullptr, *p[2] = {nullptr, nullptr}, *v[2] = {nullptr, nullptr};
     double2 *s = nullptr, *t = nullptr;
+    bool learned = false;  // left preconditioner P / X (else Jacobi)
+    double2 *w = nullptr;  // learned form: the unpreconditioned vector
   };
   struct RexiExp {
     int B = 0, Bs = 0;

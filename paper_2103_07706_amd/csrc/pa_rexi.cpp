@@ -183,6 +183,14 @@ void Engine::rexi_plan(RexiSys &rs, double theta_max, int members) {
   rs.v[1] = ar_.take<double2>(eb);
   rs.s = ar_.take<double2>(eb);
   rs.t = ar_.take<double2>(eb);
+  // learned left preconditioner P / X (P the learned approximate inverse of
+  // M_u bound to the operators) instead of Jacobi
+  rs.learned = cfg_.precond == PA_PRECOND_LEARNED;
+  if (rs.learned) {
+    if (!ops_->lp_ready || !ops_->lp_dev)
+      throw Error(PA_EINVAL, "no learned preconditioner bound to the operators");
+    rs.w = ar_.take<double2>(eb);
+  }
   rs.nwg = rexi_grid(ne_, rs.Bc);
   rs.part = ar_.take<double>((size_t)rs.nwg * 4 * bc);
 }
@@ -228,6 +236,9 @@ void Engine::rexi_solve(RexiSys &rs, const RexiSrc &src) {
   a.max_wg = rs.nwg;
   a.st = RexiState{rs.rho, rs.alpha, rs.omega, rs.beta, rs.bb, rs.ff, rs.tau2, rs.res2,
                    rs.active, rs.iters, rs.fresh, rs.restarts, rs.fail};
+  a.lp = rs.learned ? ops_->lp.p : nullptr;
+  a.lpw = rs.learned ? ops_->lp.wp : 0;
+  a.w = rs.w;
   a.seed = 0x5eed;
   a.rtol2 = cfg_.cg_rtol * cfg_.cg_rtol;
   a.maxit = cfg_.maxit;
@@ -242,6 +253,7 @@ void Engine::rexi_solve(RexiSys &rs, const RexiSrc &src) {
   bind();
   a.mode = 0;
   launch_rexi_init(a, s_);
+  if (a.lp) launch_rexi_lp(a, 0, s_);
   launch_rexi_fin_init(a, rs.nwg, s_);
   std::vector<int> act(rs.Bc);
   auto any_active = [&] {
@@ -258,8 +270,10 @@ void Engine::rexi_solve(RexiSys &rs, const RexiSrc &src) {
     for (int k = 0; k < chunk && launched < cfg_.maxit; k++, launched++) {
       bind();
       launch_rexi_v(a, s_);
+      if (a.lp) launch_rexi_lp(a, 1, s_);
       launch_rexi_fin_v(a, rs.nwg, s_);
       launch_rexi_t(a, s_);
+      if (a.lp) launch_rexi_lp(a, 2, s_);
       launch_rexi_fin_t(a, rs.nwg, s_);
       launch_rexi_x(a, s_);
       launch_rexi_fin_x(a, rs.nwg, s_);
@@ -273,6 +287,7 @@ void Engine::rexi_solve(RexiSys &rs, const RexiSrc &src) {
     bind();
     a.mode = 1;
     launch_rexi_init(a, s_);
+    if (a.lp) launch_rexi_lp(a, 0, s_);
     launch_rexi_fin_init(a, rs.nwg, s_);
     more = any_active() && launched < cfg_.maxit;
     chunk = 4;
@@ -294,6 +309,10 @@ void Engine::rexi_solve(RexiSys &rs, const RexiSrc &src) {
     if (f2[c] > 0) stats.rexi_resid_max = std::max(stats.rexi_resid_max, std::sqrt(r2[c] / f2[c]));
   }
   stats.rexi_solves++;
+  if (rs.learned) {
+    stats.precond = PA_PRECOND_LEARNED;
+    stats.lp_solves++;
+  }
   stats.rexi_iters += imax;
   stats.rexi_iters_max = std::max(stats.rexi_iters_max, imax);
   if (ctx_) ctx_->rexi_pred = std::max(2, imax);

@@ -55,6 +55,13 @@ struct RexiArgs {
   double *part;                    // per-workgroup partials [wg][nq][Bc]
   int max_wg;
   RexiState st;
+  // left preconditioner: D^-1 (Jacobi, lp == nullptr) or P / X with P the
+  // learned approximate inverse of M_u (column-major ELL [slot][row] of
+  // packed (column, FP32 value), lpw slots).  With P the gathering kernels
+  // write the unpreconditioned vector to w and k_rexi_lp applies P / X.
+  const uint2 *lp;
+  int lpw;
+  double2 *w;
   uint32_t seed;   // shadow residual (a counter hash of row and column)
   int mode;        // init kernel: 0 start from x = 0, 1 check and restart
   double rtol2;    // squared relative tolerance of the true residual
@@ -101,6 +108,10 @@ void launch_rexi_t(const RexiArgs &a, hipStream_t s);
 void launch_rexi_fin_t(const RexiArgs &a, int nwg, hipStream_t s);
 void launch_rexi_x(const RexiArgs &a, hipStream_t s);
 void launch_rexi_fin_x(const RexiArgs &a, int nwg, hipStream_t s);
+// y = P w / X into the kernel's output with its partials (learned form):
+// kind 0 after init (r = y, p = y; |w|^2, |y|^2, (r~, y)), 1 after the
+// direction product (v_next = y; (r~, y)), 2 after s (t = y; (y, s), |y|^2)
+void launch_rexi_lp(const RexiArgs &a, int kind, hipStream_t s);
 int rexi_grid(int ne, int Bc);  // workgroups of the row kernels
 void launch_rexi_eta(const RexiEtaArgs &a, hipStream_t s);
 void launch_rexi_combine(const RexiCombineArgs &a, hipStream_t s);

@@ -77,6 +77,15 @@ __device__ inline T rld(const T *p, size_t i) {
     return p[i];
 }
 template <bool UNI>
+__device__ inline uint2 rld(const uint2 *p, size_t i) {
+  if constexpr (UNI) {
+    const unsigned long long v = ((const __attribute__((address_space(4))) unsigned long long *)p)[i];
+    return make_uint2((unsigned)v, (unsigned)(v >> 32));
+  } else {
+    return p[i];
+  }
+}
+template <bool UNI>
 __device__ inline int urow(int e) {
   return UNI ? __builtin_amdgcn_readfirstlane(e) : e;
 }
@@ -238,6 +247,10 @@ __global__ __launch_bounds__(kRWG) void k_rexi_init(RexiArgs a, double2 *p_out) 
         d = cadd(cscale(rld<UNI>(a.ops.mass, 5 * e), ca), cscale(rld<UNI>(a.ops.graddiv, 5 * e), cc));
         a.x[ie] = make_double2(0.0, 0.0);
       }
+      if (a.lp) {  // k_rexi_lp forms r = P res / X and the partials
+        a.w[ie] = res;
+        continue;
+      }
       const double2 r = cdiv(res, d);
       a.r[ie] = r;
       p_out[ie] = r;
@@ -321,6 +334,10 @@ __global__ __launch_bounds__(kRWG) void k_rexi_sv(RexiArgs a, const double2 *p_i
       const int e = urow<UNI>(base);
       double2 d;
       const double2 sp = schur_row<UNI>(a, e, ca, cc, [&](int j) { return p_in[(size_t)j * Bc + col]; }, d);
+      if (a.lp) {
+        a.w[(size_t)e * Bc + col] = sp;
+        continue;
+      }
       const double2 vv = cdiv(sp, d);
       v_out[(size_t)e * Bc + col] = vv;
       const double2 rv = cdotc(shadow(a.seed, e, col), vv);
@@ -365,7 +382,13 @@ __global__ __launch_bounds__(kRWG) void k_rexi_t(RexiArgs a, const double2 *v_in
       const size_t ie = (size_t)e * Bc + col;
       double2 d;
       const double2 ss = snew(e);
-      const double2 tt = cdiv(schur_row<UNI>(a, e, ca, cc, snew, d), d);
+      const double2 ws = schur_row<UNI>(a, e, ca, cc, snew, d);
+      if (a.lp) {
+        a.s[ie] = ss;
+        a.w[ie] = ws;
+        continue;
+      }
+      const double2 tt = cdiv(ws, d);
       a.s[ie] = ss;
       a.t[ie] = tt;
       const double2 ts = cdotc(tt, ss);
@@ -434,6 +457,58 @@ __global__ __launch_bounds__(kRWG) void k_rexi_fin_x(RexiArgs a, int nwg) {
   }
   st.beta[col] = cmul(cdiv_ieee(rho_new, st.rho[col]), cdiv_ieee(st.alpha[col], omega));
   st.rho[col] = rho_new;
+}
+
+// Learned left preconditioner: y = P w / X (P real, FP32 values, FP64
+// arithmetic), then the partials the Jacobi kernels would have formed.
+template <bool UNI>
+__global__ __launch_bounds__(kRWG) void k_rexi_lp(RexiArgs a, int kind, double2 *y_out, double2 *p_out) {
+  const RLane L = rlane_t<UNI>(a.Bc, a.ops.ne);
+  const int col = L.col, Bc = a.Bc, ne = a.ops.ne;
+  const bool on = col < a.ncols && (kind == 0 || a.st.active[col]);
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  if (on) {
+    const double2 xinv = a.co.xinv[col];
+    for (int base = L.row0; base < L.rend; base += L.rstride) {
+      const int e = urow<UNI>(base);
+      const size_t ie = (size_t)e * Bc + col;
+      double2 z = make_double2(0.0, 0.0);
+      for (int k = 0; k < a.lpw; k++) {
+        const uint2 q = rld<UNI>(a.lp, (size_t)k * ne + e);
+        const double pv = (double)__uint_as_float(q.y);
+        const double2 wv = a.w[(size_t)q.x * Bc + col];
+        z.x = fma(pv, wv.x, z.x);
+        z.y = fma(pv, wv.y, z.y);
+      }
+      const double2 y = cmul(xinv, z);
+      y_out[ie] = y;
+      const double2 sh = cdotc(shadow(a.seed, e, col), y);
+      if (kind == 0) {
+        p_out[ie] = y;
+        v[0] += cabs2(a.w[ie]);
+        v[1] += cabs2(y);
+        v[2] += sh.x;
+        v[3] += sh.y;
+      } else if (kind == 1) {
+        v[0] += sh.x;
+        v[1] += sh.y;
+      } else {
+        const double2 ts = cdotc(y, a.s[ie]);
+        v[0] += ts.x;
+        v[1] += ts.y;
+        v[2] += cabs2(y);
+      }
+    }
+  }
+  if (kind == 0) {
+    rexi_partials<4>(L, v, a.part, a.Bc);
+  } else if (kind == 1) {
+    double u[2] = {v[0], v[1]};
+    rexi_partials<2>(L, u, a.part, a.Bc);
+  } else {
+    double u[3] = {v[0], v[1], v[2]};
+    rexi_partials<3>(L, u, a.part, a.Bc);
+  }
 }
 
 // Depth rows: y_eta = xinv src_eta + h (D y_u) / |c|.
@@ -538,6 +613,13 @@ void launch_rexi_init(const RexiArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_rexi_init<true>, rgrid(a.ops.ne, a.Bc), dim3(kRWG), 0, s, a, a.p);
   else
     hipLaunchKernelGGL(k_rexi_init<false>, rgrid(a.ops.ne, a.Bc), dim3(kRWG), 0, s, a, a.p);
+}
+void launch_rexi_lp(const RexiArgs &a, int kind, hipStream_t s) {
+  double2 *y = kind == 0 ? a.r : kind == 1 ? a.v_next : a.t;
+  if (uni(a.Bc))
+    hipLaunchKernelGGL(k_rexi_lp<true>, rgrid(a.ops.ne, a.Bc), dim3(kRWG), 0, s, a, kind, y, a.p);
+  else
+    hipLaunchKernelGGL(k_rexi_lp<false>, rgrid(a.ops.ne, a.Bc), dim3(kRWG), 0, s, a, kind, y, a.p);
 }
 void launch_rexi_fin_init(const RexiArgs &a, int nwg, hipStream_t s) {
   hipLaunchKernelGGL(k_rexi_fin_init, dim3(a.Bc), dim3(kRWG), 0, s, a, nwg);
