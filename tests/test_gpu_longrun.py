@@ -40,6 +40,69 @@ def test_gpu_level5_24h_drift():
     assert abs(log[-1][2]) < 0.05
 
 
+def _golden_longrun():
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "longrun_level5_m32_24h.txt")
+    scal, rows = {}, []
+    for line in open(path):
+        if line.startswith("#"):
+            continue
+        f = line.split()
+        if f[0] in ("e", "c"):
+            rows.append((f[0], int(f[1]), float(f[2]), float(f[3]), float(f[4]), float(f[5])))
+        else:
+            scal[f[0]] = float(f[1])
+    return scal, rows
+
+
+def test_gpu_level5_24h_against_oracle():
+    """The same 24-hour run against the oracle's (tests/golden/
+    longrun_level5_m32_24h.txt, written by make_longrun_golden.py from the
+    oracle alone, at the same tolerances and lambda_bar): the final state at
+    every 64th edge and cell (matched by geometry) and its diagnostics.  Both
+    sides truncate each exponential at 1e-6 and solve to 1e-10, so they
+    differ by the solves' rounding, carried through 24 steps; the difference
+    is logged and bounded."""
+    import oracle
+    from paper_2103_07706_amd import inputs, pa
+    from gpu_common import _ctx
+    from matching import MeshMap
+    scal, rows = _golden_longrun()
+    wl = inputs.WORKLOADS["l5_m32"]
+    om = oracle.Mesh(wl.level)
+    mesh = pa.Mesh(wl.level)
+    mm = MeshMap(om, mesh)
+    ops = pa.Ops(_ctx(), mesh, g=wl.phys.g, H=wl.phys.H, omega=wl.phys.omega)
+    ops.lambda_bar = scal["lambda_bar"]
+    U0 = inputs.gaussian_bumps_state(om.verts, om.cell_verts, om.edge_verts, wl.nbumps, 0,
+                                     wl.phys)
+    U = to_dev(mm.state(U0)[None, :])
+    avg = pa.Avg(wl.M, wl.T)
+    cfg = pa.solve_cfg(backward=pa.PA_BACKWARD_CLENSHAW, cheb_tol=1e-6, cg_rtol=1e-10)
+    for _ in range(wl.steps):
+        ops.step(avg, wl.dt, U, cfg)
+    got = mm.back(U.cpu().numpy()[0])
+    ne = om.ne
+    eu = np.array([got[i] for k, i, *_ in rows if k == "e"])
+    ru = np.array([r[-1] for r in rows if r[0] == "e"])
+    ee = np.array([got[ne + i] for k, i, *_ in rows if k == "c"])
+    re_ = np.array([r[-1] for r in rows if r[0] == "c"])
+    # the stored geometry is the oracle's numbering: check it is the same mesh
+    mid = 0.5 * (om.verts[om.edge_verts[:, 0]] + om.verts[om.edge_verts[:, 1]])
+    for k, i, x, y, z, _ in rows[:50]:
+        if k == "e":
+            assert np.allclose(mid[i], (x, y, z), rtol=0, atol=1e-6 * om.radius)
+    du = np.abs(eu - ru).max() / np.abs(ru).max()
+    de = np.abs(ee - re_).max() / np.abs(re_).max()
+    d = ops.diagnostics(U)[0]
+    dm = abs(d[0] / scal["final_mass"] - 1)
+    dE = abs(d[2] / scal["final_energy_nonlinear"] - 1)
+    print(f"24 h, level 5, against the oracle: max-norm u {du:.3e}, eta {de:.3e}; "
+          f"mass {dm:.3e}, nonlinear energy {dE:.3e}")
+    assert du < 1e-6 and de < 1e-6
+    assert dE < 1e-8
+
+
 @pytest.mark.parametrize("use_graph", [False, True])
 def test_gpu_growth_guard(use_graph):
     """With lambda_bar at half the spectral radius the Chebyshev basis grows

@@ -1,0 +1,107 @@
+"""Pins of the oracle's BDM2/P1DG linear operator (Sec. 2.5, the paper's
+own pair of spaces; oracle/bdm2.py).
+
+Against: the structure the spaces must give (W L skew, so a purely
+imaginary spectrum; the divergence of a continuous normal field integrates
+to zero, so constant depth is untouched), closed forms under refinement
+(the kinetic energy of solid-body rotation on the sphere, the frequency
+sqrt(2 g H)/R of the gravest gravity mode without rotation), and the
+numbers printed in Table 1: the Chebyshev degrees the paper needed at
+levels 3 and 4, which depend on the discretisation only through the
+spectral radius of L.  A wrong sign between the two cells of an edge, a
+transposed divergence, a dropped area factor or a wrong interior moment
+breaks the structure or the convergence; a basis that spans less than BDM2
+moves the spectral radius far from Table 1.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.bdm2 import BDM2P1DG
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+R = 6.37122e6
+
+
+def _K(theta, tol=1e-6):
+    a = oracle.cheb_coeffs(theta, 2 * int(np.ceil(theta)) + 64)
+    return oracle.cheb_truncate(a, tol)
+
+
+@pytest.fixture(scope="module")
+def bdm(oracle_mesh):
+    cache = {}
+
+    def get(level, **kw):
+        key = (level, tuple(sorted(kw.items())))
+        if key not in cache:
+            cache[key] = BDM2P1DG(oracle_mesh(level), **kw)
+        return cache[key]
+    return get
+
+
+def test_bdm2_structure(bdm):
+    b = bdm(2)
+    WL = b.WL()
+    assert abs(WL + WL.T).max() <= 1e-14 * abs(WL).max()
+    assert abs(b.Mu - b.Mu.T).max() <= 1e-14 * abs(b.Mu).max()
+    # 12 velocity and 3 depth dofs a cell, counted once per edge and cell
+    assert b.nu == 3 * b.mesh.ne + 3 * b.mesh.nc and b.nh == 3 * b.mesh.nc
+    # constant depth: sum of the divergence over the sphere vanishes
+    assert np.abs(b.B @ np.ones(b.nh)).max() <= 1e-14 * abs(b.B).max()
+    # M_u positive definite (Cholesky-free check: Rayleigh quotients of
+    # random vectors and of the basis vectors)
+    x = np.random.default_rng(0).standard_normal((b.nu, 4))
+    assert np.all(np.einsum("ij,ij->j", x, b.Mu @ x) > 0)
+    assert np.all(b.Mu.diagonal() > 0)
+
+
+def test_bdm2_solid_body_energy_converges(bdm):
+    """u = (u0/R)(-y, x, 0): int |u|^2 over the sphere = 8 pi/3 u0^2 R^2;
+    the flat triangles and the interpolation make a second-order error."""
+    u0 = 20.0
+    errs = []
+    for lev in (1, 2, 3):
+        b = bdm(lev, Omega=0.0)
+        u = b.interpolate(lambda x: u0 / R * np.stack([-x[..., 1], x[..., 0], 0 * x[..., 0]], -1))
+        errs.append(abs((u @ (b.Mu @ u)) / (8 * np.pi / 3 * u0 ** 2 * R ** 2) - 1))
+    assert errs[-1] < 0.02
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5, errs
+
+
+def test_bdm2_gravest_gravity_mode_converges(bdm):
+    """Without rotation the lowest nonzero frequency of L tends to that of
+    the degree-1 spherical harmonic, sqrt(2 g H)/R, at second order."""
+    g, H = 9.80616, 1000.0
+    w1 = np.sqrt(2 * g * H) / R
+    errs = [abs(bdm(lev, g=g, H=H, Omega=0.0).frequency_near(w1) / w1 - 1) for lev in (1, 2, 3)]
+    assert errs[-1] < 5e-3
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5, errs
+
+
+def test_bdm2_spectral_radius_against_table1(bdm):
+    """Table 1 (golden table1_chebyshev_iterations.txt): the Chebyshev
+    iteration counts (degree - 1 by the truncation reading) for the test
+    case's physics (H = 5960 m, g = 9.8) at 15, 30 and 60 minutes.  With
+    theta = rho(L) ds from this oracle's BDM2/P1DG operator on flat
+    triangles: level 3 gives 10, 15, 23 against 10, 15, 24; level 4 gives
+    15, 23, 37 against 16, 25, 41.  The printed counts correspond to a
+    spectral radius 4-12% above this one (the paper's curved cells and its
+    estimate of lambda_max are not reproduced); the lowest-order pair
+    (RT0/P0) is about half of it (7, 10, 16 at level 3)."""
+    rows = {int(r[0]): r[1:] for r in np.loadtxt(os.path.join(GOLDEN,
+                                                              "table1_chebyshev_iterations.txt"),
+                                                 dtype=int)}
+    for lev, tol in ((3, 1), (4, 4)):
+        b = bdm(lev, g=9.8, H=5960.0)
+        rho = b.rho()
+        counts = np.array([_K(rho * ds) - 1 for ds in (900.0, 1800.0, 3600.0)])
+        print(f"level {lev}: rho {rho:.5e}, counts {counts.tolist()}, Table 1 {rows[lev].tolist()}")
+        assert np.abs(counts - rows[lev]).max() <= tol
+        assert np.all(counts <= rows[lev])
+    # the lowest-order pair needs far fewer: rho about half at level 3
+    om = oracle.Mesh(3)
+    rt0 = oracle.lambda_bar(oracle.Ops(om, g=9.8, H=5960.0), iters=300, factor=1.0)
+    assert 0.5 < rt0 / bdm(3, g=9.8, H=5960.0).rho() < 0.6
