@@ -60,9 +60,10 @@ def test_gpu_level5_24h_against_oracle():
     longrun_level5_m32_24h.txt, written by make_longrun_golden.py from the
     oracle alone, at the same tolerances and lambda_bar): the final state at
     every 64th edge and cell (matched by geometry) and its diagnostics.  Both
-    sides truncate each exponential at 1e-6 and solve to 1e-10, so they
-    differ by the solves' rounding, carried through 24 steps; the difference
-    is logged and bounded."""
+    sides truncate each exponential at 1e-6 (at the same degrees: the same
+    lambda_bar) and solve to 1e-10, so they differ by the solves' residuals
+    and rounding, carried through 24 steps; the difference is logged and
+    bounded."""
     import oracle
     from paper_2103_07706_amd import inputs, pa
     from gpu_common import _ctx
@@ -99,8 +100,10 @@ def test_gpu_level5_24h_against_oracle():
     dE = abs(d[2] / scal["final_energy_nonlinear"] - 1)
     print(f"24 h, level 5, against the oracle: max-norm u {du:.3e}, eta {de:.3e}; "
           f"mass {dm:.3e}, nonlinear energy {dE:.3e}")
-    assert du < 1e-6 and de < 1e-6
-    assert dE < 1e-8
+    # measured on MI355X: 3.5e-12 and 4.0e-12 (both sides truncate every
+    # exponential at the same degree; the solves differ only in rounding)
+    assert du < 1e-9 and de < 1e-9
+    assert dE < 1e-10
 
 
 @pytest.mark.parametrize("use_graph", [False, True])
