@@ -75,8 +75,11 @@ def per_dispatch(d, counter, name_filter=None):
     return list(acc.values())
 
 
-def kernel_source_hash():
-    src = os.path.join(ROOT, "paper_2103_07706_amd", "csrc", "pa_kernels.hip")
+def kernel_source_hash(kernel="k_cheb_fused"):
+    """Hash of the HIP source that defines the kernel."""
+    srcs = sorted(glob.glob(os.path.join(ROOT, "paper_2103_07706_amd", "csrc", "*.hip")))
+    src = next((f for f in srcs if f" {kernel}(" in open(f).read()),
+               os.path.join(ROOT, "paper_2103_07706_amd", "csrc", "pa_kernels.hip"))
     return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
 
 
@@ -93,7 +96,7 @@ def summarize(a):
     fb = statistics.mean(fetch) * 1024.0 * f_fetch
     wb = statistics.mean(write) * 1024.0 * f_write
     rec = {"kernel": a.kernel, "workload": a.workload, "backward": a.backward, "form": a.form,
-           "kernel_source_sha256_16": kernel_source_hash(),
+           "kernel_source_sha256_16": kernel_source_hash(a.kernel),
            "dispatches": len(fetch), "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
            "hbm_bytes_per_launch": fb + wb,
            "copy_calibration": {"bytes_each_way": COPY_BYTES,
