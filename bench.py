@@ -53,6 +53,10 @@ def parse():
     ap.add_argument("--lp-steps", dest="lp_steps", type=int, default=200)
     ap.add_argument("--cpu-baseline", dest="cpu", type=int, default=1)
     ap.add_argument("--cpu-terms", type=int, default=32)
+    ap.add_argument("--secondary", type=int, default=1,
+                    help="also time the ensemble (level 5, 64 members) and the mixed batch "
+                         "(levels 4/5/6) with the FP32-refined and plain forms, reported under "
+                         "'secondary' (not the headline value)")
     return ap.parse_args()
 
 
@@ -204,6 +208,63 @@ def train_learned(pa, ctx, phys, have, steps):
     rec = {"train_levels": [o.mesh.level for o in train_ops], "train_steps": steps,
            "train_ms": tst["ms"], "loss_first": tst["loss_first"], "loss_last": tst["loss_last"]}
     return lp, rec
+
+
+def secondary_workloads(pa, ctx, steps=3, warmup=1):
+    """Member-Nbar/s of the ensemble workload (level 5, 64 members, M = 64)
+    and of the mixed batch (levels 4/5/6 with 16/8/4 members, one graph),
+    in the FP32-refined and plain FP64 forms with the library's default
+    launch shape (no autotuning), graph replay, metric tolerances."""
+    import numpy as np
+    import torch
+
+    from paper_2103_07706_amd import inputs
+    out = {}
+    forms = {"fp32_refined": pa.solve_cfg(precision=pa.PA_FP32_REFINED),
+             "plain": pa.solve_cfg()}
+    wl = inputs.WORKLOADS["l5_m64_x64"]
+    mesh = pa.Mesh(wl.level)
+    ops = pa.Ops(ctx, mesh, g=wl.phys.g, H=wl.phys.H, omega=wl.phys.omega)
+    ops.estimate_lambda(iters=200, safety=1.05)
+    U = torch.tensor(np.stack([inputs.gaussian_bumps_state(
+        mesh.verts, mesh.cell_verts, mesh.edge_verts, wl.nbumps, m, wl.phys)
+        for m in range(wl.members)]), dtype=torch.float64, device="cuda:0")
+    avg = pa.Avg(wl.M, wl.T)
+    res = {}
+    for name, cfg in forms.items():
+        el, st = measure(ops, avg, U, cfg, torch.empty_like(U), steps, warmup)
+        res[name] = {"value": wl.members * steps / el, "ms_per_step": 1e3 * el / steps,
+                     "resid_max": st["resid_max"]}
+    out["l5_m64_x64"] = {"unit": "member-Nbar/s", "members": wl.members, "level": wl.level,
+                         "M": wl.M, "forms": res}
+    del ops, U
+    items = inputs.BATCHES["mixed_l4l5l6"]
+    phys = inputs.Physics()
+    bops, Us = [], []
+    for lev, mem in items:
+        m = pa.Mesh(lev)
+        o = pa.Ops(ctx, m, g=phys.g, H=phys.H, omega=phys.omega)
+        o.estimate_lambda(iters=200, safety=1.05)
+        bops.append(o)
+        Us.append(torch.tensor(np.stack([inputs.gaussian_bumps_state(
+            m.verts, m.cell_verts, m.edge_verts, 40, k, phys) for k in range(mem)]),
+            dtype=torch.float64, device="cuda:0"))
+    batch = pa.Batch(ctx, [(o, mm) for o, (_, mm) in zip(bops, items)], pa.Avg(64, 7200.0))
+    outs = [torch.empty_like(u) for u in Us]
+    members = sum(mm for _, mm in items)
+    res = {}
+    for name, cfg in forms.items():
+        for _ in range(warmup):
+            batch.run(Us, cfg, outs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            batch.run(Us, cfg, outs)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        res[name] = {"value": members * steps / el, "ms_per_step": 1e3 * el / steps}
+    out["mixed_l4l5l6"] = {"unit": "member-Nbar/s", "items": items, "M": 64, "forms": res}
+    return out
 
 
 def bench_batch(args):
@@ -477,6 +538,9 @@ def main():
                      "compulsory_achieved": compulsory,
                      "compulsory_frac": compulsory / HBM_PEAK_GBS},
     }
+    if args.secondary and args.workload == "l6_m64":
+        print("secondary workloads ...", file=sys.stderr, flush=True)
+        rec["secondary"] = secondary_workloads(pa, ctx)
     if args.cpu:
         print("oracle sample ...", file=sys.stderr, flush=True)
         smp = oracle_sample(wl, lam, args.cpu_terms)
