@@ -248,3 +248,28 @@ class BDM2P1DG:
             x /= np.sqrt(np.real(np.vdot(x, W @ x)))
         mu = np.vdot(x, WL @ x) / np.vdot(x, W @ x)
         return float(np.imag(mu))
+
+    def expL(self, lambda_bar, t, U, tol=1e-13):
+        """exp(t L) U by the paper's modified Chebyshev recurrence (Sec. 2.4,
+        eq. cheby) in its complex form as printed, Lbar = lambda_bar |t|,
+        coefficients by the oracle's discrete cosine transform and
+        truncation (om_cheb_coeffs, om_cheb_truncate); every L application
+        solves the two mass matrices exactly (sparse LU).  Returns (result,
+        degree)."""
+        import oracle
+        U = np.asarray(U, dtype=float)
+        if t == 0.0:
+            return U.copy(), 0
+        Lbar = lambda_bar * abs(t)
+        a = oracle.cheb_coeffs(Lbar, 2 * int(np.ceil(Lbar)) + 64)
+        K = oracle.cheb_truncate(a, tol)
+        Lc = lambda X: self.apply_L(X.real) + 1j * self.apply_L(X.imag)
+        Pm = None
+        P = U.astype(complex)
+        acc = a[0] * P
+        for k in range(K):
+            LP = Lc(P)
+            nxt = -1j * t * LP / Lbar if k == 0 else 2.0 * t * LP / (1j * Lbar) - Pm
+            Pm, P = P, nxt
+            acc = acc + a[k + 1] * nxt
+        return acc.real, K

@@ -105,3 +105,25 @@ def test_bdm2_spectral_radius_against_table1(bdm):
     om = oracle.Mesh(3)
     rt0 = oracle.lambda_bar(oracle.Ops(om, g=9.8, H=5960.0), iters=300, factor=1.0)
     assert 0.5 < rt0 / bdm(3, g=9.8, H=5960.0).rho() < 0.6
+
+
+def test_bdm2_expL_against_dense_exponential(bdm):
+    """The oracle's Chebyshev exponential on this operator against the dense
+    matrix exponential (scipy.linalg.expm of L assembled column by column)
+    at level 0, for both signs of t and a degree in the tens; and the energy
+    norm (W inner product, in which L is skew) is conserved."""
+    import scipy.linalg as sla
+    b = bdm(0)
+    n = b.n
+    L = np.column_stack([b.apply_L(e) for e in np.eye(n)])
+    lb = 1.05 * b.rho()
+    U = np.random.default_rng(5).standard_normal(n)
+    W = b.W()
+    for t in (7200.0, -3000.0):
+        got, K = b.expL(lb, t, U, tol=1e-13)
+        ref = sla.expm(t * L) @ U
+        assert K > 10
+        assert np.abs(got - ref).max() <= 1e-11 * np.abs(ref).max(), (t, np.abs(got - ref).max())
+        assert abs(got @ (W @ got) / (U @ (W @ U)) - 1) < 1e-11
+    got, K = b.expL(lb, 0.0, U)
+    assert K == 0 and np.array_equal(got, U)
