@@ -52,6 +52,7 @@ typedef struct pa_ctx pa_ctx;
 typedef struct pa_mesh pa_mesh;
 typedef struct pa_ops pa_ops;
 typedef struct pa_avg pa_avg;
+typedef struct pa_bdm2 pa_bdm2;
 
 /* ---- context -------------------------------------------------------------
  * Binds a device and a stream (hipStream_t, may be NULL for the null stream).
@@ -77,6 +78,16 @@ int pa_mesh_get_info(const pa_mesh *m, pa_mesh_info *info);
  * cell_edges[nc*3], edge_cells[ne*2], edge_verts[ne*2]. */
 int pa_mesh_export(const pa_mesh *m, double *verts, int32_t *cell_verts,
                    int32_t *cell_edges, int32_t *edge_cells, int32_t *edge_verts);
+/* A mesh from the caller's host arrays (copied; same layout as
+ * pa_mesh_export): verts[nv*3] on the sphere of the given radius,
+ * cell_verts[nc*3], cell_edges[nc*3], edge_cells[ne*2], edge_verts[ne*2].
+ * Checked against every convention above (closed, 2 ne = 3 nc; cells
+ * counter-clockwise from outside; edge i of a cell joins its vertices
+ * i+1 -> i+2; c0 < c1; a -> b counter-clockwise around c0); PA_EINVAL
+ * otherwise.  pa_mesh_get_info reports level -1. */
+int pa_mesh_from_arrays(int nv, const double *verts, int nc, const int32_t *cell_verts,
+                        int ne, const int32_t *cell_edges, const int32_t *edge_cells,
+                        const int32_t *edge_verts, double radius, pa_mesh **out);
 int pa_mesh_destroy(pa_mesh *m);
 
 /* ---- operators (Sec. 2.5: discrete L and N) ------------------------------
@@ -535,6 +546,75 @@ int pa_batch_autotune(pa_ctx *ctx, pa_batch *b, const double *const *U_dev,
                       double *const *Nbar_dev, void *ws_dev, size_t ws_bytes,
                       const pa_solve_cfg *cfg, pa_launch_tune *out);
 int pa_batch_destroy(pa_batch *b);
+
+/* ---- the paper's own spaces: BDM2 velocity x P1DG depth (Sec. 2.5) -------
+ * The linear operator of eq. ueq_int and the depth equation after it,
+ *   L(u, eta) = (M_u^-1 (-F u + g B eta), M_h^-1 (-H B^T u)),
+ * M_u[i,j] = int phi_i . phi_j, F[i,j] = int phi_i . (f k x phi_j)
+ * (f = 2 omega z/|x| at the quadrature points), B[i,q] = int div(phi_i) psi_q,
+ * M_h[q,r] = int psi_q psi_r, on the flat cells of a mesh, and exp(t L) U by
+ * the Chebyshev polynomial of Sec. 2.4 on it.  Unknowns of a state (length
+ * nu + nh, velocity first):
+ *   3 e + k      the normal component of u at Gauss-Legendre point k of edge
+ *                e (points from the edge's a to its b; the normal in the
+ *                plane of cell c0, pointing out of c0),
+ *   3 ne + 3 c + m  the interior moments of cell c: the integrals of u . e1
+ *                and u . e2 over the cell divided by its area A, and of
+ *                u . (x - x_c)^perp divided by A^1.5 (e1 = unit vector from
+ *                the cell's vertex 0 to vertex 1, e2 = k x e1, x_c the
+ *                centroid, perp a quarter turn about k),
+ *   nu + 3 c + q the coefficient of the barycentric coordinate of the
+ *                cell's vertex q in the depth.
+ * nu = 3 ne + 3 nc, nh = 3 nc.  Integrals: collapsed Gauss-Legendre rule of
+ * 5 x 5 points per cell.  The mass solves M_u^-1 are Jacobi Chebyshev
+ * semi-iterations over the Ritz bounds of D^-1 M_u (widened 3% below and 1%
+ * above) to cg_rtol, checked in FP64 (PA_ENOCONV if a check fails); M_h^-1
+ * is exact (block diagonal).  phys->b_cell must be NULL; lambda_bar is the
+ * scale of the Chebyshev polynomial (set it, e.g. to rho(L) times a safety
+ * factor, before an exponential). */
+int pa_bdm2_create(const pa_mesh *m, const pa_phys *phys, pa_bdm2 **out);
+/* nu, nh, and the Ritz bounds of D^-1 M_u (any pointer may be NULL). */
+int pa_bdm2_info(const pa_bdm2 *b, int32_t *nu, int32_t *nh, double *eig_min,
+                 double *eig_max);
+/* Host copies of the assembled tables (any pointer may be NULL), rows
+ * column-major so that entry s of row i sits at s * nu + i:
+ * col, mass, cor [21 * nu] (the columns of M_u and F, unused slots point at
+ * the row itself with value 0), bcol, bval [6 * nu] (B; unused slots
+ * column 0, value 0), cdof [nc * 12] (velocity unknowns of each cell: its
+ * edges' 3 points each, edge i of the cell first, then its 3 moments), and
+ * q [nc * 3 * 12] (-H M_h^-1 B^T restricted to the cell, so that depth row
+ * 3 c + r of L u is sum_k q[(3 c + r) * 12 + k] u[cdof[12 c + k]]). */
+int pa_bdm2_tables(const pa_bdm2 *b, int32_t *col, double *mass, double *cor,
+                   int32_t *bcol, double *bval, int32_t *cdof, double *q);
+/* Device bytes of the tables; bind uploads them into the caller's buffer
+ * (256-byte aligned, kept alive and unwritten while calls run). */
+int pa_bdm2_device_size(const pa_bdm2 *b, size_t *bytes);
+int pa_bdm2_bind(pa_ctx *ctx, pa_bdm2 *b, void *dev_buf);
+int pa_bdm2_set_lambda(pa_bdm2 *b, double lambda_bar);
+/* Workspace bytes of a call on B states (B in [1, 64]): t_host NULL for
+ * pa_bdm2_apply_L, the call's B times for pa_bdm2_expL_apply (the degree
+ * depends on them). */
+int pa_bdm2_workspace_size(const pa_bdm2 *b, int B, const double *t_host,
+                           const pa_solve_cfg *cfg, size_t *bytes);
+/* out = L U for B states, member-major [B][nu + nh] in device memory (out
+ * must not alias U).  cfg: cg_rtol and maxit (the cap on semi-iteration
+ * steps) apply; NULL takes the defaults.  stats (may be NULL): solves,
+ * cg_iters (steps summed), cg_iters_max, resid_max, device_ms. */
+int pa_bdm2_apply_L(pa_ctx *ctx, const pa_bdm2 *b, int B, const double *U_dev,
+                    double *out_dev, void *ws_dev, size_t ws_bytes,
+                    const pa_solve_cfg *cfg, pa_stats *stats);
+/* U_out[j] = exp(t_j L) U_in[j] for B states by sum_k c_k R_k:
+ * R_0 = U, R_1 = L R_0 / lb, R_{k+1} = (2/lb) L R_k + R_{k-1}, c_k = (2 -
+ * delta_k0) J_k(lb |t_j|) sign(t_j)^k (lb = lambda_bar), truncated at the
+ * smallest degree whose dropped coefficients sum to at most cheb_tol.  This
+ * is the real form of eq. cheby: on an eigenvector of L with eigenvalue
+ * i omega, R_k = i^k T_k(omega/lb) U.  Valid while lambda_bar bounds the
+ * spectral radius of L.  Outputs must not alias inputs.  stats as for
+ * pa_bdm2_apply_L, plus kmax. */
+int pa_bdm2_expL_apply(pa_ctx *ctx, const pa_bdm2 *b, int B, const double *t_host,
+                       const double *U_in_dev, double *U_out_dev, void *ws_dev,
+                       size_t ws_bytes, const pa_solve_cfg *cfg, pa_stats *stats);
+int pa_bdm2_destroy(pa_bdm2 *b);
 
 #ifdef __cplusplus
 }

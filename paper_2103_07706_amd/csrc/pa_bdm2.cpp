@@ -1,0 +1,749 @@
+// The paper's own pair of spaces (Sec. 2.5), BDM2 velocity x P1DG depth:
+// host assembly of the linear operator of eq. ueq_int and the depth
+// equation after it, and the Chebyshev exponential of Sec. 2.4 on it.
+//
+// Per flat triangle (its own plane, frame e1 = (p1 - p0)/|p1 - p0|,
+// k = outward unit normal, e2 = k x e1): the velocity is any quadratic
+// tangent field (12 coefficients), fixed by the normal component at the
+// three Gauss-Legendre points of each edge (in the edge's global vertex
+// order) and by the moments of u . e1 and u . e2 over |T| and of
+// u . (x - x_T)^perp over |T|^1.5; the depth is linear (barycentric
+// coefficients).  The local basis is the dual basis of those degrees of
+// freedom, found by inverting their 12 x 12 matrix on scaled monomials
+// about the centroid.  Integrals use the collapsed Gauss rule of 5 x 5
+// points with barycentric points (1 - a - b(1 - a), a, b(1 - a)) in the
+// cell's vertex order (exact to degree 8; the Coriolis parameter
+// f = 2 Omega z/|x| is taken at its points).  Assembled:
+//   M_u (ELL 21), F (same pattern), B (ELL 6), and per cell
+//   Q = -H M_h^-1 B_T^T (the depth rows of L; M_h is block diagonal).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "pa_bdm2.h"
+#include "pa_engine.h"
+#include "pa_kernels.h"
+
+namespace pa {
+namespace {
+
+void bneed(bool ok, const char *msg) {
+  if (!ok) throw Error(PA_EINVAL, msg);
+}
+
+// Gauss-Legendre nodes and weights on [0, 1] (Newton on P_n).
+void gauss_legendre01(int n, std::vector<double> &x, std::vector<double> &w) {
+  x.resize(n);
+  w.resize(n);
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < n; i++) {
+    double z = std::cos(pi * (i + 0.75) / (n + 0.5)), dp = 0.0;
+    for (int it = 0; it < 100; it++) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; k++) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = 0.5 * (1.0 - z);
+    w[i] = 1.0 / ((1.0 - z * z) * dp * dp);  // = (2/((1-z^2) P'^2)) / 2
+  }
+}
+
+struct V2 {
+  double x, y;
+};
+
+// Solve A X = I for a 12 x 12 matrix by Gauss-Jordan elimination with
+// partial pivoting; A is destroyed.
+void invert12(double A[12][12], double X[12][12]) {
+  for (int i = 0; i < 12; i++)
+    for (int j = 0; j < 12; j++) X[i][j] = i == j ? 1.0 : 0.0;
+  for (int c = 0; c < 12; c++) {
+    int p = c;
+    for (int r = c + 1; r < 12; r++)
+      if (std::fabs(A[r][c]) > std::fabs(A[p][c])) p = r;
+    if (A[p][c] == 0.0) throw Error(PA_EINVAL, "BDM2 degrees of freedom are not unisolvent on a cell");
+    for (int j = 0; j < 12; j++) {
+      std::swap(A[c][j], A[p][j]);
+      std::swap(X[c][j], X[p][j]);
+    }
+    const double inv = 1.0 / A[c][c];
+    for (int j = 0; j < 12; j++) {
+      A[c][j] *= inv;
+      X[c][j] *= inv;
+    }
+    for (int r = 0; r < 12; r++) {
+      if (r == c || A[r][c] == 0.0) continue;
+      const double f = A[r][c];
+      for (int j = 0; j < 12; j++) {
+        A[r][j] -= f * A[c][j];
+        X[r][j] -= f * X[c][j];
+      }
+    }
+  }
+}
+
+// The 12 raw fields m_a(xi, eta) e_d, a < 6 over {1, xi, eta, xi^2, xi eta,
+// eta^2} with (xi, eta) = (x - x_T)/h: values (2 components each) and
+// divergences at a local point.
+void raw_fields(V2 p, V2 cen, double h, double val[12][2], double div[12]) {
+  const double xi = (p.x - cen.x) / h, et = (p.y - cen.y) / h;
+  const double m[6] = {1.0, xi, et, xi * xi, xi * et, et * et};
+  const double mx[6] = {0.0, 1.0, 0.0, 2.0 * xi, et, 0.0};  // d/dxi
+  const double my[6] = {0.0, 0.0, 1.0, 0.0, xi, 2.0 * et};  // d/deta
+  for (int a = 0; a < 6; a++) {
+    val[2 * a][0] = m[a];
+    val[2 * a][1] = 0.0;
+    val[2 * a + 1][0] = 0.0;
+    val[2 * a + 1][1] = m[a];
+    div[2 * a] = mx[a] / h;
+    div[2 * a + 1] = my[a] / h;
+  }
+}
+
+// Add (col, m, f) to a velocity row of at most kB2W entries.
+struct RowAcc {
+  int n = 0;
+  int col[kB2W];
+  double m[kB2W], f[kB2W];
+  void add(int c, double mv, double fv) {
+    for (int i = 0; i < n; i++)
+      if (col[i] == c) {
+        m[i] += mv;
+        f[i] += fv;
+        return;
+      }
+    if (n == kB2W) throw Error(PA_EINVAL, "BDM2 row wider than 21");
+    col[n] = c;
+    m[n] = mv;
+    f[n] = fv;
+    n++;
+  }
+};
+struct BRowAcc {
+  int n = 0;
+  int col[kB2WB];
+  double v[kB2WB];
+  void add(int c, double x) {
+    for (int i = 0; i < n; i++)
+      if (col[i] == c) {
+        v[i] += x;
+        return;
+      }
+    if (n == kB2WB) throw Error(PA_EINVAL, "BDM2 divergence row wider than 6");
+    col[n] = c;
+    v[n] = x;
+    n++;
+  }
+};
+
+}  // namespace
+
+void bdm2_assemble(pa_bdm2 *b, const Mesh &m, const pa_phys &ph) {
+  const int ne = m.ne(), nc = m.nc();
+  b->ne = ne;
+  b->nc = nc;
+  b->nu = 3 * ne + 3 * nc;
+  b->nh = 3 * nc;
+  b->g = ph.g;
+  b->H = ph.H;
+  b->omega = ph.omega;
+  b->lambda_bar = ph.lambda_bar;
+  const int nu = b->nu;
+  // collapsed Gauss rule (5 x 5) in barycentric coordinates
+  std::vector<double> gx, gw;
+  gauss_legendre01(5, gx, gw);
+  std::vector<double> ql0, ql1, ql2, qw;
+  for (int i = 0; i < 5; i++)
+    for (int j = 0; j < 5; j++) {
+      const double a = gx[i], bb = gx[j] * (1.0 - gx[i]);
+      ql0.push_back(1.0 - a - bb);
+      ql1.push_back(a);
+      ql2.push_back(bb);
+      qw.push_back(2.0 * gw[i] * gw[j] * (1.0 - gx[i]));  // sums to 1 over the triangle
+    }
+  const int nq = (int)qw.size();
+  const double sq06 = std::sqrt(0.6);
+  const double tg[3] = {0.5 - 0.5 * sq06, 0.5, 0.5 + 0.5 * sq06};
+
+  std::vector<RowAcc> rows(nu);
+  std::vector<BRowAcc> brows(nu);
+  b->cdof.assign((size_t)12 * nc, 0);
+  b->q.assign((size_t)36 * nc, 0.0);
+  for (int c = 0; c < nc; c++) {
+    double P[3][3];
+    for (int i = 0; i < 3; i++)
+      for (int d = 0; d < 3; d++) P[i][d] = m.xyz[3 * m.tri[3 * c + i] + d];
+    double u1[3], u2[3], k[3];
+    for (int d = 0; d < 3; d++) {
+      u1[d] = P[1][d] - P[0][d];
+      u2[d] = P[2][d] - P[0][d];
+    }
+    k[0] = u1[1] * u2[2] - u1[2] * u2[1];
+    k[1] = u1[2] * u2[0] - u1[0] * u2[2];
+    k[2] = u1[0] * u2[1] - u1[1] * u2[0];
+    const double kn = std::sqrt(k[0] * k[0] + k[1] * k[1] + k[2] * k[2]);
+    const double A = 0.5 * kn;
+    const double l1 = std::sqrt(u1[0] * u1[0] + u1[1] * u1[1] + u1[2] * u1[2]);
+    double e1[3], e2[3];
+    for (int d = 0; d < 3; d++) {
+      e1[d] = u1[d] / l1;
+      k[d] /= kn;
+    }
+    e2[0] = k[1] * e1[2] - k[2] * e1[1];
+    e2[1] = k[2] * e1[0] - k[0] * e1[2];
+    e2[2] = k[0] * e1[1] - k[1] * e1[0];
+    V2 x[3];
+    for (int i = 0; i < 3; i++) {
+      double dv[3];
+      for (int d = 0; d < 3; d++) dv[d] = P[i][d] - P[0][d];
+      x[i] = {dv[0] * e1[0] + dv[1] * e1[1] + dv[2] * e1[2], dv[0] * e2[0] + dv[1] * e2[1] + dv[2] * e2[2]};
+    }
+    const V2 cen = {(x[0].x + x[1].x + x[2].x) / 3.0, (x[0].y + x[1].y + x[2].y) / 3.0};
+    const double h = std::sqrt(A);
+    // degrees of freedom of the raw fields
+    double Dm[12][12];
+    int gid[12];
+    double sg[12];
+    for (int i = 0; i < 3; i++) {
+      const int e = m.cedge[3 * c + i];
+      const int va = m.evert[2 * e], vb = m.evert[2 * e + 1];
+      int ia = -1, ib = -1;
+      for (int v = 0; v < 3; v++) {
+        if (m.tri[3 * c + v] == va) ia = v;
+        if (m.tri[3 * c + v] == vb) ib = v;
+      }
+      bneed(ia >= 0 && ib >= 0 && ia != i && ib != i, "edge i of a cell must be opposite its vertex i");
+      // outward unit normal of edge i in the plane
+      const V2 pa_ = x[(i + 1) % 3], pb_ = x[(i + 2) % 3];
+      V2 n = {pb_.y - pa_.y, -(pb_.x - pa_.x)};
+      const V2 mid = {0.5 * (pa_.x + pb_.x), 0.5 * (pa_.y + pb_.y)};
+      if (n.x * (mid.x - cen.x) + n.y * (mid.y - cen.y) < 0) {
+        n.x = -n.x;
+        n.y = -n.y;
+      }
+      const double nl = std::sqrt(n.x * n.x + n.y * n.y);
+      n.x /= nl;
+      n.y /= nl;
+      const int sgn = (m.ecell[2 * e] == c) ? 1 : -1;
+      for (int kq = 0; kq < 3; kq++) {
+        const V2 p = {(1.0 - tg[kq]) * x[ia].x + tg[kq] * x[ib].x, (1.0 - tg[kq]) * x[ia].y + tg[kq] * x[ib].y};
+        double val[12][2], dvv[12];
+        raw_fields(p, cen, h, val, dvv);
+        for (int f = 0; f < 12; f++) Dm[3 * i + kq][f] = val[f][0] * n.x + val[f][1] * n.y;
+        gid[3 * i + kq] = 3 * e + kq;
+        sg[3 * i + kq] = sgn;
+      }
+    }
+    for (int mm = 0; mm < 3; mm++) {
+      gid[9 + mm] = 3 * ne + 3 * c + mm;
+      sg[9 + mm] = 1.0;
+      for (int f = 0; f < 12; f++) Dm[9 + mm][f] = 0.0;
+    }
+    // quadrature points: local position, 3D position, weight
+    std::vector<V2> qp(nq);
+    std::vector<double> qf(nq), qa(nq);
+    for (int q = 0; q < nq; q++) {
+      const double b0 = ql0[q], b1 = ql1[q], b2 = ql2[q];
+      qp[q] = {b0 * x[0].x + b1 * x[1].x + b2 * x[2].x, b0 * x[0].y + b1 * x[1].y + b2 * x[2].y};
+      double X3[3];
+      for (int d = 0; d < 3; d++) X3[d] = b0 * P[0][d] + b1 * P[1][d] + b2 * P[2][d];
+      qf[q] = 2.0 * ph.omega * X3[2] / std::sqrt(X3[0] * X3[0] + X3[1] * X3[1] + X3[2] * X3[2]);
+      qa[q] = qw[q] * A;
+    }
+    for (int q = 0; q < nq; q++) {
+      double val[12][2], dvv[12];
+      raw_fields(qp[q], cen, h, val, dvv);
+      const V2 pp = {-(qp[q].y - cen.y), qp[q].x - cen.x};
+      for (int f = 0; f < 12; f++) {
+        Dm[9][f] += qa[q] * val[f][0] / A;
+        Dm[10][f] += qa[q] * val[f][1] / A;
+        Dm[11][f] += qa[q] * (val[f][0] * pp.x + val[f][1] * pp.y) / std::pow(A, 1.5);
+      }
+    }
+    double C[12][12];
+    invert12(Dm, C);  // column j of C: raw coefficients of basis function j
+    // element matrices
+    double Ml[12][12] = {}, Fl[12][12] = {}, Bl[12][3] = {};
+    for (int q = 0; q < nq; q++) {
+      double val[12][2], dvv[12];
+      raw_fields(qp[q], cen, h, val, dvv);
+      double ph0[12], ph1[12], dph[12];
+      for (int j = 0; j < 12; j++) {
+        double s0 = 0, s1 = 0, sd = 0;
+        for (int f = 0; f < 12; f++) {
+          s0 += C[f][j] * val[f][0];
+          s1 += C[f][j] * val[f][1];
+          sd += C[f][j] * dvv[f];
+        }
+        ph0[j] = s0;
+        ph1[j] = s1;
+        dph[j] = sd;
+      }
+      const double lam[3] = {ql0[q], ql1[q], ql2[q]};
+      for (int i = 0; i < 12; i++) {
+        for (int j = 0; j < 12; j++) {
+          Ml[i][j] += qa[q] * (ph0[i] * ph0[j] + ph1[i] * ph1[j]);
+          // phi_i . (f k x phi_j), k x (a, b) = (-b, a) in the frame
+          Fl[i][j] += qa[q] * qf[q] * (ph0[i] * -ph1[j] + ph1[i] * ph0[j]);
+        }
+        for (int r = 0; r < 3; r++) Bl[i][r] += qa[q] * dph[i] * lam[r];
+      }
+    }
+    for (int i = 0; i < 12; i++) {
+      for (int j = 0; j < 12; j++) rows[gid[i]].add(gid[j], sg[i] * sg[j] * Ml[i][j], sg[i] * sg[j] * Fl[i][j]);
+      for (int r = 0; r < 3; r++) brows[gid[i]].add(3 * c + r, sg[i] * Bl[i][r]);
+      b->cdof[12 * c + i] = gid[i];
+    }
+    // depth rows: -H M_h^-1 B_T^T, M_h^-1 = (12/A)(I - J/4)
+    for (int qq = 0; qq < 3; qq++)
+      for (int j = 0; j < 12; j++) {
+        double s = 0.0;
+        for (int r = 0; r < 3; r++) s += (12.0 / A) * ((qq == r ? 1.0 : 0.0) - 0.25) * sg[j] * Bl[j][r];
+        b->q[((size_t)c * 3 + qq) * 12 + j] = -ph.H * s;
+      }
+  }
+  // column-major ELL tables, padded with the row itself and zero values
+  b->col.assign((size_t)kB2W * nu, 0);
+  b->mass.assign((size_t)kB2W * nu, 0.0);
+  b->cor.assign((size_t)kB2W * nu, 0.0);
+  b->bcol.assign((size_t)kB2WB * nu, 0);
+  b->bval.assign((size_t)kB2WB * nu, 0.0);
+  b->dinv.assign(nu, 0.0);
+  for (int r = 0; r < nu; r++) {
+    const RowAcc &ra = rows[r];
+    for (int s = 0; s < kB2W; s++) {
+      const bool on = s < ra.n;
+      b->col[(size_t)s * nu + r] = on ? ra.col[s] : r;
+      b->mass[(size_t)s * nu + r] = on ? ra.m[s] : 0.0;
+      b->cor[(size_t)s * nu + r] = on ? ra.f[s] : 0.0;
+      if (on && ra.col[s] == r) b->dinv[r] = 1.0 / ra.m[s];
+    }
+    const BRowAcc &rb = brows[r];
+    for (int s = 0; s < kB2WB; s++) {
+      b->bcol[(size_t)s * nu + r] = s < rb.n ? rb.col[s] : 0;
+      b->bval[(size_t)s * nu + r] = s < rb.n ? rb.v[s] : 0.0;
+    }
+  }
+  // Ritz bounds of D^-1 M_u (as D^-1/2 M D^-1/2)
+  std::vector<double> sq(nu);
+  for (int i = 0; i < nu; i++) sq[i] = std::sqrt(b->dinv[i]);
+  ritz_bounds(
+      nu,
+      [&](const std::vector<double> &v, std::vector<double> &w) {
+        for (int i = 0; i < nu; i++) {
+          double s = 0.0;
+          for (int k2 = 0; k2 < kB2W; k2++) {
+            const int cc = b->col[(size_t)k2 * nu + i];
+            s += b->mass[(size_t)k2 * nu + i] * sq[cc] * v[cc];
+          }
+          w[i] = sq[i] * s;
+        }
+      },
+      200, &b->eig_min, &b->eig_max);
+}
+
+// ------------------------------------------------------------- the calls
+namespace {
+
+struct B2Buf {
+  int Bs = 0, kmax = 0, steps = 0;
+  double *Ra = nullptr, *Rb = nullptr, *acc = nullptr, *r = nullptr, *dir[2] = {nullptr, nullptr};
+  double *part = nullptr, *norms = nullptr, *coef = nullptr;
+  int *fail = nullptr;
+  unsigned long long *rmax = nullptr;
+  std::vector<double> c1, c2, hcoef;
+  double theta = 0.0;
+};
+
+template <class T>
+T *take(char *base, size_t &off, size_t cap, size_t n) {
+  off = (off + 255) & ~(size_t)255;
+  T *p = base ? (T *)(base + off) : nullptr;
+  off += n * sizeof(T);
+  if (base && off > cap) throw Error(PA_ENOMEM, "workspace too small");
+  return p;
+}
+
+// Plan (sizes and Chebyshev tables) of a call on B columns; times t (or
+// nullptr for one application of L).
+size_t b2_plan(const pa_bdm2 *b, int B, const double *t, const pa_solve_cfg &cfg, char *ws,
+               size_t cap, B2Buf &bf) {
+  bf.Bs = pad_cols(B);
+  if (bf.Bs > 64) throw Error(PA_ENOTSUP, "at most 64 states per BDM2 call");
+  const int Bs = bf.Bs, n = b->nu + b->nh;
+  // Jacobi Chebyshev semi-iteration over the widened Ritz bounds
+  const double lo = 0.97 * b->eig_min, hi = 1.01 * b->eig_max;
+  if (!(lo > 0) || !(hi > lo)) throw Error(PA_EINVAL, "no spectral bounds of the BDM2 mass matrix");
+  const double th = 0.5 * (lo + hi), de = 0.5 * (hi - lo), sigma = th / de;
+  bf.steps = std::min(cfg.maxit, (int)std::ceil(std::acosh(2.0 / cfg.cg_rtol) / std::acosh(sigma)) + 1);
+  bf.theta = th;
+  bf.c1.assign(bf.steps, 0.0);
+  bf.c2.assign(bf.steps, 0.0);
+  double rho = 1.0 / sigma;
+  for (int k = 0; k < bf.steps; k++) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    bf.c1[k] = rn * rho;
+    bf.c2[k] = 2.0 * rn / de;
+    rho = rn;
+  }
+  bf.kmax = 0;
+  if (t) {
+    std::vector<std::vector<double>> cs(B);
+    std::vector<int> K(B);
+    for (int j = 0; j < B; j++) {
+      const double theta = b->lambda_bar * std::fabs(t[j]);
+      cs[j] = bessel_weights(theta, 2 * (int)std::ceil(theta) + 64);
+      K[j] = t[j] == 0.0 ? 0 : truncate_degree(cs[j], cfg.cheb_tol);
+      bf.kmax = std::max(bf.kmax, K[j]);
+    }
+    bf.hcoef.assign((size_t)(bf.kmax + 1) * Bs, 0.0);
+    for (int j = 0; j < B; j++) {
+      const double sg = t[j] < 0 ? -1.0 : 1.0;
+      double sk = 1.0;
+      for (int k = 0; k <= K[j]; k++, sk *= sg) bf.hcoef[(size_t)k * Bs + j] = cs[j][k] * sk;
+    }
+  }
+  size_t off = 0;
+  bf.Ra = take<double>(ws, off, cap, (size_t)n * Bs);
+  bf.Rb = take<double>(ws, off, cap, (size_t)n * Bs);
+  bf.acc = take<double>(ws, off, cap, (size_t)n * Bs);
+  bf.r = take<double>(ws, off, cap, (size_t)b->nu * Bs);
+  bf.dir[0] = take<double>(ws, off, cap, (size_t)b->nu * Bs);
+  bf.dir[1] = take<double>(ws, off, cap, (size_t)b->nu * Bs);
+  bf.part = take<double>(ws, off, cap, (size_t)2048 * Bs);
+  bf.norms = take<double>(ws, off, cap, (size_t)2 * Bs);
+  bf.coef = take<double>(ws, off, cap, std::max<size_t>(bf.hcoef.size(), (size_t)256 * Bs));
+  bf.fail = take<int>(ws, off, cap, 2);
+  bf.rmax = take<unsigned long long>(ws, off, cap, 1);
+  return off + 4096;
+}
+
+// out = scale L in + add (velocity: M_u^-1 (scale(-F u + g B eta)) + add_u
+// as the solve from x_0 = add_u; depth: scale Q u + add_eta).
+void b2_lapply(const pa_bdm2 *b, B2Buf &bf, const pa_solve_cfg &cfg, hipStream_t s, const double *in,
+               double *out, const double *add, double scale, pa_stats *st) {
+  const int Bs = bf.Bs;
+  B2Args a{};
+  a.d = b->d;
+  a.Bs = Bs;
+  a.scale = scale;
+  a.u = in;
+  a.eta = in + (size_t)b->nu * Bs;
+  a.addu = add;
+  a.adde = add ? add + (size_t)b->nu * Bs : nullptr;
+  a.x = out;
+  a.eta_out = out + (size_t)b->nu * Bs;
+  a.r = bf.r;
+  a.dir = bf.dir[0];
+  a.theta_inv = 1.0 / bf.theta;
+  a.part = bf.part;
+  a.norms = bf.norms;
+  a.rtol2 = cfg.cg_rtol * cfg.cg_rtol;
+  a.fail = bf.fail;
+  a.rmax = bf.rmax;
+  launch_b2_stiff(a, s);
+  for (int k = 0; k < bf.steps; k++) {
+    a.dir_in = bf.dir[k & 1];
+    a.dir_out = bf.dir[(k + 1) & 1];
+    a.c1 = bf.c1[k];
+    a.c2 = bf.c2[k];
+    a.last = k + 1 == bf.steps;
+    launch_b2_step(a, s);
+  }
+  launch_b2_check(a, s);
+  if (st) {
+    st->solves++;
+    st->cg_iters += bf.steps;
+    st->cg_iters_max = std::max(st->cg_iters_max, bf.steps);
+  }
+}
+
+void b2_acc(const pa_bdm2 *b, B2Buf &bf, hipStream_t s, const double *R, int k) {
+  B2Args a{};
+  a.d = b->d;
+  a.Bs = bf.Bs;
+  a.u = R;
+  a.eta = R + (size_t)b->nu * bf.Bs;
+  a.acc = bf.acc;
+  a.coef = bf.coef + (size_t)k * bf.Bs;
+  launch_b2_acc(a, s);
+}
+
+template <class T>
+void place(size_t &off, const std::vector<T> &v, const T **dst, char *base) {
+  off = (off + 255) & ~(size_t)255;
+  if (base) *dst = (const T *)(base + off);
+  off += v.size() * sizeof(T);
+}
+
+size_t b2_layout(pa_bdm2 *b, char *base) {
+  size_t off = 0;
+  B2Dev d;
+  place(off, b->col, &d.col, base);
+  place(off, b->mass, &d.mass, base);
+  place(off, b->cor, &d.cor, base);
+  place(off, b->bcol, &d.bcol, base);
+  place(off, b->bval, &d.bval, base);
+  place(off, b->dinv, &d.dinv, base);
+  place(off, b->cdof, &d.cdof, base);
+  place(off, b->q, &d.q, base);
+  if (base) {
+    d.nu = b->nu;
+    d.nh = b->nh;
+    d.nc = b->nc;
+    d.g = b->g;
+    b->d = d;
+  }
+  return (off + 255) & ~(size_t)255;
+}
+
+template <class T>
+void up(hipStream_t s, const T *dst, const std::vector<T> &v) {
+  if (!v.empty())
+    PA_HIP(hipMemcpyAsync((void *)dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+pa_solve_cfg cfg_of(const pa_solve_cfg *cfg) {
+  pa_solve_cfg c;
+  pa_solve_cfg_default(&c);
+  if (cfg) c = *cfg;
+  bneed(c.cg_rtol > 0 && c.cheb_tol > 0 && c.maxit > 0, "bad solve configuration");
+  return c;
+}
+
+// The call on a workspace: set-up, kernels, the solves' residual check.
+void b2_run(pa_ctx *ctx, const pa_bdm2 *b, int B, const double *t, const double *Uin, double *Uout, void *ws,
+            size_t ws_bytes, const pa_solve_cfg &cfg, pa_stats *stats) {
+  bneed(ctx && b && Uin && Uout && ws && B >= 1, "bad arguments");
+  bneed(b->dev != nullptr, "BDM2 operators not bound (pa_bdm2_bind)");
+  if (t) bneed(b->lambda_bar > 0, "lambda_bar is not set");
+  B2Buf bf;
+  b2_plan(b, B, t, cfg, (char *)ws, ws_bytes, bf);
+  PA_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  const int n = b->nu + b->nh, Bs = bf.Bs;
+  pa_stats st{};
+  hipEvent_t e0, e1;
+  PA_HIP(hipEventCreate(&e0));
+  PA_HIP(hipEventCreate(&e1));
+  PA_HIP(hipEventRecord(e0, s));
+  launch_zero((unsigned *)bf.fail, 1, s);
+  launch_zero((unsigned *)bf.rmax, 2, s);
+  TransArgs tr{n, B, Bs, const_cast<double *>(Uin), bf.Ra};
+  launch_to_block(tr, s);
+  double *out_blk = bf.Rb;
+  if (!t) {
+    b2_lapply(b, bf, cfg, s, bf.Ra, bf.Rb, nullptr, 1.0, &st);
+  } else {
+    PA_HIP(hipMemcpyAsync(bf.coef, bf.hcoef.data(), bf.hcoef.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    // acc = c_0 R_0; R_1 = L R_0 / lb; R_{k+1} = (2/lb) L R_k + R_{k-1}
+    // (R_{k+1} overwrites R_{k-1}); acc += c_k R_k
+    AxpyArgs z{(size_t)n * Bs, 0.0, 0.0, 0.0, nullptr, nullptr, nullptr, bf.acc};
+    launch_axpy(z, s);
+    b2_acc(b, bf, s, bf.Ra, 0);
+    double *prev = bf.Ra, *cur = bf.Rb;
+    const double lb = b->lambda_bar;
+    for (int k = 0; k < bf.kmax; k++) {
+      if (k == 0) {
+        b2_lapply(b, bf, cfg, s, prev, cur, nullptr, 1.0 / lb, &st);
+      } else {
+        // cur <- (2/lb) L cur_k + prev, written into prev's storage
+        b2_lapply(b, bf, cfg, s, cur, prev, prev, 2.0 / lb, &st);
+        std::swap(prev, cur);
+      }
+      b2_acc(b, bf, s, cur, k + 1);
+    }
+    st.kmax = bf.kmax;
+    out_blk = bf.acc;
+  }
+  TransArgs tb{n, B, Bs, Uout, out_blk};
+  launch_from_block(tb, s);
+  PA_HIP(hipEventRecord(e1, s));
+  int fail = 0;
+  unsigned long long rmax = 0;
+  PA_HIP(hipMemcpyAsync(&fail, bf.fail, sizeof(int), hipMemcpyDeviceToHost, s));
+  PA_HIP(hipMemcpyAsync(&rmax, bf.rmax, sizeof(rmax), hipMemcpyDeviceToHost, s));
+  sync_checked(s);
+  float ms = 0;
+  PA_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  st.device_ms = ms;
+  std::memcpy(&st.resid_max, &rmax, sizeof(double));
+  if (stats) *stats = st;
+  if (fail > 0) throw Error(PA_ENOCONV, "a BDM2 mass solve missed cg_rtol");
+}
+
+}  // namespace
+}  // namespace pa
+
+extern "C" {
+
+int pa_mesh_from_arrays(int nv, const double *verts, int nc, const int32_t *cell_verts, int ne,
+                        const int32_t *cell_edges, const int32_t *edge_cells, const int32_t *edge_verts,
+                        double radius, pa_mesh **out) {
+  return pa::guard([&] {
+    pa::bneed(out && verts && cell_verts && cell_edges && edge_cells && edge_verts && nv > 0 && nc > 0 &&
+                      ne > 0,
+                  "bad arguments");
+    auto *m = new pa_mesh;
+    try {
+      pa::Mesh &M = m->m;
+      M.level = -1;
+      M.radius = radius;
+      M.xyz.assign(verts, verts + 3 * (size_t)nv);
+      M.tri.assign(cell_verts, cell_verts + 3 * (size_t)nc);
+      M.cedge.assign(cell_edges, cell_edges + 3 * (size_t)nc);
+      M.ecell.assign(edge_cells, edge_cells + 2 * (size_t)ne);
+      M.evert.assign(edge_verts, edge_verts + 2 * (size_t)ne);
+      M.csgn.assign(3 * (size_t)nc, 0);
+      pa::bneed(2 * (size_t)ne == 3 * (size_t)nc, "a closed triangulation has 2 ne = 3 nc");
+      for (int v = 0; v < 3 * nc; v++) pa::bneed(M.tri[v] >= 0 && M.tri[v] < nv, "cell vertex out of range");
+      for (int e = 0; e < ne; e++)
+        pa::bneed(M.ecell[2 * e] >= 0 && M.ecell[2 * e] < M.ecell[2 * e + 1] && M.ecell[2 * e + 1] < nc,
+                  "edge cells must satisfy 0 <= c0 < c1 < nc");
+      for (int c = 0; c < nc; c++) {
+        const double *p0 = &M.xyz[3 * M.tri[3 * c]], *p1 = &M.xyz[3 * M.tri[3 * c + 1]],
+                     *p2 = &M.xyz[3 * M.tri[3 * c + 2]];
+        const double a[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+        const double b[3] = {p2[0] - p0[0], p2[1] - p0[1], p2[2] - p0[2]};
+        const double k[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+        pa::bneed(k[0] * p0[0] + k[1] * p0[1] + k[2] * p0[2] > 0, "cells must be counter-clockwise seen from outside");
+        for (int i = 0; i < 3; i++) {
+          const int e = M.cedge[3 * c + i];
+          pa::bneed(e >= 0 && e < ne, "cell edge out of range");
+          const int va = M.tri[3 * c + (i + 1) % 3], vb = M.tri[3 * c + (i + 2) % 3];
+          const bool first = M.ecell[2 * e] == c;
+          pa::bneed(first || M.ecell[2 * e + 1] == c, "edge and cell tables disagree");
+          // the edge runs a -> b counter-clockwise about its first cell
+          const bool fwd = M.evert[2 * e] == va && M.evert[2 * e + 1] == vb;
+          const bool rev = M.evert[2 * e] == vb && M.evert[2 * e + 1] == va;
+          pa::bneed(first ? fwd : rev, "edge i of a cell must join its other two vertices, counter-clockwise about c0");
+          M.csgn[3 * c + i] = first ? 1 : -1;
+        }
+      }
+    } catch (...) {
+      delete m;
+      throw;
+    }
+    *out = m;
+  });
+}
+
+int pa_bdm2_create(const pa_mesh *m, const pa_phys *ph, pa_bdm2 **out) {
+  return pa::guard([&] {
+    pa::bneed(m && ph && out, "NULL argument");
+    pa::bneed(ph->g > 0 && ph->H > 0 && ph->lambda_bar >= 0, "g and H must be positive");
+    pa::bneed(ph->b_cell == nullptr, "no bottom topography in the BDM2 operator");
+    auto *b = new pa_bdm2;
+    try {
+      b->mesh = m;
+      pa::bdm2_assemble(b, m->m, *ph);
+      b->dev_bytes = pa::b2_layout(b, nullptr);
+    } catch (...) {
+      delete b;
+      throw;
+    }
+    *out = b;
+  });
+}
+
+int pa_bdm2_info(const pa_bdm2 *b, int32_t *nu, int32_t *nh, double *eig_min, double *eig_max) {
+  return pa::guard([&] {
+    pa::bneed(b != nullptr, "NULL argument");
+    if (nu) *nu = b->nu;
+    if (nh) *nh = b->nh;
+    if (eig_min) *eig_min = b->eig_min;
+    if (eig_max) *eig_max = b->eig_max;
+  });
+}
+
+int pa_bdm2_tables(const pa_bdm2 *b, int32_t *col, double *mass, double *cor, int32_t *bcol, double *bval,
+                   int32_t *cdof, double *q) {
+  return pa::guard([&] {
+    pa::bneed(b != nullptr, "NULL argument");
+    auto cp = [](auto *dst, const auto &v) {
+      if (dst) std::copy(v.begin(), v.end(), dst);
+    };
+    cp(col, b->col);
+    cp(mass, b->mass);
+    cp(cor, b->cor);
+    cp(bcol, b->bcol);
+    cp(bval, b->bval);
+    cp(cdof, b->cdof);
+    cp(q, b->q);
+  });
+}
+
+int pa_bdm2_device_size(const pa_bdm2 *b, size_t *bytes) {
+  return pa::guard([&] {
+    pa::bneed(b && bytes, "NULL argument");
+    *bytes = b->dev_bytes;
+  });
+}
+
+int pa_bdm2_bind(pa_ctx *ctx, pa_bdm2 *b, void *dev_buf) {
+  return pa::guard([&] {
+    pa::bneed(ctx && b && dev_buf, "NULL argument");
+    pa::bneed(((uintptr_t)dev_buf & 255) == 0, "device buffer must be 256-byte aligned");
+    PA_HIP(hipSetDevice(ctx->device));
+    b->dev = dev_buf;
+    pa::b2_layout(b, (char *)dev_buf);
+    hipStream_t s = ctx->stream;
+    pa::up(s, b->d.col, b->col);
+    pa::up(s, b->d.mass, b->mass);
+    pa::up(s, b->d.cor, b->cor);
+    pa::up(s, b->d.bcol, b->bcol);
+    pa::up(s, b->d.bval, b->bval);
+    pa::up(s, b->d.dinv, b->dinv);
+    pa::up(s, b->d.cdof, b->cdof);
+    pa::up(s, b->d.q, b->q);
+    pa::sync_checked(s);
+  });
+}
+
+int pa_bdm2_set_lambda(pa_bdm2 *b, double lambda_bar) {
+  return pa::guard([&] {
+    pa::bneed(b && lambda_bar > 0, "bad arguments");
+    b->lambda_bar = lambda_bar;
+  });
+}
+
+int pa_bdm2_workspace_size(const pa_bdm2 *b, int B, const double *t_host, const pa_solve_cfg *cfg,
+                           size_t *bytes) {
+  return pa::guard([&] {
+    pa::bneed(b && bytes && B >= 1, "bad arguments");
+    if (t_host) pa::bneed(b->lambda_bar > 0, "lambda_bar is not set");
+    pa::B2Buf bf;
+    *bytes = pa::b2_plan(b, B, t_host, pa::cfg_of(cfg), nullptr, 0, bf);
+  });
+}
+
+int pa_bdm2_apply_L(pa_ctx *ctx, const pa_bdm2 *b, int B, const double *U_dev, double *out_dev, void *ws,
+                    size_t ws_bytes, const pa_solve_cfg *cfg, pa_stats *stats) {
+  return pa::guard([&] {
+    pa::b2_run(ctx, b, B, nullptr, U_dev, out_dev, ws, ws_bytes, pa::cfg_of(cfg), stats);
+  });
+}
+
+int pa_bdm2_expL_apply(pa_ctx *ctx, const pa_bdm2 *b, int B, const double *t_host, const double *U_in_dev,
+                       double *U_out_dev, void *ws, size_t ws_bytes, const pa_solve_cfg *cfg,
+                       pa_stats *stats) {
+  return pa::guard([&] {
+    pa::bneed(t_host != nullptr, "t_host is NULL");
+    pa::b2_run(ctx, b, B, t_host, U_in_dev, U_out_dev, ws, ws_bytes, pa::cfg_of(cfg), stats);
+  });
+}
+
+int pa_bdm2_destroy(pa_bdm2 *b) {
+  return pa::guard([&] { delete b; });
+}
+
+}  // extern "C"

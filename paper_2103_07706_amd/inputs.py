@@ -98,6 +98,30 @@ def gaussian_bumps_state(verts, cell_verts, edge_verts, nbumps: int, seed: int,
     return np.concatenate([u, eta])
 
 
+def p1dg_bumps_state(verts, cell_verts, ne: int, nbumps: int, seed: int,
+                     phys: Physics = Physics(), width: float = 1.0e6):
+    """State of the BDM2 x P1DG pair (unknowns 3 ne + 3 nc velocity, then 3
+    per cell depth): the velocity at rest and, for each cell, the bump sum
+    of gaussian_bumps_state at the cell's three vertices (radially projected)
+    as the coefficients of the cell's barycentric coordinates -- the
+    geostrophic adjustment problem of the same bumps."""
+    verts = np.asarray(verts, dtype=np.float64)
+    amp, cen, zc = bump_params(seed, nbumps)
+    ev = _bump_sum(verts, amp, cen, np.ones(nbumps), phys.radius, width)
+    cv = np.asarray(cell_verts)
+    return np.concatenate([np.zeros(3 * ne + 3 * len(cv)), ev[cv].ravel()])
+
+
+def random_state(nu: int, nh: int, seed: int, u_scale: float = 10.0,
+                 eta_scale: float = 50.0):
+    """Independent normal unknowns (numpy's PCG64 stream of the seed):
+    velocity unknowns with standard deviation u_scale (m/s), then depth
+    unknowns with eta_scale (m).  Excites the whole spectrum of L."""
+    rng = np.random.default_rng(seed)
+    return np.concatenate([u_scale * rng.standard_normal(nu),
+                           eta_scale * rng.standard_normal(nh)])
+
+
 def balanced_zonal_state(verts, cell_verts, edge_verts, u0: float = 20.0,
                          phys: Physics = Physics()):
     """Zonal flow in geostrophic balance from the paper's test case (Sec. 3)

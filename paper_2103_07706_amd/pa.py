@@ -137,6 +137,21 @@ EXPORTS = {
     "pa_mesh_get_info": (ctypes.c_int, [_V, ctypes.POINTER(MeshInfo)]),
     "pa_mesh_export": (ctypes.c_int, [_V, _D, _I, _I, _I, _I]),
     "pa_mesh_destroy": (ctypes.c_int, [_V]),
+    "pa_mesh_from_arrays": (ctypes.c_int, [ctypes.c_int, _D, ctypes.c_int, _I, ctypes.c_int, _I, _I,
+                                           _I, ctypes.c_double, ctypes.POINTER(_V)]),
+    "pa_bdm2_create": (ctypes.c_int, [_V, ctypes.POINTER(Phys), ctypes.POINTER(_V)]),
+    "pa_bdm2_info": (ctypes.c_int, [_V, _I, _I, _D, _D]),
+    "pa_bdm2_tables": (ctypes.c_int, [_V, _I, _D, _D, _I, _D, _I, _D]),
+    "pa_bdm2_device_size": (ctypes.c_int, [_V, ctypes.POINTER(_SZ)]),
+    "pa_bdm2_bind": (ctypes.c_int, [_V, _V, _V]),
+    "pa_bdm2_set_lambda": (ctypes.c_int, [_V, ctypes.c_double]),
+    "pa_bdm2_workspace_size": (ctypes.c_int, [_V, ctypes.c_int, _D, ctypes.POINTER(SolveCfg),
+                                              ctypes.POINTER(_SZ)]),
+    "pa_bdm2_apply_L": (ctypes.c_int, [_V, _V, ctypes.c_int, _V, _V, _V, _SZ,
+                                       ctypes.POINTER(SolveCfg), ctypes.POINTER(Stats)]),
+    "pa_bdm2_expL_apply": (ctypes.c_int, [_V, _V, ctypes.c_int, _D, _V, _V, _V, _SZ,
+                                          ctypes.POINTER(SolveCfg), ctypes.POINTER(Stats)]),
+    "pa_bdm2_destroy": (ctypes.c_int, [_V]),
     "pa_ops_create": (ctypes.c_int, [_V, ctypes.POINTER(Phys), ctypes.POINTER(_V)]),
     "pa_ops_device_size": (ctypes.c_int, [_V, ctypes.POINTER(_SZ)]),
     "pa_ops_bind": (ctypes.c_int, [_V, _V, _V]),
@@ -304,9 +319,12 @@ class Context:
 class Mesh:
     """Icosahedral mesh (host)."""
 
-    def __init__(self, level: int, radius: float = 6.37122e6):
+    def __init__(self, level: int, radius: float = 6.37122e6, _handle=None):
         h = _V()
-        _check(lib().pa_mesh_icosahedral(level, radius, ctypes.byref(h)))
+        if _handle is None:
+            _check(lib().pa_mesh_icosahedral(level, radius, ctypes.byref(h)))
+        else:
+            h = _handle
         self._h = h
         info = MeshInfo()
         _check(lib().pa_mesh_get_info(h, ctypes.byref(info)))
@@ -321,6 +339,20 @@ class Mesh:
                                     self.cell_edges.ctypes.data_as(_I),
                                     self.edge_cells.ctypes.data_as(_I),
                                     self.edge_verts.ctypes.data_as(_I)))
+
+    @classmethod
+    def from_arrays(cls, verts, cell_verts, cell_edges, edge_cells, edge_verts,
+                    radius: float = 6.37122e6):
+        """pa_mesh_from_arrays: a mesh from host arrays in the layout of
+        pa_mesh_export (checked against the library's mesh conventions)."""
+        v = np.ascontiguousarray(verts, np.float64)
+        cv, ce, ec, ev = (np.ascontiguousarray(a, np.int32)
+                          for a in (cell_verts, cell_edges, edge_cells, edge_verts))
+        h = _V()
+        _check(lib().pa_mesh_from_arrays(len(v), _dp(v), len(cv), cv.ctypes.data_as(_I), len(ec),
+                                         ce.ctypes.data_as(_I), ec.ctypes.data_as(_I),
+                                         ev.ctypes.data_as(_I), radius, ctypes.byref(h)))
+        return cls(-1, radius, _handle=h)
 
     @property
     def n(self):
@@ -533,6 +565,91 @@ class Ops:
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:
             _lib.pa_ops_destroy(self._h)
+            self._h = None
+
+
+class BDM2:
+    """The BDM2 x P1DG linear operator and its Chebyshev exponential
+    (pa_bdm2_*).  Assembled on the host at construction; bind(ctx) uploads
+    the tables before the device calls."""
+
+    def __init__(self, mesh: Mesh, g=9.80616, H=1000.0, omega=7.292e-5, lambda_bar=0.0):
+        self.mesh = mesh
+        ph = Phys(g, H, omega, None, lambda_bar)
+        h = _V()
+        _check(lib().pa_bdm2_create(mesh._h, ctypes.byref(ph), ctypes.byref(h)))
+        self._h = h
+        nu, nh = ctypes.c_int32(), ctypes.c_int32()
+        lo, hi = ctypes.c_double(), ctypes.c_double()
+        _check(lib().pa_bdm2_info(h, ctypes.byref(nu), ctypes.byref(nh), ctypes.byref(lo),
+                                  ctypes.byref(hi)))
+        self.nu, self.nh = nu.value, nh.value
+        self.n = self.nu + self.nh
+        self.eig_bounds = (lo.value, hi.value)
+        self.ctx = None
+        self._buf = None
+        self._ws = None
+
+    def tables(self):
+        nu, nc = self.nu, self.mesh.nc
+        t = dict(col=np.zeros(21 * nu, np.int32), mass=np.zeros(21 * nu), cor=np.zeros(21 * nu),
+                 bcol=np.zeros(6 * nu, np.int32), bval=np.zeros(6 * nu),
+                 cdof=np.zeros(12 * nc, np.int32), q=np.zeros(36 * nc))
+        ip = lambda a: a.ctypes.data_as(_I)  # noqa: E731
+        _check(lib().pa_bdm2_tables(self._h, ip(t["col"]), _dp(t["mass"]), _dp(t["cor"]),
+                                    ip(t["bcol"]), _dp(t["bval"]), ip(t["cdof"]), _dp(t["q"])))
+        return t
+
+    def bind(self, ctx: Context):
+        import torch
+        sz = _SZ()
+        _check(lib().pa_bdm2_device_size(self._h, ctypes.byref(sz)))
+        buf = torch.empty(sz.value + 256, dtype=torch.uint8, device=f"cuda:{ctx.device}")
+        base = buf.data_ptr()
+        _check(lib().pa_bdm2_bind(ctx._h, self._h, _V(base + (-base) % 256)))
+        self.ctx, self._buf = ctx, buf
+        return self
+
+    def set_lambda(self, lambda_bar):
+        _check(lib().pa_bdm2_set_lambda(self._h, float(lambda_bar)))
+
+    def _workspace(self, B, t, cfg):
+        import torch
+        sz = _SZ()
+        _check(lib().pa_bdm2_workspace_size(self._h, B, None if t is None else _dp(t),
+                                            ctypes.byref(cfg), ctypes.byref(sz)))
+        if self._ws is None or self._ws.numel() < sz.value + 256:
+            self._ws = None
+            self._ws = torch.empty(sz.value + 256, dtype=torch.uint8,
+                                   device=f"cuda:{self.ctx.device}")
+        base = self._ws.data_ptr()
+        off = (-base) % 256
+        return _V(base + off), self._ws.numel() - off
+
+    def apply_L(self, U, cfg=None, out=None):
+        cfg = cfg or solve_cfg()
+        B = U.shape[0]
+        out = U.new_empty(U.shape) if out is None else out
+        ws, nb = self._workspace(B, None, cfg)
+        st = Stats()
+        _check(lib().pa_bdm2_apply_L(self.ctx._h, self._h, B, _ptr(U), _ptr(out), ws, nb,
+                                     ctypes.byref(cfg), ctypes.byref(st)))
+        return out, st.as_dict()
+
+    def expL_apply(self, t, U, cfg=None, out=None):
+        cfg = cfg or solve_cfg()
+        B = U.shape[0]
+        t = np.ascontiguousarray(np.broadcast_to(np.asarray(t, np.float64), (B,)))
+        out = U.new_empty(U.shape) if out is None else out
+        ws, nb = self._workspace(B, t, cfg)
+        st = Stats()
+        _check(lib().pa_bdm2_expL_apply(self.ctx._h, self._h, B, _dp(t), _ptr(U), _ptr(out), ws,
+                                        nb, ctypes.byref(cfg), ctypes.byref(st)))
+        return out, st.as_dict()
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.pa_bdm2_destroy(self._h)
             self._h = None
 
 

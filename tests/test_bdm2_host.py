@@ -1,0 +1,109 @@
+"""Host-side checks of the library's BDM2 x P1DG assembly (Sec. 2.5, the
+paper's own pair of spaces) against the oracle (oracle/bdm2.py), on the
+oracle's own mesh imported through pa_mesh_from_arrays so that both number
+every unknown alike.  The library writes its own basis (scaled monomials
+about the centroid, dual to the same degrees of freedom) and quadrature;
+the assembled matrices agree entry by entry only if the degrees of freedom,
+their signs and scalings, the Coriolis term and the divergence are the
+same.  No GPU: the tables are read back with pa_bdm2_tables."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle.bdm2 import BDM2P1DG
+
+
+def _lib_bdm2(om, **kw):
+    from paper_2103_07706_amd import pa
+    m = pa.Mesh.from_arrays(om.verts, om.cell_verts, om.cell_edges, om.edge_cells,
+                            om.edge_verts, om.radius)
+    return m, pa.BDM2(m, **kw)
+
+
+def _mats(b):
+    T = b.tables()
+    nu, nh = b.nu, b.nh
+    r21, r6 = np.tile(np.arange(nu), 21), np.tile(np.arange(nu), 6)
+    Mu = sp.csr_matrix((T["mass"], (r21, T["col"])), shape=(nu, nu))
+    F = sp.csr_matrix((T["cor"], (r21, T["col"])), shape=(nu, nu))
+    B = sp.csr_matrix((T["bval"], (r6, T["bcol"])), shape=(nu, nh))
+    return T, Mu, F, B
+
+
+@pytest.mark.parametrize("level", [0, 1, 3])
+def test_bdm2_tables_match_oracle(oracle_mesh, level):
+    om = oracle_mesh(level)
+    ob = BDM2P1DG(om, g=9.80616, H=1000.0, Omega=7.292e-5)
+    m, b = _lib_bdm2(om, g=9.80616, H=1000.0, omega=7.292e-5)
+    assert (b.nu, b.nh) == (ob.nu, ob.nh)
+    T, Mu, F, B = _mats(b)
+    for lib_m, or_m in ((Mu, ob.Mu), (F, ob.F), (B, ob.B)):
+        assert abs(lib_m - or_m).max() <= 1e-13 * abs(or_m).max()
+    # depth rows of L: -H M_h^-1 B^T u through the per-cell tables
+    u = np.random.default_rng(1).standard_normal(b.nu)
+    ref = ob._Mh_lu.solve(-ob.H * (ob.B.T @ u))
+    q, cd = T["q"].reshape(-1, 12), T["cdof"].reshape(-1, 12)
+    got = np.einsum("rk,rk->r", q, u[np.repeat(cd, 3, axis=0)])
+    assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+    # every cell's 12 unknowns are distinct and the padding is inert
+    assert all(len(set(r)) == 12 for r in cd)
+    pad = T["mass"] == 0
+    assert np.all(T["cor"][pad] == 0)
+
+
+def test_bdm2_mass_bounds_bracket_the_spectrum(oracle_mesh):
+    """The Ritz bounds the semi-iteration is planned on against the dense
+    spectrum of D^-1/2 M_u D^-1/2 (oracle matrices, level 2)."""
+    om = oracle_mesh(2)
+    ob = BDM2P1DG(om)
+    m, b = _lib_bdm2(om)
+    D = ob.Mu.diagonal()
+    ev = np.linalg.eigvalsh((sp.diags(D ** -0.5) @ ob.Mu @ sp.diags(D ** -0.5)).toarray())
+    lo, hi = b.eig_bounds
+    assert abs(lo / ev.min() - 1) < 1e-6 and abs(hi / ev.max() - 1) < 1e-6
+    # widened by 3% below and 1% above before planning
+    assert 0.97 * lo < ev.min() and 1.01 * hi > ev.max()
+
+
+def test_mesh_import_checks_conventions(oracle_mesh):
+    from paper_2103_07706_amd import pa
+    om = oracle_mesh(1)
+    args = [om.verts, om.cell_verts, om.cell_edges, om.edge_cells, om.edge_verts]
+    m = pa.Mesh.from_arrays(*args, om.radius)
+    assert (m.nv, m.ne, m.nc, m.level) == (om.nv, om.ne, om.nc, -1)
+    assert np.array_equal(m.edge_verts, om.edge_verts)
+
+    def bad(i, fix):
+        a = [np.array(x, copy=True) for x in args]
+        fix(a[i])
+        with pytest.raises(pa.PAError):
+            pa.Mesh.from_arrays(*a, om.radius)
+
+    bad(1, lambda cv: cv.__setitem__(0, cv[0, ::-1].copy()))       # a clockwise cell
+    bad(3, lambda ec: ec.__setitem__(0, ec[0, ::-1].copy()))       # c0 > c1
+    bad(4, lambda ev: ev.__setitem__(0, ev[0, ::-1].copy()))       # b -> a about c0
+    bad(2, lambda ce: ce.__setitem__(0, np.roll(ce[0], 1)))        # edge not opposite its vertex
+    bad(1, lambda cv: cv.__setitem__((0, 0), len(om.verts)))       # vertex out of range
+
+
+def test_bdm2_refuses_topography_and_bad_sizes(oracle_mesh):
+    import ctypes
+    from paper_2103_07706_amd import pa
+    om = oracle_mesh(0)
+    m, b = _lib_bdm2(om)
+    bcell = np.zeros(om.nc)
+    ph = pa.Phys(9.8, 1000.0, 7.292e-5, bcell.ctypes.data_as(pa._D), 0.0)
+    h = ctypes.c_void_p()
+    assert pa.lib().pa_bdm2_create(m._h, ctypes.byref(ph), ctypes.byref(h)) == pa.PA_EINVAL
+    sz = ctypes.c_size_t()
+    cfg = pa.solve_cfg()
+    assert pa.lib().pa_bdm2_workspace_size(b._h, 65, None, ctypes.byref(cfg),
+                                           ctypes.byref(sz)) == pa.PA_ENOTSUP
+    # an exponential needs lambda_bar
+    t = np.array([100.0])
+    assert pa.lib().pa_bdm2_workspace_size(b._h, 1, pa._dp(t), ctypes.byref(cfg),
+                                           ctypes.byref(sz)) == pa.PA_EINVAL
+    b.set_lambda(1e-2)
+    assert pa.lib().pa_bdm2_workspace_size(b._h, 1, pa._dp(t), ctypes.byref(cfg),
+                                           ctypes.byref(sz)) == 0
+    assert sz.value > 0

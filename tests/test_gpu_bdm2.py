@@ -1,0 +1,173 @@
+"""GPU parity of the BDM2 x P1DG linear operator and its Chebyshev
+exponential (Sec. 2.5, the paper's own pair of spaces; Sec. 2.4, eq. cheby)
+against the oracle (oracle/bdm2.py), on the oracle's mesh imported through
+pa_mesh_from_arrays so that unknowns are numbered alike on both sides.
+
+The oracle solves both mass matrices exactly (sparse LU) and runs the
+complex recurrence of eq. cheby with DCT coefficients; the library solves
+M_u by a Jacobi Chebyshev semi-iteration to cg_rtol, M_h in closed form, and
+runs the real recurrence with Bessel weights.  With cg_rtol = 1e-13 a single
+application of L agrees to 1e-10 of the output's largest entry (the
+relative solve error times the conditioning of D^-1 M_u, about 9); an
+exponential of degree K to 1e-9 (K applications, each within that bound;
+the truncation tolerance 1e-12 on both sides).
+"""
+import numpy as np
+import pytest
+
+from oracle.bdm2 import BDM2P1DG
+
+pytestmark = pytest.mark.gpu
+_CACHE = {}
+
+
+def _pair(level, **phys):
+    """(oracle operator, bound library operator, library mesh)."""
+    import oracle
+    from gpu_common import _ctx
+    from paper_2103_07706_amd import pa
+    key = (level, tuple(sorted(phys.items())))
+    if key not in _CACHE:
+        om = oracle.Mesh(level)
+        ob = BDM2P1DG(om, **{("Omega" if k == "omega" else k): v for k, v in phys.items()})
+        lm = pa.Mesh.from_arrays(om.verts, om.cell_verts, om.cell_edges, om.edge_cells,
+                                 om.edge_verts, om.radius)
+        lb = pa.BDM2(lm, **phys).bind(_ctx())
+        _CACHE[key] = (om, ob, lb, lm)
+    return _CACHE[key][1:]
+
+
+def _cfg(**kw):
+    from paper_2103_07706_amd import pa
+    base = dict(cg_rtol=1e-13, cheb_tol=1e-12, maxit=400)
+    base.update(kw)
+    return pa.solve_cfg(**base)
+
+
+def _states(ob, seeds, om=None):
+    from paper_2103_07706_amd import inputs
+    return np.stack([inputs.random_state(ob.nu, ob.nh, s) for s in seeds])
+
+
+def _dev(x):
+    import torch
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.float64, device="cuda:0")
+
+
+def _close(got, ref, tol, what=""):
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    assert err <= tol, f"{what}: {err:.3e} > {tol:g}"
+    return err
+
+
+@pytest.mark.parametrize("level,B", [(0, 1), (3, 3), (2, 64)])
+def test_gpu_bdm2_apply_L_parity(level, B):
+    """One application of L: single state, a ragged block (3 of 4 padded
+    columns), and the widest block; every column against the oracle."""
+    ob, lb, lm = _pair(level)
+    U = _states(ob, range(B))
+    out, st = lb.apply_L(_dev(U), _cfg())
+    got = out.cpu().numpy()
+    for j in range(B):
+        ref = ob.apply_L(U[j])
+        # velocity and depth rows have different units: each part on its own
+        _close(got[j, :ob.nu], ref[:ob.nu], 1e-10, f"u col {j}")
+        _close(got[j, ob.nu:], ref[ob.nu:], 1e-12, f"eta col {j}")
+    assert st["solves"] == 1 and st["cg_iters"] > 0
+    assert 0 < st["resid_max"] <= 1e-13
+
+
+def test_gpu_bdm2_apply_L_of_constant_depth_is_zero():
+    """Constant depth, fluid at rest: the divergence of a continuous normal
+    field integrates to zero, so L of (0, 1) has no velocity forcing from a
+    uniform surface and no depth change: a structural zero, exact up to
+    rounding on both sides."""
+    ob, lb, lm = _pair(2)
+    U = np.concatenate([np.zeros(ob.nu), np.full(ob.nh, 100.0)])[None]
+    out, st = lb.apply_L(_dev(U), _cfg())
+    got = out.cpu().numpy()[0]
+    scale = np.abs(ob.apply_L(_states(ob, [0])[0])).max()
+    assert np.abs(got).max() <= 1e-11 * scale
+
+
+def test_gpu_bdm2_expL_parity():
+    """exp(t L) U for five members with different times in one call (both
+    signs, zero, and a degree in the twenties), against the oracle's
+    complex recurrence with exact solves."""
+    ob, lb, lm = _pair(3)
+    lam = 1.05 * ob.rho()
+    lb.set_lambda(lam)
+    ts = [3600.0, -1800.0, 0.0, 900.0, 7200.0]
+    U = _states(ob, range(len(ts)))
+    out, st = lb.expL_apply(ts, _dev(U), _cfg())
+    got = out.cpu().numpy()
+    Ks = []
+    for j, t in enumerate(ts):
+        ref, K = ob.expL(lam, t, U[j], tol=1e-12)
+        Ks.append(K)
+        if t == 0.0:
+            assert np.array_equal(got[j], U[j])
+            continue
+        _close(got[j, :ob.nu], ref[:ob.nu], 1e-9, f"u t={t}")
+        _close(got[j, ob.nu:], ref[ob.nu:], 1e-9, f"eta t={t}")
+    assert abs(st["kmax"] - max(Ks)) <= 1
+    assert st["solves"] == st["kmax"]
+
+
+def test_gpu_bdm2_expL_smooth_adjustment_and_energy():
+    """The geostrophic adjustment of depth bumps from rest (smooth input):
+    parity with the oracle, and the energy H u.M_u u + g eta.M_h eta is
+    conserved by exp(t L) (L is skew in that inner product)."""
+    from paper_2103_07706_amd import inputs
+    ob, lb, lm = _pair(3)
+    lam = 1.05 * ob.rho()
+    lb.set_lambda(lam)
+    import oracle
+    om = oracle.Mesh(3)
+    U = np.stack([inputs.p1dg_bumps_state(om.verts, om.cell_verts, om.ne, 6, s) for s in (1, 2)])
+    ts = [5400.0, 10800.0]
+    out, st = lb.expL_apply(ts, _dev(U), _cfg())
+    got = out.cpu().numpy()
+    W = ob.W()
+    for j, t in enumerate(ts):
+        ref, _ = ob.expL(lam, t, U[j], tol=1e-12)
+        _close(got[j], ref, 1e-9, f"t={t}")
+        e0, e1 = U[j] @ (W @ U[j]), got[j] @ (W @ got[j])
+        assert abs(e1 / e0 - 1) < 1e-9
+        # the bumps have started to move: velocity of order 0.1 m/s or more
+        assert np.abs(got[j, :ob.nu]).max() > 0.05
+
+
+def test_gpu_bdm2_full_size_level5():
+    """Level 5 (the paper's N_C = 20480 grid; 153600 velocity and 61440
+    depth unknowns), eight members at the averaging window's half width
+    T/2 = 3600 s and its negative: every output against the oracle on two
+    members, the energy of all eight."""
+    ob, lb, lm = _pair(5)
+    # rho(L) doubles with each level on this family (the oracle's Lanczos
+    # estimate at level 5 takes minutes): twice level 4's, plus 10%
+    lam = 1.1 * 2.0 * BDM2P1DG(__import__("oracle").Mesh(4)).rho()
+    lb.set_lambda(lam)
+    ts = [3600.0, -3600.0] * 4
+    U = _states(ob, range(8))
+    out, st = lb.expL_apply(ts, _dev(U), _cfg())
+    got = out.cpu().numpy()
+    for j in (0, 1):
+        ref, K = ob.expL(lam, ts[j], U[j], tol=1e-12)
+        _close(got[j], ref, 1e-9, f"member {j}")
+    W = ob.W()
+    for j in range(8):
+        assert abs((got[j] @ (W @ got[j])) / (U[j] @ (W @ U[j])) - 1) < 1e-9
+    assert st["resid_max"] <= 1e-13 and st["kmax"] >= 40
+
+
+def test_gpu_bdm2_errors():
+    """Host-side refusals of the device calls (no kernel runs)."""
+    from paper_2103_07706_amd import pa
+    ob, lb, lm = _pair(0)
+    U = _dev(_states(ob, [0]))
+    with pytest.raises(pa.PAError):
+        lb.expL_apply([100.0] * 65, _dev(_states(ob, range(65))), _cfg())
+    bad = _cfg(cg_rtol=0.0)
+    with pytest.raises(pa.PAError):
+        lb.apply_L(U, bad)
