@@ -21,8 +21,10 @@ Operators (eq. ueq_int and the depth equation):
   L(u, eta) = (M_u^-1 (-F u + g B eta), M_h^-1 (-H B^T u)),
 with f = 2 Omega z / |x| at the quadrature points and every integral by a
 collapsed (Duffy) Gauss-Legendre rule of 5 x 5 points per triangle (exact
-for polynomials of degree 8).  Written with numpy and scipy.sparse in the
-order above; no code is shared with the library.
+for polynomials of degree 8).  Also: exp(t L) by the Chebyshev recurrence
+(Sec. 2.4) and the nonlinearity N of Sec. 2.5 on this pair (BDM2P1DG.expL,
+BDM2P1DG.nonlinear).  Written with numpy and scipy.sparse in the order
+above; no code is shared with the library.
 """
 from __future__ import annotations
 
@@ -138,6 +140,7 @@ class BDM2P1DG:
         A[:, 11] = np.einsum("cq,cqfd,cqd->cf", wA, val, perp) / area[:, None] ** 1.5
         self._frame = (P, e1, e2, area, lq, wq, perp)
         C = np.linalg.inv(A)                                  # columns: dual basis
+        self._C, self._gl, self._k3 = C, gl, k
         phi = np.einsum("cqfd,cfj->cqjd", val, C)             # [nc, q, 12, 2]
         dphi = np.einsum("cqf,cfj->cqj", div, C)
         # physical quadrature points and Coriolis parameter
@@ -157,6 +160,7 @@ class BDM2P1DG:
         for m in range(3):
             gid[:, 9 + m] = 3 * ne + 3 * np.arange(nc) + m
         hid = 3 * np.arange(nc)[:, None] + np.arange(3)[None, :]
+        self._gid, self._sg = gid, sg
         S = sg[:, :, None] * sg[:, None, :]
 
         def asm(loc_, rows, cols, shape):
@@ -273,3 +277,108 @@ class BDM2P1DG:
             Pm, P = P, nxt
             acc = acc + a[k + 1] * nxt
         return acc.real, K
+
+    # ------------------------------------------------------------ nonlinearity
+    def _basis_at(self, l):
+        """Dual basis at per-cell barycentric points l [nc, q, 3]: values
+        [nc, q, 12, 2], Jacobians [nc, q, 12, 2 (component), 2 (derivative)]
+        in each cell's frame."""
+        N, dN = _p2(l)                                        # [nc,q,6], [nc,q,6,3]
+        grad = np.einsum("cqaj,cjd->cqad", dN, self._gl)      # [nc,q,6,2]
+        nc, q = l.shape[0], l.shape[1]
+        val = np.zeros((nc, q, 12, 2))
+        jac = np.zeros((nc, q, 12, 2, 2))
+        for a in range(6):
+            for c in range(2):
+                val[:, :, 2 * a + c, c] = N[:, :, a]
+                jac[:, :, 2 * a + c, c, :] = grad[:, :, a, :]
+        return (np.einsum("cqfd,cfj->cqjd", val, self._C),
+                np.einsum("cqfde,cfj->cqjde", jac, self._C))
+
+    def nonlinear(self, U, b=None):
+        """N(U) of Sec. 2.5 on this pair: for every test function w in BDM2
+        and psi in P1DG,
+          int w . u2 = int u . grad^perp(u^perp . w)
+                       - int_Gamma [[n^perp (u^perp . w)]] . u~ + int (div w) |u|^2/2,
+          int psi eta2 = int grad psi . u (eta - b) - int_Gamma [[psi u]] (eta - b)~,
+        with the readings of the lowest-order oracle (om_nonlin.c): the upwind
+        value comes from the cell the flow leaves (normal flux out of c0 > 0:
+        c0, else c1), the depth facet term carries a minus sign, and (eta -
+        b) on a facet is the upwind value.  Here the flux varies along an
+        edge, so the upwind side is chosen at every quadrature point.
+        Quadrature: the collapsed 5 x 5 rule in the cells (the volume
+        integrands have degree 5), 4-point Gauss-Legendre on every side (the
+        facet integrands have degree 6 away from a change of upwind side).
+        b: bottom height as P1DG coefficients (nh values) or None (flat).
+        Both mass matrices are solved exactly (sparse LU)."""
+        m = self.mesh
+        nc, ne, nu = m.nc, m.ne, self.nu
+        U = np.asarray(U, dtype=float)
+        coef = self._sg * U[:nu][self._gid]                   # [nc, 12]
+        h = U[nu:] - (0.0 if b is None else np.asarray(b, dtype=float))
+        h = h.reshape(nc, 3)
+        P, e1, e2, area, lq, wq, perp = self._frame
+        wA = wq[None, :] * area[:, None]
+        gl = self._gl                                         # [nc, 3, 2]
+        # ---- cell integrals
+        phi, jac = self._basis_at(np.broadcast_to(lq, (nc,) + lq.shape))
+        u = np.einsum("cj,cqjd->cqd", coef, phi)              # [nc, q, 2]
+        Ju = np.einsum("cj,cqjde->cqde", coef, jac)           # [nc, q, comp, deriv]
+        up = np.stack([-u[..., 1], u[..., 0]], -1)            # k x u
+        Jup = np.stack([-Ju[..., 1, :], Ju[..., 0, :]], -2)
+        # grad (u^perp . phi_i) = (grad u^perp)^T phi_i + (grad phi_i)^T u^perp
+        gq = np.einsum("cqed,cqie->cqid", Jup, phi) + np.einsum("cqe,cqied->cqid", up, jac)
+        gq_perp = np.stack([-gq[..., 1], gq[..., 0]], -1)     # k x grad
+        divphi = jac[..., 0, 0] + jac[..., 1, 1]              # [nc, q, 12]
+        ke = 0.5 * np.einsum("cqd,cqd->cq", u, u)
+        rl = (np.einsum("cq,cqd,cqid->ci", wA, u, gq_perp)
+              + np.einsum("cq,cqi,cq->ci", wA, divphi, ke))
+        hq = np.einsum("cr,qr->cq", h, lq)
+        rh = np.einsum("cq,crd,cqd,cq->cr", wA, gl, u, hq)
+        # ---- facet integrals: traces at 4 Gauss points of every side, the
+        # points ordered from the edge's first vertex to its second
+        x4, w4 = np.polynomial.legendre.leggauss(4)
+        t4, w4 = 0.5 * (x4 + 1.0), 0.5 * w4
+        tri = np.asarray(m.cell_verts)
+        ce = np.asarray(m.cell_edges)
+        ev = np.asarray(m.edge_verts)
+        ec = np.asarray(m.edge_cells)
+        lf = np.zeros((nc, 3, 4, 3))
+        for i in range(3):
+            la = (tri == ev[ce[:, i], 0][:, None]).astype(float)
+            lb = (tri == ev[ce[:, i], 1][:, None]).astype(float)
+            lf[:, i] = (1.0 - t4)[None, :, None] * la[:, None] + t4[None, :, None] * lb[:, None]
+        phf, _ = self._basis_at(lf.reshape(nc, 12, 3))
+        phf = phf.reshape(nc, 3, 4, 12, 2)
+        uf = np.einsum("cj,cspjd->cspd", coef, phf)           # own trace [nc, 3, 4, 2]
+        nloc = np.einsum("csd,cd->cs", self._n3, e1), np.einsum("csd,cd->cs", self._n3, e2)
+        nloc = np.stack(nloc, -1)                             # outward normals [nc, 3, 2]
+        flux = np.einsum("cspd,csd->csp", uf, nloc)           # u . n_out
+        uf3 = uf[..., :1] * e1[:, None, None] + uf[..., 1:] * e2[:, None, None]
+        hf = np.einsum("cr,cspr->csp", h, lf)
+        # upwind cell per edge point: from c0's trace of the flux
+        side = np.argmax(ce[ec] == np.arange(ne)[:, None, None], axis=2)   # [ne, 2]
+        f0 = flux[ec[:, 0], side[:, 0]]                       # [ne, 4]
+        pick = np.where(f0 > 0, 0, 1)                         # 0: c0, 1: c1
+        cu = np.take_along_axis(ec, pick, 1)
+        su = np.take_along_axis(side, pick, 1)
+        ut = uf3[cu, su, np.arange(4)[None, :]]               # [ne, 4, 3]
+        ht = hf[cu, su, np.arange(4)[None, :]]                # [ne, 4]
+        # side lengths (edge i joins the cell's vertices i+1, i+2)
+        lens = np.stack([np.linalg.norm(P[:, (i + 2) % 3] - P[:, (i + 1) % 3], axis=1)
+                         for i in range(3)], 1)               # [nc, 3]
+        wl = lens[:, :, None] * w4[None, None, :]             # [nc, 3, 4]
+        n3 = self._n3                                         # [nc, 3, 3]
+        nperp3 = np.cross(self._k3[:, None, :], n3)           # k x n_out
+        utc, htc = ut[ce], ht[ce]                             # upwind values seen by each cell side
+        upf = np.stack([-uf[..., 1], uf[..., 0]], -1)         # own u^perp
+        qf = np.einsum("cspd,cspid->cspi", upf, phf)          # u^perp . phi_i
+        rl -= np.einsum("csp,csd,cspd,cspi->ci", wl, nperp3, utc, qf)
+        rh -= np.einsum("csp,cspr,csp,csp->cr", wl, lf, flux, htc)
+        # ---- assemble and solve
+        rhs_u = np.zeros(nu)
+        np.add.at(rhs_u, self._gid.ravel(), (self._sg * rl).ravel())
+        u2 = self._Mu_lu.solve(rhs_u)
+        e2_ = self._Mh_lu.solve(rh.ravel())
+        return np.concatenate([u2, e2_])
+

@@ -21,8 +21,8 @@
  *   exponential, rational exponential, nonlinearity, nodes/weights, averaged
  *   RHS, RK4 step, diagnostics: all pinned.  The velocity upwind direction
  *   inside N is a reading of the paper (its printed inequality selects the
- *   downwind side) that no pin distinguishes from the alternative: parity
- *   unpinned for that choice.
+ *   downwind side); the pin of the facet term in closed form (divergence-free
+ *   fields, constant per cell) tells the two sides apart.
  */
 #ifndef ORACLE_H
 #define ORACLE_H

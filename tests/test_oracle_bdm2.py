@@ -127,3 +127,198 @@ def test_bdm2_expL_against_dense_exponential(bdm):
         assert abs(got @ (W @ got) / (U @ (W @ U)) - 1) < 1e-11
     got, K = b.expL(lb, 0.0, U)
     assert K == 0 and np.array_equal(got, U)
+
+
+# ---------------------------------------------------------------- nonlinearity
+def _pc_field(m, psi):
+    """A divergence-free field that BDM2 holds exactly: u = k x grad psi_h for
+    the continuous piecewise-linear psi_h with vertex values psi, constant
+    in each flat cell.  Returns its unknowns (normal flux density at the
+    edges' points, seen from c0; moments u.e1, u.e2, 0) and the per-cell
+    3D vectors, by elementary geometry written here."""
+    V = np.asarray(m.verts)
+    tri = np.asarray(m.cell_verts)
+    P = V[tri]
+    k = np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0])
+    A = 0.5 * np.linalg.norm(k, axis=1)
+    k /= (2 * A)[:, None]
+    grad = sum(psi[tri[:, r], None] * np.cross(k, P[:, (r + 2) % 3] - P[:, (r + 1) % 3])
+               for r in range(3)) / (2 * A)[:, None]
+    u = np.cross(k, grad)
+    e1 = (P[:, 1] - P[:, 0]) / np.linalg.norm(P[:, 1] - P[:, 0], axis=1)[:, None]
+    e2 = np.cross(k, e1)
+    nout = np.zeros((m.nc, 3, 3))
+    lens = np.zeros((m.nc, 3))
+    for i in range(3):
+        t = P[:, (i + 2) % 3] - P[:, (i + 1) % 3]
+        lens[:, i] = np.linalg.norm(t, axis=1)
+        n = np.cross(t, k)
+        n /= np.linalg.norm(n, axis=1)[:, None]
+        mid = 0.5 * (P[:, (i + 1) % 3] + P[:, (i + 2) % 3]) - P.mean(axis=1)
+        n *= np.sign(np.einsum("cd,cd->c", n, mid))[:, None]
+        nout[:, i] = n
+    ce, ec = np.asarray(m.cell_edges), np.asarray(m.edge_cells)
+    side0 = np.argmax(ce[ec[:, 0]] == np.arange(m.ne)[:, None], axis=1)
+    flux = np.einsum("ed,ed->e", u[ec[:, 0]], nout[ec[:, 0], side0])
+    U = np.concatenate([np.repeat(flux, 3), np.stack([np.einsum("cd,cd->c", u, e1),
+                                                     np.einsum("cd,cd->c", u, e2),
+                                                     np.zeros(m.nc)], 1).ravel()])
+    return U, dict(u=u, k=k, nout=nout, lens=lens, flux=flux)
+
+
+def _psi(m, seed):
+    """A smooth stream function at the vertices (m^2/s): a random
+    quadratic form of the unit position vector."""
+    p = np.asarray(m.verts) / R
+    G = np.random.default_rng(seed).standard_normal((3, 3))
+    return 2e7 * (np.einsum("vi,ij,vj->v", p, G, p) + p @ G[0])
+
+
+def test_bdm2_nonlinear_zero_homogeneity_mass(bdm):
+    from paper_2103_07706_amd import inputs
+    b = bdm(3)
+    U = inputs.random_state(b.nu, b.nh, 0)
+    N = b.nonlinear(U)
+    assert np.abs(b.nonlinear(3.0 * U) - 9.0 * N).max() <= 1e-13 * np.abs(9.0 * N).max()
+    Z = U.copy()
+    Z[:b.nu] = 0.0
+    assert np.abs(b.nonlinear(Z)).max() == 0.0
+    # depth mass: the sum of the P1DG coefficients times |T|/3
+    mass = (b.area[:, None] / 3.0 * N[b.nu:].reshape(-1, 3))
+    assert abs(mass.sum()) <= 1e-14 * np.abs(mass).sum()
+
+
+def test_bdm2_nonlinear_constant_depth_is_linear_divergence(bdm):
+    """(eta - b) = c everywhere: the depth tendency is -c div u, projected
+    on P1DG: exactly (c/H) times the depth rows of L (pinned above).  With
+    the paper's mountain as b, only eta - b enters."""
+    from paper_2103_07706_amd import inputs
+    b = bdm(3)
+    m = b.mesh
+    U = inputs.random_state(b.nu, b.nh, 1)
+    Lu = b.apply_L(np.concatenate([U[:b.nu], np.zeros(b.nh)]))[b.nu:]
+    V = np.asarray(m.verts)[np.asarray(m.cell_verts)]
+    bot = np.repeat(inputs.williamson5_bottom(m.verts, m.cell_verts), 3)
+    for c, bb in ((3.5, None), (-250.0, bot)):
+        eta = np.full(b.nh, c) + (0.0 if bb is None else bb)
+        N = b.nonlinear(np.concatenate([U[:b.nu], eta]), b=bb)
+        ref = c / b.H * Lu
+        assert np.abs(N[b.nu:] - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_bdm2_upwind_depth_flux_dissipates_exactly(bdm):
+    """For u divergence-free in every cell, eta' M_h N_eta = -1/2 sum over
+    edges of |u.n| times the integral of the squared jump of eta: the
+    upwind value makes the advection dissipate exactly that (the downwind
+    value would give the opposite sign, the central one zero)."""
+    from paper_2103_07706_amd import inputs
+    b = bdm(3)
+    m = b.mesh
+    Uv, g = _pc_field(m, _psi(m, 0))
+    eta = inputs.random_state(0, b.nh, 5)
+    N = b.nonlinear(np.concatenate([Uv, eta]))
+    lhs = eta @ (b.Mh @ N[b.nu:])
+    tri, ce, ec, ev = (np.asarray(a) for a in (m.cell_verts, m.cell_edges, m.edge_cells,
+                                               m.edge_verts))
+    E = eta.reshape(-1, 3)
+
+    def at(c, v):  # P1DG value of cell c at its vertex v
+        return E[c, np.argmax(tri[c] == v[:, None], axis=1)]
+    da = at(ec[:, 0], ev[:, 0]) - at(ec[:, 1], ev[:, 0])
+    db = at(ec[:, 0], ev[:, 1]) - at(ec[:, 1], ev[:, 1])
+    side0 = np.argmax(ce[ec[:, 0]] == np.arange(m.ne)[:, None], axis=1)
+    L = g["lens"][ec[:, 0], side0]
+    rhs = -0.5 * np.sum(L * np.abs(g["flux"]) * (da * da + da * db + db * db) / 3.0)
+    assert rhs < 0
+    assert abs(lhs / rhs - 1) < 1e-11
+
+
+def test_bdm2_velocity_facet_term_closed_form(bdm):
+    """u, w piecewise constant and divergence-free: in w' M_u N_u(u) the
+    cell terms vanish (u^perp . w and div w are constant and zero in each
+    cell) and only the facet term is left: -sum over cell sides of
+    |side| ((k x n_out) . u~)(u^perp . w), u~ from the cell the flow
+    leaves.  Pins the facet term's sign, its n^perp, and the upwind side
+    of the velocity trace; with w = u it vanishes."""
+    b = bdm(2)
+    m = b.mesh
+    Uu, gu = _pc_field(m, _psi(m, 1))
+    Uw, gw = _pc_field(m, _psi(m, 2))
+    N = b.nonlinear(np.concatenate([Uu, np.zeros(b.nh)]))
+    lhs = Uw @ (b.Mu @ N[:b.nu])
+    ce, ec = np.asarray(m.cell_edges), np.asarray(m.edge_cells)
+    up = np.where(gu["flux"] > 0, ec[:, 0], ec[:, 1])
+    ut = gu["u"][up][ce]                                   # [nc, 3, 3]
+    nperp = np.cross(gu["k"][:, None, :], gu["nout"])
+    uperp_w = np.einsum("cd,cd->c", np.cross(gu["k"], gu["u"]), gw["u"])
+    rhs = -np.sum(gu["lens"] * np.einsum("csd,csd->cs", nperp, ut) * uperp_w[:, None])
+    assert abs(lhs / rhs - 1) < 1e-11, (lhs, rhs)
+    self_ = Uu @ (b.Mu @ N[:b.nu])
+    assert abs(self_) <= 1e-12 * np.abs(Uu).max() * np.abs(b.Mu @ N[:b.nu]).sum()
+    # the downwind trace gives a different value
+    dn = np.where(gu["flux"] > 0, ec[:, 1], ec[:, 0])
+    rdn = -np.sum(gu["lens"] * np.einsum("csd,csd->cs", nperp, gu["u"][dn][ce]) * uperp_w[:, None])
+    assert abs(rdn / rhs - 1) > 1e-3
+
+
+def test_bdm2_zonal_flow_balance_converges(bdm):
+    """The balanced zonal flow of Sec. 3 (flat bottom) is steady, and its
+    depth splits into a part eta_f (u0 R Omega z^2 term) that balances the
+    Coriolis force and a part eta_k (u0^2/2 term) that balances the
+    nonlinear terms: L(u, eta_f) -> 0 and N_u(u) + L_u(0, eta_k) -> 0.  On
+    flat triangles both residuals fall at first order, each relative to the
+    size of the Coriolis term; with N's sign flipped the second stays at
+    the size of N (a few per cent of it)."""
+    u0, Om, g, H = 20.0, 7.292e-5, 9.80616, 5960.0
+    lin, res, flip = [], [], []
+    for lev in (2, 3, 4):
+        b = bdm(lev, g=g, H=H)
+        m = b.mesh
+        u = b.interpolate(lambda x: u0 / R * np.stack([-x[..., 1], x[..., 0], 0 * x[..., 0]], -1))
+        V = np.asarray(m.verts)[np.asarray(m.cell_verts)]
+        z2 = ((R * V[..., 2] / np.linalg.norm(V, axis=-1)) ** 2).ravel()
+        eta_f = -R * Om * u0 * z2 / (g * R ** 2)
+        eta_k = -0.5 * u0 ** 2 * z2 / (g * R ** 2)
+        zero_u, zero_h = np.zeros(b.nu), np.zeros(b.nh)
+        cor = b.apply_L(np.concatenate([u, zero_h]))[:b.nu]
+        lin.append(np.abs(b.apply_L(np.concatenate([u, eta_f]))[:b.nu]).max() / np.abs(cor).max())
+        N = b.nonlinear(np.concatenate([u, zero_h]))[:b.nu]
+        P = b.apply_L(np.concatenate([zero_u, eta_k]))[:b.nu]
+        res.append(np.abs(N + P).max() / np.abs(cor).max())
+        flip.append(np.abs(P - N).max() / np.abs(cor).max())
+    print("linear:", lin, "nonlinear:", res, "flipped:", flip)
+    for r in (lin, res):
+        assert r[0] / r[1] > 1.8 and r[1] / r[2] > 1.8 and r[2] < 0.05
+    assert min(flip) > 5 * res[-1]
+
+
+def test_bdm2_depth_advection_converges(bdm):
+    """Depth carried by solid-body rotation about the axis: the tendency at
+    the cells' vertices tends to -(u0/R) d eta/d lambda at first order."""
+    u0 = 20.0
+    c = np.array([np.cos(0.3), 0.0, np.sin(0.3)])
+
+    def eta_f(x):
+        p = x / np.linalg.norm(x, axis=-1, keepdims=True)
+        return 100.0 * np.exp(-(R * np.arccos(np.clip(p @ c, -1, 1)) / 1.5e6) ** 2)
+
+    def deta_dlam(x):
+        p = x / np.linalg.norm(x, axis=-1, keepdims=True)
+        d = R * np.arccos(np.clip(p @ c, -1, 1))
+        # d/dlambda of the distance to c: derivative of p along (-y, x, 0)
+        dp = np.stack([-p[..., 1], p[..., 0], 0 * p[..., 0]], -1)
+        cosd = np.clip(p @ c, -1, 1)
+        dd = -R * (dp @ c) / np.sqrt(np.maximum(1 - cosd ** 2, 1e-300))
+        return eta_f(x) * (-2 * d / 1.5e6 ** 2) * dd
+
+    errs = []
+    for lev in (2, 3, 4):
+        b = bdm(lev)
+        m = b.mesh
+        u = b.interpolate(lambda x: u0 / R * np.stack([-x[..., 1], x[..., 0], 0 * x[..., 0]], -1))
+        V = np.asarray(m.verts)[np.asarray(m.cell_verts)]
+        N = b.nonlinear(np.concatenate([u, eta_f(V).ravel()]))
+        ref = -(u0 / R) * deta_dlam(V).ravel()
+        errs.append(np.abs(N[b.nu:] - ref).max() / np.abs(ref).max())
+    print("advection errors:", errs)
+    assert errs[0] / errs[1] > 1.8 and errs[1] / errs[2] > 1.8 and errs[2] < 0.6
