@@ -382,3 +382,17 @@ class BDM2P1DG:
         e2_ = self._Mh_lu.solve(rh.ravel())
         return np.concatenate([u2, e2_])
 
+
+    # ------------------------------------------------------ averaged rhs
+    def phase_avg_rhs(self, lambda_bar, s, w, U, inner="N", tol=1e-13):
+        """Nbar(U) = sum_m w_m exp(-s_m L) N(exp(s_m L) U), eq. vt_discretised
+        of Sec. 2.2, every exponential by expL (Sec. 2.4) and N by nonlinear
+        (Sec. 2.5); inner = "L" or "I" substitutes L or the identity for N
+        (the averages then reduce to L U and U)."""
+        f = {"N": self.nonlinear, "L": self.apply_L, "I": lambda X: np.array(X, copy=True)}[inner]
+        out = np.zeros(self.n)
+        for sm, wm in zip(s, w):
+            V, _ = self.expL(lambda_bar, sm, U, tol)
+            Y, _ = self.expL(lambda_bar, -sm, f(V), tol)
+            out += wm * Y
+        return out

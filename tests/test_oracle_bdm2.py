@@ -322,3 +322,33 @@ def test_bdm2_depth_advection_converges(bdm):
         errs.append(np.abs(N[b.nu:] - ref).max() / np.abs(ref).max())
     print("advection errors:", errs)
     assert errs[0] / errs[1] > 1.8 and errs[1] / errs[2] > 1.8 and errs[2] < 0.6
+
+
+def test_bdm2_phase_avg_rhs_substitutions_and_limit(bdm):
+    """The average of Sec. 2.2 on this pair: with N := L it returns L U
+    (exp(-sL) L exp(sL) = L), with N := I it returns U (weights sum to 1),
+    and as T -> 0 it tends to N(U) at second order in T (the nodes are
+    symmetric, so the first-order term cancels).  The limit needs a smooth
+    state: in a rough one the upwind side flips wherever a flux is near
+    zero, an O(1) change however small the shift."""
+    from paper_2103_07706_amd import inputs
+    b = bdm(1)
+    lam = 1.05 * b.rho()
+    U = inputs.random_state(b.nu, b.nh, 3)
+    s, w = oracle.avg_nodes(8, 3600.0)
+    LU = b.apply_L(U)
+    assert np.abs(b.phase_avg_rhs(lam, s, w, U, inner="L") - LU).max() <= 1e-10 * np.abs(LU).max()
+    assert np.abs(b.phase_avg_rhs(lam, s, w, U, inner="I") - U).max() <= 1e-11 * np.abs(U).max()
+    b = bdm(3)
+    m = b.mesh
+    lam = 1.05 * b.rho()
+    u = b.interpolate(lambda x: 20.0 / R * np.stack([-x[..., 1], x[..., 0], 0 * x[..., 0]], -1))
+    U = inputs.p1dg_bumps_state(m.verts, m.cell_verts, m.ne, 4, 1)
+    U[:b.nu] = u
+    N0 = b.nonlinear(U)
+    errs = []
+    for T in (1200.0, 600.0, 300.0):
+        s, w = oracle.avg_nodes(8, T)
+        errs.append(np.linalg.norm(b.phase_avg_rhs(lam, s, w, U) - N0) / np.linalg.norm(N0))
+    print("T -> 0:", errs)
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5, errs
