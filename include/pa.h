@@ -591,11 +591,13 @@ int pa_bdm2_tables(const pa_bdm2 *b, int32_t *col, double *mass, double *cor,
 int pa_bdm2_device_size(const pa_bdm2 *b, size_t *bytes);
 int pa_bdm2_bind(pa_ctx *ctx, pa_bdm2 *b, void *dev_buf);
 int pa_bdm2_set_lambda(pa_bdm2 *b, double lambda_bar);
-/* Workspace bytes of a call on B states (B in [1, 64]): t_host NULL for
- * pa_bdm2_apply_L, the call's B times for pa_bdm2_expL_apply (the degree
- * depends on them). */
-int pa_bdm2_workspace_size(const pa_bdm2 *b, int B, const double *t_host,
-                           const pa_solve_cfg *cfg, size_t *bytes);
+/* Workspace bytes of a call: call is one of the PA_BDM2_* values below, B
+ * the number of states (members for PA_BDM2_PHASE_AVG); t_host the B times
+ * of PA_BDM2_EXPL (the degree depends on them), avg the nodes of
+ * PA_BDM2_PHASE_AVG (others NULL). */
+enum { PA_BDM2_APPLY_L = 0, PA_BDM2_EXPL = 1, PA_BDM2_NONLINEAR = 2, PA_BDM2_PHASE_AVG = 3 };
+int pa_bdm2_workspace_size(const pa_bdm2 *b, int call, int B, const double *t_host,
+                           const pa_avg *avg, const pa_solve_cfg *cfg, size_t *bytes);
 /* out = L U for B states, member-major [B][nu + nh] in device memory (out
  * must not alias U).  cfg: cg_rtol and maxit (the cap on semi-iteration
  * steps) apply; NULL takes the defaults.  stats (may be NULL): solves,
@@ -614,6 +616,31 @@ int pa_bdm2_apply_L(pa_ctx *ctx, const pa_bdm2 *b, int B, const double *U_dev,
 int pa_bdm2_expL_apply(pa_ctx *ctx, const pa_bdm2 *b, int B, const double *t_host,
                        const double *U_in_dev, double *U_out_dev, void *ws_dev,
                        size_t ws_bytes, const pa_solve_cfg *cfg, pa_stats *stats);
+/* out = N(U) for B states (B in [1, 64]): the nonlinearity of Sec. 2.5 on
+ * this pair, for every test function w in BDM2 and psi in P1DG
+ *   int w . u2 = int u . grad^perp(u^perp . w)
+ *                - int_Gamma [[n^perp (u^perp . w)]] . u~ + int (div w) |u|^2 / 2,
+ *   int psi eta2 = int grad psi . u eta - int_Gamma [[psi u]] eta~,
+ * u^perp = k x u, grad^perp = k x grad, ~ the value of the cell the flow
+ * leaves, chosen at every facet quadrature point from the normal flux seen
+ * by the edge's first cell (positive: that cell, else the other), eta the
+ * depth perturbation over a flat bottom.  Quadrature: the collapsed 5 x 5
+ * rule in cells (the cell integrands have degree 5), 4-point Gauss-Legendre
+ * on every side.  M_u solved as for pa_bdm2_apply_L, M_h exactly.
+ * Member-major states in device memory; out must not alias U. */
+int pa_bdm2_nonlinear(pa_ctx *ctx, const pa_bdm2 *b, int B, const double *U_dev,
+                      double *out_dev, void *ws_dev, size_t ws_bytes,
+                      const pa_solve_cfg *cfg, pa_stats *stats);
+/* The averaged right-hand side of Sec. 2.2 (eq. vt_discretised) on this
+ * pair: Nbar_j = sum_m w_m exp(-s_m L) N(exp(s_m L) U_j) for every member j,
+ * the nodes of avg (terms with w_m < weight_cut * max w dropped), every
+ * exponential as in pa_bdm2_expL_apply, N as in pa_bdm2_nonlinear.  The
+ * (member, node) pairs are processed 64 columns at a time, member-major, in
+ * a fixed order (results are reproducible bit for bit).  stats: solves,
+ * cg_iters, kmax, terms (columns evaluated), resid_max, device_ms. */
+int pa_bdm2_phase_avg_rhs(pa_ctx *ctx, const pa_bdm2 *b, const pa_avg *avg, int members,
+                          const double *U_dev, double *Nbar_dev, void *ws_dev,
+                          size_t ws_bytes, const pa_solve_cfg *cfg, pa_stats *stats);
 int pa_bdm2_destroy(pa_bdm2 *b);
 
 #ifdef __cplusplus

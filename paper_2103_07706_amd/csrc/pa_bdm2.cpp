@@ -176,6 +176,26 @@ void bdm2_assemble(pa_bdm2 *b, const Mesh &m, const pa_phys &ph) {
   std::vector<BRowAcc> brows(nu);
   b->cdof.assign((size_t)12 * nc, 0);
   b->q.assign((size_t)36 * nc, 0.0);
+  b->ncell.assign((size_t)kB2NC * nc, 0.0);
+  b->rloc.assign((size_t)2 * nu, -1);
+  b->etab.assign((size_t)4 * ne, -1);
+  // volume and side rules of the nonlinear term
+  b->qtab.resize(4 * (size_t)kB2VQ);
+  for (int q = 0; q < kB2VQ; q++) {
+    b->qtab[4 * q] = ql0[q];
+    b->qtab[4 * q + 1] = ql1[q];
+    b->qtab[4 * q + 2] = ql2[q];
+    b->qtab[4 * q + 3] = qw[q];
+  }
+  {
+    std::vector<double> fx, fw;
+    gauss_legendre01(kB2FQ, fx, fw);
+    b->ftab.resize(2 * (size_t)kB2FQ);
+    for (int p = 0; p < kB2FQ; p++) {
+      b->ftab[2 * p] = fx[p];
+      b->ftab[2 * p + 1] = fw[p];
+    }
+  }
   for (int c = 0; c < nc; c++) {
     double P[3][3];
     for (int i = 0; i < 3; i++)
@@ -211,6 +231,7 @@ void bdm2_assemble(pa_bdm2 *b, const Mesh &m, const pa_phys &ph) {
     double Dm[12][12];
     int gid[12];
     double sg[12];
+    V2 nside[3];
     for (int i = 0; i < 3; i++) {
       const int e = m.cedge[3 * c + i];
       const int va = m.evert[2 * e], vb = m.evert[2 * e + 1];
@@ -231,7 +252,10 @@ void bdm2_assemble(pa_bdm2 *b, const Mesh &m, const pa_phys &ph) {
       const double nl = std::sqrt(n.x * n.x + n.y * n.y);
       n.x /= nl;
       n.y /= nl;
+      nside[i] = n;
       const int sgn = (m.ecell[2 * e] == c) ? 1 : -1;
+      b->etab[4 * e + (sgn > 0 ? 0 : 2)] = c;
+      b->etab[4 * e + (sgn > 0 ? 1 : 3)] = i;
       for (int kq = 0; kq < 3; kq++) {
         const V2 p = {(1.0 - tg[kq]) * x[ia].x + tg[kq] * x[ib].x, (1.0 - tg[kq]) * x[ia].y + tg[kq] * x[ib].y};
         double val[12][2], dvv[12];
@@ -269,6 +293,31 @@ void bdm2_assemble(pa_bdm2 *b, const Mesh &m, const pa_phys &ph) {
     }
     double C[12][12];
     invert12(Dm, C);  // column j of C: raw coefficients of basis function j
+    {
+      double *t = &b->ncell[(size_t)kB2NC * c];
+      for (int f = 0; f < 12; f++)
+        for (int j = 0; j < 12; j++) t[kNcC + 12 * f + j] = C[f][j];
+      for (int r = 0; r < 3; r++) {
+        t[kNcX + 2 * r] = (x[r].x - cen.x) / h;
+        t[kNcX + 2 * r + 1] = (x[r].y - cen.y) / h;
+        // grad l_r = k x (x_{r+2} - x_{r+1}) / 2A, k x (a, b) = (-b, a)
+        const V2 d = {x[(r + 2) % 3].x - x[(r + 1) % 3].x, x[(r + 2) % 3].y - x[(r + 1) % 3].y};
+        t[kNcGl + 2 * r] = -d.y / (2.0 * A);
+        t[kNcGl + 2 * r + 1] = d.x / (2.0 * A);
+        // side r: k x n_out = -n.y e1 + n.x e2 (3D), n_out, length, sign
+        for (int dd = 0; dd < 3; dd++) t[kNcNp + 3 * r + dd] = -nside[r].y * e1[dd] + nside[r].x * e2[dd];
+        t[kNcNo + 2 * r] = nside[r].x;
+        t[kNcNo + 2 * r + 1] = nside[r].y;
+        t[kNcLen + r] = std::sqrt(d.x * d.x + d.y * d.y);
+        t[kNcSg + r] = sg[3 * r];
+      }
+      t[kNcH] = h;
+      t[kNcA] = A;
+      for (int dd = 0; dd < 3; dd++) {
+        t[kNcE1 + dd] = e1[dd];
+        t[kNcE2 + dd] = e2[dd];
+      }
+    }
     // element matrices
     double Ml[12][12] = {}, Fl[12][12] = {}, Bl[12][3] = {};
     for (int q = 0; q < nq; q++) {
@@ -300,6 +349,7 @@ void bdm2_assemble(pa_bdm2 *b, const Mesh &m, const pa_phys &ph) {
       for (int j = 0; j < 12; j++) rows[gid[i]].add(gid[j], sg[i] * sg[j] * Ml[i][j], sg[i] * sg[j] * Fl[i][j]);
       for (int r = 0; r < 3; r++) brows[gid[i]].add(3 * c + r, sg[i] * Bl[i][r]);
       b->cdof[12 * c + i] = gid[i];
+      b->rloc[2 * (size_t)gid[i] + (b->rloc[2 * (size_t)gid[i]] < 0 ? 0 : 1)] = 12 * c + i;
     }
     // depth rows: -H M_h^-1 B_T^T, M_h^-1 = (12/A)(I - J/4)
     for (int qq = 0; qq < 3; qq++)
@@ -352,14 +402,24 @@ void bdm2_assemble(pa_bdm2 *b, const Mesh &m, const pa_phys &ph) {
 // ------------------------------------------------------------- the calls
 namespace {
 
-struct B2Buf {
-  int Bs = 0, kmax = 0, steps = 0;
+enum { kCallL = PA_BDM2_APPLY_L, kCallExp = PA_BDM2_EXPL, kCallN = PA_BDM2_NONLINEAR, kCallNbar = PA_BDM2_PHASE_AVG };
+
+// A call's plan: the mass solves' semi-iteration, the column passes
+// (chunks of at most 64 columns) with their Chebyshev tables, and the
+// workspace carve-up.
+struct B2Plan {
+  int call = 0, B = 0, Bs = 0, steps = 0, kmax = 0, nchunk = 1;
+  double theta = 0.0;
+  std::vector<double> c1, c2;
+  std::vector<double> hF, hB;     // [nchunk][kmax + 1][Bs]: forward, backward weights
+  std::vector<int32_t> cmem;      // [nchunk][Bs]: member of each column (-1: padding)
+  std::vector<double> cw;         // [nchunk][Bs]: averaging weight of each column
   double *Ra = nullptr, *Rb = nullptr, *acc = nullptr, *r = nullptr, *dir[2] = {nullptr, nullptr};
-  double *part = nullptr, *norms = nullptr, *coef = nullptr;
+  double *raw = nullptr, *ut = nullptr, *loc = nullptr, *rhs = nullptr;
+  double *part = nullptr, *norms = nullptr, *coefF = nullptr, *coefB = nullptr, *cwd = nullptr;
+  int32_t *cmemd = nullptr;
   int *fail = nullptr;
   unsigned long long *rmax = nullptr;
-  std::vector<double> c1, c2, hcoef;
-  double theta = 0.0;
 };
 
 template <class T>
@@ -371,109 +431,224 @@ T *take(char *base, size_t &off, size_t cap, size_t n) {
   return p;
 }
 
-// Plan (sizes and Chebyshev tables) of a call on B columns; times t (or
-// nullptr for one application of L).
-size_t b2_plan(const pa_bdm2 *b, int B, const double *t, const pa_solve_cfg &cfg, char *ws,
-               size_t cap, B2Buf &bf) {
-  bf.Bs = pad_cols(B);
-  if (bf.Bs > 64) throw Error(PA_ENOTSUP, "at most 64 states per BDM2 call");
-  const int Bs = bf.Bs, n = b->nu + b->nh;
+// Chebyshev weights of exp(t L) with lambda_bar lb: (2 - delta_k0) J_k(lb |t|)
+// sign(t)^k, truncated at cheb_tol.
+int exp_weights(double lb, double t, double tol, std::vector<double> &c) {
+  const double theta = lb * std::fabs(t);
+  c = bessel_weights(theta, 2 * (int)std::ceil(theta) + 64);
+  const int K = t == 0.0 ? 0 : truncate_degree(c, tol);
+  c.resize(K + 1);
+  if (t < 0)
+    for (int k = 1; k <= K; k += 2) c[k] = -c[k];
+  return K;
+}
+
+// Fill column chunk q's weights [kmax + 1][Bs] of the times tq (one per column).
+void fill_weights(const pa_bdm2 *b, const std::vector<double> &tq, int Bs, int kmax, double tol,
+                  double *dst) {
+  std::vector<double> c;
+  for (size_t j = 0; j < tq.size(); j++) {
+    const int K = exp_weights(b->lambda_bar, tq[j], tol, c);
+    for (int k = 0; k <= K && k <= kmax; k++) dst[(size_t)k * Bs + j] = c[k];
+  }
+}
+
+size_t b2_plan(const pa_bdm2 *b, int call, int B, const double *t, const pa_avg *avg,
+               const pa_solve_cfg &cfg, char *ws, size_t cap, B2Plan &p) {
+  bneed(call >= kCallL && call <= kCallNbar, "unknown BDM2 call");
+  p.call = call;
+  p.B = B;
+  const bool expo = call == kCallExp || call == kCallNbar;
+  if (expo) bneed(b->lambda_bar > 0, "lambda_bar is not set");
   // Jacobi Chebyshev semi-iteration over the widened Ritz bounds
   const double lo = 0.97 * b->eig_min, hi = 1.01 * b->eig_max;
   if (!(lo > 0) || !(hi > lo)) throw Error(PA_EINVAL, "no spectral bounds of the BDM2 mass matrix");
   const double th = 0.5 * (lo + hi), de = 0.5 * (hi - lo), sigma = th / de;
-  bf.steps = std::min(cfg.maxit, (int)std::ceil(std::acosh(2.0 / cfg.cg_rtol) / std::acosh(sigma)) + 1);
-  bf.theta = th;
-  bf.c1.assign(bf.steps, 0.0);
-  bf.c2.assign(bf.steps, 0.0);
+  p.steps = std::min(cfg.maxit, (int)std::ceil(std::acosh(2.0 / cfg.cg_rtol) / std::acosh(sigma)) + 1);
+  p.theta = th;
+  p.c1.assign(p.steps, 0.0);
+  p.c2.assign(p.steps, 0.0);
   double rho = 1.0 / sigma;
-  for (int k = 0; k < bf.steps; k++) {
+  for (int k = 0; k < p.steps; k++) {
     const double rn = 1.0 / (2.0 * sigma - rho);
-    bf.c1[k] = rn * rho;
-    bf.c2[k] = 2.0 * rn / de;
+    p.c1[k] = rn * rho;
+    p.c2[k] = 2.0 * rn / de;
     rho = rn;
   }
-  bf.kmax = 0;
-  if (t) {
-    std::vector<std::vector<double>> cs(B);
-    std::vector<int> K(B);
-    for (int j = 0; j < B; j++) {
-      const double theta = b->lambda_bar * std::fabs(t[j]);
-      cs[j] = bessel_weights(theta, 2 * (int)std::ceil(theta) + 64);
-      K[j] = t[j] == 0.0 ? 0 : truncate_degree(cs[j], cfg.cheb_tol);
-      bf.kmax = std::max(bf.kmax, K[j]);
+  std::vector<std::vector<double>> tF, tB;  // per chunk: forward and backward times
+  if (call == kCallNbar) {
+    bneed(avg != nullptr, "no averaging nodes");
+    double wmax = 0.0;
+    for (double w : avg->w) wmax = std::max(wmax, w);
+    std::vector<int> keep;
+    for (size_t m = 0; m < avg->w.size(); m++)
+      if (avg->w[m] >= cfg.weight_cut * wmax && avg->w[m] != 0.0) keep.push_back((int)m);
+    const long cols = (long)B * (long)keep.size();
+    bneed(cols > 0, "no averaging term left");
+    p.Bs = pad_cols((int)std::min<long>(cols, 64));
+    p.nchunk = (int)((cols + 63) / 64);
+    p.cmem.assign((size_t)p.nchunk * p.Bs, -1);
+    p.cw.assign((size_t)p.nchunk * p.Bs, 0.0);
+    tF.resize(p.nchunk);
+    tB.resize(p.nchunk);
+    for (long c = 0; c < cols; c++) {
+      const int q = (int)(c / 64), j = (int)(c % 64);
+      const int mem = (int)(c / (long)keep.size()), m = keep[c % keep.size()];
+      p.cmem[(size_t)q * p.Bs + j] = mem;
+      p.cw[(size_t)q * p.Bs + j] = avg->w[m];
+      tF[q].push_back(avg->s[m]);
+      tB[q].push_back(-avg->s[m]);
     }
-    bf.hcoef.assign((size_t)(bf.kmax + 1) * Bs, 0.0);
-    for (int j = 0; j < B; j++) {
-      const double sg = t[j] < 0 ? -1.0 : 1.0;
-      double sk = 1.0;
-      for (int k = 0; k <= K[j]; k++, sk *= sg) bf.hcoef[(size_t)k * Bs + j] = cs[j][k] * sk;
-    }
+  } else {
+    p.Bs = pad_cols(B);
+    if (p.Bs > 64) throw Error(PA_ENOTSUP, "at most 64 states per BDM2 call");
+    if (call == kCallExp) tF.assign(1, std::vector<double>(t, t + B));
   }
+  p.kmax = 0;
+  std::vector<double> c;
+  for (auto &v : tF)
+    for (double tj : v) p.kmax = std::max(p.kmax, exp_weights(b->lambda_bar, tj, cfg.cheb_tol, c));
+  const size_t ctab = (size_t)(p.kmax + 1) * p.Bs;
+  if (expo) {
+    p.hF.assign(ctab * p.nchunk, 0.0);
+    for (int q = 0; q < p.nchunk; q++) fill_weights(b, tF[q], p.Bs, p.kmax, cfg.cheb_tol, &p.hF[ctab * q]);
+  }
+  if (call == kCallNbar) {
+    p.hB.assign(ctab * p.nchunk, 0.0);
+    for (int q = 0; q < p.nchunk; q++) fill_weights(b, tB[q], p.Bs, p.kmax, cfg.cheb_tol, &p.hB[ctab * q]);
+  }
+  const int Bs = p.Bs;
+  const size_t n = (size_t)b->nu + b->nh;
   size_t off = 0;
-  bf.Ra = take<double>(ws, off, cap, (size_t)n * Bs);
-  bf.Rb = take<double>(ws, off, cap, (size_t)n * Bs);
-  bf.acc = take<double>(ws, off, cap, (size_t)n * Bs);
-  bf.r = take<double>(ws, off, cap, (size_t)b->nu * Bs);
-  bf.dir[0] = take<double>(ws, off, cap, (size_t)b->nu * Bs);
-  bf.dir[1] = take<double>(ws, off, cap, (size_t)b->nu * Bs);
-  bf.part = take<double>(ws, off, cap, (size_t)2048 * Bs);
-  bf.norms = take<double>(ws, off, cap, (size_t)2 * Bs);
-  bf.coef = take<double>(ws, off, cap, std::max<size_t>(bf.hcoef.size(), (size_t)256 * Bs));
-  bf.fail = take<int>(ws, off, cap, 2);
-  bf.rmax = take<unsigned long long>(ws, off, cap, 1);
+  p.Ra = take<double>(ws, off, cap, n * Bs);
+  p.Rb = take<double>(ws, off, cap, n * Bs);
+  if (expo) p.acc = take<double>(ws, off, cap, n * Bs);
+  p.r = take<double>(ws, off, cap, (size_t)b->nu * Bs);
+  p.dir[0] = take<double>(ws, off, cap, (size_t)b->nu * Bs);
+  p.dir[1] = take<double>(ws, off, cap, (size_t)b->nu * Bs);
+  if (call == kCallN || call == kCallNbar) {
+    p.raw = take<double>(ws, off, cap, (size_t)12 * b->nc * Bs);
+    p.loc = take<double>(ws, off, cap, (size_t)12 * b->nc * Bs);
+    p.ut = take<double>(ws, off, cap, (size_t)4 * kB2FQ * b->ne * Bs);
+    p.rhs = take<double>(ws, off, cap, (size_t)b->nu * Bs);
+  }
+  p.part = take<double>(ws, off, cap, (size_t)2048 * Bs);
+  p.norms = take<double>(ws, off, cap, (size_t)2 * Bs);
+  if (expo) p.coefF = take<double>(ws, off, cap, p.hF.size());
+  if (call == kCallNbar) {
+    p.coefB = take<double>(ws, off, cap, p.hB.size());
+    p.cmemd = take<int32_t>(ws, off, cap, p.cmem.size());
+    p.cwd = take<double>(ws, off, cap, p.cw.size());
+  }
+  p.fail = take<int>(ws, off, cap, 2);
+  p.rmax = take<unsigned long long>(ws, off, cap, 1);
   return off + 4096;
+}
+
+// The velocity solve M_u x = rhs (x starts at add_u) after k_b2_stiff set
+// it up, then the residual check.
+void b2_solve(const B2Plan &p, B2Args &a, hipStream_t s, pa_stats &st) {
+  launch_b2_stiff(a, s);
+  for (int k = 0; k < p.steps; k++) {
+    a.dir_in = p.dir[k & 1];
+    a.dir_out = p.dir[(k + 1) & 1];
+    a.c1 = p.c1[k];
+    a.c2 = p.c2[k];
+    a.last = k + 1 == p.steps;
+    launch_b2_step(a, s);
+  }
+  launch_b2_check(a, s);
+  st.solves++;
+  st.cg_iters += p.steps;
+  st.cg_iters_max = std::max(st.cg_iters_max, p.steps);
+}
+
+B2Args solve_args(const pa_bdm2 *b, const B2Plan &p, const pa_solve_cfg &cfg) {
+  B2Args a{};
+  a.d = b->d;
+  a.Bs = p.Bs;
+  a.r = p.r;
+  a.dir = p.dir[0];
+  a.theta_inv = 1.0 / p.theta;
+  a.part = p.part;
+  a.norms = p.norms;
+  a.rtol2 = cfg.cg_rtol * cfg.cg_rtol;
+  a.fail = p.fail;
+  a.rmax = p.rmax;
+  return a;
 }
 
 // out = scale L in + add (velocity: M_u^-1 (scale(-F u + g B eta)) + add_u
 // as the solve from x_0 = add_u; depth: scale Q u + add_eta).
-void b2_lapply(const pa_bdm2 *b, B2Buf &bf, const pa_solve_cfg &cfg, hipStream_t s, const double *in,
-               double *out, const double *add, double scale, pa_stats *st) {
-  const int Bs = bf.Bs;
-  B2Args a{};
-  a.d = b->d;
-  a.Bs = Bs;
+void b2_lapply(const pa_bdm2 *b, const B2Plan &p, const pa_solve_cfg &cfg, hipStream_t s, const double *in,
+               double *out, const double *add, double scale, pa_stats &st) {
+  B2Args a = solve_args(b, p, cfg);
+  const size_t nuB = (size_t)b->nu * p.Bs;
   a.scale = scale;
   a.u = in;
-  a.eta = in + (size_t)b->nu * Bs;
+  a.eta = in + nuB;
   a.addu = add;
-  a.adde = add ? add + (size_t)b->nu * Bs : nullptr;
+  a.adde = add ? add + nuB : nullptr;
   a.x = out;
-  a.eta_out = out + (size_t)b->nu * Bs;
-  a.r = bf.r;
-  a.dir = bf.dir[0];
-  a.theta_inv = 1.0 / bf.theta;
-  a.part = bf.part;
-  a.norms = bf.norms;
-  a.rtol2 = cfg.cg_rtol * cfg.cg_rtol;
-  a.fail = bf.fail;
-  a.rmax = bf.rmax;
-  launch_b2_stiff(a, s);
-  for (int k = 0; k < bf.steps; k++) {
-    a.dir_in = bf.dir[k & 1];
-    a.dir_out = bf.dir[(k + 1) & 1];
-    a.c1 = bf.c1[k];
-    a.c2 = bf.c2[k];
-    a.last = k + 1 == bf.steps;
-    launch_b2_step(a, s);
-  }
-  launch_b2_check(a, s);
-  if (st) {
-    st->solves++;
-    st->cg_iters += bf.steps;
-    st->cg_iters_max = std::max(st->cg_iters_max, bf.steps);
-  }
+  a.eta_out = out + nuB;
+  b2_solve(p, a, s, st);
 }
 
-void b2_acc(const pa_bdm2 *b, B2Buf &bf, hipStream_t s, const double *R, int k) {
-  B2Args a{};
-  a.d = b->d;
-  a.Bs = bf.Bs;
-  a.u = R;
-  a.eta = R + (size_t)b->nu * bf.Bs;
-  a.acc = bf.acc;
-  a.coef = bf.coef + (size_t)k * bf.Bs;
-  launch_b2_acc(a, s);
+// out = N(in) (out must not alias in).
+void b2_nl(const pa_bdm2 *b, const B2Plan &p, const pa_solve_cfg &cfg, hipStream_t s, const double *in,
+           double *out, pa_stats &st) {
+  const size_t nuB = (size_t)b->nu * p.Bs;
+  B2NlArgs na{};
+  na.d = b->d;
+  na.Bs = p.Bs;
+  na.u = in;
+  na.eta = in + nuB;
+  na.raw = p.raw;
+  na.ut = p.ut;
+  na.loc = p.loc;
+  na.rhs = p.rhs;
+  na.eta_out = out + nuB;
+  launch_b2_nl(na, s);
+  B2Args a = solve_args(b, p, cfg);
+  a.scale = 1.0;
+  a.u = in;
+  a.eta = in + nuB;
+  a.rhs = p.rhs;
+  a.x = out;
+  b2_solve(p, a, s, st);
+}
+
+// acc = sum_k c_k R_k with R_0 = Ra (overwritten), Rb scratch, coef the
+// [kmax + 1][Bs] weights on the device.
+void b2_exp(const pa_bdm2 *b, const B2Plan &p, const pa_solve_cfg &cfg, hipStream_t s, const double *coef,
+            pa_stats &st) {
+  const size_t nB = ((size_t)b->nu + b->nh) * p.Bs;
+  AxpyArgs z{nB, 0.0, 0.0, 0.0, nullptr, nullptr, nullptr, p.acc};
+  launch_axpy(z, s);
+  auto accum = [&](const double *R, int k) {
+    B2Args a{};
+    a.d = b->d;
+    a.Bs = p.Bs;
+    a.u = R;
+    a.eta = R + (size_t)b->nu * p.Bs;
+    a.acc = p.acc;
+    a.coef = coef + (size_t)k * p.Bs;
+    launch_b2_acc(a, s);
+  };
+  accum(p.Ra, 0);
+  double *prev = p.Ra, *cur = p.Rb;
+  const double lb = b->lambda_bar;
+  for (int k = 0; k < p.kmax; k++) {
+    if (k == 0) {
+      b2_lapply(b, p, cfg, s, prev, cur, nullptr, 1.0 / lb, st);
+    } else {
+      // R_{k+1} = (2/lb) L R_k + R_{k-1}, written over R_{k-1}
+      b2_lapply(b, p, cfg, s, cur, prev, prev, 2.0 / lb, st);
+      std::swap(prev, cur);
+    }
+    accum(cur, k + 1);
+  }
+  st.kmax = std::max(st.kmax, p.kmax);
 }
 
 template <class T>
@@ -494,10 +669,16 @@ size_t b2_layout(pa_bdm2 *b, char *base) {
   place(off, b->dinv, &d.dinv, base);
   place(off, b->cdof, &d.cdof, base);
   place(off, b->q, &d.q, base);
+  place(off, b->ncell, &d.ncell, base);
+  place(off, b->etab, &d.etab, base);
+  place(off, b->rloc, &d.rloc, base);
+  place(off, b->qtab, &d.qtab, base);
+  place(off, b->ftab, &d.ftab, base);
   if (base) {
     d.nu = b->nu;
     d.nh = b->nh;
     d.nc = b->nc;
+    d.ne = b->ne;
     d.g = b->g;
     b->d = d;
   }
@@ -519,57 +700,75 @@ pa_solve_cfg cfg_of(const pa_solve_cfg *cfg) {
 }
 
 // The call on a workspace: set-up, kernels, the solves' residual check.
-void b2_run(pa_ctx *ctx, const pa_bdm2 *b, int B, const double *t, const double *Uin, double *Uout, void *ws,
-            size_t ws_bytes, const pa_solve_cfg &cfg, pa_stats *stats) {
+void b2_run(pa_ctx *ctx, const pa_bdm2 *b, int call, int B, const double *t, const pa_avg *avg,
+            const double *Uin, double *Uout, void *ws, size_t ws_bytes, const pa_solve_cfg &cfg,
+            pa_stats *stats) {
   bneed(ctx && b && Uin && Uout && ws && B >= 1, "bad arguments");
+  bneed(Uin != Uout, "outputs must not alias inputs");
   bneed(b->dev != nullptr, "BDM2 operators not bound (pa_bdm2_bind)");
-  if (t) bneed(b->lambda_bar > 0, "lambda_bar is not set");
-  B2Buf bf;
-  b2_plan(b, B, t, cfg, (char *)ws, ws_bytes, bf);
+  B2Plan p;
+  b2_plan(b, call, B, t, avg, cfg, (char *)ws, ws_bytes, p);
   PA_HIP(hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
-  const int n = b->nu + b->nh, Bs = bf.Bs;
+  const int n = b->nu + b->nh, Bs = p.Bs;
   pa_stats st{};
   hipEvent_t e0, e1;
   PA_HIP(hipEventCreate(&e0));
   PA_HIP(hipEventCreate(&e1));
   PA_HIP(hipEventRecord(e0, s));
-  launch_zero((unsigned *)bf.fail, 1, s);
-  launch_zero((unsigned *)bf.rmax, 2, s);
-  TransArgs tr{n, B, Bs, const_cast<double *>(Uin), bf.Ra};
-  launch_to_block(tr, s);
-  double *out_blk = bf.Rb;
-  if (!t) {
-    b2_lapply(b, bf, cfg, s, bf.Ra, bf.Rb, nullptr, 1.0, &st);
-  } else {
-    PA_HIP(hipMemcpyAsync(bf.coef, bf.hcoef.data(), bf.hcoef.size() * sizeof(double), hipMemcpyHostToDevice, s));
-    // acc = c_0 R_0; R_1 = L R_0 / lb; R_{k+1} = (2/lb) L R_k + R_{k-1}
-    // (R_{k+1} overwrites R_{k-1}); acc += c_k R_k
-    AxpyArgs z{(size_t)n * Bs, 0.0, 0.0, 0.0, nullptr, nullptr, nullptr, bf.acc};
-    launch_axpy(z, s);
-    b2_acc(b, bf, s, bf.Ra, 0);
-    double *prev = bf.Ra, *cur = bf.Rb;
-    const double lb = b->lambda_bar;
-    for (int k = 0; k < bf.kmax; k++) {
-      if (k == 0) {
-        b2_lapply(b, bf, cfg, s, prev, cur, nullptr, 1.0 / lb, &st);
-      } else {
-        // cur <- (2/lb) L cur_k + prev, written into prev's storage
-        b2_lapply(b, bf, cfg, s, cur, prev, prev, 2.0 / lb, &st);
-        std::swap(prev, cur);
-      }
-      b2_acc(b, bf, s, cur, k + 1);
-    }
-    st.kmax = bf.kmax;
-    out_blk = bf.acc;
+  launch_zero((unsigned *)p.fail, 1, s);
+  launch_zero((unsigned *)p.rmax, 2, s);
+  if (p.coefF) PA_HIP(hipMemcpyAsync(p.coefF, p.hF.data(), p.hF.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  if (p.coefB) PA_HIP(hipMemcpyAsync(p.coefB, p.hB.data(), p.hB.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  if (p.cmemd) {
+    PA_HIP(hipMemcpyAsync(p.cmemd, p.cmem.data(), p.cmem.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    PA_HIP(hipMemcpyAsync(p.cwd, p.cw.data(), p.cw.size() * sizeof(double), hipMemcpyHostToDevice, s));
   }
-  TransArgs tb{n, B, Bs, Uout, out_blk};
-  launch_from_block(tb, s);
+  if (call == kCallNbar) {
+    // Nbar_j = sum_m w_m exp(-s_m L) N(exp(s_m L) U_j) over chunks of
+    // (member, node) columns, accumulated in a fixed order
+    launch_zero((unsigned *)Uout, (size_t)2 * n * B, s);
+    const size_t ctab = (size_t)(p.kmax + 1) * Bs;
+    for (int q = 0; q < p.nchunk; q++) {
+      int jlo = B, jhi = -1;
+      for (int c = 0; c < Bs; c++) {
+        const int m = p.cmem[(size_t)q * Bs + c];
+        if (m >= 0) {
+          jlo = std::min(jlo, m);
+          jhi = std::max(jhi, m);
+        }
+      }
+      B2ColArgs ca{n, Bs, jlo, jhi - jlo + 1, p.cmemd + (size_t)q * Bs, p.cwd + (size_t)q * Bs, Uin, Uout,
+                   p.Ra, p.acc};
+      launch_b2_bcast(ca, s);
+      b2_exp(b, p, cfg, s, p.coefF + ctab * q, st);
+      b2_nl(b, p, cfg, s, p.acc, p.Ra, st);
+      b2_exp(b, p, cfg, s, p.coefB + ctab * q, st);
+      launch_b2_wsum(ca, s);
+    }
+    long cols = 0;
+    for (int32_t m : p.cmem) cols += m >= 0;
+    st.terms = (int32_t)cols;
+  } else {
+    TransArgs tr{n, B, Bs, const_cast<double *>(Uin), p.Ra};
+    launch_to_block(tr, s);
+    double *out_blk = p.Rb;
+    if (call == kCallL) {
+      b2_lapply(b, p, cfg, s, p.Ra, p.Rb, nullptr, 1.0, st);
+    } else if (call == kCallN) {
+      b2_nl(b, p, cfg, s, p.Ra, p.Rb, st);
+    } else {
+      b2_exp(b, p, cfg, s, p.coefF, st);
+      out_blk = p.acc;
+    }
+    TransArgs tb{n, B, Bs, Uout, out_blk};
+    launch_from_block(tb, s);
+  }
   PA_HIP(hipEventRecord(e1, s));
   int fail = 0;
   unsigned long long rmax = 0;
-  PA_HIP(hipMemcpyAsync(&fail, bf.fail, sizeof(int), hipMemcpyDeviceToHost, s));
-  PA_HIP(hipMemcpyAsync(&rmax, bf.rmax, sizeof(rmax), hipMemcpyDeviceToHost, s));
+  PA_HIP(hipMemcpyAsync(&fail, p.fail, sizeof(int), hipMemcpyDeviceToHost, s));
+  PA_HIP(hipMemcpyAsync(&rmax, p.rmax, sizeof(rmax), hipMemcpyDeviceToHost, s));
   sync_checked(s);
   float ms = 0;
   PA_HIP(hipEventElapsedTime(&ms, e0, e1));
@@ -705,6 +904,11 @@ int pa_bdm2_bind(pa_ctx *ctx, pa_bdm2 *b, void *dev_buf) {
     pa::up(s, b->d.dinv, b->dinv);
     pa::up(s, b->d.cdof, b->cdof);
     pa::up(s, b->d.q, b->q);
+    pa::up(s, b->d.ncell, b->ncell);
+    pa::up(s, b->d.etab, b->etab);
+    pa::up(s, b->d.rloc, b->rloc);
+    pa::up(s, b->d.qtab, b->qtab);
+    pa::up(s, b->d.ftab, b->ftab);
     pa::sync_checked(s);
   });
 }
@@ -716,20 +920,21 @@ int pa_bdm2_set_lambda(pa_bdm2 *b, double lambda_bar) {
   });
 }
 
-int pa_bdm2_workspace_size(const pa_bdm2 *b, int B, const double *t_host, const pa_solve_cfg *cfg,
-                           size_t *bytes) {
+int pa_bdm2_workspace_size(const pa_bdm2 *b, int call, int B, const double *t_host, const pa_avg *avg,
+                           const pa_solve_cfg *cfg, size_t *bytes) {
   return pa::guard([&] {
     pa::bneed(b && bytes && B >= 1, "bad arguments");
-    if (t_host) pa::bneed(b->lambda_bar > 0, "lambda_bar is not set");
-    pa::B2Buf bf;
-    *bytes = pa::b2_plan(b, B, t_host, pa::cfg_of(cfg), nullptr, 0, bf);
+    if (call == PA_BDM2_EXPL) pa::bneed(t_host != nullptr, "t_host is NULL");
+    pa::B2Plan p;
+    *bytes = pa::b2_plan(b, call, B, t_host, avg, pa::cfg_of(cfg), nullptr, 0, p);
   });
 }
 
 int pa_bdm2_apply_L(pa_ctx *ctx, const pa_bdm2 *b, int B, const double *U_dev, double *out_dev, void *ws,
                     size_t ws_bytes, const pa_solve_cfg *cfg, pa_stats *stats) {
   return pa::guard([&] {
-    pa::b2_run(ctx, b, B, nullptr, U_dev, out_dev, ws, ws_bytes, pa::cfg_of(cfg), stats);
+    pa::b2_run(ctx, b, PA_BDM2_APPLY_L, B, nullptr, nullptr, U_dev, out_dev, ws, ws_bytes, pa::cfg_of(cfg),
+               stats);
   });
 }
 
@@ -738,7 +943,26 @@ int pa_bdm2_expL_apply(pa_ctx *ctx, const pa_bdm2 *b, int B, const double *t_hos
                        pa_stats *stats) {
   return pa::guard([&] {
     pa::bneed(t_host != nullptr, "t_host is NULL");
-    pa::b2_run(ctx, b, B, t_host, U_in_dev, U_out_dev, ws, ws_bytes, pa::cfg_of(cfg), stats);
+    pa::b2_run(ctx, b, PA_BDM2_EXPL, B, t_host, nullptr, U_in_dev, U_out_dev, ws, ws_bytes, pa::cfg_of(cfg),
+               stats);
+  });
+}
+
+int pa_bdm2_nonlinear(pa_ctx *ctx, const pa_bdm2 *b, int B, const double *U_dev, double *out_dev, void *ws,
+                      size_t ws_bytes, const pa_solve_cfg *cfg, pa_stats *stats) {
+  return pa::guard([&] {
+    pa::b2_run(ctx, b, PA_BDM2_NONLINEAR, B, nullptr, nullptr, U_dev, out_dev, ws, ws_bytes,
+               pa::cfg_of(cfg), stats);
+  });
+}
+
+int pa_bdm2_phase_avg_rhs(pa_ctx *ctx, const pa_bdm2 *b, const pa_avg *avg, int members, const double *U_dev,
+                          double *Nbar_dev, void *ws, size_t ws_bytes, const pa_solve_cfg *cfg,
+                          pa_stats *stats) {
+  return pa::guard([&] {
+    pa::bneed(avg != nullptr, "avg is NULL");
+    pa::b2_run(ctx, b, PA_BDM2_PHASE_AVG, members, nullptr, avg, U_dev, Nbar_dev, ws, ws_bytes,
+               pa::cfg_of(cfg), stats);
   });
 }
 

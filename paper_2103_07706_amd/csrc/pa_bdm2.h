@@ -16,8 +16,23 @@ namespace pa {
 constexpr int kB2W = 21;   // ELL width of the velocity rows (21 unknowns share a cell with an edge unknown)
 constexpr int kB2WB = 6;   // ELL width of the divergence rows (depth unknowns of the adjacent cells)
 
+// Per-cell table of the nonlinear term, kB2NC doubles a cell: the raw
+// coefficients of the dual basis (C[f][j] at 12 f + j: basis function j is
+// sum_f C[f][j] m_{f/2} e_{f%2}, m = 1, xi, eta, xi^2, xi eta, eta^2 in the
+// scaled coordinates (x - x_T)/h of the cell's frame), the vertices in
+// those coordinates, h, the area, the barycentric gradients, e1 and e2
+// (3D), per side k x n_out (3D), n_out (frame), the length and the sign of
+// the edge (+1: the cell is the edge's first).
+constexpr int kB2NC = 192;
+enum {
+  kNcC = 0, kNcX = 144, kNcH = 150, kNcA = 151, kNcGl = 152, kNcE1 = 158, kNcE2 = 161,
+  kNcNp = 164, kNcNo = 173, kNcLen = 179, kNcSg = 182
+};
+constexpr int kB2VQ = 25;  // volume points (collapsed 5 x 5 rule)
+constexpr int kB2FQ = 4;   // points per side (Gauss-Legendre)
+
 struct B2Dev {
-  int nu = 0, nh = 0, nc = 0;
+  int nu = 0, nh = 0, nc = 0, ne = 0;
   double g = 0;
   const int32_t *col = nullptr;    // [kB2W][nu] column-major
   const double *mass = nullptr;    // [kB2W][nu]
@@ -27,6 +42,11 @@ struct B2Dev {
   const double *dinv = nullptr;    // [nu]
   const int32_t *cdof = nullptr;   // [nc][12] velocity unknowns of each cell
   const double *q = nullptr;       // [nc][3][12]: -H M_h^-1 B^T of the cell
+  const double *ncell = nullptr;   // [nc][kB2NC]
+  const int32_t *etab = nullptr;   // [ne][4]: c0, side in c0, c1, side in c1
+  const int32_t *rloc = nullptr;   // [nu][2]: 12 c + slot of the row's cells (-1: none)
+  const double *qtab = nullptr;    // [kB2VQ][4]: barycentric l0, l1, l2, weight (sum 1)
+  const double *ftab = nullptr;    // [kB2FQ][2]: t in [0, 1], weight (sum 1)
 };
 
 // Per-launch arguments; blocks are row-major [row][Bs].
@@ -36,6 +56,8 @@ struct B2Args {
   double scale;
   const double *u, *eta;          // input state (velocity rows, depth rows)
   const double *addu, *adde;      // addends (nullable): x_0 of the solve, depth
+  const double *rhs;              // given velocity right-hand side (nullable;
+                                  // then the depth rows are not written)
   double *x, *r, *dir;            // solve: iterate, residual, direction
   double *eta_out;
   double c1, c2, theta_inv;
@@ -52,6 +74,36 @@ struct B2Args {
   const double *coef;
 };
 
+// The nonlinear term (one thread per cell or edge and column): raw
+// coefficients of the velocity, upwind traces at the edges' points, the
+// cell integrals (depth rows written, velocity contributions per cell
+// slot), and their sum per velocity row.
+struct B2NlArgs {
+  B2Dev d;
+  int Bs;
+  const double *u, *eta;   // input state (velocity rows, depth rows)
+  double *raw;             // [nc * 12][Bs]
+  double *ut;              // [ne * kB2FQ * 4][Bs]: upwind u (3D), upwind eta
+  double *loc;             // [nc * 12][Bs]
+  double *rhs;             // [nu][Bs]
+  double *eta_out;         // depth rows of N
+};
+void launch_b2_nl(const B2NlArgs &a, hipStream_t s);
+
+// Columns of an averaging pass: column c holds member cmem[c] (-1:
+// padding) at a node of weight cw[c]; members jlo .. jlo + jn - 1 occur.
+struct B2ColArgs {
+  int n, Bs, jlo, jn;
+  const int32_t *cmem;
+  const double *cw;
+  const double *U;    // member-major states [members][n]
+  double *out;        // member-major results, accumulated
+  double *blk;        // bcast: [n][Bs] block of the columns' members
+  const double *src;  // wsum: [n][Bs] block summed into out with the weights
+};
+void launch_b2_bcast(const B2ColArgs &a, hipStream_t s);
+void launch_b2_wsum(const B2ColArgs &a, hipStream_t s);
+
 void launch_b2_stiff(const B2Args &a, hipStream_t s);
 void launch_b2_step(const B2Args &a, hipStream_t s);
 void launch_b2_norm(const B2Args &a, int slot, hipStream_t s);  // partials of |r|^2 -> norms[slot]
@@ -67,7 +119,8 @@ struct pa_bdm2 {
   double g = 0, H = 0, omega = 0, lambda_bar = 0;
   double eig_min = 0, eig_max = 0;  // Ritz bounds of D^-1 M_u
   std::vector<int32_t> col, bcol, cdof;
-  std::vector<double> mass, cor, bval, dinv, q;
+  std::vector<double> mass, cor, bval, dinv, q, ncell, qtab, ftab;
+  std::vector<int32_t> etab, rloc;
   size_t dev_bytes = 0;
   void *dev = nullptr;
   pa::B2Dev d;

@@ -38,6 +38,7 @@ __global__ __launch_bounds__(kBWG) void k_b2_stiff(B2Args a) {
     if (i < nvel) {
       const int row = (int)(i / Bs), c = (int)(i % Bs);
       double fu = 0.0, be = 0.0;
+      if (!a.rhs) {
 #pragma unroll
       for (int s = 0; s < kB2W; s++) {
         const size_t k = (size_t)s * d.nu + row;
@@ -48,12 +49,13 @@ __global__ __launch_bounds__(kBWG) void k_b2_stiff(B2Args a) {
         const size_t k = (size_t)s * d.nu + row;
         be = fma(d.bval[k], a.eta[(size_t)d.bcol[k] * Bs + c], be);
       }
-      const double r = a.scale * (d.g * be - fu);
+      }
+      const double r = a.rhs ? a.rhs[i] : a.scale * (d.g * be - fu);
       a.r[i] = r;
       a.x[i] = a.addu ? a.addu[i] : 0.0;
       a.dir[i] = a.theta_inv * d.dinv[row] * r;
       rr = fma(r, r, rr);
-    } else {
+    } else if (!a.rhs) {
       const size_t j = i - nvel;
       const int row = (int)(j / Bs), c = (int)(j % Bs);
       const int cell = row / 3, qq = row % 3;
@@ -123,7 +125,253 @@ __global__ __launch_bounds__(kBWG) void k_b2_acc(B2Args a) {
     a.acc[i] = fma(a.coef[c], v, a.acc[i]);
   }
 }
+// ---------------------------------------------------------------- N
+// Velocity of a cell (raw coefficients a[12]) at scaled point (xi, et):
+// value and, when J is given, its Jacobian J[c][d] = d u_c / d x_d.
+__device__ inline void b2_eval(const double *a, double xi, double et, double h, double u[2],
+                               double J[2][2]) {
+  const double m[6] = {1.0, xi, et, xi * xi, xi * et, et * et};
+  u[0] = u[1] = 0.0;
+#pragma unroll
+  for (int k = 0; k < 6; k++) {
+    u[0] = fma(m[k], a[2 * k], u[0]);
+    u[1] = fma(m[k], a[2 * k + 1], u[1]);
+  }
+  if (J) {
+    const double mx[6] = {0.0, 1.0, 0.0, 2.0 * xi, et, 0.0};
+    const double my[6] = {0.0, 0.0, 1.0, 0.0, xi, 2.0 * et};
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+      double jx = 0.0, jy = 0.0;
+#pragma unroll
+      for (int k = 0; k < 6; k++) {
+        jx = fma(mx[k], a[2 * k + c], jx);
+        jy = fma(my[k], a[2 * k + c], jy);
+      }
+      J[c][0] = jx / h;
+      J[c][1] = jy / h;
+    }
+  }
+}
+
+// Scaled coordinates and barycentric weights of point t of side s of a cell
+// (t runs from the edge's first vertex to its second: from local vertex
+// s+1 to s+2 in the edge's first cell, the reverse in its second).
+__device__ inline void b2_side_point(const double *T, int s, double t, double &xi, double &et,
+                                     double l[3]) {
+  const int v1 = (s + 1) % 3, v2 = (s + 2) % 3;
+  const bool first = T[kNcSg + s] > 0.0;
+  const int ia = first ? v1 : v2, ib = first ? v2 : v1;
+  xi = (1.0 - t) * T[kNcX + 2 * ia] + t * T[kNcX + 2 * ib];
+  et = (1.0 - t) * T[kNcX + 2 * ia + 1] + t * T[kNcX + 2 * ib + 1];
+  l[0] = l[1] = l[2] = 0.0;
+  l[ia] = 1.0 - t;
+  l[ib] = t;
+}
+
+// raw[12 c + f] = sum_j C[f][j] s_j u[cdof_j]
+__global__ __launch_bounds__(kBWG) void k_b2_raw(B2NlArgs a) {
+  const B2Dev &d = a.d;
+  const int Bs = a.Bs;
+  const size_t total = (size_t)d.nc * Bs, stride = (size_t)gridDim.x * kBWG;
+  for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < total; i += stride) {
+    const int cell = (int)(i / Bs), col = (int)(i % Bs);
+    const double *T = d.ncell + (size_t)kB2NC * cell;
+    double v[12];
+#pragma unroll
+    for (int j = 0; j < 12; j++) {
+      const double sg = j < 9 ? T[kNcSg + j / 3] : 1.0;
+      v[j] = sg * a.u[(size_t)d.cdof[12 * cell + j] * Bs + col];
+    }
+#pragma unroll
+    for (int f = 0; f < 12; f++) {
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < 12; j++) s = fma(T[kNcC + 12 * f + j], v[j], s);
+      a.raw[((size_t)12 * cell + f) * Bs + col] = s;
+    }
+  }
+}
+
+// Upwind traces at the edges' points: the cell the flow leaves (normal
+// flux out of c0 positive: c0, else c1); u as a 3D vector and eta.
+__global__ __launch_bounds__(kBWG) void k_b2_edge(B2NlArgs a) {
+  const B2Dev &d = a.d;
+  const int Bs = a.Bs;
+  const size_t total = (size_t)d.ne * Bs, stride = (size_t)gridDim.x * kBWG;
+  for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < total; i += stride) {
+    const int e = (int)(i / Bs), col = (int)(i % Bs);
+    int cc[2], ss[2];
+    for (int k = 0; k < 2; k++) {
+      cc[k] = d.etab[4 * e + 2 * k];
+      ss[k] = d.etab[4 * e + 2 * k + 1];
+    }
+    double ar[2][12], hc[2][3];
+    for (int k = 0; k < 2; k++) {
+#pragma unroll
+      for (int f = 0; f < 12; f++) ar[k][f] = a.raw[((size_t)12 * cc[k] + f) * Bs + col];
+#pragma unroll
+      for (int r = 0; r < 3; r++) hc[k][r] = a.eta[((size_t)3 * cc[k] + r) * Bs + col];
+    }
+    for (int p = 0; p < kB2FQ; p++) {
+      const double t = d.ftab[2 * p];
+      double u[2][2], hv[2], flux0 = 0.0;
+      for (int k = 0; k < 2; k++) {
+        const double *T = d.ncell + (size_t)kB2NC * cc[k];
+        double xi, et, l[3];
+        b2_side_point(T, ss[k], t, xi, et, l);
+        b2_eval(ar[k], xi, et, T[kNcH], u[k], nullptr);
+        hv[k] = l[0] * hc[k][0] + l[1] * hc[k][1] + l[2] * hc[k][2];
+        if (k == 0) flux0 = u[0][0] * T[kNcNo + 2 * ss[0]] + u[0][1] * T[kNcNo + 2 * ss[0] + 1];
+      }
+      const int w = flux0 > 0.0 ? 0 : 1;
+      const double *T = d.ncell + (size_t)kB2NC * cc[w];
+      double *o = a.ut + ((size_t)(e * kB2FQ + p) * 4) * Bs + col;
+#pragma unroll
+      for (int dd = 0; dd < 3; dd++) o[(size_t)dd * Bs] = u[w][0] * T[kNcE1 + dd] + u[w][1] * T[kNcE2 + dd];
+      o[(size_t)3 * Bs] = hv[w];
+    }
+  }
+}
+
+// Cell integrals: velocity contributions per cell slot (signed), depth rows
+// of N (the block-diagonal M_h solved in closed form).
+__global__ __launch_bounds__(kBWG) void k_b2_cell(B2NlArgs a) {
+  const B2Dev &d = a.d;
+  const int Bs = a.Bs;
+  const size_t total = (size_t)d.nc * Bs, stride = (size_t)gridDim.x * kBWG;
+  for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < total; i += stride) {
+    const int cell = (int)(i / Bs), col = (int)(i % Bs);
+    const double *T = d.ncell + (size_t)kB2NC * cell;
+    const double h = T[kNcH], A = T[kNcA];
+    double ar[12], hc[3], g[12], rh[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int f = 0; f < 12; f++) {
+      ar[f] = a.raw[((size_t)12 * cell + f) * Bs + col];
+      g[f] = 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < 3; r++) hc[r] = a.eta[((size_t)3 * cell + r) * Bs + col];
+    // volume: u . grad^perp(u^perp . m_a e_c) + (div m_a e_c) |u|^2 / 2
+    for (int q = 0; q < kB2VQ; q++) {
+      const double l0 = d.qtab[4 * q], l1 = d.qtab[4 * q + 1], l2 = d.qtab[4 * q + 2];
+      const double w = d.qtab[4 * q + 3] * A;
+      const double xi = l0 * T[kNcX] + l1 * T[kNcX + 2] + l2 * T[kNcX + 4];
+      const double et = l0 * T[kNcX + 1] + l1 * T[kNcX + 3] + l2 * T[kNcX + 5];
+      double u[2], J[2][2];
+      b2_eval(ar, xi, et, h, u, J);
+      const double up[2] = {-u[1], u[0]};
+      const double Jp[2][2] = {{-J[1][0], -J[1][1]}, {J[0][0], J[0][1]}};
+      const double ke = 0.5 * (u[0] * u[0] + u[1] * u[1]);
+      const double m[6] = {1.0, xi, et, xi * xi, xi * et, et * et};
+      const double mx[6] = {0.0, 1.0 / h, 0.0, 2.0 * xi / h, et / h, 0.0};
+      const double my[6] = {0.0, 0.0, 1.0 / h, 0.0, xi / h, 2.0 * et / h};
+#pragma unroll
+      for (int k = 0; k < 6; k++) {
+#pragma unroll
+        for (int c = 0; c < 2; c++) {
+          const double gx = Jp[c][0] * m[k] + up[c] * mx[k];
+          const double gy = Jp[c][1] * m[k] + up[c] * my[k];
+          const double dv = c == 0 ? mx[k] : my[k];
+          g[2 * k + c] = fma(w, -u[0] * gy + u[1] * gx + dv * ke, g[2 * k + c]);
+        }
+      }
+      const double hq = l0 * hc[0] + l1 * hc[1] + l2 * hc[2];
+#pragma unroll
+      for (int r = 0; r < 3; r++)
+        rh[r] = fma(w * hq, T[kNcGl + 2 * r] * u[0] + T[kNcGl + 2 * r + 1] * u[1], rh[r]);
+    }
+    // sides: - |s| w_p ((k x n_out) . u~)(u^perp . m_a e_c) and
+    //        - |s| w_p l_r (u . n_out) eta~
+    for (int s = 0; s < 3; s++) {
+      const int e = d.cdof[12 * cell + 3 * s] / 3;
+      const double len = T[kNcLen + s];
+      for (int p = 0; p < kB2FQ; p++) {
+        const double t = d.ftab[2 * p], wl = len * d.ftab[2 * p + 1];
+        double xi, et, l[3], u[2];
+        b2_side_point(T, s, t, xi, et, l);
+        b2_eval(ar, xi, et, h, u, nullptr);
+        const double *o = a.ut + ((size_t)(e * kB2FQ + p) * 4) * Bs + col;
+        const double sv = T[kNcNp + 3 * s] * o[0] + T[kNcNp + 3 * s + 1] * o[(size_t)Bs] +
+                          T[kNcNp + 3 * s + 2] * o[(size_t)2 * Bs];
+        const double ht = o[(size_t)3 * Bs];
+        const double flux = u[0] * T[kNcNo + 2 * s] + u[1] * T[kNcNo + 2 * s + 1];
+        const double up[2] = {-u[1], u[0]};
+        const double m[6] = {1.0, xi, et, xi * xi, xi * et, et * et};
+#pragma unroll
+        for (int k = 0; k < 6; k++) {
+          g[2 * k] = fma(-wl * sv, up[0] * m[k], g[2 * k]);
+          g[2 * k + 1] = fma(-wl * sv, up[1] * m[k], g[2 * k + 1]);
+        }
+#pragma unroll
+        for (int r = 0; r < 3; r++) rh[r] = fma(-wl * flux * ht, l[r], rh[r]);
+      }
+    }
+    // velocity: slot j gets s_j sum_f C[f][j] g[f]
+#pragma unroll
+    for (int j = 0; j < 12; j++) {
+      double v = 0.0;
+#pragma unroll
+      for (int f = 0; f < 12; f++) v = fma(T[kNcC + 12 * f + j], g[f], v);
+      const double sg = j < 9 ? T[kNcSg + j / 3] : 1.0;
+      a.loc[((size_t)12 * cell + j) * Bs + col] = sg * v;
+    }
+    // depth: M_h^-1 = (12/A)(I - J/4)
+    const double sum = rh[0] + rh[1] + rh[2];
+#pragma unroll
+    for (int r = 0; r < 3; r++) a.eta_out[((size_t)3 * cell + r) * Bs + col] = (12.0 / A) * (rh[r] - 0.25 * sum);
+  }
+}
+
+// rhs[row] = the (one or two) cell slots of the row
+__global__ __launch_bounds__(kBWG) void k_b2_gather(B2NlArgs a) {
+  const B2Dev &d = a.d;
+  const int Bs = a.Bs;
+  const size_t total = (size_t)d.nu * Bs, stride = (size_t)gridDim.x * kBWG;
+  for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < total; i += stride) {
+    const int row = (int)(i / Bs), col = (int)(i % Bs);
+    const int p0 = d.rloc[2 * row], p1 = d.rloc[2 * row + 1];
+    double v = a.loc[(size_t)p0 * Bs + col];
+    if (p1 >= 0) v += a.loc[(size_t)p1 * Bs + col];
+    a.rhs[i] = v;
+  }
+}
+__global__ __launch_bounds__(kBWG) void k_b2_bcast(B2ColArgs a) {
+  const size_t total = (size_t)a.n * a.Bs, stride = (size_t)gridDim.x * kBWG;
+  for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < total; i += stride) {
+    const int row = (int)(i / a.Bs), c = (int)(i % a.Bs);
+    const int m = a.cmem[c];
+    a.blk[i] = m >= 0 ? a.U[(size_t)m * a.n + row] : 0.0;
+  }
+}
+
+// out[j][row] += sum over the columns c of member j of cw[c] src[row][c]
+// (columns in increasing order).
+__global__ __launch_bounds__(kBWG) void k_b2_wsum(B2ColArgs a) {
+  const size_t total = (size_t)a.jn * a.n, stride = (size_t)gridDim.x * kBWG;
+  for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < total; i += stride) {
+    const int j = a.jlo + (int)(i / a.n), row = (int)(i % a.n);
+    double v = 0.0;
+    for (int c = 0; c < a.Bs; c++)
+      if (a.cmem[c] == j) v = fma(a.cw[c], a.src[(size_t)row * a.Bs + c], v);
+    a.out[(size_t)j * a.n + row] += v;
+  }
+}
 }  // namespace
+
+void launch_b2_bcast(const B2ColArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_b2_bcast, dim3(b2_grid(a.n, a.Bs)), dim3(kBWG), 0, s, a);
+}
+void launch_b2_wsum(const B2ColArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_b2_wsum, dim3(b2_grid(a.n, a.jn)), dim3(kBWG), 0, s, a);
+}
+
+void launch_b2_nl(const B2NlArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_b2_raw, dim3(b2_grid(a.d.nc, a.Bs)), dim3(kBWG), 0, s, a);
+  hipLaunchKernelGGL(k_b2_edge, dim3(b2_grid(a.d.ne, a.Bs)), dim3(kBWG), 0, s, a);
+  hipLaunchKernelGGL(k_b2_cell, dim3(b2_grid(a.d.nc, a.Bs)), dim3(kBWG), 0, s, a);
+  hipLaunchKernelGGL(k_b2_gather, dim3(b2_grid(a.d.nu, a.Bs)), dim3(kBWG), 0, s, a);
+}
 
 int b2_grid(int rows, int Bs) {
   const size_t n = (size_t)rows * Bs;

@@ -112,6 +112,39 @@ def p1dg_bumps_state(verts, cell_verts, ne: int, nbumps: int, seed: int,
     return np.concatenate([np.zeros(3 * ne + 3 * len(cv)), ev[cv].ravel()])
 
 
+def bdm2_bumps_state(verts, cell_verts, edge_cells, edge_verts, nbumps: int, seed: int,
+                     phys: Physics = Physics(), width: float = 1.0e6):
+    """The bumps of gaussian_bumps_state on the BDM2 x P1DG unknowns: the
+    same stream function psi at the vertices, its continuous piecewise-
+    linear interpolant psi_h, and u = k x grad psi_h (constant in each flat
+    cell, divergence free, held exactly by BDM2): normal flux density
+    (psi(a) - psi(b)) / |b - a| at all three points of each edge, moments
+    u . e1, u . e2 and 0 in each cell (e1 from the cell's vertex 0 to 1,
+    e2 = k x e1); depth: the bump sum at each cell's vertices."""
+    verts = np.asarray(verts, dtype=np.float64)
+    tri = np.asarray(cell_verts)
+    ev = np.asarray(edge_verts)
+    amp, cen, zc = bump_params(seed, nbumps)
+    fmin = math.sin(math.radians(10.0))
+    fb = np.array([2.0 * phys.omega * (1.0 if z >= 0 else -1.0) * max(abs(z), fmin)
+                   for z in zc])
+    psi = _bump_sum(verts, amp, cen, phys.g / fb, phys.radius, width)
+    eta = _bump_sum(verts, amp, cen, np.ones(nbumps), phys.radius, width)
+    flux = (psi[ev[:, 0]] - psi[ev[:, 1]]) / np.linalg.norm(verts[ev[:, 1]] - verts[ev[:, 0]], axis=1)
+    P = verts[tri]
+    k = np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0])
+    twoA = np.linalg.norm(k, axis=1)
+    k /= twoA[:, None]
+    grad = sum(psi[tri[:, r], None] * np.cross(k, P[:, (r + 2) % 3] - P[:, (r + 1) % 3])
+               for r in range(3)) / twoA[:, None]
+    u = np.cross(k, grad)
+    e1 = (P[:, 1] - P[:, 0]) / np.linalg.norm(P[:, 1] - P[:, 0], axis=1)[:, None]
+    e2 = np.cross(k, e1)
+    mom = np.stack([np.einsum("cd,cd->c", u, e1), np.einsum("cd,cd->c", u, e2),
+                    np.zeros(len(tri))], 1)
+    return np.concatenate([np.repeat(flux, 3), mom.ravel(), eta[tri].ravel()])
+
+
 def random_state(nu: int, nh: int, seed: int, u_scale: float = 10.0,
                  eta_scale: float = 50.0):
     """Independent normal unknowns (numpy's PCG64 stream of the seed):

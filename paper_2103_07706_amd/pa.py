@@ -19,6 +19,7 @@ PA_FP64, PA_FP32_REFINED = 0, 1
 PA_BACKWARD_PER_TERM, PA_BACKWARD_CLENSHAW = 0, 1
 PA_SOLVER_CG, PA_SOLVER_CHEBYSHEV = 0, 1
 PA_EXP_CHEBYSHEV, PA_EXP_REXI = 0, 1
+PA_BDM2_APPLY_L, PA_BDM2_EXPL, PA_BDM2_NONLINEAR, PA_BDM2_PHASE_AVG = range(4)
 PA_OK, PA_EINVAL, PA_ENOMEM, PA_EHIP, PA_ENOCONV, PA_ENOTSUP, PA_EGROWTH = range(7)
 _STATUS = {0: "PA_OK", 1: "PA_EINVAL", 2: "PA_ENOMEM", 3: "PA_EHIP", 4: "PA_ENOCONV",
            5: "PA_ENOTSUP", 6: "PA_EGROWTH"}
@@ -145,8 +146,12 @@ EXPORTS = {
     "pa_bdm2_device_size": (ctypes.c_int, [_V, ctypes.POINTER(_SZ)]),
     "pa_bdm2_bind": (ctypes.c_int, [_V, _V, _V]),
     "pa_bdm2_set_lambda": (ctypes.c_int, [_V, ctypes.c_double]),
-    "pa_bdm2_workspace_size": (ctypes.c_int, [_V, ctypes.c_int, _D, ctypes.POINTER(SolveCfg),
-                                              ctypes.POINTER(_SZ)]),
+    "pa_bdm2_workspace_size": (ctypes.c_int, [_V, ctypes.c_int, ctypes.c_int, _D, _V,
+                                              ctypes.POINTER(SolveCfg), ctypes.POINTER(_SZ)]),
+    "pa_bdm2_nonlinear": (ctypes.c_int, [_V, _V, ctypes.c_int, _V, _V, _V, _SZ,
+                                         ctypes.POINTER(SolveCfg), ctypes.POINTER(Stats)]),
+    "pa_bdm2_phase_avg_rhs": (ctypes.c_int, [_V, _V, _V, ctypes.c_int, _V, _V, _V, _SZ,
+                                             ctypes.POINTER(SolveCfg), ctypes.POINTER(Stats)]),
     "pa_bdm2_apply_L": (ctypes.c_int, [_V, _V, ctypes.c_int, _V, _V, _V, _SZ,
                                        ctypes.POINTER(SolveCfg), ctypes.POINTER(Stats)]),
     "pa_bdm2_expL_apply": (ctypes.c_int, [_V, _V, ctypes.c_int, _D, _V, _V, _V, _SZ,
@@ -613,14 +618,20 @@ class BDM2:
     def set_lambda(self, lambda_bar):
         _check(lib().pa_bdm2_set_lambda(self._h, float(lambda_bar)))
 
-    def _workspace(self, B, t, cfg):
-        import torch
+    def workspace_size(self, call, B, t=None, avg=None, cfg=None):
+        cfg = cfg or solve_cfg()
         sz = _SZ()
-        _check(lib().pa_bdm2_workspace_size(self._h, B, None if t is None else _dp(t),
-                                            ctypes.byref(cfg), ctypes.byref(sz)))
-        if self._ws is None or self._ws.numel() < sz.value + 256:
+        _check(lib().pa_bdm2_workspace_size(self._h, call, B, None if t is None else _dp(t),
+                                            None if avg is None else avg._h, ctypes.byref(cfg),
+                                            ctypes.byref(sz)))
+        return sz.value
+
+    def _workspace(self, call, B, t, cfg, avg=None):
+        import torch
+        need = self.workspace_size(call, B, t, avg, cfg)
+        if self._ws is None or self._ws.numel() < need + 256:
             self._ws = None
-            self._ws = torch.empty(sz.value + 256, dtype=torch.uint8,
+            self._ws = torch.empty(need + 256, dtype=torch.uint8,
                                    device=f"cuda:{self.ctx.device}")
         base = self._ws.data_ptr()
         off = (-base) % 256
@@ -630,7 +641,7 @@ class BDM2:
         cfg = cfg or solve_cfg()
         B = U.shape[0]
         out = U.new_empty(U.shape) if out is None else out
-        ws, nb = self._workspace(B, None, cfg)
+        ws, nb = self._workspace(PA_BDM2_APPLY_L, B, None, cfg)
         st = Stats()
         _check(lib().pa_bdm2_apply_L(self.ctx._h, self._h, B, _ptr(U), _ptr(out), ws, nb,
                                      ctypes.byref(cfg), ctypes.byref(st)))
@@ -641,10 +652,31 @@ class BDM2:
         B = U.shape[0]
         t = np.ascontiguousarray(np.broadcast_to(np.asarray(t, np.float64), (B,)))
         out = U.new_empty(U.shape) if out is None else out
-        ws, nb = self._workspace(B, t, cfg)
+        ws, nb = self._workspace(PA_BDM2_EXPL, B, t, cfg)
         st = Stats()
         _check(lib().pa_bdm2_expL_apply(self.ctx._h, self._h, B, _dp(t), _ptr(U), _ptr(out), ws,
                                         nb, ctypes.byref(cfg), ctypes.byref(st)))
+        return out, st.as_dict()
+
+    def nonlinear(self, U, cfg=None, out=None):
+        cfg = cfg or solve_cfg()
+        B = U.shape[0]
+        out = U.new_empty(U.shape) if out is None else out
+        ws, nb = self._workspace(PA_BDM2_NONLINEAR, B, None, cfg)
+        st = Stats()
+        _check(lib().pa_bdm2_nonlinear(self.ctx._h, self._h, B, _ptr(U), _ptr(out), ws, nb,
+                                       ctypes.byref(cfg), ctypes.byref(st)))
+        return out, st.as_dict()
+
+    def phase_avg_rhs(self, avg: Avg, U, cfg=None, out=None):
+        cfg = cfg or solve_cfg()
+        members = U.shape[0]
+        out = U.new_empty(U.shape) if out is None else out
+        ws, nb = self._workspace(PA_BDM2_PHASE_AVG, members, None, cfg, avg)
+        st = Stats()
+        _check(lib().pa_bdm2_phase_avg_rhs(self.ctx._h, self._h, avg._h, members, _ptr(U),
+                                           _ptr(out), ws, nb, ctypes.byref(cfg),
+                                           ctypes.byref(st)))
         return out, st.as_dict()
 
     def __del__(self):

@@ -97,13 +97,27 @@ def test_bdm2_refuses_topography_and_bad_sizes(oracle_mesh):
     assert pa.lib().pa_bdm2_create(m._h, ctypes.byref(ph), ctypes.byref(h)) == pa.PA_EINVAL
     sz = ctypes.c_size_t()
     cfg = pa.solve_cfg()
-    assert pa.lib().pa_bdm2_workspace_size(b._h, 65, None, ctypes.byref(cfg),
-                                           ctypes.byref(sz)) == pa.PA_ENOTSUP
-    # an exponential needs lambda_bar
+    W = pa.lib().pa_bdm2_workspace_size
+    assert W(b._h, pa.PA_BDM2_APPLY_L, 65, None, None, ctypes.byref(cfg),
+             ctypes.byref(sz)) == pa.PA_ENOTSUP
+    assert W(b._h, 7, 1, None, None, ctypes.byref(cfg), ctypes.byref(sz)) == pa.PA_EINVAL
+    # an exponential needs lambda_bar and its times, an average its nodes
     t = np.array([100.0])
-    assert pa.lib().pa_bdm2_workspace_size(b._h, 1, pa._dp(t), ctypes.byref(cfg),
-                                           ctypes.byref(sz)) == pa.PA_EINVAL
+    avg = pa.Avg(8, 3600.0)
+    assert W(b._h, pa.PA_BDM2_EXPL, 1, pa._dp(t), None, ctypes.byref(cfg),
+             ctypes.byref(sz)) == pa.PA_EINVAL
+    assert W(b._h, pa.PA_BDM2_PHASE_AVG, 1, None, avg._h, ctypes.byref(cfg),
+             ctypes.byref(sz)) == pa.PA_EINVAL
     b.set_lambda(1e-2)
-    assert pa.lib().pa_bdm2_workspace_size(b._h, 1, pa._dp(t), ctypes.byref(cfg),
-                                           ctypes.byref(sz)) == 0
+    assert W(b._h, pa.PA_BDM2_EXPL, 1, None, None, ctypes.byref(cfg),
+             ctypes.byref(sz)) == pa.PA_EINVAL
+    assert W(b._h, pa.PA_BDM2_PHASE_AVG, 1, None, None, ctypes.byref(cfg),
+             ctypes.byref(sz)) == pa.PA_EINVAL
+    assert W(b._h, pa.PA_BDM2_EXPL, 1, pa._dp(t), None, ctypes.byref(cfg),
+             ctypes.byref(sz)) == 0
     assert sz.value > 0
+    # an average over 100 members x 8 nodes runs 64 columns at a time: past
+    # the first chunk only the per-chunk weight tables grow
+    sizes = [b.workspace_size(pa.PA_BDM2_PHASE_AVG, mem, avg=avg) for mem in (1, 8, 100)]
+    assert sizes[0] < sizes[1] and sizes[2] < 1.25 * sizes[1]
+    assert b.workspace_size(pa.PA_BDM2_NONLINEAR, 3) > b.workspace_size(pa.PA_BDM2_APPLY_L, 3)

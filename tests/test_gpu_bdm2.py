@@ -171,3 +171,86 @@ def test_gpu_bdm2_errors():
     bad = _cfg(cg_rtol=0.0)
     with pytest.raises(pa.PAError):
         lb.apply_L(U, bad)
+
+
+# ---------------------------------------------------------------- N and Nbar
+def _smooth(om, seeds):
+    """Geostrophic depth bumps (inputs.bdm2_bumps_state): the velocity
+    divergence free and constant in each cell, the depth smooth."""
+    from paper_2103_07706_amd import inputs
+    return np.stack([inputs.bdm2_bumps_state(om.verts, om.cell_verts, om.edge_cells, om.edge_verts,
+                                             6, s) for s in seeds])
+
+
+@pytest.mark.parametrize("level,B", [(0, 1), (3, 3), (2, 64)])
+def test_gpu_bdm2_nonlinear_parity(level, B):
+    """N of Sec. 2.5 on the pair for random states.  Every facet point's
+    upwind side is decided by an FP64 flux on both sides; a flux within
+    rounding of zero could be decided differently, which random states
+    make vanishingly unlikely (it would show as one large entry)."""
+    ob, lb, lm = _pair(level)
+    U = _states(ob, range(B))
+    out, st = lb.nonlinear(_dev(U), _cfg())
+    got = out.cpu().numpy()
+    for j in range(B):
+        ref = ob.nonlinear(U[j])
+        _close(got[j, :ob.nu], ref[:ob.nu], 1e-10, f"u col {j}")
+        _close(got[j, ob.nu:], ref[ob.nu:], 1e-12, f"eta col {j}")
+    assert st["solves"] == 1 and 0 < st["resid_max"] <= 1e-13
+
+
+def test_gpu_bdm2_phase_avg_rhs_parity():
+    """Nbar for two members with M = 8 nodes over T = 3600 s (16 columns in
+    one pass) and for nine members (72 columns: two passes, the second
+    ragged), against the oracle's composition; the same call twice gives
+    the same bits."""
+    import oracle
+    from paper_2103_07706_amd import pa
+    ob, lb, lm = _pair(3)
+    om = oracle.Mesh(3)
+    lam = 1.05 * ob.rho()
+    lb.set_lambda(lam)
+    avg = pa.Avg(8, 3600.0)
+    s, w = oracle.avg_nodes(8, 3600.0)
+    for members in (2, 9):
+        U = _smooth(om, range(members))
+        out, st = lb.phase_avg_rhs(avg, _dev(U), _cfg())
+        got = out.cpu().numpy()
+        for j in sorted({0, members - 1}):
+            ref = ob.phase_avg_rhs(lam, s, w, U[j], tol=1e-12)
+            _close(got[j, :ob.nu], ref[:ob.nu], 1e-9, f"u member {j} of {members}")
+            _close(got[j, ob.nu:], ref[ob.nu:], 1e-9, f"eta member {j} of {members}")
+        assert st["terms"] == 8 * members
+        assert 0 < st["resid_max"] <= 1e-13
+    again, _ = lb.phase_avg_rhs(avg, _dev(U), _cfg())
+    assert np.array_equal(again.cpu().numpy(), got)
+
+
+def test_gpu_bdm2_phase_avg_rhs_level5():
+    """Level 5 (153600 velocity and 61440 depth unknowns).  64 members x
+    M = 8 nodes, eight passes of 64 columns: members repeat every seven, so
+    equal inputs sit in different passes and columns and must give equal
+    bits; every member's depth mass is conserved (N conserves it, the
+    exponentials keep it).  One member at M = 2 against the oracle (its
+    M = 8 average takes minutes on the host)."""
+    import oracle
+    from paper_2103_07706_amd import pa
+    ob, lb, lm = _pair(5)
+    om = oracle.Mesh(5)
+    lam = 1.1 * 2.0 * BDM2P1DG(oracle.Mesh(4)).rho()
+    lb.set_lambda(lam)
+    cfg = _cfg(cheb_tol=1e-10)
+    U = _smooth(om, [j % 7 for j in range(64)])
+    out, st = lb.phase_avg_rhs(pa.Avg(8, 3600.0), _dev(U), cfg)
+    got = out.cpu().numpy()
+    assert st["terms"] == 512
+    for j in range(7, 64):
+        assert np.array_equal(got[j], got[j - 7]), j
+    area3 = np.repeat(ob.area / 3.0, 3)
+    dm = got[:, ob.nu:] @ area3
+    scale = np.abs(got[:, ob.nu:]) @ area3
+    assert np.all(np.abs(dm) <= 1e-11 * scale)
+    one, _ = lb.phase_avg_rhs(pa.Avg(2, 3600.0), _dev(U[:1]), cfg)
+    s, w = oracle.avg_nodes(2, 3600.0)
+    ref = ob.phase_avg_rhs(lam, s, w, U[0], tol=1e-10)
+    _close(one.cpu().numpy()[0], ref, 1e-8, "member 0, M = 2")

@@ -352,3 +352,28 @@ def test_bdm2_phase_avg_rhs_substitutions_and_limit(bdm):
         errs.append(np.linalg.norm(b.phase_avg_rhs(lam, s, w, U) - N0) / np.linalg.norm(N0))
     print("T -> 0:", errs)
     assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5, errs
+
+
+def test_bdm2_bumps_state_is_the_interpolant(bdm):
+    """The input generator's BDM2 state (inputs.bdm2_bumps_state) holds the
+    unknowns of u = k x grad psi_h as this test's own geometry computes them
+    (normal flux density out of c0, moments), and that field is divergence
+    free: L leaves the depth of a state with that velocity untouched."""
+    import math
+    from paper_2103_07706_amd import inputs
+    b = bdm(2)
+    m = b.mesh
+    U = inputs.bdm2_bumps_state(m.verts, m.cell_verts, m.edge_cells, m.edge_verts, 5, 3)
+    assert U.shape == (b.n,)
+    ph = inputs.Physics()
+    amp, cen, zc = inputs.bump_params(3, 5)
+    fb = np.array([2 * ph.omega * (1.0 if z >= 0 else -1.0) * max(abs(z), math.sin(math.radians(10)))
+                   for z in zc])
+    p = np.asarray(m.verts) / np.linalg.norm(m.verts, axis=1)[:, None]
+    psi = sum(ph.g / fb[i] * amp[i] * np.exp(-(ph.radius * np.arccos(np.clip(p @ cen[i], -1, 1))
+                                               / 1e6) ** 2) for i in range(5))
+    ref, _ = _pc_field(m, psi)
+    assert np.abs(U[:b.nu] - ref).max() <= 1e-9 * np.abs(ref).max()
+    Ld = b.apply_L(np.concatenate([U[:b.nu], np.zeros(b.nh)]))[b.nu:]
+    Lr = b.apply_L(np.concatenate([U[:b.nu][::-1], np.zeros(b.nh)]))[b.nu:]
+    assert np.abs(Ld).max() <= 1e-9 * np.abs(Lr).max()
