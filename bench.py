@@ -264,7 +264,56 @@ def secondary_workloads(pa, ctx, steps=3, warmup=1):
         el = time.perf_counter() - t0
         res[name] = {"value": members * steps / el, "ms_per_step": 1e3 * el / steps}
     out["mixed_l4l5l6"] = {"unit": "member-Nbar/s", "items": items, "M": 64, "forms": res}
+    del batch, bops, Us, outs
+    out["bdm2_l5_m64"] = bdm2_workload(pa, ctx, steps=steps, warmup=warmup)
     return out
+
+
+def bdm2_workload(pa, ctx, steps=3, warmup=1):
+    """Nbar on the paper's own spaces (BDM2 velocity, P1DG depth) at level 5
+    (its N_C = 20480 grid), one member of 40 geostrophic bumps, M = 64 nodes
+    over T = 2 h (64 columns, one pass), FP64 at the metric tolerances;
+    lambda_bar from the library's power iteration.  Also the mass-solve
+    step kernel's time and algorithmic bytes (pa_ctx_profile) over one
+    evaluation."""
+    import numpy as np
+    import torch
+
+    from paper_2103_07706_amd import inputs
+    phys = inputs.Physics()
+    mesh = pa.Mesh(5)
+    b = pa.BDM2(mesh, g=phys.g, H=phys.H, omega=phys.omega).bind(ctx)
+    lam = b.estimate_lambda(iters=200, safety=1.05)
+    U = torch.tensor(inputs.bdm2_bumps_state(mesh.verts, mesh.cell_verts, mesh.edge_cells,
+                                             mesh.edge_verts, 40, 0, phys)[None],
+                     dtype=torch.float64, device="cuda:0")
+    avg = pa.Avg(64, 7200.0)
+    cfg = pa.solve_cfg(cg_rtol=1e-10, cheb_tol=1e-6)
+    out = torch.empty_like(U)
+    for _ in range(warmup):
+        b.phase_avg_rhs(avg, U, cfg, out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = None
+    for i in range(steps):
+        _, st = b.phase_avg_rhs(avg, U, cfg, out=out)
+        print(f"bdm2 step {i} {st['device_ms']:.1f} ms", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.profile(pa.PA_KERNEL_B2_STEP)
+    b.phase_avg_rhs(avg, U, cfg, out=out)
+    prof = ctx.profile_read()
+    ctx.profile(pa.PA_KERNEL_NONE)
+    gbs = prof["bytes"] / (prof["total_ms"] * 1e-3) / 1e9
+    return {"unit": "Nbar/s", "level": 5, "M": 64, "T": 7200.0, "members": 1,
+            "nu": b.nu, "nh": b.nh, "lambda_bar": lam,
+            "value": steps / el, "ms_per_step": 1e3 * el / steps,
+            "solves": st["solves"], "steps_per_solve": st["cg_iters_max"], "kmax": st["kmax"],
+            "resid_max": st["resid_max"],
+            "k_b2_step": {"launches": prof["launches"],
+                          "avg_us": 1e3 * prof["total_ms"] / max(prof["launches"], 1),
+                          "GB/s": gbs, "frac_hbm": gbs / 8000.0,
+                          "bytes_per_launch": prof["bytes"] / max(prof["launches"], 1)}}
 
 
 def bench_batch(args):
@@ -359,6 +408,18 @@ def main():
     from paper_2103_07706_amd import inputs
     if args.workload in inputs.BATCHES:
         bench_batch(args)
+        return
+    if args.workload == "bdm2_l5_m64":
+        from paper_2103_07706_amd import pa
+        r = bdm2_workload(pa, pa.Context(0), steps=args.steps, warmup=args.warmup)
+        print(json.dumps({"metric": "BDM2/P1DG phase-avg RHS evals/s (level 5, M=64)",
+                          "value": r["value"], "unit": "Nbar/s", "n_gpus": 1, "steps": args.steps,
+                          "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                          "dtype": "f64", "data": "synthetic",
+                          "config": {"workload": "bdm2_l5_m64", "level": 5, "M": 64, "T_s": 7200.0,
+                                     "members": 1, "spaces": "BDM2/P1DG"},
+                          "detail": r}), flush=True)
         return
     import numpy as np
     import torch

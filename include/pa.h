@@ -347,13 +347,15 @@ int pa_diagnostics(pa_ctx *ctx, const pa_ops *ops, int B, const double *U_dev,
  *   PA_KERNEL_CHEB_FUSED   fused single-column steps (k_cheb_fused)
  *   PA_KERNEL_CHEB3_ITER   three-term block step (k_cheb3_iter)
  *   PA_KERNEL_CHEB32_ITER  FP32 three-term step (k_cheb32_iter[4])
+ *   PA_KERNEL_B2_STEP      BDM2 mass-solve step (k_b2_step: per row the ELL
+ *                          row and D^-1, 260 bytes; per row and column 48)
  * pa_ctx_profile starts a new tally (PA_KERNEL_NONE switches it off and
  * graph capture is not used while it is on); pa_ctx_profile_read returns the
  * tally so far.  The calls made while the hook is on fill it; reading needs
  * no further synchronisation. */
 enum { PA_KERNEL_NONE = 0, PA_KERNEL_CG_ITER = 1, PA_KERNEL_CHEB_ITER = 2,
        PA_KERNEL_CHEB_LP_ITER = 3, PA_KERNEL_CHEB_FUSED = 4, PA_KERNEL_CHEB3_ITER = 5,
-       PA_KERNEL_CHEB32_ITER = 6 };
+       PA_KERNEL_CHEB32_ITER = 6, PA_KERNEL_B2_STEP = 7 };
 typedef struct {
   int64_t launches;   /* launches of the kernel */
   int64_t work_launches; /* launches that found active columns */
@@ -591,6 +593,13 @@ int pa_bdm2_tables(const pa_bdm2 *b, int32_t *col, double *mass, double *cor,
 int pa_bdm2_device_size(const pa_bdm2 *b, size_t *bytes);
 int pa_bdm2_bind(pa_ctx *ctx, pa_bdm2 *b, void *dev_buf);
 int pa_bdm2_set_lambda(pa_bdm2 *b, double lambda_bar);
+/* Power iteration on the GPU, v <- -L^2 v normalised in the energy norm
+ * H u' M_u u + g eta' M_h eta (L is skew in it), from a fixed start vector
+ * (a counter hash of the index); sets lambda_bar = safety * the estimate of
+ * rho(L), which approaches rho(L) from below.  Mass solves to 1e-12.
+ * Needs a workspace of pa_bdm2_workspace_size(b, PA_BDM2_APPLY_L, 1, ...). */
+int pa_bdm2_estimate_lambda(pa_ctx *ctx, pa_bdm2 *b, int iters, double safety,
+                            void *ws_dev, size_t ws_bytes, double *lambda_bar);
 /* Workspace bytes of a call: call is one of the PA_BDM2_* values below, B
  * the number of states (members for PA_BDM2_PHASE_AVG); t_host the B times
  * of PA_BDM2_EXPL (the degree depends on them), avg the nodes of

@@ -414,13 +414,51 @@ struct B2Plan {
   std::vector<double> hF, hB;     // [nchunk][kmax + 1][Bs]: forward, backward weights
   std::vector<int32_t> cmem;      // [nchunk][Bs]: member of each column (-1: padding)
   std::vector<double> cw;         // [nchunk][Bs]: averaging weight of each column
+  // shared-basis average (PA_BACKWARD_CLENSHAW): groups of G members
+  bool shared = false;
+  int G = 0, Gs = 0, Mk = 0, Vs = 0, nvch = 0, ngroup = 0;
+  std::vector<double> cfh, cbh;   // [kmax + 1][Mk]: c_k(s_m), w_m c_k(-s_m)
+  double *basis = nullptr, *V = nullptr, *Y = nullptr, *cfd = nullptr, *cbd = nullptr;
   double *Ra = nullptr, *Rb = nullptr, *acc = nullptr, *r = nullptr, *dir[2] = {nullptr, nullptr};
   double *raw = nullptr, *ut = nullptr, *loc = nullptr, *rhs = nullptr;
   double *part = nullptr, *norms = nullptr, *coefF = nullptr, *coefB = nullptr, *cwd = nullptr;
   int32_t *cmemd = nullptr;
   int *fail = nullptr;
   unsigned long long *rmax = nullptr;
+  // measurement hook (PA_KERNEL_B2_STEP): one event pair around the steps of
+  // each mass solve, with the steps' algorithmic bytes and units
+  pa_ctx *ctx = nullptr;
+  mutable std::vector<std::pair<hipEvent_t, hipEvent_t>> spans;
+  mutable double prof_launches = 0, prof_bytes = 0, prof_units = 0;
 };
+
+hipEvent_t prof_event(pa_ctx *ctx) {
+  if (!ctx->prof_pool.empty()) {
+    hipEvent_t e = ctx->prof_pool.back();
+    ctx->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  PA_HIP(hipEventCreate(&e));
+  return e;
+}
+
+// After the call's synchronisation: add the spans to the context's tally.
+void prof_collect(const B2Plan &p) {
+  if (!p.ctx || p.ctx->prof_kernel != PA_KERNEL_B2_STEP) return;
+  for (auto &e : p.spans) {
+    float t = 0;
+    PA_HIP(hipEventElapsedTime(&t, e.first, e.second));
+    p.ctx->prof_ms += t;
+    p.ctx->prof_pool.push_back(e.first);
+    p.ctx->prof_pool.push_back(e.second);
+  }
+  p.spans.clear();
+  p.ctx->prof_launches += (int64_t)p.prof_launches;
+  p.ctx->prof_work += (int64_t)p.prof_launches;
+  p.ctx->prof_bytes += p.prof_bytes;
+  p.ctx->prof_units += p.prof_units;
+}
 
 template <class T>
 T *take(char *base, size_t &off, size_t cap, size_t n) {
@@ -476,6 +514,55 @@ size_t b2_plan(const pa_bdm2 *b, int call, int B, const double *t, const pa_avg 
     rho = rn;
   }
   std::vector<std::vector<double>> tF, tB;  // per chunk: forward and backward times
+  p.shared = call == kCallNbar && cfg.backward == PA_BACKWARD_CLENSHAW;
+  if (p.shared) {
+    bneed(avg != nullptr, "no averaging nodes");
+    double wmax = 0.0;
+    for (double w : avg->w) wmax = std::max(wmax, w);
+    std::vector<int> keep;
+    for (size_t m = 0; m < avg->w.size(); m++)
+      if (avg->w[m] >= cfg.weight_cut * wmax && avg->w[m] != 0.0) keep.push_back((int)m);
+    bneed(!keep.empty(), "no averaging term left");
+    p.Mk = (int)keep.size();
+    p.G = std::max(1, std::min(B, 64 / p.Mk));
+    p.Gs = pad_cols(p.G);
+    p.ngroup = (B + p.G - 1) / p.G;
+    const int cols = p.G * p.Mk;
+    p.Vs = pad_cols(std::min(cols, 64));
+    p.nvch = (cols + p.Vs - 1) / p.Vs;
+    p.Bs = p.Vs;  // the wide blocks (N and its solve)
+    std::vector<double> c;
+    p.kmax = 0;
+    for (int m : keep) p.kmax = std::max(p.kmax, exp_weights(b->lambda_bar, avg->s[m], cfg.cheb_tol, c));
+    p.cfh.assign((size_t)(p.kmax + 1) * p.Mk, 0.0);
+    p.cbh.assign((size_t)(p.kmax + 1) * p.Mk, 0.0);
+    for (int i = 0; i < p.Mk; i++) {
+      const int m = keep[i];
+      int K = exp_weights(b->lambda_bar, avg->s[m], cfg.cheb_tol, c);
+      for (int k = 0; k <= K; k++) p.cfh[(size_t)k * p.Mk + i] = c[k];
+      K = exp_weights(b->lambda_bar, -avg->s[m], cfg.cheb_tol, c);
+      for (int k = 0; k <= K; k++) p.cbh[(size_t)k * p.Mk + i] = avg->w[m] * c[k];
+    }
+    const size_t n = (size_t)b->nu + b->nh;
+    size_t off = 0;
+    p.basis = take<double>(ws, off, cap, (size_t)(p.kmax + 1) * n * p.Gs);
+    p.V = take<double>(ws, off, cap, (size_t)p.nvch * n * p.Vs);
+    p.Y = take<double>(ws, off, cap, (size_t)p.nvch * n * p.Vs);
+    p.r = take<double>(ws, off, cap, (size_t)b->nu * 64);
+    p.dir[0] = take<double>(ws, off, cap, (size_t)b->nu * 64);
+    p.dir[1] = take<double>(ws, off, cap, (size_t)b->nu * 64);
+    p.raw = take<double>(ws, off, cap, (size_t)12 * b->nc * p.Vs);
+    p.loc = take<double>(ws, off, cap, (size_t)12 * b->nc * p.Vs);
+    p.ut = take<double>(ws, off, cap, (size_t)4 * kB2FQ * b->ne * p.Vs);
+    p.rhs = take<double>(ws, off, cap, (size_t)b->nu * p.Vs);
+    p.part = take<double>(ws, off, cap, (size_t)2048 * 64);
+    p.norms = take<double>(ws, off, cap, (size_t)2 * 64);
+    p.cfd = take<double>(ws, off, cap, p.cfh.size());
+    p.cbd = take<double>(ws, off, cap, p.cbh.size());
+    p.fail = take<int>(ws, off, cap, 2);
+    p.rmax = take<unsigned long long>(ws, off, cap, 1);
+    return off + 4096;
+  }
   if (call == kCallNbar) {
     bneed(avg != nullptr, "no averaging nodes");
     double wmax = 0.0;
@@ -549,6 +636,17 @@ size_t b2_plan(const pa_bdm2 *b, int call, int B, const double *t, const pa_avg 
 // it up, then the residual check.
 void b2_solve(const B2Plan &p, B2Args &a, hipStream_t s, pa_stats &st) {
   launch_b2_stiff(a, s);
+  const bool prof = p.ctx && p.ctx->prof_kernel == PA_KERNEL_B2_STEP && p.steps > 0;
+  if (prof) {
+    p.spans.emplace_back(prof_event(p.ctx), prof_event(p.ctx));
+    PA_HIP(hipEventRecord(p.spans.back().first, s));
+    // per row: the ELL row (21 columns and values) and D^-1; per row and
+    // column: x and r in and out, d in, d' out (not on the last step)
+    const double rows = a.d.nu, cols = a.Bs;
+    p.prof_launches += p.steps;
+    p.prof_bytes += rows * (p.steps * (260.0 + 48.0 * cols) - 8.0 * cols);
+    p.prof_units += (double)p.steps * cols;
+  }
   for (int k = 0; k < p.steps; k++) {
     a.dir_in = p.dir[k & 1];
     a.dir_out = p.dir[(k + 1) & 1];
@@ -557,16 +655,17 @@ void b2_solve(const B2Plan &p, B2Args &a, hipStream_t s, pa_stats &st) {
     a.last = k + 1 == p.steps;
     launch_b2_step(a, s);
   }
+  if (prof) PA_HIP(hipEventRecord(p.spans.back().second, s));
   launch_b2_check(a, s);
   st.solves++;
   st.cg_iters += p.steps;
   st.cg_iters_max = std::max(st.cg_iters_max, p.steps);
 }
 
-B2Args solve_args(const pa_bdm2 *b, const B2Plan &p, const pa_solve_cfg &cfg) {
+B2Args solve_args(const pa_bdm2 *b, const B2Plan &p, const pa_solve_cfg &cfg, int Bs) {
   B2Args a{};
   a.d = b->d;
-  a.Bs = p.Bs;
+  a.Bs = Bs;
   a.r = p.r;
   a.dir = p.dir[0];
   a.theta_inv = 1.0 / p.theta;
@@ -581,9 +680,10 @@ B2Args solve_args(const pa_bdm2 *b, const B2Plan &p, const pa_solve_cfg &cfg) {
 // out = scale L in + add (velocity: M_u^-1 (scale(-F u + g B eta)) + add_u
 // as the solve from x_0 = add_u; depth: scale Q u + add_eta).
 void b2_lapply(const pa_bdm2 *b, const B2Plan &p, const pa_solve_cfg &cfg, hipStream_t s, const double *in,
-               double *out, const double *add, double scale, pa_stats &st) {
-  B2Args a = solve_args(b, p, cfg);
-  const size_t nuB = (size_t)b->nu * p.Bs;
+               double *out, const double *add, double scale, pa_stats &st, int Bs = 0) {
+  if (Bs == 0) Bs = p.Bs;
+  B2Args a = solve_args(b, p, cfg, Bs);
+  const size_t nuB = (size_t)b->nu * Bs;
   a.scale = scale;
   a.u = in;
   a.eta = in + nuB;
@@ -609,7 +709,7 @@ void b2_nl(const pa_bdm2 *b, const B2Plan &p, const pa_solve_cfg &cfg, hipStream
   na.rhs = p.rhs;
   na.eta_out = out + nuB;
   launch_b2_nl(na, s);
-  B2Args a = solve_args(b, p, cfg);
+  B2Args a = solve_args(b, p, cfg, p.Bs);
   a.scale = 1.0;
   a.u = in;
   a.eta = in + nuB;
@@ -708,6 +808,7 @@ void b2_run(pa_ctx *ctx, const pa_bdm2 *b, int call, int B, const double *t, con
   bneed(b->dev != nullptr, "BDM2 operators not bound (pa_bdm2_bind)");
   B2Plan p;
   b2_plan(b, call, B, t, avg, cfg, (char *)ws, ws_bytes, p);
+  p.ctx = ctx;
   PA_HIP(hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
   const int n = b->nu + b->nh, Bs = p.Bs;
@@ -724,7 +825,46 @@ void b2_run(pa_ctx *ctx, const pa_bdm2 *b, int call, int B, const double *t, con
     PA_HIP(hipMemcpyAsync(p.cmemd, p.cmem.data(), p.cmem.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     PA_HIP(hipMemcpyAsync(p.cwd, p.cw.data(), p.cw.size() * sizeof(double), hipMemcpyHostToDevice, s));
   }
-  if (call == kCallNbar) {
+  if (p.shared) {
+    // Nbar_j = sum_m w_m exp(-s_m L) N(exp(s_m L) U_j) with the exponentials
+    // through each member's own basis: forward R_k = P_k(L) U_j on the
+    // member's column (V(j, m) = sum_k c_k(s_m) R_k), N on the node columns,
+    // backward Z_k = sum_m w_m c_k(-s_m) N(V(j, m)) summed by Clenshaw's
+    // recurrence b_k = Z_k + (2/lb) L b_{k+1} + b_{k+2}, Nbar = Z_0 + b_2 +
+    // (1/lb) L b_1 (P_1 = L / lb is half the general step).
+    PA_HIP(hipMemcpyAsync(p.cfd, p.cfh.data(), p.cfh.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    PA_HIP(hipMemcpyAsync(p.cbd, p.cbh.data(), p.cbh.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    const size_t nG = (size_t)n * p.Gs, nV = (size_t)n * p.Vs;
+    const double lb = b->lambda_bar;
+    for (int g = 0; g < p.ngroup; g++) {
+      const int j0 = g * p.G, gm = std::min(p.G, B - j0);
+      TransArgs tr{n, gm, p.Gs, const_cast<double *>(Uin) + (size_t)j0 * n, p.basis};
+      launch_to_block(tr, s);
+      for (int k = 0; k < p.kmax; k++) {
+        double *Rk = p.basis + k * nG, *Rn = p.basis + (k + 1) * nG;
+        if (k == 0)
+          b2_lapply(b, p, cfg, s, Rk, Rn, nullptr, 1.0 / lb, st, p.Gs);
+        else
+          b2_lapply(b, p, cfg, s, Rk, Rn, p.basis + (k - 1) * nG, 2.0 / lb, st, p.Gs);
+      }
+      B2BasisArgs ba{n, p.Gs, gm, p.Mk, p.Vs, p.nvch, p.kmax, p.cfd, p.cbd, p.basis, p.V, p.Y, p.basis};
+      launch_b2_comb(ba, s);
+      for (int q = 0; q < p.nvch; q++) b2_nl(b, p, cfg, s, p.V + q * nV, p.Y + q * nV, st);
+      launch_b2_zsum(ba, s);
+      for (int k = p.kmax - 1; k >= 0; k--) {
+        double *Zk = p.basis + k * nG;
+        if (k + 2 <= p.kmax) {
+          AxpyArgs ax{nG, 1.0, 1.0, 0.0, Zk, p.basis + (k + 2) * nG, nullptr, Zk};
+          launch_axpy(ax, s);
+        }
+        b2_lapply(b, p, cfg, s, p.basis + (k + 1) * nG, Zk, Zk, (k == 0 ? 1.0 : 2.0) / lb, st, p.Gs);
+      }
+      TransArgs tb{n, gm, p.Gs, Uout + (size_t)j0 * n, p.basis};
+      launch_from_block(tb, s);
+    }
+    st.terms = B * p.Mk;
+    st.kmax = p.kmax;
+  } else if (call == kCallNbar) {
     // Nbar_j = sum_m w_m exp(-s_m L) N(exp(s_m L) U_j) over chunks of
     // (member, node) columns, accumulated in a fixed order
     launch_zero((unsigned *)Uout, (size_t)2 * n * B, s);
@@ -770,6 +910,7 @@ void b2_run(pa_ctx *ctx, const pa_bdm2 *b, int call, int B, const double *t, con
   PA_HIP(hipMemcpyAsync(&fail, p.fail, sizeof(int), hipMemcpyDeviceToHost, s));
   PA_HIP(hipMemcpyAsync(&rmax, p.rmax, sizeof(rmax), hipMemcpyDeviceToHost, s));
   sync_checked(s);
+  prof_collect(p);
   float ms = 0;
   PA_HIP(hipEventElapsedTime(&ms, e0, e1));
   (void)hipEventDestroy(e0);
@@ -778,6 +919,60 @@ void b2_run(pa_ctx *ctx, const pa_bdm2 *b, int call, int B, const double *t, con
   std::memcpy(&st.resid_max, &rmax, sizeof(double));
   if (stats) *stats = st;
   if (fail > 0) throw Error(PA_ENOCONV, "a BDM2 mass solve missed cg_rtol");
+}
+
+// Power iteration for rho(L): L is skew in the energy inner product W, so
+// -L^2 is W-symmetric with eigenvalues rho_j^2; v <- -L^2 v / |.|_W and the
+// Rayleigh quotient |L v|_W^2 of the normalised v rises to rho^2.
+double b2_estimate_lambda(pa_ctx *ctx, pa_bdm2 *b, int iters, void *ws, size_t ws_bytes) {
+  pa_solve_cfg cfg;
+  pa_solve_cfg_default(&cfg);
+  cfg.cg_rtol = 1e-12;
+  B2Plan p;
+  b2_plan(b, kCallL, 1, nullptr, nullptr, cfg, (char *)ws, ws_bytes, p);
+  PA_HIP(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  const int n = b->nu + b->nh;
+  // start vector from a counter hash (SplitMix64 of the index), in [-1, 1)
+  std::vector<double> h(n);
+  for (int i = 0; i < n; i++) {
+    uint64_t z = (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    h[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+  }
+  launch_zero((unsigned *)p.fail, 1, s);
+  PA_HIP(hipMemcpyAsync(p.Ra, h.data(), sizeof(double) * n, hipMemcpyHostToDevice, s));
+  pa_stats st{};
+  auto wnorm2 = [&](const double *x) {
+    B2Args a{};
+    a.d = b->d;
+    a.Bs = 1;
+    a.u = x;
+    a.eta = x + b->nu;
+    a.part = p.part;
+    a.norms = p.norms;
+    launch_b2_wnorm(a, b->H, s);
+    double v = 0.0;
+    PA_HIP(hipMemcpyAsync(&v, p.norms, sizeof(double), hipMemcpyDeviceToHost, s));
+    sync_checked(s);
+    return v;
+  };
+  double rho2 = 0.0;
+  for (int it = 0; it < iters; it++) {
+    const double nv = std::sqrt(wnorm2(p.Ra));
+    AxpyArgs sc{(size_t)n, 1.0 / nv, 0.0, 0.0, p.Ra, nullptr, nullptr, p.Ra};
+    launch_axpy(sc, s);
+    b2_lapply(b, p, cfg, s, p.Ra, p.Rb, nullptr, 1.0, st);   // Rb = L v
+    rho2 = wnorm2(p.Rb);
+    b2_lapply(b, p, cfg, s, p.Rb, p.Ra, nullptr, -1.0, st);  // Ra = -L L v
+  }
+  int fail = 0;
+  PA_HIP(hipMemcpyAsync(&fail, p.fail, sizeof(int), hipMemcpyDeviceToHost, s));
+  sync_checked(s);
+  if (fail > 0) throw Error(PA_ENOCONV, "a BDM2 mass solve missed its tolerance");
+  return std::sqrt(rho2);
 }
 
 }  // namespace
@@ -963,6 +1158,17 @@ int pa_bdm2_phase_avg_rhs(pa_ctx *ctx, const pa_bdm2 *b, const pa_avg *avg, int 
     pa::bneed(avg != nullptr, "avg is NULL");
     pa::b2_run(ctx, b, PA_BDM2_PHASE_AVG, members, nullptr, avg, U_dev, Nbar_dev, ws, ws_bytes,
                pa::cfg_of(cfg), stats);
+  });
+}
+
+int pa_bdm2_estimate_lambda(pa_ctx *ctx, pa_bdm2 *b, int iters, double safety, void *ws, size_t ws_bytes,
+                            double *lambda_bar) {
+  return pa::guard([&] {
+    pa::bneed(ctx && b && ws, "bad arguments");
+    pa::bneed(b->dev != nullptr, "BDM2 operators not bound (pa_bdm2_bind)");
+    pa::bneed(iters >= 1 && safety >= 1.0, "need iters >= 1 and safety >= 1");
+    b->lambda_bar = safety * pa::b2_estimate_lambda(ctx, b, iters, ws, ws_bytes);
+    if (lambda_bar) *lambda_bar = b->lambda_bar;
   });
 }
 

@@ -101,6 +101,21 @@ struct B2ColArgs {
   double *blk;        // bcast: [n][Bs] block of the columns' members
   const double *src;  // wsum: [n][Bs] block summed into out with the weights
 };
+// The average with shared bases (members j < G of a group, kept nodes
+// m < Mk, column j Mk + m of the node columns, stored in chunks of Vs
+// columns [q][n][Vs]; bases and sums [k][n][Gs]):
+//   comb: V(j, m) = sum_k cf[k][m] R_k[j]        (forward exponentials)
+//   zsum: Z_k[j] = sum_m cb[k][m] Y(j, m)        (backward weights)
+struct B2BasisArgs {
+  int n, Gs, G, Mk, Vs, nvch, K;
+  const double *cf, *cb;   // [K + 1][Mk]
+  const double *R;         // comb: bases
+  double *V;               // comb: node columns
+  const double *Y;         // zsum: N of the node columns
+  double *Z;               // zsum: the backward sums
+};
+void launch_b2_comb(const B2BasisArgs &a, hipStream_t s);
+void launch_b2_zsum(const B2BasisArgs &a, hipStream_t s);
 void launch_b2_bcast(const B2ColArgs &a, hipStream_t s);
 void launch_b2_wsum(const B2ColArgs &a, hipStream_t s);
 
@@ -109,6 +124,8 @@ void launch_b2_step(const B2Args &a, hipStream_t s);
 void launch_b2_norm(const B2Args &a, int slot, hipStream_t s);  // partials of |r|^2 -> norms[slot]
 void launch_b2_check(const B2Args &a, hipStream_t s);
 void launch_b2_acc(const B2Args &a, hipStream_t s);
+// norms[0][c] = H u' M_u u + g eta' M_h eta of column c of (u, eta)
+void launch_b2_wnorm(const B2Args &a, double H, hipStream_t s);
 int b2_grid(int rows, int Bs);
 
 }  // namespace pa

@@ -101,18 +101,66 @@ __global__ __launch_bounds__(kBWG) void k_b2_norm(B2Args a) {
 // norms[slot][c] = sum of the partials; slot 1 also checks the solve
 // (|r_K|^2 <= rtol^2 |r_0|^2, NaN fails) and keeps the largest relative
 // residual (non-negative doubles order as their bit patterns).
-__global__ void k_b2_fin(B2Args a, int nwg, int slot) {
-  const int c = threadIdx.x;
-  if (c >= a.Bs) return;
-  double s = 0.0;
-  for (int w = 0; w < nwg; w++) s += a.part[(size_t)w * a.Bs + c];
-  a.norms[slot * a.Bs + c] = s;
+// One workgroup of kFinT threads: column c = t % Bs, group t / Bs sums the
+// partials w = group, group + G, ... with four interleaved accumulators,
+// then the groups are added in a fixed tree (the order never changes).
+constexpr int kFinT = 1024;
+__global__ __launch_bounds__(kFinT) void k_b2_fin(B2Args a, int nwg, int slot) {
+  __shared__ double red[kFinT];
+  const int t = threadIdx.x, Bs = a.Bs, G = kFinT / Bs, grp = t / Bs, c = t % Bs;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int w = grp;
+  for (; w + 3 * G < nwg; w += 4 * G) {
+    s0 += a.part[(size_t)w * Bs + c];
+    s1 += a.part[(size_t)(w + G) * Bs + c];
+    s2 += a.part[(size_t)(w + 2 * G) * Bs + c];
+    s3 += a.part[(size_t)(w + 3 * G) * Bs + c];
+  }
+  for (; w < nwg; w += G) s0 += a.part[(size_t)w * Bs + c];
+  red[t] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  for (int h = G / 2; h >= 1; h /= 2) {
+    if (grp < h) red[t] += red[t + h * Bs];
+    __syncthreads();
+  }
+  if (grp != 0) return;
+  const double s = red[c];
+  a.norms[slot * Bs + c] = s;
   if (slot == 1) {
     const double r0 = a.norms[c];
     if (!(s <= a.rtol2 * r0)) atomicAdd(a.fail, 1);
     const double rel = r0 > 0.0 ? sqrt(s / r0) : 0.0;
     if (rel == rel) atomicMax(a.rmax, (unsigned long long)__double_as_longlong(rel));
   }
+}
+
+// Per-workgroup partials of the energy norm H u' M_u u + g eta' M_h eta
+// (M_h per cell: A/12 (I + J)).
+__global__ __launch_bounds__(kBWG) void k_b2_wnorm(B2Args a, double H) {
+  const B2Dev &d = a.d;
+  const int Bs = a.Bs;
+  const size_t nvel = (size_t)d.nu * Bs, total = nvel + (size_t)d.nh * Bs;
+  const size_t stride = (size_t)gridDim.x * kBWG;
+  double acc = 0.0;
+  for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < total; i += stride) {
+    const int row = (int)(i / Bs), c = (int)(i % Bs);
+    if (i < nvel) {
+      double mu = 0.0;
+#pragma unroll
+      for (int s = 0; s < kB2W; s++) {
+        const size_t k = (size_t)s * d.nu + row;
+        mu = fma(d.mass[k], a.u[(size_t)d.col[k] * Bs + c], mu);
+      }
+      acc = fma(H * a.u[i], mu, acc);
+    } else {
+      const int hr = row - d.nu, cell = hr / 3;
+      const double *e = a.eta + (size_t)3 * cell * Bs + c;
+      const double sum = e[0] + e[(size_t)Bs] + e[(size_t)2 * Bs];
+      const double v = a.eta[(size_t)hr * Bs + c];
+      acc = fma(d.g * v, d.ncell[(size_t)kB2NC * cell + kNcA] / 12.0 * (v + sum), acc);
+    }
+  }
+  b2_partial(acc, Bs, a.part);
 }
 
 __global__ __launch_bounds__(kBWG) void k_b2_acc(B2Args a) {
@@ -357,7 +405,46 @@ __global__ __launch_bounds__(kBWG) void k_b2_wsum(B2ColArgs a) {
     a.out[(size_t)j * a.n + row] += v;
   }
 }
+__global__ __launch_bounds__(kBWG) void k_b2_comb(B2BasisArgs a) {
+  const size_t per = (size_t)a.n * a.Vs, total = per * a.nvch;
+  const size_t stride = (size_t)gridDim.x * kBWG;
+  for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < total; i += stride) {
+    const int q = (int)(i / per);
+    const size_t rem = i % per;
+    const int row = (int)(rem / a.Vs), c = (int)(rem % a.Vs);
+    const int col = q * a.Vs + c, j = col / a.Mk, m = col % a.Mk;
+    double v = 0.0;
+    if (j < a.G)
+      for (int k = 0; k <= a.K; k++)
+        v = fma(a.cf[(size_t)k * a.Mk + m], a.R[((size_t)k * a.n + row) * a.Gs + j], v);
+    a.V[i] = v;
+  }
+}
+
+__global__ __launch_bounds__(kBWG) void k_b2_zsum(B2BasisArgs a) {
+  const int Kp = a.K + 1;
+  const size_t total = (size_t)a.n * a.Gs * Kp, stride = (size_t)gridDim.x * kBWG;
+  for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < total; i += stride) {
+    const int k = (int)(i % Kp);
+    const size_t rj = i / Kp;
+    const int j = (int)(rj % a.Gs), row = (int)(rj / a.Gs);
+    double v = 0.0;
+    if (j < a.G)
+      for (int m = 0; m < a.Mk; m++) {
+        const int col = j * a.Mk + m, q = col / a.Vs, c = col % a.Vs;
+        v = fma(a.cb[(size_t)k * a.Mk + m], a.Y[((size_t)q * a.n + row) * a.Vs + c], v);
+      }
+    a.Z[((size_t)k * a.n + row) * a.Gs + j] = v;
+  }
+}
 }  // namespace
+
+void launch_b2_comb(const B2BasisArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_b2_comb, dim3(b2_grid(a.n, a.Vs * a.nvch)), dim3(kBWG), 0, s, a);
+}
+void launch_b2_zsum(const B2BasisArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_b2_zsum, dim3(b2_grid(a.n, a.Gs * (a.K + 1))), dim3(kBWG), 0, s, a);
+}
 
 void launch_b2_bcast(const B2ColArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_b2_bcast, dim3(b2_grid(a.n, a.Bs)), dim3(kBWG), 0, s, a);
@@ -381,18 +468,23 @@ int b2_grid(int rows, int Bs) {
 
 void launch_b2_stiff(const B2Args &a, hipStream_t s) {
   hipLaunchKernelGGL(k_b2_stiff, dim3(b2_grid(a.d.nu + 3 * a.d.nc, a.Bs)), dim3(kBWG), 0, s, a);
-  hipLaunchKernelGGL(k_b2_fin, dim3(1), dim3(64), 0, s, a, b2_grid(a.d.nu + 3 * a.d.nc, a.Bs), 0);
+  hipLaunchKernelGGL(k_b2_fin, dim3(1), dim3(kFinT), 0, s, a, b2_grid(a.d.nu + 3 * a.d.nc, a.Bs), 0);
 }
 void launch_b2_step(const B2Args &a, hipStream_t s) {
   hipLaunchKernelGGL(k_b2_step, dim3(b2_grid(a.d.nu, a.Bs)), dim3(kBWG), 0, s, a);
 }
 void launch_b2_check(const B2Args &a, hipStream_t s) {
   hipLaunchKernelGGL(k_b2_norm, dim3(b2_grid(a.d.nu, a.Bs)), dim3(kBWG), 0, s, a);
-  hipLaunchKernelGGL(k_b2_fin, dim3(1), dim3(64), 0, s, a, b2_grid(a.d.nu, a.Bs), 1);
+  hipLaunchKernelGGL(k_b2_fin, dim3(1), dim3(kFinT), 0, s, a, b2_grid(a.d.nu, a.Bs), 1);
 }
 void launch_b2_norm(const B2Args &a, int slot, hipStream_t s) {
   hipLaunchKernelGGL(k_b2_norm, dim3(b2_grid(a.d.nu, a.Bs)), dim3(kBWG), 0, s, a);
-  hipLaunchKernelGGL(k_b2_fin, dim3(1), dim3(64), 0, s, a, b2_grid(a.d.nu, a.Bs), slot);
+  hipLaunchKernelGGL(k_b2_fin, dim3(1), dim3(kFinT), 0, s, a, b2_grid(a.d.nu, a.Bs), slot);
+}
+void launch_b2_wnorm(const B2Args &a, double H, hipStream_t s) {
+  const int g = b2_grid(a.d.nu + a.d.nh, a.Bs);
+  hipLaunchKernelGGL(k_b2_wnorm, dim3(g), dim3(kBWG), 0, s, a, H);
+  hipLaunchKernelGGL(k_b2_fin, dim3(1), dim3(kFinT), 0, s, a, g, 0);
 }
 void launch_b2_acc(const B2Args &a, hipStream_t s) {
   hipLaunchKernelGGL(k_b2_acc, dim3(b2_grid(a.d.nu + a.d.nh, a.Bs)), dim3(kBWG), 0, s, a);

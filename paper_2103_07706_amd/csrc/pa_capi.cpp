@@ -63,7 +63,7 @@ int pa_ctx_set_stream(pa_ctx *ctx, void *stream) {
 int pa_ctx_profile(pa_ctx *ctx, int kernel) {
   return guard([&] {
     need(ctx != nullptr, "ctx is NULL");
-    need(kernel >= PA_KERNEL_NONE && kernel <= PA_KERNEL_CHEB32_ITER, "unknown kernel id");
+    need(kernel >= PA_KERNEL_NONE && kernel <= PA_KERNEL_B2_STEP, "unknown kernel id");
     ctx->prof_kernel = kernel;
     ctx->prof_launches = ctx->prof_work = 0;
     ctx->prof_ms = ctx->prof_bytes = ctx->prof_units = 0.0;

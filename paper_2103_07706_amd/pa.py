@@ -56,6 +56,7 @@ PA_KERNEL_NONE, PA_KERNEL_CG_ITER, PA_KERNEL_CHEB_ITER, PA_KERNEL_CHEB_LP_ITER =
 PA_KERNEL_CHEB_FUSED = 4
 PA_KERNEL_CHEB3_ITER = 5
 PA_KERNEL_CHEB32_ITER = 6
+PA_KERNEL_B2_STEP = 7
 
 
 class TrainCfg(ctypes.Structure):
@@ -146,6 +147,8 @@ EXPORTS = {
     "pa_bdm2_device_size": (ctypes.c_int, [_V, ctypes.POINTER(_SZ)]),
     "pa_bdm2_bind": (ctypes.c_int, [_V, _V, _V]),
     "pa_bdm2_set_lambda": (ctypes.c_int, [_V, ctypes.c_double]),
+    "pa_bdm2_estimate_lambda": (ctypes.c_int, [_V, _V, ctypes.c_int, ctypes.c_double, _V, _SZ,
+                                               _D]),
     "pa_bdm2_workspace_size": (ctypes.c_int, [_V, ctypes.c_int, ctypes.c_int, _D, _V,
                                               ctypes.POINTER(SolveCfg), ctypes.POINTER(_SZ)]),
     "pa_bdm2_nonlinear": (ctypes.c_int, [_V, _V, ctypes.c_int, _V, _V, _V, _SZ,
@@ -617,6 +620,15 @@ class BDM2:
 
     def set_lambda(self, lambda_bar):
         _check(lib().pa_bdm2_set_lambda(self._h, float(lambda_bar)))
+
+    def estimate_lambda(self, iters=200, safety=1.05):
+        """pa_bdm2_estimate_lambda: sets and returns lambda_bar."""
+        cfg = solve_cfg(cg_rtol=1e-12)
+        ws, nb = self._workspace(PA_BDM2_APPLY_L, 1, None, cfg)
+        v = ctypes.c_double()
+        _check(lib().pa_bdm2_estimate_lambda(self.ctx._h, self._h, iters, safety, ws, nb,
+                                             ctypes.byref(v)))
+        return v.value
 
     def workspace_size(self, call, B, t=None, avg=None, cfg=None):
         cfg = cfg or solve_cfg()

@@ -199,11 +199,14 @@ def test_gpu_bdm2_nonlinear_parity(level, B):
     assert st["solves"] == 1 and 0 < st["resid_max"] <= 1e-13
 
 
-def test_gpu_bdm2_phase_avg_rhs_parity():
-    """Nbar for two members with M = 8 nodes over T = 3600 s (16 columns in
-    one pass) and for nine members (72 columns: two passes, the second
-    ragged), against the oracle's composition; the same call twice gives
-    the same bits."""
+@pytest.mark.parametrize("backward", ["clenshaw", "per_term"])
+def test_gpu_bdm2_phase_avg_rhs_parity(backward):
+    """Nbar for two members with M = 8 nodes over T = 3600 s and for nine
+    members (72 node columns: two groups or passes, the last ragged),
+    against the oracle's composition, in both forms: every node's
+    exponentials on its own column (per term), or each member's forward
+    basis and one Clenshaw sum backward (the default); the same call twice
+    gives the same bits."""
     import oracle
     from paper_2103_07706_amd import pa
     ob, lb, lm = _pair(3)
@@ -212,9 +215,10 @@ def test_gpu_bdm2_phase_avg_rhs_parity():
     lb.set_lambda(lam)
     avg = pa.Avg(8, 3600.0)
     s, w = oracle.avg_nodes(8, 3600.0)
+    bw = pa.PA_BACKWARD_CLENSHAW if backward == "clenshaw" else pa.PA_BACKWARD_PER_TERM
     for members in (2, 9):
         U = _smooth(om, range(members))
-        out, st = lb.phase_avg_rhs(avg, _dev(U), _cfg())
+        out, st = lb.phase_avg_rhs(avg, _dev(U), _cfg(backward=bw))
         got = out.cpu().numpy()
         for j in sorted({0, members - 1}):
             ref = ob.phase_avg_rhs(lam, s, w, U[j], tol=1e-12)
@@ -222,17 +226,18 @@ def test_gpu_bdm2_phase_avg_rhs_parity():
             _close(got[j, ob.nu:], ref[ob.nu:], 1e-9, f"eta member {j} of {members}")
         assert st["terms"] == 8 * members
         assert 0 < st["resid_max"] <= 1e-13
-    again, _ = lb.phase_avg_rhs(avg, _dev(U), _cfg())
+    again, _ = lb.phase_avg_rhs(avg, _dev(U), _cfg(backward=bw))
     assert np.array_equal(again.cpu().numpy(), got)
 
 
 def test_gpu_bdm2_phase_avg_rhs_level5():
     """Level 5 (153600 velocity and 61440 depth unknowns).  64 members x
-    M = 8 nodes, eight passes of 64 columns: members repeat every seven, so
-    equal inputs sit in different passes and columns and must give equal
-    bits; every member's depth mass is conserved (N conserves it, the
-    exponentials keep it).  One member at M = 2 against the oracle (its
-    M = 8 average takes minutes on the host)."""
+    M = 8 nodes in the default form: eight groups of eight members sharing
+    their passes; members repeat every seven, so equal inputs sit in
+    different groups and columns and must give equal bits; every member's
+    depth mass is conserved (N conserves it, the exponentials keep it).
+    One member at M = 2 against the oracle (its M = 8 average takes
+    minutes on the host)."""
     import oracle
     from paper_2103_07706_amd import pa
     ob, lb, lm = _pair(5)
@@ -254,3 +259,14 @@ def test_gpu_bdm2_phase_avg_rhs_level5():
     s, w = oracle.avg_nodes(2, 3600.0)
     ref = ob.phase_avg_rhs(lam, s, w, U[0], tol=1e-10)
     _close(one.cpu().numpy()[0], ref, 1e-8, "member 0, M = 2")
+
+
+def test_gpu_bdm2_estimate_lambda():
+    """The GPU power iteration on -L^2 in the energy norm approaches rho(L)
+    from below: against the oracle's Lanczos value at level 3."""
+    ob, lb, lm = _pair(3)
+    rho = ob.rho()
+    est = lb.estimate_lambda(iters=200, safety=1.0)
+    assert 0.97 * rho <= est <= rho * (1 + 1e-9), (est, rho)
+    lam = lb.estimate_lambda(iters=200, safety=1.05)
+    assert abs(lam / (1.05 * est) - 1) < 1e-12
