@@ -396,3 +396,30 @@ class BDM2P1DG:
             Y, _ = self.expL(lambda_bar, -sm, f(V), tol)
             out += wm * Y
         return out
+
+    # ------------------------------------------------------------ RK4 step
+    def step(self, lambda_bar, s, w, dt, U, inner="N", tol=1e-13):
+        """One step of the averaged system (Sec. 2.3): the Lawson form of
+        the classical fourth-order Runge-Kutta method on the averaged
+        equation, with the stages in the paper's order (stages 2 and 4 take
+        exp(L dt/2) inside N, after exp(L s)), every exponential by expL and
+        the averages by phase_avg_rhs (inner as there)."""
+        U = np.asarray(U, dtype=float)
+        E = lambda t, X: self.expL(lambda_bar, t, X, tol)[0]  # noqa: E731
+        f = {"N": self.nonlinear, "L": self.apply_L, "I": lambda X: np.array(X, copy=True)}[inner]
+        h = 0.5 * dt
+
+        def shifted(X):  # sum_m w_m exp(-s_m L) N(exp(L dt/2) exp(s_m L) X)
+            out = np.zeros(self.n)
+            for sm, wm in zip(s, w):
+                out += wm * E(-sm, f(E(h, E(sm, X))))
+            return out
+        k1 = self.phase_avg_rhs(lambda_bar, s, w, U, inner, tol)
+        U1 = U + h * k1
+        Eh = E(h, U)
+        k2 = shifted(U1)
+        U2 = Eh + h * k2
+        k3 = self.phase_avg_rhs(lambda_bar, s, w, U2, inner, tol)
+        U3 = Eh + dt * k3
+        k4 = shifted(U3)
+        return (E(dt, U) + dt / 6.0 * (E(dt, k1) + 2.0 * E(h, k2) + 2.0 * E(h, k3) + k4))

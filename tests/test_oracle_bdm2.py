@@ -377,3 +377,32 @@ def test_bdm2_bumps_state_is_the_interpolant(bdm):
     Ld = b.apply_L(np.concatenate([U[:b.nu], np.zeros(b.nh)]))[b.nu:]
     Lr = b.apply_L(np.concatenate([U[:b.nu][::-1], np.zeros(b.nh)]))[b.nu:]
     assert np.abs(Ld).max() <= 1e-9 * np.abs(Lr).max()
+
+
+def test_bdm2_step_fourth_order_with_N_as_L(bdm):
+    """With N := L the averaged system is U' = L U + L U, solved by
+    exp(2 L t) U0 (scipy expm of the dense L at level 0): the step converges
+    at fourth order; with N itself it conserves the depth mass."""
+    import scipy.linalg as sla
+    from paper_2103_07706_amd import inputs
+    b = bdm(0)
+    L = np.column_stack([b.apply_L(e) for e in np.eye(b.n)])
+    lam = 1.05 * b.rho()
+    U0 = inputs.random_state(b.nu, b.nh, 2)
+    s, w = oracle.avg_nodes(4, 1800.0)
+    tend = 7200.0
+    errs = []
+    for nsteps in (2, 4):
+        dt = tend / nsteps
+        U = U0.copy()
+        for _ in range(nsteps):
+            U = b.step(lam, s, w, dt, U, inner="L")
+        ref = sla.expm(2.0 * tend * L) @ U0
+        errs.append(np.abs(U - ref).max() / np.abs(ref).max())
+    print("step errors:", errs)
+    assert errs[0] / errs[1] > 12.0 and errs[1] < 1e-3
+    m = b.mesh
+    Us = inputs.bdm2_bumps_state(m.verts, m.cell_verts, m.edge_cells, m.edge_verts, 3, 1)
+    U1 = b.step(lam, s, w, 1800.0, Us)
+    a3 = np.repeat(b.area / 3.0, 3)
+    assert abs(a3 @ (U1[b.nu:] - Us[b.nu:])) <= 1e-12 * (a3 @ np.abs(Us[b.nu:]))
