@@ -604,7 +604,8 @@ int pa_bdm2_estimate_lambda(pa_ctx *ctx, pa_bdm2 *b, int iters, double safety,
  * the number of states (members for PA_BDM2_PHASE_AVG); t_host the B times
  * of PA_BDM2_EXPL (the degree depends on them), avg the nodes of
  * PA_BDM2_PHASE_AVG (others NULL). */
-enum { PA_BDM2_APPLY_L = 0, PA_BDM2_EXPL = 1, PA_BDM2_NONLINEAR = 2, PA_BDM2_PHASE_AVG = 3 };
+enum { PA_BDM2_APPLY_L = 0, PA_BDM2_EXPL = 1, PA_BDM2_NONLINEAR = 2, PA_BDM2_PHASE_AVG = 3,
+       PA_BDM2_STEP = 4 };  /* PA_BDM2_STEP: t_host points to dt */
 int pa_bdm2_workspace_size(const pa_bdm2 *b, int call, int B, const double *t_host,
                            const pa_avg *avg, const pa_solve_cfg *cfg, size_t *bytes);
 /* out = L U for B states, member-major [B][nu + nh] in device memory (out
@@ -650,6 +651,20 @@ int pa_bdm2_nonlinear(pa_ctx *ctx, const pa_bdm2 *b, int B, const double *U_dev,
 int pa_bdm2_phase_avg_rhs(pa_ctx *ctx, const pa_bdm2 *b, const pa_avg *avg, int members,
                           const double *U_dev, double *Nbar_dev, void *ws_dev,
                           size_t ws_bytes, const pa_solve_cfg *cfg, pa_stats *stats);
+/* One step dt of the averaged system (Sec. 2.3) for the members' states U
+ * (member-major, in place; members in [1, 64]): the Lawson form of RK4,
+ *   k1 = Nbar(U), k2 = Nbar(E (U + h k1)), k3 = Nbar(E U + h k2),
+ *   k4 = Nbar(E (E U + dt k3)),
+ *   U <- E (E (U + dt/6 k1) + dt/3 (k2 + k3)) + dt/6 k4,
+ * E = exp(h L), h = dt/2: the paper's stages with exp(L dt/2) applied
+ * before the averages of stages 2 and 4 (it commutes with exp(L s)) and the
+ * final exp(L dt) U + dt/6 (exp(L dt) k1 + 2 exp(L h) (k2 + k3) + k4)
+ * regrouped by linearity.  Averages as pa_bdm2_phase_avg_rhs, exponentials
+ * as pa_bdm2_expL_apply.  Stats summed over the stages (maxima for
+ * cg_iters_max, kmax and resid_max). */
+int pa_bdm2_step(pa_ctx *ctx, const pa_bdm2 *b, const pa_avg *avg, double dt, int members,
+                 double *U_dev, void *ws_dev, size_t ws_bytes, const pa_solve_cfg *cfg,
+                 pa_stats *stats);
 int pa_bdm2_destroy(pa_bdm2 *b);
 
 #ifdef __cplusplus

@@ -921,6 +921,89 @@ void b2_run(pa_ctx *ctx, const pa_bdm2 *b, int call, int B, const double *t, con
   if (fail > 0) throw Error(PA_ENOCONV, "a BDM2 mass solve missed cg_rtol");
 }
 
+// One step of the averaged system (Sec. 2.3), the Lawson RK4 form with
+// exp(L dt/2) applied before the averages in stages 2 and 4 (it commutes
+// with exp(L s)) and the last combination regrouped by linearity:
+//   k1 = Nbar(U), k2 = Nbar(E (U + h k1)), k3 = Nbar(E U + h k2),
+//   k4 = Nbar(E (E U + dt k3)),
+//   U' = E (E (U + dt/6 k1) + dt/3 (k2 + k3)) + dt/6 k4,   E = exp(L h), h = dt/2.
+// Member-major states; seven state buffers then the sub-calls' workspace.
+size_t b2_step_ws(const pa_bdm2 *b, const pa_avg *avg, double dt, int B, const pa_solve_cfg &cfg,
+                  char *ws, size_t cap, double **bufs) {
+  bneed(B >= 1 && B <= 64, "at most 64 members per BDM2 step");
+  bneed(dt > 0, "dt must be positive");
+  const size_t nB = ((size_t)b->nu + b->nh) * B;
+  size_t off = 0;
+  for (int i = 0; i < 7; i++) {
+    double *p = take<double>(ws, off, cap, nB);
+    if (bufs) bufs[i] = p;
+  }
+  off = (off + 255) & ~(size_t)255;
+  const std::vector<double> th(B, 0.5 * dt);
+  B2Plan p1, p2;
+  const size_t a = b2_plan(b, kCallNbar, B, nullptr, avg, cfg, nullptr, 0, p1);
+  const size_t e = b2_plan(b, kCallExp, B, th.data(), nullptr, cfg, nullptr, 0, p2);
+  return off + std::max(a, e);
+}
+
+void b2_step(pa_ctx *ctx, const pa_bdm2 *b, const pa_avg *avg, double dt, int B, double *U, void *ws,
+             size_t ws_bytes, const pa_solve_cfg &cfg, pa_stats *stats) {
+  bneed(ctx && b && avg && U && ws, "bad arguments");
+  double *k[7];
+  const size_t need = b2_step_ws(b, avg, dt, B, cfg, (char *)ws, ws_bytes, k);
+  bneed(need <= ws_bytes, "workspace too small");
+  double *k1 = k[0], *k2 = k[1], *k3 = k[2], *k4 = k[3], *A = k[4], *Eh = k[5], *T = k[6];
+  const size_t nB = ((size_t)b->nu + b->nh) * B;
+  size_t sub_off = (7 * ((nB * sizeof(double) + 255) & ~(size_t)255) + 255) & ~(size_t)255;
+  char *sub = (char *)ws + sub_off;
+  const size_t sub_bytes = ws_bytes - sub_off;
+  const std::vector<double> th(B, 0.5 * dt);
+  const double h = 0.5 * dt;
+  hipStream_t s = ctx->stream;
+  pa_stats tot{};
+  auto add = [&](const pa_stats &x) {
+    tot.solves += x.solves;
+    tot.cg_iters += x.cg_iters;
+    tot.cg_iters_max = std::max(tot.cg_iters_max, x.cg_iters_max);
+    tot.kmax = std::max(tot.kmax, x.kmax);
+    tot.terms += x.terms;
+    tot.resid_max = std::max(tot.resid_max, x.resid_max);
+    tot.device_ms += x.device_ms;
+  };
+  auto nbar = [&](const double *in, double *out) {
+    pa_stats x{};
+    b2_run(ctx, b, kCallNbar, B, nullptr, avg, in, out, sub, sub_bytes, cfg, &x);
+    add(x);
+  };
+  auto expo = [&](const double *in, double *out) {
+    pa_stats x{};
+    b2_run(ctx, b, kCallExp, B, th.data(), nullptr, in, out, sub, sub_bytes, cfg, &x);
+    add(x);
+  };
+  auto axpy = [&](double a0, const double *x0, double a1, const double *x1, double a2, const double *x2,
+                  double *out) {
+    AxpyArgs ax{nB, a0, a1, a2, x0, x1, x2, out};
+    launch_axpy(ax, s);
+  };
+  nbar(U, k1);
+  axpy(1.0, U, h, k1, 0.0, nullptr, A);
+  expo(U, Eh);
+  expo(A, T);
+  nbar(T, k2);
+  axpy(1.0, Eh, h, k2, 0.0, nullptr, A);
+  nbar(A, k3);
+  axpy(1.0, Eh, dt, k3, 0.0, nullptr, A);
+  expo(A, T);
+  nbar(T, k4);
+  axpy(1.0, U, dt / 6.0, k1, 0.0, nullptr, A);
+  expo(A, T);
+  axpy(1.0, T, dt / 3.0, k2, dt / 3.0, k3, A);
+  expo(A, T);
+  axpy(1.0, T, dt / 6.0, k4, 0.0, nullptr, U);
+  sync_checked(s);
+  if (stats) *stats = tot;
+}
+
 // Power iteration for rho(L): L is skew in the energy inner product W, so
 // -L^2 is W-symmetric with eigenvalues rho_j^2; v <- -L^2 v / |.|_W and the
 // Rayleigh quotient |L v|_W^2 of the normalised v rises to rho^2.
@@ -1119,7 +1202,12 @@ int pa_bdm2_workspace_size(const pa_bdm2 *b, int call, int B, const double *t_ho
                            const pa_solve_cfg *cfg, size_t *bytes) {
   return pa::guard([&] {
     pa::bneed(b && bytes && B >= 1, "bad arguments");
-    if (call == PA_BDM2_EXPL) pa::bneed(t_host != nullptr, "t_host is NULL");
+    if (call == PA_BDM2_EXPL || call == PA_BDM2_STEP) pa::bneed(t_host != nullptr, "t_host is NULL");
+    if (call == PA_BDM2_STEP) {
+      pa::bneed(avg != nullptr, "avg is NULL");
+      *bytes = pa::b2_step_ws(b, avg, *t_host, B, pa::cfg_of(cfg), nullptr, 0, nullptr);
+      return;
+    }
     pa::B2Plan p;
     *bytes = pa::b2_plan(b, call, B, t_host, avg, pa::cfg_of(cfg), nullptr, 0, p);
   });
@@ -1159,6 +1247,11 @@ int pa_bdm2_phase_avg_rhs(pa_ctx *ctx, const pa_bdm2 *b, const pa_avg *avg, int 
     pa::b2_run(ctx, b, PA_BDM2_PHASE_AVG, members, nullptr, avg, U_dev, Nbar_dev, ws, ws_bytes,
                pa::cfg_of(cfg), stats);
   });
+}
+
+int pa_bdm2_step(pa_ctx *ctx, const pa_bdm2 *b, const pa_avg *avg, double dt, int members, double *U_dev,
+                 void *ws, size_t ws_bytes, const pa_solve_cfg *cfg, pa_stats *stats) {
+  return pa::guard([&] { pa::b2_step(ctx, b, avg, dt, members, U_dev, ws, ws_bytes, pa::cfg_of(cfg), stats); });
 }
 
 int pa_bdm2_estimate_lambda(pa_ctx *ctx, pa_bdm2 *b, int iters, double safety, void *ws, size_t ws_bytes,

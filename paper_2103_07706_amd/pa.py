@@ -19,7 +19,7 @@ PA_FP64, PA_FP32_REFINED = 0, 1
 PA_BACKWARD_PER_TERM, PA_BACKWARD_CLENSHAW = 0, 1
 PA_SOLVER_CG, PA_SOLVER_CHEBYSHEV = 0, 1
 PA_EXP_CHEBYSHEV, PA_EXP_REXI = 0, 1
-PA_BDM2_APPLY_L, PA_BDM2_EXPL, PA_BDM2_NONLINEAR, PA_BDM2_PHASE_AVG = range(4)
+PA_BDM2_APPLY_L, PA_BDM2_EXPL, PA_BDM2_NONLINEAR, PA_BDM2_PHASE_AVG, PA_BDM2_STEP = range(5)
 PA_OK, PA_EINVAL, PA_ENOMEM, PA_EHIP, PA_ENOCONV, PA_ENOTSUP, PA_EGROWTH = range(7)
 _STATUS = {0: "PA_OK", 1: "PA_EINVAL", 2: "PA_ENOMEM", 3: "PA_EHIP", 4: "PA_ENOCONV",
            5: "PA_ENOTSUP", 6: "PA_EGROWTH"}
@@ -159,6 +159,8 @@ EXPORTS = {
                                        ctypes.POINTER(SolveCfg), ctypes.POINTER(Stats)]),
     "pa_bdm2_expL_apply": (ctypes.c_int, [_V, _V, ctypes.c_int, _D, _V, _V, _V, _SZ,
                                           ctypes.POINTER(SolveCfg), ctypes.POINTER(Stats)]),
+    "pa_bdm2_step": (ctypes.c_int, [_V, _V, _V, ctypes.c_double, ctypes.c_int, _V, _V, _SZ,
+                                    ctypes.POINTER(SolveCfg), ctypes.POINTER(Stats)]),
     "pa_bdm2_destroy": (ctypes.c_int, [_V]),
     "pa_ops_create": (ctypes.c_int, [_V, ctypes.POINTER(Phys), ctypes.POINTER(_V)]),
     "pa_ops_device_size": (ctypes.c_int, [_V, ctypes.POINTER(_SZ)]),
@@ -690,6 +692,17 @@ class BDM2:
                                            _ptr(out), ws, nb, ctypes.byref(cfg),
                                            ctypes.byref(st)))
         return out, st.as_dict()
+
+    def step(self, avg: Avg, dt: float, U, cfg=None):
+        """pa_bdm2_step: one averaged RK4 step, U updated in place."""
+        cfg = cfg or solve_cfg()
+        members = U.shape[0]
+        dtv = np.array([dt], np.float64)
+        ws, nb = self._workspace(PA_BDM2_STEP, members, dtv, cfg, avg)
+        st = Stats()
+        _check(lib().pa_bdm2_step(self.ctx._h, self._h, avg._h, float(dt), members, _ptr(U), ws,
+                                  nb, ctypes.byref(cfg), ctypes.byref(st)))
+        return U, st.as_dict()
 
     def __del__(self):
         if getattr(self, "_h", None) and _lib is not None:

@@ -121,3 +121,12 @@ def test_bdm2_refuses_topography_and_bad_sizes(oracle_mesh):
     sizes = [b.workspace_size(pa.PA_BDM2_PHASE_AVG, mem, avg=avg) for mem in (1, 8, 100)]
     assert sizes[0] < sizes[1] and sizes[2] < 1.25 * sizes[1]
     assert b.workspace_size(pa.PA_BDM2_NONLINEAR, 3) > b.workspace_size(pa.PA_BDM2_APPLY_L, 3)
+    # a step needs dt and the nodes; its workspace holds seven states more
+    dt = np.array([1800.0])
+    assert W(b._h, pa.PA_BDM2_STEP, 2, None, avg._h, ctypes.byref(cfg), ctypes.byref(sz)) == pa.PA_EINVAL
+    assert W(b._h, pa.PA_BDM2_STEP, 2, pa._dp(dt), None, ctypes.byref(cfg), ctypes.byref(sz)) == pa.PA_EINVAL
+    assert W(b._h, pa.PA_BDM2_STEP, 65, pa._dp(dt), avg._h, ctypes.byref(cfg),
+             ctypes.byref(sz)) == pa.PA_EINVAL
+    st = b.workspace_size(pa.PA_BDM2_STEP, 2, dt, avg)
+    assert st >= 7 * 8 * b.n * 2 + b.workspace_size(pa.PA_BDM2_PHASE_AVG, 2, avg=avg)
+

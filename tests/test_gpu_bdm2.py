@@ -270,3 +270,29 @@ def test_gpu_bdm2_estimate_lambda():
     assert 0.97 * rho <= est <= rho * (1 + 1e-9), (est, rho)
     lam = lb.estimate_lambda(iters=200, safety=1.05)
     assert abs(lam / (1.05 * est) - 1) < 1e-12
+
+
+def test_gpu_bdm2_step_parity():
+    """One averaged RK4 step (Sec. 2.3) for three members at level 3 (M = 4
+    nodes over T = 1800 s, dt = 1800 s) against the oracle's step, which
+    takes the stages in the paper's order; the depth mass is unchanged."""
+    import oracle
+    from paper_2103_07706_amd import pa
+    ob, lb, lm = _pair(3)
+    om = oracle.Mesh(3)
+    lam = 1.05 * ob.rho()
+    lb.set_lambda(lam)
+    avg = pa.Avg(4, 1800.0)
+    s, w = oracle.avg_nodes(4, 1800.0)
+    U0 = _smooth(om, [0, 1, 2])
+    U = _dev(U0)
+    _, st = lb.step(avg, 1800.0, U, _cfg())
+    got = U.cpu().numpy()
+    for j in (0, 2):
+        ref = ob.step(lam, s, w, 1800.0, U0[j], tol=1e-12)
+        _close(got[j, :ob.nu], ref[:ob.nu], 1e-9, f"u member {j}")
+        _close(got[j, ob.nu:], ref[ob.nu:], 1e-9, f"eta member {j}")
+    a3 = np.repeat(ob.area / 3.0, 3)
+    for j in range(3):
+        assert abs(a3 @ (got[j, ob.nu:] - U0[j, ob.nu:])) <= 1e-12 * (a3 @ np.abs(U0[j, ob.nu:]))
+    assert st["terms"] == 4 * 3 * 4 and st["resid_max"] <= 1e-13
