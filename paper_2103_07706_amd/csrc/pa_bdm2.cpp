@@ -177,6 +177,7 @@ void bdm2_assemble(pa_bdm2 *b, const Mesh &m, const pa_phys &ph) {
   b->cdof.assign((size_t)12 * nc, 0);
   b->q.assign((size_t)36 * nc, 0.0);
   b->ncell.assign((size_t)kB2NC * nc, 0.0);
+  b->mT.assign((size_t)144 * nc, 0.0);
   b->rloc.assign((size_t)2 * nu, -1);
   b->etab.assign((size_t)4 * ne, -1);
   // volume and side rules of the nonlinear term
@@ -346,7 +347,10 @@ void bdm2_assemble(pa_bdm2 *b, const Mesh &m, const pa_phys &ph) {
       }
     }
     for (int i = 0; i < 12; i++) {
-      for (int j = 0; j < 12; j++) rows[gid[i]].add(gid[j], sg[i] * sg[j] * Ml[i][j], sg[i] * sg[j] * Fl[i][j]);
+      for (int j = 0; j < 12; j++) {
+        rows[gid[i]].add(gid[j], sg[i] * sg[j] * Ml[i][j], sg[i] * sg[j] * Fl[i][j]);
+        b->mT[(size_t)144 * c + 12 * i + j] = sg[i] * sg[j] * Ml[i][j];
+      }
       for (int r = 0; r < 3; r++) brows[gid[i]].add(3 * c + r, sg[i] * Bl[i][r]);
       b->cdof[12 * c + i] = gid[i];
       b->rloc[2 * (size_t)gid[i] + (b->rloc[2 * (size_t)gid[i]] < 0 ? 0 : 1)] = 12 * c + i;
@@ -419,6 +423,7 @@ struct B2Plan {
   int G = 0, Gs = 0, Mk = 0, Vs = 0, nvch = 0, ngroup = 0;
   std::vector<double> cfh, cbh;   // [kmax + 1][Mk]: c_k(s_m), w_m c_k(-s_m)
   double *basis = nullptr, *V = nullptr, *Y = nullptr, *cfd = nullptr, *cbd = nullptr;
+  double *eloc = nullptr;  // element-form step products [nc * 12][Bs] (wide blocks)
   double *Ra = nullptr, *Rb = nullptr, *acc = nullptr, *r = nullptr, *dir[2] = {nullptr, nullptr};
   double *raw = nullptr, *ut = nullptr, *loc = nullptr, *rhs = nullptr;
   double *part = nullptr, *norms = nullptr, *coefF = nullptr, *coefB = nullptr, *cwd = nullptr;
@@ -555,6 +560,7 @@ size_t b2_plan(const pa_bdm2 *b, int call, int B, const double *t, const pa_avg 
     p.loc = take<double>(ws, off, cap, (size_t)12 * b->nc * p.Vs);
     p.ut = take<double>(ws, off, cap, (size_t)4 * kB2FQ * b->ne * p.Vs);
     p.rhs = take<double>(ws, off, cap, (size_t)b->nu * p.Vs);
+    if (p.Vs >= kB2ElMin) p.eloc = take<double>(ws, off, cap, (size_t)12 * b->nc * p.Vs);
     p.part = take<double>(ws, off, cap, (size_t)2048 * 64);
     p.norms = take<double>(ws, off, cap, (size_t)2 * 64);
     p.cfd = take<double>(ws, off, cap, p.cfh.size());
@@ -619,6 +625,7 @@ size_t b2_plan(const pa_bdm2 *b, int call, int B, const double *t, const pa_avg 
     p.ut = take<double>(ws, off, cap, (size_t)4 * kB2FQ * b->ne * Bs);
     p.rhs = take<double>(ws, off, cap, (size_t)b->nu * Bs);
   }
+  if (Bs >= kB2ElMin) p.eloc = take<double>(ws, off, cap, (size_t)12 * b->nc * Bs);
   p.part = take<double>(ws, off, cap, (size_t)2048 * Bs);
   p.norms = take<double>(ws, off, cap, (size_t)2 * Bs);
   if (expo) p.coefF = take<double>(ws, off, cap, p.hF.size());
@@ -636,15 +643,18 @@ size_t b2_plan(const pa_bdm2 *b, int call, int B, const double *t, const pa_avg 
 // it up, then the residual check.
 void b2_solve(const B2Plan &p, B2Args &a, hipStream_t s, pa_stats &st) {
   launch_b2_stiff(a, s);
+  const bool el = a.Bs >= kB2ElMin && a.loc != nullptr;
   const bool prof = p.ctx && p.ctx->prof_kernel == PA_KERNEL_B2_STEP && p.steps > 0;
   if (prof) {
     p.spans.emplace_back(prof_event(p.ctx), prof_event(p.ctx));
     PA_HIP(hipEventRecord(p.spans.back().first, s));
-    // per row: the ELL row (21 columns and values) and D^-1; per row and
-    // column: x and r in and out, d in, d' out (not on the last step)
+    // per row and column: x and r in and out, d in, d' out (not on the
+    // last step); per row the ELL row (21 columns and values) and D^-1, or
+    // in the element form per cell its 12 x 12 block and per row D^-1
     const double rows = a.d.nu, cols = a.Bs;
+    const double mat = el ? 1152.0 * a.d.nc + 8.0 * rows : 260.0 * rows;
     p.prof_launches += p.steps;
-    p.prof_bytes += rows * (p.steps * (260.0 + 48.0 * cols) - 8.0 * cols);
+    p.prof_bytes += p.steps * (mat + 48.0 * rows * cols) - 8.0 * rows * cols;
     p.prof_units += (double)p.steps * cols;
   }
   for (int k = 0; k < p.steps; k++) {
@@ -653,7 +663,10 @@ void b2_solve(const B2Plan &p, B2Args &a, hipStream_t s, pa_stats &st) {
     a.c1 = p.c1[k];
     a.c2 = p.c2[k];
     a.last = k + 1 == p.steps;
-    launch_b2_step(a, s);
+    if (el)
+      launch_b2_step_el(a, s);
+    else
+      launch_b2_step(a, s);
   }
   if (prof) PA_HIP(hipEventRecord(p.spans.back().second, s));
   launch_b2_check(a, s);
@@ -674,6 +687,7 @@ B2Args solve_args(const pa_bdm2 *b, const B2Plan &p, const pa_solve_cfg &cfg, in
   a.rtol2 = cfg.cg_rtol * cfg.cg_rtol;
   a.fail = p.fail;
   a.rmax = p.rmax;
+  a.loc = p.eloc;
   return a;
 }
 
@@ -774,6 +788,7 @@ size_t b2_layout(pa_bdm2 *b, char *base) {
   place(off, b->rloc, &d.rloc, base);
   place(off, b->qtab, &d.qtab, base);
   place(off, b->ftab, &d.ftab, base);
+  place(off, b->mT, &d.mT, base);
   if (base) {
     d.nu = b->nu;
     d.nh = b->nh;
@@ -1187,6 +1202,7 @@ int pa_bdm2_bind(pa_ctx *ctx, pa_bdm2 *b, void *dev_buf) {
     pa::up(s, b->d.rloc, b->rloc);
     pa::up(s, b->d.qtab, b->qtab);
     pa::up(s, b->d.ftab, b->ftab);
+    pa::up(s, b->d.mT, b->mT);
     pa::sync_checked(s);
   });
 }

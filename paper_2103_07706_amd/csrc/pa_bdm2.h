@@ -47,7 +47,11 @@ struct B2Dev {
   const int32_t *rloc = nullptr;   // [nu][2]: 12 c + slot of the row's cells (-1: none)
   const double *qtab = nullptr;    // [kB2VQ][4]: barycentric l0, l1, l2, weight (sum 1)
   const double *ftab = nullptr;    // [kB2FQ][2]: t in [0, 1], weight (sum 1)
+  const double *mT = nullptr;      // [nc][12][12]: s_i s_j (M_u)_T of the cell slots
 };
+// Blocks at least this wide take the element form of the mass-solve step
+// (a cell pass and a row pass) instead of the row kernel.
+constexpr int kB2ElMin = 8;
 
 // Per-launch arguments; blocks are row-major [row][Bs].
 struct B2Args {
@@ -65,6 +69,7 @@ struct B2Args {
   double *dir_out;
   int last;
   double *part;                   // per-workgroup partials [wg][Bs]
+  double *loc;                    // element step: [nc * 12][Bs] cell products
   double *norms;                  // [2][Bs]: |r_0|^2, |r_K|^2
   double rtol2;
   int *fail;
@@ -120,7 +125,8 @@ void launch_b2_bcast(const B2ColArgs &a, hipStream_t s);
 void launch_b2_wsum(const B2ColArgs &a, hipStream_t s);
 
 void launch_b2_stiff(const B2Args &a, hipStream_t s);
-void launch_b2_step(const B2Args &a, hipStream_t s);
+void launch_b2_step(const B2Args &a, hipStream_t s);     // row form (ELL rows)
+void launch_b2_step_el(const B2Args &a, hipStream_t s);  // element form (cell pass + row pass)
 void launch_b2_norm(const B2Args &a, int slot, hipStream_t s);  // partials of |r|^2 -> norms[slot]
 void launch_b2_check(const B2Args &a, hipStream_t s);
 void launch_b2_acc(const B2Args &a, hipStream_t s);
@@ -136,7 +142,7 @@ struct pa_bdm2 {
   double g = 0, H = 0, omega = 0, lambda_bar = 0;
   double eig_min = 0, eig_max = 0;  // Ritz bounds of D^-1 M_u
   std::vector<int32_t> col, bcol, cdof;
-  std::vector<double> mass, cor, bval, dinv, q, ncell, qtab, ftab;
+  std::vector<double> mass, cor, bval, dinv, q, ncell, qtab, ftab, mT;
   std::vector<int32_t> etab, rloc;
   size_t dev_bytes = 0;
   void *dev = nullptr;

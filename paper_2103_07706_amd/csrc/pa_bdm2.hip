@@ -90,6 +90,46 @@ __global__ __launch_bounds__(kBWG) void k_b2_step(B2Args a) {
   }
 }
 
+// Element form of the step, cell pass: loc[12 c + i] = sum_j mT_c[i][j] d[cdof_j].
+__global__ __launch_bounds__(kBWG) void k_b2_mel(B2Args a) {
+  const B2Dev &d = a.d;
+  const int Bs = a.Bs;
+  const size_t total = (size_t)d.nc * Bs, stride = (size_t)gridDim.x * kBWG;
+  for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < total; i += stride) {
+    const int cell = (int)(i / Bs), c = (int)(i % Bs);
+    double v[12];
+#pragma unroll
+    for (int j = 0; j < 12; j++) v[j] = a.dir_in[(size_t)d.cdof[12 * cell + j] * Bs + c];
+    const double *M = d.mT + (size_t)144 * cell;
+#pragma unroll
+    for (int r = 0; r < 12; r++) {
+      double y = 0.0;
+#pragma unroll
+      for (int j = 0; j < 12; j++) y = fma(M[12 * r + j], v[j], y);
+      a.loc[((size_t)12 * cell + r) * Bs + c] = y;
+    }
+  }
+}
+
+// Element form, row pass: M d from the row's one or two cell slots, then
+// the same update as k_b2_step.
+__global__ __launch_bounds__(kBWG) void k_b2_step_el(B2Args a) {
+  const B2Dev &d = a.d;
+  const int Bs = a.Bs;
+  const size_t nvel = (size_t)d.nu * Bs, stride = (size_t)gridDim.x * kBWG;
+  for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < nvel; i += stride) {
+    const int row = (int)(i / Bs), c = (int)(i % Bs);
+    const int p0 = d.rloc[2 * row], p1 = d.rloc[2 * row + 1];
+    double md = a.loc[(size_t)p0 * Bs + c];
+    if (p1 >= 0) md += a.loc[(size_t)p1 * Bs + c];
+    const double di = a.dir_in[i];
+    a.x[i] += di;
+    const double r = a.r[i] - md;
+    a.r[i] = r;
+    if (!a.last) a.dir_out[i] = a.c1 * di + a.c2 * d.dinv[row] * r;
+  }
+}
+
 __global__ __launch_bounds__(kBWG) void k_b2_norm(B2Args a) {
   const int Bs = a.Bs;
   const size_t nvel = (size_t)a.d.nu * Bs, stride = (size_t)gridDim.x * kBWG;
@@ -472,6 +512,10 @@ void launch_b2_stiff(const B2Args &a, hipStream_t s) {
 }
 void launch_b2_step(const B2Args &a, hipStream_t s) {
   hipLaunchKernelGGL(k_b2_step, dim3(b2_grid(a.d.nu, a.Bs)), dim3(kBWG), 0, s, a);
+}
+void launch_b2_step_el(const B2Args &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_b2_mel, dim3(b2_grid(a.d.nc, a.Bs)), dim3(kBWG), 0, s, a);
+  hipLaunchKernelGGL(k_b2_step_el, dim3(b2_grid(a.d.nu, a.Bs)), dim3(kBWG), 0, s, a);
 }
 void launch_b2_check(const B2Args &a, hipStream_t s) {
   hipLaunchKernelGGL(k_b2_norm, dim3(b2_grid(a.d.nu, a.Bs)), dim3(kBWG), 0, s, a);
