@@ -347,8 +347,12 @@ int pa_diagnostics(pa_ctx *ctx, const pa_ops *ops, int B, const double *U_dev,
  *   PA_KERNEL_CHEB_FUSED   fused single-column steps (k_cheb_fused)
  *   PA_KERNEL_CHEB3_ITER   three-term block step (k_cheb3_iter)
  *   PA_KERNEL_CHEB32_ITER  FP32 three-term step (k_cheb32_iter[4])
- *   PA_KERNEL_B2_STEP      BDM2 mass-solve step (k_b2_step: per row the ELL
- *                          row and D^-1, 260 bytes; per row and column 48)
+ *   PA_KERNEL_B2_STEP      BDM2 mass-solve step (k_b2_step, row form: per row
+ *                          the ELL row's 21 values, a third of its block's 7
+ *                          column-block ids and D^-1, 185.3 bytes; element
+ *                          form on 8 or more columns, k_b2_mel + k_b2_step_el:
+ *                          per cell its 12 x 12 block, per row D^-1; per row
+ *                          and column 48 bytes in both)
  * pa_ctx_profile starts a new tally (PA_KERNEL_NONE switches it off and
  * graph capture is not used while it is on); pa_ctx_profile_read returns the
  * tally so far.  The calls made while the hook is on fill it; reading needs
@@ -571,7 +575,8 @@ int pa_batch_destroy(pa_batch *b);
  * 5 x 5 points per cell.  The mass solves M_u^-1 are Jacobi Chebyshev
  * semi-iterations over the Ritz bounds of D^-1 M_u (widened 3% below and 1%
  * above) to cg_rtol, checked in FP64 (PA_ENOCONV if a check fails); M_h^-1
- * is exact (block diagonal).  phys->b_cell must be NULL; lambda_bar is the
+ * is exact (block diagonal).  phys->b_cell must be NULL (the bottom of this
+ * pair is P1DG: pa_bdm2_set_bottom); lambda_bar is the
  * scale of the Chebyshev polynomial (set it, e.g. to rho(L) times a safety
  * factor, before an exponential). */
 int pa_bdm2_create(const pa_mesh *m, const pa_phys *phys, pa_bdm2 **out);
@@ -592,6 +597,10 @@ int pa_bdm2_tables(const pa_bdm2 *b, int32_t *col, double *mass, double *cor,
  * (256-byte aligned, kept alive and unwritten while calls run). */
 int pa_bdm2_device_size(const pa_bdm2 *b, size_t *bytes);
 int pa_bdm2_bind(pa_ctx *ctx, pa_bdm2 *b, void *dev_buf);
+/* Bottom height b as P1DG coefficients (nh host values, copied; NULL: flat),
+ * before pa_bdm2_bind (PA_EINVAL after).  Only N sees it: its depth flux
+ * carries eta - b (L keeps the mean depth H). */
+int pa_bdm2_set_bottom(pa_bdm2 *b, const double *bottom_host);
 int pa_bdm2_set_lambda(pa_bdm2 *b, double lambda_bar);
 /* Power iteration on the GPU, v <- -L^2 v normalised in the energy norm
  * H u' M_u u + g eta' M_h eta (L is skew in it), from a fixed start vector
@@ -633,8 +642,8 @@ int pa_bdm2_expL_apply(pa_ctx *ctx, const pa_bdm2 *b, int B, const double *t_hos
  *   int psi eta2 = int grad psi . u eta - int_Gamma [[psi u]] eta~,
  * u^perp = k x u, grad^perp = k x grad, ~ the value of the cell the flow
  * leaves, chosen at every facet quadrature point from the normal flux seen
- * by the edge's first cell (positive: that cell, else the other), eta the
- * depth perturbation over a flat bottom.  Quadrature: the collapsed 5 x 5
+ * by the edge's first cell (positive: that cell, else the other), eta - b
+ * in place of eta when a bottom is set (pa_bdm2_set_bottom).  Quadrature: the collapsed 5 x 5
  * rule in cells (the cell integrands have degree 5), 4-point Gauss-Legendre
  * on every side.  M_u solved as for pa_bdm2_apply_L, M_h exactly.
  * Member-major states in device memory; out must not alias U. */

@@ -178,6 +178,7 @@ void bdm2_assemble(pa_bdm2 *b, const Mesh &m, const pa_phys &ph) {
   b->q.assign((size_t)36 * nc, 0.0);
   b->ncell.assign((size_t)kB2NC * nc, 0.0);
   b->mT.assign((size_t)144 * nc, 0.0);
+  b->bot.assign((size_t)3 * nc, 0.0);
   b->rloc.assign((size_t)2 * nu, -1);
   b->etab.assign((size_t)4 * ne, -1);
   // volume and side rules of the nonlinear term
@@ -363,7 +364,14 @@ void bdm2_assemble(pa_bdm2 *b, const Mesh &m, const pa_phys &ph) {
         b->q[((size_t)c * 3 + qq) * 12 + j] = -ph.H * s;
       }
   }
-  // column-major ELL tables, padded with the row itself and zero values
+  // column-major ELL tables in block order: unknowns come in blocks of three
+  // (an edge's points, a cell's moments) and the three rows of a block share
+  // their columns, which are whole blocks (seven for an edge row: five edges
+  // and two cells; four for a cell row, padded with the row's own block and
+  // zero values).  Slot s = 3 b + k holds column 3 bid[b] + k, the block ids
+  // ascending; one id table per row block serves its three rows.
+  const int nb = nu / 3;
+  b->bid.assign((size_t)kB2WBlk * nb, 0);
   b->col.assign((size_t)kB2W * nu, 0);
   b->mass.assign((size_t)kB2W * nu, 0.0);
   b->cor.assign((size_t)kB2W * nu, 0.0);
@@ -372,12 +380,32 @@ void bdm2_assemble(pa_bdm2 *b, const Mesh &m, const pa_phys &ph) {
   b->dinv.assign(nu, 0.0);
   for (int r = 0; r < nu; r++) {
     const RowAcc &ra = rows[r];
-    for (int s = 0; s < kB2W; s++) {
-      const bool on = s < ra.n;
-      b->col[(size_t)s * nu + r] = on ? ra.col[s] : r;
-      b->mass[(size_t)s * nu + r] = on ? ra.m[s] : 0.0;
-      b->cor[(size_t)s * nu + r] = on ? ra.f[s] : 0.0;
-      if (on && ra.col[s] == r) b->dinv[r] = 1.0 / ra.m[s];
+    int blk[kB2WBlk], nbk = 0;
+    for (int s = 0; s < ra.n; s++) {
+      const int bk = ra.col[s] / 3;
+      bool seen = false;
+      for (int t = 0; t < nbk; t++) seen |= blk[t] == bk;
+      if (!seen) {
+        if (nbk == kB2WBlk) throw Error(PA_EINVAL, "BDM2 row meets more than seven blocks");
+        blk[nbk++] = bk;
+      }
+    }
+    std::sort(blk, blk + nbk);
+    if (3 * nbk != ra.n) throw Error(PA_EINVAL, "BDM2 row holds a partial block");
+    for (int t = nbk; t < kB2WBlk; t++) blk[t] = r / 3;
+    for (int t = 0; t < kB2WBlk; t++) {
+      if (r % 3 == 0) b->bid[(size_t)t * nb + r / 3] = blk[t];
+      else if (b->bid[(size_t)t * nb + r / 3] != blk[t])
+        throw Error(PA_EINVAL, "rows of a BDM2 block differ in their columns");
+      for (int k = 0; k < 3; k++) b->col[(size_t)(3 * t + k) * nu + r] = 3 * blk[t] + k;
+    }
+    for (int s = 0; s < ra.n; s++) {
+      const int bk = ra.col[s] / 3, k = ra.col[s] % 3;
+      int t = 0;
+      while (blk[t] != bk) t++;
+      b->mass[(size_t)(3 * t + k) * nu + r] = ra.m[s];
+      b->cor[(size_t)(3 * t + k) * nu + r] = ra.f[s];
+      if (ra.col[s] == r) b->dinv[r] = 1.0 / ra.m[s];
     }
     const BRowAcc &rb = brows[r];
     for (int s = 0; s < kB2WB; s++) {
@@ -649,10 +677,11 @@ void b2_solve(const B2Plan &p, B2Args &a, hipStream_t s, pa_stats &st) {
     p.spans.emplace_back(prof_event(p.ctx), prof_event(p.ctx));
     PA_HIP(hipEventRecord(p.spans.back().first, s));
     // per row and column: x and r in and out, d in, d' out (not on the
-    // last step); per row the ELL row (21 columns and values) and D^-1, or
-    // in the element form per cell its 12 x 12 block and per row D^-1
+    // last step); per row the ELL row (21 values, a third of seven block
+    // ids) and D^-1, or in the element form per cell its 12 x 12 block and
+    // per row D^-1
     const double rows = a.d.nu, cols = a.Bs;
-    const double mat = el ? 1152.0 * a.d.nc + 8.0 * rows : 260.0 * rows;
+    const double mat = el ? 1152.0 * a.d.nc + 8.0 * rows : (168.0 + 28.0 / 3.0 + 8.0) * rows;
     p.prof_launches += p.steps;
     p.prof_bytes += p.steps * (mat + 48.0 * rows * cols) - 8.0 * rows * cols;
     p.prof_units += (double)p.steps * cols;
@@ -775,7 +804,7 @@ void place(size_t &off, const std::vector<T> &v, const T **dst, char *base) {
 size_t b2_layout(pa_bdm2 *b, char *base) {
   size_t off = 0;
   B2Dev d;
-  place(off, b->col, &d.col, base);
+  place(off, b->bid, &d.bid, base);
   place(off, b->mass, &d.mass, base);
   place(off, b->cor, &d.cor, base);
   place(off, b->bcol, &d.bcol, base);
@@ -789,6 +818,7 @@ size_t b2_layout(pa_bdm2 *b, char *base) {
   place(off, b->qtab, &d.qtab, base);
   place(off, b->ftab, &d.ftab, base);
   place(off, b->mT, &d.mT, base);
+  place(off, b->bot, &d.bot, base);
   if (base) {
     d.nu = b->nu;
     d.nh = b->nh;
@@ -1189,7 +1219,7 @@ int pa_bdm2_bind(pa_ctx *ctx, pa_bdm2 *b, void *dev_buf) {
     b->dev = dev_buf;
     pa::b2_layout(b, (char *)dev_buf);
     hipStream_t s = ctx->stream;
-    pa::up(s, b->d.col, b->col);
+    pa::up(s, b->d.bid, b->bid);
     pa::up(s, b->d.mass, b->mass);
     pa::up(s, b->d.cor, b->cor);
     pa::up(s, b->d.bcol, b->bcol);
@@ -1203,7 +1233,19 @@ int pa_bdm2_bind(pa_ctx *ctx, pa_bdm2 *b, void *dev_buf) {
     pa::up(s, b->d.qtab, b->qtab);
     pa::up(s, b->d.ftab, b->ftab);
     pa::up(s, b->d.mT, b->mT);
+    pa::up(s, b->d.bot, b->bot);
     pa::sync_checked(s);
+  });
+}
+
+int pa_bdm2_set_bottom(pa_bdm2 *b, const double *bottom_host) {
+  return pa::guard([&] {
+    pa::bneed(b != nullptr, "NULL argument");
+    pa::bneed(b->dev == nullptr, "set the bottom before pa_bdm2_bind");
+    if (bottom_host)
+      std::copy(bottom_host, bottom_host + b->nh, b->bot.begin());
+    else
+      std::fill(b->bot.begin(), b->bot.end(), 0.0);
   });
 }
 

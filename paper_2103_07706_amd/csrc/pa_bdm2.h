@@ -15,6 +15,7 @@ namespace pa {
 
 constexpr int kB2W = 21;   // ELL width of the velocity rows (21 unknowns share a cell with an edge unknown)
 constexpr int kB2WB = 6;   // ELL width of the divergence rows (depth unknowns of the adjacent cells)
+constexpr int kB2WBlk = 7; // column blocks of three per velocity row (kB2W = 3 kB2WBlk)
 
 // Per-cell table of the nonlinear term, kB2NC doubles a cell: the raw
 // coefficients of the dual basis (C[f][j] at 12 f + j: basis function j is
@@ -34,7 +35,8 @@ constexpr int kB2FQ = 4;   // points per side (Gauss-Legendre)
 struct B2Dev {
   int nu = 0, nh = 0, nc = 0, ne = 0;
   double g = 0;
-  const int32_t *col = nullptr;    // [kB2W][nu] column-major
+  const int32_t *bid = nullptr;    // [kB2WBlk][nu / 3]: column blocks of each row block;
+                                   // slot s of row r is column 3 bid[s / 3][r / 3] + s % 3
   const double *mass = nullptr;    // [kB2W][nu]
   const double *cor = nullptr;     // [kB2W][nu]
   const int32_t *bcol = nullptr;   // [kB2WB][nu]
@@ -48,6 +50,7 @@ struct B2Dev {
   const double *qtab = nullptr;    // [kB2VQ][4]: barycentric l0, l1, l2, weight (sum 1)
   const double *ftab = nullptr;    // [kB2FQ][2]: t in [0, 1], weight (sum 1)
   const double *mT = nullptr;      // [nc][12][12]: s_i s_j (M_u)_T of the cell slots
+  const double *bot = nullptr;     // [nh]: bottom height (P1DG coefficients)
 };
 // Blocks at least this wide take the element form of the mass-solve step
 // (a cell pass and a row pass) instead of the row kernel.
@@ -141,8 +144,8 @@ struct pa_bdm2 {
   int ne = 0, nc = 0, nu = 0, nh = 0;
   double g = 0, H = 0, omega = 0, lambda_bar = 0;
   double eig_min = 0, eig_max = 0;  // Ritz bounds of D^-1 M_u
-  std::vector<int32_t> col, bcol, cdof;
-  std::vector<double> mass, cor, bval, dinv, q, ncell, qtab, ftab, mT;
+  std::vector<int32_t> col, bid, bcol, cdof;
+  std::vector<double> mass, cor, bval, dinv, q, ncell, qtab, ftab, mT, bot;
   std::vector<int32_t> etab, rloc;
   size_t dev_bytes = 0;
   void *dev = nullptr;

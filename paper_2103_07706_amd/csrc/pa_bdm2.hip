@@ -1,6 +1,7 @@
 // HIP kernels of the BDM2 x P1DG linear operator (the paper's own spaces,
 // Sec. 2.5): the stiffness with the mass-solve set-up, Jacobi Chebyshev
-// steps on the velocity mass matrix (ELL width 21, column-major tables so
+// steps on the velocity mass matrix (ELL width 21 in seven blocks of three
+// columns, one block-id table per three rows; column-major value tables so
 // that consecutive rows read consecutive entries), residual norms and the
 // weighted accumulation of the exponential.  Blocks are row-major
 // [row][Bs] with Bs a power of two up to 64, one (row, column) per thread in
@@ -15,6 +16,7 @@ namespace pa {
 
 namespace {
 constexpr int kBWG = 256;
+
 
 // Per-workgroup column sums of v (the thread's column is tid % Bs).
 __device__ void b2_partial(double v, int Bs, double *part) {
@@ -40,9 +42,11 @@ __global__ __launch_bounds__(kBWG) void k_b2_stiff(B2Args a) {
       double fu = 0.0, be = 0.0;
       if (!a.rhs) {
 #pragma unroll
-      for (int s = 0; s < kB2W; s++) {
-        const size_t k = (size_t)s * d.nu + row;
-        fu = fma(d.cor[k], a.u[(size_t)d.col[k] * Bs + c], fu);
+      for (int t = 0; t < kB2WBlk; t++) {
+        const size_t col0 = (size_t)3 * d.bid[(size_t)t * (d.nu / 3) + row / 3];
+#pragma unroll
+        for (int q = 0; q < 3; q++)
+          fu = fma(d.cor[(size_t)(3 * t + q) * d.nu + row], a.u[(col0 + q) * Bs + c], fu);
       }
 #pragma unroll
       for (int s = 0; s < kB2WB; s++) {
@@ -78,9 +82,11 @@ __global__ __launch_bounds__(kBWG) void k_b2_step(B2Args a) {
     const int row = (int)(i / Bs), c = (int)(i % Bs);
     double md = 0.0;
 #pragma unroll
-    for (int s = 0; s < kB2W; s++) {
-      const size_t k = (size_t)s * d.nu + row;
-      md = fma(d.mass[k], a.dir_in[(size_t)d.col[k] * Bs + c], md);
+    for (int t = 0; t < kB2WBlk; t++) {
+      const size_t col0 = (size_t)3 * d.bid[(size_t)t * (d.nu / 3) + row / 3];
+#pragma unroll
+      for (int q = 0; q < 3; q++)
+        md = fma(d.mass[(size_t)(3 * t + q) * d.nu + row], a.dir_in[(col0 + q) * Bs + c], md);
     }
     const double di = a.dir_in[i];
     a.x[i] += di;
@@ -187,9 +193,11 @@ __global__ __launch_bounds__(kBWG) void k_b2_wnorm(B2Args a, double H) {
     if (i < nvel) {
       double mu = 0.0;
 #pragma unroll
-      for (int s = 0; s < kB2W; s++) {
-        const size_t k = (size_t)s * d.nu + row;
-        mu = fma(d.mass[k], a.u[(size_t)d.col[k] * Bs + c], mu);
+      for (int t = 0; t < kB2WBlk; t++) {
+        const size_t col0 = (size_t)3 * d.bid[(size_t)t * (d.nu / 3) + row / 3];
+#pragma unroll
+        for (int q = 0; q < 3; q++)
+          mu = fma(d.mass[(size_t)(3 * t + q) * d.nu + row], a.u[(col0 + q) * Bs + c], mu);
       }
       acc = fma(H * a.u[i], mu, acc);
     } else {
@@ -299,7 +307,8 @@ __global__ __launch_bounds__(kBWG) void k_b2_edge(B2NlArgs a) {
 #pragma unroll
       for (int f = 0; f < 12; f++) ar[k][f] = a.raw[((size_t)12 * cc[k] + f) * Bs + col];
 #pragma unroll
-      for (int r = 0; r < 3; r++) hc[k][r] = a.eta[((size_t)3 * cc[k] + r) * Bs + col];
+      for (int r = 0; r < 3; r++)
+        hc[k][r] = a.eta[((size_t)3 * cc[k] + r) * Bs + col] - d.bot[3 * cc[k] + r];
     }
     for (int p = 0; p < kB2FQ; p++) {
       const double t = d.ftab[2 * p];
@@ -339,7 +348,7 @@ __global__ __launch_bounds__(kBWG) void k_b2_cell(B2NlArgs a) {
       g[f] = 0.0;
     }
 #pragma unroll
-    for (int r = 0; r < 3; r++) hc[r] = a.eta[((size_t)3 * cell + r) * Bs + col];
+    for (int r = 0; r < 3; r++) hc[r] = a.eta[((size_t)3 * cell + r) * Bs + col] - d.bot[3 * cell + r];
     // volume: u . grad^perp(u^perp . m_a e_c) + (div m_a e_c) |u|^2 / 2
     for (int q = 0; q < kB2VQ; q++) {
       const double l0 = d.qtab[4 * q], l1 = d.qtab[4 * q + 1], l2 = d.qtab[4 * q + 2];

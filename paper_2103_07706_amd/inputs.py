@@ -189,6 +189,14 @@ def williamson5_bottom(verts, cell_verts, b0: float = 2000.0, r0: float = math.p
     return b0 * (1.0 - r / r0)
 
 
+def williamson5_bottom_p1dg(verts, cell_verts, **kw):
+    """The same mountain as P1DG coefficients: its height at each cell's
+    three vertices (radially projected), cell by cell."""
+    verts = np.asarray(verts, dtype=np.float64)
+    at_v = williamson5_bottom(verts, np.repeat(np.arange(len(verts))[:, None], 3, axis=1), **kw)
+    return at_v[np.asarray(cell_verts)].ravel()
+
+
 def williamson5_state(verts, cell_verts, edge_verts, phys: Physics = None, u0: float = 20.0):
     """Initial state of the paper's test case (Sec. 3, flow over a mountain):
     the zonal flow u = (u0/R)(-y, x, 0) and the free surface in geostrophic

@@ -147,6 +147,7 @@ EXPORTS = {
     "pa_bdm2_device_size": (ctypes.c_int, [_V, ctypes.POINTER(_SZ)]),
     "pa_bdm2_bind": (ctypes.c_int, [_V, _V, _V]),
     "pa_bdm2_set_lambda": (ctypes.c_int, [_V, ctypes.c_double]),
+    "pa_bdm2_set_bottom": (ctypes.c_int, [_V, _D]),
     "pa_bdm2_estimate_lambda": (ctypes.c_int, [_V, _V, ctypes.c_int, ctypes.c_double, _V, _SZ,
                                                _D]),
     "pa_bdm2_workspace_size": (ctypes.c_int, [_V, ctypes.c_int, ctypes.c_int, _D, _V,
@@ -622,6 +623,17 @@ class BDM2:
 
     def set_lambda(self, lambda_bar):
         _check(lib().pa_bdm2_set_lambda(self._h, float(lambda_bar)))
+
+    def set_bottom(self, b):
+        """pa_bdm2_set_bottom (before bind): P1DG bottom heights, or None."""
+        if b is None:
+            _check(lib().pa_bdm2_set_bottom(self._h, None))
+            return self
+        self._bot = np.ascontiguousarray(b, np.float64)
+        if self._bot.shape != (self.nh,):
+            raise ValueError("bottom needs nh values")
+        _check(lib().pa_bdm2_set_bottom(self._h, _dp(self._bot)))
+        return self
 
     def estimate_lambda(self, iters=200, safety=1.05):
         """pa_bdm2_estimate_lambda: sets and returns lambda_bar."""
