@@ -131,7 +131,7 @@ void launch_b2_stiff(const B2Args &a, hipStream_t s);
 void launch_b2_step(const B2Args &a, hipStream_t s);     // row form (ELL rows)
 void launch_b2_step_el(const B2Args &a, hipStream_t s);  // element form (cell pass + row pass)
 void launch_b2_norm(const B2Args &a, int slot, hipStream_t s);  // partials of |r|^2 -> norms[slot]
-void launch_b2_check(const B2Args &a, hipStream_t s);
+void launch_b2_check(const B2Args &a, hipStream_t s);  // after the last step: |r_K|^2 vs rtol^2 |r_0|^2
 void launch_b2_acc(const B2Args &a, hipStream_t s);
 // norms[0][c] = H u' M_u u + g eta' M_h eta of column c of (u, eta)
 void launch_b2_wnorm(const B2Args &a, double H, hipStream_t s);

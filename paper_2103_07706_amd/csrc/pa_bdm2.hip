@@ -18,16 +18,19 @@ namespace {
 constexpr int kBWG = 256;
 
 
-// Per-workgroup column sums of v (the thread's column is tid % Bs).
+// Per-workgroup column sums of v (the thread's column is tid % Bs): a tree
+// over the workgroup in a fixed order (strides are multiples of Bs, so each
+// addition stays within one column).
 __device__ void b2_partial(double v, int Bs, double *part) {
   __shared__ double red[kBWG];
-  red[threadIdx.x] = v;
+  const int t = threadIdx.x;
+  red[t] = v;
   __syncthreads();
-  if ((int)threadIdx.x < Bs) {
-    double s = 0.0;
-    for (int t = threadIdx.x; t < kBWG; t += Bs) s += red[t];
-    part[(size_t)blockIdx.x * Bs + threadIdx.x] = s;
+  for (int h = kBWG / 2; h >= Bs; h /= 2) {
+    if (t < h) red[t] += red[t + h];
+    __syncthreads();
   }
+  if (t < Bs) part[(size_t)blockIdx.x * Bs + t] = red[t];
 }
 
 __global__ __launch_bounds__(kBWG) void k_b2_stiff(B2Args a) {
@@ -73,11 +76,13 @@ __global__ __launch_bounds__(kBWG) void k_b2_stiff(B2Args a) {
   b2_partial(rr, Bs, a.part);
 }
 
-// x += d, r -= M d, d' = c1 d + c2 D^-1 r (not on the last step).
+// x += d, r -= M d, d' = c1 d + c2 D^-1 r (not on the last step; the last
+// step leaves the per-workgroup partials of |r|^2 instead).
 __global__ __launch_bounds__(kBWG) void k_b2_step(B2Args a) {
   const B2Dev &d = a.d;
   const int Bs = a.Bs;
   const size_t nvel = (size_t)d.nu * Bs, stride = (size_t)gridDim.x * kBWG;
+  double rr = 0.0;
   for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < nvel; i += stride) {
     const int row = (int)(i / Bs), c = (int)(i % Bs);
     double md = 0.0;
@@ -92,8 +97,12 @@ __global__ __launch_bounds__(kBWG) void k_b2_step(B2Args a) {
     a.x[i] += di;
     const double r = a.r[i] - md;
     a.r[i] = r;
-    if (!a.last) a.dir_out[i] = a.c1 * di + a.c2 * d.dinv[row] * r;
+    if (!a.last)
+      a.dir_out[i] = a.c1 * di + a.c2 * d.dinv[row] * r;
+    else
+      rr = fma(r, r, rr);
   }
+  if (a.last) b2_partial(rr, Bs, a.part);
 }
 
 // Element form of the step, cell pass: loc[12 c + i] = sum_j mT_c[i][j] d[cdof_j].
@@ -123,6 +132,7 @@ __global__ __launch_bounds__(kBWG) void k_b2_step_el(B2Args a) {
   const B2Dev &d = a.d;
   const int Bs = a.Bs;
   const size_t nvel = (size_t)d.nu * Bs, stride = (size_t)gridDim.x * kBWG;
+  double rr = 0.0;
   for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < nvel; i += stride) {
     const int row = (int)(i / Bs), c = (int)(i % Bs);
     const int p0 = d.rloc[2 * row], p1 = d.rloc[2 * row + 1];
@@ -132,8 +142,12 @@ __global__ __launch_bounds__(kBWG) void k_b2_step_el(B2Args a) {
     a.x[i] += di;
     const double r = a.r[i] - md;
     a.r[i] = r;
-    if (!a.last) a.dir_out[i] = a.c1 * di + a.c2 * d.dinv[row] * r;
+    if (!a.last)
+      a.dir_out[i] = a.c1 * di + a.c2 * d.dinv[row] * r;
+    else
+      rr = fma(r, r, rr);
   }
+  if (a.last) b2_partial(rr, Bs, a.part);
 }
 
 __global__ __launch_bounds__(kBWG) void k_b2_norm(B2Args a) {
@@ -526,8 +540,9 @@ void launch_b2_step_el(const B2Args &a, hipStream_t s) {
   hipLaunchKernelGGL(k_b2_mel, dim3(b2_grid(a.d.nc, a.Bs)), dim3(kBWG), 0, s, a);
   hipLaunchKernelGGL(k_b2_step_el, dim3(b2_grid(a.d.nu, a.Bs)), dim3(kBWG), 0, s, a);
 }
+// After a last step (row or element form, both on b2_grid(nu, Bs) workgroups)
+// left the partials of |r_K|^2: the check against |r_0|^2.
 void launch_b2_check(const B2Args &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_b2_norm, dim3(b2_grid(a.d.nu, a.Bs)), dim3(kBWG), 0, s, a);
   hipLaunchKernelGGL(k_b2_fin, dim3(1), dim3(kFinT), 0, s, a, b2_grid(a.d.nu, a.Bs), 1);
 }
 void launch_b2_norm(const B2Args &a, int slot, hipStream_t s) {
