@@ -370,3 +370,40 @@ def test_gpu_bdm2_phase_avg_rhs_single_node_at_zero_is_N():
     n, _ = lb.nonlinear(U, _cfg())
     assert st["kmax"] == 0
     assert np.array_equal(nb.cpu().numpy(), n.cpu().numpy())
+
+
+def test_gpu_bdm2_table1_levels_3_to_5():
+    """Table 1 (golden table1_chebyshev_iterations.txt) with the library's
+    BDM2/P1DG operator and the test case's physics (H = 5960 m, g = 9.8):
+    the degree of exp(ds L) at 15, 30 and 60 minutes (the library's own
+    truncation, its kmax; iterations = degree - 1) from the GPU power
+    iteration's rho(L), on the library's own meshes, levels 3 to 5.  At
+    levels 3 and 4 this reproduces the oracle's counts (its Lanczos rho:
+    10, 15, 23 and 15, 23, 37); every count stays at or below the printed
+    one and the gap grows with the level (the printed counts imply a
+    spectral radius 4-12% above this flat-triangle operator's at levels 3
+    and 4)."""
+    import os
+    from gpu_common import _ctx
+    from paper_2103_07706_amd import pa
+    rows = {int(r[0]): r[1:] for r in np.loadtxt(
+        os.path.join(os.path.dirname(__file__), "golden", "table1_chebyshev_iterations.txt"),
+        dtype=int)}
+    got = {}
+    for lev in (3, 4, 5):
+        lb = pa.BDM2(pa.Mesh(lev), g=9.8, H=5960.0).bind(_ctx())
+        rho = lb.estimate_lambda(iters=400, safety=1.0)
+        counts = []
+        for ds in (900.0, 1800.0, 3600.0):
+            U = _dev(np.zeros((1, lb.n)))
+            _, st = lb.expL_apply([ds], U, _cfg(cheb_tol=1e-6, cg_rtol=1e-10))
+            counts.append(st["kmax"] - 1)
+        got[lev] = counts
+        print(f"level {lev}: rho {rho:.5e}, counts {counts}, Table 1 {rows[lev].tolist()}")
+        assert np.all(np.array(counts) <= rows[lev])
+    # the power iteration approaches rho from below: within one of the
+    # oracle's Lanczos counts
+    for lev, ref in ((3, [10, 15, 23]), (4, [15, 23, 37])):
+        assert np.abs(np.array(got[lev]) - ref).max() <= 1, (lev, got[lev])
+    gap = [float(np.mean(rows[l] / np.array(got[l]))) for l in (3, 4, 5)]
+    assert gap[0] <= gap[1] <= gap[2] < 1.3, gap
