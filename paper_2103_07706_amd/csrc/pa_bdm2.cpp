@@ -450,7 +450,7 @@ struct B2Plan {
   bool shared = false;
   int G = 0, Gs = 0, Mk = 0, Vs = 0, nvch = 0, ngroup = 0;
   std::vector<double> cfh, cbh;   // [kmax + 1][Mk]: c_k(s_m), w_m c_k(-s_m)
-  double *basis = nullptr, *V = nullptr, *Y = nullptr, *cfd = nullptr, *cbd = nullptr;
+  double *basis = nullptr, *Zs = nullptr, *V = nullptr, *Y = nullptr, *cfd = nullptr, *cbd = nullptr;
   double *eloc = nullptr;  // element-form step products [nc * 12][Bs] (wide blocks)
   double *Ra = nullptr, *Rb = nullptr, *acc = nullptr, *r = nullptr, *dir[2] = {nullptr, nullptr};
   double *raw = nullptr, *ut = nullptr, *loc = nullptr, *rhs = nullptr;
@@ -557,7 +557,9 @@ size_t b2_plan(const pa_bdm2 *b, int call, int B, const double *t, const pa_avg 
       if (avg->w[m] >= cfg.weight_cut * wmax && avg->w[m] != 0.0) keep.push_back((int)m);
     bneed(!keep.empty(), "no averaging term left");
     p.Mk = (int)keep.size();
-    p.G = std::max(1, std::min(B, 64 / p.Mk));
+    // up to 64 members share a basis; their node columns go through N 64
+    // at a time
+    p.G = std::min(B, 64);
     p.Gs = pad_cols(p.G);
     p.ngroup = (B + p.G - 1) / p.G;
     const int cols = p.G * p.Mk;
@@ -579,8 +581,9 @@ size_t b2_plan(const pa_bdm2 *b, int call, int B, const double *t, const pa_avg 
     const size_t n = (size_t)b->nu + b->nh;
     size_t off = 0;
     p.basis = take<double>(ws, off, cap, (size_t)(p.kmax + 1) * n * p.Gs);
-    p.V = take<double>(ws, off, cap, (size_t)p.nvch * n * p.Vs);
-    p.Y = take<double>(ws, off, cap, (size_t)p.nvch * n * p.Vs);
+    p.Zs = take<double>(ws, off, cap, (size_t)(p.kmax + 1) * n * p.Gs);
+    p.V = take<double>(ws, off, cap, n * p.Vs);
+    p.Y = take<double>(ws, off, cap, n * p.Vs);
     p.r = take<double>(ws, off, cap, (size_t)b->nu * 64);
     p.dir[0] = take<double>(ws, off, cap, (size_t)b->nu * 64);
     p.dir[1] = take<double>(ws, off, cap, (size_t)b->nu * 64);
@@ -879,7 +882,7 @@ void b2_run(pa_ctx *ctx, const pa_bdm2 *b, int call, int B, const double *t, con
     // (1/lb) L b_1 (P_1 = L / lb is half the general step).
     PA_HIP(hipMemcpyAsync(p.cfd, p.cfh.data(), p.cfh.size() * sizeof(double), hipMemcpyHostToDevice, s));
     PA_HIP(hipMemcpyAsync(p.cbd, p.cbh.data(), p.cbh.size() * sizeof(double), hipMemcpyHostToDevice, s));
-    const size_t nG = (size_t)n * p.Gs, nV = (size_t)n * p.Vs;
+    const size_t nG = (size_t)n * p.Gs;
     const double lb = b->lambda_bar;
     for (int g = 0; g < p.ngroup; g++) {
       const int j0 = g * p.G, gm = std::min(p.G, B - j0);
@@ -892,19 +895,26 @@ void b2_run(pa_ctx *ctx, const pa_bdm2 *b, int call, int B, const double *t, con
         else
           b2_lapply(b, p, cfg, s, Rk, Rn, p.basis + (k - 1) * nG, 2.0 / lb, st, p.Gs);
       }
-      B2BasisArgs ba{n, p.Gs, gm, p.Mk, p.Vs, p.nvch, p.kmax, p.cfd, p.cbd, p.basis, p.V, p.Y, p.basis};
-      launch_b2_comb(ba, s);
-      for (int q = 0; q < p.nvch; q++) b2_nl(b, p, cfg, s, p.V + q * nV, p.Y + q * nV, st);
-      launch_b2_zsum(ba, s);
+      AxpyArgs z0{nG * (p.kmax + 1), 0.0, 0.0, 0.0, nullptr, nullptr, nullptr, p.Zs};
+      launch_axpy(z0, s);
+      const int cols = gm * p.Mk;
+      for (int col0 = 0; col0 < cols; col0 += p.Vs) {
+        const int jlo = col0 / p.Mk, jhi = std::min(gm - 1, (col0 + p.Vs - 1) / p.Mk);
+        B2BasisArgs ba{n,    p.Gs,  gm,      p.Mk,    p.Vs, col0, jlo, jhi - jlo + 1, p.kmax,
+                       p.cfd, p.cbd, p.basis, p.V, p.Y, p.Zs};
+        launch_b2_comb(ba, s);
+        b2_nl(b, p, cfg, s, p.V, p.Y, st);
+        launch_b2_zsum(ba, s);
+      }
       for (int k = p.kmax - 1; k >= 0; k--) {
-        double *Zk = p.basis + k * nG;
+        double *Zk = p.Zs + k * nG;
         if (k + 2 <= p.kmax) {
-          AxpyArgs ax{nG, 1.0, 1.0, 0.0, Zk, p.basis + (k + 2) * nG, nullptr, Zk};
+          AxpyArgs ax{nG, 1.0, 1.0, 0.0, Zk, p.Zs + (k + 2) * nG, nullptr, Zk};
           launch_axpy(ax, s);
         }
-        b2_lapply(b, p, cfg, s, p.basis + (k + 1) * nG, Zk, Zk, (k == 0 ? 1.0 : 2.0) / lb, st, p.Gs);
+        b2_lapply(b, p, cfg, s, p.Zs + (k + 1) * nG, Zk, Zk, (k == 0 ? 1.0 : 2.0) / lb, st, p.Gs);
       }
-      TransArgs tb{n, gm, p.Gs, Uout + (size_t)j0 * n, p.basis};
+      TransArgs tb{n, gm, p.Gs, Uout + (size_t)j0 * n, p.Zs};
       launch_from_block(tb, s);
     }
     st.terms = B * p.Mk;

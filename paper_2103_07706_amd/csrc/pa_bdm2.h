@@ -110,12 +110,14 @@ struct B2ColArgs {
   const double *src;  // wsum: [n][Bs] block summed into out with the weights
 };
 // The average with shared bases (members j < G of a group, kept nodes
-// m < Mk, column j Mk + m of the node columns, stored in chunks of Vs
-// columns [q][n][Vs]; bases and sums [k][n][Gs]):
+// m < Mk, node column j Mk + m; a pass holds the Vs node columns from col0
+// on, [n][Vs], and touches members jlo .. jlo + jn - 1; bases and sums
+// [k][n][Gs]):
 //   comb: V(j, m) = sum_k cf[k][m] R_k[j]        (forward exponentials)
-//   zsum: Z_k[j] = sum_m cb[k][m] Y(j, m)        (backward weights)
+//   zsum: Z_k[j] += sum_m cb[k][m] Y(j, m)       (backward weights, the
+//         pass's columns; passes in a fixed order)
 struct B2BasisArgs {
-  int n, Gs, G, Mk, Vs, nvch, K;
+  int n, Gs, G, Mk, Vs, col0, jlo, jn, K;
   const double *cf, *cb;   // [K + 1][Mk]
   const double *R;         // comb: bases
   double *V;               // comb: node columns

@@ -469,13 +469,10 @@ __global__ __launch_bounds__(kBWG) void k_b2_wsum(B2ColArgs a) {
   }
 }
 __global__ __launch_bounds__(kBWG) void k_b2_comb(B2BasisArgs a) {
-  const size_t per = (size_t)a.n * a.Vs, total = per * a.nvch;
-  const size_t stride = (size_t)gridDim.x * kBWG;
+  const size_t total = (size_t)a.n * a.Vs, stride = (size_t)gridDim.x * kBWG;
   for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < total; i += stride) {
-    const int q = (int)(i / per);
-    const size_t rem = i % per;
-    const int row = (int)(rem / a.Vs), c = (int)(rem % a.Vs);
-    const int col = q * a.Vs + c, j = col / a.Mk, m = col % a.Mk;
+    const int row = (int)(i / a.Vs), c = (int)(i % a.Vs);
+    const int col = a.col0 + c, j = col / a.Mk, m = col % a.Mk;
     double v = 0.0;
     if (j < a.G)
       for (int k = 0; k <= a.K; k++)
@@ -486,27 +483,26 @@ __global__ __launch_bounds__(kBWG) void k_b2_comb(B2BasisArgs a) {
 
 __global__ __launch_bounds__(kBWG) void k_b2_zsum(B2BasisArgs a) {
   const int Kp = a.K + 1;
-  const size_t total = (size_t)a.n * a.Gs * Kp, stride = (size_t)gridDim.x * kBWG;
+  const size_t total = (size_t)a.n * a.jn * Kp, stride = (size_t)gridDim.x * kBWG;
   for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < total; i += stride) {
     const int k = (int)(i % Kp);
     const size_t rj = i / Kp;
-    const int j = (int)(rj % a.Gs), row = (int)(rj / a.Gs);
-    double v = 0.0;
-    if (j < a.G)
-      for (int m = 0; m < a.Mk; m++) {
-        const int col = j * a.Mk + m, q = col / a.Vs, c = col % a.Vs;
-        v = fma(a.cb[(size_t)k * a.Mk + m], a.Y[((size_t)q * a.n + row) * a.Vs + c], v);
-      }
+    const int j = a.jlo + (int)(rj % a.jn), row = (int)(rj / a.jn);
+    if (j >= a.G) continue;
+    const int m0 = max(0, a.col0 - j * a.Mk), m1 = min(a.Mk, a.col0 + a.Vs - j * a.Mk);
+    double v = a.Z[((size_t)k * a.n + row) * a.Gs + j];
+    for (int m = m0; m < m1; m++)
+      v = fma(a.cb[(size_t)k * a.Mk + m], a.Y[(size_t)row * a.Vs + (j * a.Mk + m - a.col0)], v);
     a.Z[((size_t)k * a.n + row) * a.Gs + j] = v;
   }
 }
 }  // namespace
 
 void launch_b2_comb(const B2BasisArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_b2_comb, dim3(b2_grid(a.n, a.Vs * a.nvch)), dim3(kBWG), 0, s, a);
+  hipLaunchKernelGGL(k_b2_comb, dim3(b2_grid(a.n, a.Vs)), dim3(kBWG), 0, s, a);
 }
 void launch_b2_zsum(const B2BasisArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_b2_zsum, dim3(b2_grid(a.n, a.Gs * (a.K + 1))), dim3(kBWG), 0, s, a);
+  hipLaunchKernelGGL(k_b2_zsum, dim3(b2_grid(a.n, a.jn * (a.K + 1))), dim3(kBWG), 0, s, a);
 }
 
 void launch_b2_bcast(const B2ColArgs &a, hipStream_t s) {

@@ -116,9 +116,13 @@ def test_bdm2_refuses_topography_and_bad_sizes(oracle_mesh):
     assert W(b._h, pa.PA_BDM2_EXPL, 1, pa._dp(t), None, ctypes.byref(cfg),
              ctypes.byref(sz)) == 0
     assert sz.value > 0
-    # an average over 100 members x 8 nodes runs 64 columns at a time: past
-    # the first chunk only the per-chunk weight tables grow
-    sizes = [b.workspace_size(pa.PA_BDM2_PHASE_AVG, mem, avg=avg) for mem in (1, 8, 100)]
+    # the average shares one basis among up to 64 members and streams the
+    # node columns through N 64 at a time: past 64 members the workspace
+    # stops growing (per term: past one pass only the weight tables grow)
+    sizes = [b.workspace_size(pa.PA_BDM2_PHASE_AVG, mem, avg=avg) for mem in (1, 64, 100)]
+    assert sizes[0] < sizes[1] and sizes[2] == sizes[1]
+    pt = pa.solve_cfg(backward=pa.PA_BACKWARD_PER_TERM)
+    sizes = [b.workspace_size(pa.PA_BDM2_PHASE_AVG, mem, avg=avg, cfg=pt) for mem in (1, 8, 100)]
     assert sizes[0] < sizes[1] and sizes[2] < 1.25 * sizes[1]
     assert b.workspace_size(pa.PA_BDM2_NONLINEAR, 3) > b.workspace_size(pa.PA_BDM2_APPLY_L, 3)
     # a step needs dt and the nodes; its workspace holds seven states more

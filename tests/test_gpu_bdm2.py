@@ -232,10 +232,11 @@ def test_gpu_bdm2_phase_avg_rhs_parity(backward):
 
 def test_gpu_bdm2_phase_avg_rhs_level5():
     """Level 5 (153600 velocity and 61440 depth unknowns).  64 members x
-    M = 8 nodes in the default form: eight groups of eight members sharing
-    their passes; members repeat every seven, so equal inputs sit in
-    different groups and columns and must give equal bits; every member's
-    depth mass is conserved (N conserves it, the exponentials keep it).
+    M = 8 nodes in the default form: one basis of 64 columns, the 512 node
+    columns through N in eight passes; members repeat every seven, so equal
+    inputs sit in different columns and passes and must give equal bits
+    (each member's eight nodes lie in one pass); every member's depth mass
+    is conserved (N conserves it, the exponentials keep it).
     One member at M = 2 against the oracle (its M = 8 average takes
     minutes on the host)."""
     import oracle
@@ -330,13 +331,14 @@ def test_gpu_bdm2_nonlinear_over_the_mountain():
         lb.set_bottom(None)   # after bind
 
 
-@pytest.mark.parametrize("M,members", [(3, 5), (100, 1), (1, 2)])
+@pytest.mark.parametrize("M,members", [(3, 5), (100, 1), (1, 2), (3, 30)])
 def test_gpu_bdm2_phase_avg_rhs_grouping(M, members):
-    """The shared-basis form's grouping at its edges: M = 3 (21 members a
-    group, 63 of 64 node columns, the last group ragged), M = 100 (one
-    member, its node columns over two passes of 64), M = 1 (64 members a
-    group at one column each): against the per-term form (every node on
-    its own column) and, for one member, the oracle."""
+    """The shared-basis form's passes at their edges: M = 3 (15 node
+    columns in one pass, members of one basis), M = 100 (one member, its
+    node columns over two passes of 64, the backward sums accumulated
+    across them), M = 1 (two members at one column each): against the
+    per-term form (every node on its own column) and, for one member, the
+    oracle."""
     import oracle
     from paper_2103_07706_amd import pa
     ob, lb, lm = _pair(2)
