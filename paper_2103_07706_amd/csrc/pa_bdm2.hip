@@ -17,6 +17,28 @@ namespace pa {
 namespace {
 constexpr int kBWG = 256;
 
+// Table reads of a wave-uniform cell, edge or row go through the constant
+// address space (scalar loads) when UNI: with 64 columns a wave holds one
+// cell, edge or row at all 64 columns (workgroup starts and strides are
+// multiples of 64, and the totals are too, so whole waves leave the loops
+// together).
+template <bool UNI, class T>
+struct KPtr {
+  using type = const T *;
+};
+template <class T>
+struct KPtr<true, T> {
+  using type = const __attribute__((address_space(4))) T *;
+};
+template <bool UNI, class T>
+__device__ inline typename KPtr<UNI, T>::type kp(const T *p) {
+  return (typename KPtr<UNI, T>::type)p;
+}
+template <bool UNI>
+__device__ inline int uni(int v) {
+  return UNI ? __builtin_amdgcn_readfirstlane(v) : v;
+}
+
 
 // Per-workgroup column sums of v (the thread's column is tid % Bs): a tree
 // over the workgroup in a fixed order (strides are multiples of Bs, so each
@@ -106,16 +128,18 @@ __global__ __launch_bounds__(kBWG) void k_b2_step(B2Args a) {
 }
 
 // Element form of the step, cell pass: loc[12 c + i] = sum_j mT_c[i][j] d[cdof_j].
+template <bool UNI>
 __global__ __launch_bounds__(kBWG) void k_b2_mel(B2Args a) {
   const B2Dev &d = a.d;
   const int Bs = a.Bs;
   const size_t total = (size_t)d.nc * Bs, stride = (size_t)gridDim.x * kBWG;
   for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < total; i += stride) {
-    const int cell = (int)(i / Bs), c = (int)(i % Bs);
+    const int cell = uni<UNI>((int)(i / Bs)), c = (int)(i % Bs);
+    const auto cdof = kp<UNI>(d.cdof + 12 * (size_t)cell);
     double v[12];
 #pragma unroll
-    for (int j = 0; j < 12; j++) v[j] = a.dir_in[(size_t)d.cdof[12 * cell + j] * Bs + c];
-    const double *M = d.mT + (size_t)144 * cell;
+    for (int j = 0; j < 12; j++) v[j] = a.dir_in[(size_t)cdof[j] * Bs + c];
+    const auto M = kp<UNI>(d.mT + (size_t)144 * cell);
 #pragma unroll
     for (int r = 0; r < 12; r++) {
       double y = 0.0;
@@ -128,14 +152,16 @@ __global__ __launch_bounds__(kBWG) void k_b2_mel(B2Args a) {
 
 // Element form, row pass: M d from the row's one or two cell slots, then
 // the same update as k_b2_step.
+template <bool UNI>
 __global__ __launch_bounds__(kBWG) void k_b2_step_el(B2Args a) {
   const B2Dev &d = a.d;
   const int Bs = a.Bs;
   const size_t nvel = (size_t)d.nu * Bs, stride = (size_t)gridDim.x * kBWG;
   double rr = 0.0;
   for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < nvel; i += stride) {
-    const int row = (int)(i / Bs), c = (int)(i % Bs);
-    const int p0 = d.rloc[2 * row], p1 = d.rloc[2 * row + 1];
+    const int row = uni<UNI>((int)(i / Bs)), c = (int)(i % Bs);
+    const auto rl = kp<UNI>(d.rloc + 2 * (size_t)row);
+    const int p0 = rl[0], p1 = rl[1];
     double md = a.loc[(size_t)p0 * Bs + c];
     if (p1 >= 0) md += a.loc[(size_t)p1 * Bs + c];
     const double di = a.dir_in[i];
@@ -143,7 +169,7 @@ __global__ __launch_bounds__(kBWG) void k_b2_step_el(B2Args a) {
     const double r = a.r[i] - md;
     a.r[i] = r;
     if (!a.last)
-      a.dir_out[i] = a.c1 * di + a.c2 * d.dinv[row] * r;
+      a.dir_out[i] = a.c1 * di + a.c2 * kp<UNI>(d.dinv)[row] * r;
     else
       rr = fma(r, r, rr);
   }
@@ -267,8 +293,8 @@ __device__ inline void b2_eval(const double *a, double xi, double et, double h, 
 // Scaled coordinates and barycentric weights of point t of side s of a cell
 // (t runs from the edge's first vertex to its second: from local vertex
 // s+1 to s+2 in the edge's first cell, the reverse in its second).
-__device__ inline void b2_side_point(const double *T, int s, double t, double &xi, double &et,
-                                     double l[3]) {
+template <class TP>
+__device__ inline void b2_side_point(TP T, int s, double t, double &xi, double &et, double l[3]) {
   const int v1 = (s + 1) % 3, v2 = (s + 2) % 3;
   const bool first = T[kNcSg + s] > 0.0;
   const int ia = first ? v1 : v2, ib = first ? v2 : v1;
@@ -280,18 +306,20 @@ __device__ inline void b2_side_point(const double *T, int s, double t, double &x
 }
 
 // raw[12 c + f] = sum_j C[f][j] s_j u[cdof_j]
+template <bool UNI>
 __global__ __launch_bounds__(kBWG) void k_b2_raw(B2NlArgs a) {
   const B2Dev &d = a.d;
   const int Bs = a.Bs;
   const size_t total = (size_t)d.nc * Bs, stride = (size_t)gridDim.x * kBWG;
   for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < total; i += stride) {
-    const int cell = (int)(i / Bs), col = (int)(i % Bs);
-    const double *T = d.ncell + (size_t)kB2NC * cell;
+    const int cell = uni<UNI>((int)(i / Bs)), col = (int)(i % Bs);
+    const auto T = kp<UNI>(d.ncell + (size_t)kB2NC * cell);
+    const auto cdof = kp<UNI>(d.cdof + 12 * (size_t)cell);
     double v[12];
 #pragma unroll
     for (int j = 0; j < 12; j++) {
       const double sg = j < 9 ? T[kNcSg + j / 3] : 1.0;
-      v[j] = sg * a.u[(size_t)d.cdof[12 * cell + j] * Bs + col];
+      v[j] = sg * a.u[(size_t)cdof[j] * Bs + col];
     }
 #pragma unroll
     for (int f = 0; f < 12; f++) {
@@ -305,41 +333,51 @@ __global__ __launch_bounds__(kBWG) void k_b2_raw(B2NlArgs a) {
 
 // Upwind traces at the edges' points: the cell the flow leaves (normal
 // flux out of c0 positive: c0, else c1); u as a 3D vector and eta.
+template <bool UNI>
 __global__ __launch_bounds__(kBWG) void k_b2_edge(B2NlArgs a) {
   const B2Dev &d = a.d;
   const int Bs = a.Bs;
   const size_t total = (size_t)d.ne * Bs, stride = (size_t)gridDim.x * kBWG;
   for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < total; i += stride) {
-    const int e = (int)(i / Bs), col = (int)(i % Bs);
+    const int e = uni<UNI>((int)(i / Bs)), col = (int)(i % Bs);
+    const auto et4 = kp<UNI>(d.etab + 4 * (size_t)e);
     int cc[2], ss[2];
     for (int k = 0; k < 2; k++) {
-      cc[k] = d.etab[4 * e + 2 * k];
-      ss[k] = d.etab[4 * e + 2 * k + 1];
+      cc[k] = et4[2 * k];
+      ss[k] = et4[2 * k + 1];
     }
+    const auto bot = kp<UNI>(d.bot);
     double ar[2][12], hc[2][3];
     for (int k = 0; k < 2; k++) {
 #pragma unroll
       for (int f = 0; f < 12; f++) ar[k][f] = a.raw[((size_t)12 * cc[k] + f) * Bs + col];
 #pragma unroll
       for (int r = 0; r < 3; r++)
-        hc[k][r] = a.eta[((size_t)3 * cc[k] + r) * Bs + col] - d.bot[3 * cc[k] + r];
+        hc[k][r] = a.eta[((size_t)3 * cc[k] + r) * Bs + col] - bot[3 * cc[k] + r];
     }
+    const auto ftab = kp<UNI>(d.ftab);
     for (int p = 0; p < kB2FQ; p++) {
-      const double t = d.ftab[2 * p];
-      double u[2][2], hv[2], flux0 = 0.0;
+      const double t = ftab[2 * p];
+      double u[2][2], hv[2], e3[2][6], flux0 = 0.0;
       for (int k = 0; k < 2; k++) {
-        const double *T = d.ncell + (size_t)kB2NC * cc[k];
+        const auto T = kp<UNI>(d.ncell + (size_t)kB2NC * cc[k]);
         double xi, et, l[3];
         b2_side_point(T, ss[k], t, xi, et, l);
         b2_eval(ar[k], xi, et, T[kNcH], u[k], nullptr);
         hv[k] = l[0] * hc[k][0] + l[1] * hc[k][1] + l[2] * hc[k][2];
         if (k == 0) flux0 = u[0][0] * T[kNcNo + 2 * ss[0]] + u[0][1] * T[kNcNo + 2 * ss[0] + 1];
+#pragma unroll
+        for (int dd = 0; dd < 3; dd++) {
+          e3[k][dd] = T[kNcE1 + dd];
+          e3[k][3 + dd] = T[kNcE2 + dd];
+        }
       }
+      // the upwind side differs from column to column: select, per lane,
+      // between the two cells' values
       const int w = flux0 > 0.0 ? 0 : 1;
-      const double *T = d.ncell + (size_t)kB2NC * cc[w];
       double *o = a.ut + ((size_t)(e * kB2FQ + p) * 4) * Bs + col;
 #pragma unroll
-      for (int dd = 0; dd < 3; dd++) o[(size_t)dd * Bs] = u[w][0] * T[kNcE1 + dd] + u[w][1] * T[kNcE2 + dd];
+      for (int dd = 0; dd < 3; dd++) o[(size_t)dd * Bs] = u[w][0] * e3[w][dd] + u[w][1] * e3[w][3 + dd];
       o[(size_t)3 * Bs] = hv[w];
     }
   }
@@ -347,13 +385,18 @@ __global__ __launch_bounds__(kBWG) void k_b2_edge(B2NlArgs a) {
 
 // Cell integrals: velocity contributions per cell slot (signed), depth rows
 // of N (the block-diagonal M_h solved in closed form).
+template <bool UNI>
 __global__ __launch_bounds__(kBWG) void k_b2_cell(B2NlArgs a) {
   const B2Dev &d = a.d;
   const int Bs = a.Bs;
   const size_t total = (size_t)d.nc * Bs, stride = (size_t)gridDim.x * kBWG;
   for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < total; i += stride) {
-    const int cell = (int)(i / Bs), col = (int)(i % Bs);
-    const double *T = d.ncell + (size_t)kB2NC * cell;
+    const int cell = uni<UNI>((int)(i / Bs)), col = (int)(i % Bs);
+    const auto T = kp<UNI>(d.ncell + (size_t)kB2NC * cell);
+    const auto qtab = kp<UNI>(d.qtab);
+    const auto ftab = kp<UNI>(d.ftab);
+    const auto bot = kp<UNI>(d.bot);
+    const auto cdof = kp<UNI>(d.cdof + 12 * (size_t)cell);
     const double h = T[kNcH], A = T[kNcA];
     double ar[12], hc[3], g[12], rh[3] = {0.0, 0.0, 0.0};
 #pragma unroll
@@ -362,11 +405,11 @@ __global__ __launch_bounds__(kBWG) void k_b2_cell(B2NlArgs a) {
       g[f] = 0.0;
     }
 #pragma unroll
-    for (int r = 0; r < 3; r++) hc[r] = a.eta[((size_t)3 * cell + r) * Bs + col] - d.bot[3 * cell + r];
+    for (int r = 0; r < 3; r++) hc[r] = a.eta[((size_t)3 * cell + r) * Bs + col] - bot[3 * cell + r];
     // volume: u . grad^perp(u^perp . m_a e_c) + (div m_a e_c) |u|^2 / 2
     for (int q = 0; q < kB2VQ; q++) {
-      const double l0 = d.qtab[4 * q], l1 = d.qtab[4 * q + 1], l2 = d.qtab[4 * q + 2];
-      const double w = d.qtab[4 * q + 3] * A;
+      const double l0 = qtab[4 * q], l1 = qtab[4 * q + 1], l2 = qtab[4 * q + 2];
+      const double w = qtab[4 * q + 3] * A;
       const double xi = l0 * T[kNcX] + l1 * T[kNcX + 2] + l2 * T[kNcX + 4];
       const double et = l0 * T[kNcX + 1] + l1 * T[kNcX + 3] + l2 * T[kNcX + 5];
       double u[2], J[2][2];
@@ -395,10 +438,10 @@ __global__ __launch_bounds__(kBWG) void k_b2_cell(B2NlArgs a) {
     // sides: - |s| w_p ((k x n_out) . u~)(u^perp . m_a e_c) and
     //        - |s| w_p l_r (u . n_out) eta~
     for (int s = 0; s < 3; s++) {
-      const int e = d.cdof[12 * cell + 3 * s] / 3;
+      const int e = cdof[3 * s] / 3;
       const double len = T[kNcLen + s];
       for (int p = 0; p < kB2FQ; p++) {
-        const double t = d.ftab[2 * p], wl = len * d.ftab[2 * p + 1];
+        const double t = ftab[2 * p], wl = len * ftab[2 * p + 1];
         double xi, et, l[3], u[2];
         b2_side_point(T, s, t, xi, et, l);
         b2_eval(ar, xi, et, h, u, nullptr);
@@ -513,9 +556,15 @@ void launch_b2_wsum(const B2ColArgs &a, hipStream_t s) {
 }
 
 void launch_b2_nl(const B2NlArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_b2_raw, dim3(b2_grid(a.d.nc, a.Bs)), dim3(kBWG), 0, s, a);
-  hipLaunchKernelGGL(k_b2_edge, dim3(b2_grid(a.d.ne, a.Bs)), dim3(kBWG), 0, s, a);
-  hipLaunchKernelGGL(k_b2_cell, dim3(b2_grid(a.d.nc, a.Bs)), dim3(kBWG), 0, s, a);
+  if (a.Bs == 64) {
+    hipLaunchKernelGGL(k_b2_raw<true>, dim3(b2_grid(a.d.nc, a.Bs)), dim3(kBWG), 0, s, a);
+    hipLaunchKernelGGL(k_b2_edge<true>, dim3(b2_grid(a.d.ne, a.Bs)), dim3(kBWG), 0, s, a);
+    hipLaunchKernelGGL(k_b2_cell<true>, dim3(b2_grid(a.d.nc, a.Bs)), dim3(kBWG), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(k_b2_raw<false>, dim3(b2_grid(a.d.nc, a.Bs)), dim3(kBWG), 0, s, a);
+    hipLaunchKernelGGL(k_b2_edge<false>, dim3(b2_grid(a.d.ne, a.Bs)), dim3(kBWG), 0, s, a);
+    hipLaunchKernelGGL(k_b2_cell<false>, dim3(b2_grid(a.d.nc, a.Bs)), dim3(kBWG), 0, s, a);
+  }
   hipLaunchKernelGGL(k_b2_gather, dim3(b2_grid(a.d.nu, a.Bs)), dim3(kBWG), 0, s, a);
 }
 
@@ -533,8 +582,13 @@ void launch_b2_step(const B2Args &a, hipStream_t s) {
   hipLaunchKernelGGL(k_b2_step, dim3(b2_grid(a.d.nu, a.Bs)), dim3(kBWG), 0, s, a);
 }
 void launch_b2_step_el(const B2Args &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_b2_mel, dim3(b2_grid(a.d.nc, a.Bs)), dim3(kBWG), 0, s, a);
-  hipLaunchKernelGGL(k_b2_step_el, dim3(b2_grid(a.d.nu, a.Bs)), dim3(kBWG), 0, s, a);
+  if (a.Bs == 64) {
+    hipLaunchKernelGGL(k_b2_mel<true>, dim3(b2_grid(a.d.nc, a.Bs)), dim3(kBWG), 0, s, a);
+    hipLaunchKernelGGL(k_b2_step_el<true>, dim3(b2_grid(a.d.nu, a.Bs)), dim3(kBWG), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(k_b2_mel<false>, dim3(b2_grid(a.d.nc, a.Bs)), dim3(kBWG), 0, s, a);
+    hipLaunchKernelGGL(k_b2_step_el<false>, dim3(b2_grid(a.d.nu, a.Bs)), dim3(kBWG), 0, s, a);
+  }
 }
 // After a last step (row or element form, both on b2_grid(nu, Bs) workgroups)
 // left the partials of |r_K|^2: the check against |r_0|^2.
