@@ -839,11 +839,19 @@ void up(hipStream_t s, const T *dst, const std::vector<T> &v) {
     PA_HIP(hipMemcpyAsync((void *)dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
+// The pair's calls run FP64 Jacobi Chebyshev mass solves and the Chebyshev
+// exponential only; settings asking for anything else are refused rather
+// than ignored.
 pa_solve_cfg cfg_of(const pa_solve_cfg *cfg) {
   pa_solve_cfg c;
   pa_solve_cfg_default(&c);
   if (cfg) c = *cfg;
-  bneed(c.cg_rtol > 0 && c.cheb_tol > 0 && c.maxit > 0, "bad solve configuration");
+  bneed(c.cg_rtol > 0 && c.cheb_tol > 0 && c.maxit > 0 && c.weight_cut >= 0, "bad solve configuration");
+  bneed(c.backward == PA_BACKWARD_CLENSHAW || c.backward == PA_BACKWARD_PER_TERM, "unknown backward form");
+  if (c.exponential != PA_EXP_CHEBYSHEV) throw Error(PA_ENOTSUP, "BDM2 calls take the Chebyshev exponential only");
+  if (c.precision != PA_FP64) throw Error(PA_ENOTSUP, "BDM2 mass solves run in FP64 only");
+  if (c.solver != PA_SOLVER_CHEBYSHEV || c.precond != PA_PRECOND_JACOBI)
+    throw Error(PA_ENOTSUP, "BDM2 mass solves are Jacobi Chebyshev semi-iterations only");
   return c;
 }
 
@@ -852,6 +860,7 @@ void b2_run(pa_ctx *ctx, const pa_bdm2 *b, int call, int B, const double *t, con
             const double *Uin, double *Uout, void *ws, size_t ws_bytes, const pa_solve_cfg &cfg,
             pa_stats *stats) {
   bneed(ctx && b && Uin && Uout && ws && B >= 1, "bad arguments");
+  bneed(((uintptr_t)ws & 255) == 0, "workspace must be 256-byte aligned");
   bneed(Uin != Uout, "outputs must not alias inputs");
   bneed(b->dev != nullptr, "BDM2 operators not bound (pa_bdm2_bind)");
   B2Plan p;
@@ -1004,6 +1013,7 @@ size_t b2_step_ws(const pa_bdm2 *b, const pa_avg *avg, double dt, int B, const p
 void b2_step(pa_ctx *ctx, const pa_bdm2 *b, const pa_avg *avg, double dt, int B, double *U, void *ws,
              size_t ws_bytes, const pa_solve_cfg &cfg, pa_stats *stats) {
   bneed(ctx && b && avg && U && ws, "bad arguments");
+  bneed(((uintptr_t)ws & 255) == 0, "workspace must be 256-byte aligned");
   double *k[7];
   const size_t need = b2_step_ws(b, avg, dt, B, cfg, (char *)ws, ws_bytes, k);
   bneed(need <= ws_bytes, "workspace too small");

@@ -134,3 +134,24 @@ def test_bdm2_refuses_topography_and_bad_sizes(oracle_mesh):
     st = b.workspace_size(pa.PA_BDM2_STEP, 2, dt, avg)
     assert st >= 7 * 8 * b.n * 2 + b.workspace_size(pa.PA_BDM2_PHASE_AVG, 2, avg=avg)
 
+
+
+def test_bdm2_refuses_settings_it_does_not_implement(oracle_mesh):
+    """The pair's calls run FP64 Jacobi Chebyshev solves and the Chebyshev
+    exponential: other settings are refused (PA_ENOTSUP), not ignored."""
+    import ctypes
+    from paper_2103_07706_amd import pa
+    m, b = _lib_bdm2(oracle_mesh(0))
+    b.set_lambda(1e-2)
+    avg = pa.Avg(4, 1800.0)
+    sz = ctypes.c_size_t()
+    for kw in (dict(exponential=pa.PA_EXP_REXI), dict(precision=pa.PA_FP32_REFINED),
+               dict(solver=pa.PA_SOLVER_CG), dict(precond=pa.PA_PRECOND_LEARNED)):
+        cfg = pa.solve_cfg(**kw)
+        for call in (pa.PA_BDM2_APPLY_L, pa.PA_BDM2_PHASE_AVG):
+            code = pa.lib().pa_bdm2_workspace_size(b._h, call, 1, None, avg._h, ctypes.byref(cfg),
+                                                   ctypes.byref(sz))
+            assert code == pa.PA_ENOTSUP, (kw, call, code)
+    cfg = pa.solve_cfg(backward=7)
+    assert pa.lib().pa_bdm2_workspace_size(b._h, pa.PA_BDM2_APPLY_L, 1, None, None,
+                                           ctypes.byref(cfg), ctypes.byref(sz)) == pa.PA_EINVAL
