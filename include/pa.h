@@ -660,7 +660,11 @@ int pa_bdm2_nonlinear(pa_ctx *ctx, const pa_bdm2 *b, int B, const double *U_dev,
  * the nodes of avg (terms with w_m < weight_cut * max w dropped), every
  * exponential as in pa_bdm2_expL_apply, N as in pa_bdm2_nonlinear.  The
  * (member, node) pairs are processed 64 columns at a time, member-major, in
- * a fixed order (results are reproducible bit for bit).  stats: solves,
+ * a fixed order (results are reproducible bit for bit).  backward
+ * PA_BACKWARD_CLENSHAW (the default): members in groups of up to 64 share
+ * one forward basis and one Clenshaw sum (a group narrows so that its
+ * 2 (kmax + 1) basis and sum vectors a member stay within 32 GiB); per term:
+ * every node's exponentials on its own column.  stats: solves,
  * cg_iters, kmax, terms (columns evaluated), resid_max, device_ms. */
 int pa_bdm2_phase_avg_rhs(pa_ctx *ctx, const pa_bdm2 *b, const pa_avg *avg, int members,
                           const double *U_dev, double *Nbar_dev, void *ws_dev,

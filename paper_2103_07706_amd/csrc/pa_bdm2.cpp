@@ -557,18 +557,22 @@ size_t b2_plan(const pa_bdm2 *b, int call, int B, const double *t, const pa_avg 
       if (avg->w[m] >= cfg.weight_cut * wmax && avg->w[m] != 0.0) keep.push_back((int)m);
     bneed(!keep.empty(), "no averaging term left");
     p.Mk = (int)keep.size();
-    // up to 64 members share a basis; their node columns go through N 64
-    // at a time
-    p.G = std::min(B, 64);
+    std::vector<double> c;
+    p.kmax = 0;
+    for (int m : keep) p.kmax = std::max(p.kmax, exp_weights(b->lambda_bar, avg->s[m], cfg.cheb_tol, c));
+    // up to 64 members share a basis (their node columns go through N 64 at
+    // a time), fewer where the basis and the sums, 2 (kmax + 1) vectors a
+    // member, would pass kB2BasisBytes
+    const double per_col = 2.0 * (p.kmax + 1) * ((double)b->nu + b->nh) * sizeof(double);
+    int gcap = 64;
+    while (gcap > 1 && gcap * per_col > kB2BasisBytes) gcap /= 2;
+    p.G = std::min(B, gcap);
     p.Gs = pad_cols(p.G);
     p.ngroup = (B + p.G - 1) / p.G;
     const int cols = p.G * p.Mk;
     p.Vs = pad_cols(std::min(cols, 64));
     p.nvch = (cols + p.Vs - 1) / p.Vs;
     p.Bs = p.Vs;  // the wide blocks (N and its solve)
-    std::vector<double> c;
-    p.kmax = 0;
-    for (int m : keep) p.kmax = std::max(p.kmax, exp_weights(b->lambda_bar, avg->s[m], cfg.cheb_tol, c));
     p.cfh.assign((size_t)(p.kmax + 1) * p.Mk, 0.0);
     p.cbh.assign((size_t)(p.kmax + 1) * p.Mk, 0.0);
     for (int i = 0; i < p.Mk; i++) {

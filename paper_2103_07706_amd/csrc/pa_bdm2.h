@@ -55,6 +55,9 @@ struct B2Dev {
 // Blocks at least this wide take the element form of the mass-solve step
 // (a cell pass and a row pass) instead of the row kernel.
 constexpr int kB2ElMin = 8;
+// Workspace the shared-basis average may spend on a group's bases and sums
+// (the group narrows below 64 members beyond it).
+constexpr double kB2BasisBytes = 32.0 * (1ull << 30);
 
 // Per-launch arguments; blocks are row-major [row][Bs].
 struct B2Args {

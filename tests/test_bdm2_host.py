@@ -155,3 +155,20 @@ def test_bdm2_refuses_settings_it_does_not_implement(oracle_mesh):
     cfg = pa.solve_cfg(backward=7)
     assert pa.lib().pa_bdm2_workspace_size(b._h, pa.PA_BDM2_APPLY_L, 1, None, None,
                                            ctypes.byref(cfg), ctypes.byref(sz)) == pa.PA_EINVAL
+
+
+def test_bdm2_average_groups_narrow_within_the_basis_budget(oracle_mesh):
+    """A group's bases and Clenshaw sums take 2 (kmax + 1) state vectors a
+    member; beyond 32 GiB the group narrows (by halving from 64), so the
+    workspace stops growing with the members sooner.  Forced here with a
+    degree in the tens of thousands on a small mesh (sizes only, nothing
+    allocated)."""
+    from paper_2103_07706_amd import pa
+    m, b = _lib_bdm2(oracle_mesh(2))
+    avg = pa.Avg(8, 3600.0)
+    b.set_lambda(15.0)   # theta = 27000 at the window's edge
+    ws = {mem: b.workspace_size(pa.PA_BDM2_PHASE_AVG, mem, avg=avg) for mem in (8, 16, 64)}
+    assert ws[8] < ws[16] == ws[64] < 40 * 2 ** 30
+    b.set_lambda(1e-2)
+    ws = {mem: b.workspace_size(pa.PA_BDM2_PHASE_AVG, mem, avg=avg) for mem in (16, 64)}
+    assert ws[16] < ws[64]
