@@ -62,13 +62,14 @@ def _rows(d):
 
 def per_dispatch(d, counter, name_filter=None):
     """Counter value (KiB, as rocprofv3 reports these derived counters) per
-    dispatch, summed over the counter's instances."""
+    dispatch, summed over the counter's instances; name_filter keeps the
+    dispatches whose bare kernel name (kernel_base) is exactly it."""
     acc = {}
     for r in _rows(d):
         if r.get("Counter_Name") != counter:
             continue
         kn = r.get("Kernel_Name", "")
-        if name_filter and name_filter not in kn:
+        if name_filter and kernel_base(kn) != name_filter:
             continue
         key = r.get("Dispatch_Id") or r.get("Correlation_Id")
         acc[key] = acc.get(key, 0.0) + float(r["Counter_Value"])
