@@ -384,12 +384,14 @@ class BDM2P1DG:
 
 
     # ------------------------------------------------------ averaged rhs
-    def phase_avg_rhs(self, lambda_bar, s, w, U, inner="N", tol=1e-13):
+    def phase_avg_rhs(self, lambda_bar, s, w, U, inner="N", tol=1e-13, b=None):
         """Nbar(U) = sum_m w_m exp(-s_m L) N(exp(s_m L) U), eq. vt_discretised
         of Sec. 2.2, every exponential by expL (Sec. 2.4) and N by nonlinear
-        (Sec. 2.5); inner = "L" or "I" substitutes L or the identity for N
-        (the averages then reduce to L U and U)."""
-        f = {"N": self.nonlinear, "L": self.apply_L, "I": lambda X: np.array(X, copy=True)}[inner]
+        (Sec. 2.5, over the bottom b, P1DG coefficients or None); inner =
+        "L" or "I" substitutes L or the identity for N (the averages then
+        reduce to L U and U)."""
+        f = {"N": lambda X: self.nonlinear(X, b=b), "L": self.apply_L,
+             "I": lambda X: np.array(X, copy=True)}[inner]
         out = np.zeros(self.n)
         for sm, wm in zip(s, w):
             V, _ = self.expL(lambda_bar, sm, U, tol)
@@ -398,15 +400,16 @@ class BDM2P1DG:
         return out
 
     # ------------------------------------------------------------ RK4 step
-    def step(self, lambda_bar, s, w, dt, U, inner="N", tol=1e-13):
+    def step(self, lambda_bar, s, w, dt, U, inner="N", tol=1e-13, b=None):
         """One step of the averaged system (Sec. 2.3): the Lawson form of
         the classical fourth-order Runge-Kutta method on the averaged
         equation, with the stages in the paper's order (stages 2 and 4 take
         exp(L dt/2) inside N, after exp(L s)), every exponential by expL and
-        the averages by phase_avg_rhs (inner as there)."""
+        the averages by phase_avg_rhs (inner and the bottom b as there)."""
         U = np.asarray(U, dtype=float)
         E = lambda t, X: self.expL(lambda_bar, t, X, tol)[0]  # noqa: E731
-        f = {"N": self.nonlinear, "L": self.apply_L, "I": lambda X: np.array(X, copy=True)}[inner]
+        f = {"N": lambda X: self.nonlinear(X, b=b), "L": self.apply_L,
+             "I": lambda X: np.array(X, copy=True)}[inner]
         h = 0.5 * dt
 
         def shifted(X):  # sum_m w_m exp(-s_m L) N(exp(L dt/2) exp(s_m L) X)
@@ -414,12 +417,12 @@ class BDM2P1DG:
             for sm, wm in zip(s, w):
                 out += wm * E(-sm, f(E(h, E(sm, X))))
             return out
-        k1 = self.phase_avg_rhs(lambda_bar, s, w, U, inner, tol)
+        k1 = self.phase_avg_rhs(lambda_bar, s, w, U, inner, tol, b)
         U1 = U + h * k1
         Eh = E(h, U)
         k2 = shifted(U1)
         U2 = Eh + h * k2
-        k3 = self.phase_avg_rhs(lambda_bar, s, w, U2, inner, tol)
+        k3 = self.phase_avg_rhs(lambda_bar, s, w, U2, inner, tol, b)
         U3 = Eh + dt * k3
         k4 = shifted(U3)
         return (E(dt, U) + dt / 6.0 * (E(dt, k1) + 2.0 * E(h, k2) + 2.0 * E(h, k3) + k4))

@@ -112,24 +112,13 @@ def p1dg_bumps_state(verts, cell_verts, ne: int, nbumps: int, seed: int,
     return np.concatenate([np.zeros(3 * ne + 3 * len(cv)), ev[cv].ravel()])
 
 
-def bdm2_bumps_state(verts, cell_verts, edge_cells, edge_verts, nbumps: int, seed: int,
-                     phys: Physics = Physics(), width: float = 1.0e6):
-    """The bumps of gaussian_bumps_state on the BDM2 x P1DG unknowns: the
-    same stream function psi at the vertices, its continuous piecewise-
-    linear interpolant psi_h, and u = k x grad psi_h (constant in each flat
+def _bdm2_velocity_from_stream(verts, tri, ev, psi):
+    """BDM2 unknowns of u = k x grad psi_h, psi_h the continuous piecewise-
+    linear interpolant of the vertex values psi (constant in each flat
     cell, divergence free, held exactly by BDM2): normal flux density
     (psi(a) - psi(b)) / |b - a| at all three points of each edge, moments
     u . e1, u . e2 and 0 in each cell (e1 from the cell's vertex 0 to 1,
-    e2 = k x e1); depth: the bump sum at each cell's vertices."""
-    verts = np.asarray(verts, dtype=np.float64)
-    tri = np.asarray(cell_verts)
-    ev = np.asarray(edge_verts)
-    amp, cen, zc = bump_params(seed, nbumps)
-    fmin = math.sin(math.radians(10.0))
-    fb = np.array([2.0 * phys.omega * (1.0 if z >= 0 else -1.0) * max(abs(z), fmin)
-                   for z in zc])
-    psi = _bump_sum(verts, amp, cen, phys.g / fb, phys.radius, width)
-    eta = _bump_sum(verts, amp, cen, np.ones(nbumps), phys.radius, width)
+    e2 = k x e1)."""
     flux = (psi[ev[:, 0]] - psi[ev[:, 1]]) / np.linalg.norm(verts[ev[:, 1]] - verts[ev[:, 0]], axis=1)
     P = verts[tri]
     k = np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0])
@@ -142,7 +131,43 @@ def bdm2_bumps_state(verts, cell_verts, edge_cells, edge_verts, nbumps: int, see
     e2 = np.cross(k, e1)
     mom = np.stack([np.einsum("cd,cd->c", u, e1), np.einsum("cd,cd->c", u, e2),
                     np.zeros(len(tri))], 1)
-    return np.concatenate([np.repeat(flux, 3), mom.ravel(), eta[tri].ravel()])
+    return np.concatenate([np.repeat(flux, 3), mom.ravel()])
+
+
+def bdm2_bumps_state(verts, cell_verts, edge_cells, edge_verts, nbumps: int, seed: int,
+                     phys: Physics = Physics(), width: float = 1.0e6):
+    """The bumps of gaussian_bumps_state on the BDM2 x P1DG unknowns: the
+    same stream function psi at the vertices, the velocity k x grad psi_h
+    (_bdm2_velocity_from_stream); depth: the bump sum at each cell's
+    vertices."""
+    verts = np.asarray(verts, dtype=np.float64)
+    tri = np.asarray(cell_verts)
+    amp, cen, zc = bump_params(seed, nbumps)
+    fmin = math.sin(math.radians(10.0))
+    fb = np.array([2.0 * phys.omega * (1.0 if z >= 0 else -1.0) * max(abs(z), fmin)
+                   for z in zc])
+    psi = _bump_sum(verts, amp, cen, phys.g / fb, phys.radius, width)
+    eta = _bump_sum(verts, amp, cen, np.ones(nbumps), phys.radius, width)
+    return np.concatenate([_bdm2_velocity_from_stream(verts, tri, np.asarray(edge_verts), psi),
+                           eta[tri].ravel()])
+
+
+def williamson5_bdm2_state(verts, cell_verts, edge_cells, edge_verts, phys: Physics = None,
+                           u0: float = 20.0):
+    """The paper's test case (Sec. 3) on the BDM2 x P1DG unknowns: the zonal
+    flow from its stream function psi = -u0 z (z radially projected) as
+    k x grad psi_h, and the free surface of williamson5_state at each
+    cell's vertices, -(R Omega u0 + u0^2/2) z^2 / (g R^2) (the bottom left
+    out: williamson5_bottom_p1dg)."""
+    phys = TC5_PHYSICS if phys is None else phys
+    verts = np.asarray(verts, dtype=np.float64)
+    tri = np.asarray(cell_verts)
+    R = phys.radius
+    z = R * verts[:, 2] / np.linalg.norm(verts, axis=1)
+    psi = -u0 * z
+    eta = -(R * phys.omega * u0 + 0.5 * u0 * u0) * z * z / (phys.g * R * R)
+    return np.concatenate([_bdm2_velocity_from_stream(verts, tri, np.asarray(edge_verts), psi),
+                           eta[tri].ravel()])
 
 
 def random_state(nu: int, nh: int, seed: int, u_scale: float = 10.0,

@@ -406,3 +406,25 @@ def test_bdm2_step_fourth_order_with_N_as_L(bdm):
     U1 = b.step(lam, s, w, 1800.0, Us)
     a3 = np.repeat(b.area / 3.0, 3)
     assert abs(a3 @ (U1[b.nu:] - Us[b.nu:])) <= 1e-12 * (a3 @ np.abs(Us[b.nu:]))
+
+
+def test_bdm2_nonlinear_sees_only_eta_minus_b(bdm):
+    """The bottom enters N only through the depth flux of eta - b (Sec. 2.1):
+    raising eta by the mountain (a P1DG field) with the mountain as b gives
+    N of the unraised state over a flat bottom, both parts, up to rounding;
+    and the average passes b on to N (one node at s = 0: the average is N
+    itself)."""
+    from paper_2103_07706_amd import inputs
+    b = bdm(2)
+    m = b.mesh
+    bot = inputs.williamson5_bottom_p1dg(m.verts, m.cell_verts)
+    assert bot.max() > 1000.0
+    U = inputs.bdm2_bumps_state(m.verts, m.cell_verts, m.edge_cells, m.edge_verts, 4, 2)
+    V = U.copy()
+    V[b.nu:] += bot
+    N0 = b.nonlinear(U)
+    Nb = b.nonlinear(V, b=bot)
+    assert np.abs(Nb - N0).max() <= 1e-12 * np.abs(N0).max()
+    assert np.abs(b.nonlinear(V) - N0).max() > 1e-3 * np.abs(N0).max()
+    avg = b.phase_avg_rhs(1.05 * b.rho(), [0.0], [1.0], V, b=bot)
+    assert np.abs(avg - Nb).max() <= 1e-14 * np.abs(Nb).max()
