@@ -534,3 +534,46 @@ def test_gpu_bdm2_williamson5_window_sweep():
     assert errs[-1] > 1.5 * errs[k]
     assert rows[k][0] == 0.35, rows
     assert rows[int(np.argmin([r[3] for r in rows]))][0] in (0.35, 0.5), rows
+
+
+def test_gpu_bdm2_williamson5_smallest_stable_window():
+    """The paper's stability result (Sec. 3): at dt = 450 / 900 / 1350 s the
+    averaged model runs the test case for a day only with windows of at
+    least 0.1 / 0.25 / 0.375 h.  On its spaces here (level 5, flat
+    triangles, M >= 2 T lambda_bar / pi) the smallest stable windows, on
+    the grid 0.05, 0.075, 0.1, 0.15, 0.2, 0.25, 0.3, 0.375 h, are at most
+    0.05, 0.2 and 0.25 h: they grow with dt as in the paper and sit at or
+    below its values (this operator's fastest frequency is lower than the
+    paper's; compare Table 1).  Checked at the boundaries: 0.25 h stable and
+    0.2 h not at 1350 s, 0.2 h stable and 0.15 h not at 900 s, 0.1 h stable
+    at 450 s."""
+    import math
+
+    import torch
+    from gpu_common import _ctx
+    from paper_2103_07706_amd import inputs, pa
+    ph = inputs.TC5_PHYSICS
+    lm = pa.Mesh(5)
+    lb = pa.BDM2(lm, g=ph.g, H=ph.H, omega=ph.omega)
+    lb.set_bottom(inputs.williamson5_bottom_p1dg(lm.verts, lm.cell_verts)).bind(_ctx())
+    lam = lb.estimate_lambda(iters=200, safety=1.05)
+    U0 = inputs.williamson5_bdm2_state(lm.verts, lm.cell_verts, lm.edge_cells, lm.edge_verts)
+    cfg = _cfg(cheb_tol=1e-10, cg_rtol=1e-12)
+
+    def stable(T_h, dt):
+        T = 3600.0 * T_h
+        avg = pa.Avg(min(64, max(4, 4 * math.ceil(2.0 * T * lam / math.pi / 4.0))), T)
+        U = _dev(U0[None])
+        try:
+            for _ in range(int(round(86400.0 / dt))):
+                lb.step(avg, dt, U, cfg)
+        except pa.PAError:   # a solve met non-finite values
+            return False
+        u = U.cpu().numpy()[0]
+        ok = bool(np.all(np.isfinite(u)) and np.abs(u[lb.nu:]).max() < 1e4)
+        print(f"dt = {dt:.0f} s, T = {T_h} h: {'stable' if ok else 'blow-up'}", flush=True)
+        return ok
+
+    assert stable(0.25, 1350.0) and not stable(0.2, 1350.0)
+    assert stable(0.2, 900.0) and not stable(0.15, 900.0)
+    assert stable(0.1, 450.0)
