@@ -506,6 +506,7 @@ T *take(char *base, size_t &off, size_t cap, size_t n) {
 // sign(t)^k, truncated at cheb_tol.
 int exp_weights(double lb, double t, double tol, std::vector<double> &c) {
   const double theta = lb * std::fabs(t);
+  if (!std::isfinite(theta) || theta > 1e7) throw Error(PA_EINVAL, "exponential time must be finite (lambda_bar |t| <= 1e7)");
   c = bessel_weights(theta, 2 * (int)std::ceil(theta) + 64);
   const int K = t == 0.0 ? 0 : truncate_degree(c, tol);
   c.resize(K + 1);
@@ -999,7 +1000,7 @@ void b2_run(pa_ctx *ctx, const pa_bdm2 *b, int call, int B, const double *t, con
 size_t b2_step_ws(const pa_bdm2 *b, const pa_avg *avg, double dt, int B, const pa_solve_cfg &cfg,
                   char *ws, size_t cap, double **bufs) {
   bneed(B >= 1 && B <= 64, "at most 64 members per BDM2 step");
-  bneed(dt > 0, "dt must be positive");
+  bneed(dt > 0 && std::isfinite(dt), "dt must be positive and finite");
   const size_t nB = ((size_t)b->nu + b->nh) * B;
   size_t off = 0;
   for (int i = 0; i < 7; i++) {

@@ -172,3 +172,20 @@ def test_bdm2_average_groups_narrow_within_the_basis_budget(oracle_mesh):
     b.set_lambda(1e-2)
     ws = {mem: b.workspace_size(pa.PA_BDM2_PHASE_AVG, mem, avg=avg) for mem in (16, 64)}
     assert ws[16] < ws[64]
+
+
+def test_bdm2_refuses_non_finite_times(oracle_mesh):
+    import ctypes
+    from paper_2103_07706_amd import pa
+    m, b = _lib_bdm2(oracle_mesh(0))
+    b.set_lambda(1e-2)
+    sz = ctypes.c_size_t()
+    cfg = pa.solve_cfg()
+    for t in (np.nan, np.inf, 1e12):
+        tt = np.array([100.0, t])
+        assert pa.lib().pa_bdm2_workspace_size(b._h, pa.PA_BDM2_EXPL, 2, pa._dp(tt), None,
+                                               ctypes.byref(cfg), ctypes.byref(sz)) == pa.PA_EINVAL
+    avg = pa.Avg(4, 1800.0)
+    dt = np.array([np.nan])
+    assert pa.lib().pa_bdm2_workspace_size(b._h, pa.PA_BDM2_STEP, 1, pa._dp(dt), avg._h,
+                                           ctypes.byref(cfg), ctypes.byref(sz)) == pa.PA_EINVAL
