@@ -176,6 +176,33 @@ __global__ __launch_bounds__(kBWG) void k_b2_step_el(B2Args a) {
   if (a.last) b2_partial(rr, Bs, a.part);
 }
 
+// Element form, three-term row pass on the increment y of the solve (x =
+// x_0 + y, b held in r): y_{k+1} = y_k + c1 (y_k - y_{k-1}) + c2 D^-1 (b -
+// M y_k), written over y_{k-1} (dir_out); with a.last instead the finish:
+// x += y_K and the partials of |b - M y_K|^2.
+template <bool UNI>
+__global__ __launch_bounds__(kBWG) void k_b2_step3_el(B2Args a) {
+  const B2Dev &d = a.d;
+  const int Bs = a.Bs;
+  const size_t nvel = (size_t)d.nu * Bs, stride = (size_t)gridDim.x * kBWG;
+  double rr = 0.0;
+  for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < nvel; i += stride) {
+    const int row = uni<UNI>((int)(i / Bs)), c = (int)(i % Bs);
+    const auto rl = kp<UNI>(d.rloc + 2 * (size_t)row);
+    const int p0 = rl[0], p1 = rl[1];
+    double my = a.loc[(size_t)p0 * Bs + c];
+    if (p1 >= 0) my += a.loc[(size_t)p1 * Bs + c];
+    const double yk = a.dir_in[i], res = a.r[i] - my;
+    if (!a.last) {
+      a.dir_out[i] = yk + a.c1 * (yk - a.dir_out[i]) + a.c2 * kp<UNI>(d.dinv)[row] * res;
+    } else {
+      a.x[i] += yk;
+      rr = fma(res, res, rr);
+    }
+  }
+  if (a.last) b2_partial(rr, Bs, a.part);
+}
+
 __global__ __launch_bounds__(kBWG) void k_b2_norm(B2Args a) {
   const int Bs = a.Bs;
   const size_t nvel = (size_t)a.d.nu * Bs, stride = (size_t)gridDim.x * kBWG;
@@ -592,6 +619,15 @@ void launch_b2_step_el(const B2Args &a, hipStream_t s) {
 }
 // After a last step (row or element form, both on b2_grid(nu, Bs) workgroups)
 // left the partials of |r_K|^2: the check against |r_0|^2.
+void launch_b2_step3_el(const B2Args &a, hipStream_t s) {
+  if (a.Bs == 64) {
+    hipLaunchKernelGGL(k_b2_mel<true>, dim3(b2_grid(a.d.nc, a.Bs)), dim3(kBWG), 0, s, a);
+    hipLaunchKernelGGL(k_b2_step3_el<true>, dim3(b2_grid(a.d.nu, a.Bs)), dim3(kBWG), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(k_b2_mel<false>, dim3(b2_grid(a.d.nc, a.Bs)), dim3(kBWG), 0, s, a);
+    hipLaunchKernelGGL(k_b2_step3_el<false>, dim3(b2_grid(a.d.nu, a.Bs)), dim3(kBWG), 0, s, a);
+  }
+}
 void launch_b2_check(const B2Args &a, hipStream_t s) {
   hipLaunchKernelGGL(k_b2_fin, dim3(1), dim3(kFinT), 0, s, a, b2_grid(a.d.nu, a.Bs), 1);
 }
