@@ -347,12 +347,12 @@ int pa_diagnostics(pa_ctx *ctx, const pa_ops *ops, int B, const double *U_dev,
  *   PA_KERNEL_CHEB_FUSED   fused single-column steps (k_cheb_fused)
  *   PA_KERNEL_CHEB3_ITER   three-term block step (k_cheb3_iter)
  *   PA_KERNEL_CHEB32_ITER  FP32 three-term step (k_cheb32_iter[4])
- *   PA_KERNEL_B2_STEP      BDM2 mass-solve step (k_b2_step, row form: per row
- *                          the ELL row's 21 values, a third of its block's 7
- *                          column-block ids and D^-1, 185.3 bytes; element
- *                          form on 8 or more columns, k_b2_mel + k_b2_step_el:
- *                          per cell its 12 x 12 block, per row D^-1; per row
- *                          and column 48 bytes in both)
+ *   PA_KERNEL_B2_STEP      BDM2 mass-solve step, three-term form (k_b2_step3,
+ *                          row form: per row the ELL row's 21 values, a third
+ *                          of its block's 7 column-block ids and D^-1, 185.3
+ *                          bytes; element form on 8 or more columns, k_b2_mel
+ *                          + k_b2_step3_el: per cell its 12 x 12 block, per
+ *                          row D^-1; per row and column 32 bytes in both)
  * pa_ctx_profile starts a new tally (PA_KERNEL_NONE switches it off and
  * graph capture is not used while it is on); pa_ctx_profile_read returns the
  * tally so far.  The calls made while the hook is on fill it; reading needs

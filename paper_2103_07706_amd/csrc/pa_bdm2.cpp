@@ -684,45 +684,34 @@ void b2_solve(const B2Plan &p, B2Args &a, hipStream_t s, pa_stats &st) {
   if (prof) {
     p.spans.emplace_back(prof_event(p.ctx), prof_event(p.ctx));
     PA_HIP(hipEventRecord(p.spans.back().first, s));
-    // per row and column: x and r in and out, d in, d' out (not on the
-    // last step); per row the ELL row (21 values, a third of seven block
-    // ids) and D^-1, or in the element form per cell its 12 x 12 block and
-    // per row D^-1
+    // per row and column four vectors (below); per row the ELL row (21
+    // values, a third of seven block ids) and D^-1, or in the element form
+    // per cell its 12 x 12 block and per row D^-1
     const double rows = a.d.nu, cols = a.Bs;
     const double mat = el ? 1152.0 * a.d.nc + 8.0 * rows : (168.0 + 28.0 / 3.0 + 8.0) * rows;
     p.prof_launches += p.steps;
-    if (el)  // three-term: y_k, y_{k-1}, b in, y_{k+1} out; the finish x, y_K, b in, x out
-      p.prof_bytes += p.steps * (mat + 32.0 * rows * cols);
-    else
-      p.prof_bytes += p.steps * (mat + 48.0 * rows * cols) - 8.0 * rows * cols;
+    // three-term: y_k, y_{k-1}, b in, y_{k+1} out; the finish x, y_K, b in, x out
+    p.prof_bytes += p.steps * (mat + 32.0 * rows * cols);
     p.prof_units += (double)p.steps * cols;
   }
-  if (el) {
-    // three-term form on the increment: y_1 = d_0 (set up in dir[0]), y_0 =
-    // 0 in dir[1]; steps k = 1 .. K-1 write y_{k+1} over y_{k-1}; the
-    // finish takes M y_K for the true residual (as many launches as the
-    // two-term form, four vectors a step instead of six)
-    AxpyArgs z{(size_t)a.d.nu * a.Bs, 0.0, 0.0, 0.0, nullptr, nullptr, nullptr, p.dir[1]};
-    launch_axpy(z, s);
-    for (int k = 1; k <= p.steps; k++) {
-      a.dir_in = p.dir[(k + 1) & 1];   // y_k
-      a.dir_out = p.dir[k & 1];        // y_{k-1} -> y_{k+1}
-      a.last = k == p.steps;
-      if (!a.last) {
-        a.c1 = p.c1[k - 1];
-        a.c2 = p.c2[k - 1];
-      }
+  // three-term form on the increment: y_1 = d_0 (set up in dir[0]), y_0 = 0
+  // in dir[1]; steps k = 1 .. K-1 write y_{k+1} over y_{k-1}; the finish
+  // takes M y_K for the true residual (as many launches as the two-term
+  // form, four vectors a step instead of six)
+  AxpyArgs z{(size_t)a.d.nu * a.Bs, 0.0, 0.0, 0.0, nullptr, nullptr, nullptr, p.dir[1]};
+  launch_axpy(z, s);
+  for (int k = 1; k <= p.steps; k++) {
+    a.dir_in = p.dir[(k + 1) & 1];   // y_k
+    a.dir_out = p.dir[k & 1];        // y_{k-1} -> y_{k+1}
+    a.last = k == p.steps;
+    if (!a.last) {
+      a.c1 = p.c1[k - 1];
+      a.c2 = p.c2[k - 1];
+    }
+    if (el)
       launch_b2_step3_el(a, s);
-    }
-  } else {
-    for (int k = 0; k < p.steps; k++) {
-      a.dir_in = p.dir[k & 1];
-      a.dir_out = p.dir[(k + 1) & 1];
-      a.c1 = p.c1[k];
-      a.c2 = p.c2[k];
-      a.last = k + 1 == p.steps;
-      launch_b2_step(a, s);
-    }
+    else
+      launch_b2_step3(a, s);
   }
   if (prof) PA_HIP(hipEventRecord(p.spans.back().second, s));
   launch_b2_check(a, s);

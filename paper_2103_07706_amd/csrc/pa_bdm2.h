@@ -133,10 +133,11 @@ void launch_b2_bcast(const B2ColArgs &a, hipStream_t s);
 void launch_b2_wsum(const B2ColArgs &a, hipStream_t s);
 
 void launch_b2_stiff(const B2Args &a, hipStream_t s);
-void launch_b2_step(const B2Args &a, hipStream_t s);     // row form (ELL rows)
-void launch_b2_step_el(const B2Args &a, hipStream_t s);  // element form (cell pass + row pass)
-// element form, three-term on the increment y (dir_in = y_k, dir_out =
-// y_{k-1} -> y_{k+1}; last: the finish x += y_K and the residual partials)
+// One step of a mass solve in three-term form on the increment y (dir_in =
+// y_k, dir_out = y_{k-1} -> y_{k+1}; with last: the finish x += y_K and the
+// residual partials), row form (ELL rows) or element form (cell pass and
+// row pass, for blocks of at least kB2ElMin columns).
+void launch_b2_step3(const B2Args &a, hipStream_t s);
 void launch_b2_step3_el(const B2Args &a, hipStream_t s);
 void launch_b2_norm(const B2Args &a, int slot, hipStream_t s);  // partials of |r|^2 -> norms[slot]
 void launch_b2_check(const B2Args &a, hipStream_t s);  // after the last step: |r_K|^2 vs rtol^2 |r_0|^2

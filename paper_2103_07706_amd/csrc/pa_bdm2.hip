@@ -98,31 +98,31 @@ __global__ __launch_bounds__(kBWG) void k_b2_stiff(B2Args a) {
   b2_partial(rr, Bs, a.part);
 }
 
-// x += d, r -= M d, d' = c1 d + c2 D^-1 r (not on the last step; the last
-// step leaves the per-workgroup partials of |r|^2 instead).
-__global__ __launch_bounds__(kBWG) void k_b2_step(B2Args a) {
+// Row form, three-term on the increment y (x = x_0 + y, b in r): y_{k+1} =
+// y_k + c1 (y_k - y_{k-1}) + c2 D^-1 (b - M y_k) over y_{k-1} (dir_out);
+// with a.last the finish: x += y_K and the partials of |b - M y_K|^2.
+__global__ __launch_bounds__(kBWG) void k_b2_step3(B2Args a) {
   const B2Dev &d = a.d;
   const int Bs = a.Bs;
   const size_t nvel = (size_t)d.nu * Bs, stride = (size_t)gridDim.x * kBWG;
   double rr = 0.0;
   for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < nvel; i += stride) {
     const int row = (int)(i / Bs), c = (int)(i % Bs);
-    double md = 0.0;
+    double my = 0.0;
 #pragma unroll
     for (int t = 0; t < kB2WBlk; t++) {
       const size_t col0 = (size_t)3 * d.bid[(size_t)t * (d.nu / 3) + row / 3];
 #pragma unroll
       for (int q = 0; q < 3; q++)
-        md = fma(d.mass[(size_t)(3 * t + q) * d.nu + row], a.dir_in[(col0 + q) * Bs + c], md);
+        my = fma(d.mass[(size_t)(3 * t + q) * d.nu + row], a.dir_in[(col0 + q) * Bs + c], my);
     }
-    const double di = a.dir_in[i];
-    a.x[i] += di;
-    const double r = a.r[i] - md;
-    a.r[i] = r;
-    if (!a.last)
-      a.dir_out[i] = a.c1 * di + a.c2 * d.dinv[row] * r;
-    else
-      rr = fma(r, r, rr);
+    const double yk = a.dir_in[i], res = a.r[i] - my;
+    if (!a.last) {
+      a.dir_out[i] = yk + a.c1 * (yk - a.dir_out[i]) + a.c2 * d.dinv[row] * res;
+    } else {
+      a.x[i] += yk;
+      rr = fma(res, res, rr);
+    }
   }
   if (a.last) b2_partial(rr, Bs, a.part);
 }
@@ -148,32 +148,6 @@ __global__ __launch_bounds__(kBWG) void k_b2_mel(B2Args a) {
       a.loc[((size_t)12 * cell + r) * Bs + c] = y;
     }
   }
-}
-
-// Element form, row pass: M d from the row's one or two cell slots, then
-// the same update as k_b2_step.
-template <bool UNI>
-__global__ __launch_bounds__(kBWG) void k_b2_step_el(B2Args a) {
-  const B2Dev &d = a.d;
-  const int Bs = a.Bs;
-  const size_t nvel = (size_t)d.nu * Bs, stride = (size_t)gridDim.x * kBWG;
-  double rr = 0.0;
-  for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < nvel; i += stride) {
-    const int row = uni<UNI>((int)(i / Bs)), c = (int)(i % Bs);
-    const auto rl = kp<UNI>(d.rloc + 2 * (size_t)row);
-    const int p0 = rl[0], p1 = rl[1];
-    double md = a.loc[(size_t)p0 * Bs + c];
-    if (p1 >= 0) md += a.loc[(size_t)p1 * Bs + c];
-    const double di = a.dir_in[i];
-    a.x[i] += di;
-    const double r = a.r[i] - md;
-    a.r[i] = r;
-    if (!a.last)
-      a.dir_out[i] = a.c1 * di + a.c2 * kp<UNI>(d.dinv)[row] * r;
-    else
-      rr = fma(r, r, rr);
-  }
-  if (a.last) b2_partial(rr, Bs, a.part);
 }
 
 // Element form, three-term row pass on the increment y of the solve (x =
@@ -605,20 +579,11 @@ void launch_b2_stiff(const B2Args &a, hipStream_t s) {
   hipLaunchKernelGGL(k_b2_stiff, dim3(b2_grid(a.d.nu + 3 * a.d.nc, a.Bs)), dim3(kBWG), 0, s, a);
   hipLaunchKernelGGL(k_b2_fin, dim3(1), dim3(kFinT), 0, s, a, b2_grid(a.d.nu + 3 * a.d.nc, a.Bs), 0);
 }
-void launch_b2_step(const B2Args &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_b2_step, dim3(b2_grid(a.d.nu, a.Bs)), dim3(kBWG), 0, s, a);
-}
-void launch_b2_step_el(const B2Args &a, hipStream_t s) {
-  if (a.Bs == 64) {
-    hipLaunchKernelGGL(k_b2_mel<true>, dim3(b2_grid(a.d.nc, a.Bs)), dim3(kBWG), 0, s, a);
-    hipLaunchKernelGGL(k_b2_step_el<true>, dim3(b2_grid(a.d.nu, a.Bs)), dim3(kBWG), 0, s, a);
-  } else {
-    hipLaunchKernelGGL(k_b2_mel<false>, dim3(b2_grid(a.d.nc, a.Bs)), dim3(kBWG), 0, s, a);
-    hipLaunchKernelGGL(k_b2_step_el<false>, dim3(b2_grid(a.d.nu, a.Bs)), dim3(kBWG), 0, s, a);
-  }
-}
 // After a last step (row or element form, both on b2_grid(nu, Bs) workgroups)
 // left the partials of |r_K|^2: the check against |r_0|^2.
+void launch_b2_step3(const B2Args &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_b2_step3, dim3(b2_grid(a.d.nu, a.Bs)), dim3(kBWG), 0, s, a);
+}
 void launch_b2_step3_el(const B2Args &a, hipStream_t s) {
   if (a.Bs == 64) {
     hipLaunchKernelGGL(k_b2_mel<true>, dim3(b2_grid(a.d.nc, a.Bs)), dim3(kBWG), 0, s, a);
