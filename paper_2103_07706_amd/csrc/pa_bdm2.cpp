@@ -695,14 +695,13 @@ void b2_solve(const B2Plan &p, B2Args &a, hipStream_t s, pa_stats &st) {
     p.prof_units += (double)p.steps * cols;
   }
   // three-term form on the increment: y_1 = d_0 (set up in dir[0]), y_0 = 0
-  // in dir[1]; steps k = 1 .. K-1 write y_{k+1} over y_{k-1}; the finish
-  // takes M y_K for the true residual (as many launches as the two-term
-  // form, four vectors a step instead of six)
-  AxpyArgs z{(size_t)a.d.nu * a.Bs, 0.0, 0.0, 0.0, nullptr, nullptr, nullptr, p.dir[1]};
-  launch_axpy(z, s);
+  // (step 1 does not read it); steps k = 1 .. K-1 write y_{k+1} over
+  // y_{k-1}; the finish takes M y_K for the true residual (as many launches
+  // as the two-term form, four vectors a step instead of six)
   for (int k = 1; k <= p.steps; k++) {
     a.dir_in = p.dir[(k + 1) & 1];   // y_k
     a.dir_out = p.dir[k & 1];        // y_{k-1} -> y_{k+1}
+    a.first = k == 1;
     a.last = k == p.steps;
     if (!a.last) {
       a.c1 = p.c1[k - 1];

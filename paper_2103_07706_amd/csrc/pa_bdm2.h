@@ -74,6 +74,7 @@ struct B2Args {
   const double *dir_in;
   double *dir_out;
   int last;
+  int first;                      // three-term step 1: y_0 = 0 (dir_out not read)
   double *part;                   // per-workgroup partials [wg][Bs]
   double *loc;                    // element step: [nc * 12][Bs] cell products
   double *norms;                  // [2][Bs]: |r_0|^2, |r_K|^2

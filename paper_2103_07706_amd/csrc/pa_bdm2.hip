@@ -118,7 +118,7 @@ __global__ __launch_bounds__(kBWG) void k_b2_step3(B2Args a) {
     }
     const double yk = a.dir_in[i], res = a.r[i] - my;
     if (!a.last) {
-      a.dir_out[i] = yk + a.c1 * (yk - a.dir_out[i]) + a.c2 * d.dinv[row] * res;
+      a.dir_out[i] = yk + a.c1 * (yk - (a.first ? 0.0 : a.dir_out[i])) + a.c2 * d.dinv[row] * res;
     } else {
       a.x[i] += yk;
       rr = fma(res, res, rr);
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(kBWG) void k_b2_step3_el(B2Args a) {
     if (p1 >= 0) my += a.loc[(size_t)p1 * Bs + c];
     const double yk = a.dir_in[i], res = a.r[i] - my;
     if (!a.last) {
-      a.dir_out[i] = yk + a.c1 * (yk - a.dir_out[i]) + a.c2 * kp<UNI>(d.dinv)[row] * res;
+      a.dir_out[i] = yk + a.c1 * (yk - (a.first ? 0.0 : a.dir_out[i])) + a.c2 * kp<UNI>(d.dinv)[row] * res;
     } else {
       a.x[i] += yk;
       rr = fma(res, res, rr);
