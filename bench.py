@@ -472,7 +472,7 @@ def main():
                "dtype": "f64", "data": "synthetic",
                "config": {"workload": "bdm2_l5_m64", "level": 5, "M": 64, "T_s": 7200.0,
                           "members": 1, "spaces": "BDM2/P1DG"},
-               "roofline": {"bound": "hbm", "kernel": "k_b2_step3 (row and element forms)",
+               "roofline": {"bound": "hbm", "kernel": "k_b2_step3 (row form), k_b2_cstep (cell form, 64 columns)",
                             "achieved": k["GB/s"], "peak": 8000.0, "unit": "GB/s",
                             "frac": k["frac_hbm"], "traffic": None},
                "detail": r}

@@ -596,7 +596,7 @@ size_t b2_plan(const pa_bdm2 *b, int call, int B, const double *t, const pa_avg 
     p.loc = take<double>(ws, off, cap, (size_t)12 * b->nc * p.Vs);
     p.ut = take<double>(ws, off, cap, (size_t)4 * kB2FQ * b->ne * p.Vs);
     p.rhs = take<double>(ws, off, cap, (size_t)b->nu * p.Vs);
-    if (p.Vs >= kB2ElMin) p.eloc = take<double>(ws, off, cap, (size_t)12 * b->nc * p.Vs);
+    if (p.Vs >= kB2ElMin && p.Vs < 64) p.eloc = take<double>(ws, off, cap, (size_t)12 * b->nc * p.Vs);
     p.part = take<double>(ws, off, cap, (size_t)2048 * 64);
     p.norms = take<double>(ws, off, cap, (size_t)2 * 64);
     p.cfd = take<double>(ws, off, cap, p.cfh.size());
@@ -661,7 +661,7 @@ size_t b2_plan(const pa_bdm2 *b, int call, int B, const double *t, const pa_avg 
     p.ut = take<double>(ws, off, cap, (size_t)4 * kB2FQ * b->ne * Bs);
     p.rhs = take<double>(ws, off, cap, (size_t)b->nu * Bs);
   }
-  if (Bs >= kB2ElMin) p.eloc = take<double>(ws, off, cap, (size_t)12 * b->nc * Bs);
+  if (Bs >= kB2ElMin && Bs < 64) p.eloc = take<double>(ws, off, cap, (size_t)12 * b->nc * Bs);
   p.part = take<double>(ws, off, cap, (size_t)2048 * Bs);
   p.norms = take<double>(ws, off, cap, (size_t)2 * Bs);
   if (expo) p.coefF = take<double>(ws, off, cap, p.hF.size());
@@ -679,16 +679,17 @@ size_t b2_plan(const pa_bdm2 *b, int call, int B, const double *t, const pa_avg 
 // it up, then the residual check.
 void b2_solve(const B2Plan &p, B2Args &a, hipStream_t s, pa_stats &st) {
   launch_b2_stiff(a, s);
-  const bool el = a.Bs >= kB2ElMin && a.loc != nullptr;
+  const bool cel = a.Bs == 64;
+  const bool el = !cel && a.Bs >= kB2ElMin && a.loc != nullptr;
   const bool prof = p.ctx && p.ctx->prof_kernel == PA_KERNEL_B2_STEP && p.steps > 0;
   if (prof) {
     p.spans.emplace_back(prof_event(p.ctx), prof_event(p.ctx));
     PA_HIP(hipEventRecord(p.spans.back().first, s));
     // per row and column four vectors (below); per row the ELL row (21
-    // values, a third of seven block ids) and D^-1, or in the element form
-    // per cell its 12 x 12 block and per row D^-1
+    // values, a third of seven block ids) and D^-1, or in the element and
+    // cell forms per cell its 12 x 12 block and per row D^-1
     const double rows = a.d.nu, cols = a.Bs;
-    const double mat = el ? 1152.0 * a.d.nc + 8.0 * rows : (168.0 + 28.0 / 3.0 + 8.0) * rows;
+    const double mat = el || cel ? 1152.0 * a.d.nc + 8.0 * rows : (168.0 + 28.0 / 3.0 + 8.0) * rows;
     p.prof_launches += p.steps;
     // three-term: y_k, y_{k-1}, b in, y_{k+1} out; the finish x, y_K, b in, x out
     p.prof_bytes += p.steps * (mat + 32.0 * rows * cols);
@@ -707,7 +708,9 @@ void b2_solve(const B2Plan &p, B2Args &a, hipStream_t s, pa_stats &st) {
       a.c1 = p.c1[k - 1];
       a.c2 = p.c2[k - 1];
     }
-    if (el)
+    if (cel)
+      launch_b2_cstep(a, s);
+    else if (el)
       launch_b2_step3_el(a, s);
     else
       launch_b2_step3(a, s);

@@ -53,7 +53,8 @@ struct B2Dev {
   const double *bot = nullptr;     // [nh]: bottom height (P1DG coefficients)
 };
 // Blocks at least this wide take the element form of the mass-solve step
-// (a cell pass and a row pass) instead of the row kernel.
+// (a cell pass and a row pass) instead of the row kernel; blocks of 64
+// columns take the cell form (one launch, no cell products in memory).
 constexpr int kB2ElMin = 8;
 // Workspace the shared-basis average may spend on a group's bases and sums
 // (the group narrows below 64 members beyond it).
@@ -136,10 +137,11 @@ void launch_b2_wsum(const B2ColArgs &a, hipStream_t s);
 void launch_b2_stiff(const B2Args &a, hipStream_t s);
 // One step of a mass solve in three-term form on the increment y (dir_in =
 // y_k, dir_out = y_{k-1} -> y_{k+1}; with last: the finish x += y_K and the
-// residual partials), row form (ELL rows) or element form (cell pass and
-// row pass, for blocks of at least kB2ElMin columns).
+// residual partials), row form (ELL rows), element form (cell pass and
+// row pass, for blocks of kB2ElMin to 32 columns) or cell form (64 columns).
 void launch_b2_step3(const B2Args &a, hipStream_t s);
 void launch_b2_step3_el(const B2Args &a, hipStream_t s);
+void launch_b2_cstep(const B2Args &a, hipStream_t s);
 void launch_b2_norm(const B2Args &a, int slot, hipStream_t s);  // partials of |r|^2 -> norms[slot]
 void launch_b2_check(const B2Args &a, hipStream_t s);  // after the last step: |r_K|^2 vs rtol^2 |r_0|^2
 void launch_b2_acc(const B2Args &a, hipStream_t s);

@@ -177,6 +177,78 @@ __global__ __launch_bounds__(kBWG) void k_b2_step3_el(B2Args a) {
   if (a.last) b2_partial(rr, Bs, a.part);
 }
 
+// Cell form of the three-term step on 64-column blocks: a wave holds one
+// cell at all 64 columns and forms its 12 x 12 product against the cell's
+// gathered y_k in registers.  It finishes the cell's three interior rows,
+// and the three rows of each edge whose first cell (rloc slot 0) it is,
+// adding the other cell's three block rows against that cell's gathered
+// values.  Each row's sum is the element form's (the first cell's 12-term
+// chain, then the second's), so the result is the same bits, without the
+// products' round trip through memory (12 values a cell and column written
+// and read again) and in one launch instead of two.
+__global__ __launch_bounds__(kBWG) void k_b2_cstep(B2Args a) {
+  const B2Dev &d = a.d;
+  constexpr int Bs = 64;
+  const size_t total = (size_t)d.nc * Bs, stride = (size_t)gridDim.x * kBWG;
+  const auto rloc = kp<true>(d.rloc);
+  const auto dinv = kp<true>(d.dinv);
+  double rr = 0.0;
+  auto update = [&](int g, double yk, double my) {
+    const size_t gi = (size_t)g * Bs + threadIdx.x % Bs;
+    const double res = a.r[gi] - my;
+    if (!a.last) {
+      a.dir_out[gi] = yk + a.c1 * (yk - (a.first ? 0.0 : a.dir_out[gi])) + a.c2 * dinv[g] * res;
+    } else {
+      a.x[gi] += yk;
+      rr = fma(res, res, rr);
+    }
+  };
+  for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < total; i += stride) {
+    const int cell = uni<true>((int)(i / Bs)), c = (int)(i % Bs);
+    const auto cdof = kp<true>(d.cdof + 12 * (size_t)cell);
+    const auto M = kp<true>(d.mT + (size_t)144 * cell);
+    double v[12];
+#pragma unroll
+    for (int j = 0; j < 12; j++) v[j] = a.dir_in[(size_t)cdof[j] * Bs + c];
+#pragma unroll
+    for (int r = 9; r < 12; r++) {
+      double y = 0.0;
+#pragma unroll
+      for (int j = 0; j < 12; j++) y = fma(M[12 * r + j], v[j], y);
+      update(cdof[r], v[r], y);
+    }
+    for (int e = 0; e < 3; e++) {
+      const int g0 = cdof[3 * e];
+      if (rloc[2 * (size_t)g0] != 12 * cell + 3 * e) continue;  // the edge's second cell
+      const int o = rloc[2 * (size_t)g0 + 1];
+      const int oc = o >= 0 ? o / 12 : cell;
+      const auto ocd = kp<true>(d.cdof + 12 * (size_t)oc);
+      const auto OM = kp<true>(d.mT + (size_t)144 * oc);
+      double w[12];
+      if (o >= 0) {
+#pragma unroll
+        for (int j = 0; j < 12; j++) w[j] = a.dir_in[(size_t)ocd[j] * Bs + c];
+      }
+#pragma unroll
+      for (int q = 0; q < 3; q++) {
+        const int g = cdof[3 * e + q];
+        double y = 0.0;
+#pragma unroll
+        for (int j = 0; j < 12; j++) y = fma(M[12 * (3 * e + q) + j], v[j], y);
+        if (o >= 0) {
+          const int os = rloc[2 * (size_t)g + 1] - 12 * oc;
+          double z = 0.0;
+#pragma unroll
+          for (int j = 0; j < 12; j++) z = fma(OM[12 * os + j], w[j], z);
+          y += z;
+        }
+        update(g, v[3 * e + q], y);
+      }
+    }
+  }
+  if (a.last) b2_partial(rr, Bs, a.part);
+}
+
 __global__ __launch_bounds__(kBWG) void k_b2_norm(B2Args a) {
   const int Bs = a.Bs;
   const size_t nvel = (size_t)a.d.nu * Bs, stride = (size_t)gridDim.x * kBWG;
@@ -583,6 +655,11 @@ void launch_b2_stiff(const B2Args &a, hipStream_t s) {
 // left the partials of |r_K|^2: the check against |r_0|^2.
 void launch_b2_step3(const B2Args &a, hipStream_t s) {
   hipLaunchKernelGGL(k_b2_step3, dim3(b2_grid(a.d.nu, a.Bs)), dim3(kBWG), 0, s, a);
+}
+// The cell form's grid matches the row kernels' (b2_grid(nu, Bs)): the
+// check reads that many workgroups' partials.
+void launch_b2_cstep(const B2Args &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_b2_cstep, dim3(b2_grid(a.d.nu, a.Bs)), dim3(kBWG), 0, s, a);
 }
 void launch_b2_step3_el(const B2Args &a, hipStream_t s) {
   if (a.Bs == 64) {

@@ -77,6 +77,30 @@ def test_gpu_bdm2_apply_L_parity(level, B):
     assert 0 < st["resid_max"] <= 1e-13
 
 
+@pytest.mark.parametrize("level", [0, 3, 5])
+def test_gpu_bdm2_cell_form_equals_element_form(level):
+    """64-column solves take the cell form of the mass-solve step (one
+    launch, both cells' block rows of an edge row in registers), 32-column
+    solves the element form (a cell pass writing the products, a row pass
+    adding them).  Columns are independent and each row's sum is formed in
+    the same order, so L and the exponential on 64 states equal, bit for
+    bit, the same calls on each half of them (level 0: more workgroups than
+    cells)."""
+    ob, lb, lm = _pair(level)
+    lb.estimate_lambda(iters=60)
+    U = _states(ob, range(64))
+    wide, st = lb.apply_L(_dev(U), _cfg())
+    halves = [lb.apply_L(_dev(U[h:h + 32]), _cfg())[0].cpu().numpy() for h in (0, 32)]
+    assert np.array_equal(wide.cpu().numpy(), np.concatenate(halves))
+    assert 0 < st["resid_max"] <= 1e-13
+    t = np.linspace(-3600.0, 3600.0, 64)
+    wide, st = lb.expL_apply(t, _dev(U), _cfg(cg_rtol=1e-10, cheb_tol=1e-6))
+    halves = [lb.expL_apply(t[h:h + 32], _dev(U[h:h + 32]), _cfg(cg_rtol=1e-10, cheb_tol=1e-6))[0]
+              .cpu().numpy() for h in (0, 32)]
+    assert np.array_equal(wide.cpu().numpy(), np.concatenate(halves))
+    assert st["solves"] > 1
+
+
 def test_gpu_bdm2_apply_L_of_constant_depth_is_zero():
     """Constant depth, fluid at rest: the divergence of a continuous normal
     field integrates to zero, so L of (0, 1) has no velocity forcing from a
