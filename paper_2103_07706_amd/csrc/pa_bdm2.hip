@@ -185,11 +185,17 @@ __global__ __launch_bounds__(kBWG) void k_b2_step3_el(B2Args a) {
 // values.  Each row's sum is the element form's (the first cell's 12-term
 // chain, then the second's), so the result is the same bits, without the
 // products' round trip through memory (12 values a cell and column written
-// and read again) and in one launch instead of two.
+// and read again) and in one launch instead of two.  Cells are laid over
+// the XCDs in eight contiguous ranges (workgroup b runs on XCD b % 8, and
+// the grid is a multiple of 8), so the neighbours a cell gathers from are
+// mostly in flight on the same XCD and its L2.
 __global__ __launch_bounds__(kBWG) void k_b2_cstep(B2Args a) {
   const B2Dev &d = a.d;
-  constexpr int Bs = 64;
-  const size_t total = (size_t)d.nc * Bs, stride = (size_t)gridDim.x * kBWG;
+  constexpr int Bs = 64, kWaves = kBWG / 64;
+  const int xcd = blockIdx.x & 7, per = gridDim.x >> 3;
+  const int cpx = (d.nc + 7) >> 3;
+  const int c_end = min(d.nc, (xcd + 1) * cpx);
+  const size_t total = (size_t)c_end * Bs, stride = (size_t)per * kWaves * Bs;
   const auto rloc = kp<true>(d.rloc);
   const auto dinv = kp<true>(d.dinv);
   double rr = 0.0;
@@ -203,7 +209,8 @@ __global__ __launch_bounds__(kBWG) void k_b2_cstep(B2Args a) {
       rr = fma(res, res, rr);
     }
   };
-  for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < total; i += stride) {
+  const size_t i0 = ((size_t)xcd * cpx + (size_t)(blockIdx.x >> 3) * kWaves) * Bs + threadIdx.x;
+  for (size_t i = i0; i < total; i += stride) {
     const int cell = uni<true>((int)(i / Bs)), c = (int)(i % Bs);
     const auto cdof = kp<true>(d.cdof + 12 * (size_t)cell);
     const auto M = kp<true>(d.mT + (size_t)144 * cell);
@@ -656,10 +663,14 @@ void launch_b2_stiff(const B2Args &a, hipStream_t s) {
 void launch_b2_step3(const B2Args &a, hipStream_t s) {
   hipLaunchKernelGGL(k_b2_step3, dim3(b2_grid(a.d.nu, a.Bs)), dim3(kBWG), 0, s, a);
 }
-// The cell form's grid matches the row kernels' (b2_grid(nu, Bs)): the
-// check reads that many workgroups' partials.
+// Workgroups of a step: the cell form's grid is a multiple of 8 (at most
+// 2048, the partials' room); the check reads that many partials.
+static int b2_step_grid(const B2Args &a) {
+  const int g = b2_grid(a.d.nu, a.Bs);
+  return a.Bs == 64 ? (g + 7) / 8 * 8 : g;
+}
 void launch_b2_cstep(const B2Args &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_b2_cstep, dim3(b2_grid(a.d.nu, a.Bs)), dim3(kBWG), 0, s, a);
+  hipLaunchKernelGGL(k_b2_cstep, dim3(b2_step_grid(a)), dim3(kBWG), 0, s, a);
 }
 void launch_b2_step3_el(const B2Args &a, hipStream_t s) {
   if (a.Bs == 64) {
@@ -671,7 +682,7 @@ void launch_b2_step3_el(const B2Args &a, hipStream_t s) {
   }
 }
 void launch_b2_check(const B2Args &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_b2_fin, dim3(1), dim3(kFinT), 0, s, a, b2_grid(a.d.nu, a.Bs), 1);
+  hipLaunchKernelGGL(k_b2_fin, dim3(1), dim3(kFinT), 0, s, a, b2_step_grid(a), 1);
 }
 void launch_b2_norm(const B2Args &a, int slot, hipStream_t s) {
   hipLaunchKernelGGL(k_b2_norm, dim3(b2_grid(a.d.nu, a.Bs)), dim3(kBWG), 0, s, a);
