@@ -613,7 +613,9 @@ int pa_bdm2_estimate_lambda(pa_ctx *ctx, pa_bdm2 *b, int iters, double safety,
 /* Workspace bytes of a call: call is one of the PA_BDM2_* values below, B
  * the number of states (members for PA_BDM2_PHASE_AVG); t_host the B times
  * of PA_BDM2_EXPL (the degree depends on them), avg the nodes of
- * PA_BDM2_PHASE_AVG (others NULL). */
+ * PA_BDM2_PHASE_AVG (others NULL).  B < 1 is PA_EINVAL; L, the exponential
+ * and N take at most 64 states (PA_ENOTSUP beyond), the step at most 64
+ * members (PA_EINVAL beyond), the average any number. */
 enum { PA_BDM2_APPLY_L = 0, PA_BDM2_EXPL = 1, PA_BDM2_NONLINEAR = 2, PA_BDM2_PHASE_AVG = 3,
        PA_BDM2_STEP = 4 };  /* PA_BDM2_STEP: t_host points to dt */
 int pa_bdm2_workspace_size(const pa_bdm2 *b, int call, int B, const double *t_host,

@@ -101,6 +101,9 @@ def test_bdm2_refuses_topography_and_bad_sizes(oracle_mesh):
     assert W(b._h, pa.PA_BDM2_APPLY_L, 65, None, None, ctypes.byref(cfg),
              ctypes.byref(sz)) == pa.PA_ENOTSUP
     assert W(b._h, 7, 1, None, None, ctypes.byref(cfg), ctypes.byref(sz)) == pa.PA_EINVAL
+    # no states at all is an error for every call, not an empty no-op
+    for call in (pa.PA_BDM2_APPLY_L, pa.PA_BDM2_NONLINEAR):
+        assert W(b._h, call, 0, None, None, ctypes.byref(cfg), ctypes.byref(sz)) == pa.PA_EINVAL
     # an exponential needs lambda_bar and its times, an average its nodes
     t = np.array([100.0])
     avg = pa.Avg(8, 3600.0)
@@ -130,6 +133,10 @@ def test_bdm2_refuses_topography_and_bad_sizes(oracle_mesh):
     assert W(b._h, pa.PA_BDM2_STEP, 2, None, avg._h, ctypes.byref(cfg), ctypes.byref(sz)) == pa.PA_EINVAL
     assert W(b._h, pa.PA_BDM2_STEP, 2, pa._dp(dt), None, ctypes.byref(cfg), ctypes.byref(sz)) == pa.PA_EINVAL
     assert W(b._h, pa.PA_BDM2_STEP, 65, pa._dp(dt), avg._h, ctypes.byref(cfg),
+             ctypes.byref(sz)) == pa.PA_EINVAL
+    assert W(b._h, pa.PA_BDM2_STEP, 0, pa._dp(dt), avg._h, ctypes.byref(cfg),
+             ctypes.byref(sz)) == pa.PA_EINVAL
+    assert W(b._h, pa.PA_BDM2_PHASE_AVG, 0, None, avg._h, ctypes.byref(cfg),
              ctypes.byref(sz)) == pa.PA_EINVAL
     st = b.workspace_size(pa.PA_BDM2_STEP, 2, dt, avg)
     assert st >= 7 * 8 * b.n * 2 + b.workspace_size(pa.PA_BDM2_PHASE_AVG, 2, avg=avg)
