@@ -267,16 +267,21 @@ def secondary_workloads(pa, ctx, steps=3, warmup=1):
     del batch, bops, Us, outs
     out["bdm2_l5_m64"] = bdm2_workload(pa, ctx, steps=steps, warmup=warmup)
     out["bdm2_l5_m64_x64"] = bdm2_workload(pa, ctx, steps=2, warmup=1, members=64)
+    out["bdm2_l5_m64_fp32_refined"] = bdm2_workload(pa, ctx, steps=steps, warmup=warmup,
+                                                    precision="fp32_refined")
+    out["bdm2_l5_m64_x64_fp32_refined"] = bdm2_workload(pa, ctx, steps=2, warmup=1, members=64,
+                                                        precision="fp32_refined")
     return out
 
 
-def bdm2_workload(pa, ctx, steps=3, warmup=1, members=1):
+def bdm2_workload(pa, ctx, steps=3, warmup=1, members=1, precision="fp64"):
     """Nbar on the paper's own spaces (BDM2 velocity, P1DG depth) at level 5
     (its N_C = 20480 grid), members of 40 geostrophic bumps each (seeds
-    0, 1, ...), M = 64 nodes over T = 2 h, FP64 at the metric tolerances;
-    lambda_bar from the library's power iteration.  Value: member-Nbar/s.
-    Also the mass-solve step kernel's time and algorithmic bytes
-    (pa_ctx_profile) over one evaluation."""
+    0, 1, ...), M = 64 nodes over T = 2 h, at the metric tolerances, FP64
+    or with FP32 inner solves and FP64 refinement on the 64-column blocks
+    (fp32_refined); lambda_bar from the library's power iteration.  Value:
+    member-Nbar/s.  Also the FP64 mass-solve step kernels' time and
+    algorithmic bytes (pa_ctx_profile) over one evaluation."""
     import numpy as np
     import torch
 
@@ -290,7 +295,8 @@ def bdm2_workload(pa, ctx, steps=3, warmup=1, members=1):
                                                        phys) for m in range(members)]),
                      dtype=torch.float64, device="cuda:0")
     avg = pa.Avg(64, 7200.0)
-    cfg = pa.solve_cfg(cg_rtol=1e-10, cheb_tol=1e-6)
+    prec = pa.PA_FP32_REFINED if precision == "fp32_refined" else pa.PA_FP64
+    cfg = pa.solve_cfg(cg_rtol=1e-10, cheb_tol=1e-6, precision=prec)
     out = torch.empty_like(U)
     for _ in range(warmup):
         b.phase_avg_rhs(avg, U, cfg, out=out)
@@ -306,9 +312,11 @@ def bdm2_workload(pa, ctx, steps=3, warmup=1, members=1):
     b.phase_avg_rhs(avg, U, cfg, out=out)
     prof = ctx.profile_read()
     ctx.profile(pa.PA_KERNEL_NONE)
-    gbs = prof["bytes"] / (prof["total_ms"] * 1e-3) / 1e9
+    # (FP32-refined ensembles run no FP64 steps: nothing for the hook to time)
+    gbs = prof["bytes"] / (prof["total_ms"] * 1e-3) / 1e9 if prof["total_ms"] > 0 else 0.0
     return {"unit": "member-Nbar/s" if members > 1 else "Nbar/s", "level": 5, "M": 64,
-            "T": 7200.0, "members": members, "nu": b.nu, "nh": b.nh, "lambda_bar": lam,
+            "T": 7200.0, "members": members, "precision": precision, "nu": b.nu, "nh": b.nh,
+            "lambda_bar": lam, "refinements": st["refinements"],
             "value": members * steps / el, "ms_per_step": 1e3 * el / steps,
             "solves": st["solves"], "steps_per_solve": st["cg_iters_max"], "kmax": st["kmax"],
             "resid_max": st["resid_max"],

@@ -624,11 +624,15 @@ int pa_bdm2_workspace_size(const pa_bdm2 *b, int call, int B, const double *t_ho
  * must not alias U).  cfg: cg_rtol and maxit (the cap on semi-iteration
  * steps) apply, and cheb_tol, weight_cut and backward where the call has an
  * exponential or an average; NULL takes the defaults.  The pair's solves
- * are FP64 Jacobi Chebyshev semi-iterations and its exponential is the
- * Chebyshev one: a cfg asking for PA_EXP_REXI, PA_FP32_REFINED,
- * PA_SOLVER_CG or PA_PRECOND_LEARNED is refused with PA_ENOTSUP (use_graph
- * is ignored).  Every call's workspace is 256-byte aligned (PA_EINVAL).  stats (may be NULL): solves,
- * cg_iters (steps summed), cg_iters_max, resid_max, device_ms. */
+ * are Jacobi Chebyshev semi-iterations and its exponential is the
+ * Chebyshev one.  With precision PA_FP32_REFINED the solves on 64-column
+ * blocks run FP32 inner rounds to max(inner_rtol, 1e-6) closed by FP64
+ * refinements of x and r (narrower blocks stay FP64); the FP64 residual
+ * check decides either way.  A cfg asking for PA_EXP_REXI, PA_SOLVER_CG or
+ * PA_PRECOND_LEARNED is refused with PA_ENOTSUP (use_graph is ignored).
+ * Every call's workspace is 256-byte aligned (PA_EINVAL).  stats (may be
+ * NULL): solves, cg_iters (steps summed, inner FP32 steps included),
+ * cg_iters_max, refinements, resid_max, device_ms. */
 int pa_bdm2_apply_L(pa_ctx *ctx, const pa_bdm2 *b, int B, const double *U_dev,
                     double *out_dev, void *ws_dev, size_t ws_bytes,
                     const pa_solve_cfg *cfg, pa_stats *stats);

@@ -452,6 +452,12 @@ struct B2Plan {
   std::vector<double> cfh, cbh;   // [kmax + 1][Mk]: c_k(s_m), w_m c_k(-s_m)
   double *basis = nullptr, *Zs = nullptr, *V = nullptr, *Y = nullptr, *cfd = nullptr, *cbd = nullptr;
   double *eloc = nullptr;  // element-form step products [nc * 12][Bs] (wide blocks)
+  // FP32 inner solves with FP64 refinement (PA_FP32_REFINED) on 64-column
+  // blocks: rounds of kin steps, the last of klast, outer rounds in all
+  bool mixed = false;
+  int kin = 0, klast = 0, outer = 0;
+  std::vector<double> mc1, mc2;
+  float *r32 = nullptr, *y32[2] = {nullptr, nullptr};
   double *Ra = nullptr, *Rb = nullptr, *acc = nullptr, *r = nullptr, *dir[2] = {nullptr, nullptr};
   double *raw = nullptr, *ut = nullptr, *loc = nullptr, *rhs = nullptr;
   double *part = nullptr, *norms = nullptr, *coefF = nullptr, *coefB = nullptr, *cwd = nullptr;
@@ -547,6 +553,32 @@ size_t b2_plan(const pa_bdm2 *b, int call, int B, const double *t, const pa_avg 
     p.c2[k] = 2.0 * rn / de;
     rho = rn;
   }
+  p.mixed = cfg.precision == PA_FP32_REFINED;
+  if (p.mixed) {
+    // inner FP32 rounds to eps = max(inner_rtol, 1e-6) (the single-precision
+    // floor), as many FP64 refinements as eps per round (counted as 10 eps)
+    // needs to reach cg_rtol, the last round sized to the rest; the FP64
+    // residual check of the solve decides
+    const double eps = std::max(cfg.inner_rtol, 1e-6);
+    p.kin = std::min(cfg.maxit, (int)std::ceil(std::acosh(2.0 / eps) / std::acosh(sigma)) + 1);
+    p.outer = std::max(1, (int)std::ceil(std::log(cfg.cg_rtol) / std::log(10.0 * eps)));
+    const double rest = cfg.cg_rtol / std::pow(eps, p.outer - 1);
+    int kl = p.kin;
+    if (rest > eps && rest < 1.0)
+      kl = (int)std::ceil(std::acosh(2.0 / rest) / std::acosh(sigma)) + 1;
+    else if (rest >= 1.0)
+      kl = 1;
+    p.klast = std::min(p.kin, std::max(kl, (p.kin + 1) / 2));
+    p.mc1.assign(p.kin, 0.0);
+    p.mc2.assign(p.kin, 0.0);
+    double rh = 1.0 / sigma;
+    for (int k = 0; k < p.kin; k++) {
+      const double rn = 1.0 / (2.0 * sigma - rh);
+      p.mc1[k] = rn * rh;
+      p.mc2[k] = 2.0 * rn / de;
+      rh = rn;
+    }
+  }
   std::vector<std::vector<double>> tF, tB;  // per chunk: forward and backward times
   p.shared = call == kCallNbar && cfg.backward == PA_BACKWARD_CLENSHAW;
   if (p.shared) {
@@ -598,6 +630,11 @@ size_t b2_plan(const pa_bdm2 *b, int call, int B, const double *t, const pa_avg 
     p.rhs = take<double>(ws, off, cap, (size_t)b->nu * p.Vs);
     if (p.Vs >= kB2ElMin && p.Vs < 64) p.eloc = take<double>(ws, off, cap, (size_t)12 * b->nc * p.Vs);
     p.part = take<double>(ws, off, cap, (size_t)2048 * 64);
+    if (p.mixed) {
+      p.r32 = take<float>(ws, off, cap, (size_t)b->nu * 64);
+      p.y32[0] = take<float>(ws, off, cap, (size_t)b->nu * 64);
+      p.y32[1] = take<float>(ws, off, cap, (size_t)b->nu * 64);
+    }
     p.norms = take<double>(ws, off, cap, (size_t)2 * 64);
     p.cfd = take<double>(ws, off, cap, p.cfh.size());
     p.cbd = take<double>(ws, off, cap, p.cbh.size());
@@ -663,6 +700,11 @@ size_t b2_plan(const pa_bdm2 *b, int call, int B, const double *t, const pa_avg 
   }
   if (Bs >= kB2ElMin && Bs < 64) p.eloc = take<double>(ws, off, cap, (size_t)12 * b->nc * Bs);
   p.part = take<double>(ws, off, cap, (size_t)2048 * Bs);
+  if (p.mixed && Bs == 64) {
+    p.r32 = take<float>(ws, off, cap, (size_t)b->nu * 64);
+    p.y32[0] = take<float>(ws, off, cap, (size_t)b->nu * 64);
+    p.y32[1] = take<float>(ws, off, cap, (size_t)b->nu * 64);
+  }
   p.norms = take<double>(ws, off, cap, (size_t)2 * Bs);
   if (expo) p.coefF = take<double>(ws, off, cap, p.hF.size());
   if (call == kCallNbar) {
@@ -679,6 +721,47 @@ size_t b2_plan(const pa_bdm2 *b, int call, int B, const double *t, const pa_avg 
 // it up, then the residual check.
 void b2_solve(const B2Plan &p, B2Args &a, hipStream_t s, pa_stats &st) {
   launch_b2_stiff(a, s);
+  if (p.mixed && a.Bs == 64 && p.r32) {
+    // FP32 inner rounds in the three-term form (the round's start y_1 from
+    // k_b2_mix_init or the previous refinement, steps 2..kr over y_{k-1}),
+    // each closed by an FP64 refinement of x and r; then the FP64 check of
+    // |r|^2 against cg_rtol^2 |r_0|^2
+    B2MixArgs m{};
+    m.d = a.d;
+    m.x = a.x;
+    m.r = a.r;
+    m.r32 = p.r32;
+    m.part = a.part;
+    m.theta_inv = (float)(1.0 / p.theta);
+    float *cur = p.y32[0], *prev = p.y32[1];
+    m.y_out = cur;
+    launch_b2_mix_init(m, s);
+    int steps = 0;
+    for (int o = 0; o < p.outer; o++) {
+      const int kr = o + 1 == p.outer ? p.klast : p.kin;
+      steps += kr;
+      for (int i = 1; i < kr; i++) {
+        m.y_cur = cur;
+        m.y_out = prev;
+        m.c1 = (float)p.mc1[i - 1];
+        m.c2 = (float)p.mc2[i - 1];
+        m.zero_prev = i == 1 ? 1 : 0;
+        launch_b2_cstep32(m, s);
+        std::swap(cur, prev);
+      }
+      m.y_cur = cur;
+      m.y_out = prev;
+      m.last = o + 1 == p.outer ? 1 : 0;
+      launch_b2_refine(m, s);
+      std::swap(cur, prev);
+    }
+    launch_b2_check(a, s);
+    st.solves++;
+    st.refinements += p.outer;
+    st.cg_iters += steps;
+    st.cg_iters_max = std::max(st.cg_iters_max, steps);
+    return;
+  }
   const bool cel = a.Bs == 64;
   const bool el = !cel && a.Bs >= kB2ElMin && a.loc != nullptr;
   const bool prof = p.ctx && p.ctx->prof_kernel == PA_KERNEL_B2_STEP && p.steps > 0;
@@ -836,6 +919,7 @@ size_t b2_layout(pa_bdm2 *b, char *base) {
   place(off, b->qtab, &d.qtab, base);
   place(off, b->ftab, &d.ftab, base);
   place(off, b->mT, &d.mT, base);
+  place(off, b->mT32, &d.mT32, base);
   place(off, b->bot, &d.bot, base);
   if (base) {
     d.nu = b->nu;
@@ -864,7 +948,7 @@ pa_solve_cfg cfg_of(const pa_solve_cfg *cfg) {
   bneed(c.cg_rtol > 0 && c.cheb_tol > 0 && c.maxit > 0 && c.weight_cut >= 0, "bad solve configuration");
   bneed(c.backward == PA_BACKWARD_CLENSHAW || c.backward == PA_BACKWARD_PER_TERM, "unknown backward form");
   if (c.exponential != PA_EXP_CHEBYSHEV) throw Error(PA_ENOTSUP, "BDM2 calls take the Chebyshev exponential only");
-  if (c.precision != PA_FP64) throw Error(PA_ENOTSUP, "BDM2 mass solves run in FP64 only");
+  bneed(c.precision == PA_FP64 || c.precision == PA_FP32_REFINED, "unknown precision");
   if (c.solver != PA_SOLVER_CHEBYSHEV || c.precond != PA_PRECOND_JACOBI)
     throw Error(PA_ENOTSUP, "BDM2 mass solves are Jacobi Chebyshev semi-iterations only");
   return c;
@@ -1203,6 +1287,7 @@ int pa_bdm2_create(const pa_mesh *m, const pa_phys *ph, pa_bdm2 **out) {
     try {
       b->mesh = m;
       pa::bdm2_assemble(b, m->m, *ph);
+      b->mT32.assign(b->mT.begin(), b->mT.end());
       b->dev_bytes = pa::b2_layout(b, nullptr);
     } catch (...) {
       delete b;
@@ -1268,6 +1353,7 @@ int pa_bdm2_bind(pa_ctx *ctx, pa_bdm2 *b, void *dev_buf) {
     pa::up(s, b->d.qtab, b->qtab);
     pa::up(s, b->d.ftab, b->ftab);
     pa::up(s, b->d.mT, b->mT);
+    pa::up(s, b->d.mT32, b->mT32);
     pa::up(s, b->d.bot, b->bot);
     pa::sync_checked(s);
   });

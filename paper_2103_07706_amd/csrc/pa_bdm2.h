@@ -50,6 +50,7 @@ struct B2Dev {
   const double *qtab = nullptr;    // [kB2VQ][4]: barycentric l0, l1, l2, weight (sum 1)
   const double *ftab = nullptr;    // [kB2FQ][2]: t in [0, 1], weight (sum 1)
   const double *mT = nullptr;      // [nc][12][12]: s_i s_j (M_u)_T of the cell slots
+  const float *mT32 = nullptr;     // [nc][12][12]: the same rounded to FP32 (inner solves)
   const double *bot = nullptr;     // [nh]: bottom height (P1DG coefficients)
 };
 // Blocks at least this wide take the element form of the mass-solve step
@@ -142,6 +143,23 @@ void launch_b2_stiff(const B2Args &a, hipStream_t s);
 void launch_b2_step3(const B2Args &a, hipStream_t s);
 void launch_b2_step3_el(const B2Args &a, hipStream_t s);
 void launch_b2_cstep(const B2Args &a, hipStream_t s);
+// FP32 inner solves with FP64 refinement on 64-column blocks (cell form):
+// k_b2_mix_init starts the first round from r; each round runs FP32 steps
+// (k_b2_cstep32) and ends in k_b2_refine (x += y, r -= M y in FP64, the
+// next round's start or, on the last, the residual partials).
+struct B2MixArgs {
+  B2Dev d;
+  double *x, *r;          // FP64 iterate and residual, [nu][64]
+  float *r32;             // FP32 right-hand side of the inner solve
+  const float *y_cur;     // step: y_k; refine: the round's increment
+  float *y_out;           // step: y_{k-1} -> y_{k+1}; init, refine: the next y_1
+  float c1, c2, theta_inv;
+  int zero_prev, last;
+  double *part;           // refine on the last round: partials of |r|^2
+};
+void launch_b2_mix_init(const B2MixArgs &a, hipStream_t s);
+void launch_b2_cstep32(const B2MixArgs &a, hipStream_t s);
+void launch_b2_refine(const B2MixArgs &a, hipStream_t s);
 void launch_b2_norm(const B2Args &a, int slot, hipStream_t s);  // partials of |r|^2 -> norms[slot]
 void launch_b2_check(const B2Args &a, hipStream_t s);  // after the last step: |r_K|^2 vs rtol^2 |r_0|^2
 void launch_b2_acc(const B2Args &a, hipStream_t s);
@@ -158,6 +176,7 @@ struct pa_bdm2 {
   double eig_min = 0, eig_max = 0;  // Ritz bounds of D^-1 M_u
   std::vector<int32_t> col, bid, bcol, cdof;
   std::vector<double> mass, cor, bval, dinv, q, ncell, qtab, ftab, mT, bot;
+  std::vector<float> mT32;
   std::vector<int32_t> etab, rloc;
   size_t dev_bytes = 0;
   void *dev = nullptr;

@@ -189,40 +189,33 @@ __global__ __launch_bounds__(kBWG) void k_b2_step3_el(B2Args a) {
 // the XCDs in eight contiguous ranges (workgroup b runs on XCD b % 8, and
 // the grid is a multiple of 8), so the neighbours a cell gathers from are
 // mostly in flight on the same XCD and its L2.
-__global__ __launch_bounds__(kBWG) void k_b2_cstep(B2Args a) {
-  const B2Dev &d = a.d;
+__device__ inline double b2fma(double x, double y, double z) { return fma(x, y, z); }
+__device__ inline float b2fma(float x, float y, float z) { return fmaf(x, y, z); }
+
+// The cell walk of the cell form: for each row the wave's cell finishes,
+// row(g, y_g, (M y)_g) in the table's type T (values of y converted to T).
+template <class T, class V, class F>
+__device__ __forceinline__ void b2_cells(const B2Dev &d, const T *mtab, const V *y, F &&row) {
   constexpr int Bs = 64, kWaves = kBWG / 64;
   const int xcd = blockIdx.x & 7, per = gridDim.x >> 3;
   const int cpx = (d.nc + 7) >> 3;
   const int c_end = min(d.nc, (xcd + 1) * cpx);
   const size_t total = (size_t)c_end * Bs, stride = (size_t)per * kWaves * Bs;
   const auto rloc = kp<true>(d.rloc);
-  const auto dinv = kp<true>(d.dinv);
-  double rr = 0.0;
-  auto update = [&](int g, double yk, double my) {
-    const size_t gi = (size_t)g * Bs + threadIdx.x % Bs;
-    const double res = a.r[gi] - my;
-    if (!a.last) {
-      a.dir_out[gi] = yk + a.c1 * (yk - (a.first ? 0.0 : a.dir_out[gi])) + a.c2 * dinv[g] * res;
-    } else {
-      a.x[gi] += yk;
-      rr = fma(res, res, rr);
-    }
-  };
   const size_t i0 = ((size_t)xcd * cpx + (size_t)(blockIdx.x >> 3) * kWaves) * Bs + threadIdx.x;
   for (size_t i = i0; i < total; i += stride) {
     const int cell = uni<true>((int)(i / Bs)), c = (int)(i % Bs);
     const auto cdof = kp<true>(d.cdof + 12 * (size_t)cell);
-    const auto M = kp<true>(d.mT + (size_t)144 * cell);
-    double v[12];
+    const auto M = kp<true>(mtab + (size_t)144 * cell);
+    T v[12];
 #pragma unroll
-    for (int j = 0; j < 12; j++) v[j] = a.dir_in[(size_t)cdof[j] * Bs + c];
+    for (int j = 0; j < 12; j++) v[j] = (T)y[(size_t)cdof[j] * Bs + c];
 #pragma unroll
     for (int r = 9; r < 12; r++) {
-      double y = 0.0;
+      T acc = 0;
 #pragma unroll
-      for (int j = 0; j < 12; j++) y = fma(M[12 * r + j], v[j], y);
-      update(cdof[r], v[r], y);
+      for (int j = 0; j < 12; j++) acc = b2fma(M[12 * r + j], v[j], acc);
+      row(cdof[r], v[r], acc);
     }
     for (int e = 0; e < 3; e++) {
       const int g0 = cdof[3 * e];
@@ -230,30 +223,92 @@ __global__ __launch_bounds__(kBWG) void k_b2_cstep(B2Args a) {
       const int o = rloc[2 * (size_t)g0 + 1];
       const int oc = o >= 0 ? o / 12 : cell;
       const auto ocd = kp<true>(d.cdof + 12 * (size_t)oc);
-      const auto OM = kp<true>(d.mT + (size_t)144 * oc);
-      double w[12];
+      const auto OM = kp<true>(mtab + (size_t)144 * oc);
+      T w[12];
       if (o >= 0) {
 #pragma unroll
-        for (int j = 0; j < 12; j++) w[j] = a.dir_in[(size_t)ocd[j] * Bs + c];
+        for (int j = 0; j < 12; j++) w[j] = (T)y[(size_t)ocd[j] * Bs + c];
       }
 #pragma unroll
       for (int q = 0; q < 3; q++) {
         const int g = cdof[3 * e + q];
-        double y = 0.0;
+        T acc = 0;
 #pragma unroll
-        for (int j = 0; j < 12; j++) y = fma(M[12 * (3 * e + q) + j], v[j], y);
+        for (int j = 0; j < 12; j++) acc = b2fma(M[12 * (3 * e + q) + j], v[j], acc);
         if (o >= 0) {
           const int os = rloc[2 * (size_t)g + 1] - 12 * oc;
-          double z = 0.0;
+          T z = 0;
 #pragma unroll
-          for (int j = 0; j < 12; j++) z = fma(OM[12 * os + j], w[j], z);
-          y += z;
+          for (int j = 0; j < 12; j++) z = b2fma(OM[12 * os + j], w[j], z);
+          acc += z;
         }
-        update(g, v[3 * e + q], y);
+        row(g, v[3 * e + q], acc);
       }
     }
   }
-  if (a.last) b2_partial(rr, Bs, a.part);
+}
+
+__global__ __launch_bounds__(kBWG) void k_b2_cstep(B2Args a) {
+  const auto dinv = kp<true>(a.d.dinv);
+  double rr = 0.0;
+  b2_cells(a.d, a.d.mT, a.dir_in, [&](int g, double yk, double my) {
+    const size_t gi = (size_t)g * 64 + threadIdx.x % 64;
+    const double res = a.r[gi] - my;
+    if (!a.last) {
+      a.dir_out[gi] = yk + a.c1 * (yk - (a.first ? 0.0 : a.dir_out[gi])) + a.c2 * dinv[g] * res;
+    } else {
+      a.x[gi] += yk;
+      rr = fma(res, res, rr);
+    }
+  });
+  if (a.last) b2_partial(rr, 64, a.part);
+}
+
+// FP32 inner solves of a 64-column FP64 solve (iterative refinement).
+// Start of the first round, rows in order: b32 = (float) r, y_1 = D^-1 b32
+// / theta.
+__global__ __launch_bounds__(kBWG) void k_b2_mix_init(B2MixArgs a) {
+  const size_t total = (size_t)a.d.nu * 64, stride = (size_t)gridDim.x * kBWG;
+  for (size_t i = (size_t)blockIdx.x * kBWG + threadIdx.x; i < total; i += stride) {
+    const float b = (float)a.r[i];
+    a.r32[i] = b;
+    a.y_out[i] = (float)a.d.dinv[i / 64] * b * a.theta_inv;
+  }
+}
+
+// Inner step in FP32, cell form with the FP32 cell blocks: y_{k+1} = y_k +
+// c1 (y_k - y_{k-1}) + c2 D^-1 (b32 - M y_k) over y_{k-1} (y_out).
+__global__ __launch_bounds__(kBWG) void k_b2_cstep32(B2MixArgs a) {
+  const auto dinv = kp<true>(a.d.dinv);
+  b2_cells(a.d, a.d.mT32, a.y_cur, [&](int g, float yk, float my) {
+    const size_t gi = (size_t)g * 64 + threadIdx.x % 64;
+    const float res = a.r32[gi] - my;
+    const float yp = a.zero_prev ? 0.0f : a.y_out[gi];
+    a.y_out[gi] = yk + a.c1 * (yk - yp) + a.c2 * (float)dinv[g] * res;
+  });
+}
+
+// End of a round, FP64 cell form: x += y (the round's increment, y_cur),
+// r -= M y with the FP64 blocks; then the next round's b32 = (float) r and
+// y_1 = D^-1 b32 / theta (y_out), or on the last round the partials of
+// |r|^2 for the check.
+__global__ __launch_bounds__(kBWG) void k_b2_refine(B2MixArgs a) {
+  const auto dinv = kp<true>(a.d.dinv);
+  double rr = 0.0;
+  b2_cells(a.d, a.d.mT, a.y_cur, [&](int g, double yk, double my) {
+    const size_t gi = (size_t)g * 64 + threadIdx.x % 64;
+    a.x[gi] += yk;
+    const double rn = a.r[gi] - my;
+    a.r[gi] = rn;
+    if (a.last) {
+      rr = fma(rn, rn, rr);
+    } else {
+      const float b = (float)rn;
+      a.r32[gi] = b;
+      a.y_out[gi] = (float)dinv[g] * b * a.theta_inv;
+    }
+  });
+  if (a.last) b2_partial(rr, 64, a.part);
 }
 
 __global__ __launch_bounds__(kBWG) void k_b2_norm(B2Args a) {
@@ -671,6 +726,16 @@ static int b2_step_grid(const B2Args &a) {
 }
 void launch_b2_cstep(const B2Args &a, hipStream_t s) {
   hipLaunchKernelGGL(k_b2_cstep, dim3(b2_step_grid(a)), dim3(kBWG), 0, s, a);
+}
+static int b2_mix_grid(const B2MixArgs &a) { return (b2_grid(a.d.nu, 64) + 7) / 8 * 8; }
+void launch_b2_mix_init(const B2MixArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_b2_mix_init, dim3(b2_grid(a.d.nu, 64)), dim3(kBWG), 0, s, a);
+}
+void launch_b2_cstep32(const B2MixArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_b2_cstep32, dim3(b2_mix_grid(a)), dim3(kBWG), 0, s, a);
+}
+void launch_b2_refine(const B2MixArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_b2_refine, dim3(b2_mix_grid(a)), dim3(kBWG), 0, s, a);
 }
 void launch_b2_step3_el(const B2Args &a, hipStream_t s) {
   if (a.Bs == 64) {

@@ -144,7 +144,8 @@ def test_bdm2_refuses_topography_and_bad_sizes(oracle_mesh):
 
 
 def test_bdm2_refuses_settings_it_does_not_implement(oracle_mesh):
-    """The pair's calls run FP64 Jacobi Chebyshev solves and the Chebyshev
+    """The pair's calls run Jacobi Chebyshev solves (FP64, or FP32 inner
+    rounds with FP64 refinement on 64-column blocks) and the Chebyshev
     exponential: other settings are refused (PA_ENOTSUP), not ignored."""
     import ctypes
     from paper_2103_07706_amd import pa
@@ -152,13 +153,22 @@ def test_bdm2_refuses_settings_it_does_not_implement(oracle_mesh):
     b.set_lambda(1e-2)
     avg = pa.Avg(4, 1800.0)
     sz = ctypes.c_size_t()
-    for kw in (dict(exponential=pa.PA_EXP_REXI), dict(precision=pa.PA_FP32_REFINED),
-               dict(solver=pa.PA_SOLVER_CG), dict(precond=pa.PA_PRECOND_LEARNED)):
+    for kw in (dict(exponential=pa.PA_EXP_REXI), dict(solver=pa.PA_SOLVER_CG),
+               dict(precond=pa.PA_PRECOND_LEARNED)):
         cfg = pa.solve_cfg(**kw)
         for call in (pa.PA_BDM2_APPLY_L, pa.PA_BDM2_PHASE_AVG):
             code = pa.lib().pa_bdm2_workspace_size(b._h, call, 1, None, avg._h, ctypes.byref(cfg),
                                                    ctypes.byref(sz))
             assert code == pa.PA_ENOTSUP, (kw, call, code)
+    # FP32-refined solves take FP32 buffers on 64-column blocks only
+    fp32 = pa.solve_cfg(precision=pa.PA_FP32_REFINED)
+    assert (b.workspace_size(pa.PA_BDM2_APPLY_L, 64, cfg=fp32)
+            > b.workspace_size(pa.PA_BDM2_APPLY_L, 64))
+    assert (b.workspace_size(pa.PA_BDM2_APPLY_L, 3, cfg=fp32)
+            == b.workspace_size(pa.PA_BDM2_APPLY_L, 3))
+    cfg = pa.solve_cfg(precision=7)
+    assert pa.lib().pa_bdm2_workspace_size(b._h, pa.PA_BDM2_APPLY_L, 1, None, None,
+                                           ctypes.byref(cfg), ctypes.byref(sz)) == pa.PA_EINVAL
     cfg = pa.solve_cfg(backward=7)
     assert pa.lib().pa_bdm2_workspace_size(b._h, pa.PA_BDM2_APPLY_L, 1, None, None,
                                            ctypes.byref(cfg), ctypes.byref(sz)) == pa.PA_EINVAL

@@ -101,6 +101,44 @@ def test_gpu_bdm2_cell_form_equals_element_form(level):
     assert st["solves"] > 1
 
 
+def test_gpu_bdm2_fp32_refined_solves():
+    """PA_FP32_REFINED: 64-column mass solves run FP32 inner rounds (cell
+    form, FP32 cell blocks) closed by FP64 refinements of x and r, and the
+    FP64 residual check decides.  L on 64 states against the oracle's exact
+    solves and against the FP64 form at the same cg_rtol; the averaged
+    right-hand side of 64 members (their shared basis and the node columns
+    both 64 wide) against the FP64 form.  Narrower blocks keep FP64 steps."""
+    from paper_2103_07706_amd import pa
+    ob, lb, lm = _pair(3)
+    lb.set_lambda(1.05 * ob.rho())
+    U = _states(ob, range(64))
+    cf = _cfg(cg_rtol=1e-10, cheb_tol=1e-6, precision=pa.PA_FP32_REFINED)
+    c64 = _cfg(cg_rtol=1e-10, cheb_tol=1e-6)
+    got, st = lb.apply_L(_dev(U), cf)
+    ref64, st64 = lb.apply_L(_dev(U), c64)
+    got, ref64 = got.cpu().numpy(), ref64.cpu().numpy()
+    assert st["refinements"] >= 2 and st64["refinements"] == 0
+    assert 0 < st["resid_max"] <= 1e-10
+    for j in (0, 17, 63):
+        ref = ob.apply_L(U[j])
+        _close(got[j, :ob.nu], ref[:ob.nu], 1e-8, f"u col {j} vs oracle")
+        _close(got[j, ob.nu:], ref[ob.nu:], 1e-12, f"eta col {j} vs oracle")
+    _close(got, ref64, 1e-8, "FP32-refined vs FP64 form")
+    # narrower blocks are not refined
+    _, st3 = lb.apply_L(_dev(U[:3]), cf)
+    assert st3["refinements"] == 0 and 0 < st3["resid_max"] <= 1e-10
+    import oracle
+    om = oracle.Mesh(3)
+    avg = pa.Avg(8, 3600.0)
+    V = _smooth(om, range(64))
+    a, sa = lb.phase_avg_rhs(avg, _dev(V), cf)
+    b, sb = lb.phase_avg_rhs(avg, _dev(V), c64)
+    assert sa["refinements"] > 0 and 0 < sa["resid_max"] <= 1e-10
+    a, b = a.cpu().numpy(), b.cpu().numpy()
+    for j in range(0, 64, 9):
+        _close(a[j], b[j], 1e-8, f"member {j}: FP32-refined vs FP64 Nbar")
+
+
 def test_gpu_bdm2_apply_L_of_constant_depth_is_zero():
     """Constant depth, fluid at rest: the divergence of a continuous normal
     field integrates to zero, so L of (0, 1) has no velocity forcing from a
