@@ -1129,6 +1129,7 @@ void b2_step(pa_ctx *ctx, const pa_bdm2 *b, const pa_avg *avg, double dt, int B,
     tot.solves += x.solves;
     tot.cg_iters += x.cg_iters;
     tot.cg_iters_max = std::max(tot.cg_iters_max, x.cg_iters_max);
+    tot.refinements += x.refinements;
     tot.kmax = std::max(tot.kmax, x.kmax);
     tot.terms += x.terms;
     tot.resid_max = std::max(tot.resid_max, x.resid_max);

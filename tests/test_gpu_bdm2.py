@@ -139,6 +139,46 @@ def test_gpu_bdm2_fp32_refined_solves():
         _close(a[j], b[j], 1e-8, f"member {j}: FP32-refined vs FP64 Nbar")
 
 
+def test_gpu_bdm2_fp32_refined_passes_and_step():
+    """The refined form where the node columns of one member go through two
+    passes of 64 (M = 100, level 2) and in the averaged RK4 step of 64
+    members (every stage's solves 64 wide): both against the FP64 form at
+    the same tolerances, and the single member against the oracle.  L moves
+    no depth mass, so a polynomial p of L keeps p(0) times it: the step's
+    exponentials conserve the mass to their truncation (cheb_tol here), and
+    the refined step exactly as well as the FP64 one."""
+    import oracle
+    from paper_2103_07706_amd import pa
+    ob, lb, lm = _pair(2)
+    om = oracle.Mesh(2)
+    lam = 1.05 * ob.rho()
+    lb.set_lambda(lam)
+    cf = _cfg(cg_rtol=1e-10, cheb_tol=1e-8, precision=pa.PA_FP32_REFINED)
+    c64 = _cfg(cg_rtol=1e-10, cheb_tol=1e-8)
+    avg = pa.Avg(100, 3600.0)
+    U = _smooth(om, [5])
+    a, sa = lb.phase_avg_rhs(avg, _dev(U), cf)
+    b, _ = lb.phase_avg_rhs(avg, _dev(U), c64)
+    assert sa["refinements"] > 0 and 0 < sa["resid_max"] <= 1e-10
+    _close(a.cpu().numpy()[0], b.cpu().numpy()[0], 1e-8, "two passes: FP32-refined vs FP64")
+    s, w = oracle.avg_nodes(100, 3600.0)
+    ref = ob.phase_avg_rhs(lam, s, w, U[0], tol=1e-12)
+    _close(a.cpu().numpy()[0], ref, 1e-7, "two passes: FP32-refined vs oracle")
+    avg = pa.Avg(4, 1800.0)
+    U0 = _smooth(om, range(64))
+    X, Y = _dev(U0), _dev(U0)
+    _, st = lb.step(avg, 1800.0, X, cf)
+    lb.step(avg, 1800.0, Y, c64)
+    X, Y = X.cpu().numpy(), Y.cpu().numpy()
+    assert st["refinements"] > 0 and 0 < st["resid_max"] <= 1e-10
+    a3 = np.repeat(ob.area / 3.0, 3)
+    for j in range(0, 64, 7):
+        _close(X[j], Y[j], 1e-8, f"step member {j}: FP32-refined vs FP64")
+        scale = a3 @ np.abs(U0[j, ob.nu:])
+        assert abs(a3 @ (X[j, ob.nu:] - U0[j, ob.nu:])) <= 1e-6 * scale
+        assert abs(a3 @ (X[j, ob.nu:] - Y[j, ob.nu:])) <= 1e-12 * scale
+
+
 def test_gpu_bdm2_apply_L_of_constant_depth_is_zero():
     """Constant depth, fluid at rest: the divergence of a continuous normal
     field integrates to zero, so L of (0, 1) has no velocity forcing from a
