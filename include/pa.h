@@ -353,7 +353,9 @@ int pa_diagnostics(pa_ctx *ctx, const pa_ops *ops, int B, const double *U_dev,
  *                          bytes; element form on 8 to 32 columns, k_b2_mel
  *                          + k_b2_step3_el, and cell form on 64, k_b2_cstep:
  *                          per cell its 12 x 12 block, per row D^-1; per row
- *                          and column 32 bytes in all three)
+ *                          and column 32 bytes in all three; FP64 steps
+ *                          only, not the FP32 inner steps of
+ *                          PA_FP32_REFINED solves)
  * pa_ctx_profile starts a new tally (PA_KERNEL_NONE switches it off and
  * graph capture is not used while it is on); pa_ctx_profile_read returns the
  * tally so far.  The calls made while the hook is on fill it; reading needs
