@@ -461,7 +461,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the path shards over averaging terms or members, see the design notes)",
+              "(on several GPUs the path would shard its averaging terms or ensemble members, "
+              "one share per GPU)",
               file=sys.stderr)
         sys.exit(2)
     from paper_2103_07706_amd import inputs
